@@ -1,0 +1,248 @@
+"""ctypes front-end of the FP64 CPU oracle (test infrastructure only).
+
+Only the tests, the smoke check and the CPU-baseline leg of the benchmark use
+this package.  It never imports the HIP library and the HIP library never
+imports it.  All arrays are numpy; float32 inputs are widened exactly to
+binary64 inside the C code.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liboracle.so")
+
+FMT_F32, FMT_BF16, FMT_FP8_E4M3, FMT_F64 = 0, 1, 2, 3
+MODE_NEAREST, MODE_BILINEAR = 0, 1
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        from . import build as _b
+        _b.build()
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.c_void_p
+    i64, i32, d = ctypes.c_int64, ctypes.c_int, ctypes.c_double
+    lib.orc_num_threads.restype = i32
+    lib.orc_bf16_to_f64.argtypes = [ctypes.c_uint16]
+    lib.orc_bf16_to_f64.restype = d
+    lib.orc_e4m3_to_f64.argtypes = [ctypes.c_uint8]
+    lib.orc_e4m3_to_f64.restype = d
+    lib.orc_f32_to_bf16_rne.argtypes = [ctypes.c_float]
+    lib.orc_f32_to_bf16_rne.restype = ctypes.c_uint16
+    lib.orc_f32_to_e4m3_sat.argtypes = [ctypes.c_float]
+    lib.orc_f32_to_e4m3_sat.restype = ctypes.c_uint8
+    lib.orc_quantize.argtypes = [P, i64, i64, i32, P, P]
+    for name in ("orc_equisolid_tangent", "orc_square", "orc_unsquare",
+                 "orc_inverse_equisolid_tangent", "orc_reflection"):
+        getattr(lib, name).argtypes = [P, P]
+    lib.orc_equisolid_general.argtypes = [P, P, P]
+    lib.orc_inverse_equisolid_general.argtypes = [P, P, P]
+    lib.orc_texel_coord.argtypes = [P, i32, P]
+    lib.orc_lookup_fwd.argtypes = [i64, P, P, P, i32, i32, i32, i32, i32, P, P, i32, P]
+    lib.orc_lookup_one_f64.argtypes = [P, P, P, i32, i32, i32, i32, i32, P, P, i32, P]
+    lib.orc_indices.argtypes = [i64, P, P, P, i32, i32, i32, P, P, P]
+    lib.orc_map_one.argtypes = [P, P, i32, P]
+    lib.orc_lookup_bwd.argtypes = [i64, P, P, P, P, i32, i32, i32, i32, i32, P, P, i32,
+                                   P, P, i32, i32, i32, i32, P, P]
+    _lib = lib
+    return lib
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _c(a, dtype):
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+def num_threads() -> int:
+    return _load().orc_num_threads()
+
+
+# --- scalar conversions ----------------------------------------------------
+
+def bf16_to_f64(code: int) -> float:
+    return _load().orc_bf16_to_f64(int(code))
+
+
+def e4m3_to_f64(code: int) -> float:
+    return _load().orc_e4m3_to_f64(int(code))
+
+
+def f32_to_bf16(x: float) -> int:
+    return int(_load().orc_f32_to_bf16_rne(float(np.float32(x))))
+
+
+def f32_to_e4m3(x: float) -> int:
+    return int(_load().orc_f32_to_e4m3_sat(float(np.float32(x))))
+
+
+def quantize(tex_f32: np.ndarray, n_buckets: int, bucket_elems: int, fmt: int):
+    """Per-bucket quantiser.  Returns (codes, scales-or-None)."""
+    t = _c(tex_f32, np.float32).reshape(-1)
+    assert t.size == n_buckets * bucket_elems
+    if fmt == FMT_BF16:
+        codes = np.empty(t.size, np.uint16)
+        _load().orc_quantize(_p(t), n_buckets, bucket_elems, fmt, _p(codes), None)
+        return codes, None
+    codes = np.empty(t.size, np.uint8)
+    scales = np.empty(n_buckets, np.float32)
+    _load().orc_quantize(_p(t), n_buckets, bucket_elems, fmt, _p(codes), _p(scales))
+    return codes, scales
+
+
+# --- mapping pieces (binary64) ---------------------------------------------
+
+def _vec_call(fn, inp, in_len, out_len):
+    a = _c(inp, np.float64).reshape(-1, in_len)
+    out = np.empty((a.shape[0], out_len), np.float64)
+    for k in range(a.shape[0]):
+        fn(_p(a[k]), _p(out[k]))
+    return out
+
+
+def equisolid_tangent(I):
+    return _vec_call(_load().orc_equisolid_tangent, I, 3, 2)
+
+
+def square(A):
+    return _vec_call(_load().orc_square, A, 2, 2)
+
+
+def unsquare(B):
+    return _vec_call(_load().orc_unsquare, B, 2, 2)
+
+
+def inverse_equisolid_tangent(A):
+    return _vec_call(_load().orc_inverse_equisolid_tangent, A, 2, 3)
+
+
+def reflection(A):
+    return _vec_call(_load().orc_reflection, A, 2, 3)
+
+
+def equisolid_general(I, N):
+    I = _c(I, np.float64).reshape(-1, 3)
+    N = _c(N, np.float64).reshape(-1, 3)
+    out = np.empty((I.shape[0], 3))
+    for k in range(I.shape[0]):
+        _load().orc_equisolid_general(_p(I[k]), _p(N[k]), _p(out[k]))
+    return out
+
+
+def inverse_equisolid_general(A, N):
+    A = _c(A, np.float64).reshape(-1, 2)
+    N = _c(N, np.float64).reshape(-1, 3)
+    out = np.empty((A.shape[0], 3))
+    for k in range(A.shape[0]):
+        _load().orc_inverse_equisolid_general(_p(A[k]), _p(N[k]), _p(out[k]))
+    return out
+
+
+def texel_coord(B, n):
+    B = _c(B, np.float64).reshape(-1, 2)
+    out = np.empty((B.shape[0], 2))
+    for k in range(B.shape[0]):
+        _load().orc_texel_coord(_p(B[k]), int(n), _p(out[k]))
+    return out
+
+
+def map_one(M, V, n):
+    """(A_x, A_y, B_x, B_y, s_x, s_y) for frame M (9) and view V (3)."""
+    M = _c(M, np.float64).reshape(9)
+    V = _c(V, np.float64).reshape(3)
+    out = np.empty(6)
+    _load().orc_map_one(_p(M), _p(V), int(n), _p(out))
+    return out
+
+
+# --- whole lookups -----------------------------------------------------------
+
+class Tex:
+    """Texture description for the oracle (host arrays, bucket-major)."""
+
+    def __init__(self, data, W, H, n, C, fmt=FMT_F32, scales=None):
+        dt = {FMT_F32: np.float32, FMT_BF16: np.uint16, FMT_FP8_E4M3: np.uint8,
+              FMT_F64: np.float64}[fmt]
+        self.data = _c(data, dt).reshape(-1)
+        assert self.data.size == W * H * n * n * C, (self.data.size, W, H, n, C)
+        self.W, self.H, self.n, self.C, self.fmt = int(W), int(H), int(n), int(C), fmt
+        self.scales = None if scales is None else _c(scales, np.float32).reshape(-1)
+        if fmt == FMT_FP8_E4M3:
+            assert self.scales is not None and self.scales.size == W * H
+
+    def args(self):
+        return (self.W, self.H, self.n, self.C, self.fmt, _p(self.data), _p(self.scales))
+
+
+def _frags(uv, tbn, view):
+    uv = _c(uv, np.float32).reshape(-1, 2)
+    tbn = _c(tbn, np.float32).reshape(-1, 9)
+    view = _c(view, np.float32).reshape(-1, 3)
+    assert uv.shape[0] == tbn.shape[0] == view.shape[0]
+    return uv, tbn, view
+
+
+def lookup_fwd(tex: Tex, uv, tbn, view, mode=MODE_NEAREST):
+    uv, tbn, view = _frags(uv, tbn, view)
+    N = uv.shape[0]
+    out = np.empty((N, tex.C), np.float64)
+    _load().orc_lookup_fwd(N, _p(uv), _p(tbn), _p(view), *tex.args(), int(mode), _p(out))
+    return out
+
+
+def lookup_one_f64(tex: Tex, U, M, V, mode=MODE_NEAREST):
+    U = _c(U, np.float64).reshape(2)
+    M = _c(M, np.float64).reshape(9)
+    V = _c(V, np.float64).reshape(3)
+    out = np.empty(tex.C, np.float64)
+    _load().orc_lookup_one_f64(_p(U), _p(M), _p(V), *tex.args(), int(mode), _p(out))
+    return out
+
+
+def indices(uv, tbn, view, W, H, n):
+    """Returns idx [N,4] int32 (i, j, x0, y0), frac [N,2], edge [N,2]."""
+    uv, tbn, view = _frags(uv, tbn, view)
+    N = uv.shape[0]
+    idx = np.empty((N, 4), np.int32)
+    frac = np.empty((N, 2), np.float64)
+    edge = np.empty((N, 2), np.float64)
+    _load().orc_indices(N, _p(uv), _p(tbn), _p(view), int(W), int(H), int(n), _p(idx),
+                        _p(frac), _p(edge))
+    return idx, frac, edge
+
+
+def lookup_bwd(tex: Tex, uv, tbn, view, g, mode=MODE_NEAREST, want_tex=True, window=None,
+               want_view=True, want_uv=True):
+    """Analytic backward in binary64.
+
+    window = (bi0, bj0, bw, bh) restricts grad_tex to that bucket rectangle
+    (default: the whole matrix).  Returns dict with grad_tex [bh,bw,n,n,C],
+    abs_tex, grad_view [N,3], grad_uv [N,2] (entries None when not asked).
+    """
+    uv, tbn, view = _frags(uv, tbn, view)
+    g = _c(g, np.float32).reshape(-1, tex.C)
+    N = uv.shape[0]
+    assert g.shape[0] == N
+    if window is None:
+        window = (0, 0, tex.W, tex.H)
+    bi0, bj0, bw, bh = (int(x) for x in window)
+    gt = at = gv = gu = None
+    if want_tex:
+        gt = np.empty((bh, bw, tex.n, tex.n, tex.C), np.float64)
+        at = np.empty_like(gt)
+    if want_view:
+        gv = np.empty((N, 3), np.float64)
+    if want_uv:
+        gu = np.empty((N, 2), np.float64)
+    _load().orc_lookup_bwd(N, _p(uv), _p(tbn), _p(view), _p(g), *tex.args(), int(mode),
+                           _p(gt), _p(at), bi0, bj0, bw, bh, _p(gv), _p(gu))
+    return {"grad_tex": gt, "abs_tex": at, "grad_view": gv, "grad_uv": gu}

@@ -1,0 +1,767 @@
+/*
+ * radtex_oracle.c -- plain, slow FP64 CPU oracle for the radiance-bucket lookup
+ * of "Radiance Textures for Rasterizing Ray-Traced Data" (Fober, 2023,
+ * arXiv 2301.01719).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the independent reference that the
+ * GPU path is checked against.  It shares no code, header, table or constant
+ * generator with the HIP library, and only the test-suite, the smoke check and
+ * the CPU-baseline leg of the benchmark may load it.  Nothing in the product
+ * path calls it.
+ *
+ * Everything is double precision and written as the paper states it, step by
+ * step, with no blocking or fusion:
+ *
+ *   tangent-space incidence   Sec. 2.1: the incidence vector is moved into the
+ *                             orthogonal texture space (N_z = 1) by the
+ *                             per-fragment frame M = [T;B;N] and normalised
+ *   equisolid projection      Eq. (1b) (and the general-normal Eq. (1a))
+ *   disc -> square            Eq. (3)
+ *   bucket-edge clamp         the Note after Eq. (3): B clamped to
+ *                             [1/n - 1, 1 - 1/n]^2
+ *   bucket selection          Sec. 2: texture u,v index the bucket matrix
+ *   filtered fetch            bilinear inside the bucket (the clamp only has a
+ *                             purpose for a filtered fetch)
+ *   inverse mappings          Eqs. (2a)-(2c), (4a), (4b)
+ *
+ * Readings of points the paper leaves open (texel-centre convention, UV wrap,
+ * axis orientation, the A = 0 case of Eq. (3), the storage formats) are listed
+ * with the design notes of the repository; each is restated where it is used.
+ *
+ * Parity pins: every function here is checked by the CPU test-suite against
+ * closed forms, a second formulation from the paper, brute force, or an
+ * independent library routine (see tests/test_oracle_pins.py).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORC_FMT_F32 0
+#define ORC_FMT_BF16 1
+#define ORC_FMT_FP8_E4M3 2
+#define ORC_FMT_F64 3 /* oracle-only: for finite differences w.r.t. texels */
+
+#define ORC_MODE_NEAREST 0
+#define ORC_MODE_BILINEAR 1
+
+static const double SQRT2 = 1.41421356237309504880168872420969808;
+
+int orc_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+/* ------------------------------------------------------------------------ */
+/* Storage formats (the quantised storage is an addition to the paper, which  */
+/* only says buckets compress well; see the abstract and Sec. 2).             */
+/* ------------------------------------------------------------------------ */
+
+/* BF16 is, by definition, the upper 16 bits of an IEEE binary32. */
+double orc_bf16_to_f64(uint16_t code)
+{
+    uint32_t bits = (uint32_t)code << 16;
+    float f;
+    memcpy(&f, &bits, 4);
+    return (double)f;
+}
+
+/* OCP 8-bit E4M3 ("FN" variant): 1 sign, 4 exponent (bias 7), 3 mantissa
+ * bits; exponent field 0 is subnormal (M * 2^-9); S.1111.111 is NaN; there is
+ * no infinity; largest finite magnitude 448. */
+double orc_e4m3_to_f64(uint8_t code)
+{
+    int s = code >> 7;
+    int E = (code >> 3) & 15;
+    int M = code & 7;
+    double v;
+    if (E == 15 && M == 7)
+        return NAN;
+    if (E == 0)
+        v = ldexp((double)M, -9);
+    else
+        v = ldexp(1.0 + M / 8.0, E - 7);
+    return s ? -v : v;
+}
+
+/* Round-to-nearest-even of a binary32 to BF16, written from the definition:
+ * the two BF16 neighbours of x are found, the nearer one is taken, and a tie
+ * goes to the one whose code is even. */
+uint16_t orc_f32_to_bf16_rne(float x)
+{
+    uint32_t bits;
+    memcpy(&bits, &x, 4);
+    if (isnan(x))
+        return (uint16_t)((bits >> 16) | 0x0040u); /* quiet NaN, sign kept */
+    if (isinf(x))
+        return (uint16_t)(bits >> 16);
+    uint32_t sign = bits & 0x80000000u;
+    uint32_t mag = bits & 0x7FFFFFFFu;
+    uint32_t lo_code = mag >> 16;        /* neighbour toward zero */
+    uint32_t hi_code = lo_code + 1;      /* neighbour away from zero */
+    double ax = fabs((double)x);
+    double vlo = fabs(orc_bf16_to_f64((uint16_t)lo_code));
+    double vhi;
+    if (hi_code == 0x7F80u)
+        vhi = ldexp(1.0, 128); /* overflow threshold of round-to-nearest */
+    else
+        vhi = fabs(orc_bf16_to_f64((uint16_t)hi_code));
+    uint32_t pick;
+    double dlo = ax - vlo, dhi = vhi - ax;
+    if (dlo < dhi)
+        pick = lo_code;
+    else if (dhi < dlo)
+        pick = hi_code;
+    else
+        pick = (lo_code & 1u) ? hi_code : lo_code;
+    return (uint16_t)((sign >> 16) | pick);
+}
+
+/* Round-to-nearest-even to E4M3 with saturation to +-448 ("satfinite"),
+ * written from the definition: the non-negative finite codes 0x00..0x7E are
+ * in increasing order of value, the nearest one to |y| is chosen, ties go to
+ * the even code, values above 448 (and infinities) become 448, NaN stays NaN. */
+uint8_t orc_f32_to_e4m3_sat(float y)
+{
+    if (isnan(y))
+        return (uint8_t)(signbit(y) ? 0xFF : 0x7F);
+    int neg = signbit(y) ? 1 : 0;
+    double a = fabs((double)y);
+    int best;
+    if (a >= 448.0) {
+        best = 0x7E;
+    } else {
+        /* find k with v(k) <= a < v(k+1) by scanning the ordered code list */
+        int k = 0;
+        while (k < 0x7E && orc_e4m3_to_f64((uint8_t)(k + 1)) <= a)
+            k++;
+        if (k == 0x7E) {
+            best = 0x7E;
+        } else {
+            double vl = orc_e4m3_to_f64((uint8_t)k);
+            double vh = orc_e4m3_to_f64((uint8_t)(k + 1));
+            double dl = a - vl, dh = vh - a;
+            if (dl < dh)
+                best = k;
+            else if (dh < dl)
+                best = k + 1;
+            else
+                best = (k & 1) ? k + 1 : k;
+        }
+    }
+    return (uint8_t)((neg << 7) | best);
+}
+
+/* Per-bucket quantiser.  Texture is bucket-major [H][W][n][n][C] float32.
+ * fmt == ORC_FMT_BF16: codes_u16 receives RNE BF16 codes, no scale.
+ * fmt == ORC_FMT_FP8_E4M3: per bucket b, amax = max |x| (binary32), and if
+ * amax is zero or not finite then scale = inv = 1, else inv = 448/amax and
+ * scale = amax/448, both rounded to binary32; every value becomes
+ * e4m3_sat(x * inv) (product rounded to binary32).  The decision that yields
+ * an integer code is therefore taken in binary32 arithmetic, as in the GPU
+ * quantiser; the rounding to the code is done from the definition above. */
+void orc_quantize(const float *tex, int64_t n_buckets, int64_t bucket_elems, int fmt,
+                  void *codes, float *scales)
+{
+    if (fmt == ORC_FMT_BF16) {
+        uint16_t *out = (uint16_t *)codes;
+        int64_t total = n_buckets * bucket_elems;
+#pragma omp parallel for schedule(static)
+        for (int64_t e = 0; e < total; e++)
+            out[e] = orc_f32_to_bf16_rne(tex[e]);
+        return;
+    }
+    uint8_t *out = (uint8_t *)codes;
+#pragma omp parallel for schedule(static)
+    for (int64_t b = 0; b < n_buckets; b++) {
+        const float *src = tex + b * bucket_elems;
+        float amax = 0.0f;
+        for (int64_t e = 0; e < bucket_elems; e++) {
+            float a = fabsf(src[e]);
+            if (a > amax)
+                amax = a;
+        }
+        volatile float inv, scale; /* force binary32 rounding of each step */
+        if (amax == 0.0f || !isfinite(amax)) {
+            inv = 1.0f;
+            scale = 1.0f;
+        } else {
+            inv = 448.0f / amax;
+            scale = amax / 448.0f;
+        }
+        for (int64_t e = 0; e < bucket_elems; e++) {
+            volatile float y = src[e] * inv;
+            out[b * bucket_elems + e] = orc_f32_to_e4m3_sat(y);
+        }
+        scales[b] = scale;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Mapping of the incidence vector to the radiance bucket (Sec. 2.1)         */
+/* ------------------------------------------------------------------------ */
+
+/* Eq. (1b): equisolid azimuthal projection in orthogonal texture space
+ * (N = e_z).  I is a unit vector from the surface toward the viewer.
+ * The projection is singular only for I = -N, where the paper's denominator
+ * vanishes; that direction is mapped to A = 0 (a reading; it is measure-zero
+ * and lies below the horizon). */
+void orc_equisolid_tangent(const double I[3], double A[2])
+{
+    double D = sqrt(I[0] * I[0] + I[1] * I[1] + (I[2] + 1.0) * (I[2] + 1.0));
+    if (D == 0.0) {
+        A[0] = A[1] = 0.0;
+        return;
+    }
+    A[0] = SQRT2 * I[0] / D;
+    A[1] = SQRT2 * I[1] / D;
+}
+
+/* Eq. (1a): the same projection for a general unit normal N.  The double-bar
+ * is read as "direction of" (normalisation), so the result is
+ * sqrt(2) * (I + N) / |I + N|; its first two components are the projection
+ * expressed in the frame of the vectors, its third is sqrt(2) cos(theta/2)
+ * when N = e_z. */
+void orc_equisolid_general(const double I[3], const double N[3], double out[3])
+{
+    double s0 = I[0] + N[0], s1 = I[1] + N[1], s2 = I[2] + N[2];
+    double len = sqrt(s0 * s0 + s1 * s1 + s2 * s2);
+    if (len == 0.0) {
+        out[0] = out[1] = out[2] = 0.0;
+        return;
+    }
+    out[0] = SQRT2 * s0 / len;
+    out[1] = SQRT2 * s1 / len;
+    out[2] = SQRT2 * s2 / len;
+}
+
+/* Eq. (3): disc -> square.  B = (|A|_2 / max(|A_x|,|A_y|)) A.  The paper's
+ * condition is read as "A is not the zero vector"; B = 0 at A = 0, which is
+ * the limit of the map there. */
+void orc_square(const double A[2], double B[2])
+{
+    double rho = sqrt(A[0] * A[0] + A[1] * A[1]);
+    double m = fmax(fabs(A[0]), fabs(A[1]));
+    if (m == 0.0) {
+        B[0] = B[1] = 0.0;
+        return;
+    }
+    B[0] = rho / m * A[0];
+    B[1] = rho / m * A[1];
+}
+
+/* Eq. (4a): square -> disc, the inverse of Eq. (3). */
+void orc_unsquare(const double B[2], double A[2])
+{
+    double rho = sqrt(B[0] * B[0] + B[1] * B[1]);
+    double m = fmax(fabs(B[0]), fabs(B[1]));
+    if (rho == 0.0) {
+        A[0] = A[1] = 0.0;
+        return;
+    }
+    A[0] = m / rho * B[0];
+    A[1] = m / rho * B[1];
+}
+
+/* Eq. (2c): inverse equisolid mapping in orthogonal texture space. */
+void orc_inverse_equisolid_tangent(const double A[2], double I[3])
+{
+    double r2 = A[0] * A[0] + A[1] * A[1];
+    double w = sqrt(fmax(0.0, 2.0 - r2));
+    I[0] = A[0] * w;
+    I[1] = A[1] * w;
+    I[2] = 1.0 - r2;
+}
+
+/* Eqs. (2a)-(2b): inverse mapping for a general normal; A' is the half-vector
+ * built from A in the frame where the normal is e_z (Eq. 2a), and the
+ * incidence is the normal reflected about A' (Eq. 2b). */
+void orc_inverse_equisolid_general(const double A[2], const double N[3], double I[3])
+{
+    double Ap[3];
+    Ap[0] = A[0] * sqrt(0.5);
+    Ap[1] = A[1] * sqrt(0.5);
+    Ap[2] = sqrt(fmax(0.0, 1.0 - A[0] * A[0] / 2.0 - A[1] * A[1] / 2.0));
+    double d = Ap[0] * N[0] + Ap[1] * N[1] + Ap[2] * N[2];
+    for (int k = 0; k < 3; k++)
+        I[k] = 2.0 * (d * Ap[k] - N[k]) + N[k];
+}
+
+/* Eq. (4b): equisolid reflection vector, the incidence mirrored about N. */
+void orc_reflection(const double A[2], double R[3])
+{
+    double r2 = A[0] * A[0] + A[1] * A[1];
+    double w = sqrt(fmax(0.0, 2.0 - r2));
+    R[0] = -A[0] * w;
+    R[1] = -A[1] * w;
+    R[2] = 1.0 - r2;
+}
+
+/* Bucket-edge clamp (the Note after Eq. (3)) followed by the texel-centre
+ * reading: B in [-1,1] spans the bucket's n samples with sample centres at
+ * B = (2k+1)/n - 1, so the continuous sample coordinate is
+ * s = (B + 1) n/2 - 1/2 and the clamp range [1/n - 1, 1 - 1/n] becomes
+ * exactly [0, n-1].  The final min/max only removes rounding residue of the
+ * affine map (it is the identity in exact arithmetic).
+ * s_unclamped receives the coordinate before the clamp. */
+static void texel_coord(const double B[2], int n, double s[2], double s_unclamped[2],
+                        int clamped[2])
+{
+    double lo = 1.0 / n - 1.0, hi = 1.0 - 1.0 / n;
+    for (int k = 0; k < 2; k++) {
+        double b = B[k];
+        s_unclamped[k] = (b + 1.0) * n / 2.0 - 0.5;
+        clamped[k] = !(b > lo && b < hi);
+        if (b < lo)
+            b = lo;
+        if (b > hi)
+            b = hi;
+        double t = (b + 1.0) * n / 2.0 - 0.5;
+        if (!(t >= 0.0))
+            t = 0.0; /* also maps NaN (undefined input) to the first sample */
+        if (t > n - 1)
+            t = n - 1;
+        s[k] = t;
+    }
+}
+
+void orc_texel_coord(const double B[2], int n, double s[2])
+{
+    double su[2];
+    int cl[2];
+    texel_coord(B, n, s, su, cl);
+}
+
+/* Sec. 2.1: the incidence vector in orthogonal texture space.  The frame M
+ * has rows T, B, N (row-major, vectors as columns, as in the paper's naming
+ * convention), u = M V, and I = u / |u|. */
+static int tangent_incidence(const double tbn[9], const double V[3], double u[3], double I[3],
+                             double *L)
+{
+    for (int k = 0; k < 3; k++)
+        u[k] = tbn[3 * k + 0] * V[0] + tbn[3 * k + 1] * V[1] + tbn[3 * k + 2] * V[2];
+    *L = sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+    if (!(*L > 0.0) || !isfinite(*L)) {
+        I[0] = I[1] = I[2] = NAN;
+        return 0;
+    }
+    for (int k = 0; k < 3; k++)
+        I[k] = u[k] / *L;
+    return 1;
+}
+
+/* The texture coordinate of Sec. 2 selects the bucket: the UV plane is read
+ * as repeating (wrap), the bucket column is floor(frac(u) W) and the row
+ * floor(frac(v) H) with row 0 first in memory.  A rounding result of W is
+ * put in the last column; non-finite coordinates give bucket 0. */
+static int bucket_index(double u, int W, double *edge_dist)
+{
+    double f = u - floor(u);
+    if (!isfinite(f)) {
+        if (edge_dist)
+            *edge_dist = INFINITY;
+        return 0;
+    }
+    double p = f * W;
+    int i = (int)floor(p);
+    if (i > W - 1)
+        i = W - 1;
+    if (i < 0)
+        i = 0;
+    if (edge_dist) {
+        double k = floor(p + 0.5);
+        *edge_dist = fabs(p - k) / W;
+    }
+    return i;
+}
+
+/* distance (in units of the bucket side) of the unclamped sample coordinate
+ * to the nearest cell edge, the clamp bounds included */
+static double sample_edge_dist(double su, int n)
+{
+    double k;
+    if (su <= 0.0)
+        k = 0.0;
+    else if (su >= n - 1)
+        k = n - 1;
+    else
+        k = floor(su + 0.5);
+    return fabs(su - k) / n;
+}
+
+typedef struct {
+    int W, H, n, C, fmt;
+    const void *data;
+    const float *scales;
+} tex_t;
+
+/* Texel (row y, column x, channel c) of bucket (column i, row j).  Storage is
+ * bucket-major [H][W][n][n][C]; the decoded value is exact in binary64. */
+static double texel(const tex_t *t, int i, int j, int y, int x, int c)
+{
+    int64_t b = (int64_t)j * t->W + i;
+    int64_t e = ((b * t->n + y) * t->n + x) * t->C + c;
+    switch (t->fmt) {
+    case ORC_FMT_F32:
+        return (double)((const float *)t->data)[e];
+    case ORC_FMT_BF16:
+        return orc_bf16_to_f64(((const uint16_t *)t->data)[e]);
+    case ORC_FMT_FP8_E4M3:
+        return orc_e4m3_to_f64(((const uint8_t *)t->data)[e]) * (double)t->scales[b];
+    default:
+        return ((const double *)t->data)[e];
+    }
+}
+
+typedef struct {
+    double s[2], su[2];
+    int clamped[2];
+    int x0, y0, x1, y1;
+    double fx, fy;
+    double A[2], B[2];
+    double u[3], I[3], L;
+    int valid;
+} dirmap_t;
+
+/* All steps from the view vector to the bilinear footprint inside a bucket. */
+static void map_direction(const double tbn[9], const double V[3], int n, dirmap_t *d)
+{
+    d->valid = tangent_incidence(tbn, V, d->u, d->I, &d->L);
+    if (d->valid) {
+        orc_equisolid_tangent(d->I, d->A);
+        orc_square(d->A, d->B);
+    } else {
+        d->A[0] = d->A[1] = NAN;
+        d->B[0] = d->B[1] = NAN;
+    }
+    texel_coord(d->B, n, d->s, d->su, d->clamped);
+    d->x0 = (int)floor(d->s[0]);
+    d->y0 = (int)floor(d->s[1]);
+    d->fx = d->s[0] - d->x0;
+    d->fy = d->s[1] - d->y0;
+    d->x1 = d->x0 + 1 < n - 1 ? d->x0 + 1 : n - 1;
+    d->y1 = d->y0 + 1 < n - 1 ? d->y0 + 1 : n - 1;
+}
+
+/* Bilinear value inside bucket (i,j) at the footprint of d, channel c. */
+static double bilerp(const tex_t *t, int i, int j, const dirmap_t *d, int c)
+{
+    double T00 = texel(t, i, j, d->y0, d->x0, c);
+    double T01 = texel(t, i, j, d->y0, d->x1, c);
+    double T10 = texel(t, i, j, d->y1, d->x0, c);
+    double T11 = texel(t, i, j, d->y1, d->x1, c);
+    return (1.0 - d->fy) * ((1.0 - d->fx) * T00 + d->fx * T01) +
+           d->fy * ((1.0 - d->fx) * T10 + d->fx * T11);
+}
+
+/* Bucket footprint in UV: nearest (one bucket, weight 1) or, in the
+ * bilinear-bucket mode, the four buckets around p = frac(u) W - 1/2 with
+ * bilinear weights, wrapping across the matrix edges. */
+typedef struct {
+    int i[4], j[4];
+    double w[4];
+    int count;
+    double a, b;       /* bilinear-bucket fractions */
+    int i0, i1, j0, j1;
+} bucketfp_t;
+
+static void bucket_footprint(double u, double v, int W, int H, int mode, bucketfp_t *f)
+{
+    if (mode == ORC_MODE_NEAREST) {
+        f->count = 1;
+        f->i[0] = bucket_index(u, W, NULL);
+        f->j[0] = bucket_index(v, H, NULL);
+        f->w[0] = 1.0;
+        f->a = f->b = 0.0;
+        return;
+    }
+    double fu = u - floor(u), fv = v - floor(v);
+    if (!isfinite(fu))
+        fu = 0.0;
+    if (!isfinite(fv))
+        fv = 0.0;
+    double p = fu * W - 0.5, q = fv * H - 0.5;
+    double pi0 = floor(p), qj0 = floor(q);
+    double a = p - pi0, b = q - qj0;
+    int i0 = (int)pi0, j0 = (int)qj0;
+    /* wrap */
+    i0 = ((i0 % W) + W) % W;
+    j0 = ((j0 % H) + H) % H;
+    int i1 = (i0 + 1) % W, j1 = (j0 + 1) % H;
+    f->count = 4;
+    f->i0 = i0; f->i1 = i1; f->j0 = j0; f->j1 = j1;
+    f->a = a; f->b = b;
+    f->i[0] = i0; f->j[0] = j0; f->w[0] = (1.0 - a) * (1.0 - b);
+    f->i[1] = i1; f->j[1] = j0; f->w[1] = a * (1.0 - b);
+    f->i[2] = i0; f->j[2] = j1; f->w[2] = (1.0 - a) * b;
+    f->i[3] = i1; f->j[3] = j1; f->w[3] = a * b;
+}
+
+static void widen_fragment(const float *uv, const float *tbn, const float *view, int64_t f,
+                           double U[2], double M[9], double V[3])
+{
+    U[0] = uv[2 * f];
+    U[1] = uv[2 * f + 1];
+    for (int k = 0; k < 9; k++)
+        M[k] = tbn[9 * f + k];
+    for (int k = 0; k < 3; k++)
+        V[k] = view[3 * f + k];
+}
+
+static void lookup_one(const tex_t *t, const double U[2], const double M[9], const double V[3],
+                       int mode, double *out)
+{
+    dirmap_t d;
+    bucketfp_t bf;
+    map_direction(M, V, t->n, &d);
+    bucket_footprint(U[0], U[1], t->W, t->H, mode, &bf);
+    for (int c = 0; c < t->C; c++) {
+        double acc = 0.0;
+        for (int k = 0; k < bf.count; k++)
+            acc += bf.w[k] * bilerp(t, bf.i[k], bf.j[k], &d, c);
+        out[c] = acc;
+    }
+}
+
+/* Forward lookup of N fragments: out[f][c] in binary64. */
+void orc_lookup_fwd(int64_t N, const float *uv, const float *tbn, const float *view, int W,
+                    int H, int n, int C, int fmt, const void *data, const float *scales,
+                    int mode, double *out)
+{
+    tex_t t = {W, H, n, C, fmt, data, scales};
+#pragma omp parallel for schedule(static)
+    for (int64_t f = 0; f < N; f++) {
+        double U[2], M[9], V[3];
+        widen_fragment(uv, tbn, view, f, U, M, V);
+        lookup_one(&t, U, M, V, mode, out + f * C);
+    }
+}
+
+/* Forward lookup of a single fragment given in binary64 (finite differences). */
+void orc_lookup_one_f64(const double U[2], const double M[9], const double V[3], int W, int H,
+                        int n, int C, int fmt, const void *data, const float *scales, int mode,
+                        double *out)
+{
+    tex_t t = {W, H, n, C, fmt, data, scales};
+    lookup_one(&t, U, M, V, mode, out);
+}
+
+/* Per-fragment indices of the nearest-bucket lookup, for bit-exact checks:
+ * idx[f] = (i, j, x0, y0), frac[f] = (fx, fy), and the distances (in units
+ * of the matrix side and of the bucket side) of the unrounded coordinates to
+ * the nearest cell edge: edge[f] = (bucket distance, sample distance). */
+void orc_indices(int64_t N, const float *uv, const float *tbn, const float *view, int W, int H,
+                 int n, int32_t *idx, double *frac, double *edge)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t f = 0; f < N; f++) {
+        double U[2], M[9], V[3], du, dv;
+        widen_fragment(uv, tbn, view, f, U, M, V);
+        dirmap_t d;
+        map_direction(M, V, n, &d);
+        idx[4 * f + 0] = bucket_index(U[0], W, &du);
+        idx[4 * f + 1] = bucket_index(U[1], H, &dv);
+        idx[4 * f + 2] = d.x0;
+        idx[4 * f + 3] = d.y0;
+        frac[2 * f + 0] = d.fx;
+        frac[2 * f + 1] = d.fy;
+        if (edge) {
+            double sd = fmin(sample_edge_dist(d.su[0], n), sample_edge_dist(d.su[1], n));
+            if (!d.valid)
+                sd = INFINITY;
+            edge[2 * f + 0] = fmin(du, dv);
+            edge[2 * f + 1] = sd;
+        }
+    }
+}
+
+/* Intermediate values of the mapping for one direction, in binary64:
+ * out = (A_x, A_y, B_x, B_y, s_x, s_y). */
+void orc_map_one(const double M[9], const double V[3], int n, double out[6])
+{
+    dirmap_t d;
+    map_direction(M, V, n, &d);
+    out[0] = d.A[0];
+    out[1] = d.A[1];
+    out[2] = d.B[0];
+    out[3] = d.B[1];
+    out[4] = d.s[0];
+    out[5] = d.s[1];
+}
+
+/* ------------------------------------------------------------------------ */
+/* Backward (an addition to the paper: analytic derivatives of the lookup)   */
+/* ------------------------------------------------------------------------ */
+
+/* dB/dA of Eq. (3), as a 2x2 matrix J[r][c] = dB_r/dA_c.  On the branch
+ * |A_x| >= |A_y| the map is B = (rho sgn(A_x), rho A_y/|A_x|); the other
+ * branch is its mirror image.  At A = 0 the limit along the axes (identity)
+ * is used. */
+static void square_jacobian(const double A[2], double J[2][2])
+{
+    double ax = A[0], ay = A[1];
+    double rho = sqrt(ax * ax + ay * ay);
+    if (rho == 0.0) {
+        J[0][0] = 1.0; J[0][1] = 0.0; J[1][0] = 0.0; J[1][1] = 1.0;
+        return;
+    }
+    if (fabs(ax) >= fabs(ay)) {
+        double sx = ax >= 0 ? 1.0 : -1.0;
+        J[0][0] = fabs(ax) / rho;
+        J[0][1] = sx * ay / rho;
+        J[1][0] = -sx * ay * ay * ay / (rho * ax * ax);
+        J[1][1] = (ay * ay + rho * rho) / (rho * fabs(ax));
+    } else {
+        double sy = ay >= 0 ? 1.0 : -1.0;
+        J[1][1] = fabs(ay) / rho;
+        J[1][0] = sy * ax / rho;
+        J[0][1] = -sy * ax * ax * ax / (rho * ay * ay);
+        J[0][0] = (ax * ax + rho * rho) / (rho * fabs(ay));
+    }
+}
+
+/* dA/dI of Eq. (1b) taken literally (I free in R^3), J[r][c] = dA_r/dI_c. */
+static void equisolid_jacobian(const double I[3], double J[2][3])
+{
+    double D2 = I[0] * I[0] + I[1] * I[1] + (I[2] + 1.0) * (I[2] + 1.0);
+    double D = sqrt(D2);
+    if (D == 0.0) {
+        memset(J, 0, sizeof(double) * 6);
+        return;
+    }
+    double D3 = D2 * D;
+    double dD[3] = {I[0], I[1], I[2] + 1.0}; /* times 1/D: dD/dI */
+    for (int r = 0; r < 2; r++)
+        for (int c = 0; c < 3; c++)
+            J[r][c] = SQRT2 * ((r == c ? 1.0 / D : 0.0) - I[r] * dD[c] / D3);
+}
+
+/* Gradient of the loss w.r.t. the view vector of one fragment, given
+ * dL/ds (per axis) accumulated over all buckets of the footprint:
+ * dL/dB = (n/2) dL/ds on unclamped axes (0 on clamped axes),
+ * dL/dA = J3^T dL/dB, dL/dI = J1^T dL/dA, dL/du = (1/L)(P) dL/dI with
+ * P = 1 - I I^T (normalisation), dL/dV = M^T dL/du. */
+static void view_gradient(const double M[9], const dirmap_t *d, int n, const double gs[2],
+                          double gV[3])
+{
+    gV[0] = gV[1] = gV[2] = 0.0;
+    if (!d->valid)
+        return;
+    double gB[2];
+    for (int k = 0; k < 2; k++)
+        gB[k] = d->clamped[k] ? 0.0 : gs[k] * n / 2.0;
+    double J3[2][2], J1[2][3];
+    square_jacobian(d->A, J3);
+    equisolid_jacobian(d->I, J1);
+    double gA[2] = {J3[0][0] * gB[0] + J3[1][0] * gB[1], J3[0][1] * gB[0] + J3[1][1] * gB[1]};
+    double gI[3];
+    for (int c = 0; c < 3; c++)
+        gI[c] = J1[0][c] * gA[0] + J1[1][c] * gA[1];
+    double dot = gI[0] * d->I[0] + gI[1] * d->I[1] + gI[2] * d->I[2];
+    double gu[3];
+    for (int c = 0; c < 3; c++)
+        gu[c] = (gI[c] - d->I[c] * dot) / d->L;
+    for (int m = 0; m < 3; m++)
+        gV[m] = M[0 * 3 + m] * gu[0] + M[1 * 3 + m] * gu[1] + M[2 * 3 + m] * gu[2];
+}
+
+/* Backward of N fragments with upstream gradient g[N][C] (binary32).
+ *   grad_tex   dL/d(texel) accumulated in fragment order, binary64, over the
+ *              bucket window [bi0, bi0+bw) x [bj0, bj0+bh) only (laid out
+ *              [bh][bw][n][n][C]); NULL skips it.  abs_tex receives the sum of
+ *              |weight * g| per element (the scale of the error criterion).
+ *   grad_view  dL/dV [N][3]; grad_uv dL/d(u,v) [N][2] (zero in nearest mode
+ *              away from bucket edges, where the lookup is piecewise constant
+ *              in u,v).  Either may be NULL.
+ * Taps that coincide (x1 = x0 at the clamp bound) each receive their own
+ * weight, so the texel gets the sum. */
+void orc_lookup_bwd(int64_t N, const float *uv, const float *tbn, const float *view,
+                    const float *g, int W, int H, int n, int C, int fmt, const void *data,
+                    const float *scales, int mode, double *grad_tex, double *abs_tex, int bi0,
+                    int bj0, int bw, int bh, double *grad_view, double *grad_uv)
+{
+    tex_t t = {W, H, n, C, fmt, data, scales};
+    if (grad_view || grad_uv) {
+#pragma omp parallel for schedule(static)
+        for (int64_t f = 0; f < N; f++) {
+            double U[2], M[9], V[3];
+            widen_fragment(uv, tbn, view, f, U, M, V);
+            dirmap_t d;
+            bucketfp_t bf;
+            map_direction(M, V, n, &d);
+            bucket_footprint(U[0], U[1], W, H, mode, &bf);
+            const float *gf = g + f * C;
+            double gs[2] = {0.0, 0.0};
+            double Lb[4] = {0, 0, 0, 0}; /* sum_c g_c * bilerp per footprint bucket */
+            for (int k = 0; k < bf.count; k++) {
+                int i = bf.i[k], j = bf.j[k];
+                for (int c = 0; c < C; c++) {
+                    double T00 = texel(&t, i, j, d.y0, d.x0, c);
+                    double T01 = texel(&t, i, j, d.y0, d.x1, c);
+                    double T10 = texel(&t, i, j, d.y1, d.x0, c);
+                    double T11 = texel(&t, i, j, d.y1, d.x1, c);
+                    double dsx = (1.0 - d.fy) * (T01 - T00) + d.fy * (T11 - T10);
+                    double dsy = (1.0 - d.fx) * (T10 - T00) + d.fx * (T11 - T01);
+                    gs[0] += bf.w[k] * gf[c] * dsx;
+                    gs[1] += bf.w[k] * gf[c] * dsy;
+                    Lb[k] += gf[c] * bilerp(&t, i, j, &d, c);
+                }
+            }
+            if (grad_view)
+                view_gradient(M, &d, n, gs, grad_view + 3 * f);
+            if (grad_uv) {
+                if (mode == ORC_MODE_NEAREST || !isfinite(U[0] - floor(U[0])) ||
+                    !isfinite(U[1] - floor(U[1]))) {
+                    grad_uv[2 * f] = grad_uv[2 * f + 1] = 0.0;
+                } else {
+                    /* d/du of sum_k w_k(a,b) L_k with a = frac(u) W - 1/2 */
+                    double a = bf.a, b = bf.b;
+                    grad_uv[2 * f + 0] =
+                        W * ((1.0 - b) * (Lb[1] - Lb[0]) + b * (Lb[3] - Lb[2]));
+                    grad_uv[2 * f + 1] =
+                        H * ((1.0 - a) * (Lb[2] - Lb[0]) + a * (Lb[3] - Lb[1]));
+                }
+            }
+        }
+    }
+    if (grad_tex) {
+        int64_t win = (int64_t)bw * bh * n * n * C;
+        memset(grad_tex, 0, sizeof(double) * win);
+        if (abs_tex)
+            memset(abs_tex, 0, sizeof(double) * win);
+        for (int64_t f = 0; f < N; f++) { /* fragment order: sequential */
+            double U[2], M[9], V[3];
+            widen_fragment(uv, tbn, view, f, U, M, V);
+            dirmap_t d;
+            bucketfp_t bf;
+            map_direction(M, V, n, &d);
+            bucket_footprint(U[0], U[1], W, H, mode, &bf);
+            const float *gf = g + f * C;
+            double wt[4] = {(1.0 - d.fx) * (1.0 - d.fy), d.fx * (1.0 - d.fy),
+                            (1.0 - d.fx) * d.fy, d.fx * d.fy};
+            int ty[4] = {d.y0, d.y0, d.y1, d.y1};
+            int tx[4] = {d.x0, d.x1, d.x0, d.x1};
+            for (int k = 0; k < bf.count; k++) {
+                int i = bf.i[k] - bi0, j = bf.j[k] - bj0;
+                if (i < 0 || i >= bw || j < 0 || j >= bh)
+                    continue;
+                for (int tap = 0; tap < 4; tap++) {
+                    int64_t base = ((((int64_t)j * bw + i) * n + ty[tap]) * n + tx[tap]) * C;
+                    for (int c = 0; c < C; c++) {
+                        double contrib = bf.w[k] * wt[tap] * gf[c];
+                        grad_tex[base + c] += contrib;
+                        if (abs_tex)
+                            abs_tex[base + c] += fabs(contrib);
+                    }
+                }
+            }
+        }
+    }
+}

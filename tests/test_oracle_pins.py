@@ -1,0 +1,618 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Nothing here compares the oracle with itself: each check is a closed form
+stated in the paper, a second formulation the paper gives, a brute-force
+search, an invariant of the method, a hand-derived worked example
+(tests/golden/worked_examples.txt), or an independent library routine.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "worked_examples.txt")
+
+
+def _rand_dirs(rng, k, zmin=0.0):
+    """Uniform directions on the cap z >= zmin (uniform in z and azimuth)."""
+    z = rng.uniform(zmin, 1.0, k)
+    phi = rng.uniform(0, 2 * np.pi, k)
+    r = np.sqrt(1 - z * z)
+    return np.stack([r * np.cos(phi), r * np.sin(phi), z], 1)
+
+
+def _rand_rot(rng):
+    q, r = np.linalg.qr(rng.normal(size=(3, 3)))
+    q = q * np.sign(np.diag(r))
+    if np.linalg.det(q) < 0:
+        q[:, 0] = -q[:, 0]
+    return q
+
+
+# --------------------------------------------------------------------------
+# Eq. (1a)/(1b): equisolid projection
+# --------------------------------------------------------------------------
+
+def test_equisolid_radius_closed_form():
+    # Sec. 2.1: the projected radius equals sqrt(2) sin(theta/2)
+    rng = np.random.default_rng(0)
+    I = _rand_dirs(rng, 2000, zmin=-0.999)
+    A = oracle.equisolid_tangent(I)
+    theta = np.arccos(np.clip(I[:, 2], -1, 1))
+    np.testing.assert_allclose(np.linalg.norm(A, axis=1), np.sqrt(2) * np.sin(theta / 2),
+                               atol=1e-14)
+    # the azimuth is kept: A is parallel to (I_x, I_y)
+    cross = A[:, 0] * I[:, 1] - A[:, 1] * I[:, 0]
+    assert np.max(np.abs(cross)) < 1e-14
+    assert np.all(A[:, 0] * I[:, 0] + A[:, 1] * I[:, 1] >= 0)
+
+
+def test_equisolid_rim_and_pole():
+    # Eq. (1): r = 1 at Omega = 180 deg, i.e. the horizon maps to |A| = 1
+    phi = np.linspace(0, 2 * np.pi, 37)
+    I = np.stack([np.cos(phi), np.sin(phi), np.zeros_like(phi)], 1)
+    A = oracle.equisolid_tangent(I)
+    np.testing.assert_allclose(np.linalg.norm(A, axis=1), 1.0, atol=1e-15)
+    assert np.all(oracle.equisolid_tangent([0, 0, 1.0]) == 0.0)
+
+
+def test_equisolid_preserves_area():
+    # Sec. 2.1: the projection preserves area, so for directions uniform on
+    # the hemisphere |A|^2 (= 1 - cos theta) is uniform on [0, 1].
+    from scipy import stats
+    rng = np.random.default_rng(1)
+    I = _rand_dirs(rng, 20000, zmin=0.0)
+    A = oracle.equisolid_tangent(I)
+    r2 = np.sum(A * A, axis=1)
+    assert stats.kstest(r2, "uniform").pvalue > 1e-3
+    # and areas scale by one constant: a cap of half-angle t (solid angle
+    # 2 pi (1 - cos t)) maps to a disc of area pi |A|^2 = half that solid
+    # angle, for every t (the hemisphere's 2 pi onto the unit disc's pi)
+    for t in np.radians([5.0, 30.0, 60.0, 89.0]):
+        rad = np.linalg.norm(oracle.equisolid_tangent([np.sin(t), 0, np.cos(t)]))
+        assert abs(np.pi * rad ** 2 - 0.5 * 2 * np.pi * (1 - np.cos(t))) < 1e-14
+
+
+def test_general_normal_form_matches_tangent_form():
+    # Eq. (1a) for an arbitrary unit normal N, expressed in a frame (T, B, N),
+    # equals Eq. (1b) applied to the incidence moved into that frame.
+    rng = np.random.default_rng(2)
+    for _ in range(300):
+        R = _rand_rot(rng)  # rows T, B, N
+        It = _rand_dirs(rng, 1, zmin=-0.9)[0]
+        Iw = R.T @ It
+        g = oracle.equisolid_general(Iw, R[2])[0]
+        A_general = np.array([R[0] @ g, R[1] @ g])
+        A_tangent = oracle.equisolid_tangent(It)[0]
+        np.testing.assert_allclose(A_general, A_tangent, atol=1e-14)
+        # third component of Eq. (1a): sqrt(2) cos(theta/2)
+        theta = np.arccos(np.clip(It[2], -1, 1))
+        assert abs(R[2] @ g - np.sqrt(2) * np.cos(theta / 2)) < 1e-14
+
+
+def test_inverse_equisolid_round_trip():
+    # Eq. (2c) inverts Eq. (1b) on the whole sphere except -N
+    rng = np.random.default_rng(3)
+    I = _rand_dirs(rng, 3000, zmin=-0.99)
+    A = oracle.equisolid_tangent(I)
+    I2 = oracle.inverse_equisolid_tangent(A)
+    np.testing.assert_allclose(I2, I, atol=1e-13)
+    A2 = rng.uniform(-1, 1, (3000, 2)) * 0.7
+    np.testing.assert_allclose(oracle.equisolid_tangent(oracle.inverse_equisolid_tangent(A2)),
+                               A2, atol=1e-14)
+
+
+def test_inverse_general_reduces_to_tangent_form():
+    # Eq. (2b) with N = e_z is Eq. (2c)
+    rng = np.random.default_rng(4)
+    A = rng.uniform(-1, 1, (500, 2)) * 0.7
+    Ig = oracle.inverse_equisolid_general(A, np.tile([0.0, 0.0, 1.0], (500, 1)))
+    It = oracle.inverse_equisolid_tangent(A)
+    np.testing.assert_allclose(Ig, It, atol=1e-14)
+    # Eq. (2b) is a reflection: |I| = 1 and I + N is parallel to the half vector
+    np.testing.assert_allclose(np.linalg.norm(Ig, axis=1), 1.0, atol=1e-14)
+
+
+def test_reflection_vector_is_mirror_of_incidence():
+    # Eq. (4b): R is the incidence of Eq. (2c) mirrored about the normal
+    rng = np.random.default_rng(5)
+    A = rng.uniform(-1, 1, (500, 2)) * 0.7
+    R = oracle.reflection(A)
+    I = oracle.inverse_equisolid_tangent(A)
+    np.testing.assert_allclose(R, np.stack([-I[:, 0], -I[:, 1], I[:, 2]], 1), atol=1e-15)
+    # and it is the reflection of -I about N = e_z: R = 2 (N . I) N - I ... with
+    # the tangential part flipped: R . N = I . N, R_t = -I_t
+    np.testing.assert_allclose(R[:, 2], I[:, 2], atol=1e-15)
+
+
+# --------------------------------------------------------------------------
+# Eq. (3)/(4a): disc <-> square
+# --------------------------------------------------------------------------
+
+def test_square_map_properties():
+    rng = np.random.default_rng(6)
+    A = rng.uniform(-1, 1, (5000, 2))
+    A = A[np.linalg.norm(A, axis=1) <= 1]
+    B = oracle.square(A)
+    # |B|_inf = |A|_2 (the disc of radius r goes to the square of half-side r)
+    np.testing.assert_allclose(np.max(np.abs(B), axis=1), np.linalg.norm(A, axis=1), atol=1e-15)
+    # direction kept
+    assert np.max(np.abs(A[:, 0] * B[:, 1] - A[:, 1] * B[:, 0])) < 1e-15
+    # Eq. (4a) inverts it, both ways
+    np.testing.assert_allclose(oracle.unsquare(B), A, atol=1e-15)
+    S = rng.uniform(-1, 1, (3000, 2))
+    np.testing.assert_allclose(oracle.square(oracle.unsquare(S)), S, atol=1e-15)
+    # on the axes the map is the identity; the unit disc fills [-1,1]^2
+    ax = np.array([[0.3, 0.0], [0.0, -0.8], [-1.0, 0.0]])
+    np.testing.assert_allclose(oracle.square(ax), ax, atol=0)
+    assert np.all(oracle.square([0.0, 0.0]) == 0.0)
+    d = 1 / np.sqrt(2)
+    np.testing.assert_allclose(oracle.square([d, d])[0], [1.0, 1.0], atol=1e-15)
+
+
+def test_square_map_d4_equivariance():
+    rng = np.random.default_rng(7)
+    A = rng.uniform(-1, 1, (1000, 2))
+    B = oracle.square(A)
+    np.testing.assert_allclose(oracle.square(A[:, ::-1]), B[:, ::-1], atol=1e-15)
+    np.testing.assert_allclose(oracle.square(A * [-1, 1]), B * [-1, 1], atol=1e-15)
+    np.testing.assert_allclose(oracle.square(A * [1, -1]), B * [1, -1], atol=1e-15)
+
+
+# --------------------------------------------------------------------------
+# bucket-edge clamp and texel coordinate
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n", [2, 3, 4, 8, 16])
+def test_clamp_maps_to_outer_texel_centres(n):
+    # The Note after Eq. (3): B clamped to [1/n - 1, 1 - 1/n]; the texel
+    # centre reading turns that range into exactly [0, n - 1].
+    lo, hi = 1.0 / n - 1.0, 1.0 - 1.0 / n
+    s = oracle.texel_coord([[lo, hi], [-1.0, 1.0], [-5.0, 7.0], [0.0, 0.0]], n)
+    np.testing.assert_allclose(s[0], [0.0, n - 1.0], atol=1e-12)
+    assert np.all(s[1] == [0.0, n - 1.0]) and np.all(s[2] == [0.0, n - 1.0])
+    np.testing.assert_allclose(s[3], [(n - 1) / 2.0] * 2, atol=1e-15)
+    # sample k's centre in B-space is (2k + 1)/n - 1
+    k = np.arange(n)
+    Bc = (2 * k + 1.0) / n - 1.0
+    sc = oracle.texel_coord(np.stack([Bc, Bc[::-1]], 1), n)
+    np.testing.assert_allclose(sc[:, 0], k, atol=1e-12)
+    np.testing.assert_allclose(sc[:, 1], k[::-1], atol=1e-12)
+
+
+def test_worked_examples():
+    rows = [l.split() for l in open(GOLDEN) if l.strip() and not l.startswith("#")]
+    assert len(rows) >= 7
+    for r in rows:
+        name, n = r[0], int(r[1])
+        V = np.array([float(x) for x in r[2:5]])
+        exp = np.array([float(x) for x in r[5:11]])
+        x0, y0 = int(r[11]), int(r[12])
+        fx, fy = float(r[13]), float(r[14])
+        got = oracle.map_one(np.eye(3), V, n)
+        np.testing.assert_allclose(got, exp, atol=2e-14, err_msg=name)
+        uv = np.array([[0.5, 0.5]], np.float32)
+        idx, frac, _ = oracle.indices(uv, np.eye(3, dtype=np.float32)[None],
+                                      V.astype(np.float32)[None], 4, 4, n)
+        assert (idx[0, 2], idx[0, 3]) == (x0, y0), name
+        np.testing.assert_allclose(frac[0], [fx, fy], atol=1e-6, err_msg=name)
+
+
+def test_brute_force_inverse_search():
+    # For a direction I, search a fine grid of bucket coordinates B for the one
+    # whose inverse-mapped direction (Eq. 4a then Eq. 2c) is closest to I; it
+    # must be the B the forward chain (Eq. 1b then Eq. 3) produces.
+    rng = np.random.default_rng(8)
+    g = np.linspace(-1, 1, 801)
+    GX, GY = np.meshgrid(g, g, indexing="xy")
+    Bgrid = np.stack([GX.ravel(), GY.ravel()], 1)
+    # vectorised inverse (restated only for the grid search)
+    rho = np.linalg.norm(Bgrid, axis=1)
+    m = np.max(np.abs(Bgrid), axis=1)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        Agrid = np.where(rho[:, None] > 0, Bgrid * (m / rho)[:, None], 0.0)
+    r2 = np.sum(Agrid ** 2, 1)
+    w = np.sqrt(np.maximum(0, 2 - r2))
+    Igrid = np.stack([Agrid[:, 0] * w, Agrid[:, 1] * w, 1 - r2], 1)
+    # spot check the vectorised inverse against the oracle's Eqs. (4a)/(2c)
+    pick = rng.integers(0, len(Bgrid), 50)
+    np.testing.assert_allclose(
+        oracle.inverse_equisolid_tangent(oracle.unsquare(Bgrid[pick])), Igrid[pick], atol=1e-14)
+    for I in _rand_dirs(rng, 40, zmin=0.05):
+        B = oracle.square(oracle.equisolid_tangent(I))[0]
+        k = np.argmax(Igrid @ I)
+        assert np.max(np.abs(Bgrid[k] - B)) <= 2.5 / 800 + 1e-12
+
+
+# --------------------------------------------------------------------------
+# whole lookup: bucket selection, bilinear fetch, invariants
+# --------------------------------------------------------------------------
+
+def _tex(rng, W, H, n, C):
+    return rng.uniform(0, 1, (H, W, n, n, C)).astype(np.float32)
+
+
+def test_bucket_index_brute_force():
+    # Sec. 2: u,v index the bucket matrix; the bucket of a coordinate is the
+    # cell interval [i/W, (i+1)/W) containing frac(u) (UV wrap).
+    rng = np.random.default_rng(9)
+    for W in (1, 3, 5, 7, 64):
+        u = rng.uniform(-3, 3, 4000).astype(np.float32)
+        v = rng.uniform(-3, 3, 4000).astype(np.float32)
+        uv = np.stack([u, v], 1)
+        N = len(u)
+        idx, _, edge = oracle.indices(uv, np.tile(np.eye(3, dtype=np.float32), (N, 1, 1)),
+                                      np.tile(np.float32([0, 0, 1]), (N, 1)), W, W, 4)
+        fu = np.float64(u) - np.floor(np.float64(u))
+        for k in range(N):
+            cells = [i for i in range(W) if i / W <= fu[k] < (i + 1) / W]
+            assert idx[k, 0] == cells[0]
+        assert np.all((idx[:, :2] >= 0) & (idx[:, :2] < W))
+
+
+def test_bilinear_equals_tent_filter_brute_force():
+    # out = sum over all n^2 samples of tent(s_x - x) tent(s_y - y) T[y, x],
+    # an independent form of the bilinear fetch inside the bucket.
+    rng = np.random.default_rng(10)
+    W = H = 3
+    for n in (2, 3, 5, 8):
+        C = 2
+        T = _tex(rng, W, H, n, C)
+        tex = oracle.Tex(T, W, H, n, C)
+        N = 300
+        uv = rng.uniform(0, 1, (N, 2)).astype(np.float32)
+        V = _rand_dirs(rng, N, zmin=-0.3).astype(np.float32)
+        tbn = np.tile(np.eye(3, dtype=np.float32), (N, 1, 1))
+        out = oracle.lookup_fwd(tex, uv, tbn, V)
+        idx, _, _ = oracle.indices(uv, tbn, V, W, H, n)
+        for f in range(N):
+            s = oracle.map_one(np.eye(3), V[f].astype(np.float64), n)[4:6]
+            xs = np.arange(n)
+            wx = np.maximum(0, 1 - np.abs(s[0] - xs))
+            wy = np.maximum(0, 1 - np.abs(s[1] - xs))
+            bucket = T[idx[f, 1], idx[f, 0]].astype(np.float64)  # [n(y), n(x), C]
+            ref = np.einsum("y,x,yxc->c", wy, wx, bucket)
+            np.testing.assert_allclose(out[f], ref, atol=1e-14)
+
+
+def test_lookup_invariants():
+    rng = np.random.default_rng(11)
+    W, H, n, C = 4, 3, 8, 3
+    T = _tex(rng, W, H, n, C)
+    tex = oracle.Tex(T, W, H, n, C)
+    N = 500
+    uv = rng.uniform(-2, 2, (N, 2)).astype(np.float32)
+    V = _rand_dirs(rng, N, zmin=0.0).astype(np.float32)
+    eye = np.tile(np.eye(3, dtype=np.float32), (N, 1, 1))
+    out = oracle.lookup_fwd(tex, uv, eye, V)
+    idx, _, _ = oracle.indices(uv, eye, V, W, H, n)
+    # normal incidence -> mean of the four centre samples (even n)
+    Vn = np.tile(np.float32([0, 0, 1]), (N, 1))
+    on = oracle.lookup_fwd(tex, uv, eye, Vn)
+    c = n // 2
+    for f in range(0, N, 37):
+        b = T[idx[f, 1], idx[f, 0]].astype(np.float64)
+        np.testing.assert_allclose(on[f], b[c - 1:c + 1, c - 1:c + 1].mean(axis=(0, 1)),
+                                   atol=1e-15)
+    # constant texture -> constant image
+    oc = oracle.lookup_fwd(oracle.Tex(np.full_like(T, 0.375), W, H, n, C), uv, eye, V)
+    assert np.all(oc == 0.375)
+    # output inside the convex hull of its bucket
+    for f in range(N):
+        b = T[idx[f, 1], idx[f, 0]].reshape(-1, C)
+        assert np.all(out[f] >= b.min(0) - 1e-15) and np.all(out[f] <= b.max(0) + 1e-15)
+    # changing every other bucket leaves the output unchanged (no cross-bucket
+    # blending, the Note after Eq. (3))
+    for f in range(0, N, 50):
+        T2 = _tex(rng, W, H, n, C)
+        T2[idx[f, 1], idx[f, 0]] = T[idx[f, 1], idx[f, 0]]
+        o2 = oracle.lookup_fwd(oracle.Tex(T2, W, H, n, C), uv[f:f + 1], eye[:1], V[f:f + 1])
+        np.testing.assert_array_equal(o2[0], out[f])
+    # the same lookup with a rotated world: rotating V and the frame together
+    R = _rand_rot(rng).astype(np.float64)
+    Mrot = np.tile((np.eye(3) @ R.T).astype(np.float32), (N, 1, 1))
+    Vrot = (V.astype(np.float64) @ R.T).astype(np.float32)
+    orot = oracle.lookup_fwd(tex, uv, Mrot, Vrot)
+    assert np.max(np.abs(orot - out)) < 5e-6  # float32 storage of the rotated inputs
+    # scale invariance: the view need not be unit (a power of two keeps the
+    # float32 direction exact)
+    np.testing.assert_allclose(oracle.lookup_fwd(tex, uv, eye, V * 4.0), out, atol=1e-12)
+    np.testing.assert_allclose(oracle.lookup_fwd(tex, uv, eye, V * 0.125), out, atol=1e-12)
+
+
+def test_lookup_mirror_symmetry():
+    # mirroring the view in x and the texture inside every bucket in x gives
+    # the same output (and likewise y, and the transpose x <-> y)
+    rng = np.random.default_rng(12)
+    W, H, n, C = 2, 2, 8, 2
+    T = _tex(rng, W, H, n, C)
+    N = 400
+    uv = rng.uniform(0, 1, (N, 2)).astype(np.float32)
+    V = _rand_dirs(rng, N, zmin=0.0).astype(np.float32)
+    eye = np.tile(np.eye(3, dtype=np.float32), (N, 1, 1))
+    out = oracle.lookup_fwd(oracle.Tex(T, W, H, n, C), uv, eye, V)
+    Tx = np.ascontiguousarray(T[:, :, :, ::-1, :])
+    ox = oracle.lookup_fwd(oracle.Tex(Tx, W, H, n, C), uv, eye, V * np.float32([-1, 1, 1]))
+    np.testing.assert_allclose(ox, out, atol=1e-12)
+    Ty = np.ascontiguousarray(T[:, :, ::-1, :, :])
+    oy = oracle.lookup_fwd(oracle.Tex(Ty, W, H, n, C), uv, eye, V * np.float32([1, -1, 1]))
+    np.testing.assert_allclose(oy, out, atol=1e-12)
+    Tt = np.ascontiguousarray(np.swapaxes(T, 2, 3))
+    ot = oracle.lookup_fwd(oracle.Tex(Tt, W, H, n, C), uv, eye,
+                           np.ascontiguousarray(V[:, [1, 0, 2]]))
+    np.testing.assert_allclose(ot, out, atol=1e-12)
+
+
+def test_bilinear_bucket_mode_reduces_to_nearest_at_centres():
+    # bilinear-bucket mode sampled at bucket centres equals nearest mode, and
+    # is a convex combination of the four neighbouring buckets otherwise
+    rng = np.random.default_rng(13)
+    W, H, n, C = 4, 8, 4, 3  # powers of two: bucket centres are exact in float32
+    T = _tex(rng, W, H, n, C)
+    tex = oracle.Tex(T, W, H, n, C)
+    N = 60
+    ij = np.stack([rng.integers(0, W, N), rng.integers(0, H, N)], 1)
+    uv = ((ij + 0.5) / [W, H]).astype(np.float32)
+    V = _rand_dirs(rng, N, 0.1).astype(np.float32)
+    eye = np.tile(np.eye(3, dtype=np.float32), (N, 1, 1))
+    a = oracle.lookup_fwd(tex, uv, eye, V, mode=oracle.MODE_NEAREST)
+    b = oracle.lookup_fwd(tex, uv, eye, V, mode=oracle.MODE_BILINEAR)
+    np.testing.assert_allclose(a, b, atol=1e-12)
+    # halfway between columns i and i+1 (wrapping): average of the two
+    uvh = ((ij + [1.0, 0.5]) / [W, H]).astype(np.float32)
+    bh = oracle.lookup_fwd(tex, uvh, eye, V, mode=oracle.MODE_BILINEAR)
+    nb0 = oracle.lookup_fwd(tex, ((ij + [0.5, 0.5]) / [W, H]).astype(np.float32), eye, V)
+    ij1 = ij.copy()
+    ij1[:, 0] = (ij1[:, 0] + 1) % W
+    nb1 = oracle.lookup_fwd(tex, ((ij1 + [0.5, 0.5]) / [W, H]).astype(np.float32), eye, V)
+    np.testing.assert_allclose(bh, 0.5 * (nb0 + nb1), atol=1e-6)
+
+
+# --------------------------------------------------------------------------
+# storage formats and the quantiser
+# --------------------------------------------------------------------------
+
+def test_e4m3_decode_matches_torch():
+    codes = torch.arange(256, dtype=torch.uint8)
+    ref = codes.view(torch.float8_e4m3fn).to(torch.float64).numpy()
+    mine = np.array([oracle.e4m3_to_f64(c) for c in range(256)])
+    finite = np.isfinite(ref)
+    assert np.array_equal(np.isnan(mine), ~finite)
+    np.testing.assert_array_equal(mine[finite], ref[finite])
+    assert oracle.e4m3_to_f64(0x7E) == 448.0 and oracle.e4m3_to_f64(0x01) == 2.0 ** -9
+
+
+def _e4m3_test_values():
+    # every representable value, every midpoint, and one ulp either side
+    vals = np.array([oracle.e4m3_to_f64(c) for c in range(0x7F)], np.float64)
+    mids = (vals[:-1] + vals[1:]) / 2
+    m32 = mids.astype(np.float32)
+    pts = np.concatenate([vals.astype(np.float32), m32, np.nextafter(m32, np.float32(0)),
+                          np.nextafter(m32, np.float32(1e9))])
+    rng = np.random.default_rng(14)
+    pts = np.concatenate([pts, rng.uniform(0, 448, 20000).astype(np.float32),
+                          np.exp2(rng.uniform(-14, 8.8, 20000)).astype(np.float32)])
+    pts = pts[pts <= 448]
+    return np.concatenate([pts, -pts]).astype(np.float32)
+
+
+def test_e4m3_encode_matches_torch():
+    # torch's float8_e4m3fn conversion (round to nearest even) is an
+    # independent implementation; inside the finite range the two agree
+    x = _e4m3_test_values()
+    ref = torch.from_numpy(x).to(torch.float8_e4m3fn).view(torch.uint8).numpy()
+    lib = oracle._load()
+    mine = np.array([lib.orc_f32_to_e4m3_sat(float(v)) for v in x], np.uint8)
+    np.testing.assert_array_equal(mine, ref)
+    # saturation: beyond 448 (and infinity) the code is +-448, NaN stays NaN
+    for v, c in ((449.0, 0x7E), (1e30, 0x7E), (float("inf"), 0x7E), (-500.0, 0xFE)):
+        assert oracle.f32_to_e4m3(v) == c
+    assert oracle.f32_to_e4m3(float("nan")) & 0x7F == 0x7F
+
+
+def test_bf16_encode_matches_torch():
+    rng = np.random.default_rng(15)
+    bits = rng.integers(0, 2 ** 32, 200000, dtype=np.uint64).astype(np.uint32)
+    # halfway cases and their neighbours
+    half = (rng.integers(0, 2 ** 16, 20000, dtype=np.uint64).astype(np.uint32) << 16) | 0x8000
+    bits = np.concatenate([bits, half, half + 1, half - 1])
+    x = bits.view(np.float32)
+    x = x[np.isfinite(x)]
+    ref = torch.from_numpy(x).to(torch.bfloat16).view(torch.int16).numpy().view(np.uint16)
+    lib = oracle._load()
+    mine = np.array([lib.orc_f32_to_bf16_rne(float(v)) for v in x], np.uint16)
+    np.testing.assert_array_equal(mine, ref)
+
+
+def test_quantize_per_bucket_scale():
+    rng = np.random.default_rng(16)
+    nb, be = 50, 64
+    T = (rng.uniform(-1, 1, (nb, be)) * np.exp2(rng.uniform(-12, 6, (nb, 1)))).astype(np.float32)
+    T[3] = 0.0  # all-zero bucket: scale 1, codes 0
+    codes, scales = oracle.quantize(T, nb, be, oracle.FMT_FP8_E4M3)
+    codes = codes.reshape(nb, be)
+    amax = np.max(np.abs(T), axis=1)
+    for b in range(nb):
+        if amax[b] == 0:
+            assert scales[b] == 1.0 and np.all(codes[b] == 0)
+            continue
+        assert scales[b] == np.float32(amax[b]) / np.float32(448.0)
+        # the largest magnitude goes to the largest code
+        assert np.max(codes[b] & 0x7F) == 0x7E
+        dec = np.array([oracle.e4m3_to_f64(c) for c in codes[b]]) * np.float64(scales[b])
+        # relative error of E4M3 in the normal range is at most 2^-4; the
+        # absolute error below the normal range at most half a subnormal step
+        err = np.abs(dec - T[b])
+        bound = np.maximum(np.abs(T[b]) * 2.0 ** -4, 2.0 ** -10 * scales[b]) * 1.0001
+        assert np.all(err <= bound)
+    c16, s16 = oracle.quantize(T, nb, be, oracle.FMT_BF16)
+    assert s16 is None
+    ref = torch.from_numpy(T.reshape(-1)).to(torch.bfloat16).view(torch.int16).numpy()
+    np.testing.assert_array_equal(c16, ref.view(np.uint16))
+
+
+def test_quantized_lookup_decodes_exactly():
+    # the oracle's BF16/FP8 lookup equals its FP32 lookup on the decoded texture
+    rng = np.random.default_rng(17)
+    W, H, n, C = 3, 3, 8, 4
+    T = _tex(rng, W, H, n, C)
+    N = 200
+    uv = rng.uniform(0, 1, (N, 2)).astype(np.float32)
+    V = _rand_dirs(rng, N, 0.05).astype(np.float32)
+    eye = np.tile(np.eye(3, dtype=np.float32), (N, 1, 1))
+    codes, scales = oracle.quantize(T, W * H, n * n * C, oracle.FMT_FP8_E4M3)
+    dec = (np.array([oracle.e4m3_to_f64(c) for c in range(256)])[codes].reshape(W * H, -1)
+           * scales[:, None].astype(np.float64))
+    o8 = oracle.lookup_fwd(oracle.Tex(codes, W, H, n, C, oracle.FMT_FP8_E4M3, scales), uv, eye, V)
+    o64 = oracle.lookup_fwd(oracle.Tex(dec.reshape(-1), W, H, n, C, oracle.FMT_F64), uv, eye, V)
+    np.testing.assert_allclose(o8, o64, atol=1e-15)
+    c16, _ = oracle.quantize(T, W * H, n * n * C, oracle.FMT_BF16)
+    d16 = torch.from_numpy(c16.view(np.int16)).view(torch.bfloat16).to(torch.float64).numpy()
+    o16 = oracle.lookup_fwd(oracle.Tex(c16, W, H, n, C, oracle.FMT_BF16), uv, eye, V)
+    o64b = oracle.lookup_fwd(oracle.Tex(d16, W, H, n, C, oracle.FMT_F64), uv, eye, V)
+    np.testing.assert_allclose(o16, o64b, atol=1e-15)
+
+
+# --------------------------------------------------------------------------
+# backward: finite differences and exact identities
+# --------------------------------------------------------------------------
+
+def _away_from_kinks(tbn, V, n, margin=2e-3):
+    """True when the direction is away from every non-smooth point of the
+    lookup: texel lines, clamp bounds, the diagonal |A_x| = |A_y|, A = 0."""
+    a = oracle.map_one(tbn, V, n)
+    A, B = a[0:2], a[2:4]
+    su = (B + 1) * n / 2 - 0.5
+    if np.any(np.abs(su - np.round(su)) < margin * n) and True:
+        return False
+    if abs(abs(A[0]) - abs(A[1])) < margin or np.linalg.norm(A) < margin:
+        return False
+    return True
+
+
+def _fd_setup(seed, mode, W=4, H=4, n=8, C=3, N=60):
+    rng = np.random.default_rng(seed)
+    T = _tex(rng, W, H, n, C)
+    tex = oracle.Tex(T, W, H, n, C)
+    uv = rng.uniform(-1, 2, (N, 2)).astype(np.float32)
+    Vs, Ms = [], []
+    while len(Vs) < N:
+        R = _rand_rot(rng) if rng.uniform() < 0.5 else np.eye(3)
+        Vt = _rand_dirs(rng, 1, zmin=0.02)[0] * rng.uniform(0.5, 2.0)
+        M = R.astype(np.float32).astype(np.float64)
+        V = (R.T @ Vt).astype(np.float32).astype(np.float64)
+        if _away_from_kinks(M.reshape(9), V, n):
+            Vs.append(V)
+            Ms.append(M)
+    return rng, tex, uv, np.array(Ms, np.float32), np.array(Vs, np.float32)
+
+
+@pytest.mark.parametrize("mode", [oracle.MODE_NEAREST, oracle.MODE_BILINEAR])
+def test_grad_view_finite_differences(mode):
+    rng, tex, uv, tbn, V = _fd_setup(20 + mode, mode)
+    N = len(V)
+    g = rng.normal(size=(N, tex.C)).astype(np.float32)
+    res = oracle.lookup_bwd(tex, uv, tbn, V, g, mode=mode)
+    h = 1e-6
+    for f in range(N):
+        U = uv[f].astype(np.float64)
+        M = tbn[f].astype(np.float64)
+        fd = np.zeros(3)
+        for k in range(3):
+            Vp = V[f].astype(np.float64).copy()
+            Vm = Vp.copy()
+            Vp[k] += h
+            Vm[k] -= h
+            op = oracle.lookup_one_f64(tex, U, M, Vp, mode)
+            om = oracle.lookup_one_f64(tex, U, M, Vm, mode)
+            fd[k] = np.dot(g[f].astype(np.float64), (op - om) / (2 * h))
+        gv = res["grad_view"][f]
+        assert np.linalg.norm(gv - fd) <= 1e-6 * max(1.0, np.linalg.norm(fd)), (f, gv, fd)
+        # the lookup depends on the direction of V only
+        assert abs(np.dot(gv, V[f])) <= 1e-9 * max(1.0, np.linalg.norm(gv) * np.linalg.norm(V[f]))
+
+
+def test_grad_uv_finite_differences_bilinear_bucket_mode():
+    rng, tex, uv, tbn, V = _fd_setup(30, oracle.MODE_BILINEAR)
+    N = len(V)
+    g = rng.normal(size=(N, tex.C)).astype(np.float32)
+    res = oracle.lookup_bwd(tex, uv, tbn, V, g, mode=oracle.MODE_BILINEAR)
+    h = 1e-7
+    checked = 0
+    for f in range(N):
+        U = uv[f].astype(np.float64)
+        p = (U - np.floor(U)) * [tex.W, tex.H] - 0.5
+        if np.any(np.abs(p - np.round(p)) < 1e-3):
+            continue
+        fd = np.zeros(2)
+        for k in range(2):
+            Up, Um = U.copy(), U.copy()
+            Up[k] += h
+            Um[k] -= h
+            op = oracle.lookup_one_f64(tex, Up, tbn[f], V[f], oracle.MODE_BILINEAR)
+            om = oracle.lookup_one_f64(tex, Um, tbn[f], V[f], oracle.MODE_BILINEAR)
+            fd[k] = np.dot(g[f].astype(np.float64), (op - om) / (2 * h))
+        np.testing.assert_allclose(res["grad_uv"][f], fd, rtol=1e-6, atol=1e-6)
+        checked += 1
+    assert checked > N // 2
+    # nearest mode: piecewise constant in u, v
+    res0 = oracle.lookup_bwd(tex, uv, tbn, V, g, mode=oracle.MODE_NEAREST)
+    assert np.all(res0["grad_uv"] == 0.0)
+
+
+@pytest.mark.parametrize("mode", [oracle.MODE_NEAREST, oracle.MODE_BILINEAR])
+def test_grad_tex_adjoint_and_conservation(mode):
+    # the lookup is linear in the texture, so <grad_tex, T> = <g, out> and a
+    # finite difference in one texel is exact up to rounding; every fragment's
+    # weights sum to one, so sum over texels of grad_tex = sum of g.
+    rng = np.random.default_rng(40 + mode)
+    W, H, n, C = 5, 4, 8, 3
+    T = _tex(rng, W, H, n, C)
+    tex = oracle.Tex(T, W, H, n, C)
+    N = 3000
+    uv = rng.uniform(-1, 2, (N, 2)).astype(np.float32)
+    V = _rand_dirs(rng, N, zmin=-0.2).astype(np.float32)
+    tbn = np.tile(np.eye(3, dtype=np.float32), (N, 1, 1))
+    g = rng.normal(size=(N, C)).astype(np.float32)
+    out = oracle.lookup_fwd(tex, uv, tbn, V, mode=mode)
+    res = oracle.lookup_bwd(tex, uv, tbn, V, g, mode=mode)
+    G = res["grad_tex"]
+    lhs = np.sum(G * T.astype(np.float64))
+    rhs = np.sum(g.astype(np.float64) * out)
+    assert abs(lhs - rhs) <= 1e-11 * np.sum(np.abs(g) * np.abs(out))
+    np.testing.assert_allclose(G.sum(axis=(0, 1, 2, 3)), g.astype(np.float64).sum(0), atol=1e-10)
+    assert np.all(res["abs_tex"] >= np.abs(G) - 1e-15)
+    if mode == oracle.MODE_NEAREST:
+        idx, _, _ = oracle.indices(uv, tbn, V, W, H, n)
+        for b in [(0, 0), (2, 3), (4, 1)]:
+            sel = (idx[:, 0] == b[0]) & (idx[:, 1] == b[1])
+            np.testing.assert_allclose(G[b[1], b[0]].sum(axis=(0, 1)),
+                                       g[sel].astype(np.float64).sum(0), atol=1e-11)
+    # finite difference in single texels (float64 texture)
+    T64 = T.astype(np.float64)
+    for _ in range(5):
+        j, i, y, x, c = (rng.integers(0, s) for s in (H, W, n, n, C))
+        Tp = T64.copy()
+        Tp[j, i, y, x, c] += 0.5
+        op = oracle.lookup_fwd(oracle.Tex(Tp, W, H, n, C, oracle.FMT_F64), uv, tbn, V, mode=mode)
+        fd = np.sum(g.astype(np.float64) * (op - out)) / 0.5
+        assert abs(fd - G[j, i, y, x, c]) <= 1e-9 * max(1.0, abs(fd))
+
+
+def test_grad_tex_window_matches_full():
+    rng = np.random.default_rng(50)
+    W, H, n, C = 6, 5, 4, 2
+    T = _tex(rng, W, H, n, C)
+    tex = oracle.Tex(T, W, H, n, C)
+    N = 800
+    uv = rng.uniform(0, 1, (N, 2)).astype(np.float32)
+    V = _rand_dirs(rng, N, 0.0).astype(np.float32)
+    tbn = np.tile(np.eye(3, dtype=np.float32), (N, 1, 1))
+    g = rng.normal(size=(N, C)).astype(np.float32)
+    full = oracle.lookup_bwd(tex, uv, tbn, V, g)["grad_tex"]
+    win = oracle.lookup_bwd(tex, uv, tbn, V, g, window=(2, 1, 3, 2))["grad_tex"]
+    np.testing.assert_array_equal(win, full[1:3, 2:5])
