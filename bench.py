@@ -1,0 +1,300 @@
+"""Benchmark of the radiance-bucket lookup hot path on one MI355X.
+
+Workload (default): the single-view configuration -- a 1024 x 1024 bucket
+matrix of 16 x 16 RGBA samples (smooth synthetic radiance, FP32 master copy,
+4.29 GB) seen by one 1920 x 1080 perspective view of a UV-tiled plane with
+perturbed normals.  One step is one pass of the whole hot path over that
+batch, as a fitting loop runs it:
+
+    quantise   FP32 master texture -> BF16 storage          (rt_quantize)
+    forward    per-fragment lookup from the BF16 texture     (rt_lookup_fwd)
+    backward   dL/dtexture (dense, deterministic), dL/dview,
+               dL/duv for i.i.d. N(0,1) upstream gradients   (rt_lookup_bwd)
+
+All inputs are resident in HBM before timing starts.  `value` is fragments
+(lookups) per second of the whole step.  The JSON line also carries per-format
+forward numbers (FP32 / BF16 / FP8 storage), the roofline of the dominant
+kernel measured with HIP events on the launch stream, and the FP64 CPU oracle
+timed on a bounded sample of the same workload.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+    python bench.py --calibrate-copy     (plain copy kernel for the PMC scale)
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "lookups/s + % HBM peak, fwd & bwd; FP32 vs BF16/FP8 texture at stated error"
+HBM_PEAK_GBS = 8000.0
+KERNEL_SOURCES = ["rt_device.hpp", "rt_lookup.hip", "rt_quantize.hip", "rt_backward.hip"]
+
+
+def source_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2301_01719_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def pmc_traffic(kernel: str, workload: str):
+    """HBM bytes per launch from a committed rocprofv3 PMC summary, or None when
+    the summary is missing or was taken on different kernel sources."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_pmc.txt")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("source_hash") != source_hash():
+        return None
+    try:
+        return float(vals["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="c2")
+    ap.add_argument("--storage", default="bf16", choices=["f32", "bf16", "fp8"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true")
+    ap.add_argument("--profile-steps", type=int, default=0,
+                    help="run only this many steps (for rocprofv3) and print the line")
+    return ap.parse_args()
+
+
+def calibrate_copy():
+    import torch
+    n = 1 << 28  # 1 GiB of float32
+    src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"calibrate_copy_bytes_read": n * 4, "calibrate_copy_bytes_written": n * 4,
+                      "launches": 5}), flush=True)
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: the lookup needs no communication and this build "
+              "runs on a single MI355X (see the sharding notes in DESIGN.md); use --gpus 1",
+              file=sys.stderr)
+        sys.exit(2)
+    if args.calibrate_copy:
+        calibrate_copy()
+        return
+
+    import numpy as np
+    import torch
+
+    from paper_2301_01719_amd import radtex as rt
+    from paper_2301_01719_amd import workloads as wl
+
+    dev = "cuda:0"
+    w = wl.WORKLOADS[args.workload]
+    W, H, n, C = w.W, w.H, w.n, w.C
+    t_setup = time.time()
+    tex32 = w.make_texture(dev)
+    gb = w.make_gbuffer(dev)
+    N = gb.count
+    go = wl.grad_out(N, C, seed=w.seed, device=dev)
+    torch.cuda.synchronize()
+    print(f"# inputs ready in {time.time() - t_setup:.1f} s: {W}x{H} buckets of {n}x{n}x{C}, "
+          f"{N} fragments", file=sys.stderr, flush=True)
+
+    master = rt.Texture(tex32, W, H, n, C)
+    E = W * H * n * n * C
+    storage = {}
+    if args.storage != "f32":
+        codes, scales = rt.quantize(master, args.storage)
+        storage["tex"] = rt.Texture(codes, W, H, n, C, args.storage, scales)
+        storage["codes"], storage["scales"] = codes, scales
+    else:
+        storage["tex"] = master
+    tex_s = storage["tex"]
+    grad_tex = torch.empty((H, W, n, n, C), dtype=torch.float32, device=dev)
+    ws = torch.empty(rt.bwd_workspace_bytes(tex_s, N), dtype=torch.uint8, device=dev)
+    out = torch.empty((N, C), dtype=torch.float32, device=dev)
+
+    def step():
+        if args.storage != "f32":
+            rt._check(rt.LIB.rt_quantize(master.handle, rt.FORMATS[args.storage],
+                                         rt._ptr(storage["codes"]), rt._ptr(storage["scales"]),
+                                         rt._stream(dev)))
+        rt.lookup_fwd(tex_s, gb.uv, gb.tbn, gb.view, out=out)
+        rt.lookup_bwd(tex_s, gb.uv, gb.tbn, gb.view, go, workspace=ws, grad_tex=grad_tex)
+
+    if args.profile_steps:
+        for _ in range(args.profile_steps):
+            step()
+        torch.cuda.synchronize()
+        print(json.dumps({"profile_steps": args.profile_steps, "workload": w.name}), flush=True)
+        return
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    rt.profile_reset()
+    rt.profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    rt.profile_enable(False)
+    prof = rt.profile_read()
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    value = N / (ms_per_step * 1e-3)
+
+    # ---- algorithmic bytes per launch of each kernel ------------------------
+    eb = {"f32": 4, "bf16": 2, "fp8": 1}[args.storage]
+    idx, _ = rt.debug_indices(tex_s, gb.uv, gb.tbn, gb.view)
+    x0 = torch.clamp(idx[:, 2], max=n - 2).to(torch.int64)
+    y0 = torch.clamp(idx[:, 3], max=n - 2).to(torch.int64)
+    b = idx[:, 1].to(torch.int64) * W + idx[:, 0].to(torch.int64)
+    taps = torch.cat([b * n * n + (y0 + dy) * n + (x0 + dx) for dy in (0, 1) for dx in (0, 1)])
+    uniq_texels = int(torch.unique(taps).numel())
+    uniq_buckets = int(torch.unique(b).numel())
+    del taps, idx
+    texel_bytes = uniq_texels * C * eb + (uniq_buckets * 4 if args.storage == "fp8" else 0)
+    gbuf = N * 56
+    alg = {
+        "k_quant_bf16": E * 4 + E * 2,
+        "k_quant_fp8": E * 4 + E + W * H * 4,
+        "k_lookup_fwd": gbuf + N * C * 4 + texel_bytes,
+        "k_bwd_fragment": gbuf + N * C * 4 + texel_bytes + N * (12 + 8) + N * (4 + 8),
+        "k_segacc": E * 4 + N * (4 + 4 + 8 + C * 4) + W * H * 8,
+    }
+    per_kernel = {}
+    for name, (launches, total) in prof.items():
+        avg = total / launches
+        entry = {"launches_per_step": launches / args.steps, "avg_ms": round(avg, 5),
+                 "ms_per_step": round(total / args.steps, 5)}
+        if name in alg:
+            entry["alg_bytes"] = alg[name]
+            entry["GBps"] = round(alg[name] / (avg * 1e-3) / 1e9, 1)
+            entry["hbm_frac"] = round(entry["GBps"] / HBM_PEAK_GBS, 4)
+        per_kernel[name] = entry
+    dom = max((k for k in per_kernel if k in alg), key=lambda k: per_kernel[k]["ms_per_step"])
+    d = per_kernel[dom]
+    traffic = pmc_traffic(dom, args.workload)
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": d["GBps"], "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": d["hbm_frac"], "traffic": traffic,
+                "alg_bytes_per_launch": d["alg_bytes"], "avg_ms": d["avg_ms"]}
+
+    # ---- forward per storage format (FP32 / BF16 / FP8) ----------------------
+    formats = {}
+    S = min(N, 200000)
+    sel = torch.linspace(0, N - 1, S, device=dev).round().to(torch.int64)
+    sampled = {}
+    ref32 = rt.lookup_fwd(master, gb.uv, gb.tbn, gb.view)
+    for fmt in ("f32", "bf16", "fp8"):
+        if fmt == "f32":
+            t = master
+        else:
+            c_, s_ = rt.quantize(master, fmt)
+            t = rt.Texture(c_, W, H, n, C, fmt, s_)
+        o = torch.empty_like(out)
+        for _ in range(3):
+            rt.lookup_fwd(t, gb.uv, gb.tbn, gb.view, out=o)
+        torch.cuda.synchronize()
+        rt.profile_reset()
+        rt.profile_enable(True)
+        reps = 20
+        for _ in range(reps):
+            rt.lookup_fwd(t, gb.uv, gb.tbn, gb.view, out=o)
+        torch.cuda.synchronize()
+        rt.profile_enable(False)
+        launches, total = rt.profile_read()["k_lookup_fwd"]
+        avg = total / launches
+        ebf = {"f32": 4, "bf16": 2, "fp8": 1}[fmt]
+        fb = gbuf + N * C * 4 + uniq_texels * C * ebf + (uniq_buckets * 4 if fmt == "fp8" else 0)
+        e2e = (o - ref32).abs()
+        sampled[fmt] = o[sel].cpu().numpy().astype(np.float64)
+        formats[fmt] = {"fwd_ms": round(avg, 5), "fwd_lookups_per_s": round(N / (avg * 1e-3), 1),
+                        "fwd_alg_GBps": round(fb / (avg * 1e-3) / 1e9, 1),
+                        "fwd_hbm_frac": round(fb / (avg * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                        "max_abs_diff_vs_f32_storage": float(e2e.max()),
+                        "mean_abs_diff_vs_f32_storage": float(e2e.mean())}
+        if fmt != "f32":
+            del c_, s_, t
+
+    # ---- the FP64 oracle on a bounded sample (CPU baseline and error) -------
+    cpu = None
+    errors = None
+    if not args.no_cpu_baseline:
+        import oracle
+        uv_h, tbn_h, view_h = (t[sel].cpu().numpy() for t in (gb.uv, gb.tbn, gb.view))
+        go_h = go[sel].cpu().numpy()
+        tex_h = tex32.cpu().numpy()
+        otex = oracle.Tex(tex_h, W, H, n, C)
+        nb_s = min(W * H, 65536)
+        threads = oracle.num_threads()
+        t_a = time.perf_counter()
+        ref = oracle.lookup_fwd(otex, uv_h, tbn_h, view_h)
+        t_b = time.perf_counter()
+        oracle.lookup_bwd(otex, uv_h, tbn_h, view_h, go_h, window=(0, 0, 64, 64))
+        t_c = time.perf_counter()
+        oracle.quantize(tex_h.reshape(W * H, -1)[:nb_s], nb_s, n * n * C,
+                        oracle.FMT_BF16 if args.storage != "fp8" else oracle.FMT_FP8_E4M3)
+        t_d = time.perf_counter()
+        per_step_s = ((t_b - t_a) + (t_c - t_b)) * (N / S) + (t_d - t_c) * (W * H / nb_s)
+        if args.storage == "f32":
+            per_step_s -= (t_d - t_c) * (W * H / nb_s)
+        cpu = {"value": round(N / per_step_s, 1), "unit": "lookups/s", "cores": threads,
+               "kind": "oracle",
+               "sample": (f"FP64 oracle forward + backward (grad_view, grad_uv, grad_tex on a "
+                          f"64x64-bucket window) of {S} evenly spaced fragments of the view and "
+                          f"the {args.storage} quantiser on {nb_s} of {W * H} buckets, scaled to "
+                          f"the full step; {per_step_s:.1f} s per step extrapolated from "
+                          f"{t_d - t_a:.1f} s measured"),
+               "fwd_lookups_per_s": round(S / (t_b - t_a), 1)}
+        errors = {"sample_fragments": S,
+                  "note": "forward of each storage format against the FP64 oracle on the FP32 "
+                          "texture: for f32 the parity error, for bf16/fp8 the end-to-end "
+                          "quantisation error"}
+        for fmt in ("f32", "bf16", "fp8"):
+            dlt = np.abs(sampled[fmt] - ref)
+            errors[fmt] = {"max_abs": float(dlt.max()), "mean_abs": float(dlt.mean()),
+                           "psnr_db": float(10 * np.log10(1.0 / max(np.mean(dlt ** 2), 1e-30)))}
+        del tex_h
+
+    line = {
+        "metric": METRIC, "value": round(value, 1), "unit": "lookups/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 5),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": w.name, "buckets": [W, H], "n": n, "channels": C,
+                   "fragments": N, "storage": args.storage,
+                   "step": "quantize(f32->%s) + forward + backward(grad_tex dense, grad_view, "
+                           "grad_uv)" % args.storage, "mode": "nearest"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "kernels": per_kernel,
+        "formats": formats,
+        "errors": errors,
+        "unique_texels_touched": uniq_texels,
+        "source_hash": source_hash(),
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,212 @@
+/*
+ * radtex.h -- C ABI of the MI355X (gfx950) radiance-bucket lookup library
+ * (libradtex.so).
+ *
+ * Method: "Radiance Textures for Rasterizing Ray-Traced Data" (Fober, 2023,
+ * arXiv 2301.01719).  A radiance texture is a W x H matrix of "buckets"; each
+ * bucket is an n x n discrete map of the hemisphere (Sec. 2).  A fragment's
+ * texture coordinate (u, v) selects the bucket and its incidence (view)
+ * vector, moved into the orthogonal texture space of the surface, selects the
+ * position inside the bucket through the equisolid projection (Eq. 1b) and
+ * the disc-to-square map (Eq. 3); the position is clamped half a sample away
+ * from the bucket edge (the Note after Eq. 3) and a bilinear fetch is taken
+ * from the bucket's samples.
+ *
+ * Conventions used by every entry point
+ *   - All array pointers are DEVICE pointers (HIP global memory) that the
+ *     caller allocates and owns.  The library never frees them.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).  All
+ *     work is enqueued asynchronously on it; no entry point synchronises the
+ *     host with the device, except rt_profile_read.
+ *   - Every entry point returns an rt_status and never throws or aborts.
+ *     Arguments are validated on the host before anything is enqueued; on a
+ *     non-OK status no output has been touched.  rt_last_error() returns a
+ *     thread-local message describing the last non-OK status.  Faults of
+ *     already-enqueued kernels surface at the caller's next synchronisation.
+ *   - All GPU arithmetic is binary32.
+ *
+ * Layouts
+ *   texture, bucket-major   [H][W][n][n][C]: bucket (column i, row j) holds
+ *                           n rows y of n samples x of C channels, contiguous.
+ *                           Bucket axes: x follows the tangent T (+u), y the
+ *                           bitangent B (+v); row j = 0 is first in memory.
+ *   texture, atlas          [H*n][W*n][C]: the paper's arrangement of buckets
+ *                           "in place of the texture's pixels" (Sec. 2); it is
+ *                           re-laid into bucket-major by rt_create_texture.
+ *   fragments               uv [N][2], tbn [N][3][3] (rows T, B, N of the
+ *                           world-to-tangent frame, row-major), view [N][3]
+ *                           (from the surface toward the eye; need not be unit).
+ *   outputs                 out / grad_out [N][C]; grad_view [N][3];
+ *                           grad_uv [N][2]; grad_tex bucket-major float32.
+ *
+ * Alignment: texture data and grad_tex 16 bytes; scales 4; uv and grad_uv 8;
+ * out and grad_out 16 (C = 4), 8 (C = 2) or 4 (C = 1, 3); tbn, view and
+ * grad_view 4; workspace 256.
+ */
+#ifndef RADTEX_H
+#define RADTEX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define RT_VERSION 100
+
+typedef enum {
+    RT_OK = 0,
+    RT_ERR_INVALID_ARG = 1,        /* NULL / misaligned pointer, bad size or enum   */
+    RT_ERR_UNSUPPORTED = 2,        /* valid request outside the supported range     */
+    RT_ERR_OUT_OF_MEMORY = 3,      /* device allocation failed (atlas copy only)    */
+    RT_ERR_WORKSPACE_TOO_SMALL = 4,
+    RT_ERR_NO_DEVICE = 5,          /* no HIP device is visible                      */
+    RT_ERR_HIP = 6                 /* a HIP runtime call or kernel launch failed    */
+} rt_status;
+
+typedef enum {
+    RT_FMT_F32 = 0,       /* binary32 texels                                        */
+    RT_FMT_BF16 = 1,      /* bfloat16 texels (round-to-nearest-even), no scale      */
+    RT_FMT_FP8_E4M3 = 2   /* OCP E4M3 ("FN": bias 7, max 448, no inf) texels, times */
+                          /* one binary32 scale per bucket                          */
+} rt_format;
+
+typedef enum {
+    RT_LAYOUT_BUCKET_MAJOR = 0,
+    RT_LAYOUT_ATLAS = 1
+} rt_layout;
+
+/* lookup flags */
+enum {
+    RT_BUCKET_NEAREST = 0,   /* one bucket per fragment: the paper's "single sample
+                                per bucket" synthesis (Sec. 2)                    */
+    RT_BUCKET_BILINEAR = 1   /* the synthesised W x H output sampled bilinearly in
+                                UV: four buckets around frac(u)W - 1/2, wrapping   */
+};
+
+/* Limits: 1 <= W, H <= 65536; 1 <= n <= 32; 1 <= C <= 4.  The backward
+ * additionally needs W*H*n*n <= 2^32 (its sort key), and the number of
+ * records (N, or 4N in the bilinear-bucket mode) below 2^31. */
+
+typedef struct {
+    int32_t buckets_w;      /* W: bucket-matrix width  (paper's w, Sec. 2)        */
+    int32_t buckets_h;      /* H: bucket-matrix height (paper's h, Sec. 2)        */
+    int32_t n;              /* angular resolution: each bucket is n x n samples   */
+    int32_t channels;       /* C, 1..4                                            */
+    int32_t format;         /* rt_format                                          */
+    int32_t layout;         /* rt_layout                                          */
+    const void* data;       /* texels in `format` and `layout`                    */
+    const float* scales;    /* [H][W] per-bucket scale: required for FP8 (decoded */
+                            /* value = e4m3(code) * scale), must be NULL otherwise */
+} rt_texture_desc;
+
+typedef struct {
+    int64_t count;          /* N fragments (0 allowed)                            */
+    const float* uv;        /* [N][2] texture coordinates; wrap (repeat)          */
+    const float* tbn;       /* [N][3][3] rows T, B, N                              */
+    const float* view;      /* [N][3] surface -> eye                               */
+} rt_fragments;
+
+typedef struct rt_texture rt_texture;   /* opaque handle (host metadata)          */
+
+/* Wrap a radiance texture (Sec. 2: the bucket matrix of n x n hemispherical
+ * maps).  For RT_LAYOUT_BUCKET_MAJOR the handle BORROWS desc->data and
+ * desc->scales: the caller keeps them alive and unmodified while work that
+ * reads them is in flight, and no device memory is allocated.  For
+ * RT_LAYOUT_ATLAS the handle allocates a bucket-major copy on the current
+ * device and enqueues the re-layout on `stream` (RT_ERR_OUT_OF_MEMORY if the
+ * allocation fails); the handle owns that copy.
+ * Errors: RT_ERR_INVALID_ARG (NULL pointers, sizes, enum values, alignment,
+ * scales present/absent against the format), RT_ERR_UNSUPPORTED (limits),
+ * RT_ERR_NO_DEVICE, RT_ERR_HIP. */
+rt_status rt_create_texture(const rt_texture_desc* desc, void* stream, rt_texture** out);
+
+/* Release a handle (and its owned copy, after a device synchronisation when
+ * it owns one).  NULL is accepted. */
+rt_status rt_destroy_texture(rt_texture* tex);
+
+/* Per-bucket quantiser (the storage-footprint lever named in the abstract:
+ * buckets "compress" well).  src must be an RT_FMT_F32 texture.
+ *   RT_FMT_BF16      dst_codes: uint16 [H][W][n][n][C], round-to-nearest-even;
+ *                    dst_scales must be NULL.
+ *   RT_FMT_FP8_E4M3  per bucket: amax = max |x| (binary32); if amax is 0 or not
+ *                    finite, scale = 1 and inv = 1, else inv = 448 / amax and
+ *                    scale = amax / 448 (binary32, correctly rounded); codes =
+ *                    E4M3 round-to-nearest-even of x * inv with saturation to
+ *                    +-448 (NaN stays NaN).  dst_codes: uint8 [H][W][n][n][C];
+ *                    dst_scales: float [H][W].
+ * Errors: RT_ERR_INVALID_ARG (NULL/misaligned outputs, src not F32, bad dst). */
+rt_status rt_quantize(const rt_texture* src, int32_t dst_format, void* dst_codes,
+                      float* dst_scales, void* stream);
+
+/* Forward lookup (Sec. 2 and 2.1): for every fragment f and channel c,
+ *   M = tbn[f], I = M view / |M view|         (tangent-space incidence)
+ *   A = sqrt(2) (I_x, I_y) / |(I_x, I_y, I_z + 1)|          (Eq. 1b)
+ *   B = (|A|_2 / |A|_inf) A, B = 0 at A = 0                 (Eq. 3)
+ *   B clamped to [1/n - 1, 1 - 1/n]^2                       (Note after Eq. 3)
+ *   s = (B + 1) n / 2 - 1/2 in [0, n-1]^2  (sample centres at integers)
+ *   bucket i = floor(frac(u) W), j = floor(frac(v) H)       (Sec. 2; nearest)
+ *   out[f][c] = bilinear fetch at s inside bucket (i, j), decoded to binary32.
+ * flags: RT_BUCKET_NEAREST or RT_BUCKET_BILINEAR.  out: float [N][C].
+ * Non-finite inputs give unspecified values but never out-of-bounds reads.
+ * Errors: RT_ERR_INVALID_ARG (NULL/misaligned pointers, N < 0, bad flags). */
+rt_status rt_lookup_fwd(const rt_texture* tex, const rt_fragments* frags, float* out,
+                        uint32_t flags, void* stream);
+
+/* Bytes of device workspace rt_lookup_bwd needs for `count` fragments (0 when
+ * the arguments are invalid). */
+size_t rt_lookup_bwd_workspace(const rt_texture* tex, int64_t count, uint32_t flags);
+
+/* Backward of rt_lookup_fwd (an addition to the paper, which has no
+ * derivatives) for upstream gradients grad_out [N][C]:
+ *   grad_tex   float [H][W][n][n][C], dL/d(decoded texel); every element is
+ *              OVERWRITTEN (untouched buckets get 0).  Computed by a stable
+ *              bucket sort of the fragments' taps followed by a two-pass
+ *              segmented reduction with a fixed summation order: the result is
+ *              bitwise reproducible run to run and uses no float atomics.
+ *              For BF16/FP8 textures it is the gradient w.r.t. the decoded
+ *              values (straight-through).  NULL skips it.
+ *   grad_view  float [N][3], dL/d(view).  NULL skips it.
+ *   grad_uv    float [N][2], dL/d(u,v): 0 in nearest mode (the lookup is
+ *              piecewise constant in u, v); the bilinear-bucket weights'
+ *              derivative in RT_BUCKET_BILINEAR mode.  NULL skips it.
+ * At the non-smooth points (texel lines, clamp bounds, the diagonal
+ * |A_x| = |A_y|, A = 0, bucket edges) one-sided values are returned: an axis
+ * clamped at (or beyond) its bound contributes no view gradient.
+ * workspace: device memory of at least rt_lookup_bwd_workspace() bytes,
+ * 256-byte aligned, owned by the caller, not used by concurrent calls.
+ * Errors: RT_ERR_INVALID_ARG, RT_ERR_WORKSPACE_TOO_SMALL, RT_ERR_UNSUPPORTED
+ * (sort key or record count beyond the limits above). */
+rt_status rt_lookup_bwd(const rt_texture* tex, const rt_fragments* frags,
+                        const float* grad_out, float* grad_tex, float* grad_view,
+                        float* grad_uv, void* workspace, size_t workspace_bytes,
+                        uint32_t flags, void* stream);
+
+/* Per-fragment indices of the nearest-bucket lookup, for exact checks:
+ * idx int32 [N][4] = (i, j, x0, y0) with x0 = floor(s_x) in [0, n-1], and
+ * frac float [N][2] = (s_x - x0, s_y - y0).  Same arithmetic as the lookup. */
+rt_status rt_debug_indices(const rt_texture* tex, const rt_fragments* frags, int32_t* idx,
+                           float* frac, void* stream);
+
+/* Thread-local description of the last non-OK status ("" if none). */
+const char* rt_last_error(void);
+const char* rt_status_string(rt_status status);
+int32_t rt_version(void);
+
+/* Kernel timing.  While enabled, every kernel the library enqueues is
+ * bracketed by a pair of HIP events recorded on the same stream.
+ * rt_profile_read synchronises on the recorded events and returns, for
+ * kernel id k in [0, rt_profile_kernel_count()), the number of launches and
+ * their summed duration in milliseconds since the last reset. */
+rt_status rt_profile_enable(int32_t enabled);
+rt_status rt_profile_reset(void);
+int32_t rt_profile_kernel_count(void);
+const char* rt_profile_kernel_name(int32_t kernel);
+rt_status rt_profile_read(int32_t kernel, int64_t* launches, double* total_ms);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RADTEX_H */

@@ -50,7 +50,7 @@ def _load():
     lib.orc_indices.argtypes = [i64, P, P, P, i32, i32, i32, P, P, P]
     lib.orc_map_one.argtypes = [P, P, i32, P]
     lib.orc_lookup_bwd.argtypes = [i64, P, P, P, P, i32, i32, i32, i32, i32, P, P, i32,
-                                   P, P, i32, i32, i32, i32, P, P]
+                                   P, P, P, i32, i32, i32, i32, P, P, P, P]
     _lib = lib
     return lib
 
@@ -209,12 +209,14 @@ def lookup_one_f64(tex: Tex, U, M, V, mode=MODE_NEAREST):
 
 
 def indices(uv, tbn, view, W, H, n):
-    """Returns idx [N,4] int32 (i, j, x0, y0), frac [N,2], edge [N,2]."""
+    """Returns idx [N,4] int32 (i, j, x0, y0), frac [N,2] and edge [N,3]:
+    distances to the nearest bucket edge, sample edge (clamp bounds included)
+    and to the diagonal |A_x| = |A_y|."""
     uv, tbn, view = _frags(uv, tbn, view)
     N = uv.shape[0]
     idx = np.empty((N, 4), np.int32)
     frac = np.empty((N, 2), np.float64)
-    edge = np.empty((N, 2), np.float64)
+    edge = np.empty((N, 3), np.float64)
     _load().orc_indices(N, _p(uv), _p(tbn), _p(view), int(W), int(H), int(n), _p(idx),
                         _p(frac), _p(edge))
     return idx, frac, edge
@@ -226,7 +228,9 @@ def lookup_bwd(tex: Tex, uv, tbn, view, g, mode=MODE_NEAREST, want_tex=True, win
 
     window = (bi0, bj0, bw, bh) restricts grad_tex to that bucket rectangle
     (default: the whole matrix).  Returns dict with grad_tex [bh,bw,n,n,C],
-    abs_tex, grad_view [N,3], grad_uv [N,2] (entries None when not asked).
+    abs_tex (sum of |w g|), absg_tex (sum of |g| over the taps touching the
+    element), grad_view [N,3], grad_uv [N,2], and scale_view / scale_uv (the
+    chain rule evaluated with magnitudes); entries are None when not asked.
     """
     uv, tbn, view = _frags(uv, tbn, view)
     g = _c(g, np.float32).reshape(-1, tex.C)
@@ -235,14 +239,19 @@ def lookup_bwd(tex: Tex, uv, tbn, view, g, mode=MODE_NEAREST, want_tex=True, win
     if window is None:
         window = (0, 0, tex.W, tex.H)
     bi0, bj0, bw, bh = (int(x) for x in window)
-    gt = at = gv = gu = None
+    gt = at = ag = gv = gu = sv = su = None
     if want_tex:
         gt = np.empty((bh, bw, tex.n, tex.n, tex.C), np.float64)
         at = np.empty_like(gt)
+        ag = np.empty_like(gt)
     if want_view:
         gv = np.empty((N, 3), np.float64)
+        sv = np.empty((N, 3), np.float64)
     if want_uv:
         gu = np.empty((N, 2), np.float64)
+        su = np.empty((N, 2), np.float64)
     _load().orc_lookup_bwd(N, _p(uv), _p(tbn), _p(view), _p(g), *tex.args(), int(mode),
-                           _p(gt), _p(at), bi0, bj0, bw, bh, _p(gv), _p(gu))
-    return {"grad_tex": gt, "abs_tex": at, "grad_view": gv, "grad_uv": gu}
+                           _p(gt), _p(at), _p(ag), bi0, bj0, bw, bh, _p(gv), _p(gu), _p(sv),
+                           _p(su))
+    return {"grad_tex": gt, "abs_tex": at, "absg_tex": ag, "grad_view": gv, "grad_uv": gu,
+            "scale_view": sv, "scale_uv": su}

@@ -554,9 +554,12 @@ void orc_lookup_one_f64(const double U[2], const double M[9], const double V[3],
 }
 
 /* Per-fragment indices of the nearest-bucket lookup, for bit-exact checks:
- * idx[f] = (i, j, x0, y0), frac[f] = (fx, fy), and the distances (in units
- * of the matrix side and of the bucket side) of the unrounded coordinates to
- * the nearest cell edge: edge[f] = (bucket distance, sample distance). */
+ * idx[f] = (i, j, x0, y0), frac[f] = (fx, fy), and the distances of the
+ * unrounded quantities to the points where a result changes discontinuously
+ * or is not differentiable: edge[f] = (bucket distance in units of the matrix
+ * side, sample distance in units of the bucket side with the clamp bounds
+ * included, distance | |A_x| - |A_y| | to the diagonal where Eq. (3) switches
+ * between its two branches). */
 void orc_indices(int64_t N, const float *uv, const float *tbn, const float *view, int W, int H,
                  int n, int32_t *idx, double *frac, double *edge)
 {
@@ -576,8 +579,9 @@ void orc_indices(int64_t N, const float *uv, const float *tbn, const float *view
             double sd = fmin(sample_edge_dist(d.su[0], n), sample_edge_dist(d.su[1], n));
             if (!d.valid)
                 sd = INFINITY;
-            edge[2 * f + 0] = fmin(du, dv);
-            edge[2 * f + 1] = sd;
+            edge[3 * f + 0] = fmin(du, dv);
+            edge[3 * f + 1] = sd;
+            edge[3 * f + 2] = d.valid ? fabs(fabs(d.A[0]) - fabs(d.A[1])) : INFINITY;
         }
     }
 }
@@ -649,7 +653,7 @@ static void equisolid_jacobian(const double I[3], double J[2][3])
  * dL/dA = J3^T dL/dB, dL/dI = J1^T dL/dA, dL/du = (1/L)(P) dL/dI with
  * P = 1 - I I^T (normalisation), dL/dV = M^T dL/du. */
 static void view_gradient(const double M[9], const dirmap_t *d, int n, const double gs[2],
-                          double gV[3])
+                          int absolute, double gV[3])
 {
     gV[0] = gV[1] = gV[2] = 0.0;
     if (!d->valid)
@@ -657,38 +661,59 @@ static void view_gradient(const double M[9], const dirmap_t *d, int n, const dou
     double gB[2];
     for (int k = 0; k < 2; k++)
         gB[k] = d->clamped[k] ? 0.0 : gs[k] * n / 2.0;
-    double J3[2][2], J1[2][3];
+    double J3[2][2], J1[2][3], I[3] = {d->I[0], d->I[1], d->I[2]}, Mx[9];
     square_jacobian(d->A, J3);
     equisolid_jacobian(d->I, J1);
+    memcpy(Mx, M, sizeof(Mx));
+    if (absolute) { /* every factor by its magnitude: the scale of the rounding */
+        for (int r = 0; r < 2; r++) {
+            for (int c = 0; c < 2; c++)
+                J3[r][c] = fabs(J3[r][c]);
+            for (int c = 0; c < 3; c++)
+                J1[r][c] = fabs(J1[r][c]);
+        }
+        for (int k = 0; k < 3; k++)
+            I[k] = fabs(I[k]);
+        for (int k = 0; k < 9; k++)
+            Mx[k] = fabs(Mx[k]);
+    }
     double gA[2] = {J3[0][0] * gB[0] + J3[1][0] * gB[1], J3[0][1] * gB[0] + J3[1][1] * gB[1]};
     double gI[3];
     for (int c = 0; c < 3; c++)
         gI[c] = J1[0][c] * gA[0] + J1[1][c] * gA[1];
-    double dot = gI[0] * d->I[0] + gI[1] * d->I[1] + gI[2] * d->I[2];
+    double dot = gI[0] * I[0] + gI[1] * I[1] + gI[2] * I[2];
     double gu[3];
     for (int c = 0; c < 3; c++)
-        gu[c] = (gI[c] - d->I[c] * dot) / d->L;
+        gu[c] = absolute ? (gI[c] + I[c] * dot) / d->L : (gI[c] - I[c] * dot) / d->L;
     for (int m = 0; m < 3; m++)
-        gV[m] = M[0 * 3 + m] * gu[0] + M[1 * 3 + m] * gu[1] + M[2 * 3 + m] * gu[2];
+        gV[m] = Mx[0 * 3 + m] * gu[0] + Mx[1 * 3 + m] * gu[1] + Mx[2 * 3 + m] * gu[2];
 }
 
 /* Backward of N fragments with upstream gradient g[N][C] (binary32).
  *   grad_tex   dL/d(texel) accumulated in fragment order, binary64, over the
  *              bucket window [bi0, bi0+bw) x [bj0, bj0+bh) only (laid out
  *              [bh][bw][n][n][C]); NULL skips it.  abs_tex receives the sum of
- *              |weight * g| per element (the scale of the error criterion).
+ *              |weight * g| per element (the scale of the error criterion) and
+ *              absg_tex the sum of |g| over the taps that include the element
+ *              (the scale of the rounding of the weights themselves); either
+ *              may be NULL.
  *   grad_view  dL/dV [N][3]; grad_uv dL/d(u,v) [N][2] (zero in nearest mode
  *              away from bucket edges, where the lookup is piecewise constant
  *              in u,v).  Either may be NULL.
+ *   scale_view, scale_uv  the same chain rule evaluated with the magnitude of
+ *              every factor and term (the scale against which a binary32
+ *              evaluation's rounding error is measured); either may be NULL.
  * Taps that coincide (x1 = x0 at the clamp bound) each receive their own
  * weight, so the texel gets the sum. */
 void orc_lookup_bwd(int64_t N, const float *uv, const float *tbn, const float *view,
                     const float *g, int W, int H, int n, int C, int fmt, const void *data,
-                    const float *scales, int mode, double *grad_tex, double *abs_tex, int bi0,
-                    int bj0, int bw, int bh, double *grad_view, double *grad_uv)
+                    const float *scales, int mode, double *grad_tex, double *abs_tex,
+                    double *absg_tex, int bi0,
+                    int bj0, int bw, int bh, double *grad_view, double *grad_uv,
+                    double *scale_view, double *scale_uv)
 {
     tex_t t = {W, H, n, C, fmt, data, scales};
-    if (grad_view || grad_uv) {
+    if (grad_view || grad_uv || scale_view || scale_uv) {
 #pragma omp parallel for schedule(static)
         for (int64_t f = 0; f < N; f++) {
             double U[2], M[9], V[3];
@@ -698,8 +723,9 @@ void orc_lookup_bwd(int64_t N, const float *uv, const float *tbn, const float *v
             map_direction(M, V, n, &d);
             bucket_footprint(U[0], U[1], W, H, mode, &bf);
             const float *gf = g + f * C;
-            double gs[2] = {0.0, 0.0};
+            double gs[2] = {0.0, 0.0}, gsa[2] = {0.0, 0.0};
             double Lb[4] = {0, 0, 0, 0}; /* sum_c g_c * bilerp per footprint bucket */
+            double La[4] = {0, 0, 0, 0}; /* the same with magnitudes */
             for (int k = 0; k < bf.count; k++) {
                 int i = bf.i[k], j = bf.j[k];
                 for (int c = 0; c < C; c++) {
@@ -712,10 +738,27 @@ void orc_lookup_bwd(int64_t N, const float *uv, const float *tbn, const float *v
                     gs[0] += bf.w[k] * gf[c] * dsx;
                     gs[1] += bf.w[k] * gf[c] * dsy;
                     Lb[k] += gf[c] * bilerp(&t, i, j, &d, c);
+                    double ag = fabs(bf.w[k] * gf[c]);
+                    gsa[0] += ag * ((1.0 - d.fy) * fabs(T01 - T00) + d.fy * fabs(T11 - T10));
+                    gsa[1] += ag * ((1.0 - d.fx) * fabs(T10 - T00) + d.fx * fabs(T11 - T01));
+                    La[k] += fabs(gf[c]) *
+                             ((1.0 - d.fy) * ((1.0 - d.fx) * fabs(T00) + d.fx * fabs(T01)) +
+                              d.fy * ((1.0 - d.fx) * fabs(T10) + d.fx * fabs(T11)));
                 }
             }
             if (grad_view)
-                view_gradient(M, &d, n, gs, grad_view + 3 * f);
+                view_gradient(M, &d, n, gs, 0, grad_view + 3 * f);
+            if (scale_view)
+                view_gradient(M, &d, n, gsa, 1, scale_view + 3 * f);
+            if (scale_uv) {
+                if (mode == ORC_MODE_NEAREST) {
+                    scale_uv[2 * f] = scale_uv[2 * f + 1] = 0.0;
+                } else {
+                    double a = bf.a, b = bf.b;
+                    scale_uv[2 * f + 0] = W * ((1.0 - b) * (La[1] + La[0]) + b * (La[3] + La[2]));
+                    scale_uv[2 * f + 1] = H * ((1.0 - a) * (La[2] + La[0]) + a * (La[3] + La[1]));
+                }
+            }
             if (grad_uv) {
                 if (mode == ORC_MODE_NEAREST || !isfinite(U[0] - floor(U[0])) ||
                     !isfinite(U[1] - floor(U[1]))) {
@@ -736,6 +779,8 @@ void orc_lookup_bwd(int64_t N, const float *uv, const float *tbn, const float *v
         memset(grad_tex, 0, sizeof(double) * win);
         if (abs_tex)
             memset(abs_tex, 0, sizeof(double) * win);
+        if (absg_tex)
+            memset(absg_tex, 0, sizeof(double) * win);
         for (int64_t f = 0; f < N; f++) { /* fragment order: sequential */
             double U[2], M[9], V[3];
             widen_fragment(uv, tbn, view, f, U, M, V);
@@ -759,6 +804,8 @@ void orc_lookup_bwd(int64_t N, const float *uv, const float *tbn, const float *v
                         grad_tex[base + c] += contrib;
                         if (abs_tex)
                             abs_tex[base + c] += fabs(contrib);
+                        if (absg_tex)
+                            absg_tex[base + c] += fabs((double)gf[c]);
                     }
                 }
             }

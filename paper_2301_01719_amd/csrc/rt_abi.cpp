@@ -1,0 +1,401 @@
+// rt_abi.cpp -- the extern "C" boundary of libradtex.so (declared in
+// include/radtex.h): argument validation, texture handles, workspace sizing,
+// kernel dispatch and the event-based kernel timer.
+#include "../../include/radtex.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <exception>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "rt_device.hpp"
+#include "rt_kernels.hpp"
+
+struct rt_texture {
+    rt::TexView view;
+    int fmt;
+    void* owned;  // bucket-major copy made from an atlas, or nullptr
+};
+
+namespace {
+
+thread_local std::string g_last_error;
+
+rt_status fail(rt_status st, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+rt_status fail(rt_status st, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return st;
+}
+
+rt_status ok() { return RT_OK; }
+
+rt_status hip_fail(hipError_t e, const char* what) {
+    return fail(RT_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+bool aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
+
+size_t out_align(int C) { return C == 4 ? 16 : (C == 2 ? 8 : 4); }
+
+rt_status check_device() {
+    int count = 0;
+    hipError_t e = hipGetDeviceCount(&count);
+    if (e != hipSuccess || count <= 0) {
+        (void)hipGetLastError();
+        return fail(RT_ERR_NO_DEVICE, "no HIP device is visible");
+    }
+    return RT_OK;
+}
+
+rt_status check_tex(const rt_texture* t) {
+    if (!t) return fail(RT_ERR_INVALID_ARG, "texture handle is NULL");
+    return RT_OK;
+}
+
+rt_status check_frags(const rt_fragments* f) {
+    if (!f) return fail(RT_ERR_INVALID_ARG, "fragments is NULL");
+    if (f->count < 0) return fail(RT_ERR_INVALID_ARG, "fragment count %lld < 0", (long long)f->count);
+    if (f->count >= (1ll << 31))
+        return fail(RT_ERR_UNSUPPORTED, "fragment count %lld >= 2^31", (long long)f->count);
+    if (f->count == 0) return RT_OK;
+    if (!f->uv || !f->tbn || !f->view)
+        return fail(RT_ERR_INVALID_ARG, "uv, tbn and view must be non-NULL when count > 0");
+    if (!aligned(f->uv, 8)) return fail(RT_ERR_INVALID_ARG, "uv must be 8-byte aligned");
+    if (!aligned(f->tbn, 4) || !aligned(f->view, 4))
+        return fail(RT_ERR_INVALID_ARG, "tbn and view must be 4-byte aligned");
+    return RT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// kernel timer
+// ---------------------------------------------------------------------------
+struct Pending {
+    int id;
+    hipEvent_t a, b;
+};
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+std::vector<Pending> g_pending;
+std::vector<hipEvent_t> g_pool;
+double g_total_ms[rt::K_COUNT];
+int64_t g_launches[rt::K_COUNT];
+thread_local hipEvent_t t_open = nullptr;
+
+hipEvent_t pool_get() {
+    if (!g_pool.empty()) {
+        hipEvent_t e = g_pool.back();
+        g_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+void drain_locked() {
+    for (auto& p : g_pending) {
+        float ms = 0.f;
+        if (hipEventSynchronize(p.b) == hipSuccess && hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+            g_total_ms[p.id] += ms;
+            g_launches[p.id] += 1;
+        }
+        g_pool.push_back(p.a);
+        g_pool.push_back(p.b);
+    }
+    g_pending.clear();
+}
+
+}  // namespace
+
+namespace rt {
+
+const char* kernel_name(int id) {
+    static const char* names[K_COUNT] = {
+        "k_lookup_fwd",   "k_debug_indices", "k_quant_bf16",    "k_quant_fp8",
+        "k_atlas_to_buckets", "k_bwd_fragment", "k_fill_u32",   "k_radix_hist",
+        "k_scan",         "k_radix_scatter", "k_bucket_ranges", "k_segacc",
+        "k_segacc_hot",   "k_combine_hot"};
+    return (id >= 0 && id < K_COUNT) ? names[id] : "";
+}
+
+void prof_begin(int, hipStream_t s) {
+    if (!g_prof_on) return;
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    t_open = pool_get();
+    if (t_open) (void)hipEventRecord(t_open, s);
+}
+
+void prof_end(int id, hipStream_t s) {
+    if (!g_prof_on || !t_open) return;
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    hipEvent_t b = pool_get();
+    if (!b) return;
+    (void)hipEventRecord(b, s);
+    g_pending.push_back({id, t_open, b});
+    t_open = nullptr;
+}
+
+}  // namespace rt
+
+#define RT_GUARD_BEGIN try {
+#define RT_GUARD_END                                                              \
+    }                                                                             \
+    catch (const std::bad_alloc&) {                                               \
+        return fail(RT_ERR_OUT_OF_MEMORY, "host allocation failed");              \
+    }                                                                             \
+    catch (const std::exception& ex) {                                            \
+        return fail(RT_ERR_HIP, "internal error: %s", ex.what());                 \
+    }                                                                             \
+    catch (...) {                                                                 \
+        return fail(RT_ERR_HIP, "internal error");                                \
+    }
+
+extern "C" {
+
+const char* rt_last_error(void) { return g_last_error.c_str(); }
+
+int32_t rt_version(void) { return RT_VERSION; }
+
+const char* rt_status_string(rt_status s) {
+    switch (s) {
+    case RT_OK: return "RT_OK";
+    case RT_ERR_INVALID_ARG: return "RT_ERR_INVALID_ARG";
+    case RT_ERR_UNSUPPORTED: return "RT_ERR_UNSUPPORTED";
+    case RT_ERR_OUT_OF_MEMORY: return "RT_ERR_OUT_OF_MEMORY";
+    case RT_ERR_WORKSPACE_TOO_SMALL: return "RT_ERR_WORKSPACE_TOO_SMALL";
+    case RT_ERR_NO_DEVICE: return "RT_ERR_NO_DEVICE";
+    case RT_ERR_HIP: return "RT_ERR_HIP";
+    }
+    return "unknown rt_status";
+}
+
+rt_status rt_create_texture(const rt_texture_desc* d, void* stream, rt_texture** out) {
+    RT_GUARD_BEGIN
+    if (!out) return fail(RT_ERR_INVALID_ARG, "out is NULL");
+    if (!d) return fail(RT_ERR_INVALID_ARG, "desc is NULL");
+    if (d->buckets_w < 1 || d->buckets_h < 1)
+        return fail(RT_ERR_INVALID_ARG, "bucket matrix %d x %d must be at least 1 x 1", d->buckets_w, d->buckets_h);
+    if (d->buckets_w > 65536 || d->buckets_h > 65536)
+        return fail(RT_ERR_UNSUPPORTED, "bucket matrix %d x %d exceeds 65536 per side", d->buckets_w, d->buckets_h);
+    if (d->n < 1) return fail(RT_ERR_INVALID_ARG, "angular resolution n = %d must be >= 1", d->n);
+    if (d->n > 32) return fail(RT_ERR_UNSUPPORTED, "angular resolution n = %d exceeds 32", d->n);
+    if (d->channels < 1 || d->channels > 4)
+        return fail(RT_ERR_INVALID_ARG, "channels = %d must be in 1..4", d->channels);
+    if (d->format < RT_FMT_F32 || d->format > RT_FMT_FP8_E4M3)
+        return fail(RT_ERR_INVALID_ARG, "unknown format %d", d->format);
+    if (d->layout != RT_LAYOUT_BUCKET_MAJOR && d->layout != RT_LAYOUT_ATLAS)
+        return fail(RT_ERR_INVALID_ARG, "unknown layout %d", d->layout);
+    if (!d->data) return fail(RT_ERR_INVALID_ARG, "data is NULL");
+    if (!aligned(d->data, 16)) return fail(RT_ERR_INVALID_ARG, "data must be 16-byte aligned");
+    if (d->format == RT_FMT_FP8_E4M3) {
+        if (!d->scales) return fail(RT_ERR_INVALID_ARG, "FP8 textures need per-bucket scales");
+        if (!aligned(d->scales, 4)) return fail(RT_ERR_INVALID_ARG, "scales must be 4-byte aligned");
+    } else if (d->scales) {
+        return fail(RT_ERR_INVALID_ARG, "scales must be NULL for F32 and BF16 textures");
+    }
+    rt_status st = check_device();
+    if (st != RT_OK) return st;
+    rt_texture* t = new rt_texture();
+    t->view.data = d->data;
+    t->view.scales = d->scales;
+    t->view.W = d->buckets_w;
+    t->view.H = d->buckets_h;
+    t->view.n = d->n;
+    t->view.C = d->channels;
+    t->fmt = d->format;
+    t->owned = nullptr;
+    if (d->layout == RT_LAYOUT_ATLAS) {
+        const int eb = d->format == RT_FMT_F32 ? 4 : (d->format == RT_FMT_BF16 ? 2 : 1);
+        const size_t bytes = (size_t)d->buckets_w * d->buckets_h * d->n * d->n * d->channels * eb;
+        void* p = nullptr;
+        hipError_t e = hipMalloc(&p, bytes);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            delete t;
+            return fail(RT_ERR_OUT_OF_MEMORY, "allocation of %zu bytes for the bucket-major copy failed", bytes);
+        }
+        e = rt::launch_atlas_to_buckets(d->data, p, d->buckets_w, d->buckets_h, d->n, d->channels,
+                                        eb, (hipStream_t)stream);
+        if (e != hipSuccess) {
+            (void)hipFree(p);
+            delete t;
+            return hip_fail(e, "atlas re-layout launch");
+        }
+        t->owned = p;
+        t->view.data = p;
+    }
+    *out = t;
+    return ok();
+    RT_GUARD_END
+}
+
+rt_status rt_destroy_texture(rt_texture* t) {
+    RT_GUARD_BEGIN
+    if (!t) return RT_OK;
+    if (t->owned) {
+        (void)hipDeviceSynchronize();
+        (void)hipFree(t->owned);
+    }
+    delete t;
+    return RT_OK;
+    RT_GUARD_END
+}
+
+rt_status rt_quantize(const rt_texture* src, int32_t dst_format, void* codes, float* scales,
+                      void* stream) {
+    RT_GUARD_BEGIN
+    rt_status st = check_tex(src);
+    if (st != RT_OK) return st;
+    if (src->fmt != RT_FMT_F32) return fail(RT_ERR_INVALID_ARG, "quantiser source must be an F32 texture");
+    if (!codes) return fail(RT_ERR_INVALID_ARG, "dst_codes is NULL");
+    if (dst_format == RT_FMT_BF16) {
+        if (scales) return fail(RT_ERR_INVALID_ARG, "BF16 has no scales: dst_scales must be NULL");
+        if (!aligned(codes, 8)) return fail(RT_ERR_INVALID_ARG, "dst_codes must be 8-byte aligned");
+    } else if (dst_format == RT_FMT_FP8_E4M3) {
+        if (!scales) return fail(RT_ERR_INVALID_ARG, "FP8 needs dst_scales");
+        if (!aligned(codes, 4) || !aligned(scales, 4))
+            return fail(RT_ERR_INVALID_ARG, "dst_codes and dst_scales must be 4-byte aligned");
+    } else {
+        return fail(RT_ERR_INVALID_ARG, "dst_format must be RT_FMT_BF16 or RT_FMT_FP8_E4M3");
+    }
+    hipError_t e = rt::launch_quantize(src->view, dst_format, codes, scales, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "quantiser launch");
+    return ok();
+    RT_GUARD_END
+}
+
+rt_status rt_lookup_fwd(const rt_texture* t, const rt_fragments* f, float* out, uint32_t flags,
+                        void* stream) {
+    RT_GUARD_BEGIN
+    rt_status st = check_tex(t);
+    if (st != RT_OK) return st;
+    st = check_frags(f);
+    if (st != RT_OK) return st;
+    if (flags > RT_BUCKET_BILINEAR) return fail(RT_ERR_INVALID_ARG, "unknown flags 0x%x", flags);
+    if (f->count > 0) {
+        if (!out) return fail(RT_ERR_INVALID_ARG, "out is NULL");
+        if (!aligned(out, out_align(t->view.C)))
+            return fail(RT_ERR_INVALID_ARG, "out must be %zu-byte aligned", out_align(t->view.C));
+    }
+    hipError_t e = rt::launch_lookup_fwd(t->view, t->fmt, (int)flags, f->uv, f->tbn, f->view, out,
+                                         f->count, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "lookup launch");
+    return ok();
+    RT_GUARD_END
+}
+
+size_t rt_lookup_bwd_workspace(const rt_texture* t, int64_t count, uint32_t flags) {
+    try {
+        if (!t || count < 0 || flags > RT_BUCKET_BILINEAR) return 0;
+        rt::BwdPlan p;
+        if (!rt::plan_backward(t->view.W, t->view.H, t->view.n, t->view.C, count, (int)flags, &p))
+            return 0;
+        return p.total;
+    } catch (...) {
+        return 0;
+    }
+}
+
+rt_status rt_lookup_bwd(const rt_texture* t, const rt_fragments* f, const float* grad_out,
+                        float* grad_tex, float* grad_view, float* grad_uv, void* ws,
+                        size_t ws_bytes, uint32_t flags, void* stream) {
+    RT_GUARD_BEGIN
+    rt_status st = check_tex(t);
+    if (st != RT_OK) return st;
+    st = check_frags(f);
+    if (st != RT_OK) return st;
+    if (flags > RT_BUCKET_BILINEAR) return fail(RT_ERR_INVALID_ARG, "unknown flags 0x%x", flags);
+    const int C = t->view.C;
+    if (f->count > 0) {
+        if (!grad_out) return fail(RT_ERR_INVALID_ARG, "grad_out is NULL");
+        if (!aligned(grad_out, out_align(C)))
+            return fail(RT_ERR_INVALID_ARG, "grad_out must be %zu-byte aligned", out_align(C));
+    }
+    if (grad_tex && !aligned(grad_tex, 16)) return fail(RT_ERR_INVALID_ARG, "grad_tex must be 16-byte aligned");
+    if (grad_view && !aligned(grad_view, 4)) return fail(RT_ERR_INVALID_ARG, "grad_view must be 4-byte aligned");
+    if (grad_uv && !aligned(grad_uv, 8)) return fail(RT_ERR_INVALID_ARG, "grad_uv must be 8-byte aligned");
+    rt::BwdPlan plan;
+    if (!rt::plan_backward(t->view.W, t->view.H, t->view.n, C, f->count, (int)flags, &plan))
+        return fail(RT_ERR_UNSUPPORTED, "sort key (W*H*n*n) or record count beyond the backward's limits");
+    if (!grad_tex && !grad_view && !grad_uv) return ok();  // nothing requested
+    if (grad_tex) {
+        if (!ws) return fail(RT_ERR_INVALID_ARG, "workspace is NULL");
+        if (!aligned(ws, 256)) return fail(RT_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+        if (ws_bytes < plan.total)
+            return fail(RT_ERR_WORKSPACE_TOO_SMALL, "workspace has %zu bytes, %zu needed", ws_bytes, plan.total);
+    }
+    hipError_t e = rt::launch_backward(t->view, t->fmt, (int)flags, f->uv, f->tbn, f->view,
+                                       grad_out, grad_tex, grad_view, grad_uv, f->count, plan,
+                                       ws, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "backward launch");
+    return ok();
+    RT_GUARD_END
+}
+
+rt_status rt_debug_indices(const rt_texture* t, const rt_fragments* f, int32_t* idx, float* frac,
+                           void* stream) {
+    RT_GUARD_BEGIN
+    rt_status st = check_tex(t);
+    if (st != RT_OK) return st;
+    st = check_frags(f);
+    if (st != RT_OK) return st;
+    if (f->count > 0) {
+        if (!idx || !frac) return fail(RT_ERR_INVALID_ARG, "idx and frac must be non-NULL");
+        if (!aligned(idx, 16) || !aligned(frac, 8))
+            return fail(RT_ERR_INVALID_ARG, "idx must be 16-byte and frac 8-byte aligned");
+    }
+    rt::prof_begin(rt::K_DEBUG_INDICES, (hipStream_t)stream);
+    hipError_t e = rt::launch_debug_indices(t->view, f->uv, f->tbn, f->view, idx, frac, f->count,
+                                            (hipStream_t)stream);
+    rt::prof_end(rt::K_DEBUG_INDICES, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "debug-indices launch");
+    return ok();
+    RT_GUARD_END
+}
+
+rt_status rt_profile_enable(int32_t on) {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    g_prof_on = on != 0;
+    return RT_OK;
+}
+
+rt_status rt_profile_reset(void) {
+    RT_GUARD_BEGIN
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    drain_locked();
+    for (int k = 0; k < rt::K_COUNT; k++) {
+        g_total_ms[k] = 0.0;
+        g_launches[k] = 0;
+    }
+    return RT_OK;
+    RT_GUARD_END
+}
+
+int32_t rt_profile_kernel_count(void) { return rt::K_COUNT; }
+
+const char* rt_profile_kernel_name(int32_t k) { return rt::kernel_name(k); }
+
+rt_status rt_profile_read(int32_t k, int64_t* launches, double* total_ms) {
+    RT_GUARD_BEGIN
+    if (k < 0 || k >= rt::K_COUNT) return fail(RT_ERR_INVALID_ARG, "kernel id %d out of range", k);
+    if (!launches || !total_ms) return fail(RT_ERR_INVALID_ARG, "outputs are NULL");
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    drain_locked();
+    *launches = g_launches[k];
+    *total_ms = g_total_ms[k];
+    return RT_OK;
+    RT_GUARD_END
+}
+
+}  // extern "C"

@@ -1,0 +1,832 @@
+// rt_backward.hip -- deterministic backward of the radiance-bucket lookup for
+// gfx950.
+//
+//   1. k_bwd_fragment   one lane per fragment: recompute the mapping, write
+//                       dL/dview (chain through the bilinear weights, the
+//                       clamp, Eq. 3, Eq. 1b and the normalisation) and
+//                       dL/duv, and emit one record per (fragment, bucket):
+//                       key = bucket << cell_bits | (y0 n + x0).
+//   2. radix sort       stable LSD sort of (key, record) by 8-bit digits:
+//                       per-tile digit histograms, one exclusive scan over
+//                       (digit, tile), stable in-tile ranking with wave ballots.
+//                       Equal keys keep record order, so the sorted sequence
+//                       depends only on the inputs.
+//   3. k_bucket_ranges  [start, end) of every bucket in the sorted records.
+//   4. k_segacc         one wavefront per bucket (pass 1): the bucket's records
+//                       are reduced per cell by a segmented scan across lanes
+//                       with a fixed shape, the four cell sums are added to the
+//                       texels of the cell in four ordered phases in LDS, and
+//                       the n x n x C tile is written once.  Untouched buckets
+//                       get zeros.  Buckets with more than PIECE records are
+//                       left to pass 2.
+//   5. k_segacc_hot /   pass 2: hot buckets are cut at fixed chunk boundaries of
+//      k_combine_hot    the sorted records; each chunk's part is reduced as in
+//                       pass 1 into a partial tile, and the partials are summed
+//                       in chunk order.
+// No float atomics are used, and every summation order is a function of the
+// sorted records alone, so the gradient is bitwise reproducible.
+#include "rt_device.hpp"
+#include "rt_kernels.hpp"
+
+namespace rt {
+
+constexpr int SORT_THREADS = 256;
+constexpr int SORT_IPT = 16;
+constexpr int SORT_TILE = SORT_THREADS * SORT_IPT;  // 4096
+constexpr int SCAN_TILE = 4096;
+
+// ---------------------------------------------------------------------------
+// 1. per-fragment backward
+// ---------------------------------------------------------------------------
+
+// dL/dA from dL/dB through Eq. (3).  On the branch |A_x| >= |A_y|,
+// B = (rho sgn A_x, rho A_y / |A_x|); the other branch mirrors it; at A = 0
+// the map's limit along the axes (identity) is used.
+__device__ __forceinline__ void square_vjp(float ax, float ay, float gbx, float gby, float& gax,
+                                           float& gay) {
+    float rho = sqrtf(ax * ax + ay * ay);
+    if (!(rho > 0.f)) {
+        gax = gbx;
+        gay = gby;
+        return;
+    }
+    if (fabsf(ax) >= fabsf(ay)) {
+        float sx = ax >= 0.f ? 1.f : -1.f;
+        float j00 = fabsf(ax) / rho, j01 = sx * ay / rho;
+        float j10 = -sx * ay * ay * ay / (rho * ax * ax);
+        float j11 = (ay * ay + rho * rho) / (rho * fabsf(ax));
+        gax = j00 * gbx + j10 * gby;
+        gay = j01 * gbx + j11 * gby;
+    } else {
+        float sy = ay >= 0.f ? 1.f : -1.f;
+        float j11 = fabsf(ay) / rho, j10 = sy * ax / rho;
+        float j01 = -sy * ax * ax * ax / (rho * ay * ay);
+        float j00 = (ax * ax + rho * rho) / (rho * fabsf(ay));
+        gax = j00 * gbx + j10 * gby;
+        gay = j01 * gbx + j11 * gby;
+    }
+}
+
+// Per-bucket part of the per-fragment backward: dL/ds (x, y) and sum_c g_c * value.
+template <int FMT, int C>
+__device__ __forceinline__ void bucket_grads(const TexView& t, int64_t b, const Foot& p,
+                                             const float go[4], float& dsx, float& dsy,
+                                             float& lval) {
+    const int n = t.n;
+    const int64_t base = b * (int64_t)(n * n);
+    F4 t00 = load_texel<FMT, C>(t.data, base + p.y0 * n + p.x0);
+    F4 t01 = load_texel<FMT, C>(t.data, base + p.y0 * n + p.x1);
+    F4 t10 = load_texel<FMT, C>(t.data, base + p.y1 * n + p.x0);
+    F4 t11 = load_texel<FMT, C>(t.data, base + p.y1 * n + p.x1);
+    float f = bucket_factor<FMT>(t.scales, b);
+    float gx = 0.f, gy = 0.f, lv = 0.f;
+    float w00 = (1.f - p.fx) * (1.f - p.fy), w01 = p.fx * (1.f - p.fy);
+    float w10 = (1.f - p.fx) * p.fy, w11 = p.fx * p.fy;
+#pragma unroll
+    for (int c = 0; c < C; c++) {
+        gx += go[c] * ((1.f - p.fy) * (t01.v[c] - t00.v[c]) + p.fy * (t11.v[c] - t10.v[c]));
+        gy += go[c] * ((1.f - p.fx) * (t10.v[c] - t00.v[c]) + p.fx * (t11.v[c] - t01.v[c]));
+        lv += go[c] * (w00 * t00.v[c] + w01 * t01.v[c] + w10 * t10.v[c] + w11 * t11.v[c]);
+    }
+    dsx = f * gx;
+    dsy = f * gy;
+    lval = f * lv;
+}
+
+template <int FMT, int C, int MODE>
+__global__ __launch_bounds__(256) void k_bwd_fragment(
+    TexView t, const float* __restrict__ uv, const float* __restrict__ tbn,
+    const float* __restrict__ view, const float* __restrict__ grad_out,
+    float* __restrict__ grad_view, float* __restrict__ grad_uv, uint32_t* __restrict__ keys,
+    float* __restrict__ wrec, int64_t N, int cell_bits) {
+    const int64_t f = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (f >= N) return;
+    const int n = t.n;
+    Frag g = load_frag(uv, tbn, view, f);
+    Dir d = map_direction(g.m, g.w, n);
+    Foot p = footprint(d.sx, d.sy, n);
+    float go[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int c = 0; c < C; c++) go[c] = grad_out[f * C + c];
+    const uint32_t cell = (uint32_t)(p.y0 * n + p.x0);
+
+    float gsx = 0.f, gsy = 0.f;
+    if constexpr (MODE == MODE_NEAREST) {
+        int i = bucket_of(g.u, t.W), j = bucket_of(g.v, t.H);
+        int64_t b = (int64_t)j * t.W + i;
+        float lv;
+        if (grad_view) bucket_grads<FMT, C>(t, b, p, go, gsx, gsy, lv);
+        if (grad_uv) ((float2*)grad_uv)[f] = make_float2(0.f, 0.f);
+        if (keys) {
+            keys[f] = ((uint32_t)b << cell_bits) | cell;
+            ((float2*)wrec)[f] = make_float2(p.fx, p.fy);
+        }
+    } else {
+        int i0, i1, j0, j1;
+        float a, bb;
+        bucket_pair(g.u, t.W, i0, i1, a);
+        bucket_pair(g.v, t.H, j0, j1, bb);
+        const int64_t bk[4] = {(int64_t)j0 * t.W + i0, (int64_t)j0 * t.W + i1,
+                               (int64_t)j1 * t.W + i0, (int64_t)j1 * t.W + i1};
+        const float wb[4] = {(1.f - a) * (1.f - bb), a * (1.f - bb), (1.f - a) * bb, a * bb};
+        if (grad_view || grad_uv) {
+            float lv[4];
+#pragma unroll
+            for (int k = 0; k < 4; k++) {
+                float dx, dy;
+                bucket_grads<FMT, C>(t, bk[k], p, go, dx, dy, lv[k]);
+                gsx += wb[k] * dx;
+                gsy += wb[k] * dy;
+            }
+            if (grad_uv) {
+                float gu = (float)t.W * ((1.f - bb) * (lv[1] - lv[0]) + bb * (lv[3] - lv[2]));
+                float gv = (float)t.H * ((1.f - a) * (lv[2] - lv[0]) + a * (lv[3] - lv[1]));
+                ((float2*)grad_uv)[f] = make_float2(gu, gv);
+            }
+        }
+        if (keys) {
+#pragma unroll
+            for (int k = 0; k < 4; k++) keys[4 * f + k] = ((uint32_t)bk[k] << cell_bits) | cell;
+            ((float4*)wrec)[f] = make_float4(p.fx, p.fy, a, bb);
+        }
+    }
+
+    if (grad_view) {
+        // dL/dB = (n/2) dL/ds on unclamped axes
+        float gbx = d.clx ? 0.f : gsx * (0.5f * (float)n);
+        float gby = d.cly ? 0.f : gsy * (0.5f * (float)n);
+        float gax, gay;
+        square_vjp(d.ax, d.ay, gbx, gby, gax, gay);
+        // A = (u_x, u_y) k, k = (L (L + u_z))^(-1/2):
+        // dk/du = -k^3/2 * [(u / L)(2L + u_z) + L e_z]
+        float gux = 0.f, guy = 0.f, guz = 0.f;
+        if (d.k > 0.f && d.L > 0.f) {
+            float sdot = d.ux * gax + d.uy * gay;
+            float coef = -0.5f * d.k * d.k * d.k * sdot;
+            float t2 = (2.f * d.L + d.uz) / d.L;
+            gux = d.k * gax + coef * d.ux * t2;
+            guy = d.k * gay + coef * d.uy * t2;
+            guz = coef * (d.uz * t2 + d.L);
+        }
+        // dL/dV = M^T dL/du
+        grad_view[f * 3 + 0] = g.m[0] * gux + g.m[3] * guy + g.m[6] * guz;
+        grad_view[f * 3 + 1] = g.m[1] * gux + g.m[4] * guy + g.m[7] * guz;
+        grad_view[f * 3 + 2] = g.m[2] * gux + g.m[5] * guy + g.m[8] * guz;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// 2. stable LSD radix sort of (key, record index), 8-bit digits
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(SORT_THREADS) void k_radix_hist(const uint32_t* __restrict__ keys,
+                                                             int64_t R, int shift,
+                                                             uint32_t* __restrict__ hist,
+                                                             int64_t tiles) {
+    __shared__ uint32_t cnt[256];
+    const int t = threadIdx.x;
+    cnt[t] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * SORT_TILE;
+#pragma unroll 4
+    for (int r = 0; r < SORT_IPT; r++) {
+        int64_t i = base + r * SORT_THREADS + t;
+        if (i < R) atomicAdd(&cnt[(keys[i] >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    hist[(int64_t)t * tiles + blockIdx.x] = cnt[t];
+}
+
+// exclusive prefix of v over the 256 threads of the block; *total receives the sum
+__device__ __forceinline__ uint32_t block_exclusive(uint32_t v, uint32_t* wsum, uint32_t* total) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    uint32_t x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        uint32_t y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) wsum[w] = x;
+    __syncthreads();
+    uint32_t before = 0, all = 0;
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+        uint32_t s = wsum[k];
+        if (k < w) before += s;
+        all += s;
+    }
+    __syncthreads();
+    if (total) *total = all;
+    return before + x - v;
+}
+
+// device-wide exclusive scan: per-block sums, a one-block scan of the sums,
+// then per-block scans offset by the scanned sums
+__global__ __launch_bounds__(256) void k_scan_reduce(const uint32_t* __restrict__ in, int64_t L,
+                                                     uint32_t* __restrict__ part) {
+    __shared__ uint32_t wsum[4];
+    const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + threadIdx.x * 16;
+    uint32_t s = 0;
+#pragma unroll
+    for (int k = 0; k < 16; k++)
+        if (base + k < L) s += in[base + k];
+    uint32_t total;
+    block_exclusive(s, wsum, &total);
+    if (threadIdx.x == 0) part[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(256) void k_scan_top(uint32_t* __restrict__ part, int64_t P) {
+    __shared__ uint32_t wsum[4];
+    uint32_t carry = 0;
+    for (int64_t base = 0; base < P; base += 256 * 16) {
+        const int64_t b = base + threadIdx.x * 16;
+        uint32_t v[16], s = 0;
+#pragma unroll
+        for (int k = 0; k < 16; k++) {
+            v[k] = (b + k < P) ? part[b + k] : 0u;
+            s += v[k];
+        }
+        uint32_t total;
+        uint32_t run = carry + block_exclusive(s, wsum, &total);
+#pragma unroll
+        for (int k = 0; k < 16; k++) {
+            if (b + k < P) part[b + k] = run;
+            run += v[k];
+        }
+        carry += total;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_scan_down(const uint32_t* __restrict__ in, int64_t L,
+                                                   const uint32_t* __restrict__ part,
+                                                   uint32_t* __restrict__ out) {
+    __shared__ uint32_t wsum[4];
+    const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + threadIdx.x * 16;
+    uint32_t v[16], s = 0;
+#pragma unroll
+    for (int k = 0; k < 16; k++) {
+        v[k] = (base + k < L) ? in[base + k] : 0u;
+        s += v[k];
+    }
+    uint32_t run = part[blockIdx.x] + block_exclusive(s, wsum, nullptr);
+#pragma unroll
+    for (int k = 0; k < 16; k++) {
+        if (base + k < L) out[base + k] = run;
+        run += v[k];
+    }
+}
+
+// Stable scatter of one radix pass.  Items of a tile are taken in rounds of
+// 256 in index order; within a wave, lanes holding the same digit are found
+// with one ballot per digit bit, and ranks follow lane order; across the
+// block's waves and rounds, ranks follow wave order then round order.  The
+// tile is first ordered in LDS, then written out so that each digit's run is
+// contiguous in memory.
+__global__ __launch_bounds__(SORT_THREADS) void k_radix_scatter(
+    const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in,
+    uint32_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out, int64_t R, int shift,
+    const uint32_t* __restrict__ hist, const uint32_t* __restrict__ hoff, int64_t tiles) {
+    __shared__ uint32_t skeys[SORT_TILE];
+    __shared__ uint32_t svals[SORT_TILE];
+    __shared__ uint32_t dstart[256], run[256], goff[256];
+    __shared__ uint32_t wcnt[4][256];
+    __shared__ uint32_t wsum[4];
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int64_t tile = blockIdx.x;
+    const int64_t base = tile * SORT_TILE;
+    const uint32_t mycount = hist[(int64_t)t * tiles + tile];
+    dstart[t] = block_exclusive(mycount, wsum, nullptr);
+    goff[t] = hoff[(int64_t)t * tiles + tile];
+    run[t] = 0;
+    wcnt[0][t] = wcnt[1][t] = wcnt[2][t] = wcnt[3][t] = 0;
+    __syncthreads();
+    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    for (int r = 0; r < SORT_IPT; r++) {
+        const int64_t i = base + r * SORT_THREADS + t;
+        const bool valid = i < R;
+        uint32_t k = 0, v = 0;
+        if (valid) {
+            k = keys_in[i];
+            v = vals_in ? vals_in[i] : (uint32_t)i;
+        }
+        const uint32_t dg = (k >> shift) & 255u;
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (int bit = 0; bit < 8; bit++) {
+            const bool on = (dg >> bit) & 1u;
+            const uint64_t m = __ballot(on);
+            peers &= on ? m : ~m;
+        }
+        const uint32_t rank = (uint32_t)__popcll(peers & lt_mask);
+        if (valid && rank == 0) wcnt[w][dg] = (uint32_t)__popcll(peers);
+        __syncthreads();
+        if (valid) {
+            uint32_t off = run[dg] + rank;
+            for (int q = 0; q < w; q++) off += wcnt[q][dg];
+            const uint32_t pos = dstart[dg] + off;
+            skeys[pos] = k;
+            svals[pos] = v;
+        }
+        __syncthreads();
+        run[t] += wcnt[0][t] + wcnt[1][t] + wcnt[2][t] + wcnt[3][t];
+        wcnt[0][t] = wcnt[1][t] = wcnt[2][t] = wcnt[3][t] = 0;
+        __syncthreads();
+    }
+    const int64_t nvalid = (R - base) < SORT_TILE ? (R - base) : SORT_TILE;
+    for (int r = 0; r < SORT_IPT; r++) {
+        const int p = r * SORT_THREADS + t;
+        if (p < nvalid) {
+            const uint32_t k = skeys[p];
+            const uint32_t dg = (k >> shift) & 255u;
+            const uint32_t dst = goff[dg] + ((uint32_t)p - dstart[dg]);
+            keys_out[dst] = k;
+            vals_out[dst] = svals[p];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// 3. bucket ranges in the sorted records
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void k_fill_u32(uint32_t* __restrict__ p, int64_t n, uint32_t v) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+__global__ __launch_bounds__(256) void k_bucket_ranges(const uint32_t* __restrict__ skeys,
+                                                       int64_t R, int cell_bits,
+                                                       int2* __restrict__ range) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= R) return;
+    const uint32_t b = skeys[i] >> cell_bits;
+    if (i == 0 || (skeys[i - 1] >> cell_bits) != b) range[b].x = (int)i;
+    if (i == R - 1 || (skeys[i + 1] >> cell_bits) != b) range[b].y = (int)(i + 1);
+}
+
+// ---------------------------------------------------------------------------
+// 4./5. segmented reduction of a bucket's records into its gradient tile
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ void wave_sync_lds() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Reduce sorted records [a, e) (all of one bucket) into the wave's LDS tile
+// (n*n*C floats, zeroed by the caller).  Rounds of 64 records; inside a round
+// the four tap contributions are summed per cell by an inclusive segmented
+// scan with a fixed shape; a cell that runs past the round carries its sum
+// into the next round's first lane.  A completed cell adds its four sums to
+// its four texels in four phases, so no two lanes touch one texel at once.
+template <int C, int MODE>
+__device__ __forceinline__ void reduce_records(const uint32_t* __restrict__ skeys,
+                               const uint32_t* __restrict__ svals,
+                               const float* __restrict__ wrec, const float* __restrict__ grad_out,
+                               int64_t a, int64_t e, int n, uint32_t cell_mask, float* tile) {
+    const int lane = threadIdx.x & 63;
+    constexpr int F = 4 * C;
+    float carry[F];
+#pragma unroll
+    for (int q = 0; q < F; q++) carry[q] = 0.f;
+    int carry_cell = -1;
+    for (int64_t base = a; base < e; base += 64) {
+        const int64_t i = base + lane;
+        const bool valid = i < e;
+        int cell = -2 - lane;  // distinct from every real cell and from each other
+        float v[F];
+#pragma unroll
+        for (int q = 0; q < F; q++) v[q] = 0.f;
+        if (valid) {
+            const uint32_t key = skeys[i];
+            const uint32_t rec = svals[i];
+            cell = (int)(key & cell_mask);
+            float fx, fy, wb = 1.f;
+            int64_t frag;
+            if constexpr (MODE == MODE_NEAREST) {
+                frag = rec;
+                float2 w2 = ((const float2*)wrec)[frag];
+                fx = w2.x;
+                fy = w2.y;
+            } else {
+                frag = rec >> 2;
+                const int k = rec & 3;
+                float4 w4 = ((const float4*)wrec)[frag];
+                fx = w4.x;
+                fy = w4.y;
+                const float aa = w4.z, bb = w4.w;
+                wb = (k == 0) ? (1.f - aa) * (1.f - bb)
+                              : (k == 1) ? aa * (1.f - bb) : (k == 2) ? (1.f - aa) * bb : aa * bb;
+            }
+            const float w00 = (1.f - fx) * (1.f - fy), w01 = fx * (1.f - fy);
+            const float w10 = (1.f - fx) * fy, w11 = fx * fy;
+#pragma unroll
+            for (int c = 0; c < C; c++) {
+                const float gc = grad_out[frag * C + c] * wb;
+                v[0 * C + c] = w00 * gc;
+                v[1 * C + c] = w01 * gc;
+                v[2 * C + c] = w10 * gc;
+                v[3 * C + c] = w11 * gc;
+            }
+        }
+        if (lane == 0 && cell == carry_cell) {
+#pragma unroll
+            for (int q = 0; q < F; q++) v[q] = carry[q] + v[q];
+        }
+        const int prev_cell = __shfl_up(cell, 1, 64);
+        const bool joins_prev = lane > 0 && prev_cell == cell;
+        if (__ballot(joins_prev) != 0ull) {
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const int oc = __shfl_up(cell, o, 64);
+                const bool same = lane >= o && oc == cell;
+#pragma unroll
+                for (int q = 0; q < F; q++) {
+                    const float ov = __shfl_up(v[q], o, 64);
+                    if (same) v[q] += ov;
+                }
+            }
+        }
+        const int next_cell = __shfl_down(cell, 1, 64);
+        bool continues = valid && lane < 63 && i + 1 < e && next_cell == cell;
+        bool spills = false;
+        if (valid && lane == 63 && i + 1 < e) spills = (int)(skeys[i + 1] & cell_mask) == cell;
+        const bool tail = valid && !continues && !spills;
+        // carry the sum of a cell that runs into the next round
+        const uint64_t spill_mask = __ballot(spills);
+        if (spill_mask) {
+#pragma unroll
+            for (int q = 0; q < F; q++) carry[q] = __shfl(v[q], 63, 64);
+            carry_cell = __shfl(cell, 63, 64);
+        } else {
+            carry_cell = -1;
+        }
+        const uint64_t tails = __ballot(tail);
+        if (tails) {
+            int y0 = 0, x0 = 0, x1 = 0, y1 = 0;
+            if (tail) {
+                y0 = cell / n;
+                x0 = cell - y0 * n;
+                x1 = min(x0 + 1, n - 1);
+                y1 = min(y0 + 1, n - 1);
+            }
+            wave_sync_lds();
+            if (tail) {
+#pragma unroll
+                for (int c = 0; c < C; c++) tile[(y0 * n + x0) * C + c] += v[0 * C + c];
+            }
+            wave_sync_lds();
+            if (tail) {
+#pragma unroll
+                for (int c = 0; c < C; c++) tile[(y0 * n + x1) * C + c] += v[1 * C + c];
+            }
+            wave_sync_lds();
+            if (tail) {
+#pragma unroll
+                for (int c = 0; c < C; c++) tile[(y1 * n + x0) * C + c] += v[2 * C + c];
+            }
+            wave_sync_lds();
+            if (tail) {
+#pragma unroll
+                for (int c = 0; c < C; c++) tile[(y1 * n + x1) * C + c] += v[3 * C + c];
+            }
+            wave_sync_lds();
+        }
+    }
+}
+
+__device__ __forceinline__ void tile_zero(float* tile, int te) {
+    const int lane = threadIdx.x & 63;
+    for (int q = lane; q < te; q += 64) tile[q] = 0.f;
+    wave_sync_lds();
+}
+
+__device__ __forceinline__ void tile_store(const float* tile, float* __restrict__ dst, int te) {
+    const int lane = threadIdx.x & 63;
+    wave_sync_lds();
+    if ((te & 255) == 0) {
+        for (int q = lane; q < te / 4; q += 64) ((float4*)dst)[q] = ((const float4*)tile)[q];
+    } else {
+        for (int q = lane; q < te; q += 64) dst[q] = tile[q];
+    }
+}
+
+__device__ __forceinline__ void zero_store(float* __restrict__ dst, int te) {
+    const int lane = threadIdx.x & 63;
+    if ((te & 255) == 0) {
+        const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
+        for (int q = lane; q < te / 4; q += 64) ((float4*)dst)[q] = z;
+    } else {
+        for (int q = lane; q < te; q += 64) dst[q] = 0.f;
+    }
+}
+
+// pass 1: one wavefront per bucket, four buckets per workgroup
+template <int C, int MODE>
+__global__ __launch_bounds__(256) void k_segacc(const uint32_t* __restrict__ skeys,
+                                                const uint32_t* __restrict__ svals,
+                                                const float* __restrict__ wrec,
+                                                const float* __restrict__ grad_out,
+                                                const int2* __restrict__ range,
+                                                float* __restrict__ grad_tex, int64_t nbuckets,
+                                                int n, uint32_t cell_mask) {
+    extern __shared__ float lds[];
+    const int te = n * n * C;
+    const int w = threadIdx.x >> 6;
+    const int64_t b = (int64_t)xcd_block_id(blockIdx.x, gridDim.x) * 4 + w;
+    if (b >= nbuckets) return;
+    float* tile = lds + w * te;
+    float* dst = grad_tex + b * te;
+    const int2 r = range[b];
+    const int64_t cnt = (int64_t)r.y - r.x;
+    if (cnt <= 0) {
+        zero_store(dst, te);
+        return;
+    }
+    if (cnt > PIECE) return;  // hot bucket: pass 2
+    tile_zero(tile, te);
+    reduce_records<C, MODE>(skeys, svals, wrec, grad_out, r.x, r.y, n, cell_mask, tile);
+    tile_store(tile, dst, te);
+}
+
+// pass 2a: one wavefront per fixed chunk of PIECE sorted records; a hot bucket
+// overlapping the chunk (only the chunk's first or last bucket can be hot)
+// gets a partial tile, slot 0 for the first bucket and slot 1 for the last.
+template <int C, int MODE>
+__global__ __launch_bounds__(64) void k_segacc_hot(const uint32_t* __restrict__ skeys,
+                                                   const uint32_t* __restrict__ svals,
+                                                   const float* __restrict__ wrec,
+                                                   const float* __restrict__ grad_out,
+                                                   const int2* __restrict__ range,
+                                                   float* __restrict__ part, int64_t R, int n,
+                                                   int cell_bits) {
+    extern __shared__ float lds[];
+    const int te = n * n * C;
+    const uint32_t cell_mask = (cell_bits >= 32) ? 0xFFFFFFFFu : ((1u << cell_bits) - 1u);
+    const int64_t k = blockIdx.x;
+    const int64_t c0 = k * PIECE;
+    const int64_t c1 = (c0 + PIECE < R) ? c0 + PIECE : R;
+    const uint32_t bf = skeys[c0] >> cell_bits;
+    const uint32_t bl = skeys[c1 - 1] >> cell_bits;
+    for (int slot = 0; slot < 2; slot++) {
+        const uint32_t b = slot == 0 ? bf : bl;
+        if (slot == 1 && bl == bf) break;
+        const int2 r = range[b];
+        if ((int64_t)r.y - r.x <= PIECE) continue;
+        const int64_t a = r.x > c0 ? r.x : c0;
+        const int64_t e = r.y < c1 ? r.y : c1;
+        tile_zero(lds, te);
+        reduce_records<C, MODE>(skeys, svals, wrec, grad_out, a, e, n, cell_mask, lds);
+        tile_store(lds, part + (k * 2 + slot) * (int64_t)te, te);
+        wave_sync_lds();
+    }
+}
+
+// pass 2b: the chunk in which a hot bucket starts sums its partial tiles in
+// chunk order and writes the bucket's tile.
+__global__ __launch_bounds__(64) void k_combine_hot(const uint32_t* __restrict__ skeys,
+                                                    const int2* __restrict__ range,
+                                                    const float* __restrict__ part,
+                                                    float* __restrict__ grad_tex, int64_t R,
+                                                    int te, int cell_bits) {
+    const int lane = threadIdx.x;
+    const int64_t k = blockIdx.x;
+    const int64_t c0 = k * PIECE;
+    const int64_t c1 = (c0 + PIECE < R) ? c0 + PIECE : R;
+    const uint32_t bf = skeys[c0] >> cell_bits;
+    const uint32_t bl = skeys[c1 - 1] >> cell_bits;
+    for (int slot = 0; slot < 2; slot++) {
+        const uint32_t b = slot == 0 ? bf : bl;
+        if (slot == 1 && bl == bf) break;
+        const int2 r = range[b];
+        if ((int64_t)r.y - r.x <= PIECE) continue;
+        if ((int64_t)r.x / PIECE != k) continue;  // combined by the chunk it starts in
+        const int64_t k0 = (int64_t)r.x / PIECE, k1 = ((int64_t)r.y - 1) / PIECE;
+        float* dst = grad_tex + (int64_t)b * te;
+        for (int q0 = 0; q0 < te; q0 += 64 * 8) {
+            float acc[8];
+#pragma unroll
+            for (int u = 0; u < 8; u++) acc[u] = 0.f;
+            for (int64_t kc = k0; kc <= k1; kc++) {
+                const int s = ((skeys[kc * PIECE] >> cell_bits) == b) ? 0 : 1;
+                const float* src = part + (kc * 2 + s) * (int64_t)te;
+#pragma unroll
+                for (int u = 0; u < 8; u++) {
+                    const int q = q0 + u * 64 + lane;
+                    if (q < te) acc[u] += src[q];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 8; u++) {
+                const int q = q0 + u * 64 + lane;
+                if (q < te) dst[q] = acc[u];
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// planning and launch sequence
+// ---------------------------------------------------------------------------
+
+static int ceil_log2(uint64_t x) {
+    int b = 0;
+    while ((1ull << b) < x) b++;
+    return b;
+}
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+bool plan_backward(int W, int H, int n, int C, int64_t N, int mode, BwdPlan* p) {
+    const int64_t nb = (int64_t)W * H;
+    const int bucket_bits = ceil_log2((uint64_t)nb);
+    const int cell_bits = ceil_log2((uint64_t)n * n);
+    if (bucket_bits + cell_bits > 32) return false;
+    const int64_t R = mode == MODE_NEAREST ? N : 4 * N;
+    if (R >= (1ll << 31)) return false;
+    p->records = R;
+    p->key_bits = bucket_bits + cell_bits;
+    p->cell_bits = cell_bits;
+    p->passes = p->key_bits == 0 ? 1 : (p->key_bits + 7) / 8;
+    p->tiles = (R + SORT_TILE - 1) / SORT_TILE;
+    p->scan_len = 256 * p->tiles;
+    p->scan_blocks = (p->scan_len + SCAN_TILE - 1) / SCAN_TILE;
+    p->chunks = (R + PIECE - 1) / PIECE;
+    p->tile_elems = (int64_t)n * n * C;
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = o;
+        o += align256(bytes);
+        return at;
+    };
+    p->off_keys0 = take((size_t)R * 4);
+    p->off_keys1 = take((size_t)R * 4);
+    p->off_vals0 = take((size_t)R * 4);
+    p->off_vals1 = take((size_t)R * 4);
+    p->off_wrec = take((size_t)N * (mode == MODE_NEAREST ? 8 : 16));
+    p->off_hist = take((size_t)p->scan_len * 4);
+    p->off_hoff = take((size_t)p->scan_len * 4);
+    p->off_scanp = take((size_t)(p->scan_blocks + 1) * 4);
+    p->off_range = take((size_t)nb * 8);
+    p->off_part = take((size_t)p->chunks * 2 * p->tile_elems * 4);
+    p->total = o;
+    return true;
+}
+
+template <int FMT, int MODE>
+static void launch_bwd_fragment_c(const TexView& t, const float* uv, const float* tbn,
+                                  const float* view, const float* go, float* gview, float* guv,
+                                  uint32_t* keys, float* wrec, int64_t N, int cell_bits,
+                                  hipStream_t s) {
+    const uint32_t blocks = (uint32_t)((N + 255) / 256);
+    switch (t.C) {
+    case 1: hipLaunchKernelGGL((k_bwd_fragment<FMT, 1, MODE>), dim3(blocks), dim3(256), 0, s, t, uv, tbn, view, go, gview, guv, keys, wrec, N, cell_bits); break;
+    case 2: hipLaunchKernelGGL((k_bwd_fragment<FMT, 2, MODE>), dim3(blocks), dim3(256), 0, s, t, uv, tbn, view, go, gview, guv, keys, wrec, N, cell_bits); break;
+    case 3: hipLaunchKernelGGL((k_bwd_fragment<FMT, 3, MODE>), dim3(blocks), dim3(256), 0, s, t, uv, tbn, view, go, gview, guv, keys, wrec, N, cell_bits); break;
+    default: hipLaunchKernelGGL((k_bwd_fragment<FMT, 4, MODE>), dim3(blocks), dim3(256), 0, s, t, uv, tbn, view, go, gview, guv, keys, wrec, N, cell_bits); break;
+    }
+}
+
+template <int MODE>
+static void launch_segacc_c(int C, dim3 grid, size_t shm, hipStream_t s, const uint32_t* sk,
+                            const uint32_t* sv, const float* wrec, const float* go,
+                            const int2* range, float* gt, int64_t nb, int n, uint32_t mask) {
+    switch (C) {
+    case 1: hipLaunchKernelGGL((k_segacc<1, MODE>), grid, dim3(256), shm, s, sk, sv, wrec, go, range, gt, nb, n, mask); break;
+    case 2: hipLaunchKernelGGL((k_segacc<2, MODE>), grid, dim3(256), shm, s, sk, sv, wrec, go, range, gt, nb, n, mask); break;
+    case 3: hipLaunchKernelGGL((k_segacc<3, MODE>), grid, dim3(256), shm, s, sk, sv, wrec, go, range, gt, nb, n, mask); break;
+    default: hipLaunchKernelGGL((k_segacc<4, MODE>), grid, dim3(256), shm, s, sk, sv, wrec, go, range, gt, nb, n, mask); break;
+    }
+}
+
+template <int MODE>
+static void launch_segacc_hot_c(int C, dim3 grid, size_t shm, hipStream_t s, const uint32_t* sk,
+                                const uint32_t* sv, const float* wrec, const float* go,
+                                const int2* range, float* part, int64_t R, int n, int cb) {
+    switch (C) {
+    case 1: hipLaunchKernelGGL((k_segacc_hot<1, MODE>), grid, dim3(64), shm, s, sk, sv, wrec, go, range, part, R, n, cb); break;
+    case 2: hipLaunchKernelGGL((k_segacc_hot<2, MODE>), grid, dim3(64), shm, s, sk, sv, wrec, go, range, part, R, n, cb); break;
+    case 3: hipLaunchKernelGGL((k_segacc_hot<3, MODE>), grid, dim3(64), shm, s, sk, sv, wrec, go, range, part, R, n, cb); break;
+    default: hipLaunchKernelGGL((k_segacc_hot<4, MODE>), grid, dim3(64), shm, s, sk, sv, wrec, go, range, part, R, n, cb); break;
+    }
+}
+
+static void launch_fill(uint32_t* p, int64_t n, uint32_t v, hipStream_t s) {
+    if (n <= 0) return;
+    prof_begin(K_FILL, s);
+    hipLaunchKernelGGL(k_fill_u32, dim3((uint32_t)((n + 255) / 256)), dim3(256), 0, s, p, n, v);
+    prof_end(K_FILL, s);
+}
+
+static void launch_scan(const uint32_t* in, uint32_t* out, uint32_t* part, int64_t L,
+                        int64_t blocks, hipStream_t s) {
+    prof_begin(K_SCAN, s);
+    hipLaunchKernelGGL(k_scan_reduce, dim3((uint32_t)blocks), dim3(256), 0, s, in, L, part);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(256), 0, s, part, blocks);
+    hipLaunchKernelGGL(k_scan_down, dim3((uint32_t)blocks), dim3(256), 0, s, in, L, part, out);
+    prof_end(K_SCAN, s);
+}
+
+hipError_t launch_backward(const TexView& t, int fmt, int mode, const float* uv,
+                           const float* tbn, const float* view, const float* grad_out,
+                           float* grad_tex, float* grad_view, float* grad_uv, int64_t N,
+                           const BwdPlan& plan, void* ws, hipStream_t s) {
+    char* wsb = (char*)ws;
+    uint32_t* keys0 = (uint32_t*)(wsb + plan.off_keys0);
+    uint32_t* keys1 = (uint32_t*)(wsb + plan.off_keys1);
+    uint32_t* vals0 = (uint32_t*)(wsb + plan.off_vals0);
+    uint32_t* vals1 = (uint32_t*)(wsb + plan.off_vals1);
+    float* wrec = (float*)(wsb + plan.off_wrec);
+    uint32_t* hist = (uint32_t*)(wsb + plan.off_hist);
+    uint32_t* hoff = (uint32_t*)(wsb + plan.off_hoff);
+    uint32_t* scanp = (uint32_t*)(wsb + plan.off_scanp);
+    int2* range = (int2*)(wsb + plan.off_range);
+    float* part = (float*)(wsb + plan.off_part);
+    const int64_t R = plan.records;
+    const bool want_tex = grad_tex != nullptr;
+
+    // 1. per fragment
+    if (N > 0 && (want_tex || grad_view || grad_uv)) {
+        prof_begin(K_BWD_FRAGMENT, s);
+        uint32_t* kp = want_tex ? keys0 : nullptr;
+        if (mode == MODE_NEAREST) {
+            if (fmt == FMT_F32) launch_bwd_fragment_c<FMT_F32, MODE_NEAREST>(t, uv, tbn, view, grad_out, grad_view, grad_uv, kp, wrec, N, plan.cell_bits, s);
+            else if (fmt == FMT_BF16) launch_bwd_fragment_c<FMT_BF16, MODE_NEAREST>(t, uv, tbn, view, grad_out, grad_view, grad_uv, kp, wrec, N, plan.cell_bits, s);
+            else launch_bwd_fragment_c<FMT_FP8, MODE_NEAREST>(t, uv, tbn, view, grad_out, grad_view, grad_uv, kp, wrec, N, plan.cell_bits, s);
+        } else {
+            if (fmt == FMT_F32) launch_bwd_fragment_c<FMT_F32, MODE_BILINEAR>(t, uv, tbn, view, grad_out, grad_view, grad_uv, kp, wrec, N, plan.cell_bits, s);
+            else if (fmt == FMT_BF16) launch_bwd_fragment_c<FMT_BF16, MODE_BILINEAR>(t, uv, tbn, view, grad_out, grad_view, grad_uv, kp, wrec, N, plan.cell_bits, s);
+            else launch_bwd_fragment_c<FMT_FP8, MODE_BILINEAR>(t, uv, tbn, view, grad_out, grad_view, grad_uv, kp, wrec, N, plan.cell_bits, s);
+        }
+        prof_end(K_BWD_FRAGMENT, s);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if (!want_tex) return hipSuccess;
+
+    // 2. sort
+    const uint32_t* skeys = keys0;
+    const uint32_t* svals = nullptr;
+    if (R > 0) {
+        const uint32_t* kin = keys0;
+        const uint32_t* vin = nullptr;
+        for (int pass = 0; pass < plan.passes; pass++) {
+            uint32_t* kout = (pass & 1) ? keys0 : keys1;
+            uint32_t* vout = (pass & 1) ? vals0 : vals1;
+            const int shift = 8 * pass;
+            prof_begin(K_RADIX_HIST, s);
+            hipLaunchKernelGGL(k_radix_hist, dim3((uint32_t)plan.tiles), dim3(SORT_THREADS), 0, s,
+                               kin, R, shift, hist, plan.tiles);
+            prof_end(K_RADIX_HIST, s);
+            launch_scan(hist, hoff, scanp, plan.scan_len, plan.scan_blocks, s);
+            prof_begin(K_RADIX_SCATTER, s);
+            hipLaunchKernelGGL(k_radix_scatter, dim3((uint32_t)plan.tiles), dim3(SORT_THREADS), 0,
+                               s, kin, vin, kout, vout, R, shift, hist, hoff, plan.tiles);
+            prof_end(K_RADIX_SCATTER, s);
+            kin = kout;
+            vin = vout;
+        }
+        skeys = kin;
+        svals = vin;
+    }
+
+    // 3. ranges
+    const int64_t nb = (int64_t)t.W * t.H;
+    launch_fill((uint32_t*)range, nb * 2, 0u, s);
+    if (R > 0) {
+        prof_begin(K_BUCKET_RANGES, s);
+        hipLaunchKernelGGL(k_bucket_ranges, dim3((uint32_t)((R + 255) / 256)), dim3(256), 0, s,
+                           skeys, R, plan.cell_bits, range);
+        prof_end(K_BUCKET_RANGES, s);
+    }
+
+    // 4. pass 1 over buckets
+    const int te = (int)plan.tile_elems;
+    const uint32_t cell_mask = plan.cell_bits >= 32 ? 0xFFFFFFFFu : ((1u << plan.cell_bits) - 1u);
+    prof_begin(K_SEGACC, s);
+    const dim3 g1((uint32_t)((nb + 3) / 4));
+    if (mode == MODE_NEAREST)
+        launch_segacc_c<MODE_NEAREST>(t.C, g1, (size_t)4 * te * 4, s, skeys, svals, wrec, grad_out, range, grad_tex, nb, t.n, cell_mask);
+    else
+        launch_segacc_c<MODE_BILINEAR>(t.C, g1, (size_t)4 * te * 4, s, skeys, svals, wrec, grad_out, range, grad_tex, nb, t.n, cell_mask);
+    prof_end(K_SEGACC, s);
+
+    // 5. pass 2 for buckets with more than PIECE records
+    if (R > PIECE) {
+        const dim3 g2((uint32_t)plan.chunks);
+        prof_begin(K_SEGACC_HOT, s);
+        if (mode == MODE_NEAREST)
+            launch_segacc_hot_c<MODE_NEAREST>(t.C, g2, (size_t)te * 4, s, skeys, svals, wrec, grad_out, range, part, R, t.n, plan.cell_bits);
+        else
+            launch_segacc_hot_c<MODE_BILINEAR>(t.C, g2, (size_t)te * 4, s, skeys, svals, wrec, grad_out, range, part, R, t.n, plan.cell_bits);
+        prof_end(K_SEGACC_HOT, s);
+        prof_begin(K_COMBINE_HOT, s);
+        hipLaunchKernelGGL(k_combine_hot, g2, dim3(64), 0, s, skeys, range, part, grad_tex, R, te,
+                           plan.cell_bits);
+        prof_end(K_COMBINE_HOT, s);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace rt

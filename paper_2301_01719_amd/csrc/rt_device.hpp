@@ -1,0 +1,232 @@
+// rt_device.hpp -- device-side building blocks shared by the gfx950 kernels of
+// the radiance-bucket lookup: the incidence -> bucket mapping in binary32,
+// texel loads and decodes for the three storage formats, and launch helpers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rt {
+
+constexpr int FMT_F32 = 0;
+constexpr int FMT_BF16 = 1;
+constexpr int FMT_FP8 = 2;
+
+constexpr int MODE_NEAREST = 0;
+constexpr int MODE_BILINEAR = 1;
+
+// Texture as seen by a kernel: bucket-major [H][W][n][n][C].
+struct TexView {
+    const void* data;
+    const float* scales;  // [H][W], FP8 only
+    int W, H, n, C;
+};
+
+// ---------------------------------------------------------------------------
+// Launch geometry: gfx950 places consecutive workgroups of a launch on its 8
+// XCDs round-robin.  Renumbering the workgroups so that each XCD receives a
+// contiguous range of the logical index space keeps neighbouring fragments
+// (which land in the same buckets) on the same L2.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t xcd_block_id(uint32_t bid, uint32_t nblocks) {
+    constexpr uint32_t XCDS = 8;
+    uint32_t xcd = bid % XCDS;
+    uint32_t q = nblocks / XCDS, r = nblocks % XCDS;
+    uint32_t before = xcd * q + (xcd < r ? xcd : r);
+    return before + bid / XCDS;
+}
+
+// ---------------------------------------------------------------------------
+// Decodes.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float bf16_lo(uint32_t w) { return __uint_as_float(w << 16); }
+__device__ __forceinline__ float bf16_hi(uint32_t w) { return __uint_as_float(w & 0xFFFF0000u); }
+
+// E4M3 byte -> binary32 value divided by 2^8.  The byte's exponent and
+// mantissa fields are placed in the corresponding fields of a binary16 (whose
+// exponent bias is 8 larger), which represents e4m3 * 2^-8 exactly for every
+// finite code, subnormals included; the 2^8 is folded into the bucket scale.
+__device__ __forceinline__ float e4m3_div256(uint32_t byte) {
+    uint32_t h = ((byte & 0x80u) << 8) | ((byte & 0x7Fu) << 7);
+    return (float)__builtin_bit_cast(_Float16, (unsigned short)h);
+}
+
+struct F4 {
+    float v[4];
+};
+
+// Load the C channels of texel `t` (index in texels, bucket-major) as
+// binary32.  For FP8 the values are e4m3/256; the caller multiplies by
+// 256 * scale once per bucket.
+template <int FMT, int C>
+__device__ __forceinline__ F4 load_texel(const void* __restrict__ data, int64_t t) {
+    F4 r;
+#pragma unroll
+    for (int c = 0; c < 4; c++) r.v[c] = 0.f;
+    if constexpr (FMT == FMT_F32) {
+        const float* p = (const float*)data;
+        if constexpr (C == 4) {
+            float4 q = ((const float4*)p)[t];
+            r.v[0] = q.x; r.v[1] = q.y; r.v[2] = q.z; r.v[3] = q.w;
+        } else if constexpr (C == 2) {
+            float2 q = ((const float2*)p)[t];
+            r.v[0] = q.x; r.v[1] = q.y;
+        } else {
+#pragma unroll
+            for (int c = 0; c < C; c++) r.v[c] = p[t * C + c];
+        }
+    } else if constexpr (FMT == FMT_BF16) {
+        const uint16_t* p = (const uint16_t*)data;
+        if constexpr (C == 4) {
+            uint2 q = ((const uint2*)p)[t];
+            r.v[0] = bf16_lo(q.x); r.v[1] = bf16_hi(q.x);
+            r.v[2] = bf16_lo(q.y); r.v[3] = bf16_hi(q.y);
+        } else if constexpr (C == 2) {
+            uint32_t q = ((const uint32_t*)p)[t];
+            r.v[0] = bf16_lo(q); r.v[1] = bf16_hi(q);
+        } else {
+#pragma unroll
+            for (int c = 0; c < C; c++) r.v[c] = bf16_lo((uint32_t)p[t * C + c]);
+        }
+    } else {
+        const uint8_t* p = (const uint8_t*)data;
+        if constexpr (C == 4) {
+            uint32_t q = ((const uint32_t*)p)[t];
+#pragma unroll
+            for (int c = 0; c < 4; c++) r.v[c] = e4m3_div256((q >> (8 * c)) & 0xFFu);
+        } else if constexpr (C == 2) {
+            uint32_t q = ((const uint16_t*)p)[t];
+            r.v[0] = e4m3_div256(q & 0xFFu); r.v[1] = e4m3_div256(q >> 8);
+        } else {
+#pragma unroll
+            for (int c = 0; c < C; c++) r.v[c] = e4m3_div256((uint32_t)p[t * C + c]);
+        }
+    }
+    return r;
+}
+
+// Factor applied to a bucket's decoded samples: 1, or 256 * scale for FP8.
+template <int FMT>
+__device__ __forceinline__ float bucket_factor(const float* __restrict__ scales, int64_t b) {
+    if constexpr (FMT == FMT_FP8) return 256.0f * scales[b];
+    else return 1.0f;
+}
+
+// ---------------------------------------------------------------------------
+// Fragment inputs.
+// ---------------------------------------------------------------------------
+struct Frag {
+    float u, v;
+    float m[9];
+    float w[3];
+};
+
+__device__ __forceinline__ Frag load_frag(const float* __restrict__ uv, const float* __restrict__ tbn,
+                                          const float* __restrict__ view, int64_t f) {
+    Frag r;
+    float2 t = ((const float2*)uv)[f];
+    r.u = t.x;
+    r.v = t.y;
+#pragma unroll
+    for (int k = 0; k < 9; k++) r.m[k] = tbn[f * 9 + k];
+#pragma unroll
+    for (int k = 0; k < 3; k++) r.w[k] = view[f * 3 + k];
+    return r;
+}
+
+// ---------------------------------------------------------------------------
+// Incidence -> in-bucket sample coordinate, binary32.
+//
+//   u = M V (rows T, B, N), L = |u|
+//   Eq. (1b) with I = u / L:  A = sqrt(2) (I_x, I_y) / |(I_x, I_y, I_z + 1)|.
+//   For unit I, |(I_x, I_y, I_z + 1)|^2 = 2 (1 + I_z), so A = (u_x, u_y) k with
+//   k = 1 / sqrt(L (L + u_z)); this form avoids normalising u first.
+//   Eq. (3): B = (|A|_2 / max(|A_x|, |A_y|)) A, B = 0 at A = 0.
+//   Clamp (Note after Eq. 3) and texel centres: s = clamp((B + 1) n/2 - 1/2, 0, n-1).
+// ---------------------------------------------------------------------------
+struct Dir {
+    float sx, sy;        // clamped sample coordinates
+    bool clx, cly;       // axis at or beyond its clamp bound
+    float ax, ay;        // A
+    float ux, uy, uz, L; // tangent-space incidence before normalisation
+    float k;             // 1 / sqrt(L (L + u_z))
+};
+
+__device__ __forceinline__ Dir map_direction(const float m[9], const float w[3], int n) {
+    Dir d;
+    d.ux = m[0] * w[0] + m[1] * w[1] + m[2] * w[2];
+    d.uy = m[3] * w[0] + m[4] * w[1] + m[5] * w[2];
+    d.uz = m[6] * w[0] + m[7] * w[1] + m[8] * w[2];
+    d.L = sqrtf(d.ux * d.ux + d.uy * d.uy + d.uz * d.uz);
+    float q = d.L * (d.L + d.uz);
+    d.k = q > 0.f ? 1.0f / sqrtf(q) : 0.f;  // q = 0: I = -N (or u = 0): A = 0
+    d.ax = d.ux * d.k;
+    d.ay = d.uy * d.k;
+    float rho = sqrtf(d.ax * d.ax + d.ay * d.ay);
+    float mx = fmaxf(fabsf(d.ax), fabsf(d.ay));
+    float r = mx > 0.f ? rho / mx : 0.f;
+    float bx = d.ax * r, by = d.ay * r;
+    float half_n = 0.5f * (float)n;
+    float top = (float)(n - 1);
+    float sx = (bx + 1.0f) * half_n - 0.5f;
+    float sy = (by + 1.0f) * half_n - 0.5f;
+    d.clx = !(sx > 0.f && sx < top);
+    d.cly = !(sy > 0.f && sy < top);
+    d.sx = fminf(fmaxf(sx, 0.f), top);  // NaN -> 0
+    d.sy = fminf(fmaxf(sy, 0.f), top);
+    return d;
+}
+
+// Bilinear footprint inside a bucket.  The first sample is kept at or below
+// n-2 so that the second is always x0+1 (at s = n-1 the weight of the first is
+// then exactly 0); for n = 1 both are sample 0.
+struct Foot {
+    int x0, y0, x1, y1;
+    float fx, fy;
+};
+
+__device__ __forceinline__ Foot footprint(float sx, float sy, int n) {
+    Foot p;
+    int hi = n >= 2 ? n - 2 : 0;
+    p.x0 = min((int)sx, hi);
+    p.y0 = min((int)sy, hi);
+    p.x1 = min(p.x0 + 1, n - 1);
+    p.y1 = min(p.y0 + 1, n - 1);
+    p.fx = sx - (float)p.x0;
+    p.fy = sy - (float)p.y0;
+    if (n == 1) { p.fx = 0.f; p.fy = 0.f; }
+    return p;
+}
+
+// Bucket column (or row) of a texture coordinate: floor(frac(u) W) with the UV
+// plane repeating.  It is evaluated as floor(u W) mod W, which is the same
+// integer, because u W is exact for a power-of-two W whereas frac(u) = u + 1
+// of a small negative u is not representable in binary32.  Non-finite and
+// huge coordinates (where binary32 has no fraction left) select bucket 0.
+__device__ __forceinline__ int bucket_of(float u, int W) {
+    const float fq = floorf(u * (float)W);
+    if (!(fabsf(fq) < 1073741824.0f)) return 0;
+    const int i = (int)fq % W;
+    return i < 0 ? i + W : i;
+}
+
+// Bilinear-bucket footprint in UV: p = frac(u) W - 1/2, columns floor(p) and
+// floor(p)+1 (wrapping), weight a = p - floor(p).  Evaluated from
+// q = u W - 1/2 (one rounding, exact for a power-of-two W) for the reason
+// given above; non-finite and huge coordinates behave as u = 0.
+__device__ __forceinline__ void bucket_pair(float u, int W, int& i0, int& i1, float& a) {
+    const float q = fmaf(u, (float)W, -0.5f);
+    const float fq = floorf(q);
+    if (!(fabsf(fq) < 1073741824.0f)) {
+        i0 = W - 1;
+        i1 = 0;
+        a = 0.5f;
+        return;
+    }
+    a = q - fq;
+    int k = (int)fq % W;
+    i0 = k < 0 ? k + W : k;
+    i1 = i0 + 1 == W ? 0 : i0 + 1;
+}
+
+}  // namespace rt

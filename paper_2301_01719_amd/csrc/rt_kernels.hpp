@@ -1,0 +1,69 @@
+// rt_kernels.hpp -- host-side launchers of the gfx950 kernels (internal to
+// libradtex.so; the public interface is include/radtex.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace rt {
+
+struct TexView;
+
+// Kernel ids for the event-based timing of rt_profile_*.
+enum KernelId {
+    K_LOOKUP_FWD = 0,
+    K_DEBUG_INDICES,
+    K_QUANT_BF16,
+    K_QUANT_FP8,
+    K_ATLAS_RELAYOUT,
+    K_BWD_FRAGMENT,
+    K_FILL,
+    K_RADIX_HIST,
+    K_SCAN,
+    K_RADIX_SCATTER,
+    K_BUCKET_RANGES,
+    K_SEGACC,
+    K_SEGACC_HOT,
+    K_COMBINE_HOT,
+    K_COUNT
+};
+const char* kernel_name(int id);
+void prof_begin(int id, hipStream_t s);
+void prof_end(int id, hipStream_t s);
+
+hipError_t launch_lookup_fwd(const TexView& t, int fmt, int mode, const float* uv,
+                             const float* tbn, const float* view, float* out, int64_t N,
+                             hipStream_t s);
+hipError_t launch_debug_indices(const TexView& t, const float* uv, const float* tbn,
+                                const float* view, int32_t* idx, float* frac, int64_t N,
+                                hipStream_t s);
+hipError_t launch_quantize(const TexView& src, int dst_fmt, void* codes, float* scales,
+                           hipStream_t s);
+hipError_t launch_atlas_to_buckets(const void* atlas, void* dst, int W, int H, int n, int C,
+                                   int elem_bytes, hipStream_t s);
+
+// Backward.
+struct BwdPlan {
+    int64_t records;      // N (nearest) or 4N (bilinear-bucket)
+    int key_bits;         // bucket bits + cell bits
+    int cell_bits;
+    int passes;           // radix passes of 8 bits
+    int64_t tiles;        // radix tiles
+    int64_t scan_len;     // 256 * tiles
+    int64_t scan_blocks;  // partial sums of the scan
+    int64_t chunks;       // fixed chunks of the sorted records (hot buckets)
+    int64_t tile_elems;   // n*n*C
+    // workspace offsets (bytes)
+    size_t off_keys0, off_keys1, off_vals0, off_vals1, off_wrec, off_hist, off_hoff, off_scanp,
+        off_range, off_part, total;
+};
+constexpr int PIECE = 2048;  // records per chunk; buckets with more are "hot"
+bool plan_backward(int W, int H, int n, int C, int64_t N, int mode, BwdPlan* p);
+
+hipError_t launch_backward(const TexView& t, int fmt, int mode, const float* uv,
+                           const float* tbn, const float* view, const float* grad_out,
+                           float* grad_tex, float* grad_view, float* grad_uv, int64_t N,
+                           const BwdPlan& plan, void* ws, hipStream_t s);
+
+}  // namespace rt

@@ -1,0 +1,129 @@
+// rt_lookup.hip -- forward radiance-bucket lookup for gfx950.
+//
+// One lane per fragment.  Per lane: the 56-byte G-buffer record (uv, frame,
+// view) is read, the incidence is mapped to the in-bucket sample coordinate
+// (Eq. 1b, Eq. 3, the clamp after Eq. 3), the bucket is selected from (u, v)
+// (Sec. 2) and four taps of C channels are read from the bucket-major
+// texture and blended bilinearly.  The path is a gather: no contraction, so
+// no MFMA; the bound is HBM bandwidth (the G-buffer stream dominates).
+#include "rt_device.hpp"
+#include "rt_kernels.hpp"
+
+namespace rt {
+
+template <int FMT, int C>
+__device__ __forceinline__ void bucket_bilerp(const TexView& t, int64_t b, const Foot& p,
+                                              float wgt, float acc[4]) {
+    const int n = t.n;
+    const int64_t base = b * (int64_t)(n * n);
+    F4 t00 = load_texel<FMT, C>(t.data, base + p.y0 * n + p.x0);
+    F4 t01 = load_texel<FMT, C>(t.data, base + p.y0 * n + p.x1);
+    F4 t10 = load_texel<FMT, C>(t.data, base + p.y1 * n + p.x0);
+    F4 t11 = load_texel<FMT, C>(t.data, base + p.y1 * n + p.x1);
+    float f = wgt * bucket_factor<FMT>(t.scales, b);
+    float w00 = (1.f - p.fx) * (1.f - p.fy), w01 = p.fx * (1.f - p.fy);
+    float w10 = (1.f - p.fx) * p.fy, w11 = p.fx * p.fy;
+#pragma unroll
+    for (int c = 0; c < C; c++) {
+        float v = w00 * t00.v[c] + w01 * t01.v[c] + w10 * t10.v[c] + w11 * t11.v[c];
+        acc[c] += f * v;
+    }
+}
+
+template <int C>
+__device__ __forceinline__ void store_out(float* __restrict__ out, int64_t f, const float acc[4]) {
+    if constexpr (C == 4) {
+        ((float4*)out)[f] = make_float4(acc[0], acc[1], acc[2], acc[3]);
+    } else if constexpr (C == 2) {
+        ((float2*)out)[f] = make_float2(acc[0], acc[1]);
+    } else {
+#pragma unroll
+        for (int c = 0; c < C; c++) out[f * C + c] = acc[c];
+    }
+}
+
+template <int FMT, int C, int MODE>
+__global__ __launch_bounds__(256) void k_lookup_fwd(TexView t, const float* __restrict__ uv,
+                                                    const float* __restrict__ tbn,
+                                                    const float* __restrict__ view,
+                                                    float* __restrict__ out, int64_t N) {
+    const uint32_t blk = xcd_block_id(blockIdx.x, gridDim.x);
+    const int64_t f = (int64_t)blk * 256 + threadIdx.x;
+    if (f >= N) return;
+    Frag g = load_frag(uv, tbn, view, f);
+    Dir d = map_direction(g.m, g.w, t.n);
+    Foot p = footprint(d.sx, d.sy, t.n);
+    float acc[4] = {0.f, 0.f, 0.f, 0.f};
+    if constexpr (MODE == MODE_NEAREST) {
+        int i = bucket_of(g.u, t.W), j = bucket_of(g.v, t.H);
+        bucket_bilerp<FMT, C>(t, (int64_t)j * t.W + i, p, 1.0f, acc);
+    } else {
+        int i0, i1, j0, j1;
+        float a, bb;
+        bucket_pair(g.u, t.W, i0, i1, a);
+        bucket_pair(g.v, t.H, j0, j1, bb);
+        bucket_bilerp<FMT, C>(t, (int64_t)j0 * t.W + i0, p, (1.f - a) * (1.f - bb), acc);
+        bucket_bilerp<FMT, C>(t, (int64_t)j0 * t.W + i1, p, a * (1.f - bb), acc);
+        bucket_bilerp<FMT, C>(t, (int64_t)j1 * t.W + i0, p, (1.f - a) * bb, acc);
+        bucket_bilerp<FMT, C>(t, (int64_t)j1 * t.W + i1, p, a * bb, acc);
+    }
+    store_out<C>(out, f, acc);
+}
+
+__global__ __launch_bounds__(256) void k_debug_indices(TexView t, const float* __restrict__ uv,
+                                                       const float* __restrict__ tbn,
+                                                       const float* __restrict__ view,
+                                                       int32_t* __restrict__ idx,
+                                                       float* __restrict__ frac, int64_t N) {
+    const int64_t f = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (f >= N) return;
+    Frag g = load_frag(uv, tbn, view, f);
+    Dir d = map_direction(g.m, g.w, t.n);
+    int x0 = (int)d.sx, y0 = (int)d.sy;
+    ((int4*)idx)[f] = make_int4(bucket_of(g.u, t.W), bucket_of(g.v, t.H), x0, y0);
+    ((float2*)frac)[f] = make_float2(d.sx - (float)x0, d.sy - (float)y0);
+}
+
+template <int FMT, int MODE>
+static hipError_t launch_fwd_c(const TexView& t, const float* uv, const float* tbn,
+                               const float* view, float* out, int64_t N, hipStream_t s) {
+    const uint32_t blocks = (uint32_t)((N + 255) / 256);
+    switch (t.C) {
+    case 1: hipLaunchKernelGGL((k_lookup_fwd<FMT, 1, MODE>), dim3(blocks), dim3(256), 0, s, t, uv, tbn, view, out, N); break;
+    case 2: hipLaunchKernelGGL((k_lookup_fwd<FMT, 2, MODE>), dim3(blocks), dim3(256), 0, s, t, uv, tbn, view, out, N); break;
+    case 3: hipLaunchKernelGGL((k_lookup_fwd<FMT, 3, MODE>), dim3(blocks), dim3(256), 0, s, t, uv, tbn, view, out, N); break;
+    default: hipLaunchKernelGGL((k_lookup_fwd<FMT, 4, MODE>), dim3(blocks), dim3(256), 0, s, t, uv, tbn, view, out, N); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_lookup_fwd(const TexView& t, int fmt, int mode, const float* uv,
+                             const float* tbn, const float* view, float* out, int64_t N,
+                             hipStream_t s) {
+    if (N <= 0) return hipSuccess;
+    hipError_t e;
+    prof_begin(K_LOOKUP_FWD, s);
+    if (mode == MODE_NEAREST) {
+        if (fmt == FMT_F32) e = launch_fwd_c<FMT_F32, MODE_NEAREST>(t, uv, tbn, view, out, N, s);
+        else if (fmt == FMT_BF16) e = launch_fwd_c<FMT_BF16, MODE_NEAREST>(t, uv, tbn, view, out, N, s);
+        else e = launch_fwd_c<FMT_FP8, MODE_NEAREST>(t, uv, tbn, view, out, N, s);
+    } else {
+        if (fmt == FMT_F32) e = launch_fwd_c<FMT_F32, MODE_BILINEAR>(t, uv, tbn, view, out, N, s);
+        else if (fmt == FMT_BF16) e = launch_fwd_c<FMT_BF16, MODE_BILINEAR>(t, uv, tbn, view, out, N, s);
+        else e = launch_fwd_c<FMT_FP8, MODE_BILINEAR>(t, uv, tbn, view, out, N, s);
+    }
+    prof_end(K_LOOKUP_FWD, s);
+    return e;
+}
+
+hipError_t launch_debug_indices(const TexView& t, const float* uv, const float* tbn,
+                                const float* view, int32_t* idx, float* frac, int64_t N,
+                                hipStream_t s) {
+    if (N <= 0) return hipSuccess;
+    const uint32_t blocks = (uint32_t)((N + 255) / 256);
+    hipLaunchKernelGGL(k_debug_indices, dim3(blocks), dim3(256), 0, s, t, uv, tbn, view, idx,
+                       frac, N);
+    return hipGetLastError();
+}
+
+}  // namespace rt

@@ -1,0 +1,187 @@
+// rt_quantize.hip -- per-bucket BF16 / FP8-E4M3 quantiser and the atlas ->
+// bucket-major re-layout, for gfx950.
+//
+// Both are HBM streams.  BF16 is elementwise (float4 in, 4 x bf16 out).  FP8
+// runs one wavefront per bucket: the bucket's amax is reduced across the wave
+// with cross-lane max, then every lane encodes its values with the bucket's
+// inverse scale.  Encodes are written from the formats' definitions with
+// integer arithmetic (round to nearest even, E4M3 saturating to +-448).
+#include "rt_device.hpp"
+#include "rt_kernels.hpp"
+
+namespace rt {
+
+// binary32 -> bfloat16 bits, round to nearest even; NaN stays (quiet) NaN.
+__device__ __forceinline__ uint32_t f32_to_bf16_bits(float x) {
+    uint32_t b = __float_as_uint(x);
+    if ((b & 0x7FFFFFFFu) > 0x7F800000u) return (b >> 16) | 0x40u;
+    return (b + 0x7FFFu + ((b >> 16) & 1u)) >> 16;
+}
+
+// binary32 -> OCP E4M3 (bias 7, max 448, S.1111.111 = NaN), round to nearest
+// even, saturating: magnitudes >= 448 and infinities give 448.
+__device__ __forceinline__ uint32_t f32_to_e4m3_bits(float y) {
+    uint32_t b = __float_as_uint(y);
+    uint32_t sign = (b >> 24) & 0x80u;
+    uint32_t a = b & 0x7FFFFFFFu;
+    if (a > 0x7F800000u) return sign | 0x7Fu;   // NaN
+    if (a >= 0x43E00000u) return sign | 0x7Eu;  // >= 448
+    if (a < 0x3C800000u) {                       // below 2^-6: multiples of 2^-9
+        float t = __uint_as_float(a) * 512.0f;   // exact
+        return sign | (uint32_t)rintf(t);        // 0..8 (8 is the first normal)
+    }
+    // keep 3 mantissa bits, round to nearest even on the 20 dropped bits; a
+    // carry moves into the exponent field, which is the right result
+    uint32_t r = a + 0x7FFFFu + ((a >> 20) & 1u);
+    return sign | ((r >> 20) - (120u << 3));
+}
+
+__global__ __launch_bounds__(256) void k_quant_bf16(const float* __restrict__ src,
+                                                    uint16_t* __restrict__ dst, int64_t total) {
+    const int64_t q = ((int64_t)xcd_block_id(blockIdx.x, gridDim.x) * 256 + threadIdx.x);
+    const int64_t e = q * 4;
+    if (e + 3 < total) {
+        float4 v = ((const float4*)src)[q];
+        uint2 o;
+        o.x = f32_to_bf16_bits(v.x) | (f32_to_bf16_bits(v.y) << 16);
+        o.y = f32_to_bf16_bits(v.z) | (f32_to_bf16_bits(v.w) << 16);
+        ((uint2*)dst)[q] = o;
+    } else {
+        for (int64_t k = e; k < total; k++) dst[k] = (uint16_t)f32_to_bf16_bits(src[k]);
+    }
+}
+
+__device__ __forceinline__ float wave_max(float v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// One wavefront per bucket; VEC: the bucket's element count is a multiple of
+// 256 so each lane handles whole float4s (the common n = 8, 16 RGBA case),
+// and at most 4 float4 per lane stay in registers between the two passes.
+template <bool VEC>
+__global__ __launch_bounds__(256) void k_quant_fp8(const float* __restrict__ src,
+                                                   uint8_t* __restrict__ dst,
+                                                   float* __restrict__ scales,
+                                                   int64_t n_buckets, int elems) {
+    const int lane = threadIdx.x & 63;
+    const int64_t b =
+        (int64_t)xcd_block_id(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
+    if (b >= n_buckets) return;
+    const float* s = src + b * elems;
+    uint8_t* d = dst + b * elems;
+    float amax = 0.f;
+    if constexpr (VEC) {
+        const int per_lane = elems / 256;  // float4 per lane
+        float4 cache[4];
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            if (k < per_lane) {
+                cache[k] = ((const float4*)s)[k * 64 + lane];
+                amax = fmaxf(amax, fmaxf(fmaxf(fabsf(cache[k].x), fabsf(cache[k].y)),
+                                         fmaxf(fabsf(cache[k].z), fabsf(cache[k].w))));
+            }
+        }
+        for (int k = 4; k < per_lane; k++) {
+            float4 v = ((const float4*)s)[k * 64 + lane];
+            amax = fmaxf(amax, fmaxf(fmaxf(fabsf(v.x), fabsf(v.y)), fmaxf(fabsf(v.z), fabsf(v.w))));
+        }
+        amax = wave_max(amax);
+        float inv = 1.f, scale = 1.f;
+        if (amax > 0.f && amax <= 3.402823466e38f) {
+            inv = 448.0f / amax;
+            scale = amax / 448.0f;
+        }
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            if (k < per_lane) {
+                float4 v = cache[k];
+                uint32_t w = f32_to_e4m3_bits(v.x * inv) | (f32_to_e4m3_bits(v.y * inv) << 8) |
+                             (f32_to_e4m3_bits(v.z * inv) << 16) | (f32_to_e4m3_bits(v.w * inv) << 24);
+                ((uint32_t*)d)[k * 64 + lane] = w;
+            }
+        }
+        for (int k = 4; k < per_lane; k++) {
+            float4 v = ((const float4*)s)[k * 64 + lane];
+            uint32_t w = f32_to_e4m3_bits(v.x * inv) | (f32_to_e4m3_bits(v.y * inv) << 8) |
+                         (f32_to_e4m3_bits(v.z * inv) << 16) | (f32_to_e4m3_bits(v.w * inv) << 24);
+            ((uint32_t*)d)[k * 64 + lane] = w;
+        }
+        if (lane == 0) scales[b] = scale;
+    } else {
+        for (int e = lane; e < elems; e += 64) amax = fmaxf(amax, fabsf(s[e]));
+        amax = wave_max(amax);
+        float inv = 1.f, scale = 1.f;
+        if (amax > 0.f && amax <= 3.402823466e38f) {
+            inv = 448.0f / amax;
+            scale = amax / 448.0f;
+        }
+        for (int e = lane; e < elems; e += 64) d[e] = (uint8_t)f32_to_e4m3_bits(s[e] * inv);
+        if (lane == 0) scales[b] = scale;
+    }
+}
+
+hipError_t launch_quantize(const TexView& t, int dst_fmt, void* codes, float* scales,
+                           hipStream_t s) {
+    const int64_t nb = (int64_t)t.W * t.H;
+    const int elems = t.n * t.n * t.C;
+    if (dst_fmt == FMT_BF16) {
+        const int64_t total = nb * elems;
+        const int64_t quads = (total + 3) / 4;
+        const uint32_t blocks = (uint32_t)((quads + 255) / 256);
+        prof_begin(K_QUANT_BF16, s);
+        hipLaunchKernelGGL(k_quant_bf16, dim3(blocks), dim3(256), 0, s, (const float*)t.data,
+                           (uint16_t*)codes, total);
+        prof_end(K_QUANT_BF16, s);
+        return hipGetLastError();
+    }
+    const uint32_t blocks = (uint32_t)((nb + 3) / 4);
+    prof_begin(K_QUANT_FP8, s);
+    if (elems % 256 == 0)
+        hipLaunchKernelGGL(k_quant_fp8<true>, dim3(blocks), dim3(256), 0, s,
+                           (const float*)t.data, (uint8_t*)codes, scales, nb, elems);
+    else
+        hipLaunchKernelGGL(k_quant_fp8<false>, dim3(blocks), dim3(256), 0, s,
+                           (const float*)t.data, (uint8_t*)codes, scales, nb, elems);
+    prof_end(K_QUANT_FP8, s);
+    return hipGetLastError();
+}
+
+// Atlas [H*n][W*n][C] -> bucket-major [H][W][n][n][C]; one lane per texel,
+// elements of `eb` bytes (4, 2 or 1).
+template <typename E>
+__global__ __launch_bounds__(256) void k_atlas_to_buckets(const E* __restrict__ src,
+                                                          E* __restrict__ dst, int W, int H,
+                                                          int n, int C) {
+    const int64_t texel = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t total = (int64_t)W * H * n * n;
+    if (texel >= total) return;
+    const int x = (int)(texel % n);
+    const int y = (int)((texel / n) % n);
+    const int64_t b = texel / ((int64_t)n * n);
+    const int i = (int)(b % W), j = (int)(b / W);
+    const int64_t row = (int64_t)j * n + y, col = (int64_t)i * n + x;
+    const int64_t s = (row * ((int64_t)W * n) + col) * C;
+    for (int c = 0; c < C; c++) dst[texel * C + c] = src[s + c];
+}
+
+hipError_t launch_atlas_to_buckets(const void* atlas, void* dst, int W, int H, int n, int C,
+                                   int elem_bytes, hipStream_t s) {
+    const int64_t total = (int64_t)W * H * n * n;
+    const uint32_t blocks = (uint32_t)((total + 255) / 256);
+    prof_begin(K_ATLAS_RELAYOUT, s);
+    if (elem_bytes == 4)
+        hipLaunchKernelGGL(k_atlas_to_buckets<uint32_t>, dim3(blocks), dim3(256), 0, s,
+                           (const uint32_t*)atlas, (uint32_t*)dst, W, H, n, C);
+    else if (elem_bytes == 2)
+        hipLaunchKernelGGL(k_atlas_to_buckets<uint16_t>, dim3(blocks), dim3(256), 0, s,
+                           (const uint16_t*)atlas, (uint16_t*)dst, W, H, n, C);
+    else
+        hipLaunchKernelGGL(k_atlas_to_buckets<uint8_t>, dim3(blocks), dim3(256), 0, s,
+                           (const uint8_t*)atlas, (uint8_t*)dst, W, H, n, C);
+    prof_end(K_ATLAS_RELAYOUT, s);
+    return hipGetLastError();
+}
+
+}  // namespace rt

