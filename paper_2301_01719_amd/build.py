@@ -16,17 +16,18 @@ SOURCES = ["rt_abi.cpp", "rt_lookup.hip", "rt_quantize.hip", "rt_backward.hip"]
 ARCH = os.environ.get("RADTEX_ARCH", "gfx950")
 
 
-def build(verbose: bool = False, jobs: int = 4) -> str:
-    objdir = os.path.join(HERE, "_build")
+def build(verbose: bool = False, jobs: int = 4, csrc: str = CSRC, lib: str = LIB) -> str:
+    """Compile the sources in `csrc` into the shared library `lib`."""
+    objdir = os.path.join(os.path.dirname(lib), "_build")
     os.makedirs(objdir, exist_ok=True)
     common = ["hipcc", "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
               "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
               "-fno-gpu-rdc", "-Wall", "-Wno-unused-result",
-              "-I", os.path.join(ROOT, "include"), "-I", CSRC]
+              "-I", os.path.join(ROOT, "include"), "-I", csrc]
     procs, objs = [], []
     for src in SOURCES:
         obj = os.path.join(objdir, src.rsplit(".", 1)[0] + ".o")
-        cmd = common + ["-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
+        cmd = common + ["-x", "hip", "-c", os.path.join(csrc, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append(subprocess.Popen(cmd))
@@ -37,14 +38,18 @@ def build(verbose: bool = False, jobs: int = 4) -> str:
     for p in procs:
         if p.wait() != 0:
             raise RuntimeError("hipcc failed")
-    link = ["hipcc", "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", LIB + ".tmp"] + objs
+    link = ["hipcc", "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", lib + ".tmp"] + objs
     if verbose:
         print(" ".join(link), flush=True)
     subprocess.run(link, check=True)
-    os.replace(LIB + ".tmp", LIB)
-    return LIB
+    os.replace(lib + ".tmp", lib)
+    return lib
 
 
 if __name__ == "__main__":
-    build(verbose=True)
+    # optional: python build.py <csrc dir> <output library>
+    if len(sys.argv) == 3:
+        build(verbose=False, csrc=os.path.abspath(sys.argv[1]), lib=os.path.abspath(sys.argv[2]))
+    else:
+        build(verbose=True)
     sys.exit(0)

@@ -125,7 +125,7 @@ const char* kernel_name(int id) {
         "k_lookup_fwd",   "k_debug_indices", "k_quant_bf16",    "k_quant_fp8",
         "k_atlas_to_buckets", "k_bwd_fragment", "k_fill_u32",   "k_radix_hist",
         "k_scan",         "k_radix_scatter", "k_bucket_ranges", "k_segacc",
-        "k_segacc_hot",   "k_combine_hot"};
+        "k_segacc_hot",   "k_combine_hot",   "k_segacc_big"};
     return (id >= 0 && id < K_COUNT) ? names[id] : "";
 }
 

@@ -374,17 +374,113 @@ __device__ __forceinline__ void wave_sync_lds() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// The four tap contributions of sorted record i: v = (w00, w01, w10, w11) x g
+// times the bucket weight (1 in nearest mode); returns the record's cell.
+template <int C, int MODE>
+__device__ __forceinline__ int load_record(const uint32_t* __restrict__ skeys,
+                                           const uint32_t* __restrict__ svals,
+                                           const float* __restrict__ wrec,
+                                           const float* __restrict__ grad_out, int64_t i,
+                                           uint32_t cell_mask, float v[4 * C]) {
+    const uint32_t key = skeys[i];
+    const uint32_t rec = svals[i];
+    float fx, fy, wb = 1.f;
+    int64_t frag;
+    if constexpr (MODE == MODE_NEAREST) {
+        frag = rec;
+        float2 w2 = ((const float2*)wrec)[frag];
+        fx = w2.x;
+        fy = w2.y;
+    } else {
+        frag = rec >> 2;
+        const int k = rec & 3;
+        float4 w4 = ((const float4*)wrec)[frag];
+        fx = w4.x;
+        fy = w4.y;
+        const float aa = w4.z, bb = w4.w;
+        wb = (k == 0) ? (1.f - aa) * (1.f - bb)
+                      : (k == 1) ? aa * (1.f - bb) : (k == 2) ? (1.f - aa) * bb : aa * bb;
+    }
+    const float w00 = (1.f - fx) * (1.f - fy), w01 = fx * (1.f - fy);
+    const float w10 = (1.f - fx) * fy, w11 = fx * fy;
+#pragma unroll
+    for (int c = 0; c < C; c++) {
+        const float gc = grad_out[frag * C + c] * wb;
+        v[0 * C + c] = w00 * gc;
+        v[1 * C + c] = w01 * gc;
+        v[2 * C + c] = w10 * gc;
+        v[3 * C + c] = w11 * gc;
+    }
+    return (int)(key & cell_mask);
+}
+
+// One round of up to 64 sorted records of one bucket, one record per lane
+// (lanes without a record carry a cell no record has).  The four tap
+// contributions are summed per cell by an inclusive segmented scan across
+// lanes with a fixed shape.  `ends_here` tells whether a lane's cell ends in
+// this round; a cell that ends adds its four sums to its four texels in four
+// phases, so no two lanes touch one texel at once.
+template <int C>
+__device__ __forceinline__ void accumulate_round(int cell, float v[4 * C], bool valid,
+                                                 bool next_same, int n, float* tile) {
+    const int lane = threadIdx.x & 63;
+    constexpr int F = 4 * C;
+    const int prev_cell = __shfl_up(cell, 1, 64);
+    const bool joins_prev = lane > 0 && prev_cell == cell;
+    if (__ballot(joins_prev) != 0ull) {
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int oc = __shfl_up(cell, o, 64);
+            const bool same = lane >= o && oc == cell;
+#pragma unroll
+            for (int q = 0; q < F; q++) {
+                const float ov = __shfl_up(v[q], o, 64);
+                if (same) v[q] += ov;
+            }
+        }
+    }
+    const bool tail = valid && !next_same;
+    if (__ballot(tail) == 0ull) return;
+    int y0 = 0, x0 = 0, x1 = 0, y1 = 0;
+    if (tail) {
+        y0 = cell / n;
+        x0 = cell - y0 * n;
+        x1 = min(x0 + 1, n - 1);
+        y1 = min(y0 + 1, n - 1);
+    }
+    wave_sync_lds();
+    if (tail) {
+#pragma unroll
+        for (int c = 0; c < C; c++) tile[(y0 * n + x0) * C + c] += v[0 * C + c];
+    }
+    wave_sync_lds();
+    if (tail) {
+#pragma unroll
+        for (int c = 0; c < C; c++) tile[(y0 * n + x1) * C + c] += v[1 * C + c];
+    }
+    wave_sync_lds();
+    if (tail) {
+#pragma unroll
+        for (int c = 0; c < C; c++) tile[(y1 * n + x0) * C + c] += v[2 * C + c];
+    }
+    wave_sync_lds();
+    if (tail) {
+#pragma unroll
+        for (int c = 0; c < C; c++) tile[(y1 * n + x1) * C + c] += v[3 * C + c];
+    }
+    wave_sync_lds();
+}
+
 // Reduce sorted records [a, e) (all of one bucket) into the wave's LDS tile
-// (n*n*C floats, zeroed by the caller).  Rounds of 64 records; inside a round
-// the four tap contributions are summed per cell by an inclusive segmented
-// scan with a fixed shape; a cell that runs past the round carries its sum
-// into the next round's first lane.  A completed cell adds its four sums to
-// its four texels in four phases, so no two lanes touch one texel at once.
+// (zeroed by the caller), in rounds of 64 records.  A cell that runs past a
+// round carries its partial sum into the next round's first lane.
 template <int C, int MODE>
 __device__ __forceinline__ void reduce_records(const uint32_t* __restrict__ skeys,
-                               const uint32_t* __restrict__ svals,
-                               const float* __restrict__ wrec, const float* __restrict__ grad_out,
-                               int64_t a, int64_t e, int n, uint32_t cell_mask, float* tile) {
+                                               const uint32_t* __restrict__ svals,
+                                               const float* __restrict__ wrec,
+                                               const float* __restrict__ grad_out, int64_t a,
+                                               int64_t e, int n, uint32_t cell_mask,
+                                               float* tile) {
     const int lane = threadIdx.x & 63;
     constexpr int F = 4 * C;
     float carry[F];
@@ -398,156 +494,189 @@ __device__ __forceinline__ void reduce_records(const uint32_t* __restrict__ skey
         float v[F];
 #pragma unroll
         for (int q = 0; q < F; q++) v[q] = 0.f;
-        if (valid) {
-            const uint32_t key = skeys[i];
-            const uint32_t rec = svals[i];
-            cell = (int)(key & cell_mask);
-            float fx, fy, wb = 1.f;
-            int64_t frag;
-            if constexpr (MODE == MODE_NEAREST) {
-                frag = rec;
-                float2 w2 = ((const float2*)wrec)[frag];
-                fx = w2.x;
-                fy = w2.y;
-            } else {
-                frag = rec >> 2;
-                const int k = rec & 3;
-                float4 w4 = ((const float4*)wrec)[frag];
-                fx = w4.x;
-                fy = w4.y;
-                const float aa = w4.z, bb = w4.w;
-                wb = (k == 0) ? (1.f - aa) * (1.f - bb)
-                              : (k == 1) ? aa * (1.f - bb) : (k == 2) ? (1.f - aa) * bb : aa * bb;
-            }
-            const float w00 = (1.f - fx) * (1.f - fy), w01 = fx * (1.f - fy);
-            const float w10 = (1.f - fx) * fy, w11 = fx * fy;
-#pragma unroll
-            for (int c = 0; c < C; c++) {
-                const float gc = grad_out[frag * C + c] * wb;
-                v[0 * C + c] = w00 * gc;
-                v[1 * C + c] = w01 * gc;
-                v[2 * C + c] = w10 * gc;
-                v[3 * C + c] = w11 * gc;
-            }
-        }
+        if (valid) cell = load_record<C, MODE>(skeys, svals, wrec, grad_out, i, cell_mask, v);
         if (lane == 0 && cell == carry_cell) {
 #pragma unroll
             for (int q = 0; q < F; q++) v[q] = carry[q] + v[q];
         }
-        const int prev_cell = __shfl_up(cell, 1, 64);
-        const bool joins_prev = lane > 0 && prev_cell == cell;
-        if (__ballot(joins_prev) != 0ull) {
-#pragma unroll
-            for (int o = 1; o < 64; o <<= 1) {
-                const int oc = __shfl_up(cell, o, 64);
-                const bool same = lane >= o && oc == cell;
-#pragma unroll
-                for (int q = 0; q < F; q++) {
-                    const float ov = __shfl_up(v[q], o, 64);
-                    if (same) v[q] += ov;
-                }
-            }
-        }
         const int next_cell = __shfl_down(cell, 1, 64);
-        bool continues = valid && lane < 63 && i + 1 < e && next_cell == cell;
+        bool next_same = valid && lane < 63 && i + 1 < e && next_cell == cell;
         bool spills = false;
         if (valid && lane == 63 && i + 1 < e) spills = (int)(skeys[i + 1] & cell_mask) == cell;
-        const bool tail = valid && !continues && !spills;
-        // carry the sum of a cell that runs into the next round
-        const uint64_t spill_mask = __ballot(spills);
-        if (spill_mask) {
+        // the scan runs before the carry is taken from lane 63
+        accumulate_round<C>(cell, v, valid, next_same || spills, n, tile);
+        if (__ballot(spills) != 0ull) {
 #pragma unroll
             for (int q = 0; q < F; q++) carry[q] = __shfl(v[q], 63, 64);
             carry_cell = __shfl(cell, 63, 64);
         } else {
             carry_cell = -1;
         }
-        const uint64_t tails = __ballot(tail);
-        if (tails) {
-            int y0 = 0, x0 = 0, x1 = 0, y1 = 0;
-            if (tail) {
-                y0 = cell / n;
-                x0 = cell - y0 * n;
-                x1 = min(x0 + 1, n - 1);
-                y1 = min(y0 + 1, n - 1);
-            }
-            wave_sync_lds();
-            if (tail) {
-#pragma unroll
-                for (int c = 0; c < C; c++) tile[(y0 * n + x0) * C + c] += v[0 * C + c];
-            }
-            wave_sync_lds();
-            if (tail) {
-#pragma unroll
-                for (int c = 0; c < C; c++) tile[(y0 * n + x1) * C + c] += v[1 * C + c];
-            }
-            wave_sync_lds();
-            if (tail) {
-#pragma unroll
-                for (int c = 0; c < C; c++) tile[(y1 * n + x0) * C + c] += v[2 * C + c];
-            }
-            wave_sync_lds();
-            if (tail) {
-#pragma unroll
-                for (int c = 0; c < C; c++) tile[(y1 * n + x1) * C + c] += v[3 * C + c];
-            }
-            wave_sync_lds();
-        }
     }
+}
+
+// A window of up to 64 consecutive sorted records held in registers, one per
+// lane (cell, bilinear fractions, bucket weight and upstream gradient), so that
+// the small buckets of a group are served without further global loads.
+template <int C>
+struct RecWindow {
+    int64_t start, end;  // records [start, end) are held; lane l holds start + l
+    int cell;
+    float fx, fy, wb;
+    float g[C];
+};
+
+template <int C, int MODE>
+__device__ __forceinline__ void load_window(const uint32_t* __restrict__ skeys,
+                                            const uint32_t* __restrict__ svals,
+                                            const float* __restrict__ wrec,
+                                            const float* __restrict__ grad_out, int64_t start,
+                                            int64_t R, uint32_t cell_mask, RecWindow<C>& w) {
+    const int lane = threadIdx.x & 63;
+    w.start = start;
+    w.end = (start + 64 < R) ? start + 64 : R;
+    w.cell = -2 - lane;
+    w.fx = w.fy = 0.f;
+    w.wb = 1.f;
+#pragma unroll
+    for (int c = 0; c < C; c++) w.g[c] = 0.f;
+    const int64_t i = start + lane;
+    if (i < w.end) {
+        const uint32_t rec = svals[i];
+        w.cell = (int)(skeys[i] & cell_mask);
+        int64_t frag;
+        if constexpr (MODE == MODE_NEAREST) {
+            frag = rec;
+            const float2 w2 = ((const float2*)wrec)[frag];
+            w.fx = w2.x;
+            w.fy = w2.y;
+        } else {
+            frag = rec >> 2;
+            const int k = rec & 3;
+            const float4 w4 = ((const float4*)wrec)[frag];
+            w.fx = w4.x;
+            w.fy = w4.y;
+            const float aa = w4.z, bb = w4.w;
+            w.wb = (k == 0) ? (1.f - aa) * (1.f - bb)
+                            : (k == 1) ? aa * (1.f - bb) : (k == 2) ? (1.f - aa) * bb : aa * bb;
+        }
+#pragma unroll
+        for (int c = 0; c < C; c++) w.g[c] = grad_out[frag * C + c];
+    }
+}
+
+// Reduce the records [a, e) of one bucket, all inside the window.  The tap
+// contributions are formed exactly as load_record forms them.
+template <int C>
+__device__ __forceinline__ void reduce_window(const RecWindow<C>& w, int64_t a, int64_t e, int n,
+                                              float* tile) {
+    const int lane = threadIdx.x & 63;
+    const int64_t i = w.start + lane;
+    const bool valid = i >= a && i < e;
+    const int cell = valid ? w.cell : -2 - lane;
+    float v[4 * C];
+    const float w00 = (1.f - w.fx) * (1.f - w.fy), w01 = w.fx * (1.f - w.fy);
+    const float w10 = (1.f - w.fx) * w.fy, w11 = w.fx * w.fy;
+#pragma unroll
+    for (int c = 0; c < C; c++) {
+        const float gc = valid ? w.g[c] * w.wb : 0.f;
+        v[0 * C + c] = w00 * gc;
+        v[1 * C + c] = w01 * gc;
+        v[2 * C + c] = w10 * gc;
+        v[3 * C + c] = w11 * gc;
+    }
+    const int next_cell = __shfl_down(cell, 1, 64);
+    const bool next_same = valid && lane < 63 && i + 1 < e && next_cell == cell;
+    accumulate_round<C>(cell, v, valid, next_same, n, tile);
 }
 
 __device__ __forceinline__ void tile_zero(float* tile, int te) {
     const int lane = threadIdx.x & 63;
-    for (int q = lane; q < te; q += 64) tile[q] = 0.f;
+    if ((te & 3) == 0) {
+        const f4v z = {0.f, 0.f, 0.f, 0.f};
+        for (int q = lane; q < te / 4; q += 64) ((f4v*)tile)[q] = z;
+    } else {
+        for (int q = lane; q < te; q += 64) tile[q] = 0.f;
+    }
     wave_sync_lds();
 }
 
+// The dense gradient is written once and not read back by this library, so
+// its stores are non-temporal (streamed past the caches).
 __device__ __forceinline__ void tile_store(const float* tile, float* __restrict__ dst, int te) {
     const int lane = threadIdx.x & 63;
     wave_sync_lds();
     if ((te & 255) == 0) {
-        for (int q = lane; q < te / 4; q += 64) ((float4*)dst)[q] = ((const float4*)tile)[q];
+        for (int q = lane; q < te / 4; q += 64)
+            __builtin_nontemporal_store(((const f4v*)tile)[q], (f4v*)dst + q);
     } else {
-        for (int q = lane; q < te; q += 64) dst[q] = tile[q];
+        for (int q = lane; q < te; q += 64) __builtin_nontemporal_store(tile[q], dst + q);
     }
+    wave_sync_lds();
 }
 
 __device__ __forceinline__ void zero_store(float* __restrict__ dst, int te) {
     const int lane = threadIdx.x & 63;
     if ((te & 255) == 0) {
-        const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
-        for (int q = lane; q < te / 4; q += 64) ((float4*)dst)[q] = z;
+        const f4v z = {0.f, 0.f, 0.f, 0.f};
+        for (int q = lane; q < te / 4; q += 64) __builtin_nontemporal_store(z, (f4v*)dst + q);
     } else {
-        for (int q = lane; q < te; q += 64) dst[q] = 0.f;
+        for (int q = lane; q < te; q += 64) __builtin_nontemporal_store(0.f, dst + q);
     }
 }
 
-// pass 1: one wavefront per bucket, four buckets per workgroup
-template <int C, int MODE>
+// pass 1: each wavefront owns SEG_GROUP consecutive buckets (their ranges come
+// in one coalesced load) and writes their tiles one after the other, so the
+// stores of untouched buckets are issued back to back; four wavefronts per
+// workgroup.  The launch with BIG = false writes the untouched buckets and
+// those with at most 64 records (served from one register window); the launch
+// with BIG = true those with 65..PIECE records (rounds of 64 with a carry).
+// Splitting keeps the register footprint of the common case small.
+constexpr int SEG_GROUP = 8;
+
+template <int C, int MODE, bool BIG>
 __global__ __launch_bounds__(256) void k_segacc(const uint32_t* __restrict__ skeys,
                                                 const uint32_t* __restrict__ svals,
                                                 const float* __restrict__ wrec,
                                                 const float* __restrict__ grad_out,
                                                 const int2* __restrict__ range,
                                                 float* __restrict__ grad_tex, int64_t nbuckets,
-                                                int n, uint32_t cell_mask) {
+                                                int64_t R, int n, uint32_t cell_mask) {
     extern __shared__ float lds[];
     const int te = n * n * C;
-    const int w = threadIdx.x >> 6;
-    const int64_t b = (int64_t)xcd_block_id(blockIdx.x, gridDim.x) * 4 + w;
-    if (b >= nbuckets) return;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t b0 = ((int64_t)xcd_block_id(blockIdx.x, gridDim.x) * 4 + w) * SEG_GROUP;
+    if (b0 >= nbuckets) return;
     float* tile = lds + w * te;
-    float* dst = grad_tex + b * te;
-    const int2 r = range[b];
-    const int64_t cnt = (int64_t)r.y - r.x;
-    if (cnt <= 0) {
-        zero_store(dst, te);
-        return;
+    int2 rl = make_int2(0, 0);
+    if (lane < SEG_GROUP && b0 + lane < nbuckets) rl = range[b0 + lane];
+    const int nb = (int)((nbuckets - b0) < SEG_GROUP ? (nbuckets - b0) : SEG_GROUP);
+    RecWindow<C> win;
+    win.start = win.end = -1;
+    for (int k = 0; k < nb; k++) {
+        // wave-uniform bucket range (scalar registers, scalar loop control)
+        const int rx = __builtin_amdgcn_readfirstlane(__shfl(rl.x, k, 64));
+        const int ry = __builtin_amdgcn_readfirstlane(__shfl(rl.y, k, 64));
+        float* dst = grad_tex + (b0 + k) * te;
+        const int cnt = ry - rx;
+        if constexpr (BIG) {
+            if (cnt <= 64 || cnt > PIECE) continue;
+            tile_zero(tile, te);
+            reduce_records<C, MODE>(skeys, svals, wrec, grad_out, rx, ry, n, cell_mask, tile);
+            tile_store(tile, dst, te);
+        } else {
+            if (cnt <= 0) {
+                zero_store(dst, te);
+                continue;
+            }
+            if (cnt > 64) continue;  // BIG launch, or pass 2 when hot
+            if (!(rx >= win.start && ry <= win.end))
+                load_window<C, MODE>(skeys, svals, wrec, grad_out, rx, R, cell_mask, win);
+            tile_zero(tile, te);
+            reduce_window<C>(win, rx, ry, n, tile);
+            tile_store(tile, dst, te);
+        }
     }
-    if (cnt > PIECE) return;  // hot bucket: pass 2
-    tile_zero(tile, te);
-    reduce_records<C, MODE>(skeys, svals, wrec, grad_out, r.x, r.y, n, cell_mask, tile);
-    tile_store(tile, dst, te);
 }
 
 // pass 2a: one wavefront per fixed chunk of PIECE sorted records; a hot bucket
@@ -688,15 +817,16 @@ static void launch_bwd_fragment_c(const TexView& t, const float* uv, const float
     }
 }
 
-template <int MODE>
+template <int MODE, bool BIG>
 static void launch_segacc_c(int C, dim3 grid, size_t shm, hipStream_t s, const uint32_t* sk,
                             const uint32_t* sv, const float* wrec, const float* go,
-                            const int2* range, float* gt, int64_t nb, int n, uint32_t mask) {
+                            const int2* range, float* gt, int64_t nb, int64_t R, int n,
+                            uint32_t mask) {
     switch (C) {
-    case 1: hipLaunchKernelGGL((k_segacc<1, MODE>), grid, dim3(256), shm, s, sk, sv, wrec, go, range, gt, nb, n, mask); break;
-    case 2: hipLaunchKernelGGL((k_segacc<2, MODE>), grid, dim3(256), shm, s, sk, sv, wrec, go, range, gt, nb, n, mask); break;
-    case 3: hipLaunchKernelGGL((k_segacc<3, MODE>), grid, dim3(256), shm, s, sk, sv, wrec, go, range, gt, nb, n, mask); break;
-    default: hipLaunchKernelGGL((k_segacc<4, MODE>), grid, dim3(256), shm, s, sk, sv, wrec, go, range, gt, nb, n, mask); break;
+    case 1: hipLaunchKernelGGL((k_segacc<1, MODE, BIG>), grid, dim3(256), shm, s, sk, sv, wrec, go, range, gt, nb, R, n, mask); break;
+    case 2: hipLaunchKernelGGL((k_segacc<2, MODE, BIG>), grid, dim3(256), shm, s, sk, sv, wrec, go, range, gt, nb, R, n, mask); break;
+    case 3: hipLaunchKernelGGL((k_segacc<3, MODE, BIG>), grid, dim3(256), shm, s, sk, sv, wrec, go, range, gt, nb, R, n, mask); break;
+    default: hipLaunchKernelGGL((k_segacc<4, MODE, BIG>), grid, dim3(256), shm, s, sk, sv, wrec, go, range, gt, nb, R, n, mask); break;
     }
 }
 
@@ -805,12 +935,20 @@ hipError_t launch_backward(const TexView& t, int fmt, int mode, const float* uv,
     const int te = (int)plan.tile_elems;
     const uint32_t cell_mask = plan.cell_bits >= 32 ? 0xFFFFFFFFu : ((1u << plan.cell_bits) - 1u);
     prof_begin(K_SEGACC, s);
-    const dim3 g1((uint32_t)((nb + 3) / 4));
+    const dim3 g1((uint32_t)((nb + 4 * SEG_GROUP - 1) / (4 * SEG_GROUP)));
     if (mode == MODE_NEAREST)
-        launch_segacc_c<MODE_NEAREST>(t.C, g1, (size_t)4 * te * 4, s, skeys, svals, wrec, grad_out, range, grad_tex, nb, t.n, cell_mask);
+        launch_segacc_c<MODE_NEAREST, false>(t.C, g1, (size_t)4 * te * 4, s, skeys, svals, wrec, grad_out, range, grad_tex, nb, R, t.n, cell_mask);
     else
-        launch_segacc_c<MODE_BILINEAR>(t.C, g1, (size_t)4 * te * 4, s, skeys, svals, wrec, grad_out, range, grad_tex, nb, t.n, cell_mask);
+        launch_segacc_c<MODE_BILINEAR, false>(t.C, g1, (size_t)4 * te * 4, s, skeys, svals, wrec, grad_out, range, grad_tex, nb, R, t.n, cell_mask);
     prof_end(K_SEGACC, s);
+    if (R > 64) {
+        prof_begin(K_SEGACC_BIG, s);
+        if (mode == MODE_NEAREST)
+            launch_segacc_c<MODE_NEAREST, true>(t.C, g1, (size_t)4 * te * 4, s, skeys, svals, wrec, grad_out, range, grad_tex, nb, R, t.n, cell_mask);
+        else
+            launch_segacc_c<MODE_BILINEAR, true>(t.C, g1, (size_t)4 * te * 4, s, skeys, svals, wrec, grad_out, range, grad_tex, nb, R, t.n, cell_mask);
+        prof_end(K_SEGACC_BIG, s);
+    }
 
     // 5. pass 2 for buckets with more than PIECE records
     if (R > PIECE) {

@@ -15,6 +15,10 @@ constexpr int FMT_FP8 = 2;
 constexpr int MODE_NEAREST = 0;
 constexpr int MODE_BILINEAR = 1;
 
+// Native vector types (for non-temporal loads and stores).
+typedef float f4v __attribute__((ext_vector_type(4)));
+typedef uint32_t u2v __attribute__((ext_vector_type(2)));
+
 // Texture as seen by a kernel: bucket-major [H][W][n][n][C].
 struct TexView {
     const void* data;

@@ -26,6 +26,7 @@ enum KernelId {
     K_SEGACC,
     K_SEGACC_HOT,
     K_COMBINE_HOT,
+    K_SEGACC_BIG,
     K_COUNT
 };
 const char* kernel_name(int id);

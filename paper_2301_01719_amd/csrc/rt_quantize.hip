@@ -36,18 +36,34 @@ __device__ __forceinline__ uint32_t f32_to_e4m3_bits(float y) {
     return sign | ((r >> 20) - (120u << 3));
 }
 
+// Elementwise: each thread converts QB_UNROLL float4 (loads issued together),
+// streamed with non-temporal loads and stores.
+constexpr int QB_UNROLL = 4;
+
 __global__ __launch_bounds__(256) void k_quant_bf16(const float* __restrict__ src,
                                                     uint16_t* __restrict__ dst, int64_t total) {
-    const int64_t q = ((int64_t)xcd_block_id(blockIdx.x, gridDim.x) * 256 + threadIdx.x);
-    const int64_t e = q * 4;
-    if (e + 3 < total) {
-        float4 v = ((const float4*)src)[q];
-        uint2 o;
-        o.x = f32_to_bf16_bits(v.x) | (f32_to_bf16_bits(v.y) << 16);
-        o.y = f32_to_bf16_bits(v.z) | (f32_to_bf16_bits(v.w) << 16);
-        ((uint2*)dst)[q] = o;
-    } else {
-        for (int64_t k = e; k < total; k++) dst[k] = (uint16_t)f32_to_bf16_bits(src[k]);
+    const int64_t quads = total / 4;
+    const int64_t base =
+        (int64_t)xcd_block_id(blockIdx.x, gridDim.x) * (256 * QB_UNROLL) + threadIdx.x;
+    f4v v[QB_UNROLL];
+#pragma unroll
+    for (int k = 0; k < QB_UNROLL; k++) {
+        const int64_t q = base + k * 256;
+        if (q < quads) v[k] = __builtin_nontemporal_load((const f4v*)src + q);
+    }
+#pragma unroll
+    for (int k = 0; k < QB_UNROLL; k++) {
+        const int64_t q = base + k * 256;
+        if (q < quads) {
+            u2v o;
+            o.x = f32_to_bf16_bits(v[k].x) | (f32_to_bf16_bits(v[k].y) << 16);
+            o.y = f32_to_bf16_bits(v[k].z) | (f32_to_bf16_bits(v[k].w) << 16);
+            __builtin_nontemporal_store(o, (u2v*)dst + q);
+        }
+    }
+    if (blockIdx.x == 0 && threadIdx.x < (total & 3)) {
+        const int64_t e = quads * 4 + threadIdx.x;
+        dst[e] = (uint16_t)f32_to_bf16_bits(src[e]);
     }
 }
 
@@ -78,7 +94,8 @@ __global__ __launch_bounds__(256) void k_quant_fp8(const float* __restrict__ src
 #pragma unroll
         for (int k = 0; k < 4; k++) {
             if (k < per_lane) {
-                cache[k] = ((const float4*)s)[k * 64 + lane];
+                const f4v t = __builtin_nontemporal_load((const f4v*)s + k * 64 + lane);
+                cache[k] = make_float4(t.x, t.y, t.z, t.w);
                 amax = fmaxf(amax, fmaxf(fmaxf(fabsf(cache[k].x), fabsf(cache[k].y)),
                                          fmaxf(fabsf(cache[k].z), fabsf(cache[k].w))));
             }
@@ -99,7 +116,7 @@ __global__ __launch_bounds__(256) void k_quant_fp8(const float* __restrict__ src
                 float4 v = cache[k];
                 uint32_t w = f32_to_e4m3_bits(v.x * inv) | (f32_to_e4m3_bits(v.y * inv) << 8) |
                              (f32_to_e4m3_bits(v.z * inv) << 16) | (f32_to_e4m3_bits(v.w * inv) << 24);
-                ((uint32_t*)d)[k * 64 + lane] = w;
+                __builtin_nontemporal_store(w, (uint32_t*)d + k * 64 + lane);
             }
         }
         for (int k = 4; k < per_lane; k++) {
@@ -128,8 +145,9 @@ hipError_t launch_quantize(const TexView& t, int dst_fmt, void* codes, float* sc
     const int elems = t.n * t.n * t.C;
     if (dst_fmt == FMT_BF16) {
         const int64_t total = nb * elems;
-        const int64_t quads = (total + 3) / 4;
-        const uint32_t blocks = (uint32_t)((quads + 255) / 256);
+        const int64_t quads = total / 4;
+        const uint32_t blocks =
+            (uint32_t)((quads + 256 * QB_UNROLL - 1) / (256 * QB_UNROLL)) + (quads == 0 ? 1 : 0);
         prof_begin(K_QUANT_BF16, s);
         hipLaunchKernelGGL(k_quant_bf16, dim3(blocks), dim3(256), 0, s, (const float*)t.data,
                            (uint16_t*)codes, total);

@@ -14,7 +14,9 @@ from typing import Optional
 import torch
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libradtex.so")
+# RADTEX_LIBRARY selects another build of the same library (for comparing
+# kernel variants); by default the in-tree build is loaded.
+LIB_PATH = os.environ.get("RADTEX_LIBRARY", os.path.join(HERE, "libradtex.so"))
 
 RT_OK = 0
 RT_FMT_F32, RT_FMT_BF16, RT_FMT_FP8_E4M3 = 0, 1, 2
