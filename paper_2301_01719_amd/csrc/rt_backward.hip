@@ -25,6 +25,8 @@
 //                       in chunk order.
 // No float atomics are used, and every summation order is a function of the
 // sorted records alone, so the gradient is bitwise reproducible.
+#include <algorithm>
+
 #include "rt_device.hpp"
 #include "rt_kernels.hpp"
 
@@ -628,54 +630,86 @@ __device__ __forceinline__ void zero_store(float* __restrict__ dst, int te) {
 // pass 1: each wavefront owns SEG_GROUP consecutive buckets (their ranges come
 // in one coalesced load) and writes their tiles one after the other, so the
 // stores of untouched buckets are issued back to back; four wavefronts per
-// workgroup.  The launch with BIG = false writes the untouched buckets and
-// those with at most 64 records (served from one register window); the launch
-// with BIG = true those with 65..PIECE records (rounds of 64 with a carry).
-// Splitting keeps the register footprint of the common case small.
+// workgroup.  k_segacc writes the untouched buckets and those with at most 64
+// records (served from one register window) and lists those with 65..PIECE
+// records for k_segacc_big (rounds of 64 with a carry).  Splitting keeps the
+// register footprint of the common case small.
 constexpr int SEG_GROUP = 8;
 
-template <int C, int MODE, bool BIG>
+template <int C, int MODE>
 __global__ __launch_bounds__(256) void k_segacc(const uint32_t* __restrict__ skeys,
                                                 const uint32_t* __restrict__ svals,
                                                 const float* __restrict__ wrec,
                                                 const float* __restrict__ grad_out,
                                                 const int2* __restrict__ range,
                                                 float* __restrict__ grad_tex, int64_t nbuckets,
-                                                int64_t R, int n, uint32_t cell_mask) {
+                                                int64_t R, int n, uint32_t cell_mask,
+                                                uint32_t* __restrict__ big_count,
+                                                uint32_t* __restrict__ big_list) {
     extern __shared__ float lds[];
     const int te = n * n * C;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int64_t b0 = ((int64_t)xcd_block_id(blockIdx.x, gridDim.x) * 4 + w) * SEG_GROUP;
-    if (b0 >= nbuckets) return;
     float* tile = lds + w * te;
-    int2 rl = make_int2(0, 0);
-    if (lane < SEG_GROUP && b0 + lane < nbuckets) rl = range[b0 + lane];
-    const int nb = (int)((nbuckets - b0) < SEG_GROUP ? (nbuckets - b0) : SEG_GROUP);
-    RecWindow<C> win;
-    win.start = win.end = -1;
-    for (int k = 0; k < nb; k++) {
-        // wave-uniform bucket range (scalar registers, scalar loop control)
-        const int rx = __builtin_amdgcn_readfirstlane(__shfl(rl.x, k, 64));
-        const int ry = __builtin_amdgcn_readfirstlane(__shfl(rl.y, k, 64));
-        float* dst = grad_tex + (b0 + k) * te;
-        const int cnt = ry - rx;
-        if constexpr (BIG) {
-            if (cnt <= 64 || cnt > PIECE) continue;
-            tile_zero(tile, te);
-            reduce_records<C, MODE>(skeys, svals, wrec, grad_out, rx, ry, n, cell_mask, tile);
-            tile_store(tile, dst, te);
-        } else {
+    const int64_t ngroups = (nbuckets + SEG_GROUP - 1) / SEG_GROUP;
+    // groups are visited grid-stride; the launch caps the grid
+    for (int64_t grp = (int64_t)xcd_block_id(blockIdx.x, gridDim.x) * 4 + w; grp < ngroups;
+         grp += (int64_t)gridDim.x * 4) {
+        const int64_t b0 = grp * SEG_GROUP;
+        int2 rl = make_int2(0, 0);
+        if (lane < SEG_GROUP && b0 + lane < nbuckets) rl = range[b0 + lane];
+        const int nb = (int)((nbuckets - b0) < SEG_GROUP ? (nbuckets - b0) : SEG_GROUP);
+        RecWindow<C> win;
+        win.start = win.end = -1;
+        for (int k = 0; k < nb; k++) {
+            // wave-uniform bucket range (scalar registers, scalar loop control)
+            const int rx = __builtin_amdgcn_readfirstlane(__shfl(rl.x, k, 64));
+            const int ry = __builtin_amdgcn_readfirstlane(__shfl(rl.y, k, 64));
+            float* dst = grad_tex + (b0 + k) * te;
+            const int cnt = ry - rx;
             if (cnt <= 0) {
                 zero_store(dst, te);
                 continue;
             }
-            if (cnt > 64) continue;  // BIG launch, or pass 2 when hot
+            if (cnt > 64) {
+                // left to k_segacc_big (65..PIECE records) or pass 2 (hot); the
+                // list's order does not matter, each bucket is reduced alone
+                if (cnt <= PIECE && lane == 0) big_list[atomicAdd(big_count, 1u)] = (uint32_t)(b0 + k);
+                continue;
+            }
             if (!(rx >= win.start && ry <= win.end))
                 load_window<C, MODE>(skeys, svals, wrec, grad_out, rx, R, cell_mask, win);
             tile_zero(tile, te);
             reduce_window<C>(win, rx, ry, n, tile);
             tile_store(tile, dst, te);
         }
+    }
+}
+
+// Buckets with 65..PIECE records, listed by k_segacc: one wavefront per listed
+// bucket (grid-stride), rounds of 64 records with a carry.
+template <int C, int MODE>
+__global__ __launch_bounds__(256) void k_segacc_big(const uint32_t* __restrict__ skeys,
+                                                    const uint32_t* __restrict__ svals,
+                                                    const float* __restrict__ wrec,
+                                                    const float* __restrict__ grad_out,
+                                                    const int2* __restrict__ range,
+                                                    float* __restrict__ grad_tex, int n,
+                                                    uint32_t cell_mask,
+                                                    const uint32_t* __restrict__ big_count,
+                                                    const uint32_t* __restrict__ big_list) {
+    extern __shared__ float lds[];
+    const int te = n * n * C;
+    const int w = threadIdx.x >> 6;
+    float* tile = lds + w * te;
+    const uint32_t count = *big_count;
+    for (uint32_t e = blockIdx.x * 4 + w; e < count; e += gridDim.x * 4) {
+        const uint32_t b = __builtin_amdgcn_readfirstlane(big_list[e]);
+        const int2 r = range[b];
+        const int rx = __builtin_amdgcn_readfirstlane(r.x);
+        const int ry = __builtin_amdgcn_readfirstlane(r.y);
+        tile_zero(tile, te);
+        reduce_records<C, MODE>(skeys, svals, wrec, grad_out, rx, ry, n, cell_mask, tile);
+        tile_store(tile, grad_tex + (int64_t)b * te, te);
     }
 }
 
@@ -797,7 +831,8 @@ bool plan_backward(int W, int H, int n, int C, int64_t N, int mode, BwdPlan* p) 
     p->off_hist = take((size_t)p->scan_len * 4);
     p->off_hoff = take((size_t)p->scan_len * 4);
     p->off_scanp = take((size_t)(p->scan_blocks + 1) * 4);
-    p->off_range = take((size_t)nb * 8);
+    p->off_range = take((size_t)nb * 8 + 4);
+    p->off_biglist = take((size_t)(R / 65 + 1) * 4);
     p->off_part = take((size_t)p->chunks * 2 * p->tile_elems * 4);
     p->total = o;
     return true;
@@ -817,16 +852,29 @@ static void launch_bwd_fragment_c(const TexView& t, const float* uv, const float
     }
 }
 
-template <int MODE, bool BIG>
+template <int MODE>
 static void launch_segacc_c(int C, dim3 grid, size_t shm, hipStream_t s, const uint32_t* sk,
                             const uint32_t* sv, const float* wrec, const float* go,
                             const int2* range, float* gt, int64_t nb, int64_t R, int n,
-                            uint32_t mask) {
+                            uint32_t mask, uint32_t* bc, uint32_t* bl) {
     switch (C) {
-    case 1: hipLaunchKernelGGL((k_segacc<1, MODE, BIG>), grid, dim3(256), shm, s, sk, sv, wrec, go, range, gt, nb, R, n, mask); break;
-    case 2: hipLaunchKernelGGL((k_segacc<2, MODE, BIG>), grid, dim3(256), shm, s, sk, sv, wrec, go, range, gt, nb, R, n, mask); break;
-    case 3: hipLaunchKernelGGL((k_segacc<3, MODE, BIG>), grid, dim3(256), shm, s, sk, sv, wrec, go, range, gt, nb, R, n, mask); break;
-    default: hipLaunchKernelGGL((k_segacc<4, MODE, BIG>), grid, dim3(256), shm, s, sk, sv, wrec, go, range, gt, nb, R, n, mask); break;
+    case 1: hipLaunchKernelGGL((k_segacc<1, MODE>), grid, dim3(256), shm, s, sk, sv, wrec, go, range, gt, nb, R, n, mask, bc, bl); break;
+    case 2: hipLaunchKernelGGL((k_segacc<2, MODE>), grid, dim3(256), shm, s, sk, sv, wrec, go, range, gt, nb, R, n, mask, bc, bl); break;
+    case 3: hipLaunchKernelGGL((k_segacc<3, MODE>), grid, dim3(256), shm, s, sk, sv, wrec, go, range, gt, nb, R, n, mask, bc, bl); break;
+    default: hipLaunchKernelGGL((k_segacc<4, MODE>), grid, dim3(256), shm, s, sk, sv, wrec, go, range, gt, nb, R, n, mask, bc, bl); break;
+    }
+}
+
+template <int MODE>
+static void launch_segacc_big_c(int C, dim3 grid, size_t shm, hipStream_t s, const uint32_t* sk,
+                                const uint32_t* sv, const float* wrec, const float* go,
+                                const int2* range, float* gt, int n, uint32_t mask,
+                                const uint32_t* bc, const uint32_t* bl) {
+    switch (C) {
+    case 1: hipLaunchKernelGGL((k_segacc_big<1, MODE>), grid, dim3(256), shm, s, sk, sv, wrec, go, range, gt, n, mask, bc, bl); break;
+    case 2: hipLaunchKernelGGL((k_segacc_big<2, MODE>), grid, dim3(256), shm, s, sk, sv, wrec, go, range, gt, n, mask, bc, bl); break;
+    case 3: hipLaunchKernelGGL((k_segacc_big<3, MODE>), grid, dim3(256), shm, s, sk, sv, wrec, go, range, gt, n, mask, bc, bl); break;
+    default: hipLaunchKernelGGL((k_segacc_big<4, MODE>), grid, dim3(256), shm, s, sk, sv, wrec, go, range, gt, n, mask, bc, bl); break;
     }
 }
 
@@ -872,6 +920,8 @@ hipError_t launch_backward(const TexView& t, int fmt, int mode, const float* uv,
     uint32_t* hoff = (uint32_t*)(wsb + plan.off_hoff);
     uint32_t* scanp = (uint32_t*)(wsb + plan.off_scanp);
     int2* range = (int2*)(wsb + plan.off_range);
+    uint32_t* big_count = (uint32_t*)(wsb + plan.off_range) + 2 * (int64_t)t.W * t.H;
+    uint32_t* big_list = (uint32_t*)(wsb + plan.off_biglist);
     float* part = (float*)(wsb + plan.off_part);
     const int64_t R = plan.records;
     const bool want_tex = grad_tex != nullptr;
@@ -923,7 +973,7 @@ hipError_t launch_backward(const TexView& t, int fmt, int mode, const float* uv,
 
     // 3. ranges
     const int64_t nb = (int64_t)t.W * t.H;
-    launch_fill((uint32_t*)range, nb * 2, 0u, s);
+    launch_fill((uint32_t*)range, nb * 2 + 1, 0u, s);  // ranges and the big-bucket count
     if (R > 0) {
         prof_begin(K_BUCKET_RANGES, s);
         hipLaunchKernelGGL(k_bucket_ranges, dim3((uint32_t)((R + 255) / 256)), dim3(256), 0, s,
@@ -935,18 +985,21 @@ hipError_t launch_backward(const TexView& t, int fmt, int mode, const float* uv,
     const int te = (int)plan.tile_elems;
     const uint32_t cell_mask = plan.cell_bits >= 32 ? 0xFFFFFFFFu : ((1u << plan.cell_bits) - 1u);
     prof_begin(K_SEGACC, s);
-    const dim3 g1((uint32_t)((nb + 4 * SEG_GROUP - 1) / (4 * SEG_GROUP)));
+    const int64_t groups = (nb + SEG_GROUP - 1) / SEG_GROUP;
+    const dim3 g1((uint32_t)((groups + 3) / 4));
+    prof_begin(K_SEGACC, s);
     if (mode == MODE_NEAREST)
-        launch_segacc_c<MODE_NEAREST, false>(t.C, g1, (size_t)4 * te * 4, s, skeys, svals, wrec, grad_out, range, grad_tex, nb, R, t.n, cell_mask);
+        launch_segacc_c<MODE_NEAREST>(t.C, g1, (size_t)4 * te * 4, s, skeys, svals, wrec, grad_out, range, grad_tex, nb, R, t.n, cell_mask, big_count, big_list);
     else
-        launch_segacc_c<MODE_BILINEAR, false>(t.C, g1, (size_t)4 * te * 4, s, skeys, svals, wrec, grad_out, range, grad_tex, nb, R, t.n, cell_mask);
+        launch_segacc_c<MODE_BILINEAR>(t.C, g1, (size_t)4 * te * 4, s, skeys, svals, wrec, grad_out, range, grad_tex, nb, R, t.n, cell_mask, big_count, big_list);
     prof_end(K_SEGACC, s);
     if (R > 64) {
+        const dim3 g2((uint32_t)std::min<int64_t>((R / 65 + 3) / 4 + 1, 1024));
         prof_begin(K_SEGACC_BIG, s);
         if (mode == MODE_NEAREST)
-            launch_segacc_c<MODE_NEAREST, true>(t.C, g1, (size_t)4 * te * 4, s, skeys, svals, wrec, grad_out, range, grad_tex, nb, R, t.n, cell_mask);
+            launch_segacc_big_c<MODE_NEAREST>(t.C, g2, (size_t)4 * te * 4, s, skeys, svals, wrec, grad_out, range, grad_tex, t.n, cell_mask, big_count, big_list);
         else
-            launch_segacc_c<MODE_BILINEAR, true>(t.C, g1, (size_t)4 * te * 4, s, skeys, svals, wrec, grad_out, range, grad_tex, nb, R, t.n, cell_mask);
+            launch_segacc_big_c<MODE_BILINEAR>(t.C, g2, (size_t)4 * te * 4, s, skeys, svals, wrec, grad_out, range, grad_tex, t.n, cell_mask, big_count, big_list);
         prof_end(K_SEGACC_BIG, s);
     }
 

@@ -57,7 +57,7 @@ struct BwdPlan {
     int64_t tile_elems;   // n*n*C
     // workspace offsets (bytes)
     size_t off_keys0, off_keys1, off_vals0, off_vals1, off_wrec, off_hist, off_hoff, off_scanp,
-        off_range, off_part, total;
+        off_range, off_biglist, off_part, total;
 };
 constexpr int PIECE = 2048;  // records per chunk; buckets with more are "hot"
 bool plan_backward(int W, int H, int n, int C, int64_t N, int mode, BwdPlan* p);

@@ -38,8 +38,9 @@ __device__ __forceinline__ uint32_t f32_to_e4m3_bits(float y) {
 
 // Elementwise: each thread converts QB_UNROLL float4 (loads issued together),
 // streamed with non-temporal loads and stores.
-constexpr int QB_UNROLL = 4;
+constexpr int QB_UNROLL = 2;
 
+template <int QB_UNROLL>
 __global__ __launch_bounds__(256) void k_quant_bf16(const float* __restrict__ src,
                                                     uint16_t* __restrict__ dst, int64_t total) {
     const int64_t quads = total / 4;
@@ -149,8 +150,8 @@ hipError_t launch_quantize(const TexView& t, int dst_fmt, void* codes, float* sc
         const uint32_t blocks =
             (uint32_t)((quads + 256 * QB_UNROLL - 1) / (256 * QB_UNROLL)) + (quads == 0 ? 1 : 0);
         prof_begin(K_QUANT_BF16, s);
-        hipLaunchKernelGGL(k_quant_bf16, dim3(blocks), dim3(256), 0, s, (const float*)t.data,
-                           (uint16_t*)codes, total);
+        hipLaunchKernelGGL(k_quant_bf16<QB_UNROLL>, dim3(blocks), dim3(256), 0, s,
+                           (const float*)t.data, (uint16_t*)codes, total);
         prof_end(K_QUANT_BF16, s);
         return hipGetLastError();
     }
