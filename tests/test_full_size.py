@@ -1,0 +1,248 @@
+"""Parity at the workloads' full sizes, in the launch configuration the
+benchmark times (the whole G-buffer in one launch), checked on sampled outputs
+the oracle computes one by one.
+
+* one 1920x1080 view over 1024x1024 buckets of 16x16 RGBA (the benchmark's
+  workload): FP32 / BF16 / FP8 forwards, the quantiser's codes on sampled
+  buckets, the backward's dense gradient on a bucket window and its view
+  gradients on sampled fragments;
+* 64 views of 1024x1024 over 512x512 buckets: indices and forwards on a sample;
+* 8 views of 3840x2160 over 2048x2048 buckets stored as FP8 with per-bucket
+  scales: forward and backward on samples, and the end-to-end error against
+  FP32 storage.
+
+Indices are compared only for fragments at least 1e-6 (normalised) from every
+cell edge that decides them.  For the dense gradient the upstream gradient of
+the fragments the oracle finds nearer than that is set to zero before the
+launch, so that neither side's choice of cell for them enters the comparison.
+The oracle's quantiser runs on the sampled buckets only (the codes of a bucket
+depend on that bucket's values alone).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from helpers import EDGE, check_fwd, check_grad_tex, check_grad_vec, host
+from paper_2301_01719_amd import workloads as wl
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def rt():
+    from paper_2301_01719_amd import radtex
+    return radtex
+
+
+def _sample(N, k, seed):
+    return np.sort(np.random.default_rng(seed).choice(N, size=min(k, N), replace=False))
+
+
+def _take(ts, sel):
+    st = torch.from_numpy(np.asarray(sel, np.int64)).to(DEV)
+    return tuple(host(t[st]) for t in ts)
+
+
+def _keep(edge):
+    return (edge[:, 0] >= EDGE) & (edge[:, 1] >= EDGE)
+
+
+def _oracle_codes(rows, W, H, n, C, buckets, fmt):
+    """Full-size code (and scale) arrays holding the oracle's codes for
+    `buckets`, whose FP32 values are `rows` [len(buckets), n*n*C]; every other
+    bucket is zero (the arrays are allocated lazily, so only the sampled rows
+    take host memory)."""
+    per = n * n * C
+    codes_s, scales_s = oracle.quantize(np.ascontiguousarray(rows), len(buckets), per, fmt)
+    codes = np.zeros((W * H, per), np.uint16 if fmt == oracle.FMT_BF16 else np.uint8)
+    codes[buckets] = codes_s.reshape(len(buckets), per)
+    scales = None
+    if fmt == oracle.FMT_FP8_E4M3:
+        scales = np.ones(W * H, np.float32)
+        scales[buckets] = scales_s
+    return codes, scales
+
+
+def _mask_near_edges(gb, go, frag_ids, W, H, n):
+    """Zero the upstream gradient of the fragments among `frag_ids` that lie
+    within EDGE of a cell edge; returns the masked copy of go (on the GPU)."""
+    uv, tbn, view = _take((gb.uv, gb.tbn, gb.view), frag_ids)
+    _, _, edge = oracle.indices(uv, tbn, view, W, H, n)
+    near = np.asarray(frag_ids)[~_keep(edge)]
+    gm = go.clone()
+    if near.size:
+        gm[torch.from_numpy(near.astype(np.int64)).to(DEV)] = 0.0
+    return gm, int(near.size)
+
+
+def _window_fragments(rt, tex, gb, win):
+    """Fragments whose bucket lies within one bucket of the window (a bucket
+    index can be off by one only at a bucket edge, so no other fragment can
+    reach the window)."""
+    idx, _ = rt.debug_indices(tex, gb.uv, gb.tbn, gb.view)
+    bi0, bj0, bw, bh = win
+    m = ((idx[:, 0] >= bi0 - 1) & (idx[:, 0] <= bi0 + bw) & (idx[:, 1] >= bj0 - 1)
+         & (idx[:, 1] <= bj0 + bh))
+    return host(torch.nonzero(m).flatten())
+
+
+def test_single_view_full_size(rt):
+    w = wl.WORKLOADS["c2"]
+    W, H, n, C = w.W, w.H, w.n, w.C
+    tex = w.make_texture(DEV)
+    gb = w.make_gbuffer(DEV)
+    N = gb.count
+    master = rt.Texture(tex, W, H, n, C)
+    c16, _ = rt.quantize(master, "bf16")
+    c8, s8 = rt.quantize(master, "fp8")
+    t16 = rt.Texture(c16, W, H, n, C, "bf16")
+    t8 = rt.Texture(c8, W, H, n, C, "fp8", s8)
+    out32 = rt.lookup_fwd(master, gb.uv, gb.tbn, gb.view)
+    out16 = rt.lookup_fwd(t16, gb.uv, gb.tbn, gb.view)
+    out8 = rt.lookup_fwd(t8, gb.uv, gb.tbn, gb.view)
+    torch.cuda.synchronize()
+
+    sel = _sample(N, 100000, 1)
+    uv, tbn, view = _take((gb.uv, gb.tbn, gb.view), sel)
+    idx, _, edge = oracle.indices(uv, tbn, view, W, H, n)
+    keep = _keep(edge)
+    assert keep.mean() > 0.99  # clamped samples sit on a sample-grid bound
+    tex_h = host(tex)
+    otex = oracle.Tex(tex_h, W, H, n, C)
+    err32 = check_fwd(host(out32)[sel], oracle.lookup_fwd(otex, uv, tbn, view), keep)
+
+    # quantised storage: codes of sampled buckets bit-exact, forwards on the
+    # fragments that fall in them
+    bsel = idx[:, 1].astype(np.int64) * W + idx[:, 0]
+    buckets = np.unique(bsel[:4000])
+    fsel = np.isin(bsel, buckets) & keep
+    rows = tex_h.reshape(W * H, -1)[buckets]
+    errs = {}
+    for name, fmt, out, codes_gpu, sc_gpu in (("bf16", oracle.FMT_BF16, out16, c16, None),
+                                              ("fp8", oracle.FMT_FP8_E4M3, out8, c8, s8)):
+        codes, scales = _oracle_codes(rows, W, H, n, C, buckets, fmt)
+        got = host(codes_gpu).reshape(W * H, -1)[buckets]
+        np.testing.assert_array_equal(got.view(codes.dtype), codes[buckets])
+        if sc_gpu is not None:
+            np.testing.assert_array_equal(host(sc_gpu).reshape(-1)[buckets], scales[buckets])
+        ref = oracle.lookup_fwd(oracle.Tex(codes, W, H, n, C, fmt, scales),
+                                uv[fsel], tbn[fsel], view[fsel])
+        errs[name] = check_fwd(host(out)[sel][fsel], ref)
+
+    # backward over the whole G-buffer; the dense gradient on a 32x32 window
+    go = wl.grad_out(N, C, seed=w.seed, device=DEV)
+    win = (400, 300, 32, 32)
+    near_ids = _window_fragments(rt, master, gb, win)
+    gm, n_near = _mask_near_edges(gb, go, near_ids, W, H, n)
+    gt, gv, gu = rt.lookup_bwd(master, gb.uv, gb.tbn, gb.view, gm)
+    torch.cuda.synchronize()
+    uvw, tbnw, vw, gw = _take((gb.uv, gb.tbn, gb.view, gm), near_ids)
+    r = oracle.lookup_bwd(otex, uvw, tbnw, vw, gw, window=win, want_view=False,
+                          want_uv=False)
+    assert np.count_nonzero(r["absg_tex"]) > 1000
+    G = host(gt[win[1]:win[1] + win[3], win[0]:win[0] + win[2]])
+    rt_tex = check_grad_tex(G, r, n)
+    # view gradients on sampled fragments away from the cell and diagonal kinks
+    s2 = sel[:20000]
+    uv2, tbn2, v2, g2 = _take((gb.uv, gb.tbn, gb.view, gm), s2)
+    r2 = oracle.lookup_bwd(otex, uv2, tbn2, v2, g2, want_tex=False)
+    e2 = edge[:20000]
+    smooth = _keep(e2) & (e2[:, 1] >= 1e-5) & (e2[:, 2] >= 1e-5)
+    rv = check_grad_vec(host(gv)[s2][smooth], r2["grad_view"][smooth],
+                        r2["scale_view"][smooth])
+    assert np.all(host(gu) == 0)
+    print(f"single view: fwd max err f32 {err32:.2e} bf16 {errs['bf16']:.2e} "
+          f"fp8 {errs['fp8']:.2e}; grad_tex err/tol {rt_tex:.2e} ({len(near_ids)} fragments "
+          f"near the window, {n_near} masked); grad_view err/tol {rv[0]:.2e}")
+
+
+def test_multi_view_full_size(rt):
+    w = wl.WORKLOADS["c3"]
+    W, H, n, C = w.W, w.H, w.n, w.C
+    tex = w.make_texture(DEV)
+    gb = w.make_gbuffer(DEV)
+    N = gb.count
+    master = rt.Texture(tex, W, H, n, C)
+    c8, s8 = rt.quantize(master, "fp8")
+    out32 = rt.lookup_fwd(master, gb.uv, gb.tbn, gb.view)
+    out8 = rt.lookup_fwd(rt.Texture(c8, W, H, n, C, "fp8", s8), gb.uv, gb.tbn, gb.view)
+    idx_g, _ = rt.debug_indices(master, gb.uv, gb.tbn, gb.view)
+    torch.cuda.synchronize()
+    sel = _sample(N, 300000, 2)
+    uv, tbn, view, o32, o8, gi = _take((gb.uv, gb.tbn, gb.view, out32, out8, idx_g), sel)
+    idx, _, edge = oracle.indices(uv, tbn, view, W, H, n)
+    keep = _keep(edge)
+    assert np.array_equal(gi[keep], idx[keep])
+    ref = oracle.lookup_fwd(oracle.Tex(host(tex), W, H, n, C), uv, tbn, view)
+    err = check_fwd(o32, ref, keep)
+    bsel = idx[:, 1].astype(np.int64) * W + idx[:, 0]
+    buckets = np.unique(bsel[:3000])
+    fsel = np.isin(bsel, buckets) & keep
+    rows = host(tex).reshape(W * H, -1)[buckets]
+    codes, scales = _oracle_codes(rows, W, H, n, C, buckets, oracle.FMT_FP8_E4M3)
+    np.testing.assert_array_equal(host(c8).reshape(W * H, -1)[buckets], codes[buckets])
+    ref8 = oracle.lookup_fwd(oracle.Tex(codes, W, H, n, C, oracle.FMT_FP8_E4M3, scales),
+                             uv[fsel], tbn[fsel], view[fsel])
+    err8 = check_fwd(o8[fsel], ref8)
+    print(f"64 views: {N} fragments; fwd max err f32 {err:.2e} on {int(keep.sum())}, "
+          f"fp8 {err8:.2e} on {int(fsel.sum())} sampled")
+
+
+def test_large_fp8_forward_backward(rt):
+    w = wl.WORKLOADS["c5"]
+    W, H, n, C = w.W, w.H, w.n, w.C
+    tex = w.make_texture(DEV)  # FP32 master, 17.2 GB
+    gb = w.make_gbuffer(DEV)
+    N = gb.count
+    master = rt.Texture(tex, W, H, n, C)
+    c8, s8 = rt.quantize(master, "fp8")
+    t8 = rt.Texture(c8, W, H, n, C, "fp8", s8)
+    out8 = rt.lookup_fwd(t8, gb.uv, gb.tbn, gb.view)
+    out32 = rt.lookup_fwd(master, gb.uv, gb.tbn, gb.view)
+    e2e = (out8 - out32).abs()
+    e2e_max, e2e_mean = float(e2e.max()), float(e2e.mean())
+    del e2e, out32
+    go = wl.grad_out(N, C, seed=w.seed, device=DEV)
+    win = (1000, 1000, 16, 16)
+    near_ids = _window_fragments(rt, t8, gb, win)
+    gm, n_near = _mask_near_edges(gb, go, near_ids, W, H, n)
+    gt, gv, _ = rt.lookup_bwd(t8, gb.uv, gb.tbn, gb.view, gm, want_uv=False)
+    torch.cuda.synchronize()
+
+    sel = _sample(N, 200000, 3)
+    uv, tbn, view, g_s, o8, gv_s = _take((gb.uv, gb.tbn, gb.view, gm, out8, gv), sel)
+    idx, _, edge = oracle.indices(uv, tbn, view, W, H, n)
+    keep = _keep(edge)
+    # the oracle quantises the sampled buckets and the window's neighbourhood
+    bsel = idx[:, 1].astype(np.int64) * W + idx[:, 0]
+    wi, wj = np.meshgrid(np.arange(win[0] - 1, win[0] + win[2] + 1),
+                         np.arange(win[1] - 1, win[1] + win[3] + 1))
+    buckets = np.unique(np.concatenate([bsel[:3000], (wj * W + wi).ravel()]))
+    bt = torch.from_numpy(buckets).to(DEV)
+    rows = host(tex.view(W * H, -1)[bt])
+    codes, scales = _oracle_codes(rows, W, H, n, C, buckets, oracle.FMT_FP8_E4M3)
+    np.testing.assert_array_equal(host(c8.view(W * H, -1)[bt]), codes[buckets])
+    np.testing.assert_array_equal(host(s8.view(-1)[bt]), scales[buckets])
+    otex = oracle.Tex(codes, W, H, n, C, oracle.FMT_FP8_E4M3, scales)
+    fsel = np.isin(bsel, buckets) & keep
+    ref8 = oracle.lookup_fwd(otex, uv[fsel], tbn[fsel], view[fsel])
+    err8 = check_fwd(o8[fsel], ref8)
+    # view gradients on sampled fragments of those buckets, away from kinks
+    r = oracle.lookup_bwd(otex, uv[fsel], tbn[fsel], view[fsel], g_s[fsel], want_tex=False,
+                          want_uv=False)
+    smooth = (edge[fsel, 1] >= 1e-5) & (edge[fsel, 2] >= 1e-5)
+    rv = check_grad_vec(gv_s[fsel][smooth], r["grad_view"][smooth], r["scale_view"][smooth])
+    # the dense gradient on the window
+    uvw, tbnw, vw, gw = _take((gb.uv, gb.tbn, gb.view, gm), near_ids)
+    r3 = oracle.lookup_bwd(otex, uvw, tbnw, vw, gw, window=win, want_view=False,
+                           want_uv=False)
+    assert np.count_nonzero(r3["absg_tex"]) > 100
+    G = host(gt[win[1]:win[1] + win[3], win[0]:win[0] + win[2]])
+    rt_tex = check_grad_tex(G, r3, n)
+    print(f"large fp8: {N} fragments; fwd err vs oracle {err8:.2e} on {int(fsel.sum())}; "
+          f"end-to-end vs FP32 storage max {e2e_max:.3e} mean {e2e_mean:.3e}; "
+          f"grad_view err/tol {rv[0]:.2e}; grad_tex err/tol {rt_tex:.2e} "
+          f"({len(near_ids)} fragments near the window, {n_near} masked)")
