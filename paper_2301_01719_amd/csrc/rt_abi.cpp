@@ -1,7 +1,7 @@
 // rt_abi.cpp -- the extern "C" boundary of libradtex.so (declared in
 // include/radtex.h): argument validation, texture handles, workspace sizing,
 // kernel dispatch and the event-based kernel timer.
-#include "../../include/radtex.h"
+#include "radtex.h"
 
 #include <hip/hip_runtime.h>
 

@@ -427,18 +427,17 @@ __device__ __forceinline__ void accumulate_round(int cell, float v[4 * C], bool 
                                                  bool next_same, int n, float* tile) {
     const int lane = threadIdx.x & 63;
     constexpr int F = 4 * C;
-    const int prev_cell = __shfl_up(cell, 1, 64);
-    const bool joins_prev = lane > 0 && prev_cell == cell;
-    if (__ballot(joins_prev) != 0ull) {
+    // a run of equal cells is contiguous, so once no lane has a partner at
+    // distance o every run is at most o long and the scan is complete
 #pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-            const int oc = __shfl_up(cell, o, 64);
-            const bool same = lane >= o && oc == cell;
+    for (int o = 1; o < 64; o <<= 1) {
+        const int oc = __shfl_up(cell, o, 64);
+        const bool same = lane >= o && oc == cell;
+        if (__ballot(same) == 0ull) break;
 #pragma unroll
-            for (int q = 0; q < F; q++) {
-                const float ov = __shfl_up(v[q], o, 64);
-                if (same) v[q] += ov;
-            }
+        for (int q = 0; q < F; q++) {
+            const float ov = __shfl_up(v[q], o, 64);
+            if (same) v[q] += ov;
         }
     }
     const bool tail = valid && !next_same;
@@ -633,9 +632,12 @@ __device__ __forceinline__ void zero_store(float* __restrict__ dst, int te) {
 // workgroup.  k_segacc writes the untouched buckets and those with at most 64
 // records (served from one register window) and lists those with 65..PIECE
 // records for k_segacc_big (rounds of 64 with a carry).  Splitting keeps the
-// register footprint of the common case small.
-constexpr int SEG_GROUP = 8;
-
+// register footprint of the common case small.  The list is split over
+// BIG_LISTS counters, one atomic per group, so that workloads where most
+// buckets are big do not serialise on one address: runs of BIG_RUN groups
+// take the lists in turn (group g appends to list (g / BIG_RUN) mod
+// BIG_LISTS), which keeps neighbouring buckets on one XCD in k_segacc_big.
+// The order inside a list does not matter, each bucket is reduced alone.
 template <int C, int MODE>
 __global__ __launch_bounds__(256) void k_segacc(const uint32_t* __restrict__ skeys,
                                                 const uint32_t* __restrict__ svals,
@@ -645,19 +647,33 @@ __global__ __launch_bounds__(256) void k_segacc(const uint32_t* __restrict__ ske
                                                 float* __restrict__ grad_tex, int64_t nbuckets,
                                                 int64_t R, int n, uint32_t cell_mask,
                                                 uint32_t* __restrict__ big_count,
-                                                uint32_t* __restrict__ big_list) {
+                                                uint32_t* __restrict__ big_list,
+                                                int64_t big_cap) {
     extern __shared__ float lds[];
     const int te = n * n * C;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     float* tile = lds + w * te;
     const int64_t ngroups = (nbuckets + SEG_GROUP - 1) / SEG_GROUP;
-    // groups are visited grid-stride; the launch caps the grid
     for (int64_t grp = (int64_t)xcd_block_id(blockIdx.x, gridDim.x) * 4 + w; grp < ngroups;
          grp += (int64_t)gridDim.x * 4) {
         const int64_t b0 = grp * SEG_GROUP;
         int2 rl = make_int2(0, 0);
         if (lane < SEG_GROUP && b0 + lane < nbuckets) rl = range[b0 + lane];
         const int nb = (int)((nbuckets - b0) < SEG_GROUP ? (nbuckets - b0) : SEG_GROUP);
+        // list the group's buckets with 65..PIECE records (more go to pass 2)
+        const int cl = rl.y - rl.x;
+        const bool big = cl > 64 && cl <= PIECE;
+        const uint64_t bm = __ballot(big);
+        if (bm != 0ull) {
+            const int64_t list = (grp / BIG_RUN) % BIG_LISTS;
+            uint32_t base = 0;
+            if (lane == 0) base = atomicAdd(big_count + list * BIG_STRIDE, (uint32_t)__popcll(bm));
+            base = __shfl(base, 0, 64);
+            if (big) {
+                const uint32_t below = (uint32_t)__popcll(bm & ((1ull << lane) - 1ull));
+                big_list[list * big_cap + base + below] = (uint32_t)(b0 + lane);
+            }
+        }
         RecWindow<C> win;
         win.start = win.end = -1;
         for (int k = 0; k < nb; k++) {
@@ -670,12 +686,7 @@ __global__ __launch_bounds__(256) void k_segacc(const uint32_t* __restrict__ ske
                 zero_store(dst, te);
                 continue;
             }
-            if (cnt > 64) {
-                // left to k_segacc_big (65..PIECE records) or pass 2 (hot); the
-                // list's order does not matter, each bucket is reduced alone
-                if (cnt <= PIECE && lane == 0) big_list[atomicAdd(big_count, 1u)] = (uint32_t)(b0 + k);
-                continue;
-            }
+            if (cnt > 64) continue;  // listed above, or hot
             if (!(rx >= win.start && ry <= win.end))
                 load_window<C, MODE>(skeys, svals, wrec, grad_out, rx, R, cell_mask, win);
             tile_zero(tile, te);
@@ -685,8 +696,9 @@ __global__ __launch_bounds__(256) void k_segacc(const uint32_t* __restrict__ ske
     }
 }
 
-// Buckets with 65..PIECE records, listed by k_segacc: one wavefront per listed
-// bucket (grid-stride), rounds of 64 records with a carry.
+// Buckets with 65..PIECE records, listed by k_segacc: workgroup x serves list
+// x mod BIG_LISTS, one wavefront per listed bucket, rounds of 64 records with a
+// carry.
 template <int C, int MODE>
 __global__ __launch_bounds__(256) void k_segacc_big(const uint32_t* __restrict__ skeys,
                                                     const uint32_t* __restrict__ svals,
@@ -696,14 +708,18 @@ __global__ __launch_bounds__(256) void k_segacc_big(const uint32_t* __restrict__
                                                     float* __restrict__ grad_tex, int n,
                                                     uint32_t cell_mask,
                                                     const uint32_t* __restrict__ big_count,
-                                                    const uint32_t* __restrict__ big_list) {
+                                                    const uint32_t* __restrict__ big_list,
+                                                    int64_t big_cap) {
     extern __shared__ float lds[];
     const int te = n * n * C;
     const int w = threadIdx.x >> 6;
     float* tile = lds + w * te;
-    const uint32_t count = *big_count;
-    for (uint32_t e = blockIdx.x * 4 + w; e < count; e += gridDim.x * 4) {
-        const uint32_t b = __builtin_amdgcn_readfirstlane(big_list[e]);
+    const uint32_t list = blockIdx.x % BIG_LISTS;
+    const uint32_t part = blockIdx.x / BIG_LISTS, parts = gridDim.x / BIG_LISTS;
+    const uint32_t count = __builtin_amdgcn_readfirstlane(big_count[list * BIG_STRIDE]);
+    const uint32_t* entries = big_list + list * big_cap;
+    for (uint32_t e = part * 4 + w; e < count; e += parts * 4) {
+        const uint32_t b = __builtin_amdgcn_readfirstlane(entries[e]);
         const int2 r = range[b];
         const int rx = __builtin_amdgcn_readfirstlane(r.x);
         const int ry = __builtin_amdgcn_readfirstlane(r.y);
@@ -831,8 +847,16 @@ bool plan_backward(int W, int H, int n, int C, int64_t N, int mode, BwdPlan* p) 
     p->off_hist = take((size_t)p->scan_len * 4);
     p->off_hoff = take((size_t)p->scan_len * 4);
     p->off_scanp = take((size_t)(p->scan_blocks + 1) * 4);
-    p->off_range = take((size_t)nb * 8 + 4);
-    p->off_biglist = take((size_t)(R / 65 + 1) * 4);
+    // big-bucket lists: list l receives the runs r of BIG_RUN groups with
+    // r mod BIG_LISTS = l, at most ceil(ngroups / (BIG_RUN BIG_LISTS)) runs of
+    // BIG_RUN * SEG_GROUP buckets, and no list exceeds the R/65 buckets that
+    // can hold more than 64 records
+    const int64_t ngroups = (nb + SEG_GROUP - 1) / SEG_GROUP;
+    const int64_t runs_per_list = (ngroups + BIG_RUN * BIG_LISTS - 1) / (BIG_RUN * BIG_LISTS);
+    const int64_t per_list = runs_per_list * BIG_RUN * SEG_GROUP;
+    p->big_cap = std::max<int64_t>(1, std::min<int64_t>(per_list, R / 65));
+    p->off_range = take((size_t)BIG_LISTS * BIG_STRIDE * 4 + (size_t)nb * 8);
+    p->off_biglist = take((size_t)BIG_LISTS * p->big_cap * 4);
     p->off_part = take((size_t)p->chunks * 2 * p->tile_elems * 4);
     p->total = o;
     return true;
@@ -856,12 +880,12 @@ template <int MODE>
 static void launch_segacc_c(int C, dim3 grid, size_t shm, hipStream_t s, const uint32_t* sk,
                             const uint32_t* sv, const float* wrec, const float* go,
                             const int2* range, float* gt, int64_t nb, int64_t R, int n,
-                            uint32_t mask, uint32_t* bc, uint32_t* bl) {
+                            uint32_t mask, uint32_t* bc, uint32_t* bl, int64_t cap) {
     switch (C) {
-    case 1: hipLaunchKernelGGL((k_segacc<1, MODE>), grid, dim3(256), shm, s, sk, sv, wrec, go, range, gt, nb, R, n, mask, bc, bl); break;
-    case 2: hipLaunchKernelGGL((k_segacc<2, MODE>), grid, dim3(256), shm, s, sk, sv, wrec, go, range, gt, nb, R, n, mask, bc, bl); break;
-    case 3: hipLaunchKernelGGL((k_segacc<3, MODE>), grid, dim3(256), shm, s, sk, sv, wrec, go, range, gt, nb, R, n, mask, bc, bl); break;
-    default: hipLaunchKernelGGL((k_segacc<4, MODE>), grid, dim3(256), shm, s, sk, sv, wrec, go, range, gt, nb, R, n, mask, bc, bl); break;
+    case 1: hipLaunchKernelGGL((k_segacc<1, MODE>), grid, dim3(256), shm, s, sk, sv, wrec, go, range, gt, nb, R, n, mask, bc, bl, cap); break;
+    case 2: hipLaunchKernelGGL((k_segacc<2, MODE>), grid, dim3(256), shm, s, sk, sv, wrec, go, range, gt, nb, R, n, mask, bc, bl, cap); break;
+    case 3: hipLaunchKernelGGL((k_segacc<3, MODE>), grid, dim3(256), shm, s, sk, sv, wrec, go, range, gt, nb, R, n, mask, bc, bl, cap); break;
+    default: hipLaunchKernelGGL((k_segacc<4, MODE>), grid, dim3(256), shm, s, sk, sv, wrec, go, range, gt, nb, R, n, mask, bc, bl, cap); break;
     }
 }
 
@@ -869,12 +893,12 @@ template <int MODE>
 static void launch_segacc_big_c(int C, dim3 grid, size_t shm, hipStream_t s, const uint32_t* sk,
                                 const uint32_t* sv, const float* wrec, const float* go,
                                 const int2* range, float* gt, int n, uint32_t mask,
-                                const uint32_t* bc, const uint32_t* bl) {
+                                const uint32_t* bc, const uint32_t* bl, int64_t cap) {
     switch (C) {
-    case 1: hipLaunchKernelGGL((k_segacc_big<1, MODE>), grid, dim3(256), shm, s, sk, sv, wrec, go, range, gt, n, mask, bc, bl); break;
-    case 2: hipLaunchKernelGGL((k_segacc_big<2, MODE>), grid, dim3(256), shm, s, sk, sv, wrec, go, range, gt, n, mask, bc, bl); break;
-    case 3: hipLaunchKernelGGL((k_segacc_big<3, MODE>), grid, dim3(256), shm, s, sk, sv, wrec, go, range, gt, n, mask, bc, bl); break;
-    default: hipLaunchKernelGGL((k_segacc_big<4, MODE>), grid, dim3(256), shm, s, sk, sv, wrec, go, range, gt, n, mask, bc, bl); break;
+    case 1: hipLaunchKernelGGL((k_segacc_big<1, MODE>), grid, dim3(256), shm, s, sk, sv, wrec, go, range, gt, n, mask, bc, bl, cap); break;
+    case 2: hipLaunchKernelGGL((k_segacc_big<2, MODE>), grid, dim3(256), shm, s, sk, sv, wrec, go, range, gt, n, mask, bc, bl, cap); break;
+    case 3: hipLaunchKernelGGL((k_segacc_big<3, MODE>), grid, dim3(256), shm, s, sk, sv, wrec, go, range, gt, n, mask, bc, bl, cap); break;
+    default: hipLaunchKernelGGL((k_segacc_big<4, MODE>), grid, dim3(256), shm, s, sk, sv, wrec, go, range, gt, n, mask, bc, bl, cap); break;
     }
 }
 
@@ -919,8 +943,8 @@ hipError_t launch_backward(const TexView& t, int fmt, int mode, const float* uv,
     uint32_t* hist = (uint32_t*)(wsb + plan.off_hist);
     uint32_t* hoff = (uint32_t*)(wsb + plan.off_hoff);
     uint32_t* scanp = (uint32_t*)(wsb + plan.off_scanp);
-    int2* range = (int2*)(wsb + plan.off_range);
-    uint32_t* big_count = (uint32_t*)(wsb + plan.off_range) + 2 * (int64_t)t.W * t.H;
+    uint32_t* big_count = (uint32_t*)(wsb + plan.off_range);  // BIG_LISTS counters
+    int2* range = (int2*)(big_count + BIG_LISTS * BIG_STRIDE);
     uint32_t* big_list = (uint32_t*)(wsb + plan.off_biglist);
     float* part = (float*)(wsb + plan.off_part);
     const int64_t R = plan.records;
@@ -973,7 +997,7 @@ hipError_t launch_backward(const TexView& t, int fmt, int mode, const float* uv,
 
     // 3. ranges
     const int64_t nb = (int64_t)t.W * t.H;
-    launch_fill((uint32_t*)range, nb * 2 + 1, 0u, s);  // ranges and the big-bucket count
+    launch_fill(big_count, BIG_LISTS * BIG_STRIDE + nb * 2, 0u, s);  // counters and ranges
     if (R > 0) {
         prof_begin(K_BUCKET_RANGES, s);
         hipLaunchKernelGGL(k_bucket_ranges, dim3((uint32_t)((R + 255) / 256)), dim3(256), 0, s,
@@ -984,22 +1008,25 @@ hipError_t launch_backward(const TexView& t, int fmt, int mode, const float* uv,
     // 4. pass 1 over buckets
     const int te = (int)plan.tile_elems;
     const uint32_t cell_mask = plan.cell_bits >= 32 ? 0xFFFFFFFFu : ((1u << plan.cell_bits) - 1u);
-    prof_begin(K_SEGACC, s);
     const int64_t groups = (nb + SEG_GROUP - 1) / SEG_GROUP;
     const dim3 g1((uint32_t)((groups + 3) / 4));
     prof_begin(K_SEGACC, s);
     if (mode == MODE_NEAREST)
-        launch_segacc_c<MODE_NEAREST>(t.C, g1, (size_t)4 * te * 4, s, skeys, svals, wrec, grad_out, range, grad_tex, nb, R, t.n, cell_mask, big_count, big_list);
+        launch_segacc_c<MODE_NEAREST>(t.C, g1, (size_t)4 * te * 4, s, skeys, svals, wrec, grad_out, range, grad_tex, nb, R, t.n, cell_mask, big_count, big_list, plan.big_cap);
     else
-        launch_segacc_c<MODE_BILINEAR>(t.C, g1, (size_t)4 * te * 4, s, skeys, svals, wrec, grad_out, range, grad_tex, nb, R, t.n, cell_mask, big_count, big_list);
+        launch_segacc_c<MODE_BILINEAR>(t.C, g1, (size_t)4 * te * 4, s, skeys, svals, wrec, grad_out, range, grad_tex, nb, R, t.n, cell_mask, big_count, big_list, plan.big_cap);
     prof_end(K_SEGACC, s);
     if (R > 64) {
-        const dim3 g2((uint32_t)std::min<int64_t>((R / 65 + 3) / 4 + 1, 1024));
+        // BIG_LISTS x parts workgroups, four wavefronts each; parts grows with
+        // the number of buckets that can be big
+        const int64_t parts = std::min<int64_t>(std::max<int64_t>(
+            1, (R / 65 + 4 * BIG_LISTS - 1) / (4 * BIG_LISTS)), 64);
+        const dim3 g2((uint32_t)(BIG_LISTS * parts));
         prof_begin(K_SEGACC_BIG, s);
         if (mode == MODE_NEAREST)
-            launch_segacc_big_c<MODE_NEAREST>(t.C, g2, (size_t)4 * te * 4, s, skeys, svals, wrec, grad_out, range, grad_tex, t.n, cell_mask, big_count, big_list);
+            launch_segacc_big_c<MODE_NEAREST>(t.C, g2, (size_t)4 * te * 4, s, skeys, svals, wrec, grad_out, range, grad_tex, t.n, cell_mask, big_count, big_list, plan.big_cap);
         else
-            launch_segacc_big_c<MODE_BILINEAR>(t.C, g2, (size_t)4 * te * 4, s, skeys, svals, wrec, grad_out, range, grad_tex, t.n, cell_mask, big_count, big_list);
+            launch_segacc_big_c<MODE_BILINEAR>(t.C, g2, (size_t)4 * te * 4, s, skeys, svals, wrec, grad_out, range, grad_tex, t.n, cell_mask, big_count, big_list, plan.big_cap);
         prof_end(K_SEGACC_BIG, s);
     }
 

@@ -55,11 +55,16 @@ struct BwdPlan {
     int64_t scan_blocks;  // partial sums of the scan
     int64_t chunks;       // fixed chunks of the sorted records (hot buckets)
     int64_t tile_elems;   // n*n*C
+    int64_t big_cap;      // entries per big-bucket list (one list per counter)
     // workspace offsets (bytes)
     size_t off_keys0, off_keys1, off_vals0, off_vals1, off_wrec, off_hist, off_hoff, off_scanp,
         off_range, off_biglist, off_part, total;
 };
 constexpr int PIECE = 2048;  // records per chunk; buckets with more are "hot"
+constexpr int SEG_GROUP = 8;  // buckets per wavefront in the first accumulation pass
+constexpr int BIG_LISTS = 64; // big-bucket lists, each with its own counter
+constexpr int BIG_STRIDE = 64;  // u32 between two counters (256 bytes)
+constexpr int BIG_RUN = 64;     // consecutive groups that append to one list
 bool plan_backward(int W, int H, int n, int C, int64_t N, int mode, BwdPlan* p);
 
 hipError_t launch_backward(const TexView& t, int fmt, int mode, const float* uv,
