@@ -137,8 +137,9 @@ def main():
             rt._check(rt.LIB.rt_quantize(master.handle, rt.FORMATS[args.storage],
                                          rt._ptr(storage["codes"]), rt._ptr(storage["scales"]),
                                          rt._stream(dev)))
-        rt.lookup_fwd(tex_s, gb.uv, gb.tbn, gb.view, out=out)
-        rt.lookup_bwd(tex_s, gb.uv, gb.tbn, gb.view, go, workspace=ws, grad_tex=grad_tex)
+        rt.lookup_fwd(tex_s, gb.uv, gb.tbn, gb.view, out=out, image=gb.image)
+        rt.lookup_bwd(tex_s, gb.uv, gb.tbn, gb.view, go, workspace=ws, grad_tex=grad_tex,
+                      image=gb.image)
 
     if args.profile_steps:
         for _ in range(args.profile_steps):
@@ -202,9 +203,12 @@ def main():
     # ---- forward per storage format (FP32 / BF16 / FP8) ----------------------
     formats = {}
     S = min(N, 200000)
-    sel = torch.linspace(0, N - 1, S, device=dev).round().to(torch.int64)
+    # evenly spaced sample of fragments, in exact integer arithmetic (a float32
+    # linspace rounds the last index up to N once N exceeds 2^24)
+    sel = torch.arange(S, dtype=torch.int64, device=dev) * (N - 1) // max(S - 1, 1)
+    assert 0 <= int(sel.min()) and int(sel.max()) < N
     sampled = {}
-    ref32 = rt.lookup_fwd(master, gb.uv, gb.tbn, gb.view)
+    ref32 = rt.lookup_fwd(master, gb.uv, gb.tbn, gb.view, image=gb.image)
     for fmt in ("f32", "bf16", "fp8"):
         if fmt == "f32":
             t = master
@@ -213,13 +217,13 @@ def main():
             t = rt.Texture(c_, W, H, n, C, fmt, s_)
         o = torch.empty_like(out)
         for _ in range(3):
-            rt.lookup_fwd(t, gb.uv, gb.tbn, gb.view, out=o)
+            rt.lookup_fwd(t, gb.uv, gb.tbn, gb.view, out=o, image=gb.image)
         torch.cuda.synchronize()
         rt.profile_reset()
         rt.profile_enable(True)
         reps = 20
         for _ in range(reps):
-            rt.lookup_fwd(t, gb.uv, gb.tbn, gb.view, out=o)
+            rt.lookup_fwd(t, gb.uv, gb.tbn, gb.view, out=o, image=gb.image)
         torch.cuda.synchronize()
         rt.profile_enable(False)
         launches, total = rt.profile_read()["k_lookup_fwd"]
@@ -292,7 +296,9 @@ def main():
         "config": {"workload": w.name, "buckets": [W, H], "n": n, "channels": C,
                    "fragments": N, "storage": args.storage,
                    "step": "quantize(f32->%s) + forward + backward(grad_tex dense, grad_view, "
-                           "grad_uv)" % args.storage, "mode": "nearest"},
+                           "grad_uv)" % args.storage, "mode": "nearest",
+                   "fragment_order": ("%dx%dx%d images visited in 32x8 pixel tiles" % gb.image
+                                      if gb.image else "flat")},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "kernels": per_kernel,

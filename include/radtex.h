@@ -101,8 +101,21 @@ typedef struct {
                             /* value = e4m3(code) * scale), must be NULL otherwise */
 } rt_texture_desc;
 
+/* Fragments of a G-buffer: for every visible pixel its texture coordinates
+ * u,v and its incidence (view) vector, with the tangent frame that moves the
+ * vector into orthogonal texture space (Sec. 2 and 2.1).
+ * views/height/width are an optional tiling hint.  When all three are positive
+ * the N = views * height * width fragments are `views` images of height x
+ * width pixels, view-major and row-major, and the kernels visit them in
+ * 32 x 8 pixel tiles, which keeps the texture fetches of neighbouring pixels
+ * together in the caches; all three 0 means a flat list.  The hint changes
+ * only the order of the visits, never a result.  Any other combination, or a
+ * product that differs from count, is RT_ERR_INVALID_ARG. */
 typedef struct {
     int64_t count;          /* N fragments (0 allowed)                            */
+    int32_t views;          /* tiling hint: images, or 0                          */
+    int32_t height;         /* tiling hint: rows per image, or 0                  */
+    int32_t width;          /* tiling hint: pixels per row, or 0                  */
     const float* uv;        /* [N][2] texture coordinates; wrap (repeat)          */
     const float* tbn;       /* [N][3][3] rows T, B, N                              */
     const float* view;      /* [N][3] surface -> eye                               */

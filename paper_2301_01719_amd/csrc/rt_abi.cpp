@@ -63,11 +63,24 @@ rt_status check_tex(const rt_texture* t) {
     return RT_OK;
 }
 
+rt::FragMap fragmap(const rt_fragments* f) {
+    return rt::make_fragmap(f->count, f->views, f->height, f->width);
+}
+
 rt_status check_frags(const rt_fragments* f) {
     if (!f) return fail(RT_ERR_INVALID_ARG, "fragments is NULL");
     if (f->count < 0) return fail(RT_ERR_INVALID_ARG, "fragment count %lld < 0", (long long)f->count);
     if (f->count >= (1ll << 31))
         return fail(RT_ERR_UNSUPPORTED, "fragment count %lld >= 2^31", (long long)f->count);
+    const bool flat = f->views == 0 && f->height == 0 && f->width == 0;
+    if (!flat) {
+        if (f->views <= 0 || f->height <= 0 || f->width <= 0)
+            return fail(RT_ERR_INVALID_ARG, "tiling hint views=%d height=%d width=%d: all three "
+                        "positive or all three 0", f->views, f->height, f->width);
+        if ((int64_t)f->views * f->height * f->width != f->count)
+            return fail(RT_ERR_INVALID_ARG, "tiling hint %d x %d x %d does not match count %lld",
+                        f->views, f->height, f->width, (long long)f->count);
+    }
     if (f->count == 0) return RT_OK;
     if (!f->uv || !f->tbn || !f->view)
         return fail(RT_ERR_INVALID_ARG, "uv, tbn and view must be non-NULL when count > 0");
@@ -289,7 +302,7 @@ rt_status rt_lookup_fwd(const rt_texture* t, const rt_fragments* f, float* out, 
             return fail(RT_ERR_INVALID_ARG, "out must be %zu-byte aligned", out_align(t->view.C));
     }
     hipError_t e = rt::launch_lookup_fwd(t->view, t->fmt, (int)flags, f->uv, f->tbn, f->view, out,
-                                         f->count, (hipStream_t)stream);
+                                         fragmap(f), (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "lookup launch");
     return ok();
     RT_GUARD_END
@@ -336,7 +349,7 @@ rt_status rt_lookup_bwd(const rt_texture* t, const rt_fragments* f, const float*
             return fail(RT_ERR_WORKSPACE_TOO_SMALL, "workspace has %zu bytes, %zu needed", ws_bytes, plan.total);
     }
     hipError_t e = rt::launch_backward(t->view, t->fmt, (int)flags, f->uv, f->tbn, f->view,
-                                       grad_out, grad_tex, grad_view, grad_uv, f->count, plan,
+                                       grad_out, grad_tex, grad_view, grad_uv, fragmap(f), plan,
                                        ws, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "backward launch");
     return ok();
@@ -356,8 +369,8 @@ rt_status rt_debug_indices(const rt_texture* t, const rt_fragments* f, int32_t* 
             return fail(RT_ERR_INVALID_ARG, "idx must be 16-byte and frac 8-byte aligned");
     }
     rt::prof_begin(rt::K_DEBUG_INDICES, (hipStream_t)stream);
-    hipError_t e = rt::launch_debug_indices(t->view, f->uv, f->tbn, f->view, idx, frac, f->count,
-                                            (hipStream_t)stream);
+    hipError_t e = rt::launch_debug_indices(t->view, f->uv, f->tbn, f->view, idx, frac,
+                                            fragmap(f), (hipStream_t)stream);
     rt::prof_end(rt::K_DEBUG_INDICES, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "debug-indices launch");
     return ok();

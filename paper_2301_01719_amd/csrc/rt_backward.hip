@@ -100,9 +100,9 @@ __global__ __launch_bounds__(256) void k_bwd_fragment(
     TexView t, const float* __restrict__ uv, const float* __restrict__ tbn,
     const float* __restrict__ view, const float* __restrict__ grad_out,
     float* __restrict__ grad_view, float* __restrict__ grad_uv, uint32_t* __restrict__ keys,
-    float* __restrict__ wrec, int64_t N, int cell_bits) {
-    const int64_t f = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (f >= N) return;
+    float* __restrict__ wrec, FragMap m, int cell_bits) {
+    const int64_t f = frag_of(m, blockIdx.x, gridDim.x, threadIdx.x);
+    if (f < 0) return;
     const int n = t.n;
     Frag g = load_frag(uv, tbn, view, f);
     Dir d = map_direction(g.m, g.w, n);
@@ -865,14 +865,14 @@ bool plan_backward(int W, int H, int n, int C, int64_t N, int mode, BwdPlan* p) 
 template <int FMT, int MODE>
 static void launch_bwd_fragment_c(const TexView& t, const float* uv, const float* tbn,
                                   const float* view, const float* go, float* gview, float* guv,
-                                  uint32_t* keys, float* wrec, int64_t N, int cell_bits,
+                                  uint32_t* keys, float* wrec, const FragMap& m, int cell_bits,
                                   hipStream_t s) {
-    const uint32_t blocks = (uint32_t)((N + 255) / 256);
+    const uint32_t blocks = fragmap_blocks(m);
     switch (t.C) {
-    case 1: hipLaunchKernelGGL((k_bwd_fragment<FMT, 1, MODE>), dim3(blocks), dim3(256), 0, s, t, uv, tbn, view, go, gview, guv, keys, wrec, N, cell_bits); break;
-    case 2: hipLaunchKernelGGL((k_bwd_fragment<FMT, 2, MODE>), dim3(blocks), dim3(256), 0, s, t, uv, tbn, view, go, gview, guv, keys, wrec, N, cell_bits); break;
-    case 3: hipLaunchKernelGGL((k_bwd_fragment<FMT, 3, MODE>), dim3(blocks), dim3(256), 0, s, t, uv, tbn, view, go, gview, guv, keys, wrec, N, cell_bits); break;
-    default: hipLaunchKernelGGL((k_bwd_fragment<FMT, 4, MODE>), dim3(blocks), dim3(256), 0, s, t, uv, tbn, view, go, gview, guv, keys, wrec, N, cell_bits); break;
+    case 1: hipLaunchKernelGGL((k_bwd_fragment<FMT, 1, MODE>), dim3(blocks), dim3(256), 0, s, t, uv, tbn, view, go, gview, guv, keys, wrec, m, cell_bits); break;
+    case 2: hipLaunchKernelGGL((k_bwd_fragment<FMT, 2, MODE>), dim3(blocks), dim3(256), 0, s, t, uv, tbn, view, go, gview, guv, keys, wrec, m, cell_bits); break;
+    case 3: hipLaunchKernelGGL((k_bwd_fragment<FMT, 3, MODE>), dim3(blocks), dim3(256), 0, s, t, uv, tbn, view, go, gview, guv, keys, wrec, m, cell_bits); break;
+    default: hipLaunchKernelGGL((k_bwd_fragment<FMT, 4, MODE>), dim3(blocks), dim3(256), 0, s, t, uv, tbn, view, go, gview, guv, keys, wrec, m, cell_bits); break;
     }
 }
 
@@ -932,8 +932,9 @@ static void launch_scan(const uint32_t* in, uint32_t* out, uint32_t* part, int64
 
 hipError_t launch_backward(const TexView& t, int fmt, int mode, const float* uv,
                            const float* tbn, const float* view, const float* grad_out,
-                           float* grad_tex, float* grad_view, float* grad_uv, int64_t N,
+                           float* grad_tex, float* grad_view, float* grad_uv, const FragMap& m,
                            const BwdPlan& plan, void* ws, hipStream_t s) {
+    const int64_t N = m.N;
     char* wsb = (char*)ws;
     uint32_t* keys0 = (uint32_t*)(wsb + plan.off_keys0);
     uint32_t* keys1 = (uint32_t*)(wsb + plan.off_keys1);
@@ -955,13 +956,13 @@ hipError_t launch_backward(const TexView& t, int fmt, int mode, const float* uv,
         prof_begin(K_BWD_FRAGMENT, s);
         uint32_t* kp = want_tex ? keys0 : nullptr;
         if (mode == MODE_NEAREST) {
-            if (fmt == FMT_F32) launch_bwd_fragment_c<FMT_F32, MODE_NEAREST>(t, uv, tbn, view, grad_out, grad_view, grad_uv, kp, wrec, N, plan.cell_bits, s);
-            else if (fmt == FMT_BF16) launch_bwd_fragment_c<FMT_BF16, MODE_NEAREST>(t, uv, tbn, view, grad_out, grad_view, grad_uv, kp, wrec, N, plan.cell_bits, s);
-            else launch_bwd_fragment_c<FMT_FP8, MODE_NEAREST>(t, uv, tbn, view, grad_out, grad_view, grad_uv, kp, wrec, N, plan.cell_bits, s);
+            if (fmt == FMT_F32) launch_bwd_fragment_c<FMT_F32, MODE_NEAREST>(t, uv, tbn, view, grad_out, grad_view, grad_uv, kp, wrec, m, plan.cell_bits, s);
+            else if (fmt == FMT_BF16) launch_bwd_fragment_c<FMT_BF16, MODE_NEAREST>(t, uv, tbn, view, grad_out, grad_view, grad_uv, kp, wrec, m, plan.cell_bits, s);
+            else launch_bwd_fragment_c<FMT_FP8, MODE_NEAREST>(t, uv, tbn, view, grad_out, grad_view, grad_uv, kp, wrec, m, plan.cell_bits, s);
         } else {
-            if (fmt == FMT_F32) launch_bwd_fragment_c<FMT_F32, MODE_BILINEAR>(t, uv, tbn, view, grad_out, grad_view, grad_uv, kp, wrec, N, plan.cell_bits, s);
-            else if (fmt == FMT_BF16) launch_bwd_fragment_c<FMT_BF16, MODE_BILINEAR>(t, uv, tbn, view, grad_out, grad_view, grad_uv, kp, wrec, N, plan.cell_bits, s);
-            else launch_bwd_fragment_c<FMT_FP8, MODE_BILINEAR>(t, uv, tbn, view, grad_out, grad_view, grad_uv, kp, wrec, N, plan.cell_bits, s);
+            if (fmt == FMT_F32) launch_bwd_fragment_c<FMT_F32, MODE_BILINEAR>(t, uv, tbn, view, grad_out, grad_view, grad_uv, kp, wrec, m, plan.cell_bits, s);
+            else if (fmt == FMT_BF16) launch_bwd_fragment_c<FMT_BF16, MODE_BILINEAR>(t, uv, tbn, view, grad_out, grad_view, grad_uv, kp, wrec, m, plan.cell_bits, s);
+            else launch_bwd_fragment_c<FMT_FP8, MODE_BILINEAR>(t, uv, tbn, view, grad_out, grad_view, grad_uv, kp, wrec, m, plan.cell_bits, s);
         }
         prof_end(K_BWD_FRAGMENT, s);
         hipError_t e = hipGetLastError();

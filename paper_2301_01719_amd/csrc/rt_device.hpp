@@ -119,6 +119,57 @@ __device__ __forceinline__ float bucket_factor(const float* __restrict__ scales,
 // ---------------------------------------------------------------------------
 // Fragment inputs.
 // ---------------------------------------------------------------------------
+
+// Which fragment a thread handles.  Flat: workgroup b, thread t -> 256 b + t.
+// Tiled (the caller's images of height x width pixels): workgroup b is one
+// TILE_X x TILE_Y pixel tile, tiles row-major within an image and images in
+// order, so the fragments of one workgroup are neighbouring pixels and
+// neighbouring workgroups are neighbouring tiles.  Either way the workgroup
+// index is first renumbered with xcd_block_id.
+constexpr int TILE_X = 32, TILE_Y = 8;
+static_assert(TILE_X * TILE_Y == 256, "one tile per 256-thread workgroup");
+
+struct FragMap {
+    int64_t N;
+    int32_t width, height;     // 0: flat
+    int32_t tiles_x, tiles_y;  // tiles per row and per column of an image
+};
+
+inline FragMap make_fragmap(int64_t N, int32_t views, int32_t height, int32_t width) {
+    FragMap m{N, 0, 0, 0, 0};
+    if (views > 0 && height > 0 && width > 0) {
+        m.width = width;
+        m.height = height;
+        m.tiles_x = (width + TILE_X - 1) / TILE_X;
+        m.tiles_y = (height + TILE_Y - 1) / TILE_Y;
+    }
+    return m;
+}
+
+// workgroups of a launch over all fragments
+inline uint32_t fragmap_blocks(const FragMap& m) {
+    if (m.width == 0) return (uint32_t)((m.N + 255) / 256);
+    const int64_t views = m.N / ((int64_t)m.width * m.height);
+    return (uint32_t)(views * m.tiles_x * m.tiles_y);
+}
+
+// fragment of thread `tid` in workgroup `bid`, or -1 past the end / outside
+// the image
+__device__ __forceinline__ int64_t frag_of(const FragMap& m, uint32_t bid, uint32_t nblocks,
+                                           int tid) {
+    const uint32_t b = xcd_block_id(bid, nblocks);
+    if (m.width == 0) {
+        const int64_t f = (int64_t)b * 256 + tid;
+        return f < m.N ? f : -1;
+    }
+    const uint32_t per_view = (uint32_t)(m.tiles_x * m.tiles_y);
+    const uint32_t v = b / per_view, r = b - v * per_view;
+    const uint32_t ty = r / (uint32_t)m.tiles_x, tx = r - ty * (uint32_t)m.tiles_x;
+    const int x = (int)tx * TILE_X + (tid % TILE_X), y = (int)ty * TILE_Y + (tid / TILE_X);
+    if (x >= m.width || y >= m.height) return -1;
+    return ((int64_t)v * m.height + y) * m.width + x;
+}
+
 struct Frag {
     float u, v;
     float m[9];

@@ -9,6 +9,7 @@
 namespace rt {
 
 struct TexView;
+struct FragMap;
 
 // Kernel ids for the event-based timing of rt_profile_*.
 enum KernelId {
@@ -34,10 +35,10 @@ void prof_begin(int id, hipStream_t s);
 void prof_end(int id, hipStream_t s);
 
 hipError_t launch_lookup_fwd(const TexView& t, int fmt, int mode, const float* uv,
-                             const float* tbn, const float* view, float* out, int64_t N,
+                             const float* tbn, const float* view, float* out, const FragMap& m,
                              hipStream_t s);
 hipError_t launch_debug_indices(const TexView& t, const float* uv, const float* tbn,
-                                const float* view, int32_t* idx, float* frac, int64_t N,
+                                const float* view, int32_t* idx, float* frac, const FragMap& m,
                                 hipStream_t s);
 hipError_t launch_quantize(const TexView& src, int dst_fmt, void* codes, float* scales,
                            hipStream_t s);
@@ -69,7 +70,7 @@ bool plan_backward(int W, int H, int n, int C, int64_t N, int mode, BwdPlan* p);
 
 hipError_t launch_backward(const TexView& t, int fmt, int mode, const float* uv,
                            const float* tbn, const float* view, const float* grad_out,
-                           float* grad_tex, float* grad_view, float* grad_uv, int64_t N,
+                           float* grad_tex, float* grad_view, float* grad_uv, const FragMap& m,
                            const BwdPlan& plan, void* ws, hipStream_t s);
 
 }  // namespace rt

@@ -46,10 +46,9 @@ template <int FMT, int C, int MODE>
 __global__ __launch_bounds__(256) void k_lookup_fwd(TexView t, const float* __restrict__ uv,
                                                     const float* __restrict__ tbn,
                                                     const float* __restrict__ view,
-                                                    float* __restrict__ out, int64_t N) {
-    const uint32_t blk = xcd_block_id(blockIdx.x, gridDim.x);
-    const int64_t f = (int64_t)blk * 256 + threadIdx.x;
-    if (f >= N) return;
+                                                    float* __restrict__ out, FragMap m) {
+    const int64_t f = frag_of(m, blockIdx.x, gridDim.x, threadIdx.x);
+    if (f < 0) return;
     Frag g = load_frag(uv, tbn, view, f);
     Dir d = map_direction(g.m, g.w, t.n);
     Foot p = footprint(d.sx, d.sy, t.n);
@@ -74,9 +73,9 @@ __global__ __launch_bounds__(256) void k_debug_indices(TexView t, const float* _
                                                        const float* __restrict__ tbn,
                                                        const float* __restrict__ view,
                                                        int32_t* __restrict__ idx,
-                                                       float* __restrict__ frac, int64_t N) {
-    const int64_t f = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (f >= N) return;
+                                                       float* __restrict__ frac, FragMap m) {
+    const int64_t f = frag_of(m, blockIdx.x, gridDim.x, threadIdx.x);
+    if (f < 0) return;
     Frag g = load_frag(uv, tbn, view, f);
     Dir d = map_direction(g.m, g.w, t.n);
     int x0 = (int)d.sx, y0 = (int)d.sy;
@@ -86,43 +85,42 @@ __global__ __launch_bounds__(256) void k_debug_indices(TexView t, const float* _
 
 template <int FMT, int MODE>
 static hipError_t launch_fwd_c(const TexView& t, const float* uv, const float* tbn,
-                               const float* view, float* out, int64_t N, hipStream_t s) {
-    const uint32_t blocks = (uint32_t)((N + 255) / 256);
+                               const float* view, float* out, const FragMap& m, hipStream_t s) {
+    const uint32_t blocks = fragmap_blocks(m);
     switch (t.C) {
-    case 1: hipLaunchKernelGGL((k_lookup_fwd<FMT, 1, MODE>), dim3(blocks), dim3(256), 0, s, t, uv, tbn, view, out, N); break;
-    case 2: hipLaunchKernelGGL((k_lookup_fwd<FMT, 2, MODE>), dim3(blocks), dim3(256), 0, s, t, uv, tbn, view, out, N); break;
-    case 3: hipLaunchKernelGGL((k_lookup_fwd<FMT, 3, MODE>), dim3(blocks), dim3(256), 0, s, t, uv, tbn, view, out, N); break;
-    default: hipLaunchKernelGGL((k_lookup_fwd<FMT, 4, MODE>), dim3(blocks), dim3(256), 0, s, t, uv, tbn, view, out, N); break;
+    case 1: hipLaunchKernelGGL((k_lookup_fwd<FMT, 1, MODE>), dim3(blocks), dim3(256), 0, s, t, uv, tbn, view, out, m); break;
+    case 2: hipLaunchKernelGGL((k_lookup_fwd<FMT, 2, MODE>), dim3(blocks), dim3(256), 0, s, t, uv, tbn, view, out, m); break;
+    case 3: hipLaunchKernelGGL((k_lookup_fwd<FMT, 3, MODE>), dim3(blocks), dim3(256), 0, s, t, uv, tbn, view, out, m); break;
+    default: hipLaunchKernelGGL((k_lookup_fwd<FMT, 4, MODE>), dim3(blocks), dim3(256), 0, s, t, uv, tbn, view, out, m); break;
     }
     return hipGetLastError();
 }
 
 hipError_t launch_lookup_fwd(const TexView& t, int fmt, int mode, const float* uv,
-                             const float* tbn, const float* view, float* out, int64_t N,
+                             const float* tbn, const float* view, float* out, const FragMap& m,
                              hipStream_t s) {
-    if (N <= 0) return hipSuccess;
+    if (m.N <= 0) return hipSuccess;
     hipError_t e;
     prof_begin(K_LOOKUP_FWD, s);
     if (mode == MODE_NEAREST) {
-        if (fmt == FMT_F32) e = launch_fwd_c<FMT_F32, MODE_NEAREST>(t, uv, tbn, view, out, N, s);
-        else if (fmt == FMT_BF16) e = launch_fwd_c<FMT_BF16, MODE_NEAREST>(t, uv, tbn, view, out, N, s);
-        else e = launch_fwd_c<FMT_FP8, MODE_NEAREST>(t, uv, tbn, view, out, N, s);
+        if (fmt == FMT_F32) e = launch_fwd_c<FMT_F32, MODE_NEAREST>(t, uv, tbn, view, out, m, s);
+        else if (fmt == FMT_BF16) e = launch_fwd_c<FMT_BF16, MODE_NEAREST>(t, uv, tbn, view, out, m, s);
+        else e = launch_fwd_c<FMT_FP8, MODE_NEAREST>(t, uv, tbn, view, out, m, s);
     } else {
-        if (fmt == FMT_F32) e = launch_fwd_c<FMT_F32, MODE_BILINEAR>(t, uv, tbn, view, out, N, s);
-        else if (fmt == FMT_BF16) e = launch_fwd_c<FMT_BF16, MODE_BILINEAR>(t, uv, tbn, view, out, N, s);
-        else e = launch_fwd_c<FMT_FP8, MODE_BILINEAR>(t, uv, tbn, view, out, N, s);
+        if (fmt == FMT_F32) e = launch_fwd_c<FMT_F32, MODE_BILINEAR>(t, uv, tbn, view, out, m, s);
+        else if (fmt == FMT_BF16) e = launch_fwd_c<FMT_BF16, MODE_BILINEAR>(t, uv, tbn, view, out, m, s);
+        else e = launch_fwd_c<FMT_FP8, MODE_BILINEAR>(t, uv, tbn, view, out, m, s);
     }
     prof_end(K_LOOKUP_FWD, s);
     return e;
 }
 
 hipError_t launch_debug_indices(const TexView& t, const float* uv, const float* tbn,
-                                const float* view, int32_t* idx, float* frac, int64_t N,
+                                const float* view, int32_t* idx, float* frac, const FragMap& m,
                                 hipStream_t s) {
-    if (N <= 0) return hipSuccess;
-    const uint32_t blocks = (uint32_t)((N + 255) / 256);
-    hipLaunchKernelGGL(k_debug_indices, dim3(blocks), dim3(256), 0, s, t, uv, tbn, view, idx,
-                       frac, N);
+    if (m.N <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_debug_indices, dim3(fragmap_blocks(m)), dim3(256), 0, s, t, uv, tbn,
+                       view, idx, frac, m);
     return hipGetLastError();
 }
 

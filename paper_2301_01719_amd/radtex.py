@@ -47,8 +47,9 @@ class TextureDesc(ctypes.Structure):
 
 
 class Fragments(ctypes.Structure):
-    _fields_ = [("count", ctypes.c_int64), ("uv", ctypes.c_void_p),
-                ("tbn", ctypes.c_void_p), ("view", ctypes.c_void_p)]
+    _fields_ = [("count", ctypes.c_int64), ("views", ctypes.c_int32),
+                ("height", ctypes.c_int32), ("width", ctypes.c_int32),
+                ("uv", ctypes.c_void_p), ("tbn", ctypes.c_void_p), ("view", ctypes.c_void_p)]
 
 
 def _load() -> ctypes.CDLL:
@@ -151,13 +152,16 @@ class Texture:
         return self.n * self.n * self.C
 
 
-def _frags(uv, tbn, view) -> Fragments:
+def _frags(uv, tbn, view, image=None) -> Fragments:
+    """image = (views, height, width): the fragments are that many row-major
+    images (a tiling hint, checked by the library); None: a flat list."""
     N = uv.shape[0]
     for t, name, shape in ((uv, "uv", (N, 2)), (tbn, "tbn", (N, 3, 3)), (view, "view", (N, 3))):
         _need_gpu(t, name, torch.float32)
         if tuple(t.shape) != shape and not (name == "tbn" and tuple(t.shape) == (N, 9)):
             raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {shape}")
-    return Fragments(N, uv.data_ptr(), tbn.data_ptr(), view.data_ptr())
+    v, h, w = image if image is not None else (0, 0, 0)
+    return Fragments(N, v, h, w, uv.data_ptr(), tbn.data_ptr(), view.data_ptr())
 
 
 def quantize(tex: Texture, fmt: str):
@@ -171,8 +175,8 @@ def quantize(tex: Texture, fmt: str):
     return codes, scales
 
 
-def lookup_fwd(tex: Texture, uv, tbn, view, mode: str = "nearest", out=None):
-    fr = _frags(uv, tbn, view)
+def lookup_fwd(tex: Texture, uv, tbn, view, mode: str = "nearest", out=None, image=None):
+    fr = _frags(uv, tbn, view, image)
     if out is None:
         out = torch.empty((fr.count, tex.C), dtype=torch.float32, device=tex.device)
     else:
@@ -188,10 +192,10 @@ def bwd_workspace_bytes(tex: Texture, count: int, mode: str = "nearest") -> int:
 
 def lookup_bwd(tex: Texture, uv, tbn, view, grad_out, mode: str = "nearest", want_tex=True,
                want_view=True, want_uv=True, workspace: Optional[torch.Tensor] = None,
-               grad_tex: Optional[torch.Tensor] = None):
+               grad_tex: Optional[torch.Tensor] = None, image=None):
     """Returns (grad_tex [H,W,n,n,C] f32, grad_view [N,3], grad_uv [N,2]); None where
     not requested."""
-    fr = _frags(uv, tbn, view)
+    fr = _frags(uv, tbn, view, image)
     _need_gpu(grad_out, "grad_out", torch.float32)
     dev = tex.device
     N = fr.count
@@ -214,8 +218,8 @@ def lookup_bwd(tex: Texture, uv, tbn, view, grad_out, mode: str = "nearest", wan
     return gt, gv, gu
 
 
-def debug_indices(tex: Texture, uv, tbn, view):
-    fr = _frags(uv, tbn, view)
+def debug_indices(tex: Texture, uv, tbn, view, image=None):
+    fr = _frags(uv, tbn, view, image)
     idx = torch.empty((fr.count, 4), dtype=torch.int32, device=tex.device)
     frac = torch.empty((fr.count, 2), dtype=torch.float32, device=tex.device)
     _check(LIB.rt_debug_indices(tex.handle, ctypes.byref(fr), _ptr(idx), _ptr(frac),
@@ -225,12 +229,13 @@ def debug_indices(tex: Texture, uv, tbn, view):
 
 class _LookupFn(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, texels, uv, view, tbn, shape, mode, scales, fmt):
+    def forward(ctx, texels, uv, view, tbn, shape, mode, scales, fmt, image):
         W, H, n, C = shape
         tex = Texture(texels, W, H, n, C, fmt, scales)
-        out = lookup_fwd(tex, uv, tbn, view, mode)
+        out = lookup_fwd(tex, uv, tbn, view, mode, image=image)
         ctx.save_for_backward(texels, uv, view, tbn, scales if scales is not None else uv)
         ctx.shape, ctx.mode, ctx.fmt, ctx.has_scales = shape, mode, fmt, scales is not None
+        ctx.image = image
         return out
 
     @staticmethod
@@ -241,17 +246,19 @@ class _LookupFn(torch.autograd.Function):
         need_tex, need_uv, need_view = ctx.needs_input_grad[0], ctx.needs_input_grad[1], \
             ctx.needs_input_grad[2]
         gt, gv, gu = lookup_bwd(tex, uv, tbn, view, grad_out.contiguous(), ctx.mode,
-                                want_tex=need_tex, want_view=need_view, want_uv=need_uv)
-        return gt, gu, gv, None, None, None, None, None
+                                want_tex=need_tex, want_view=need_view, want_uv=need_uv,
+                                image=ctx.image)
+        return gt, gu, gv, None, None, None, None, None, None
 
 
 def lookup(texels: torch.Tensor, uv, tbn, view, n: int, mode: str = "nearest", fmt="f32",
-           scales: Optional[torch.Tensor] = None):
+           scales: Optional[torch.Tensor] = None, image=None):
     """Differentiable lookup.  texels: bucket-major [H, W, n, n, C]; gradients
-    flow to texels (dense, deterministic), uv and view; none to tbn."""
+    flow to texels (dense, deterministic), uv and view; none to tbn.  image =
+    (views, height, width) is the optional tiling hint of the fragments."""
     H, W = texels.shape[0], texels.shape[1]
     C = texels.shape[-1]
-    return _LookupFn.apply(texels, uv, view, tbn, (W, H, n, C), mode, scales, fmt)
+    return _LookupFn.apply(texels, uv, view, tbn, (W, H, n, C), mode, scales, fmt, image)
 
 
 # --- kernel timer -------------------------------------------------------------

@@ -24,6 +24,7 @@ from __future__ import annotations
 
 import math
 from dataclasses import dataclass
+from typing import Optional, Tuple
 
 import torch
 
@@ -158,6 +159,7 @@ class GBuffer:
     uv: torch.Tensor    # [N, 2] float32
     tbn: torch.Tensor   # [N, 3, 3] float32, rows T, B, N
     view: torch.Tensor  # [N, 3] float32, surface -> eye
+    image: Optional[Tuple[int, int, int]] = None  # (views, height, width), row-major
 
     @property
     def count(self) -> int:
@@ -167,7 +169,7 @@ class GBuffer:
         return GBuffer(self.uv[a:b], self.tbn[a:b], self.view[a:b])
 
     def to(self, device) -> "GBuffer":
-        return GBuffer(self.uv.to(device), self.tbn.to(device), self.view.to(device))
+        return GBuffer(self.uv.to(device), self.tbn.to(device), self.view.to(device), self.image)
 
 
 def flat_gbuffer(N: int, seed: int, device="cpu", min_elev_deg: float = 5.0) -> GBuffer:
@@ -233,7 +235,7 @@ def plane_gbuffer(views: int, width: int, height: int, seed: int, device="cpu",
         viewsl.append(vw.to(torch.float32))
         del eye, d, lam, P, Nv
     return GBuffer(torch.cat(uvs).contiguous(), torch.cat(tbns).contiguous(),
-                   torch.cat(viewsl).contiguous())
+                   torch.cat(viewsl).contiguous(), (views, height, width))
 
 
 # --- gradient noise height field (C5) -----------------------------------------
@@ -320,7 +322,7 @@ def heightfield_gbuffer(views: int, width: int, height: int, seed: int, device="
             tbn[a:b] = _frame_from_normal(Nv).to(torch.float32)
             vw[a:b] = (-d / torch.linalg.vector_norm(d, dim=1, keepdim=True)).to(torch.float32)
         del d_all
-    return GBuffer(uv, tbn, vw)
+    return GBuffer(uv, tbn, vw, (views, height, width))
 
 
 def grad_out(N: int, C: int, seed: int, device="cpu") -> torch.Tensor:

@@ -49,6 +49,11 @@ def test_version_and_status_strings(rt):
     assert rt.LIB.rt_profile_kernel_name(0) == b"k_lookup_fwd"
 
 
+def _fr(rt, count, uv, tbn, view, image=(0, 0, 0)):
+    v, h, w = image
+    return rt.Fragments(count=count, views=v, height=h, width=w, uv=uv, tbn=tbn, view=view)
+
+
 def _desc(rt, **kw):
     d = dict(buckets_w=4, buckets_h=4, n=8, channels=4, format=0, layout=0, data=0x10000,
              scales=None)
@@ -84,7 +89,7 @@ def test_null_arguments(rt):
     h = ctypes.c_void_p()
     assert rt.LIB.rt_create_texture(None, None, ctypes.byref(h)) == 1
     assert rt.LIB.rt_create_texture(ctypes.byref(_desc(rt)), None, None) == 1
-    fr = rt.Fragments(10, 0x1000, 0x2000, 0x3000)
+    fr = _fr(rt, 10, 0x1000, 0x2000, 0x3000)
     assert rt.LIB.rt_lookup_fwd(None, ctypes.byref(fr), 0x4000, 0, None) == 1
     assert "texture handle" in rt.LIB.rt_last_error().decode()
     assert rt.LIB.rt_quantize(None, 1, 0x1000, None, None) == 1
@@ -107,13 +112,16 @@ def test_no_device_or_texture_handle(rt):
     assert st == 0 and h.value
     try:
         L = rt.LIB
-        good = rt.Fragments(10, 0x1000, 0x2000, 0x3000)
+        good = _fr(rt, 10, 0x1000, 0x2000, 0x3000)
         # fragments
-        for fr, text in ((rt.Fragments(-1, 0x1000, 0x2000, 0x3000), "< 0"),
-                         (rt.Fragments(10, None, 0x2000, 0x3000), "non-NULL"),
-                         (rt.Fragments(10, 0x1004, 0x2000, 0x3000), "8-byte"),
-                         (rt.Fragments(10, 0x1000, 0x2001, 0x3000), "4-byte"),
-                         (rt.Fragments(1 << 31, 0x1000, 0x2000, 0x3000), "2^31")):
+        for fr, text in ((_fr(rt, -1, 0x1000, 0x2000, 0x3000), "< 0"),
+                         (_fr(rt, 10, None, 0x2000, 0x3000), "non-NULL"),
+                         (_fr(rt, 10, 0x1004, 0x2000, 0x3000), "8-byte"),
+                         (_fr(rt, 10, 0x1000, 0x2001, 0x3000), "4-byte"),
+                         (_fr(rt, 1 << 31, 0x1000, 0x2000, 0x3000), "2^31"),
+                         (_fr(rt, 10, 0x1000, 0x2000, 0x3000, (1, 2, 0)), "all three"),
+                         (_fr(rt, 10, 0x1000, 0x2000, 0x3000, (1, -2, 5)), "all three"),
+                         (_fr(rt, 10, 0x1000, 0x2000, 0x3000, (1, 2, 6)), "does not match")):
             st = L.rt_lookup_fwd(h, ctypes.byref(fr), 0x4000, 0, None)
             assert st in (1, 2) and text in L.rt_last_error().decode()
         assert L.rt_lookup_fwd(h, ctypes.byref(good), None, 0, None) == 1
@@ -159,7 +167,7 @@ def test_backward_limits_are_reported(rt):
     assert st == 0
     try:
         assert rt.LIB.rt_lookup_bwd_workspace(h, 10, 0) == 0
-        fr = rt.Fragments(10, 0x1000, 0x2000, 0x3000)
+        fr = _fr(rt, 10, 0x1000, 0x2000, 0x3000)
         st = rt.LIB.rt_lookup_bwd(h, ctypes.byref(fr), 0x6000, 0x7000, None, None, 0x8000,
                                   1 << 30, 0, None)
         assert st == 2

@@ -1,6 +1,6 @@
 """Parity at the workloads' full sizes, in the launch configuration the
-benchmark times (the whole G-buffer in one launch), checked on sampled outputs
-the oracle computes one by one.
+benchmark times (the whole G-buffer in one launch, visited in pixel tiles),
+checked on sampled outputs the oracle computes one by one.
 
 * one 1920x1080 view over 1024x1024 buckets of 16x16 RGBA (the benchmark's
   workload): FP32 / BF16 / FP8 forwards, the quantiser's codes on sampled
@@ -100,9 +100,9 @@ def test_single_view_full_size(rt):
     c8, s8 = rt.quantize(master, "fp8")
     t16 = rt.Texture(c16, W, H, n, C, "bf16")
     t8 = rt.Texture(c8, W, H, n, C, "fp8", s8)
-    out32 = rt.lookup_fwd(master, gb.uv, gb.tbn, gb.view)
-    out16 = rt.lookup_fwd(t16, gb.uv, gb.tbn, gb.view)
-    out8 = rt.lookup_fwd(t8, gb.uv, gb.tbn, gb.view)
+    out32 = rt.lookup_fwd(master, gb.uv, gb.tbn, gb.view, image=gb.image)
+    out16 = rt.lookup_fwd(t16, gb.uv, gb.tbn, gb.view, image=gb.image)
+    out8 = rt.lookup_fwd(t8, gb.uv, gb.tbn, gb.view, image=gb.image)
     torch.cuda.synchronize()
 
     sel = _sample(N, 100000, 1)
@@ -137,7 +137,7 @@ def test_single_view_full_size(rt):
     win = (400, 300, 32, 32)
     near_ids = _window_fragments(rt, master, gb, win)
     gm, n_near = _mask_near_edges(gb, go, near_ids, W, H, n)
-    gt, gv, gu = rt.lookup_bwd(master, gb.uv, gb.tbn, gb.view, gm)
+    gt, gv, gu = rt.lookup_bwd(master, gb.uv, gb.tbn, gb.view, gm, image=gb.image)
     torch.cuda.synchronize()
     uvw, tbnw, vw, gw = _take((gb.uv, gb.tbn, gb.view, gm), near_ids)
     r = oracle.lookup_bwd(otex, uvw, tbnw, vw, gw, window=win, want_view=False,
@@ -167,8 +167,9 @@ def test_multi_view_full_size(rt):
     N = gb.count
     master = rt.Texture(tex, W, H, n, C)
     c8, s8 = rt.quantize(master, "fp8")
-    out32 = rt.lookup_fwd(master, gb.uv, gb.tbn, gb.view)
-    out8 = rt.lookup_fwd(rt.Texture(c8, W, H, n, C, "fp8", s8), gb.uv, gb.tbn, gb.view)
+    out32 = rt.lookup_fwd(master, gb.uv, gb.tbn, gb.view, image=gb.image)
+    out8 = rt.lookup_fwd(rt.Texture(c8, W, H, n, C, "fp8", s8), gb.uv, gb.tbn, gb.view,
+                         image=gb.image)
     idx_g, _ = rt.debug_indices(master, gb.uv, gb.tbn, gb.view)
     torch.cuda.synchronize()
     sel = _sample(N, 300000, 2)
@@ -200,8 +201,8 @@ def test_large_fp8_forward_backward(rt):
     master = rt.Texture(tex, W, H, n, C)
     c8, s8 = rt.quantize(master, "fp8")
     t8 = rt.Texture(c8, W, H, n, C, "fp8", s8)
-    out8 = rt.lookup_fwd(t8, gb.uv, gb.tbn, gb.view)
-    out32 = rt.lookup_fwd(master, gb.uv, gb.tbn, gb.view)
+    out8 = rt.lookup_fwd(t8, gb.uv, gb.tbn, gb.view, image=gb.image)
+    out32 = rt.lookup_fwd(master, gb.uv, gb.tbn, gb.view, image=gb.image)
     e2e = (out8 - out32).abs()
     e2e_max, e2e_mean = float(e2e.max()), float(e2e.mean())
     del e2e, out32
@@ -209,7 +210,8 @@ def test_large_fp8_forward_backward(rt):
     win = (1000, 1000, 16, 16)
     near_ids = _window_fragments(rt, t8, gb, win)
     gm, n_near = _mask_near_edges(gb, go, near_ids, W, H, n)
-    gt, gv, _ = rt.lookup_bwd(t8, gb.uv, gb.tbn, gb.view, gm, want_uv=False)
+    gt, gv, _ = rt.lookup_bwd(t8, gb.uv, gb.tbn, gb.view, gm, want_uv=False,
+                              image=gb.image)
     torch.cuda.synchronize()
 
     sel = _sample(N, 200000, 3)

@@ -396,3 +396,39 @@ def test_backward_identities(rt):
     # the lookup depends only on the direction of the view vector
     dots = np.abs(np.sum(host(gv) * host(gb_d.view), axis=1))
     assert np.max(dots) <= 1e-3 * max(1.0, np.abs(host(gv)).max())
+
+
+@pytest.mark.parametrize("mode", ["nearest", "bilinear"])
+def test_tiled_fragment_order(rt, mode):
+    """The tiling hint (3 views of 37 x 53 pixels: ragged in both directions
+    against the 32 x 8 tiles) changes only which thread handles a fragment:
+    forwards of every storage format and the whole backward are bit-identical
+    to the flat order, and the forward matches the oracle."""
+    W, H, n, C = 48, 40, 8, 4
+    gb = wl.plane_gbuffer(3, 53, 37, seed=21, device=DEV)
+    assert gb.image == (3, 37, 53) and gb.count == 3 * 37 * 53
+    tex = wl.iid_texture(W, H, n, C, seed=22, device=DEV)
+    master = rt.Texture(tex, W, H, n, C)
+    texs = {"f32": (master, oracle.Tex(host(tex), W, H, n, C))}
+    for fmt, ofmt in (("bf16", oracle.FMT_BF16), ("fp8", oracle.FMT_FP8_E4M3)):
+        c, s = rt.quantize(master, fmt)
+        texs[fmt] = (rt.Texture(c, W, H, n, C, fmt, s),
+                     oracle.Tex(host(c).view(np.uint16) if fmt == "bf16" else host(c), W, H, n, C,
+                                ofmt, None if s is None else host(s)))
+    uv, tbn, view = gb_host(gb)
+    keep = away_from_edges(uv, tbn, view, W, H, n, mode)
+    omode = oracle.MODE_NEAREST if mode == "nearest" else oracle.MODE_BILINEAR
+    for fmt, (t, ot) in texs.items():
+        flat = rt.lookup_fwd(t, gb.uv, gb.tbn, gb.view, mode)
+        tiled = rt.lookup_fwd(t, gb.uv, gb.tbn, gb.view, mode, image=gb.image)
+        _sync()
+        assert torch.equal(flat, tiled), fmt
+        check_fwd(host(tiled), oracle.lookup_fwd(ot, uv, tbn, view, omode), keep)
+    go = wl.grad_out(gb.count, C, seed=23, device=DEV)
+    a = rt.lookup_bwd(master, gb.uv, gb.tbn, gb.view, go, mode)
+    b = rt.lookup_bwd(master, gb.uv, gb.tbn, gb.view, go, mode, image=gb.image)
+    _sync()
+    for x, y in zip(a, b):
+        assert torch.equal(x, y)
+    with pytest.raises(rt.RadtexError):
+        rt.lookup_fwd(master, gb.uv, gb.tbn, gb.view, mode, image=(3, 37, 52))
