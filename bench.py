@@ -173,7 +173,14 @@ def main():
     taps = torch.cat([b * n * n + (y0 + dy) * n + (x0 + dx) for dy in (0, 1) for dx in (0, 1)])
     uniq_texels = int(torch.unique(taps).numel())
     uniq_buckets = int(torch.unique(b).numel())
-    del taps, idx
+    # the accumulation kernels split the buckets by record count: none or at
+    # most 64 (k_segacc), 65..2048 (k_segacc_big), more (the hot pass)
+    cnt = torch.bincount(b, minlength=W * H)
+    small = cnt <= 64
+    big = (cnt > 64) & (cnt <= 2048)
+    n_small, n_big = int(small.sum()), int(big.sum())
+    r_small, r_big = int(cnt[small].sum()), int(cnt[big].sum())
+    del taps, idx, cnt, small, big
     texel_bytes = uniq_texels * C * eb + (uniq_buckets * 4 if args.storage == "fp8" else 0)
     gbuf = N * 56
     alg = {
@@ -181,8 +188,13 @@ def main():
         "k_quant_fp8": E * 4 + E + W * H * 4,
         "k_lookup_fwd": gbuf + N * C * 4 + texel_bytes,
         "k_bwd_fragment": gbuf + N * C * 4 + texel_bytes + N * (12 + 8) + N * (4 + 8),
-        "k_segacc": E * 4 + N * (4 + 4 + 8 + C * 4) + W * H * 8,
+        # tiles written + records read (key, index, fractions, upstream
+        # gradient) + bucket ranges read (+ the list entries for the big pass)
+        "k_segacc": n_small * n * n * C * 4 + r_small * (4 + 4 + 8 + C * 4) + W * H * 8,
+        "k_segacc_big": n_big * n * n * C * 4 + r_big * (4 + 4 + 8 + C * 4) + n_big * (8 + 4),
     }
+    if n_big == 0:
+        del alg["k_segacc_big"]
     per_kernel = {}
     for name, (launches, total) in prof.items():
         avg = total / launches
