@@ -11,13 +11,15 @@ batch, as a fitting loop runs it:
     backward   dL/dtexture (dense, deterministic), dL/dview,
                dL/duv for i.i.d. N(0,1) upstream gradients   (rt_lookup_bwd)
 
-All inputs are resident in HBM before timing starts.  `value` is fragments
-(lookups) per second of the whole step.  The JSON line also carries per-format
+All inputs are resident in HBM before timing starts; the timed steps run
+without the per-kernel event timer, which gets a separate pass of the same
+steps (--graph: replays of the step captured in a HIP graph).  `value` is
+fragments (lookups) per second of the whole step.  The JSON line also carries per-format
 forward numbers (FP32 / BF16 / FP8 storage), the roofline of the dominant
 kernel measured with HIP events on the launch stream, and the FP64 CPU oracle
 timed on a bounded sample of the same workload.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--graph]
     python bench.py --calibrate-copy     (plain copy kernel for the PMC scale)
 """
 import argparse
@@ -71,6 +73,9 @@ def parse():
     ap.add_argument("--workload", default="c2")
     ap.add_argument("--storage", default="bf16", choices=["f32", "bf16", "fp8"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--graph", action="store_true",
+                    help="time replays of the step captured in a HIP graph (same kernels, no "
+                         "host launch gaps; measured equal to eager launches on this workload)")
     ap.add_argument("--calibrate-copy", action="store_true")
     ap.add_argument("--profile-steps", type=int, default=0,
                     help="run only this many steps (for rocprofv3) and print the line")
@@ -151,18 +156,33 @@ def main():
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    rt.profile_reset()
-    rt.profile_enable(True)
+    run = step
+    if args.graph:
+        # the step's 29 launches captured once and replayed: the same kernels
+        # on the same buffers, without the host's launch gaps
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            step()
+        graph.replay()
+        torch.cuda.synchronize()
+        run = graph.replay
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        step()
+        run()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    rt.profile_enable(False)
-    prof = rt.profile_read()
     ms_per_step = (t1 - t0) * 1e3 / args.steps
     value = N / (ms_per_step * 1e-3)
+    # per-kernel durations: the same number of steps launched eagerly, each
+    # kernel bracketed by HIP events on its launch stream
+    rt.profile_reset()
+    rt.profile_enable(True)
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    rt.profile_enable(False)
+    prof = rt.profile_read()
 
     # ---- algorithmic bytes per launch of each kernel ------------------------
     eb = {"f32": 4, "bf16": 2, "fp8": 1}[args.storage]
@@ -310,7 +330,8 @@ def main():
                    "step": "quantize(f32->%s) + forward + backward(grad_tex dense, grad_view, "
                            "grad_uv)" % args.storage, "mode": "nearest",
                    "fragment_order": ("%dx%dx%d images visited in 32x8 pixel tiles" % gb.image
-                                      if gb.image else "flat")},
+                                      if gb.image else "flat"),
+                   "launch": "HIP graph replay" if args.graph else "eager"},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "kernels": per_kernel,

@@ -423,6 +423,10 @@ __device__ __forceinline__ int load_record(const uint32_t* __restrict__ skeys,
 // this round; a cell that ends adds its four sums to its four texels in four
 // phases, so no two lanes touch one texel at once.
 template <int C>
+__device__ __forceinline__ void accumulate_tails(int cell, const float v[4 * C], bool tail, int n,
+                                                 float* tile);
+
+template <int C>
 __device__ __forceinline__ void accumulate_round(int cell, float v[4 * C], bool valid,
                                                  bool next_same, int n, float* tile) {
     const int lane = threadIdx.x & 63;
@@ -441,6 +445,12 @@ __device__ __forceinline__ void accumulate_round(int cell, float v[4 * C], bool 
         }
     }
     const bool tail = valid && !next_same;
+    accumulate_tails<C>(cell, v, tail, n, tile);
+}
+
+template <int C>
+__device__ __forceinline__ void accumulate_tails(int cell, const float v[4 * C], bool tail, int n,
+                                                 float* tile) {
     if (__ballot(tail) == 0ull) return;
     int y0 = 0, x0 = 0, x1 = 0, y1 = 0;
     if (tail) {
@@ -523,6 +533,7 @@ template <int C>
 struct RecWindow {
     int64_t start, end;  // records [start, end) are held; lane l holds start + l
     int cell;
+    uint32_t key;
     float fx, fy, wb;
     float g[C];
 };
@@ -537,6 +548,7 @@ __device__ __forceinline__ void load_window(const uint32_t* __restrict__ skeys,
     w.start = start;
     w.end = (start + 64 < R) ? start + 64 : R;
     w.cell = -2 - lane;
+    w.key = 0u;
     w.fx = w.fy = 0.f;
     w.wb = 1.f;
 #pragma unroll
@@ -544,7 +556,8 @@ __device__ __forceinline__ void load_window(const uint32_t* __restrict__ skeys,
     const int64_t i = start + lane;
     if (i < w.end) {
         const uint32_t rec = svals[i];
-        w.cell = (int)(skeys[i] & cell_mask);
+        w.key = skeys[i];
+        w.cell = (int)(w.key & cell_mask);
         int64_t frag;
         if constexpr (MODE == MODE_NEAREST) {
             frag = rec;
@@ -566,16 +579,14 @@ __device__ __forceinline__ void load_window(const uint32_t* __restrict__ skeys,
     }
 }
 
-// Reduce the records [a, e) of one bucket, all inside the window.  The tap
-// contributions are formed exactly as load_record forms them.
+// Segmented sums over the whole window, segments being runs of one sort key
+// (bucket and cell): each run's last lane ends with its run's sum, formed by
+// the same lanes and additions as a per-bucket scan would form it.
 template <int C>
-__device__ __forceinline__ void reduce_window(const RecWindow<C>& w, int64_t a, int64_t e, int n,
-                                              float* tile) {
+__device__ __forceinline__ void scan_window(const RecWindow<C>& w, float v[4 * C], bool& tail) {
     const int lane = threadIdx.x & 63;
     const int64_t i = w.start + lane;
-    const bool valid = i >= a && i < e;
-    const int cell = valid ? w.cell : -2 - lane;
-    float v[4 * C];
+    const bool valid = i < w.end;
     const float w00 = (1.f - w.fx) * (1.f - w.fy), w01 = w.fx * (1.f - w.fy);
     const float w10 = (1.f - w.fx) * w.fy, w11 = w.fx * w.fy;
 #pragma unroll
@@ -586,9 +597,19 @@ __device__ __forceinline__ void reduce_window(const RecWindow<C>& w, int64_t a, 
         v[2 * C + c] = w10 * gc;
         v[3 * C + c] = w11 * gc;
     }
-    const int next_cell = __shfl_down(cell, 1, 64);
-    const bool next_same = valid && lane < 63 && i + 1 < e && next_cell == cell;
-    accumulate_round<C>(cell, v, valid, next_same, n, tile);
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t ok = __shfl_up(w.key, o, 64);
+        const bool same = valid && lane >= o && ok == w.key;
+        if (__ballot(same) == 0ull) break;
+#pragma unroll
+        for (int q = 0; q < 4 * C; q++) {
+            const float ov = __shfl_up(v[q], o, 64);
+            if (same) v[q] += ov;
+        }
+    }
+    const uint32_t nk = __shfl_down(w.key, 1, 64);
+    tail = valid && (lane == 63 || i + 1 >= w.end || nk != w.key);
 }
 
 __device__ __forceinline__ void tile_zero(float* tile, int te) {
@@ -676,6 +697,8 @@ __global__ __launch_bounds__(256) void k_segacc(const uint32_t* __restrict__ ske
         }
         RecWindow<C> win;
         win.start = win.end = -1;
+        float v[4 * C];
+        bool tail = false;
         for (int k = 0; k < nb; k++) {
             // wave-uniform bucket range (scalar registers, scalar loop control)
             const int rx = __builtin_amdgcn_readfirstlane(__shfl(rl.x, k, 64));
@@ -687,10 +710,13 @@ __global__ __launch_bounds__(256) void k_segacc(const uint32_t* __restrict__ ske
                 continue;
             }
             if (cnt > 64) continue;  // listed above, or hot
-            if (!(rx >= win.start && ry <= win.end))
+            if (!(rx >= win.start && ry <= win.end)) {
                 load_window<C, MODE>(skeys, svals, wrec, grad_out, rx, R, cell_mask, win);
+                scan_window<C>(win, v, tail);
+            }
             tile_zero(tile, te);
-            reduce_window<C>(win, rx, ry, n, tile);
+            const int64_t i = win.start + lane;
+            accumulate_tails<C>(win.cell, v, tail && i >= rx && i < ry, n, tile);
             tile_store(tile, dst, te);
         }
     }

@@ -432,3 +432,41 @@ def test_tiled_fragment_order(rt, mode):
         assert torch.equal(x, y)
     with pytest.raises(rt.RadtexError):
         rt.lookup_fwd(master, gb.uv, gb.tbn, gb.view, mode, image=(3, 37, 52))
+
+
+def test_graph_replay(rt):
+    """A captured HIP graph of one whole step (quantise, forward, backward)
+    replays bit-identically to the eager step, replay after replay, with the
+    program's own eager work and synchronisations in between."""
+    W, H, n, C = 32, 24, 8, 4
+    gb = wl.plane_gbuffer(2, 61, 29, seed=31, device=DEV)
+    tex = wl.smooth_texture(W, H, n, C, seed=32, device=DEV)
+    master = rt.Texture(tex, W, H, n, C)
+    codes = torch.empty((H, W, n, n, C), dtype=torch.int16, device=DEV)
+    tq = rt.Texture(codes, W, H, n, C, "bf16")
+    go = wl.grad_out(gb.count, C, seed=33, device=DEV)
+    out = torch.empty((gb.count, C), device=DEV)
+    gt = torch.empty((H, W, n, n, C), device=DEV)
+    ws = torch.empty(rt.bwd_workspace_bytes(tq, gb.count), dtype=torch.uint8, device=DEV)
+
+    def step():
+        rt._check(rt.LIB.rt_quantize(master.handle, rt.FORMATS["bf16"], rt._ptr(codes), None,
+                                     rt._stream(DEV)))
+        rt.lookup_fwd(tq, gb.uv, gb.tbn, gb.view, out=out, image=gb.image)
+        return rt.lookup_bwd(tq, gb.uv, gb.tbn, gb.view, go, workspace=ws, grad_tex=gt,
+                             image=gb.image)
+
+    _, gv, gu = step()
+    _sync()
+    ref = [codes.clone(), out.clone(), gt.clone(), gv.clone(), gu.clone()]
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        _, gv_g, gu_g = step()
+    for r in range(3):
+        for t in (codes, out, gt, gv_g, gu_g):
+            t.fill_(float("nan") if t.dtype.is_floating_point else -1)  # eager work between
+        _sync()
+        graph.replay()
+        _sync()
+        for a, b in zip(ref, (codes, out, gt, gv_g, gu_g)):
+            assert torch.equal(a, b), r
