@@ -6,11 +6,12 @@
 //                       clamp, Eq. 3, Eq. 1b and the normalisation) and
 //                       dL/duv, and emit one record per (fragment, bucket):
 //                       key = bucket << cell_bits | (y0 n + x0).
-//   2. radix sort       stable LSD sort of (key, record) by 8-bit digits:
-//                       per-tile digit histograms, one exclusive scan over
-//                       (digit, tile), stable in-tile ranking with wave ballots.
-//                       Equal keys keep record order, so the sorted sequence
-//                       depends only on the inputs.
+//   2. radix sort       stable LSD sort of (key, record) by digits of up to
+//                       10 bits (9 for large inputs): per-tile digit
+//                       histograms, one exclusive scan over (digit, tile),
+//                       stable in-tile ranking with wave ballots.  Equal keys
+//                       keep record order, so the sorted sequence depends only
+//                       on the inputs.
 //   3. k_bucket_ranges  [start, end) of every bucket in the sorted records.
 //   4. k_segacc         one wavefront per bucket (pass 1): the bucket's records
 //                       are reduced per cell by a segmented scan across lanes
@@ -36,6 +37,14 @@ constexpr int SORT_THREADS = 256;
 constexpr int SORT_IPT = 16;
 constexpr int SORT_TILE = SORT_THREADS * SORT_IPT;  // 4096
 constexpr int SCAN_TILE = 4096;
+
+// orders one wavefront's LDS accesses before and after it
+__device__ __forceinline__ void wave_sync_lds() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 
 // ---------------------------------------------------------------------------
 // 1. per-fragment backward
@@ -181,22 +190,31 @@ __global__ __launch_bounds__(256) void k_bwd_fragment(
 // 2. stable LSD radix sort of (key, record index), 8-bit digits
 // ---------------------------------------------------------------------------
 
+// Digit counts of one tile of SORT_TILE keys: hist[d * tiles + tile].
+template <int D>
 __global__ __launch_bounds__(SORT_THREADS) void k_radix_hist(const uint32_t* __restrict__ keys,
                                                              int64_t R, int shift,
                                                              uint32_t* __restrict__ hist,
                                                              int64_t tiles) {
-    __shared__ uint32_t cnt[256];
+    constexpr int B = 1 << D;
+    __shared__ uint32_t cnt[B];
     const int t = threadIdx.x;
-    cnt[t] = 0;
+    for (int d = t; d < B; d += SORT_THREADS) cnt[d] = 0;
     __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * SORT_TILE;
-#pragma unroll 4
+    uint32_t k[SORT_IPT];
+#pragma unroll
     for (int r = 0; r < SORT_IPT; r++) {
-        int64_t i = base + r * SORT_THREADS + t;
-        if (i < R) atomicAdd(&cnt[(keys[i] >> shift) & 255u], 1u);
+        const int64_t i = base + r * SORT_THREADS + t;
+        k[r] = i < R ? keys[i] : 0u;
+    }
+#pragma unroll
+    for (int r = 0; r < SORT_IPT; r++) {
+        const int64_t i = base + r * SORT_THREADS + t;
+        if (i < R) atomicAdd(&cnt[(k[r] >> shift) & (B - 1)], 1u);
     }
     __syncthreads();
-    hist[(int64_t)t * tiles + blockIdx.x] = cnt[t];
+    for (int d = t; d < B; d += SORT_THREADS) hist[(int64_t)d * tiles + blockIdx.x] = cnt[d];
 }
 
 // exclusive prefix of v over the 256 threads of the block; *total receives the sum
@@ -278,70 +296,108 @@ __global__ __launch_bounds__(256) void k_scan_down(const uint32_t* __restrict__ 
     }
 }
 
-// Stable scatter of one radix pass.  Items of a tile are taken in rounds of
-// 256 in index order; within a wave, lanes holding the same digit are found
-// with one ballot per digit bit, and ranks follow lane order; across the
-// block's waves and rounds, ranks follow wave order then round order.  The
-// tile is first ordered in LDS, then written out so that each digit's run is
-// contiguous in memory.
+// Stable scatter of one radix pass.  Wave w ranks the contiguous quarter
+// [w SORT_TILE/4, (w+1) SORT_TILE/4) of the tile in 16 rounds of 64 records:
+// lanes holding the same digit are found with one ballot per digit bit, a
+// record's rank is the number of such lanes below it plus the wave's running
+// count of that digit (kept in LDS by the digit's lowest lane).  The tile's
+// order within a digit is therefore wave, round, lane: index order.  The tile
+// is ordered in LDS, then written so that each digit's run is contiguous in
+// memory.
+template <int D>
 __global__ __launch_bounds__(SORT_THREADS) void k_radix_scatter(
     const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in,
     uint32_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out, int64_t R, int shift,
-    const uint32_t* __restrict__ hist, const uint32_t* __restrict__ hoff, int64_t tiles) {
+    const uint32_t* __restrict__ hoff, int64_t tiles) {
+    constexpr int B = 1 << D;
+    constexpr int DPT = B / SORT_THREADS;  // digits per thread in the digit phase
+    constexpr int QUARTER = SORT_TILE / 4;
     __shared__ uint32_t skeys[SORT_TILE];
     __shared__ uint32_t svals[SORT_TILE];
-    __shared__ uint32_t dstart[256], run[256], goff[256];
-    __shared__ uint32_t wcnt[4][256];
+    __shared__ uint32_t wcnt[4][B];  // running counts, then exclusive prefixes over waves
+    __shared__ uint32_t dstart[B], goff[B];
     __shared__ uint32_t wsum[4];
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     const int64_t tile = blockIdx.x;
     const int64_t base = tile * SORT_TILE;
-    const uint32_t mycount = hist[(int64_t)t * tiles + tile];
-    dstart[t] = block_exclusive(mycount, wsum, nullptr);
-    goff[t] = hoff[(int64_t)t * tiles + tile];
-    run[t] = 0;
-    wcnt[0][t] = wcnt[1][t] = wcnt[2][t] = wcnt[3][t] = 0;
+    for (int d = t; d < B; d += SORT_THREADS) {
+        wcnt[0][d] = wcnt[1][d] = wcnt[2][d] = wcnt[3][d] = 0;
+        goff[d] = hoff[(int64_t)d * tiles + tile];
+    }
+    uint32_t k[SORT_IPT], v[SORT_IPT], loc[SORT_IPT];
+    const int64_t wbase = base + w * QUARTER;
+#pragma unroll
+    for (int r = 0; r < SORT_IPT; r++) {
+        const int64_t i = wbase + r * 64 + lane;
+        k[r] = 0u;
+        v[r] = 0u;
+        if (i < R) {
+            k[r] = keys_in[i];
+            v[r] = vals_in ? vals_in[i] : (uint32_t)i;
+        }
+    }
     __syncthreads();
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+#pragma unroll
     for (int r = 0; r < SORT_IPT; r++) {
-        const int64_t i = base + r * SORT_THREADS + t;
+        const int64_t i = wbase + r * 64 + lane;
         const bool valid = i < R;
-        uint32_t k = 0, v = 0;
-        if (valid) {
-            k = keys_in[i];
-            v = vals_in ? vals_in[i] : (uint32_t)i;
-        }
-        const uint32_t dg = (k >> shift) & 255u;
+        const uint32_t dg = (k[r] >> shift) & (B - 1);
         uint64_t peers = __ballot(valid);
 #pragma unroll
-        for (int bit = 0; bit < 8; bit++) {
+        for (int bit = 0; bit < D; bit++) {
             const bool on = (dg >> bit) & 1u;
             const uint64_t m = __ballot(on);
             peers &= on ? m : ~m;
         }
         const uint32_t rank = (uint32_t)__popcll(peers & lt_mask);
-        if (valid && rank == 0) wcnt[w][dg] = (uint32_t)__popcll(peers);
-        __syncthreads();
-        if (valid) {
-            uint32_t off = run[dg] + rank;
-            for (int q = 0; q < w; q++) off += wcnt[q][dg];
-            const uint32_t pos = dstart[dg] + off;
-            skeys[pos] = k;
-            svals[pos] = v;
-        }
-        __syncthreads();
-        run[t] += wcnt[0][t] + wcnt[1][t] + wcnt[2][t] + wcnt[3][t];
-        wcnt[0][t] = wcnt[1][t] = wcnt[2][t] = wcnt[3][t] = 0;
-        __syncthreads();
+        const uint32_t before = valid ? wcnt[w][dg] : 0u;
+        loc[r] = before + rank;
+        wave_sync_lds();
+        if (valid && rank == 0) wcnt[w][dg] = before + (uint32_t)__popcll(peers);
+        wave_sync_lds();
     }
+    __syncthreads();
+    // digits: prefixes over the waves, and the tile's exclusive scan over digits
+    uint32_t tot[DPT], mine = 0;
+#pragma unroll
+    for (int j = 0; j < DPT; j++) {
+        const int d = t * DPT + j;
+        const uint32_t c0 = wcnt[0][d], c1 = wcnt[1][d], c2 = wcnt[2][d], c3 = wcnt[3][d];
+        wcnt[0][d] = 0;
+        wcnt[1][d] = c0;
+        wcnt[2][d] = c0 + c1;
+        wcnt[3][d] = c0 + c1 + c2;
+        tot[j] = c0 + c1 + c2 + c3;
+        mine += tot[j];
+    }
+    uint32_t run = block_exclusive(mine, wsum, nullptr);
+#pragma unroll
+    for (int j = 0; j < DPT; j++) {
+        dstart[t * DPT + j] = run;
+        run += tot[j];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < SORT_IPT; r++) {
+        const int64_t i = wbase + r * 64 + lane;
+        if (i < R) {
+            const uint32_t dg = (k[r] >> shift) & (B - 1);
+            const uint32_t pos = dstart[dg] + wcnt[w][dg] + loc[r];
+            skeys[pos] = k[r];
+            svals[pos] = v[r];
+        }
+    }
+    __syncthreads();
     const int64_t nvalid = (R - base) < SORT_TILE ? (R - base) : SORT_TILE;
+#pragma unroll
     for (int r = 0; r < SORT_IPT; r++) {
         const int p = r * SORT_THREADS + t;
         if (p < nvalid) {
-            const uint32_t k = skeys[p];
-            const uint32_t dg = (k >> shift) & 255u;
+            const uint32_t kk = skeys[p];
+            const uint32_t dg = (kk >> shift) & (B - 1);
             const uint32_t dst = goff[dg] + ((uint32_t)p - dstart[dg]);
-            keys_out[dst] = k;
+            keys_out[dst] = kk;
             vals_out[dst] = svals[p];
         }
     }
@@ -369,12 +425,6 @@ __global__ __launch_bounds__(256) void k_bucket_ranges(const uint32_t* __restric
 // ---------------------------------------------------------------------------
 // 4./5. segmented reduction of a bucket's records into its gradient tile
 // ---------------------------------------------------------------------------
-
-__device__ __forceinline__ void wave_sync_lds() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
 
 // The four tap contributions of sorted record i: v = (w00, w01, w10, w11) x g
 // times the bucket weight (1 in nearest mode); returns the record's cell.
@@ -853,9 +903,23 @@ bool plan_backward(int W, int H, int n, int C, int64_t N, int mode, BwdPlan* p) 
     p->records = R;
     p->key_bits = bucket_bits + cell_bits;
     p->cell_bits = cell_bits;
-    p->passes = p->key_bits == 0 ? 1 : (p->key_bits + 7) / 8;
+    // as few passes as digits of at most 10 bits allow (9 bits beyond 4M
+    // records, where the histograms, their scan and the scatter's LDS, which
+    // grow as 2^D, cost more than a pass saves), the bits spread evenly
+    const int kb = std::max(1, p->key_bits);
+    const int maxd = R <= (1ll << 22) ? 10 : 9;
+    p->passes = (kb + maxd - 1) / maxd;
+    int at = 0, widest = 0;
+    for (int q = 0; q < 4; q++) {
+        const int bits = q < p->passes ? kb / p->passes + (q < kb % p->passes ? 1 : 0) : 0;
+        p->digit_bits[q] = bits;
+        p->digit_shift[q] = at;
+        at += bits;
+        widest = std::max(widest, bits);
+    }
+    p->bins = 1 << std::max(8, widest);
     p->tiles = (R + SORT_TILE - 1) / SORT_TILE;
-    p->scan_len = 256 * p->tiles;
+    p->scan_len = (int64_t)p->bins * p->tiles;
     p->scan_blocks = (p->scan_len + SCAN_TILE - 1) / SCAN_TILE;
     p->chunks = (R + PIECE - 1) / PIECE;
     p->tile_elems = (int64_t)n * n * C;
@@ -1005,15 +1069,20 @@ hipError_t launch_backward(const TexView& t, int fmt, int mode, const float* uv,
         for (int pass = 0; pass < plan.passes; pass++) {
             uint32_t* kout = (pass & 1) ? keys0 : keys1;
             uint32_t* vout = (pass & 1) ? vals0 : vals1;
-            const int shift = 8 * pass;
+            const int shift = plan.digit_shift[pass];
+            const int D = std::max(8, plan.digit_bits[pass]);
+            const int64_t len = ((int64_t)1 << D) * plan.tiles;
+            const dim3 grid((uint32_t)plan.tiles), block(SORT_THREADS);
             prof_begin(K_RADIX_HIST, s);
-            hipLaunchKernelGGL(k_radix_hist, dim3((uint32_t)plan.tiles), dim3(SORT_THREADS), 0, s,
-                               kin, R, shift, hist, plan.tiles);
+            if (D == 8) hipLaunchKernelGGL(k_radix_hist<8>, grid, block, 0, s, kin, R, shift, hist, plan.tiles);
+            else if (D == 9) hipLaunchKernelGGL(k_radix_hist<9>, grid, block, 0, s, kin, R, shift, hist, plan.tiles);
+            else hipLaunchKernelGGL(k_radix_hist<10>, grid, block, 0, s, kin, R, shift, hist, plan.tiles);
             prof_end(K_RADIX_HIST, s);
-            launch_scan(hist, hoff, scanp, plan.scan_len, plan.scan_blocks, s);
+            launch_scan(hist, hoff, scanp, len, (len + SCAN_TILE - 1) / SCAN_TILE, s);
             prof_begin(K_RADIX_SCATTER, s);
-            hipLaunchKernelGGL(k_radix_scatter, dim3((uint32_t)plan.tiles), dim3(SORT_THREADS), 0,
-                               s, kin, vin, kout, vout, R, shift, hist, hoff, plan.tiles);
+            if (D == 8) hipLaunchKernelGGL(k_radix_scatter<8>, grid, block, 0, s, kin, vin, kout, vout, R, shift, hoff, plan.tiles);
+            else if (D == 9) hipLaunchKernelGGL(k_radix_scatter<9>, grid, block, 0, s, kin, vin, kout, vout, R, shift, hoff, plan.tiles);
+            else hipLaunchKernelGGL(k_radix_scatter<10>, grid, block, 0, s, kin, vin, kout, vout, R, shift, hoff, plan.tiles);
             prof_end(K_RADIX_SCATTER, s);
             kin = kout;
             vin = vout;

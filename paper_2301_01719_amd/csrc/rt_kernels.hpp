@@ -50,9 +50,12 @@ struct BwdPlan {
     int64_t records;      // N (nearest) or 4N (bilinear-bucket)
     int key_bits;         // bucket bits + cell bits
     int cell_bits;
-    int passes;           // radix passes of 8 bits
+    int passes;           // radix passes, digits of at most 10 (9) bits
+    int digit_bits[4];    // bits of each pass's digit (balanced)
+    int digit_shift[4];   // position of each pass's digit in the key
+    int bins;             // 2^D of the widest pass's kernel (D = 8, 9 or 10)
     int64_t tiles;        // radix tiles
-    int64_t scan_len;     // 256 * tiles
+    int64_t scan_len;     // bins * tiles
     int64_t scan_blocks;  // partial sums of the scan
     int64_t chunks;       // fixed chunks of the sorted records (hot buckets)
     int64_t tile_elems;   // n*n*C
