@@ -51,6 +51,9 @@ def _load():
     lib.orc_map_one.argtypes = [P, P, i32, P]
     lib.orc_lookup_bwd.argtypes = [i64, P, P, P, P, i32, i32, i32, i32, i32, P, P, i32,
                                    P, P, P, i32, i32, i32, i32, P, P, P, P]
+    lib.orc_bake_directions.argtypes = [i32, P, P]
+    lib.orc_bake_environment.argtypes = [i32, i32, i32, i32, P, P, i32, P, i32, i32, i32, i32, P]
+    lib.orc_env_eval.argtypes = [P, i32, P, i32, P, P]
     _lib = lib
     return lib
 
@@ -255,3 +258,48 @@ def lookup_bwd(tex: Tex, uv, tbn, view, g, mode=MODE_NEAREST, want_tex=True, win
                            _p(su))
     return {"grad_tex": gt, "abs_tex": at, "absg_tex": ag, "grad_view": gv, "grad_uv": gu,
             "scale_view": sv, "scale_uv": su}
+
+
+# --- the bake ----------------------------------------------------------------
+
+def bake_directions(n):
+    """(inc, refl) [n, n, 3] float64: per sample centre of a bucket, the
+    incidence I (Eqs. (4a), (2c)) and the reflection vector R (Eqs. (4a),
+    (4b)) in orthogonal texture space; [y, x] indexing."""
+    inc = np.empty((n, n, 3), np.float64)
+    refl = np.empty((n, n, 3), np.float64)
+    _load().orc_bake_directions(int(n), _p(inc), _p(refl))
+    return inc, refl
+
+
+def _lobes(lobes, ambient):
+    lobes = _c(lobes, np.float32).reshape(-1, 8)
+    ambient = _c(ambient, np.float32).reshape(4)
+    return lobes, ambient
+
+
+def bake_environment(W, H, n, C, lobes, ambient, frames=None, window=None):
+    """Baked texels [bh, bw, n, n, C] float64 of the bucket window (default:
+    all): env(normalize(M^T R)) per sample centre.  lobes [K, 8] float32 (axis
+    xyz, sharpness, amplitude per channel 0..3), ambient [4]; frames [H, W, 3,
+    3] float32 rows T, B, N, or None for the identity."""
+    lobes, ambient = _lobes(lobes, ambient)
+    if frames is not None:
+        frames = _c(frames, np.float32).reshape(H * W * 9)
+    bi0, bj0, bw, bh = window if window is not None else (0, 0, W, H)
+    out = np.empty((bh, bw, n, n, C), np.float64)
+    _load().orc_bake_environment(int(W), int(H), int(n), int(C), _p(frames), _p(lobes),
+                                 lobes.shape[0], _p(ambient), int(bi0), int(bj0), int(bw),
+                                 int(bh), _p(out))
+    return out
+
+
+def env_eval(lobes, ambient, C, d):
+    """env_c at directions d [..., 3] (normalised inside): [..., C] float64."""
+    lobes, ambient = _lobes(lobes, ambient)
+    d = _c(d, np.float64).reshape(-1, 3)
+    out = np.empty((d.shape[0], C), np.float64)
+    for r in range(d.shape[0]):
+        _load().orc_env_eval(_p(lobes), lobes.shape[0], _p(ambient), int(C),
+                             _p(d[r]), _p(out[r]))
+    return out

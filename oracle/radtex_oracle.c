@@ -23,6 +23,10 @@
  *   filtered fetch            bilinear inside the bucket (the clamp only has a
  *                             purpose for a filtered fetch)
  *   inverse mappings          Eqs. (2a)-(2c), (4a), (4b)
+ *   bake                      the reflection vector of every sample centre
+ *                             (Eqs. (4a), (4b)) carried to scene coordinates
+ *                             by the bucket frame; an analytic environment
+ *                             stands in for the ray-traced radiance
  *
  * Readings of points the paper leaves open (texel-centre convention, UV wrap,
  * axis orientation, the A = 0 case of Eq. (3), the storage formats) are listed
@@ -811,4 +815,104 @@ void orc_lookup_bwd(int64_t N, const float *uv, const float *tbn, const float *v
             }
         }
     }
+}
+
+/* ------------------------------------------------------------------------- */
+/* The bake: filling a radiance texture from scene radiance (Sec. 2.1, after */
+/* Eq. (4b): the reflection vector is what ray-traced data is sampled along). */
+/* ------------------------------------------------------------------------- */
+
+/* The centre of sample (x, y) of an n x n bucket in B coordinates, by the
+ * texel-centre reading used throughout: B = ((2x+1)/n - 1, (2y+1)/n - 1). */
+static void texel_centre(int x, int y, int n, double B[2])
+{
+    B[0] = (2.0 * x + 1.0) / n - 1.0;
+    B[1] = (2.0 * y + 1.0) / n - 1.0;
+}
+
+/* Directions of the sample centres of one bucket in orthogonal texture space:
+ * inc[(y n + x) 3 + k] the incidence I that the lookup maps onto the sample
+ * (Eq. (4a) then Eq. (2c)), refl[...] the reflection vector R of Eq. (4b)
+ * (Eq. (4a) then Eq. (4b)).  Either may be NULL. */
+void orc_bake_directions(int n, double *inc, double *refl)
+{
+    for (int y = 0; y < n; y++) {
+        for (int x = 0; x < n; x++) {
+            double B[2], A[2];
+            texel_centre(x, y, n, B);
+            orc_unsquare(B, A);
+            if (inc)
+                orc_inverse_equisolid_tangent(A, inc + 3 * (y * n + x));
+            if (refl)
+                orc_reflection(A, refl + 3 * (y * n + x));
+        }
+    }
+}
+
+/* The analytic stand-in for ray-traced scene radiance: per channel c,
+ *   env_c(d) = ambient_c + sum_k a_{k,c} exp(lambda_k (mu_k . d - 1))
+ * for a unit direction d (spherical Gaussian lobes; mu_k is the lobe's axis
+ * normalised, lambda_k >= 0 its sharpness).  lobes[k] holds 8 floats: axis
+ * x, y, z, sharpness, amplitudes for channels 0..3. */
+static double env_eval(const float *lobes, int K, const float *ambient, int c, const double d[3])
+{
+    double v = ambient[c];
+    for (int k = 0; k < K; k++) {
+        const float *L = lobes + 8 * k;
+        double mx = L[0], my = L[1], mz = L[2];
+        double mn = sqrt(mx * mx + my * my + mz * mz);
+        double dot = (mx * d[0] + my * d[1] + mz * d[2]) / mn;
+        v += (double)L[4 + c] * exp((double)L[3] * (dot - 1.0));
+    }
+    return v;
+}
+
+/* Bake of the buckets in the window [bi0, bi0+bw) x [bj0, bj0+bh) of a W x H
+ * matrix: out[(((j - bj0) bw + (i - bi0)) n + y) n + x][c] =
+ *   env_c(normalize(M^T R(x, y))),
+ * where R is the reflection vector of the sample centre (Eq. (4b)) in the
+ * bucket's orthogonal texture space and M = [T;B;N] the bucket's frame
+ * (frames [H][W][9], rows T, B, N; NULL: the identity), so M^T R is R in
+ * the scene's coordinates. */
+void orc_bake_environment(int W, int H, int n, int C, const float *frames, const float *lobes,
+                          int K, const float *ambient, int bi0, int bj0, int bw, int bh,
+                          double *out)
+{
+    (void)W;
+    (void)H;
+    double *R = (double *)malloc(sizeof(double) * 3 * n * n);
+    if (!R)
+        return;
+    orc_bake_directions(n, NULL, R);
+#pragma omp parallel for schedule(static)
+    for (int64_t b = 0; b < (int64_t)bw * bh; b++) {
+        int i = bi0 + (int)(b % bw), j = bj0 + (int)(b / bw);
+        double M[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
+        if (frames)
+            for (int k = 0; k < 9; k++)
+                M[k] = frames[((int64_t)j * W + i) * 9 + k];
+        for (int s = 0; s < n * n; s++) {
+            const double *r = R + 3 * s;
+            double d[3];
+            for (int k = 0; k < 3; k++) /* (M^T r)_k = sum_m M[m][k] r_m */
+                d[k] = M[0 * 3 + k] * r[0] + M[1 * 3 + k] * r[1] + M[2 * 3 + k] * r[2];
+            double len = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+            for (int k = 0; k < 3; k++)
+                d[k] /= len;
+            for (int c = 0; c < C; c++)
+                out[(b * n * n + s) * C + c] = env_eval(lobes, K, ambient, c, d);
+        }
+    }
+    free(R);
+}
+
+/* env_c at one direction (normalised here), for the tests' analytic
+ * references. */
+void orc_env_eval(const float *lobes, int K, const float *ambient, int C, const double d_in[3],
+                  double *out)
+{
+    double len = sqrt(d_in[0] * d_in[0] + d_in[1] * d_in[1] + d_in[2] * d_in[2]);
+    double d[3] = {d_in[0] / len, d_in[1] / len, d_in[2] / len};
+    for (int c = 0; c < C; c++)
+        out[c] = env_eval(lobes, K, ambient, c, d);
 }

@@ -616,3 +616,112 @@ def test_grad_tex_window_matches_full():
     full = oracle.lookup_bwd(tex, uv, tbn, V, g)["grad_tex"]
     win = oracle.lookup_bwd(tex, uv, tbn, V, g, window=(2, 1, 3, 2))["grad_tex"]
     np.testing.assert_array_equal(win, full[1:3, 2:5])
+
+
+# --------------------------------------------------------------------------
+# The bake (Sec. 2.1 after Eq. (4b)): reflection vectors of the sample
+# centres, carried to scene coordinates, sample an analytic environment
+# --------------------------------------------------------------------------
+
+_LOBES = np.array([[0.3, -0.2, 1.0, 3.0, 0.8, 0.3, 0.1, 0.5],
+                   [1.0, 0.5, 0.4, 2.0, 0.1, 0.6, 0.2, 0.0],
+                   [-0.6, 0.9, 0.2, 1.5, 0.3, 0.1, 0.7, 0.9]], np.float32)
+_AMBIENT = np.array([0.05, 0.1, 0.02, 0.3], np.float32)
+
+
+@pytest.mark.parametrize("n", [1, 2, 5, 8, 16])
+def test_bake_directions_round_trip_through_the_lookup(n):
+    # the incidence of every sample centre maps through Eqs. (1b), (3) and the
+    # texel coordinate back onto that sample, and R is its mirror image about
+    # the normal by the textbook reflection 2 (N.I) N - I
+    inc, refl = oracle.bake_directions(n)
+    N = np.array([0.0, 0.0, 1.0])
+    for y in range(n):
+        for x in range(n):
+            s = oracle.map_one(np.eye(3), inc[y, x], n)[4:6]
+            np.testing.assert_allclose(s, [x, y], atol=1e-9)
+            I = inc[y, x]
+            np.testing.assert_allclose(refl[y, x], 2 * np.dot(N, I) * N - I, atol=1e-15)
+    np.testing.assert_allclose(np.linalg.norm(refl, axis=2), 1.0, atol=1e-14)
+    assert np.all(refl[..., 2] >= 0)
+
+
+def test_bake_constant_environment_is_constant():
+    flat = _LOBES.copy()
+    flat[:, 3] = 0.0  # sharpness 0: every lobe is its amplitude everywhere
+    t = oracle.bake_environment(3, 2, 7, 4, flat, _AMBIENT)
+    want = _AMBIENT.astype(np.float64) + flat[:, 4:8].astype(np.float64).sum(0)
+    np.testing.assert_allclose(t, np.broadcast_to(want, t.shape), atol=1e-15)
+
+
+@pytest.mark.parametrize("n", [6, 7])
+def test_bake_lobe_on_the_normal_has_the_bucket_symmetry(n):
+    # a lobe around N seen through the identity frame depends only on the
+    # polar angle, so the baked bucket has the D4 symmetry of the square map
+    lob = np.array([[0, 0, 1, 2.5, 1.0, 0.5, 0.25, 0.125]], np.float32)
+    t = oracle.bake_environment(1, 1, n, 4, lob, _AMBIENT)[0, 0]
+    np.testing.assert_allclose(t, t[:, ::-1], atol=1e-14)
+    np.testing.assert_allclose(t, t[::-1, :], atol=1e-14)
+    np.testing.assert_allclose(t, t.transpose(1, 0, 2), atol=1e-14)
+    # and it grows toward the centre (the lobe's peak is on the normal)
+    r = np.linalg.norm(np.indices((n, n)).transpose(1, 2, 0) - (n - 1) / 2, axis=2)
+    order = np.argsort(r, axis=None)
+    assert np.all(np.diff(t[..., 0].reshape(-1)[order]) <= 1e-12)
+
+
+def test_bake_frame_equivariance():
+    # sampling along M^T R with a lobe axis mu equals sampling along R with
+    # the axis M mu: a frame rotates the scene, not the bucket
+    rng = np.random.default_rng(5)
+    W, H, n = 3, 2, 6
+    frames = np.stack([_rand_rot(rng).T for _ in range(W * H)]).reshape(H, W, 3, 3)
+    t = oracle.bake_environment(W, H, n, 4, _LOBES, _AMBIENT, frames=frames.astype(np.float32))
+    for j in range(H):
+        for i in range(W):
+            M = frames[j, i].astype(np.float32).astype(np.float64)
+            lob = _LOBES.astype(np.float64).copy()
+            ax = lob[:, :3] / np.linalg.norm(lob[:, :3], axis=1, keepdims=True)
+            lob[:, :3] = ax @ M.T
+            ti = oracle.bake_environment(1, 1, n, 4, lob.astype(np.float32), _AMBIENT)[0, 0]
+            np.testing.assert_allclose(t[j, i], ti, atol=2e-6)
+
+
+def test_bake_centre_sample_sees_the_normal():
+    # an odd bucket's centre sample has B = 0, so A = 0 and R = N (Eqs. 4a,
+    # 4b): it holds the environment along the frame's normal
+    rng = np.random.default_rng(6)
+    M = _rand_rot(rng).T.astype(np.float32)
+    n = 9
+    t = oracle.bake_environment(1, 1, n, 4, _LOBES, _AMBIENT, frames=M.reshape(1, 1, 3, 3))
+    Nw = M.astype(np.float64)[2]
+    np.testing.assert_allclose(t[0, 0, n // 2, n // 2], oracle.env_eval(_LOBES, _AMBIENT, 4, Nw)[0],
+                               atol=1e-14)
+
+
+def _mirror_error(n, V):
+    tex = oracle.bake_environment(1, 1, n, 4, _LOBES, _AMBIENT)
+    otex = oracle.Tex(tex, 1, 1, n, 4, oracle.FMT_F64)
+    err = []
+    for v in V:
+        got = oracle.lookup_one_f64(otex, [0.5, 0.5], np.eye(3), v)
+        r = 2 * v[2] * np.array([0.0, 0.0, 1.0]) - v  # reflect(-V, N), N = e_z
+        err.append(np.max(np.abs(got - oracle.env_eval(_LOBES, _AMBIENT, 4, r)[0])))
+    return np.array(err)
+
+
+def test_baked_mirror_converges_to_the_reflection():
+    # a bucket baked from an environment and read back by the lookup gives the
+    # mirror reflection env(2 (N.V) N - V) up to the sampling error, which
+    # falls as n grows (views of elevation >= 20 degrees stay off the clamp):
+    # second order on average (bilinear interpolation of a smooth function),
+    # first order at worst (the square map of Eq. (3) is only continuous
+    # across the diagonals |B_x| = |B_y|, so the cells there interpolate a kink)
+    rng = np.random.default_rng(7)
+    V = _rand_dirs(rng, 300, zmin=math.sin(math.radians(20)))
+    e = {n: _mirror_error(n, V) for n in (8, 16, 32, 64)}
+    mx = [e[n].max() for n in (8, 16, 32, 64)]
+    mean = [e[n].mean() for n in (8, 16, 32, 64)]
+    for a, b in zip(mx, mx[1:]):
+        assert b < 0.6 * a
+    for a, b in zip(mean, mean[1:]):
+        assert b < 0.35 * a
