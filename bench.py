@@ -35,7 +35,8 @@ if ROOT not in sys.path:
 
 METRIC = "lookups/s + % HBM peak, fwd & bwd; FP32 vs BF16/FP8 texture at stated error"
 HBM_PEAK_GBS = 8000.0
-KERNEL_SOURCES = ["rt_device.hpp", "rt_lookup.hip", "rt_quantize.hip", "rt_backward.hip"]
+KERNEL_SOURCES = ["rt_device.hpp", "rt_lookup.hip", "rt_quantize.hip", "rt_backward.hip",
+                  "rt_bake.hip"]
 
 
 def source_hash() -> str:
@@ -73,6 +74,7 @@ def parse():
     ap.add_argument("--workload", default="c2")
     ap.add_argument("--storage", default="bf16", choices=["f32", "bf16", "fp8"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-bake", action="store_true", help="skip the bake measurement")
     ap.add_argument("--graph", action="store_true",
                     help="time replays of the step captured in a HIP graph (same kernels, no "
                          "host launch gaps; measured equal to eager launches on this workload)")
@@ -272,6 +274,36 @@ def main():
         if fmt != "f32":
             del c_, s_, t
 
+    # ---- the bake (write side): the same matrix from an analytic environment --
+    bake = None
+    if not args.no_bake:
+        lobes = [(0.3, -0.2, 1.0, 3.0, 0.8, 0.3, 0.1, 0.5), (1.0, 0.5, 0.4, 2.0, 0.1, 0.6, 0.2, 0.0),
+                 (-0.6, 0.9, 0.2, 1.5, 0.3, 0.1, 0.7, 0.9), (0.0, 0.0, 1.0, 8.0, 1.0, 1.0, 1.0, 0.0),
+                 (0.7, -0.7, 0.1, 4.0, 0.2, 0.0, 0.5, 0.1), (-0.2, -0.9, 0.4, 6.0, 0.0, 0.4, 0.3, 0.2),
+                 (0.5, 0.5, 0.7, 12.0, 0.6, 0.6, 0.0, 0.3), (-1.0, 0.1, 0.3, 1.0, 0.1, 0.2, 0.3, 0.4)]
+        amb = (0.05, 0.05, 0.05, 0.0)
+        dst = torch.empty_like(tex32)
+        for _ in range(2):
+            rt.bake_environment(W, H, n, C, lobes, amb, out=dst)
+        torch.cuda.synchronize()
+        rt.profile_reset()
+        rt.profile_enable(True)
+        reps = 10
+        for _ in range(reps):
+            rt.bake_environment(W, H, n, C, lobes, amb, out=dst)
+        torch.cuda.synchronize()
+        rt.profile_enable(False)
+        launches, total = rt.profile_read()["k_bake_env"]
+        avg = total / launches
+        bytes_bake = E * 4  # the texture, written once (identity frames: nothing read)
+        bake = {"kernel": "k_bake_env", "avg_ms": round(avg, 5), "lobes": len(lobes),
+                "texels_per_s": round(W * H * n * n / (avg * 1e-3), 1),
+                "alg_bytes": bytes_bake, "GBps": round(bytes_bake / (avg * 1e-3) / 1e9, 1),
+                "hbm_frac": round(bytes_bake / (avg * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                "note": "FP32 bake of the whole bucket matrix from 8 spherical Gaussian lobes "
+                        "along every sample's reflection vector (Eqs. 4a, 4b), identity frames"}
+        del dst
+
     # ---- the FP64 oracle on a bounded sample (CPU baseline and error) -------
     cpu = None
     errors = None
@@ -336,6 +368,7 @@ def main():
         "cpu_baseline": cpu,
         "kernels": per_kernel,
         "formats": formats,
+        "bake": bake,
         "errors": errors,
         "unique_texels_touched": uniq_texels,
         "source_hash": source_hash(),

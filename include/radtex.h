@@ -203,6 +203,48 @@ rt_status rt_debug_indices(const rt_texture* tex, const rt_fragments* frags, int
                            float* frac, void* stream);
 
 /* Thread-local description of the last non-OK status ("" if none). */
+/* --- The bake: the write side of the method --------------------------------
+ * Sec. 2.1 (after Eq. (4b)): ray-traced data is sampled onto the radiance
+ * texture along the equisolid reflection vector R of every sample.  Here an
+ * analytic environment stands in for the ray-traced radiance. */
+
+/* Directions of the n x n sample centres of a bucket in orthogonal texture
+ * space (N = e_z).  The centre of sample (x, y) is
+ * B = ((2x+1)/n - 1, (2y+1)/n - 1); A follows from Eq. (4a); refl[y][x] is
+ * the reflection vector of Eq. (4b) and inc[y][x] the incidence of Eq. (2c)
+ * (its mirror image about N, the view direction the lookup maps onto that
+ * sample).  inc, refl: DEVICE float [n][n][3], 4-byte aligned, either NULL.
+ * Errors: RT_ERR_INVALID_ARG (n < 1, alignment), RT_ERR_UNSUPPORTED (n > 32),
+ * RT_ERR_NO_DEVICE. */
+rt_status rt_bake_directions(int32_t n, float* inc, float* refl, void* stream);
+
+/* One spherical Gaussian lobe of the analytic environment. */
+typedef struct {
+    float axis[3];          /* direction in scene coordinates (normalised here)   */
+    float sharpness;        /* lambda >= 0                                         */
+    float amplitude[4];     /* per channel                                         */
+} rt_env_lobe;
+
+/* Bake a W x H matrix of n x n buckets with C channels, FP32 bucket-major:
+ *   texels[j][i][y][x][c] = ambient[c]
+ *       + sum_k amplitude_k[c] exp(sharpness_k (axis_k . d - 1)),
+ *   d = normalize(M_ji^T R(x, y)),
+ * R(x, y) as in rt_bake_directions and M_ji = frames[j][i] (rows T, B, N,
+ * world -> tangent as in the lookup), so d is R in scene coordinates; a
+ * mirror texture baked this way renders env(reflect(-V, N)) through
+ * rt_lookup_fwd.  frames: DEVICE float [H][W][3][3], 4-byte aligned, or NULL
+ * for the identity frame of every bucket.  lobes: HOST array of nlobes
+ * (0..16), read during the call; ambient: HOST float[4].  texels: DEVICE
+ * float [H][W][n][n][C], aligned to 16 (C = 4), 8 (C = 2) or 4 bytes,
+ * every element OVERWRITTEN.
+ * Errors: RT_ERR_INVALID_ARG (sizes, NULL pointers, alignment, a zero or
+ * non-finite axis, negative or non-finite sharpness, non-finite amplitude or
+ * ambient), RT_ERR_UNSUPPORTED (W or H > 65536, n > 32, nlobes > 16),
+ * RT_ERR_NO_DEVICE, RT_ERR_HIP (launch). */
+rt_status rt_bake_environment(int32_t W, int32_t H, int32_t n, int32_t C, const float* frames,
+                              const rt_env_lobe* lobes, int32_t nlobes, const float* ambient,
+                              float* texels, void* stream);
+
 const char* rt_last_error(void);
 const char* rt_status_string(rt_status status);
 int32_t rt_version(void);

@@ -5,6 +5,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -138,7 +139,8 @@ const char* kernel_name(int id) {
         "k_lookup_fwd",   "k_debug_indices", "k_quant_bf16",    "k_quant_fp8",
         "k_atlas_to_buckets", "k_bwd_fragment", "k_fill_u32",   "k_radix_hist",
         "k_scan",         "k_radix_scatter", "k_bucket_ranges", "k_segacc",
-        "k_segacc_hot",   "k_combine_hot",   "k_segacc_big"};
+        "k_segacc_hot",   "k_combine_hot",   "k_segacc_big",    "k_bake_directions",
+        "k_bake_env"};
     return (id >= 0 && id < K_COUNT) ? names[id] : "";
 }
 
@@ -373,6 +375,75 @@ rt_status rt_debug_indices(const rt_texture* t, const rt_fragments* f, int32_t* 
                                             fragmap(f), (hipStream_t)stream);
     rt::prof_end(rt::K_DEBUG_INDICES, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "debug-indices launch");
+    return ok();
+    RT_GUARD_END
+}
+
+rt_status rt_bake_directions(int32_t n, float* inc, float* refl, void* stream) {
+    RT_GUARD_BEGIN
+    if (n < 1) return fail(RT_ERR_INVALID_ARG, "angular resolution n = %d must be >= 1", n);
+    if (n > 32) return fail(RT_ERR_UNSUPPORTED, "angular resolution n = %d exceeds 32", n);
+    if ((inc && !aligned(inc, 4)) || (refl && !aligned(refl, 4)))
+        return fail(RT_ERR_INVALID_ARG, "inc and refl must be 4-byte aligned");
+    if (!inc && !refl) return ok();
+    rt_status st = check_device();
+    if (st != RT_OK) return st;
+    hipError_t e = rt::launch_bake_directions(n, inc, refl, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "bake-directions launch");
+    return ok();
+    RT_GUARD_END
+}
+
+rt_status rt_bake_environment(int32_t W, int32_t H, int32_t n, int32_t C, const float* frames,
+                              const rt_env_lobe* lobes, int32_t nlobes, const float* ambient,
+                              float* texels, void* stream) {
+    RT_GUARD_BEGIN
+    if (W < 1 || H < 1)
+        return fail(RT_ERR_INVALID_ARG, "bucket matrix %d x %d must be at least 1 x 1", W, H);
+    if (W > 65536 || H > 65536)
+        return fail(RT_ERR_UNSUPPORTED, "bucket matrix %d x %d exceeds 65536 per side", W, H);
+    if (n < 1) return fail(RT_ERR_INVALID_ARG, "angular resolution n = %d must be >= 1", n);
+    if (n > 32) return fail(RT_ERR_UNSUPPORTED, "angular resolution n = %d exceeds 32", n);
+    if (C < 1 || C > 4) return fail(RT_ERR_INVALID_ARG, "channels = %d must be in 1..4", C);
+    if (nlobes < 0) return fail(RT_ERR_INVALID_ARG, "nlobes = %d < 0", nlobes);
+    if (nlobes > rt::MAX_LOBES)
+        return fail(RT_ERR_UNSUPPORTED, "nlobes = %d exceeds %d", nlobes, rt::MAX_LOBES);
+    if (nlobes > 0 && !lobes) return fail(RT_ERR_INVALID_ARG, "lobes is NULL");
+    if (!ambient) return fail(RT_ERR_INVALID_ARG, "ambient is NULL");
+    if (!texels) return fail(RT_ERR_INVALID_ARG, "texels is NULL");
+    if (!aligned(texels, out_align(C)))
+        return fail(RT_ERR_INVALID_ARG, "texels must be %zu-byte aligned", out_align(C));
+    if (frames && !aligned(frames, 4)) return fail(RT_ERR_INVALID_ARG, "frames must be 4-byte aligned");
+    rt::EnvParams env;
+    memset(&env, 0, sizeof(env));
+    env.lobes = nlobes;
+    for (int c = 0; c < 4; c++) {
+        if (!std::isfinite(ambient[c])) return fail(RT_ERR_INVALID_ARG, "ambient[%d] is not finite", c);
+        env.ambient[c] = ambient[c];
+    }
+    for (int k = 0; k < nlobes; k++) {
+        const rt_env_lobe& L = lobes[k];
+        const double ax = L.axis[0], ay = L.axis[1], az = L.axis[2];
+        const double len = std::sqrt(ax * ax + ay * ay + az * az);
+        if (!(len > 0.0) || !std::isfinite(len))
+            return fail(RT_ERR_INVALID_ARG, "lobe %d: axis must be finite and non-zero", k);
+        if (!(L.sharpness >= 0.f) || !std::isfinite(L.sharpness))
+            return fail(RT_ERR_INVALID_ARG, "lobe %d: sharpness must be finite and >= 0", k);
+        const double l2 = (double)L.sharpness * 1.4426950408889634;  // lambda log2(e)
+        env.lobe[k][0] = (float)(l2 * ax / len);
+        env.lobe[k][1] = (float)(l2 * ay / len);
+        env.lobe[k][2] = (float)(l2 * az / len);
+        env.lobe[k][3] = (float)(-l2);
+        for (int c = 0; c < 4; c++) {
+            if (!std::isfinite(L.amplitude[c]))
+                return fail(RT_ERR_INVALID_ARG, "lobe %d: amplitude[%d] is not finite", k, c);
+            env.lobe[k][4 + c] = L.amplitude[c];
+        }
+    }
+    rt_status st = check_device();
+    if (st != RT_OK) return st;
+    hipError_t e = rt::launch_bake_env(W, H, n, C, frames, env, texels, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "bake launch");
     return ok();
     RT_GUARD_END
 }

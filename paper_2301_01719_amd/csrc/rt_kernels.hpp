@@ -28,6 +28,8 @@ enum KernelId {
     K_SEGACC_HOT,
     K_COMBINE_HOT,
     K_SEGACC_BIG,
+    K_BAKE_DIRECTIONS,
+    K_BAKE_ENV,
     K_COUNT
 };
 const char* kernel_name(int id);
@@ -44,6 +46,19 @@ hipError_t launch_quantize(const TexView& src, int dst_fmt, void* codes, float* 
                            hipStream_t s);
 hipError_t launch_atlas_to_buckets(const void* atlas, void* dst, int W, int H, int n, int C,
                                    int elem_bytes, hipStream_t s);
+
+// Bake: the analytic environment, lobe axes normalised on the host.
+constexpr int MAX_LOBES = 16;
+struct EnvParams {
+    int lobes;
+    float ambient[4];
+    // per lobe: lambda log2(e) times the unit axis (x, y, z), -lambda log2(e),
+    // amplitude per channel; the lobe's value at d is exp2(first three . d + 4th)
+    float lobe[MAX_LOBES][8];
+};
+hipError_t launch_bake_directions(int n, float* inc, float* refl, hipStream_t s);
+hipError_t launch_bake_env(int W, int H, int n, int C, const float* frames, const EnvParams& env,
+                           float* texels, hipStream_t s);
 
 // Backward.
 struct BwdPlan {

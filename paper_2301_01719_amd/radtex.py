@@ -30,7 +30,8 @@ _CODE_DTYPE = {RT_FMT_F32: torch.float32, RT_FMT_BF16: torch.int16, RT_FMT_FP8_E
 EXPORTS = ("rt_create_texture", "rt_destroy_texture", "rt_quantize", "rt_lookup_fwd",
            "rt_lookup_bwd_workspace", "rt_lookup_bwd", "rt_debug_indices", "rt_last_error",
            "rt_status_string", "rt_version", "rt_profile_enable", "rt_profile_reset",
-           "rt_profile_kernel_count", "rt_profile_kernel_name", "rt_profile_read")
+           "rt_profile_kernel_count", "rt_profile_kernel_name", "rt_profile_read",
+           "rt_bake_directions", "rt_bake_environment")
 
 
 class RadtexError(RuntimeError):
@@ -44,6 +45,11 @@ class TextureDesc(ctypes.Structure):
                 ("n", ctypes.c_int32), ("channels", ctypes.c_int32),
                 ("format", ctypes.c_int32), ("layout", ctypes.c_int32),
                 ("data", ctypes.c_void_p), ("scales", ctypes.c_void_p)]
+
+
+class EnvLobe(ctypes.Structure):
+    _fields_ = [("axis", ctypes.c_float * 3), ("sharpness", ctypes.c_float),
+                ("amplitude", ctypes.c_float * 4)]
 
 
 class Fragments(ctypes.Structure):
@@ -75,6 +81,9 @@ def _load() -> ctypes.CDLL:
         "rt_profile_kernel_count": ([], i32),
         "rt_profile_kernel_name": ([i32], ctypes.c_char_p),
         "rt_profile_read": ([i32, ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_double)], i32),
+        "rt_bake_directions": ([i32, P, P, P], i32),
+        "rt_bake_environment": ([i32, i32, i32, i32, P, ctypes.POINTER(EnvLobe), i32,
+                                 ctypes.POINTER(ctypes.c_float), P, P], i32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -225,6 +234,51 @@ def debug_indices(tex: Texture, uv, tbn, view, image=None):
     _check(LIB.rt_debug_indices(tex.handle, ctypes.byref(fr), _ptr(idx), _ptr(frac),
                                 _stream(tex.device)))
     return idx, frac
+
+
+def bake_directions(n: int, device="cuda:0"):
+    """(inc, refl) float32 [n, n, 3]: per sample centre of a bucket, the
+    incidence I (Eqs. 4a, 2c) and the reflection vector R (Eqs. 4a, 4b) in
+    orthogonal texture space."""
+    inc = torch.empty((n, n, 3), dtype=torch.float32, device=device)
+    refl = torch.empty((n, n, 3), dtype=torch.float32, device=device)
+    _check(LIB.rt_bake_directions(int(n), _ptr(inc), _ptr(refl), _stream(inc.device)))
+    return inc, refl
+
+
+def _lobe_array(lobes):
+    """lobes: a sequence of (axis xyz, sharpness, amplitudes[<=4]) or an [K, 8]
+    array (axis xyz, sharpness, amplitude per channel)."""
+    rows = [list(map(float, r)) for r in lobes]
+    arr = (EnvLobe * max(len(rows), 1))()
+    for k, r in enumerate(rows):
+        if len(r) != 8:
+            raise ValueError("a lobe is 8 numbers: axis x, y, z, sharpness, 4 amplitudes")
+        arr[k].axis[:] = r[0:3]
+        arr[k].sharpness = r[3]
+        arr[k].amplitude[:] = r[4:8]
+    return arr, len(rows)
+
+
+def bake_environment(W: int, H: int, n: int, C: int, lobes, ambient, frames=None, out=None,
+                     device="cuda:0"):
+    """Bake a W x H matrix of n x n buckets (FP32 [H, W, n, n, C]) from the
+    analytic environment ambient + spherical Gaussian lobes, sampled along each
+    sample's reflection vector carried to scene coordinates by the bucket's
+    frame (frames [H, W, 3, 3] rows T, B, N, or None: identity)."""
+    if out is None:
+        out = torch.empty((H, W, n, n, C), dtype=torch.float32, device=device)
+    else:
+        _need_gpu(out, "out", torch.float32)
+    if frames is not None:
+        _need_gpu(frames, "frames", torch.float32)
+        if frames.numel() != H * W * 9:
+            raise ValueError("frames must hold H * W frames of 3 x 3")
+    arr, K = _lobe_array(lobes)
+    amb = (ctypes.c_float * 4)(*[float(a) for a in ambient])
+    _check(LIB.rt_bake_environment(int(W), int(H), int(n), int(C), _ptr(frames), arr, K, amb,
+                                   _ptr(out), _stream(out.device)))
+    return out
 
 
 class _LookupFn(torch.autograd.Function):

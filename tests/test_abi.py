@@ -179,3 +179,40 @@ def test_product_path_refuses_cpu_tensors(rt):
     import torch
     with pytest.raises(ValueError, match="GPU tensor"):
         rt.Texture(torch.zeros(4 * 4 * 8 * 8 * 4), 4, 4, 8, 4)
+
+
+def test_bake_validation(rt):
+    """The bake entries reject bad arguments on the host; the placeholder
+    pointers are never dereferenced because every call here fails before a
+    launch (the one well-formed call runs only where no device is visible)."""
+    import math
+    import torch
+    L = rt.LIB
+    amb = (ctypes.c_float * 4)(0.1, 0.2, 0.3, 0.4)
+
+    def call(W=4, H=3, n=8, C=4, frames=None, lobes=((0, 0, 1, 2, 1, 1, 1, 1),), nlobes=None,
+             ambient=amb, texels=0x10000):
+        arr, K = rt._lobe_array(lobes)
+        return L.rt_bake_environment(W, H, n, C, frames, arr, K if nlobes is None else nlobes,
+                                     ambient, texels, None)
+
+    for kw, status, text in (
+            (dict(W=0), 1, "bucket matrix"), (dict(H=70000), 2, "exceeds"),
+            (dict(n=0), 1, "angular resolution"), (dict(n=33), 2, "exceeds 32"),
+            (dict(C=0), 1, "channels"), (dict(C=5), 1, "channels"),
+            (dict(nlobes=17), 2, "exceeds 16"), (dict(nlobes=-1), 1, "< 0"),
+            (dict(ambient=None), 1, "ambient"), (dict(texels=None), 1, "texels is NULL"),
+            (dict(texels=0x10004), 1, "16-byte"), (dict(C=2, texels=0x10004), 1, "8-byte"),
+            (dict(frames=0x2002), 1, "frames"),
+            (dict(lobes=((0, 0, 0, 2, 1, 1, 1, 1),)), 1, "axis"),
+            (dict(lobes=((0, 0, 1, -1, 1, 1, 1, 1),)), 1, "sharpness"),
+            (dict(lobes=((0, 0, 1, math.inf, 1, 1, 1, 1),)), 1, "sharpness"),
+            (dict(lobes=((0, 0, 1, 1, 1, math.nan, 1, 1),)), 1, "amplitude")):
+        assert call(**kw) == status, kw
+        assert text in L.rt_last_error().decode(), (kw, L.rt_last_error())
+    assert L.rt_bake_directions(0, 0x1000, 0x2000, None) == 1
+    assert L.rt_bake_directions(33, 0x1000, 0x2000, None) == 2
+    assert L.rt_bake_directions(8, 0x1002, None, None) == 1
+    assert L.rt_bake_directions(8, None, None, None) == 0  # nothing asked, nothing launched
+    if not torch.cuda.is_available():
+        assert call() == 5 and "no HIP device" in L.rt_last_error().decode()
