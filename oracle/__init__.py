@@ -54,6 +54,10 @@ def _load():
     lib.orc_bake_directions.argtypes = [i32, P, P]
     lib.orc_bake_environment.argtypes = [i32, i32, i32, i32, P, P, i32, P, i32, i32, i32, i32, P]
     lib.orc_env_eval.argtypes = [P, i32, P, i32, P, P]
+    lib.orc_build_mip.argtypes = [i32, i32, i32, i32, P, P]
+    lib.orc_lod.argtypes = [P, i32, i32, i32]
+    lib.orc_lod.restype = d
+    lib.orc_lookup_lod.argtypes = [i64, P, P, P, P, i32, i32, i32, i32, i32, P, i32, P, P]
     _lib = lib
     return lib
 
@@ -303,3 +307,45 @@ def env_eval(lobes, ambient, C, d):
         _load().orc_env_eval(_p(lobes), lobes.shape[0], _p(ambient), int(C),
                              _p(d[r]), _p(out[r]))
     return out
+
+
+# --- minification: mip chain and level-of-detail lookup ----------------------
+
+def level_dims(W, H, l):
+    return max(1, W >> l), max(1, H >> l)
+
+
+def build_mips(tex, W, H, n, C, levels):
+    """The mip chain [level 0 (as float64), level 1, ...] of a bucket-major
+    texture [H, W, n, n, C] (W, H powers of two)."""
+    cur = np.ascontiguousarray(np.asarray(tex, np.float64).reshape(H, W, n, n, C))
+    out = [cur]
+    for l in range(1, levels):
+        w, h = level_dims(W, H, l - 1)
+        w2, h2 = level_dims(W, H, l)
+        nxt = np.empty((h2, w2, n, n, C), np.float64)
+        _load().orc_build_mip(w, h, int(n), int(C), _p(cur), _p(nxt))
+        out.append(nxt)
+        cur = nxt
+    return out
+
+
+def lod(duv, W, H, levels):
+    duv = _c(duv, np.float64).reshape(4)
+    return float(_load().orc_lod(_p(duv), int(W), int(H), int(levels)))
+
+
+def lookup_lod(chain, uv, tbn, view, duv, W, H, n, C, mode=MODE_NEAREST):
+    """Trilinear lookup over the mip chain (list of float64 levels).  Returns
+    (out [N, C] float64, lambda [N])."""
+    uv, tbn, view = _frags(uv, tbn, view)
+    duv = _c(duv, np.float32).reshape(-1, 4)
+    N = uv.shape[0]
+    assert duv.shape[0] == N
+    flat = np.ascontiguousarray(np.concatenate([np.asarray(c, np.float64).reshape(-1)
+                                                for c in chain]))
+    out = np.empty((N, C), np.float64)
+    lam = np.empty(N, np.float64)
+    _load().orc_lookup_lod(N, _p(uv), _p(tbn), _p(view), _p(duv), int(W), int(H), int(n),
+                           int(C), len(chain), _p(flat), int(mode), _p(out), _p(lam))
+    return out, lam

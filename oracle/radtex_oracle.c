@@ -23,6 +23,9 @@
  *   filtered fetch            bilinear inside the bucket (the clamp only has a
  *                             purpose for a filtered fetch)
  *   inverse mappings          Eqs. (2a)-(2c), (4a), (4b)
+ *   minification              a mip chain of bucket matrices (2 x 2 bucket
+ *                             means) and a trilinear lookup whose level is
+ *                             log2 of the UV footprint in buckets
  *   bake                      the reflection vector of every sample centre
  *                             (Eqs. (4a), (4b)) carried to scene coordinates
  *                             by the bucket frame; an analytic environment
@@ -915,4 +918,106 @@ void orc_env_eval(const float *lobes, int K, const float *ambient, int C, const 
     double d[3] = {d_in[0] / len, d_in[1] / len, d_in[2] / len};
     for (int c = 0; c < C; c++)
         out[c] = env_eval(lobes, K, ambient, c, d);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Minification across the bucket matrix: a mip chain of bucket matrices and */
+/* a trilinear lookup whose level follows the fragment's UV footprint.       */
+/* ------------------------------------------------------------------------- */
+
+/* Sec. 2: one sample per bucket synthesises an ordinary W x H texture, and
+ * the lookup is linear in the buckets (the sample position depends only on
+ * the view), so the minified texture of a 2 x 2 block of pixels is the lookup
+ * in the texel-wise mean of the 2 x 2 buckets.  Level l+1 from level l:
+ * W_{l+1} = max(1, W_l / 2) (W a power of two; a side of 1 is not halved),
+ * and bucket (i, j) of level l+1 is the mean of the buckets of level l it
+ * covers (4, or 2 once a side is 1).  src [H][W][n][n][C], dst
+ * [H'][W'][n][n][C], binary64. */
+void orc_build_mip(int W, int H, int n, int C, const double *src, double *dst)
+{
+    int W2 = W > 1 ? W / 2 : 1, H2 = H > 1 ? H / 2 : 1;
+    int sx = W > 1 ? 2 : 1, sy = H > 1 ? 2 : 1;
+    int64_t per = (int64_t)n * n * C;
+#pragma omp parallel for schedule(static)
+    for (int64_t b = 0; b < (int64_t)W2 * H2; b++) {
+        int i = (int)(b % W2), j = (int)(b / W2);
+        for (int64_t e = 0; e < per; e++) {
+            double acc = 0.0;
+            for (int dj = 0; dj < sy; dj++)
+                for (int di = 0; di < sx; di++)
+                    acc += src[((int64_t)(j * sy + dj) * W + (i * sx + di)) * per + e];
+            dst[b * per + e] = acc / (sx * sy);
+        }
+    }
+}
+
+static int level_dim(int D, int l)
+{
+    int v = D >> l;
+    return v > 0 ? v : 1;
+}
+
+/* Level of detail of a fragment from its UV screen derivatives duv =
+ * (du/dx, dv/dx, du/dy, dv/dy): the footprint of one pixel in buckets of
+ * level 0, rho = max(|(du/dx W, dv/dx H)|, |(du/dy W, dv/dy H)|), and
+ * lambda = log2 rho, clamped to [0, levels - 1] (0 when rho is 0 or not
+ * finite). */
+double orc_lod(const double duv[4], int W, int H, int levels)
+{
+    double ax = duv[0] * W, ay = duv[1] * H, bx = duv[2] * W, by = duv[3] * H;
+    double rho = fmax(sqrt(ax * ax + ay * ay), sqrt(bx * bx + by * by));
+    if (!(rho > 0.0) || !isfinite(rho))
+        return 0.0;
+    double lambda = log2(rho);
+    if (lambda < 0.0)
+        lambda = 0.0;
+    if (lambda > levels - 1)
+        lambda = levels - 1;
+    return lambda;
+}
+
+/* Trilinear lookup: levels l0 = floor(lambda) and l0 + 1 weighted 1 - t and
+ * t (t = lambda - l0; one level when t = 0 or l0 is the last level), each a
+ * lookup as in the forward with the level's W_l x H_l buckets.  chain holds
+ * the levels 0..levels-1 back to back in binary64; lod (may be NULL)
+ * receives lambda per fragment. */
+void orc_lookup_lod(int64_t N, const float *uv, const float *tbn, const float *view,
+                    const float *duv, int W, int H, int n, int C, int levels,
+                    const double *chain, int mode, double *out, double *lod)
+{
+    const double **lv = (const double **)malloc(sizeof(double *) * levels);
+    if (!lv)
+        return;
+    int64_t off = 0;
+    for (int l = 0; l < levels; l++) {
+        lv[l] = chain + off;
+        off += (int64_t)level_dim(W, l) * level_dim(H, l) * n * n * C;
+    }
+#pragma omp parallel for schedule(static)
+    for (int64_t f = 0; f < N; f++) {
+        double U[2], M[9], V[3], D[4];
+        widen_fragment(uv, tbn, view, f, U, M, V);
+        for (int k = 0; k < 4; k++)
+            D[k] = duv[4 * f + k];
+        double lambda = orc_lod(D, W, H, levels);
+        if (lod)
+            lod[f] = lambda;
+        int l0 = (int)floor(lambda);
+        double t = lambda - l0;
+        if (l0 >= levels - 1) {
+            l0 = levels - 1;
+            t = 0.0;
+        }
+        double a[4], b[4];
+        tex_t t0 = {level_dim(W, l0), level_dim(H, l0), n, C, ORC_FMT_F64, lv[l0], NULL};
+        lookup_one(&t0, U, M, V, mode, a);
+        if (t > 0.0) {
+            tex_t t1 = {level_dim(W, l0 + 1), level_dim(H, l0 + 1), n, C, ORC_FMT_F64,
+                        lv[l0 + 1], NULL};
+            lookup_one(&t1, U, M, V, mode, b);
+        }
+        for (int c = 0; c < C; c++)
+            out[f * C + c] = t > 0.0 ? (1.0 - t) * a[c] + t * b[c] : a[c];
+    }
+    free(lv);
 }

@@ -725,3 +725,149 @@ def test_baked_mirror_converges_to_the_reflection():
         assert b < 0.6 * a
     for a, b in zip(mean, mean[1:]):
         assert b < 0.35 * a
+
+
+# --------------------------------------------------------------------------
+# Minification: mip chain of bucket matrices and the level of detail
+# --------------------------------------------------------------------------
+
+def _levels(W, H):
+    return 1 + int(math.log2(max(W, H)))
+
+
+@pytest.mark.parametrize("W,H", [(8, 4), (1, 8), (16, 16), (2, 1), (4, 32)])
+def test_mips_are_block_means_brute_force(W, H):
+    rng = np.random.default_rng(W * 7 + H)
+    n, C = 3, 2
+    t = rng.random((H, W, n, n, C))
+    ch = oracle.build_mips(t, W, H, n, C, _levels(W, H))
+    for l, lev in enumerate(ch):
+        w, h = oracle.level_dims(W, H, l)
+        sx, sy = W // w, H // h
+        ref = t.reshape(h, sy, w, sx, n, n, C).mean(axis=(1, 3))
+        np.testing.assert_allclose(lev, ref, rtol=1e-13, atol=1e-15)
+    assert ch[-1].shape[:2] == (1, 1)
+
+
+def test_lod_closed_forms():
+    W, H, L = 64, 32, 7
+    for k in range(L):
+        assert oracle.lod([2.0 ** k / W, 0, 0, 2.0 ** k / H], W, H, L) == k
+    # a rotated square footprint of side s pixels -> rho = s
+    for th in (0.3, 1.1, 2.5):
+        s = 5.0
+        lam = oracle.lod([s * math.cos(th) / W, s * math.sin(th) / H,
+                          -s * math.sin(th) / W, s * math.cos(th) / H], W, H, L)
+        assert abs(lam - math.log2(s)) < 1e-12
+    # anisotropic: the longer axis decides
+    assert abs(oracle.lod([3.0 / W, 0, 0, 12.0 / H], W, H, L) - math.log2(12.0)) < 1e-12
+    assert oracle.lod([0.25 / W, 0, 0, 0.5 / H], W, H, L) == 0.0      # magnified
+    assert oracle.lod([1e6 / W, 0, 0, 1.0 / H], W, H, L) == L - 1     # beyond the chain
+    assert oracle.lod([0, 0, 0, 0], W, H, L) == 0.0
+    assert oracle.lod([math.nan, 0, 0, 0], W, H, L) == 0.0
+
+
+def _mip_case(seed, W=16, H=8, n=5, C=3, N=300):
+    rng = np.random.default_rng(seed)
+    tex = rng.random((H, W, n, n, C)).astype(np.float32)
+    uv = rng.uniform(-1.0, 2.0, (N, 2)).astype(np.float32)
+    tbn = np.stack([_rand_rot(rng).T for _ in range(N)]).astype(np.float32)
+    vt = _rand_dirs(rng, N, zmin=0.1)
+    view = np.einsum("fkm,fk->fm", tbn.astype(np.float64), vt).astype(np.float32)
+    return tex, uv, tbn, view
+
+
+def _duv_iso(s, W, H, N):
+    return np.tile(np.array([s / W, 0, 0, s / H], np.float32), (N, 1))
+
+
+@pytest.mark.parametrize("mode", [oracle.MODE_NEAREST, oracle.MODE_BILINEAR])
+def test_lod_lookup_reduces_to_the_plain_lookup_when_magnified(mode):
+    W, H, n, C = 16, 8, 5, 3
+    tex, uv, tbn, view = _mip_case(1)
+    ch = oracle.build_mips(tex, W, H, n, C, _levels(W, H))
+    got, lam = oracle.lookup_lod(ch, uv, tbn, view, _duv_iso(0.7, W, H, len(uv)), W, H, n, C,
+                                 mode)
+    assert np.all(lam == 0)
+    ref = oracle.lookup_fwd(oracle.Tex(tex, W, H, n, C), uv, tbn, view, mode)
+    np.testing.assert_array_equal(got, ref)
+
+
+def test_lod_lookup_at_integer_levels_is_that_levels_lookup():
+    W, H, n, C = 16, 8, 5, 3
+    tex, uv, tbn, view = _mip_case(2)
+    L = _levels(W, H)
+    ch = oracle.build_mips(tex, W, H, n, C, L)
+    for k in range(L):
+        got, lam = oracle.lookup_lod(ch, uv, tbn, view, _duv_iso(2.0 ** k, W, H, len(uv)),
+                                     W, H, n, C)
+        assert np.all(lam == k)
+        w, h = oracle.level_dims(W, H, k)
+        ref = oracle.lookup_fwd(oracle.Tex(ch[k], w, h, n, C, oracle.FMT_F64), uv, tbn, view)
+        np.testing.assert_array_equal(got, ref)
+
+
+def test_lod_lookup_is_continuous_in_lambda():
+    W, H, n, C = 16, 8, 5, 3
+    tex, uv, tbn, view = _mip_case(3)
+    ch = oracle.build_mips(tex, W, H, n, C, _levels(W, H))
+    for k in (1, 2, 3):
+        at, _ = oracle.lookup_lod(ch, uv, tbn, view, _duv_iso(2.0 ** k, W, H, len(uv)), W, H, n, C)
+        for eps in (-1e-5, 1e-5):
+            near, lam = oracle.lookup_lod(ch, uv, tbn, view,
+                                          _duv_iso(2.0 ** (k + eps), W, H, len(uv)), W, H, n, C)
+            assert np.all(np.abs(lam - k) < 2e-5)
+            np.testing.assert_allclose(near, at, atol=1e-4)
+
+
+def test_lod_lookup_of_identical_buckets_ignores_the_level():
+    W, H, n, C = 16, 8, 5, 3
+    rng = np.random.default_rng(4)
+    one = rng.random((n, n, C))
+    tex = np.broadcast_to(one, (H, W, n, n, C)).astype(np.float32)
+    _, uv, tbn, view = _mip_case(4)
+    ch = oracle.build_mips(tex, W, H, n, C, _levels(W, H))
+    duv = (rng.uniform(0.1, 30.0, (len(uv), 1)) * np.array([1 / W, 0.3 / H, -0.2 / W, 1 / H])
+           ).astype(np.float32)
+    got, lam = oracle.lookup_lod(ch, uv, tbn, view, duv, W, H, n, C)
+    assert np.any((lam > 0) & (lam != np.floor(lam)))
+    ref = oracle.lookup_fwd(oracle.Tex(tex, W, H, n, C), uv, tbn, view)
+    np.testing.assert_allclose(got, ref, atol=1e-12)
+
+
+def test_lod_lookup_is_linear_in_the_texture():
+    W, H, n, C = 16, 8, 5, 3
+    texA, uv, tbn, view = _mip_case(5)
+    texB, _, _, _ = _mip_case(6)
+    rng = np.random.default_rng(7)
+    duv = (rng.uniform(0.5, 20.0, (len(uv), 1)) * np.array([1 / W, 0, 0, 1 / H])).astype(np.float32)
+    L = _levels(W, H)
+    a, _ = oracle.lookup_lod(oracle.build_mips(texA, W, H, n, C, L), uv, tbn, view, duv, W, H, n, C)
+    b, _ = oracle.lookup_lod(oracle.build_mips(texB, W, H, n, C, L), uv, tbn, view, duv, W, H, n, C)
+    mix = 0.25 * texA.astype(np.float64) - 1.5 * texB.astype(np.float64)
+    m, _ = oracle.lookup_lod(oracle.build_mips(mix, W, H, n, C, L), uv, tbn, view, duv, W, H, n, C)
+    np.testing.assert_allclose(m, 0.25 * a - 1.5 * b, atol=1e-12)
+
+
+def test_level_lookup_is_the_mean_of_plain_lookups_over_its_buckets():
+    # the lookup is linear in the buckets and its sample position depends only
+    # on the view, so level l at a bucket equals the mean of the level-0
+    # lookups over the 2^l x 2^l buckets it covers
+    W, H, n, C = 16, 8, 5, 3
+    tex, _, tbn, view = _mip_case(8, N=40)
+    ch = oracle.build_mips(tex, W, H, n, C, _levels(W, H))
+    otex = oracle.Tex(tex, W, H, n, C)
+    rng = np.random.default_rng(9)
+    for l in (1, 2, 3):
+        w, h = oracle.level_dims(W, H, l)
+        sx, sy = W // w, H // h
+        lvl = oracle.Tex(ch[l], w, h, n, C, oracle.FMT_F64)
+        for f in range(len(tbn)):
+            i, j = rng.integers(0, w), rng.integers(0, h)
+            got = oracle.lookup_fwd(lvl, [[(i + 0.5) / w, (j + 0.5) / h]], tbn[f:f + 1],
+                                    view[f:f + 1])[0]
+            uvs = np.array([[(i * sx + di + 0.5) / W, (j * sy + dj + 0.5) / H]
+                            for dj in range(sy) for di in range(sx)], np.float32)
+            base = oracle.lookup_fwd(otex, uvs, np.repeat(tbn[f:f + 1], len(uvs), 0),
+                                     np.repeat(view[f:f + 1], len(uvs), 0))
+            np.testing.assert_allclose(got, base.mean(0), atol=1e-12)
