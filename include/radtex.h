@@ -203,6 +203,42 @@ rt_status rt_debug_indices(const rt_texture* tex, const rt_fragments* frags, int
                            float* frac, void* stream);
 
 /* Thread-local description of the last non-OK status ("" if none). */
+/* --- Minification across the bucket matrix ---------------------------------
+ * Sec. 2: taking one sample per bucket synthesises an ordinary W x H texture,
+ * and the lookup is linear in the buckets (the sample position depends only
+ * on the view), so minifying that texture by 2 x 2 pixels is the lookup in
+ * the texel-wise mean of 2 x 2 buckets: a mip chain of bucket matrices. */
+
+/* One level of the chain: dst = the level below src, a matrix of
+ * max(1, W/2) x max(1, H/2) buckets whose bucket (i, j) is the texel-wise mean
+ * of the 4 buckets (2i..2i+1, 2j..2j+1) of src (2 once a side of src is 1).
+ * src: an FP32 bucket-major texture with W, H powers of two, not both 1.
+ * dst: DEVICE float [max(1,H/2)][max(1,W/2)][n][n][C], 16-byte aligned,
+ * every element OVERWRITTEN.  The mean of four FP32 values is formed as
+ * ((a + b) + (c + d)) / 4.
+ * Errors: RT_ERR_INVALID_ARG (NULL, alignment, sizes that are not powers of
+ * two, a 1 x 1 source), RT_ERR_UNSUPPORTED (a format other than FP32). */
+rt_status rt_build_mip(const rt_texture* src, float* dst, void* stream);
+
+/* Lookup over a mip chain: levels[l] (l < nlevels) is a texture of
+ * max(1, W >> l) x max(1, H >> l) buckets of level 0's n, channels and format
+ * (W, H powers of two when nlevels > 1; nlevels <= 1 + log2(max(W, H)), at
+ * most 17).  Per fragment, from duv[f] = (du/dx, dv/dx, du/dy, dv/dy), the
+ * texture-coordinate derivatives across one pixel:
+ *   rho    = max(|(du/dx W, dv/dx H)|, |(du/dy W, dv/dy H)|),
+ *   lambda = log2 rho clamped to [0, nlevels - 1] (0 if rho is 0 or not
+ *            finite),
+ *   out    = (1 - t) L(floor(lambda)) + t L(floor(lambda) + 1),
+ *            t = lambda - floor(lambda) (one level when t = 0),
+ * with L(l) the lookup of rt_lookup_fwd on level l (flags as there).
+ * duv: DEVICE float [N][4], 16-byte aligned; out as for rt_lookup_fwd.
+ * Errors: RT_ERR_INVALID_ARG (NULL levels, a level of the wrong size, n,
+ * channels or format, sizes that are not powers of two, duv/out NULL or
+ * misaligned, bad fragments or flags), RT_ERR_UNSUPPORTED (nlevels > 17). */
+rt_status rt_lookup_fwd_lod(const rt_texture* const* levels, int32_t nlevels,
+                            const rt_fragments* frags, const float* duv, float* out,
+                            uint32_t flags, void* stream);
+
 /* --- The bake: the write side of the method --------------------------------
  * Sec. 2.1 (after Eq. (4b)): ray-traced data is sampled onto the radiance
  * texture along the equisolid reflection vector R of every sample.  Here an

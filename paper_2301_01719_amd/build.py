@@ -12,7 +12,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libradtex.so")
-SOURCES = ["rt_abi.cpp", "rt_lookup.hip", "rt_quantize.hip", "rt_backward.hip", "rt_bake.hip"]
+SOURCES = ["rt_abi.cpp", "rt_lookup.hip", "rt_quantize.hip", "rt_backward.hip", "rt_bake.hip",
+           "rt_mip.hip"]
 ARCH = os.environ.get("RADTEX_ARCH", "gfx950")
 
 

@@ -5,6 +5,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -140,7 +141,7 @@ const char* kernel_name(int id) {
         "k_atlas_to_buckets", "k_bwd_fragment", "k_fill_u32",   "k_radix_hist",
         "k_scan",         "k_radix_scatter", "k_bucket_ranges", "k_segacc",
         "k_segacc_hot",   "k_combine_hot",   "k_segacc_big",    "k_bake_directions",
-        "k_bake_env"};
+        "k_bake_env",     "k_build_mip",     "k_lookup_lod"};
     return (id >= 0 && id < K_COUNT) ? names[id] : "";
 }
 
@@ -444,6 +445,84 @@ rt_status rt_bake_environment(int32_t W, int32_t H, int32_t n, int32_t C, const 
     if (st != RT_OK) return st;
     hipError_t e = rt::launch_bake_env(W, H, n, C, frames, env, texels, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "bake launch");
+    return ok();
+    RT_GUARD_END
+}
+
+namespace {
+bool pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+int log2i(int v) {
+    int l = 0;
+    while ((1 << l) < v) l++;
+    return l;
+}
+}  // namespace
+
+rt_status rt_build_mip(const rt_texture* src, float* dst, void* stream) {
+    RT_GUARD_BEGIN
+    rt_status st = check_tex(src);
+    if (st != RT_OK) return st;
+    const rt::TexView& v = src->view;
+    if (src->fmt != RT_FMT_F32)
+        return fail(RT_ERR_UNSUPPORTED, "mip levels are built from FP32 textures");
+    if (!pow2(v.W) || !pow2(v.H))
+        return fail(RT_ERR_INVALID_ARG, "bucket matrix %d x %d: a mip chain needs powers of two", v.W, v.H);
+    if (v.W == 1 && v.H == 1) return fail(RT_ERR_INVALID_ARG, "a 1 x 1 matrix has no next level");
+    if (!dst) return fail(RT_ERR_INVALID_ARG, "dst is NULL");
+    if (!aligned(dst, 16)) return fail(RT_ERR_INVALID_ARG, "dst must be 16-byte aligned");
+    hipError_t e = rt::launch_build_mip(v, dst, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "mip launch");
+    return ok();
+    RT_GUARD_END
+}
+
+rt_status rt_lookup_fwd_lod(const rt_texture* const* levels, int32_t nlevels,
+                            const rt_fragments* f, const float* duv, float* out, uint32_t flags,
+                            void* stream) {
+    RT_GUARD_BEGIN
+    if (!levels) return fail(RT_ERR_INVALID_ARG, "levels is NULL");
+    if (nlevels < 1) return fail(RT_ERR_INVALID_ARG, "nlevels = %d < 1", nlevels);
+    if (nlevels > rt::MAX_LEVELS)
+        return fail(RT_ERR_UNSUPPORTED, "nlevels = %d exceeds %d", nlevels, rt::MAX_LEVELS);
+    for (int l = 0; l < nlevels; l++)
+        if (!levels[l]) return fail(RT_ERR_INVALID_ARG, "level %d is NULL", l);
+    const rt::TexView& v0 = levels[0]->view;
+    if (nlevels > 1) {
+        if (!pow2(v0.W) || !pow2(v0.H))
+            return fail(RT_ERR_INVALID_ARG, "bucket matrix %d x %d: a mip chain needs powers of two", v0.W, v0.H);
+        if (nlevels > 1 + log2i(std::max(v0.W, v0.H)))
+            return fail(RT_ERR_INVALID_ARG, "%d levels exceed the chain of a %d x %d matrix", nlevels, v0.W, v0.H);
+    }
+    rt::LevelSet ls;
+    memset(&ls, 0, sizeof(ls));
+    ls.levels = nlevels;
+    ls.W = v0.W;
+    ls.H = v0.H;
+    ls.n = v0.n;
+    ls.C = v0.C;
+    for (int l = 0; l < nlevels; l++) {
+        const rt::TexView& v = levels[l]->view;
+        const int w = std::max(v0.W >> l, 1), h = std::max(v0.H >> l, 1);
+        if (v.W != w || v.H != h)
+            return fail(RT_ERR_INVALID_ARG, "level %d is %d x %d, the chain needs %d x %d", l, v.W, v.H, w, h);
+        if (v.n != v0.n || v.C != v0.C || levels[l]->fmt != levels[0]->fmt)
+            return fail(RT_ERR_INVALID_ARG, "level %d differs from level 0 in n, channels or format", l);
+        ls.data[l] = v.data;
+        ls.scales[l] = v.scales;
+    }
+    rt_status st = check_frags(f);
+    if (st != RT_OK) return st;
+    if (flags > RT_BUCKET_BILINEAR) return fail(RT_ERR_INVALID_ARG, "unknown flags 0x%x", flags);
+    if (f->count > 0) {
+        if (!duv) return fail(RT_ERR_INVALID_ARG, "duv is NULL");
+        if (!aligned(duv, 16)) return fail(RT_ERR_INVALID_ARG, "duv must be 16-byte aligned");
+        if (!out) return fail(RT_ERR_INVALID_ARG, "out is NULL");
+        if (!aligned(out, out_align(v0.C)))
+            return fail(RT_ERR_INVALID_ARG, "out must be %zu-byte aligned", out_align(v0.C));
+    }
+    hipError_t e = rt::launch_lookup_lod(ls, levels[0]->fmt, (int)flags, f->uv, f->tbn, f->view,
+                                         duv, out, fragmap(f), (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "lod lookup launch");
     return ok();
     RT_GUARD_END
 }

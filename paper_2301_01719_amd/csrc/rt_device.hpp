@@ -26,6 +26,16 @@ struct TexView {
     int W, H, n, C;
 };
 
+// A mip chain: level l has max(1, W >> l) x max(1, H >> l) buckets of the
+// same n, C and format; only the storage pointers differ per level.
+constexpr int MAX_LEVELS = 17;
+struct LevelSet {
+    const void* data[MAX_LEVELS];
+    const float* scales[MAX_LEVELS];
+    int levels;
+    int W, H, n, C;  // level 0
+};
+
 // ---------------------------------------------------------------------------
 // Launch geometry: gfx950 places consecutive workgroups of a launch on its 8
 // XCDs round-robin.  Renumbering the workgroups so that each XCD receives a

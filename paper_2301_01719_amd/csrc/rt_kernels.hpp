@@ -10,6 +10,7 @@ namespace rt {
 
 struct TexView;
 struct FragMap;
+struct LevelSet;
 
 // Kernel ids for the event-based timing of rt_profile_*.
 enum KernelId {
@@ -30,6 +31,8 @@ enum KernelId {
     K_SEGACC_BIG,
     K_BAKE_DIRECTIONS,
     K_BAKE_ENV,
+    K_BUILD_MIP,
+    K_LOOKUP_LOD,
     K_COUNT
 };
 const char* kernel_name(int id);
@@ -44,6 +47,10 @@ hipError_t launch_debug_indices(const TexView& t, const float* uv, const float* 
                                 hipStream_t s);
 hipError_t launch_quantize(const TexView& src, int dst_fmt, void* codes, float* scales,
                            hipStream_t s);
+hipError_t launch_build_mip(const TexView& src, float* dst, hipStream_t s);
+hipError_t launch_lookup_lod(const LevelSet& ls, int fmt, int mode, const float* uv,
+                             const float* tbn, const float* view, const float* duv, float* out,
+                             const FragMap& m, hipStream_t s);
 hipError_t launch_atlas_to_buckets(const void* atlas, void* dst, int W, int H, int n, int C,
                                    int elem_bytes, hipStream_t s);
 

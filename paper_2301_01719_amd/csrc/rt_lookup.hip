@@ -1,4 +1,5 @@
-// rt_lookup.hip -- forward radiance-bucket lookup for gfx950.
+// rt_lookup.hip -- forward radiance-bucket lookup for gfx950, on one bucket
+// matrix or, with a level of detail, on a mip chain of them.
 //
 // One lane per fragment.  Per lane: the 56-byte G-buffer record (uv, frame,
 // view) is read, the incidence is mapped to the in-bucket sample coordinate
@@ -83,6 +84,85 @@ __global__ __launch_bounds__(256) void k_debug_indices(TexView t, const float* _
     ((float2*)frac)[f] = make_float2(d.sx - (float)x0, d.sy - (float)y0);
 }
 
+// Storage of level l of a chain, selected with compile-time indices so that
+// the per-lane choice stays in registers.
+__device__ __forceinline__ void level_storage(const LevelSet& ls, int l, const void*& data,
+                                              const float*& scales) {
+    data = ls.data[0];
+    scales = ls.scales[0];
+#pragma unroll
+    for (int k = 1; k < MAX_LEVELS; k++) {
+        if (l == k) {
+            data = ls.data[k];
+            scales = ls.scales[k];
+        }
+    }
+}
+
+// The forward's bucket footprint and in-bucket bilinear blend, on level l.
+template <int FMT, int C, int MODE>
+__device__ __forceinline__ void level_lookup(const LevelSet& ls, int l, const Frag& g,
+                                             const Foot& p, float acc[4]) {
+    TexView t;
+    level_storage(ls, l, t.data, t.scales);
+    t.W = max(ls.W >> l, 1);
+    t.H = max(ls.H >> l, 1);
+    t.n = ls.n;
+    t.C = ls.C;
+    if constexpr (MODE == MODE_NEAREST) {
+        const int i = bucket_of(g.u, t.W), j = bucket_of(g.v, t.H);
+        bucket_bilerp<FMT, C>(t, (int64_t)j * t.W + i, p, 1.0f, acc);
+    } else {
+        int i0, i1, j0, j1;
+        float a, bb;
+        bucket_pair(g.u, t.W, i0, i1, a);
+        bucket_pair(g.v, t.H, j0, j1, bb);
+        bucket_bilerp<FMT, C>(t, (int64_t)j0 * t.W + i0, p, (1.f - a) * (1.f - bb), acc);
+        bucket_bilerp<FMT, C>(t, (int64_t)j0 * t.W + i1, p, a * (1.f - bb), acc);
+        bucket_bilerp<FMT, C>(t, (int64_t)j1 * t.W + i0, p, (1.f - a) * bb, acc);
+        bucket_bilerp<FMT, C>(t, (int64_t)j1 * t.W + i1, p, a * bb, acc);
+    }
+}
+
+// Lookup over a mip chain of bucket matrices: the level of detail is
+// lambda = log2 rho, rho the larger of the pixel's two UV footprints in
+// buckets of level 0 (duv = du/dx, dv/dx, du/dy, dv/dy), clamped to the
+// chain; the lookups on levels floor(lambda) and floor(lambda) + 1 are
+// blended with weights 1 - t and t, t = lambda - floor(lambda).
+template <int FMT, int C, int MODE>
+__global__ __launch_bounds__(256) void k_lookup_lod(LevelSet ls, const float* __restrict__ uv,
+                                                    const float* __restrict__ tbn,
+                                                    const float* __restrict__ view,
+                                                    const float* __restrict__ duv,
+                                                    float* __restrict__ out, FragMap m) {
+    const int64_t f = frag_of(m, blockIdx.x, gridDim.x, threadIdx.x);
+    if (f < 0) return;
+    const Frag g = load_frag(uv, tbn, view, f);
+    const float4 d = ((const float4*)duv)[f];
+    const float ax = d.x * (float)ls.W, ay = d.y * (float)ls.H;
+    const float bx = d.z * (float)ls.W, by = d.w * (float)ls.H;
+    const float rho = fmaxf(sqrtf(ax * ax + ay * ay), sqrtf(bx * bx + by * by));
+    float lambda = 0.f;
+    if (rho > 0.f && rho <= 3.0e38f)
+        lambda = fminf(fmaxf(log2f(rho), 0.f), (float)(ls.levels - 1));
+    int l0 = (int)floorf(lambda);
+    float t = lambda - (float)l0;
+    if (l0 >= ls.levels - 1) {
+        l0 = ls.levels - 1;
+        t = 0.f;
+    }
+    const Dir dd = map_direction(g.m, g.w, ls.n);
+    const Foot p = footprint(dd.sx, dd.sy, ls.n);
+    float a[4] = {0.f, 0.f, 0.f, 0.f}, b[4] = {0.f, 0.f, 0.f, 0.f};
+    level_lookup<FMT, C, MODE>(ls, l0, g, p, a);
+    if (t > 0.f) {
+        level_lookup<FMT, C, MODE>(ls, l0 + 1, g, p, b);
+#pragma unroll
+        for (int c = 0; c < C; c++) a[c] = (1.f - t) * a[c] + t * b[c];
+    }
+    store_out<C>(out, f, a);
+}
+
 template <int FMT, int MODE>
 static hipError_t launch_fwd_c(const TexView& t, const float* uv, const float* tbn,
                                const float* view, float* out, const FragMap& m, hipStream_t s) {
@@ -113,6 +193,36 @@ hipError_t launch_lookup_fwd(const TexView& t, int fmt, int mode, const float* u
     }
     prof_end(K_LOOKUP_FWD, s);
     return e;
+}
+
+template <int FMT, int MODE>
+static void launch_lod_c(const LevelSet& ls, const float* uv, const float* tbn, const float* view,
+                         const float* duv, float* out, const FragMap& m, hipStream_t s) {
+    const uint32_t blocks = fragmap_blocks(m);
+    switch (ls.C) {
+    case 1: hipLaunchKernelGGL((k_lookup_lod<FMT, 1, MODE>), dim3(blocks), dim3(256), 0, s, ls, uv, tbn, view, duv, out, m); break;
+    case 2: hipLaunchKernelGGL((k_lookup_lod<FMT, 2, MODE>), dim3(blocks), dim3(256), 0, s, ls, uv, tbn, view, duv, out, m); break;
+    case 3: hipLaunchKernelGGL((k_lookup_lod<FMT, 3, MODE>), dim3(blocks), dim3(256), 0, s, ls, uv, tbn, view, duv, out, m); break;
+    default: hipLaunchKernelGGL((k_lookup_lod<FMT, 4, MODE>), dim3(blocks), dim3(256), 0, s, ls, uv, tbn, view, duv, out, m); break;
+    }
+}
+
+hipError_t launch_lookup_lod(const LevelSet& ls, int fmt, int mode, const float* uv,
+                             const float* tbn, const float* view, const float* duv, float* out,
+                             const FragMap& m, hipStream_t s) {
+    if (m.N <= 0) return hipSuccess;
+    prof_begin(K_LOOKUP_LOD, s);
+    if (mode == MODE_NEAREST) {
+        if (fmt == FMT_F32) launch_lod_c<FMT_F32, MODE_NEAREST>(ls, uv, tbn, view, duv, out, m, s);
+        else if (fmt == FMT_BF16) launch_lod_c<FMT_BF16, MODE_NEAREST>(ls, uv, tbn, view, duv, out, m, s);
+        else launch_lod_c<FMT_FP8, MODE_NEAREST>(ls, uv, tbn, view, duv, out, m, s);
+    } else {
+        if (fmt == FMT_F32) launch_lod_c<FMT_F32, MODE_BILINEAR>(ls, uv, tbn, view, duv, out, m, s);
+        else if (fmt == FMT_BF16) launch_lod_c<FMT_BF16, MODE_BILINEAR>(ls, uv, tbn, view, duv, out, m, s);
+        else launch_lod_c<FMT_FP8, MODE_BILINEAR>(ls, uv, tbn, view, duv, out, m, s);
+    }
+    prof_end(K_LOOKUP_LOD, s);
+    return hipGetLastError();
 }
 
 hipError_t launch_debug_indices(const TexView& t, const float* uv, const float* tbn,

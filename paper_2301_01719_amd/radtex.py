@@ -31,7 +31,7 @@ EXPORTS = ("rt_create_texture", "rt_destroy_texture", "rt_quantize", "rt_lookup_
            "rt_lookup_bwd_workspace", "rt_lookup_bwd", "rt_debug_indices", "rt_last_error",
            "rt_status_string", "rt_version", "rt_profile_enable", "rt_profile_reset",
            "rt_profile_kernel_count", "rt_profile_kernel_name", "rt_profile_read",
-           "rt_bake_directions", "rt_bake_environment")
+           "rt_bake_directions", "rt_bake_environment", "rt_build_mip", "rt_lookup_fwd_lod")
 
 
 class RadtexError(RuntimeError):
@@ -82,6 +82,9 @@ def _load() -> ctypes.CDLL:
         "rt_profile_kernel_name": ([i32], ctypes.c_char_p),
         "rt_profile_read": ([i32, ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_double)], i32),
         "rt_bake_directions": ([i32, P, P, P], i32),
+        "rt_build_mip": ([P, P, P], i32),
+        "rt_lookup_fwd_lod": ([ctypes.POINTER(P), i32, ctypes.POINTER(Fragments), P, P, u32, P],
+                              i32),
         "rt_bake_environment": ([i32, i32, i32, i32, P, ctypes.POINTER(EnvLobe), i32,
                                  ctypes.POINTER(ctypes.c_float), P, P], i32),
     }
@@ -234,6 +237,50 @@ def debug_indices(tex: Texture, uv, tbn, view, image=None):
     _check(LIB.rt_debug_indices(tex.handle, ctypes.byref(fr), _ptr(idx), _ptr(frac),
                                 _stream(tex.device)))
     return idx, frac
+
+
+def build_mip(tex: Texture, out=None):
+    """The next level of the mip chain of an FP32 texture: [max(1, H/2),
+    max(1, W/2), n, n, C], each bucket the texel-wise mean of the 2 x 2 (or 2)
+    buckets it covers."""
+    W2, H2 = max(1, tex.W // 2), max(1, tex.H // 2)
+    if out is None:
+        out = torch.empty((H2, W2, tex.n, tex.n, tex.C), dtype=torch.float32, device=tex.device)
+    else:
+        _need_gpu(out, "out", torch.float32)
+    _check(LIB.rt_build_mip(tex.handle, _ptr(out), _stream(tex.device)))
+    return out
+
+
+def build_mips(tex: Texture, levels: Optional[int] = None):
+    """The whole chain as Texture handles [level 0 (tex), level 1, ...]; levels
+    defaults to 1 + log2(max(W, H))."""
+    full = 1 + max(tex.W, tex.H).bit_length() - 1
+    levels = full if levels is None else levels
+    chain = [tex]
+    for _ in range(1, levels):
+        prev = chain[-1]
+        data = build_mip(prev)
+        chain.append(Texture(data, max(1, prev.W // 2), max(1, prev.H // 2), prev.n, prev.C))
+    return chain
+
+
+def lookup_fwd_lod(levels, uv, tbn, view, duv, mode: str = "nearest", out=None, image=None):
+    """Lookup over a mip chain (list of Texture, level 0 first) with the level
+    of detail from duv [N, 4] = (du/dx, dv/dx, du/dy, dv/dy) per fragment."""
+    fr = _frags(uv, tbn, view, image)
+    _need_gpu(duv, "duv", torch.float32)
+    if tuple(duv.shape) != (fr.count, 4):
+        raise ValueError(f"duv has shape {tuple(duv.shape)}, expected {(fr.count, 4)}")
+    t0 = levels[0]
+    if out is None:
+        out = torch.empty((fr.count, t0.C), dtype=torch.float32, device=t0.device)
+    else:
+        _need_gpu(out, "out", torch.float32)
+    handles = (ctypes.c_void_p * len(levels))(*[t.handle for t in levels])
+    _check(LIB.rt_lookup_fwd_lod(handles, len(levels), ctypes.byref(fr), _ptr(duv), _ptr(out),
+                                 MODES[mode], _stream(t0.device)))
+    return out
 
 
 def bake_directions(n: int, device="cuda:0"):

@@ -160,16 +160,42 @@ class GBuffer:
     tbn: torch.Tensor   # [N, 3, 3] float32, rows T, B, N
     view: torch.Tensor  # [N, 3] float32, surface -> eye
     image: Optional[Tuple[int, int, int]] = None  # (views, height, width), row-major
+    duv: Optional[torch.Tensor] = None  # [N, 4] float32 du/dx, dv/dx, du/dy, dv/dy per pixel
 
     @property
     def count(self) -> int:
         return int(self.uv.shape[0])
 
     def slice(self, a: int, b: int) -> "GBuffer":
-        return GBuffer(self.uv[a:b], self.tbn[a:b], self.view[a:b])
+        return GBuffer(self.uv[a:b], self.tbn[a:b], self.view[a:b], None,
+                       None if self.duv is None else self.duv[a:b])
 
     def to(self, device) -> "GBuffer":
-        return GBuffer(self.uv.to(device), self.tbn.to(device), self.view.to(device), self.image)
+        return GBuffer(self.uv.to(device), self.tbn.to(device), self.view.to(device), self.image,
+                       None if self.duv is None else self.duv.to(device))
+
+
+def screen_derivatives(uv: torch.Tensor, views: int, height: int, width: int) -> torch.Tensor:
+    """UV screen derivatives of row-major images as a rasteriser's pixel quads
+    give them: central differences of the stored coordinates along x and y
+    (one-sided at the image border), in binary64, stored as float32 [N, 4]
+    (du/dx, dv/dx, du/dy, dv/dy)."""
+    g = uv.to(torch.float64).reshape(views, height, width, 2)
+    dx = torch.empty_like(g)
+    dy = torch.empty_like(g)
+    if width > 1:
+        dx[:, :, 1:-1] = 0.5 * (g[:, :, 2:] - g[:, :, :-2])
+        dx[:, :, 0] = g[:, :, 1] - g[:, :, 0]
+        dx[:, :, -1] = g[:, :, -1] - g[:, :, -2]
+    else:
+        dx.zero_()
+    if height > 1:
+        dy[:, 1:-1] = 0.5 * (g[:, 2:] - g[:, :-2])
+        dy[:, 0] = g[:, 1] - g[:, 0]
+        dy[:, -1] = g[:, -1] - g[:, -2]
+    else:
+        dy.zero_()
+    return torch.cat([dx, dy], dim=-1).reshape(-1, 4).to(torch.float32).contiguous()
 
 
 def flat_gbuffer(N: int, seed: int, device="cpu", min_elev_deg: float = 5.0) -> GBuffer:
@@ -234,8 +260,9 @@ def plane_gbuffer(views: int, width: int, height: int, seed: int, device="cpu",
         tbns.append(tbn)
         viewsl.append(vw.to(torch.float32))
         del eye, d, lam, P, Nv
-    return GBuffer(torch.cat(uvs).contiguous(), torch.cat(tbns).contiguous(),
-                   torch.cat(viewsl).contiguous(), (views, height, width))
+    uv_all = torch.cat(uvs).contiguous()
+    return GBuffer(uv_all, torch.cat(tbns).contiguous(), torch.cat(viewsl).contiguous(),
+                   (views, height, width), screen_derivatives(uv_all, views, height, width))
 
 
 # --- gradient noise height field (C5) -----------------------------------------
@@ -322,7 +349,8 @@ def heightfield_gbuffer(views: int, width: int, height: int, seed: int, device="
             tbn[a:b] = _frame_from_normal(Nv).to(torch.float32)
             vw[a:b] = (-d / torch.linalg.vector_norm(d, dim=1, keepdim=True)).to(torch.float32)
         del d_all
-    return GBuffer(uv, tbn, vw, (views, height, width))
+    return GBuffer(uv, tbn, vw, (views, height, width),
+                   screen_derivatives(uv, views, height, width))
 
 
 def grad_out(N: int, C: int, seed: int, device="cpu") -> torch.Tensor:

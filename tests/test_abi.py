@@ -135,7 +135,9 @@ def test_no_device_or_texture_handle(rt):
         # backward: workspace size and checks
         need = L.rt_lookup_bwd_workspace(h, 10, 0)
         assert need > 0 and need % 256 == 0
-        assert L.rt_lookup_bwd_workspace(h, 10, 1) > need
+        # four records per fragment in the bilinear-bucket mode (once the
+        # records, not the fixed counters, dominate the size)
+        assert L.rt_lookup_bwd_workspace(h, 10000, 1) > L.rt_lookup_bwd_workspace(h, 10000, 0)
         st = L.rt_lookup_bwd(h, ctypes.byref(good), 0x6000, 0x7000, None, None, 0x8000, need - 1,
                              0, None)
         assert st == 4 and "needed" in L.rt_last_error().decode()
@@ -216,3 +218,16 @@ def test_bake_validation(rt):
     assert L.rt_bake_directions(8, None, None, None) == 0  # nothing asked, nothing launched
     if not torch.cuda.is_available():
         assert call() == 5 and "no HIP device" in L.rt_last_error().decode()
+
+
+def test_mip_entries_reject_bad_arguments(rt):
+    L = rt.LIB
+    assert L.rt_build_mip(None, 0x1000, None) == 1
+    assert "texture handle" in L.rt_last_error().decode()
+    fr = _fr(rt, 10, 0x1000, 0x2000, 0x3000)
+    assert L.rt_lookup_fwd_lod(None, 1, ctypes.byref(fr), 0x4000, 0x5000, 0, None) == 1
+    lv = (ctypes.c_void_p * 2)(None, None)
+    assert L.rt_lookup_fwd_lod(lv, 0, ctypes.byref(fr), 0x4000, 0x5000, 0, None) == 1
+    assert L.rt_lookup_fwd_lod(lv, 18, ctypes.byref(fr), 0x4000, 0x5000, 0, None) == 2
+    assert L.rt_lookup_fwd_lod(lv, 2, ctypes.byref(fr), 0x4000, 0x5000, 0, None) == 1
+    assert "level 0 is NULL" in L.rt_last_error().decode()

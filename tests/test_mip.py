@@ -1,0 +1,153 @@
+"""Minification across the bucket matrix on the GPU: the mip chain of bucket
+matrices and the level-of-detail lookup against the FP64 oracle.
+
+Tolerances.  A level is ((a + b) + (c + d)) / 4 in binary32: three roundings
+of relative size 2^-24 of the level's magnitude, and averaging does not grow
+the error carried from the level below, so level l is within l 2e-7 of the
+exact means times the largest |texel| of level 0.  The level-of-detail lookup
+compares with the oracle's exact chain: that error plus the forward's own
+(1e-5 in all); fragments whose unclamped lambda lies within 1e-5 of an
+integer (where binary32 and binary64 may pick different levels) or whose
+indices lie within 1e-6 of a cell edge are left out, as for the forward.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from helpers import away_from_edges, gb_host, host
+from paper_2301_01719_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def rt():
+    from paper_2301_01719_amd import radtex
+    return radtex
+
+
+def _levels(W, H):
+    return 1 + int(math.log2(max(W, H)))
+
+
+@pytest.mark.parametrize("W,H,n,C", [(16, 8, 4, 4), (1, 16, 3, 3), (32, 32, 5, 1), (8, 1, 2, 2),
+                                     (64, 16, 16, 4)])
+def test_build_mip_chain_vs_oracle(rt, W, H, n, C):
+    g = torch.Generator().manual_seed(W * 3 + H)
+    base = (torch.rand((H, W, n, n, C), generator=g) * 4 - 2).to(DEV)
+    chain = rt.build_mips(rt.Texture(base, W, H, n, C))
+    torch.cuda.synchronize()
+    ref = oracle.build_mips(host(base), W, H, n, C, _levels(W, H))
+    assert len(chain) == len(ref)
+    amax = float(base.abs().max())
+    for l, (t, r) in enumerate(zip(chain, ref)):
+        assert tuple(t.data.shape) == r.shape
+        err = np.max(np.abs(host(t.data).astype(np.float64) - r))
+        assert err <= l * 2e-7 * amax + 1e-30, (l, err)
+
+
+def _lod_keep(duv, W, H):
+    """Fragments whose unclamped level of detail log2(rho) is at least 1e-5
+    from an integer (there binary32 and binary64 may pick different levels)."""
+    d = duv.astype(np.float64)
+    rho = np.maximum(np.hypot(d[:, 0] * W, d[:, 1] * H), np.hypot(d[:, 2] * W, d[:, 3] * H))
+    with np.errstate(divide="ignore"):
+        lam = np.log2(rho)
+    return ~np.isfinite(lam) | (np.abs(lam - np.round(lam)) >= 1e-5)
+
+
+def _views_case(seed, W, H, n, C):
+    gb = wl.plane_gbuffer(2, 61, 37, seed=seed, device=DEV)
+    tex = wl.smooth_texture(W, H, n, C, seed=seed + 1, device=DEV)
+    # footprints from the camera, scaled per fragment over the whole chain
+    g = torch.Generator().manual_seed(seed + 2)
+    scale = torch.exp2(torch.rand((gb.count, 1), generator=g) * 12 - 4).to(DEV)
+    duv = (gb.duv * scale).contiguous()
+    return gb, tex, duv
+
+
+@pytest.mark.parametrize("mode", ["nearest", "bilinear"])
+def test_lod_lookup_vs_oracle(rt, mode):
+    W, H, n, C = 64, 32, 8, 4
+    gb, tex, duv = _views_case(41, W, H, n, C)
+    chain = rt.build_mips(rt.Texture(tex, W, H, n, C))
+    out = rt.lookup_fwd_lod(chain, gb.uv, gb.tbn, gb.view, duv, mode, image=gb.image)
+    torch.cuda.synchronize()
+    uv, tbn, view = gb_host(gb)
+    och = oracle.build_mips(host(tex), W, H, n, C, _levels(W, H))
+    omode = oracle.MODE_NEAREST if mode == "nearest" else oracle.MODE_BILINEAR
+    ref, lam = oracle.lookup_lod(och, uv, tbn, view, host(duv), W, H, n, C, omode)
+    keep = away_from_edges(uv, tbn, view, W, H, n, mode) & _lod_keep(host(duv), W, H)
+    assert keep.mean() > 0.9 and np.ptp(lam) > 4  # the footprints span the chain
+    err = np.max(np.abs(host(out).astype(np.float64)[keep] - ref[keep]))
+    assert err <= 1e-5, err
+
+
+@pytest.mark.parametrize("fmt", ["f32", "bf16"])
+def test_lod_lookup_at_whole_levels_is_that_levels_lookup(rt, fmt):
+    """At an integer level of detail (or below one bucket per pixel) the
+    chain's lookup is the plain lookup of that one level, bit for bit."""
+    W, H, n, C = 32, 16, 8, 4
+    gb, tex, _ = _views_case(43, W, H, n, C)
+    chain = rt.build_mips(rt.Texture(tex, W, H, n, C))
+    if fmt != "f32":
+        q = []
+        for t in chain:
+            c, s = rt.quantize(t, fmt)
+            q.append(rt.Texture(c, t.W, t.H, n, C, fmt, s))
+        chain = q
+    N = gb.count
+    for k in range(len(chain)):
+        duv = torch.tensor([2.0 ** k / W, 0.0, 0.0, 2.0 ** k / H], device=DEV).repeat(N, 1)
+        got = rt.lookup_fwd_lod(chain, gb.uv, gb.tbn, gb.view, duv)
+        ref = rt.lookup_fwd(chain[k], gb.uv, gb.tbn, gb.view)
+        torch.cuda.synchronize()
+        assert torch.equal(got, ref), k
+    duv = torch.tensor([0.3 / W, 0.1 / H, 0.0, 0.5 / H], device=DEV).repeat(N, 1)
+    assert torch.equal(rt.lookup_fwd_lod(chain, gb.uv, gb.tbn, gb.view, duv),
+                       rt.lookup_fwd(chain[0], gb.uv, gb.tbn, gb.view))
+
+
+def test_lod_full_size_sampled(rt):
+    """The single-view workload: the whole chain of its 1024 x 1024 matrix and
+    the level-of-detail lookup of its 1920 x 1080 view with the camera's own
+    UV derivatives, sampled against the oracle's chain."""
+    w = wl.WORKLOADS["c2"]
+    W, H, n, C = w.W, w.H, w.n, w.C
+    tex = w.make_texture(DEV)
+    gb = w.make_gbuffer(DEV)
+    chain = rt.build_mips(rt.Texture(tex, W, H, n, C))
+    out = rt.lookup_fwd_lod(chain, gb.uv, gb.tbn, gb.view, gb.duv, image=gb.image)
+    torch.cuda.synchronize()
+    sel = np.sort(np.random.default_rng(5).choice(gb.count, 50000, replace=False))
+    st = torch.from_numpy(sel).to(DEV)
+    uv, tbn, view, duv, got = (host(t[st]) for t in (gb.uv, gb.tbn, gb.view, gb.duv, out))
+    och = oracle.build_mips(host(tex), W, H, n, C, _levels(W, H))
+    ref, lam = oracle.lookup_lod(och, uv, tbn, view, duv, W, H, n, C)
+    keep = away_from_edges(uv, tbn, view, W, H, n) & _lod_keep(duv, W, H)
+    err = np.max(np.abs(got.astype(np.float64)[keep] - ref[keep]))
+    print(f"lod full size: lambda {lam.min():.2f}..{lam.max():.2f}, max err {err:.2e}")
+    assert err <= 1e-5
+
+
+def test_lod_validation(rt):
+    W, H, n, C = 16, 8, 4, 4
+    tex = torch.rand((H, W, n, n, C), device=DEV)
+    chain = rt.build_mips(rt.Texture(tex, W, H, n, C))
+    gb = wl.flat_gbuffer(64, seed=1, device=DEV)
+    duv = torch.zeros((64, 4), device=DEV)
+    with pytest.raises(rt.RadtexError, match="level 1 is"):
+        rt.lookup_fwd_lod([chain[0], chain[2]], gb.uv, gb.tbn, gb.view, duv)
+    with pytest.raises(rt.RadtexError, match="exceed the chain"):
+        rt.lookup_fwd_lod(chain + [chain[-1]], gb.uv, gb.tbn, gb.view, duv)
+    odd = rt.Texture(torch.rand((3, 5, n, n, C), device=DEV), 5, 3, n, C)
+    with pytest.raises(rt.RadtexError, match="powers of two"):
+        rt.build_mip(odd)
+    with pytest.raises(rt.RadtexError, match="FP32"):
+        c, _ = rt.quantize(chain[0], "bf16")
+        rt.build_mip(rt.Texture(c, W, H, n, C, "bf16"))
