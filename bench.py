@@ -44,7 +44,7 @@ BAKE_AMBIENT = (0.05, 0.05, 0.05, 0.0)
 METRIC = "lookups/s + % HBM peak, fwd & bwd; FP32 vs BF16/FP8 texture at stated error"
 HBM_PEAK_GBS = 8000.0
 KERNEL_SOURCES = ["rt_device.hpp", "rt_lookup.hip", "rt_quantize.hip", "rt_backward.hip",
-                  "rt_bake.hip"]
+                  "rt_bake.hip", "rt_mip.hip"]
 
 
 def source_hash() -> str:
@@ -83,6 +83,7 @@ def parse():
     ap.add_argument("--storage", default="bf16", choices=["f32", "bf16", "fp8"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-bake", action="store_true", help="skip the bake measurement")
+    ap.add_argument("--no-mip", action="store_true", help="skip the mip-chain measurement")
     ap.add_argument("--graph", action="store_true",
                     help="time replays of the step captured in a HIP graph (same kernels, no "
                          "host launch gaps; measured equal to eager launches on this workload)")
@@ -91,6 +92,9 @@ def parse():
                     help="run only this many steps (for rocprofv3) and print the line")
     ap.add_argument("--profile-bake", type=int, default=0,
                     help="with --profile-steps: also run this many bakes of the matrix")
+    ap.add_argument("--profile-mip", type=int, default=0,
+                    help="with --profile-steps: also build the mip chain and run the "
+                         "level-of-detail lookup this many times")
     return ap.parse_args()
 
 
@@ -165,6 +169,13 @@ def main():
             dst = torch.empty_like(tex32)
             for _ in range(args.profile_bake):
                 rt.bake_environment(W, H, n, C, BAKE_LOBES, BAKE_AMBIENT, out=dst)
+            del dst
+        if args.profile_mip and gb.duv is not None:
+            chain = rt.build_mips(master)
+            for _ in range(args.profile_mip):
+                for l in range(1, len(chain)):
+                    rt.build_mip(chain[l - 1], out=chain[l].data)
+                rt.lookup_fwd_lod(chain, gb.uv, gb.tbn, gb.view, gb.duv, out=out, image=gb.image)
         torch.cuda.synchronize()
         print(json.dumps({"profile_steps": args.profile_steps, "workload": w.name}), flush=True)
         return
@@ -336,6 +347,53 @@ def main():
                         "along every sample's reflection vector (Eqs. 4a, 4b), identity frames"}
         del dst
 
+    # ---- minification: the mip chain and the level-of-detail lookup ---------
+    mip = None
+    pow2 = lambda v: v > 0 and (v & (v - 1)) == 0
+    if not args.no_mip and gb.duv is not None and pow2(W) and pow2(H):
+        chain = rt.build_mips(master)
+        L = len(chain)
+        torch.cuda.synchronize()
+        rt.profile_reset()
+        rt.profile_enable(True)
+        reps = 5
+        for _ in range(reps):
+            for l in range(1, L):
+                rt.build_mip(chain[l - 1], out=chain[l].data)
+        torch.cuda.synchronize()
+        rt.profile_enable(False)
+        launches, total = rt.profile_read()["k_build_mip"]
+        build_ms = total / reps
+        lvl_bytes = [t.W * t.H * n * n * C * 4 for t in chain]
+        build_bytes = sum(lvl_bytes[:-1]) + sum(lvl_bytes[1:])  # each level read, the next written
+        o = torch.empty_like(out)
+        for _ in range(3):
+            rt.lookup_fwd_lod(chain, gb.uv, gb.tbn, gb.view, gb.duv, out=o, image=gb.image)
+        torch.cuda.synchronize()
+        ms = []
+        for _ in range(30):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            rt.lookup_fwd_lod(chain, gb.uv, gb.tbn, gb.view, gb.duv, out=o, image=gb.image)
+            b.record()
+            b.synchronize()
+            ms.append(a.elapsed_time(b))
+        q = [round(float(x), 5) for x in np.percentile(np.array(ms), [10, 50, 90])]
+        d = gb.duv.to(torch.float64)
+        rho = torch.maximum(torch.hypot(d[:, 0] * W, d[:, 1] * H), torch.hypot(d[:, 2] * W, d[:, 3] * H))
+        lam = torch.clamp(torch.log2(rho), 0, L - 1)
+        mip = {"levels": L, "build_chain_ms": round(build_ms, 5), "build_alg_bytes": build_bytes,
+               "build_GBps": round(build_bytes / (build_ms * 1e-3) / 1e9, 1),
+               "build_hbm_frac": round(build_bytes / (build_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+               "lod_fwd_ms_p10_p50_p90": q,
+               "lod_fwd_lookups_per_s": round(N / (q[1] * 1e-3), 1),
+               "plain_fwd_f32_ms": formats["f32"]["fwd_ms"],
+               "lambda_min_mean_max": [round(float(lam.min()), 3), round(float(lam.mean()), 3),
+                                       round(float(lam.max()), 3)],
+               "note": "FP32 chain of the whole matrix; the lookup takes each pixel's UV "
+                       "derivatives from the G-buffer (central differences)"}
+        del chain, o
+
     # ---- the FP64 oracle on a bounded sample (CPU baseline and error) -------
     cpu = None
     errors = None
@@ -401,6 +459,7 @@ def main():
         "kernels": per_kernel,
         "formats": formats,
         "bake": bake,
+        "mip": mip,
         "errors": errors,
         "unique_texels_touched": uniq_texels,
         "source_hash": source_hash(),
