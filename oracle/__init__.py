@@ -13,7 +13,8 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liboracle.so")
 
-FMT_F32, FMT_BF16, FMT_FP8_E4M3, FMT_F64 = 0, 1, 2, 3
+FMT_F32, FMT_BF16, FMT_FP8_E4M3, FMT_F64, FMT_BIT1 = 0, 1, 2, 3, 4
+LIGHT_DIRECTIONAL, LIGHT_POINT = 0, 1
 MODE_NEAREST, MODE_BILINEAR = 0, 1
 
 _lib = None
@@ -58,6 +59,10 @@ def _load():
     lib.orc_lod.argtypes = [P, i32, i32, i32]
     lib.orc_lod.restype = d
     lib.orc_lookup_lod.argtypes = [i64, P, P, P, P, i32, i32, i32, i32, i32, P, i32, P, P]
+    lib.orc_pack_bits.argtypes = [P, i64, i32, P]
+    lib.orc_lookup_light.argtypes = [i64, P, P, P, i32, i32, P, i32, i32, i32, i32, i32, P, P,
+                                     i32, P]
+    lib.orc_bake_shadow.argtypes = [i32, i32, i32, P, P, P, i32, P, P]
     _lib = lib
     return lib
 
@@ -178,9 +183,12 @@ class Tex:
 
     def __init__(self, data, W, H, n, C, fmt=FMT_F32, scales=None):
         dt = {FMT_F32: np.float32, FMT_BF16: np.uint16, FMT_FP8_E4M3: np.uint8,
-              FMT_F64: np.float64}[fmt]
+              FMT_F64: np.float64, FMT_BIT1: np.uint32}[fmt]
         self.data = _c(data, dt).reshape(-1)
-        assert self.data.size == W * H * n * n * C, (self.data.size, W, H, n, C)
+        if fmt == FMT_BIT1:
+            assert C == 1 and self.data.size == W * H * words_per_bucket(n), (self.data.size, n)
+        else:
+            assert self.data.size == W * H * n * n * C, (self.data.size, W, H, n, C)
         self.W, self.H, self.n, self.C, self.fmt = int(W), int(H), int(n), int(C), fmt
         self.scales = None if scales is None else _c(scales, np.float32).reshape(-1)
         if fmt == FMT_FP8_E4M3:
@@ -349,3 +357,59 @@ def lookup_lod(chain, uv, tbn, view, duv, W, H, n, C, mode=MODE_NEAREST):
     _load().orc_lookup_lod(N, _p(uv), _p(tbn), _p(view), _p(duv), int(W), int(H), int(n),
                            int(C), len(chain), _p(flat), int(mode), _p(out), _p(lam))
     return out, lam
+
+
+# --- shadowing: 1-bit textures and the light-direction lookup -------------------
+
+def words_per_bucket(n):
+    """32-bit words of one bucket of the 1-bit storage: ceil(n n / 32)."""
+    return (int(n) * int(n) + 31) // 32
+
+
+def pack_bits(tex, n):
+    """1-bit storage of a one-channel texture [..., n, n] (or [..., n, n, 1])
+    float32: per bucket, sample k = y n + x is bit k % 32 of word k / 32, set
+    iff the value is >= 1/2; returns uint32 words [buckets * ceil(n n/32)]."""
+    t = _c(tex, np.float32).reshape(-1)
+    nn = int(n) * int(n)
+    assert t.size % nn == 0
+    nb = t.size // nn
+    out = np.empty(nb * words_per_bucket(n), np.uint32)
+    _load().orc_pack_bits(_p(t), nb, nn, _p(out))
+    return out
+
+
+def lookup_light(tex: Tex, uv, tbn, vec, kind=LIGHT_DIRECTIONAL, pos=None, mode=MODE_NEAREST):
+    """Mean over the light samples of the lookup taken with the direction
+    toward the light: vec [S, 3] float32 holds directions (directional light)
+    or sample points (point light; L = vec[s] - pos[f], pos [N, 3] float32).
+    Returns [N, C] float64."""
+    uv = _c(uv, np.float32).reshape(-1, 2)
+    tbn = _c(tbn, np.float32).reshape(-1, 9)
+    vec = _c(vec, np.float32).reshape(-1, 3)
+    N = uv.shape[0]
+    if kind == LIGHT_POINT:
+        pos = _c(pos, np.float32).reshape(-1, 3)
+        assert pos.shape[0] == N
+    else:
+        pos = None
+    out = np.empty((N, tex.C), np.float64)
+    _load().orc_lookup_light(N, _p(uv), _p(tbn), _p(pos), int(kind), vec.shape[0], _p(vec),
+                             *tex.args(), int(mode), _p(out))
+    return out
+
+
+def bake_shadow(W, H, n, origins, spheres, frames=None):
+    """1-bit shadow texture of analytic occluders: (words [H W ceil(n n/32)]
+    uint32, margin [H, W, n, n] float64).  origins [H, W, 3] float32 scene
+    points of the buckets, spheres [K, 4] float32 (centre, radius), frames
+    [H, W, 3, 3] float32 rows T, B, N or None (identity)."""
+    origins = _c(origins, np.float32).reshape(H * W * 3)
+    spheres = _c(spheres, np.float32).reshape(-1, 4)
+    if frames is not None:
+        frames = _c(frames, np.float32).reshape(H * W * 9)
+    words = np.empty(W * H * words_per_bucket(n), np.uint32)
+    margin = np.empty((H, W, n, n), np.float64)
+    _load().orc_bake_shadow(int(W), int(H), int(n), _p(origins), _p(frames), _p(spheres),
+                            spheres.shape[0], _p(words), _p(margin))
+    return words, margin

@@ -30,6 +30,11 @@
  *                             (Eqs. (4a), (4b)) carried to scene coordinates
  *                             by the bucket frame; an analytic environment
  *                             stands in for the ray-traced radiance
+ *   shadowing                 Sec. 5 (Shadowing): 1-bit storage, the lookup
+ *                             with the light direction in place of the
+ *                             incidence, averaged over an area light's
+ *                             samples; analytic occluders stand in for the
+ *                             ray-traced visibility of the bake
  *
  * Readings of points the paper leaves open (texel-centre convention, UV wrap,
  * axis orientation, the A = 0 case of Eq. (3), the storage formats) are listed
@@ -51,6 +56,7 @@
 #define ORC_FMT_BF16 1
 #define ORC_FMT_FP8_E4M3 2
 #define ORC_FMT_F64 3 /* oracle-only: for finite differences w.r.t. texels */
+#define ORC_FMT_BIT1 4 /* one bit per sample, bucket-major words (Sec. 5, Shadowing) */
 
 #define ORC_MODE_NEAREST 0
 #define ORC_MODE_BILINEAR 1
@@ -422,6 +428,14 @@ static double texel(const tex_t *t, int i, int j, int y, int x, int c)
         return orc_bf16_to_f64(((const uint16_t *)t->data)[e]);
     case ORC_FMT_FP8_E4M3:
         return orc_e4m3_to_f64(((const uint8_t *)t->data)[e]) * (double)t->scales[b];
+    case ORC_FMT_BIT1: {
+        /* one channel; sample k = y n + x of bucket b is bit k % 32 of word
+         * b wpb + k / 32, wpb = ceil(n n / 32) words per bucket */
+        int64_t wpb = ((int64_t)t->n * t->n + 31) / 32;
+        int64_t k = (int64_t)y * t->n + x;
+        uint32_t w = ((const uint32_t *)t->data)[b * wpb + k / 32];
+        return (double)((w >> (k % 32)) & 1u);
+    }
     default:
         return ((const double *)t->data)[e];
     }
@@ -1020,4 +1034,135 @@ void orc_lookup_lod(int64_t N, const float *uv, const float *tbn, const float *v
             out[f * C + c] = t > 0.0 ? (1.0 - t) * a[c] + t * b[c] : a[c];
     }
     free(lv);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Shadowing (Sec. 5, Shadowing): a 1-bit radiance texture holds the         */
+/* occlusion of static geometry, and the lookup takes the direction toward   */
+/* the light in place of the incidence vector; several light directions per */
+/* fragment, averaged, give an area light's soft shadow.                     */
+/* ------------------------------------------------------------------------- */
+
+/* The 1-bit storage: each sample becomes the bit (x >= 1/2), NaN giving 0.
+ * Bucket b of nn = n n samples occupies wpb = ceil(nn / 32) words; sample k
+ * is bit k % 32 of word b wpb + k / 32 and the bits past nn are zero. */
+void orc_pack_bits(const float *tex, int64_t n_buckets, int nn, uint32_t *words)
+{
+    int64_t wpb = ((int64_t)nn + 31) / 32;
+#pragma omp parallel for schedule(static)
+    for (int64_t b = 0; b < n_buckets; b++) {
+        for (int64_t w = 0; w < wpb; w++)
+            words[b * wpb + w] = 0u;
+        for (int k = 0; k < nn; k++)
+            if (tex[b * nn + k] >= 0.5f)
+                words[b * wpb + k / 32] |= 1u << (k % 32);
+    }
+}
+
+/* Light lookup: for fragment f and light sample s the direction toward the
+ * light is L = vec[s] (kind 0, a directional light: the same for every
+ * fragment) or L = vec[s] - pos[f] (kind 1, a point light sampled at the
+ * points vec[s]); the lookup of Sec. 2 and 2.1 is taken with L in place of
+ * the view vector, and out[f][c] is the mean over the S samples. */
+void orc_lookup_light(int64_t N, const float *uv, const float *tbn, const float *pos, int kind,
+                      int S, const float *vec, int W, int H, int n, int C, int fmt,
+                      const void *data, const float *scales, int mode, double *out)
+{
+    tex_t t = {W, H, n, C, fmt, data, scales};
+#pragma omp parallel for schedule(static)
+    for (int64_t f = 0; f < N; f++) {
+        double U[2] = {uv[2 * f], uv[2 * f + 1]};
+        double M[9];
+        for (int k = 0; k < 9; k++)
+            M[k] = tbn[9 * f + k];
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int s = 0; s < S; s++) {
+            double L[3], v[4];
+            for (int k = 0; k < 3; k++)
+                L[k] = kind == 0 ? (double)vec[3 * s + k]
+                                 : (double)vec[3 * s + k] - (double)pos[3 * f + k];
+            lookup_one(&t, U, M, L, mode, v);
+            for (int c = 0; c < C; c++)
+                acc[c] += v[c];
+        }
+        for (int c = 0; c < C; c++)
+            out[f * C + c] = acc[c] / S;
+    }
+}
+
+/* Whether the ray o + t d, t > 0, meets the closed ball (c, r): with d a unit
+ * vector, t* = d . (c - o) is the ray parameter of the line's point nearest
+ * c and h2 = |c - o|^2 - t*^2 its squared distance from c; the ray meets the
+ * ball iff o is inside it, or t* > 0 and h2 <= r^2.  *margin receives
+ * | sqrt(h2) - r | when t* > 0 (how far the ray is from grazing the sphere),
+ * and +inf otherwise. */
+static int ray_meets_ball(const double o[3], const double d[3], const double c[3], double r,
+                          double *margin)
+{
+    double oc[3] = {c[0] - o[0], c[1] - o[1], c[2] - o[2]};
+    double l2 = oc[0] * oc[0] + oc[1] * oc[1] + oc[2] * oc[2];
+    double ts = d[0] * oc[0] + d[1] * oc[1] + d[2] * oc[2];
+    *margin = INFINITY;
+    if (l2 <= r * r)
+        return 1;
+    if (ts <= 0.0)
+        return 0;
+    double h2 = l2 - ts * ts;
+    if (h2 < 0.0)
+        h2 = 0.0;
+    *margin = fabs(sqrt(h2) - r);
+    return h2 <= r * r;
+}
+
+/* Bake of a 1-bit shadow texture from analytic occluders (balls) standing in
+ * for ray-traced visibility: bucket (i, j) sits at the scene point
+ * origins[j][i] with frame M = frames[j][i] (rows T, B, N; NULL: identity);
+ * sample (x, y) is lit (bit 1) iff the ray from the origin along M^T I(x, y)
+ * meets none of the K balls spheres[k] = (centre x, y, z, radius), I(x, y)
+ * being the incidence of the sample centre (Eq. (4a) then Eq. (2c)): the
+ * direction that the light lookup maps onto that sample.  words as in
+ * orc_pack_bits; margin[(j W + i) n n + y n + x] (if not NULL) receives the
+ * smallest grazing margin of that sample's ray over the balls. */
+void orc_bake_shadow(int W, int H, int n, const float *origins, const float *frames,
+                     const float *spheres, int K, uint32_t *words, double *margin)
+{
+    int nn = n * n;
+    int64_t wpb = ((int64_t)nn + 31) / 32;
+    double *I = (double *)malloc(sizeof(double) * 3 * nn);
+    if (!I)
+        return;
+    orc_bake_directions(n, I, NULL);
+#pragma omp parallel for schedule(static)
+    for (int64_t b = 0; b < (int64_t)W * H; b++) {
+        double M[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
+        if (frames)
+            for (int k = 0; k < 9; k++)
+                M[k] = frames[b * 9 + k];
+        double o[3] = {origins[b * 3 + 0], origins[b * 3 + 1], origins[b * 3 + 2]};
+        for (int64_t w = 0; w < wpb; w++)
+            words[b * wpb + w] = 0u;
+        for (int s = 0; s < nn; s++) {
+            const double *q = I + 3 * s;
+            double d[3];
+            for (int k = 0; k < 3; k++) /* (M^T q)_k */
+                d[k] = M[0 * 3 + k] * q[0] + M[1 * 3 + k] * q[1] + M[2 * 3 + k] * q[2];
+            double len = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+            for (int k = 0; k < 3; k++)
+                d[k] /= len;
+            int hit = 0;
+            double mg = INFINITY;
+            for (int k = 0; k < K; k++) {
+                double c[3] = {spheres[4 * k], spheres[4 * k + 1], spheres[4 * k + 2]};
+                double m1;
+                hit |= ray_meets_ball(o, d, c, spheres[4 * k + 3], &m1);
+                if (m1 < mg)
+                    mg = m1;
+            }
+            if (!hit)
+                words[b * wpb + s / 32] |= 1u << (s % 32);
+            if (margin)
+                margin[b * nn + s] = mg;
+        }
+    }
+    free(I);
 }

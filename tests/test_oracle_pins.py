@@ -871,3 +871,276 @@ def test_level_lookup_is_the_mean_of_plain_lookups_over_its_buckets():
             base = oracle.lookup_fwd(otex, uvs, np.repeat(tbn[f:f + 1], len(uvs), 0),
                                      np.repeat(view[f:f + 1], len(uvs), 0))
             np.testing.assert_allclose(got, base.mean(0), atol=1e-12)
+
+
+# --------------------------------------------------------------------------
+# Shadowing (Sec. 5, Shadowing): 1-bit storage, the lookup with the light
+# direction in place of the incidence, and an analytic occluder bake
+# --------------------------------------------------------------------------
+
+def _packbits_reference(x, n):
+    """numpy's own bit packer: per bucket the n n flags (x >= 1/2) padded with
+    zeros to whole 32-bit words, least significant bit first."""
+    nn = n * n
+    wpb = (nn + 31) // 32
+    flags = (x.reshape(-1, nn) >= 0.5)
+    padded = np.zeros((flags.shape[0], wpb * 32), bool)
+    padded[:, :nn] = flags
+    return np.packbits(padded, axis=1, bitorder="little").view("<u4").reshape(-1)
+
+
+@pytest.mark.parametrize("n", [1, 3, 5, 8, 16, 31, 32])
+def test_pack_bits_matches_numpy_packbits(n):
+    rng = np.random.default_rng(n)
+    x = rng.uniform(-0.5, 1.5, (3, 4, n, n)).astype(np.float32)
+    flat = x.reshape(-1)
+    special = np.array([0.5, np.nextafter(np.float32(0.5), np.float32(0)), np.nan, np.inf,
+                        -np.inf, -0.0, 1.0, 0.0], np.float32)
+    flat[:min(flat.size, special.size)] = special[:flat.size]
+    got = oracle.pack_bits(x, n)
+    np.testing.assert_array_equal(got, _packbits_reference(x, n))
+    # 0.5 is lit, its predecessor and NaN are not
+    assert got[0] & 1 == 1
+    if n * n > 2:
+        assert (got[0] >> 1) & 1 == 0 and (got[0] >> 2) & 1 == 0
+
+
+@pytest.mark.parametrize("mode", [oracle.MODE_NEAREST, oracle.MODE_BILINEAR])
+def test_bit_texture_reads_as_its_zero_one_texture(mode):
+    # the 1-bit decode returns exactly the flag, so a 1-bit texture looks up
+    # as the binary32 texture of its zeros and ones
+    rng = np.random.default_rng(11)
+    W, H, n, N = 5, 3, 6, 400
+    x = rng.uniform(0, 1, (H, W, n, n)).astype(np.float32)
+    zo = (x >= 0.5).astype(np.float32)
+    bits = oracle.Tex(oracle.pack_bits(x, n), W, H, n, 1, oracle.FMT_BIT1)
+    ref = oracle.Tex(zo, W, H, n, 1)
+    uv = rng.uniform(-1, 2, (N, 2)).astype(np.float32)
+    tbn = np.stack([_rand_rot(rng) for _ in range(N)]).astype(np.float32)
+    view = rng.normal(size=(N, 3)).astype(np.float32)
+    np.testing.assert_array_equal(oracle.lookup_fwd(bits, uv, tbn, view, mode),
+                                  oracle.lookup_fwd(ref, uv, tbn, view, mode))
+
+
+def _light_case(seed, W=4, H=3, n=8, C=2, N=200):
+    rng = np.random.default_rng(seed)
+    tex = oracle.Tex(rng.uniform(0, 1, (H, W, n, n, C)).astype(np.float32), W, H, n, C)
+    uv = rng.uniform(-1, 2, (N, 2)).astype(np.float32)
+    tbn = np.stack([_rand_rot(rng) for _ in range(N)]).astype(np.float32)
+    return rng, tex, uv, tbn
+
+
+@pytest.mark.parametrize("mode", [oracle.MODE_NEAREST, oracle.MODE_BILINEAR])
+def test_one_light_sample_is_the_view_lookup(mode):
+    # one directional sample: the lookup of Sec. 2.1 with that direction as
+    # the incidence; a point light whose sample sits at pos + V (dyadic
+    # values, so the difference is exact in binary32) gives the lookup of V
+    rng, tex, uv, tbn = _light_case(12)
+    N = uv.shape[0]
+    L = np.array([[0.3, -0.2, 0.9]], np.float32)
+    np.testing.assert_allclose(
+        oracle.lookup_light(tex, uv, tbn, L, oracle.LIGHT_DIRECTIONAL, mode=mode),
+        oracle.lookup_fwd(tex, uv, tbn, np.repeat(L, N, 0), mode), atol=1e-15)
+    V = (rng.integers(-64, 65, (N, 3)) / 64.0).astype(np.float32)
+    V[np.all(V == 0, axis=1)] = [0, 0, 1]
+    Q = np.array([[1.5, -2.25, 3.0]], np.float32)
+    pos = (Q - V).astype(np.float32)
+    assert np.array_equal(Q - pos, V)
+    np.testing.assert_allclose(
+        oracle.lookup_light(tex, uv, tbn, Q, oracle.LIGHT_POINT, pos=pos, mode=mode),
+        oracle.lookup_fwd(tex, uv, tbn, V, mode), atol=1e-15)
+
+
+@pytest.mark.parametrize("n", [3, 8, 16])
+def test_light_toward_a_sample_reads_that_samples_bit(n):
+    # a light along the scene direction M^T I(x, y) of sample (x, y) (I from
+    # Eqs. (4a), (2c)) is mapped onto that sample's centre, so a 1-bit texture
+    # returns the sample's flag; a point light reaches it from any distance
+    # along that direction, and the opposite direction does not
+    rng = np.random.default_rng(13 + n)
+    x = rng.uniform(0, 1, (1, 1, n, n)).astype(np.float32)
+    tex = oracle.Tex(oracle.pack_bits(x, n), 1, 1, n, 1, oracle.FMT_BIT1)
+    inc, _ = oracle.bake_directions(n)
+    M = _rand_rot(rng).T
+    uv = np.array([[0.25, 0.75]], np.float32)
+    tbn = M.astype(np.float32)[None]
+    P = np.array([[0.5, -1.0, 2.0]], np.float32)
+    flips = 0
+    for y in range(n):
+        for xx in range(n):
+            d = (tbn[0].astype(np.float64).T @ inc[y, xx]).astype(np.float32)[None]
+            want = float(x[0, 0, y, xx] >= 0.5)
+            got = oracle.lookup_light(tex, uv, tbn, d, oracle.LIGHT_DIRECTIONAL)[0, 0]
+            assert abs(got - want) <= 1e-5, (y, xx, got, want)
+            Q = (P.astype(np.float64) + 3.0 * d).astype(np.float32)
+            got = oracle.lookup_light(tex, uv, tbn, Q, oracle.LIGHT_POINT, pos=P)[0, 0]
+            assert abs(got - want) <= 1e-5, (y, xx, got, want)
+            away = oracle.lookup_light(tex, uv, tbn, -d, oracle.LIGHT_DIRECTIONAL)[0, 0]
+            flips += abs(away - want) > 1e-3
+    if n >= 8:
+        assert flips > 0  # the light's sign matters
+
+
+def test_area_light_is_the_mean_of_its_samples():
+    # directions aimed at three lit samples and one dark sample read 3/4; at
+    # one lit and two dark, 1/3; the order of the samples does not matter
+    n = 8
+    x = np.zeros((1, 1, n, n), np.float32)
+    x[0, 0, 2, 3] = x[0, 0, 5, 5] = x[0, 0, 6, 1] = 1.0
+    tex = oracle.Tex(oracle.pack_bits(x, n), 1, 1, n, 1, oracle.FMT_BIT1)
+    inc, _ = oracle.bake_directions(n)
+    uv = np.array([[0.5, 0.5]], np.float32)
+    tbn = np.eye(3, dtype=np.float32)[None]
+    d = lambda y, xx: inc[y, xx].astype(np.float32)
+    L1 = np.stack([d(2, 3), d(5, 5), d(6, 1), d(4, 4)])
+    assert abs(oracle.lookup_light(tex, uv, tbn, L1)[0, 0] - 0.75) <= 1e-6
+    L2 = np.stack([d(0, 0), d(6, 1), d(7, 7)])
+    assert abs(oracle.lookup_light(tex, uv, tbn, L2)[0, 0] - 1 / 3) <= 1e-6
+    assert abs(oracle.lookup_light(tex, uv, tbn, L2[::-1].copy())[0, 0] - 1 / 3) <= 1e-6
+
+
+def _cone_hits(o, d, c, r):
+    """Whether the ray o + t d (t > 0, d unit) meets the ball (c, r), by the
+    cone the ball subtends at o: the origin is inside, or the angle between d
+    and c - o is at most asin(r / |c - o|).  Also the angular margin."""
+    oc = c - o
+    l = np.linalg.norm(oc)
+    if l <= r:
+        return True, np.inf
+    ang = math.acos(max(-1.0, min(1.0, float(np.dot(d, oc) / l))))
+    half = math.asin(r / l)
+    return ang <= half, abs(ang - half)
+
+
+def test_shadow_bake_agrees_with_the_subtended_cone():
+    rng = np.random.default_rng(14)
+    W, H, n, K = 3, 2, 9, 4
+    origins = rng.uniform(-1, 1, (H, W, 3)).astype(np.float32)
+    spheres = np.concatenate([rng.uniform(-2, 2, (K, 3)), rng.uniform(0.3, 1.2, (K, 1))],
+                             1).astype(np.float32)
+    frames = np.stack([_rand_rot(rng).T for _ in range(W * H)]).reshape(H, W, 3, 3)
+    frames = frames.astype(np.float32)
+    words, margin = oracle.bake_shadow(W, H, n, origins, spheres, frames=frames)
+    inc, _ = oracle.bake_directions(n)
+    wpb = oracle.words_per_bucket(n)
+    checked = lit = 0
+    for j in range(H):
+        for i in range(W):
+            M = frames[j, i].astype(np.float64)
+            o = origins[j, i].astype(np.float64)
+            for y in range(n):
+                for x in range(n):
+                    d = M.T @ inc[y, x]
+                    d /= np.linalg.norm(d)
+                    hits = [_cone_hits(o, d, s[:3].astype(np.float64), float(s[3]))
+                            for s in spheres]
+                    if min(h[1] for h in hits) < 1e-9:
+                        continue
+                    k = y * n + x
+                    bit = (words[(j * W + i) * wpb + k // 32] >> (k % 32)) & 1
+                    assert bit == (not any(h[0] for h in hits)), (i, j, x, y)
+                    checked += 1
+                    lit += bit
+    assert checked > 0.95 * W * H * n * n and 0 < lit < checked
+    # padding bits past n n stay clear
+    assert np.all(words.reshape(-1, wpb)[:, -1] >> ((n * n) % 32) == 0)
+
+
+def test_shadow_bake_frame_equivariance():
+    # baking with the frame M around the origin o equals baking with the
+    # identity frame after carrying each ball's centre to o + M (c - o): the
+    # frame turns the scene into the bucket's texture space, where the light
+    # lookup (u = M L) reads it
+    rng = np.random.default_rng(15)
+    n = 12
+    o = np.array([0.25, -0.5, 0.125], np.float32)
+    M = _rand_rot(rng).T
+    balls = np.array([[0.5, 0.2, 1.5, 0.6], [-1.0, 0.5, 0.8, 0.4], [0.3, -1.2, 0.9, 0.5]])
+    w1, m1 = oracle.bake_shadow(1, 1, n, o.reshape(1, 1, 3), balls.astype(np.float32),
+                                frames=M.astype(np.float32).reshape(1, 1, 3, 3))
+    Mf = M.astype(np.float32).astype(np.float64)
+    moved = balls.copy()
+    moved[:, :3] = o + (balls[:, :3] - o) @ Mf.T
+    w2, m2 = oracle.bake_shadow(1, 1, n, o.reshape(1, 1, 3), moved.astype(np.float32))
+    keep = (np.minimum(m1, m2) > 1e-5).reshape(-1)
+    k = np.arange(n * n)
+    b1 = (w1[k // 32] >> (k % 32)) & 1
+    b2 = (w2[k // 32] >> (k % 32)) & 1
+    assert keep.sum() > 0.9 * n * n
+    np.testing.assert_array_equal(b1[keep], b2[keep])
+    assert 0 < b1.sum() < n * n
+
+
+def test_shadow_of_a_ball_over_the_normal_is_a_cap():
+    # a ball of radius r centred at height h over the origin shades exactly
+    # the directions within asin(r / h) of the normal: with h = 2, r = 1 the
+    # samples whose incidence has I_z > cos 30 degrees
+    n = 15
+    words, _ = oracle.bake_shadow(1, 1, n, np.zeros((1, 1, 3), np.float32),
+                                  np.array([[0, 0, 2, 1]], np.float32))
+    inc, _ = oracle.bake_directions(n)
+    for y in range(n):
+        for x in range(n):
+            cz = inc[y, x, 2]
+            if abs(cz - math.cos(math.radians(30))) < 1e-9:
+                continue
+            k = y * n + x
+            assert ((words[k // 32] >> (k % 32)) & 1) == (cz < math.cos(math.radians(30)))
+    c = n // 2 * n + n // 2
+    assert (words[c // 32] >> (c % 32)) & 1 == 0  # the centre sample looks up the normal
+
+
+def _sun_samples(axis, alpha, k):
+    """k directions uniform in solid angle over the cap of half-angle alpha
+    around the unit axis, on a golden-angle spiral (every sample at its own
+    polar angle, so no ring of samples sits on an occluder's outline)."""
+    i = np.arange(k) + 0.5
+    cz = 1 - i / k * (1 - math.cos(alpha))
+    phi = i * math.pi * (3 - math.sqrt(5))
+    sz = np.sqrt(1 - cz * cz)
+    loc = np.stack([sz * np.cos(phi), sz * np.sin(phi), cz], -1)
+    a = np.asarray(axis, np.float64) / np.linalg.norm(axis)
+    t = np.cross(a, [1.0, 0, 0]) if abs(a[0]) < 0.9 else np.cross(a, [0, 1.0, 0])
+    t /= np.linalg.norm(t)
+    b = np.cross(a, t)
+    return loc @ np.stack([t, b, a])
+
+
+def test_area_shadow_converges_to_the_exact_penumbra():
+    # a sun of angular radius 25 degrees, tilted 20 degrees off the normal,
+    # partly hidden by the ball of the previous test.  Per sun sample the
+    # lookup departs from the exact visibility only within one cell of the
+    # occluder's outline, so the mean per-sample error falls as 1/n; the
+    # area light's value (the mean over the samples) is off by at most half
+    # the measure of that band.  A sun centred on the occluder approaches the
+    # closed-form cap fraction (cos theta_o - cos alpha) / (1 - cos alpha).
+    c = np.array([0.0, 0.0, 2.0])
+    sun = _sun_samples([math.sin(math.radians(20)), 0.0, math.cos(math.radians(20))],
+                       math.radians(25), 2048)
+    exact = np.array([not _cone_hits(np.zeros(3), s, c, 1.0)[0] for s in sun], np.float64)
+    uv = np.array([[0.5, 0.5]], np.float32)
+    eye = np.eye(3, dtype=np.float32)[None]
+    sun32 = sun.astype(np.float32)
+    per_sample, area = [], []
+    for n in (8, 16, 32, 64):
+        words, _ = oracle.bake_shadow(1, 1, n, np.zeros((1, 1, 3), np.float32),
+                                      np.array([[0, 0, 2, 1]], np.float32))
+        tex = oracle.Tex(words, 1, 1, n, 1, oracle.FMT_BIT1)
+        each = oracle.lookup_fwd(tex, np.repeat(uv, len(sun), 0), np.repeat(eye, len(sun), 0),
+                                 sun32)[:, 0]
+        got = oracle.lookup_light(tex, uv, eye, sun32)[0, 0]
+        assert abs(got - each.mean()) < 1e-12
+        per_sample.append(np.abs(each - exact).mean())
+        area.append(abs(got - exact.mean()))
+    assert 0.2 < exact.mean() < 0.8
+    for a, b in zip(per_sample, per_sample[1:]):
+        assert b < 0.7 * a, per_sample
+    assert area[-1] <= per_sample[-1] + 1e-12 and area[-1] < 0.03, area
+    centred = _sun_samples([0, 0, 1.0], math.radians(40), 4096)
+    words, _ = oracle.bake_shadow(1, 1, 64, np.zeros((1, 1, 3), np.float32),
+                                  np.array([[0, 0, 2, 1]], np.float32))
+    got = oracle.lookup_light(oracle.Tex(words, 1, 1, 64, 1, oracle.FMT_BIT1), uv, eye,
+                              centred.astype(np.float32))
+    cap = ((math.cos(math.radians(30)) - math.cos(math.radians(40)))
+           / (1 - math.cos(math.radians(40))))
+    assert abs(got[0, 0] - cap) < 0.03, (got[0, 0], cap)
