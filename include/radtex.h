@@ -68,8 +68,13 @@ typedef enum {
 typedef enum {
     RT_FMT_F32 = 0,       /* binary32 texels                                        */
     RT_FMT_BF16 = 1,      /* bfloat16 texels (round-to-nearest-even), no scale      */
-    RT_FMT_FP8_E4M3 = 2   /* OCP E4M3 ("FN": bias 7, max 448, no inf) texels, times */
+    RT_FMT_FP8_E4M3 = 2,  /* OCP E4M3 ("FN": bias 7, max 448, no inf) texels, times */
                           /* one binary32 scale per bucket                          */
+    RT_FMT_BIT1 = 3       /* one bit per sample, one channel, bucket-major only: the */
+                          /* 1-bit texture of Sec. 5 (Shadowing).  Bucket b holds    */
+                          /* ceil(n*n/32) uint32 words; sample k = y*n + x is bit    */
+                          /* k % 32 of word k / 32; the bits past n*n are zero.  A  */
+                          /* tap reads 0.0 or 1.0, so a bilinear fetch blends flags. */
 } rt_format;
 
 typedef enum {
@@ -149,7 +154,12 @@ rt_status rt_destroy_texture(rt_texture* tex);
  *                    E4M3 round-to-nearest-even of x * inv with saturation to
  *                    +-448 (NaN stays NaN).  dst_codes: uint8 [H][W][n][n][C];
  *                    dst_scales: float [H][W].
- * Errors: RT_ERR_INVALID_ARG (NULL/misaligned outputs, src not F32, bad dst). */
+ *   RT_FMT_BIT1      src with C = 1: each sample becomes the bit (x >= 0.5), NaN
+ *                    giving 0, in the layout of RT_FMT_BIT1.  dst_codes: uint32
+ *                    [H][W][ceil(n*n/32)], 4-byte aligned, every word
+ *                    OVERWRITTEN; dst_scales must be NULL.
+ * Errors: RT_ERR_INVALID_ARG (NULL/misaligned outputs, src not F32, bad dst,
+ * C != 1 for RT_FMT_BIT1). */
 rt_status rt_quantize(const rt_texture* src, int32_t dst_format, void* dst_codes,
                       float* dst_scales, void* stream);
 
@@ -162,6 +172,7 @@ rt_status rt_quantize(const rt_texture* src, int32_t dst_format, void* dst_codes
  *   bucket i = floor(frac(u) W), j = floor(frac(v) H)       (Sec. 2; nearest)
  *   out[f][c] = bilinear fetch at s inside bucket (i, j), decoded to binary32.
  * flags: RT_BUCKET_NEAREST or RT_BUCKET_BILINEAR.  out: float [N][C].
+ * Any storage format, RT_FMT_BIT1 included (its taps read 0 or 1).
  * Non-finite inputs give unspecified values but never out-of-bounds reads.
  * Errors: RT_ERR_INVALID_ARG (NULL/misaligned pointers, N < 0, bad flags). */
 rt_status rt_lookup_fwd(const rt_texture* tex, const rt_fragments* frags, float* out,
@@ -190,7 +201,7 @@ size_t rt_lookup_bwd_workspace(const rt_texture* tex, int64_t count, uint32_t fl
  * workspace: device memory of at least rt_lookup_bwd_workspace() bytes,
  * 256-byte aligned, owned by the caller, not used by concurrent calls.
  * Errors: RT_ERR_INVALID_ARG, RT_ERR_WORKSPACE_TOO_SMALL, RT_ERR_UNSUPPORTED
- * (sort key or record count beyond the limits above). */
+ * (sort key or record count beyond the limits above, an RT_FMT_BIT1 texture). */
 rt_status rt_lookup_bwd(const rt_texture* tex, const rt_fragments* frags,
                         const float* grad_out, float* grad_tex, float* grad_view,
                         float* grad_uv, void* workspace, size_t workspace_bytes,
@@ -202,7 +213,6 @@ rt_status rt_lookup_bwd(const rt_texture* tex, const rt_fragments* frags,
 rt_status rt_debug_indices(const rt_texture* tex, const rt_fragments* frags, int32_t* idx,
                            float* frac, void* stream);
 
-/* Thread-local description of the last non-OK status ("" if none). */
 /* --- Minification across the bucket matrix ---------------------------------
  * Sec. 2: taking one sample per bucket synthesises an ordinary W x H texture,
  * and the lookup is linear in the buckets (the sample position depends only
@@ -234,7 +244,8 @@ rt_status rt_build_mip(const rt_texture* src, float* dst, void* stream);
  * duv: DEVICE float [N][4], 16-byte aligned; out as for rt_lookup_fwd.
  * Errors: RT_ERR_INVALID_ARG (NULL levels, a level of the wrong size, n,
  * channels or format, sizes that are not powers of two, duv/out NULL or
- * misaligned, bad fragments or flags), RT_ERR_UNSUPPORTED (nlevels > 17). */
+ * misaligned, bad fragments or flags), RT_ERR_UNSUPPORTED (nlevels > 17, an
+ * RT_FMT_BIT1 chain). */
 rt_status rt_lookup_fwd_lod(const rt_texture* const* levels, int32_t nlevels,
                             const rt_fragments* frags, const float* duv, float* out,
                             uint32_t flags, void* stream);
@@ -281,6 +292,66 @@ rt_status rt_bake_environment(int32_t W, int32_t H, int32_t n, int32_t C, const 
                               const rt_env_lobe* lobes, int32_t nlobes, const float* ambient,
                               float* texels, void* stream);
 
+/* --- Shadowing (Sec. 5, Shadowing) -----------------------------------------
+ * A 1-bit radiance texture holds the occlusion of static geometry: a sample's
+ * bit says whether light from the sample's direction reaches the bucket's
+ * surface point.  It is read with the direction toward the light in place of
+ * the incidence vector, for directional and point lights, and an area light
+ * is several light samples whose lookups are averaged (a soft shadow). */
+
+enum {
+    RT_LIGHT_DIRECTIONAL = 0,   /* vec[s]: direction toward the light (scene space) */
+    RT_LIGHT_POINT = 1          /* vec[s]: a point of the light (scene space)        */
+};
+#define RT_MAX_LIGHT_SAMPLES 64
+
+typedef struct {
+    int32_t kind;                          /* RT_LIGHT_DIRECTIONAL or RT_LIGHT_POINT */
+    int32_t samples;                       /* S, 1..RT_MAX_LIGHT_SAMPLES             */
+    float vec[RT_MAX_LIGHT_SAMPLES][3];    /* the first S are used; need not be unit */
+} rt_light;
+
+/* Light lookup: for every fragment f and channel c,
+ *   L_s    = vec[s]            (RT_LIGHT_DIRECTIONAL)
+ *          = vec[s] - pos[f]   (RT_LIGHT_POINT, binary32 difference)
+ *   out[f][c] = (1/S) sum_s lookup(tex, uv[f], tbn[f], L_s)[c],
+ * where lookup is rt_lookup_fwd's computation with L_s in the place of the
+ * view vector (flags as there).  With an RT_FMT_BIT1 texture out is the lit
+ * fraction of the light's samples; any other format gives the light-indexed
+ * radiance.  A light below the surface's horizon is not treated specially
+ * (its direction is clamped onto the bucket edge as any vector is): the
+ * cosine factor of the shading belongs to the caller.
+ * frags: uv and tbn as for rt_lookup_fwd; frags->view is not read (may be
+ * NULL).  pos: DEVICE float [N][3], 4-byte aligned, read for point lights
+ * only (may be NULL otherwise).  light: HOST, read during the call.  out:
+ * DEVICE float [N][C], aligned as for rt_lookup_fwd.
+ * Errors: RT_ERR_INVALID_ARG (NULL/misaligned pointers, bad fragments, flags,
+ * light kind or sample count, non-finite light vectors, pos NULL for a point
+ * light). */
+rt_status rt_lookup_light(const rt_texture* tex, const rt_fragments* frags, const float* pos,
+                          const rt_light* light, float* out, uint32_t flags, void* stream);
+
+/* Bake of a 1-bit shadow texture from analytic occluders, standing in for the
+ * ray-traced visibility: bucket (i, j) sits at the scene point origins[j][i]
+ * with frame M_ji = frames[j][i] (rows T, B, N as in the lookup; NULL: the
+ * identity), and sample (x, y) gets bit 1 (lit) iff the ray from the origin
+ * along d = normalize(M_ji^T I(x, y)) meets none of the balls, I(x, y) being
+ * the incidence of rt_bake_directions (the direction the light lookup maps
+ * onto that sample).  The ray o + t d, t > 0, meets ball (c, r) iff
+ * |c - o| <= r, or t* = d . (c - o) > 0 and |c - o - t* d| <= r.
+ * origins: DEVICE float [H][W][3]; frames: DEVICE float [H][W][3][3] or NULL;
+ * both 4-byte aligned.  balls: HOST float [nballs][4] (centre x, y, z,
+ * radius > 0), nballs 0..64, read during the call.  words: DEVICE uint32
+ * [H][W][ceil(n*n/32)] in the layout of RT_FMT_BIT1, 4-byte aligned, every
+ * word OVERWRITTEN.
+ * Errors: RT_ERR_INVALID_ARG (sizes, NULL pointers, alignment, non-finite
+ * balls, radius <= 0), RT_ERR_UNSUPPORTED (W or H > 65536, n > 32,
+ * nballs > 64), RT_ERR_NO_DEVICE, RT_ERR_HIP (launch). */
+rt_status rt_bake_shadow(int32_t W, int32_t H, int32_t n, const float* origins,
+                         const float* frames, const float* balls, int32_t nballs,
+                         uint32_t* words, void* stream);
+
+/* Thread-local description of the last non-OK status ("" if none). */
 const char* rt_last_error(void);
 const char* rt_status_string(rt_status status);
 int32_t rt_version(void);

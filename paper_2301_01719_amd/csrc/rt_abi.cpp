@@ -69,7 +69,7 @@ rt::FragMap fragmap(const rt_fragments* f) {
     return rt::make_fragmap(f->count, f->views, f->height, f->width);
 }
 
-rt_status check_frags(const rt_fragments* f) {
+rt_status check_frags(const rt_fragments* f, bool need_view = true) {
     if (!f) return fail(RT_ERR_INVALID_ARG, "fragments is NULL");
     if (f->count < 0) return fail(RT_ERR_INVALID_ARG, "fragment count %lld < 0", (long long)f->count);
     if (f->count >= (1ll << 31))
@@ -84,10 +84,11 @@ rt_status check_frags(const rt_fragments* f) {
                         f->views, f->height, f->width, (long long)f->count);
     }
     if (f->count == 0) return RT_OK;
-    if (!f->uv || !f->tbn || !f->view)
-        return fail(RT_ERR_INVALID_ARG, "uv, tbn and view must be non-NULL when count > 0");
+    if (!f->uv || !f->tbn || (need_view && !f->view))
+        return fail(RT_ERR_INVALID_ARG, need_view ? "uv, tbn and view must be non-NULL when count > 0"
+                                                  : "uv and tbn must be non-NULL when count > 0");
     if (!aligned(f->uv, 8)) return fail(RT_ERR_INVALID_ARG, "uv must be 8-byte aligned");
-    if (!aligned(f->tbn, 4) || !aligned(f->view, 4))
+    if (!aligned(f->tbn, 4) || (need_view && !aligned(f->view, 4)))
         return fail(RT_ERR_INVALID_ARG, "tbn and view must be 4-byte aligned");
     return RT_OK;
 }
@@ -141,7 +142,8 @@ const char* kernel_name(int id) {
         "k_atlas_to_buckets", "k_bwd_fragment", "k_fill_u32",   "k_radix_hist",
         "k_scan",         "k_radix_scatter", "k_bucket_ranges", "k_segacc",
         "k_segacc_hot",   "k_combine_hot",   "k_segacc_big",    "k_bake_directions",
-        "k_bake_env",     "k_build_mip",     "k_lookup_lod"};
+        "k_bake_env",     "k_build_mip",     "k_lookup_lod",    "k_pack_bits",
+        "k_lookup_light", "k_bake_shadow"};
     return (id >= 0 && id < K_COUNT) ? names[id] : "";
 }
 
@@ -208,17 +210,23 @@ rt_status rt_create_texture(const rt_texture_desc* d, void* stream, rt_texture**
     if (d->n > 32) return fail(RT_ERR_UNSUPPORTED, "angular resolution n = %d exceeds 32", d->n);
     if (d->channels < 1 || d->channels > 4)
         return fail(RT_ERR_INVALID_ARG, "channels = %d must be in 1..4", d->channels);
-    if (d->format < RT_FMT_F32 || d->format > RT_FMT_FP8_E4M3)
+    if (d->format < RT_FMT_F32 || d->format > RT_FMT_BIT1)
         return fail(RT_ERR_INVALID_ARG, "unknown format %d", d->format);
     if (d->layout != RT_LAYOUT_BUCKET_MAJOR && d->layout != RT_LAYOUT_ATLAS)
         return fail(RT_ERR_INVALID_ARG, "unknown layout %d", d->layout);
+    if (d->format == RT_FMT_BIT1) {
+        if (d->channels != 1)
+            return fail(RT_ERR_INVALID_ARG, "1-bit textures have one channel, not %d", d->channels);
+        if (d->layout != RT_LAYOUT_BUCKET_MAJOR)
+            return fail(RT_ERR_UNSUPPORTED, "1-bit textures are bucket-major only");
+    }
     if (!d->data) return fail(RT_ERR_INVALID_ARG, "data is NULL");
     if (!aligned(d->data, 16)) return fail(RT_ERR_INVALID_ARG, "data must be 16-byte aligned");
     if (d->format == RT_FMT_FP8_E4M3) {
         if (!d->scales) return fail(RT_ERR_INVALID_ARG, "FP8 textures need per-bucket scales");
         if (!aligned(d->scales, 4)) return fail(RT_ERR_INVALID_ARG, "scales must be 4-byte aligned");
     } else if (d->scales) {
-        return fail(RT_ERR_INVALID_ARG, "scales must be NULL for F32 and BF16 textures");
+        return fail(RT_ERR_INVALID_ARG, "scales must be NULL for F32, BF16 and 1-bit textures");
     }
     rt_status st = check_device();
     if (st != RT_OK) return st;
@@ -282,8 +290,13 @@ rt_status rt_quantize(const rt_texture* src, int32_t dst_format, void* codes, fl
         if (!scales) return fail(RT_ERR_INVALID_ARG, "FP8 needs dst_scales");
         if (!aligned(codes, 4) || !aligned(scales, 4))
             return fail(RT_ERR_INVALID_ARG, "dst_codes and dst_scales must be 4-byte aligned");
+    } else if (dst_format == RT_FMT_BIT1) {
+        if (src->view.C != 1)
+            return fail(RT_ERR_INVALID_ARG, "1-bit packing needs a one-channel source, not %d", src->view.C);
+        if (scales) return fail(RT_ERR_INVALID_ARG, "1-bit textures have no scales: dst_scales must be NULL");
+        if (!aligned(codes, 4)) return fail(RT_ERR_INVALID_ARG, "dst_codes must be 4-byte aligned");
     } else {
-        return fail(RT_ERR_INVALID_ARG, "dst_format must be RT_FMT_BF16 or RT_FMT_FP8_E4M3");
+        return fail(RT_ERR_INVALID_ARG, "dst_format must be RT_FMT_BF16, RT_FMT_FP8_E4M3 or RT_FMT_BIT1");
     }
     hipError_t e = rt::launch_quantize(src->view, dst_format, codes, scales, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "quantiser launch");
@@ -332,6 +345,8 @@ rt_status rt_lookup_bwd(const rt_texture* t, const rt_fragments* f, const float*
     st = check_frags(f);
     if (st != RT_OK) return st;
     if (flags > RT_BUCKET_BILINEAR) return fail(RT_ERR_INVALID_ARG, "unknown flags 0x%x", flags);
+    if (t->fmt == RT_FMT_BIT1)
+        return fail(RT_ERR_UNSUPPORTED, "1-bit textures have no backward (their values are flags)");
     const int C = t->view.C;
     if (f->count > 0) {
         if (!grad_out) return fail(RT_ERR_INVALID_ARG, "grad_out is NULL");
@@ -487,6 +502,8 @@ rt_status rt_lookup_fwd_lod(const rt_texture* const* levels, int32_t nlevels,
     for (int l = 0; l < nlevels; l++)
         if (!levels[l]) return fail(RT_ERR_INVALID_ARG, "level %d is NULL", l);
     const rt::TexView& v0 = levels[0]->view;
+    if (levels[0]->fmt == RT_FMT_BIT1)
+        return fail(RT_ERR_UNSUPPORTED, "mip chains of 1-bit textures are not supported");
     if (nlevels > 1) {
         if (!pow2(v0.W) || !pow2(v0.H))
             return fail(RT_ERR_INVALID_ARG, "bucket matrix %d x %d: a mip chain needs powers of two", v0.W, v0.H);
@@ -523,6 +540,85 @@ rt_status rt_lookup_fwd_lod(const rt_texture* const* levels, int32_t nlevels,
     hipError_t e = rt::launch_lookup_lod(ls, levels[0]->fmt, (int)flags, f->uv, f->tbn, f->view,
                                          duv, out, fragmap(f), (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "lod lookup launch");
+    return ok();
+    RT_GUARD_END
+}
+
+rt_status rt_lookup_light(const rt_texture* t, const rt_fragments* f, const float* pos,
+                          const rt_light* light, float* out, uint32_t flags, void* stream) {
+    RT_GUARD_BEGIN
+    rt_status st = check_tex(t);
+    if (st != RT_OK) return st;
+    st = check_frags(f, false);
+    if (st != RT_OK) return st;
+    if (flags > RT_BUCKET_BILINEAR) return fail(RT_ERR_INVALID_ARG, "unknown flags 0x%x", flags);
+    if (!light) return fail(RT_ERR_INVALID_ARG, "light is NULL");
+    if (light->kind != RT_LIGHT_DIRECTIONAL && light->kind != RT_LIGHT_POINT)
+        return fail(RT_ERR_INVALID_ARG, "unknown light kind %d", light->kind);
+    if (light->samples < 1 || light->samples > RT_MAX_LIGHT_SAMPLES)
+        return fail(RT_ERR_INVALID_ARG, "light samples = %d must be in 1..%d", light->samples,
+                    RT_MAX_LIGHT_SAMPLES);
+    rt::LightParams lp;
+    memset(&lp, 0, sizeof(lp));
+    lp.kind = light->kind == RT_LIGHT_POINT ? rt::LIGHT_POINT : rt::LIGHT_DIRECTIONAL;
+    lp.samples = light->samples;
+    lp.inv_samples = 1.0f / (float)light->samples;
+    for (int s = 0; s < light->samples; s++)
+        for (int k = 0; k < 3; k++) {
+            if (!std::isfinite(light->vec[s][k]))
+                return fail(RT_ERR_INVALID_ARG, "light sample %d is not finite", s);
+            lp.vec[s][k] = light->vec[s][k];
+        }
+    if (f->count > 0) {
+        if (light->kind == RT_LIGHT_POINT) {
+            if (!pos) return fail(RT_ERR_INVALID_ARG, "a point light needs the fragments' positions");
+            if (!aligned(pos, 4)) return fail(RT_ERR_INVALID_ARG, "pos must be 4-byte aligned");
+        }
+        if (!out) return fail(RT_ERR_INVALID_ARG, "out is NULL");
+        if (!aligned(out, out_align(t->view.C)))
+            return fail(RT_ERR_INVALID_ARG, "out must be %zu-byte aligned", out_align(t->view.C));
+    }
+    hipError_t e = rt::launch_lookup_light(t->view, t->fmt, (int)flags, f->uv, f->tbn,
+                                           light->kind == RT_LIGHT_POINT ? pos : nullptr, lp, out,
+                                           fragmap(f), (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "light lookup launch");
+    return ok();
+    RT_GUARD_END
+}
+
+rt_status rt_bake_shadow(int32_t W, int32_t H, int32_t n, const float* origins,
+                         const float* frames, const float* balls, int32_t nballs,
+                         uint32_t* words, void* stream) {
+    RT_GUARD_BEGIN
+    if (W < 1 || H < 1)
+        return fail(RT_ERR_INVALID_ARG, "bucket matrix %d x %d must be at least 1 x 1", W, H);
+    if (W > 65536 || H > 65536)
+        return fail(RT_ERR_UNSUPPORTED, "bucket matrix %d x %d exceeds 65536 per side", W, H);
+    if (n < 1) return fail(RT_ERR_INVALID_ARG, "angular resolution n = %d must be >= 1", n);
+    if (n > 32) return fail(RT_ERR_UNSUPPORTED, "angular resolution n = %d exceeds 32", n);
+    if (nballs < 0) return fail(RT_ERR_INVALID_ARG, "nballs = %d < 0", nballs);
+    if (nballs > rt::MAX_OCCLUDERS)
+        return fail(RT_ERR_UNSUPPORTED, "nballs = %d exceeds %d", nballs, rt::MAX_OCCLUDERS);
+    if (nballs > 0 && !balls) return fail(RT_ERR_INVALID_ARG, "balls is NULL");
+    if (!origins) return fail(RT_ERR_INVALID_ARG, "origins is NULL");
+    if (!words) return fail(RT_ERR_INVALID_ARG, "words is NULL");
+    if (!aligned(origins, 4) || !aligned(words, 4) || (frames && !aligned(frames, 4)))
+        return fail(RT_ERR_INVALID_ARG, "origins, frames and words must be 4-byte aligned");
+    rt::Occluders occ;
+    memset(&occ, 0, sizeof(occ));
+    occ.count = nballs;
+    for (int k = 0; k < nballs; k++) {
+        for (int c = 0; c < 4; c++) {
+            if (!std::isfinite(balls[4 * k + c]))
+                return fail(RT_ERR_INVALID_ARG, "ball %d is not finite", k);
+            occ.ball[k][c] = balls[4 * k + c];
+        }
+        if (!(balls[4 * k + 3] > 0.f)) return fail(RT_ERR_INVALID_ARG, "ball %d: radius must be > 0", k);
+    }
+    rt_status st = check_device();
+    if (st != RT_OK) return st;
+    hipError_t e = rt::launch_bake_shadow(W, H, n, origins, frames, occ, words, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "shadow bake launch");
     return ok();
     RT_GUARD_END
 }

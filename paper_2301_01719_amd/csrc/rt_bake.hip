@@ -9,37 +9,17 @@
 // d = normalize(M^T R) with the bucket's frame M = [T;B;N], and per channel
 // ambient + sum_k a_k exp(lambda_k (mu_k . d - 1)).  The texture is written
 // once, so the bound is HBM bandwidth on the writes.
+//
+// The shadow bake (Sec. 5, Shadowing) fills a 1-bit texture: the sample's
+// bit says whether the ray from the bucket's scene point along the sample's
+// incidence direction (the direction that the light lookup maps onto it)
+// escapes a set of balls that stand in for the ray-traced occluders.
 #include <algorithm>
 
 #include "rt_device.hpp"
 #include "rt_kernels.hpp"
 
 namespace rt {
-
-// Eq. (4a) then Eq. (4b) at the centre of sample (x, y) of an n x n bucket:
-// B = ((2x+1)/n - 1, (2y+1)/n - 1); A = max(|B_x|, |B_y|) / |B| B (A = 0 at
-// B = 0); R = (-A_x w, -A_y w, 1 - |A|^2), w = sqrt(2 - |A|^2).  Also the
-// incidence I of Eq. (2c), R mirrored about the normal.
-__device__ __forceinline__ void sample_directions(int x, int y, int n, float R[3], float I[3]) {
-    const float bx = (float)(2 * x + 1) / (float)n - 1.f;
-    const float by = (float)(2 * y + 1) / (float)n - 1.f;
-    const float rho = sqrtf(bx * bx + by * by);
-    const float m = fmaxf(fabsf(bx), fabsf(by));
-    float ax = 0.f, ay = 0.f;
-    if (rho > 0.f) {
-        const float f = m / rho;
-        ax = f * bx;
-        ay = f * by;
-    }
-    const float r2 = ax * ax + ay * ay;
-    const float w = sqrtf(fmaxf(0.f, 2.f - r2));
-    R[0] = -ax * w;
-    R[1] = -ay * w;
-    R[2] = 1.f - r2;
-    I[0] = ax * w;
-    I[1] = ay * w;
-    I[2] = 1.f - r2;
-}
 
 __global__ __launch_bounds__(256) void k_bake_directions(int n, float* __restrict__ inc,
                                                          float* __restrict__ refl) {
@@ -149,6 +129,90 @@ __global__ __launch_bounds__(256) void k_bake_env(int64_t nbuckets, int n,
             }
         }
     }
+}
+
+// Shadow bake: one wavefront per bucket at a time, one lane per sample.  The
+// incidence directions of the n x n samples and the balls sit in LDS; each
+// lane turns its direction into the scene frame (M^T I, normalised), tests
+// the balls, and a wave ballot packs 64 samples into two words.  Samples
+// past n n give 0, which clears the padding bits of the last word.
+//
+// Ray o + t d (t > 0, |d| = 1) against ball (c, r): with e = c - o, the ray
+// meets the ball iff |e| <= r (o inside) or t* = d . e > 0 and the distance
+// |e - t* d| of the line from c is at most r.
+__global__ __launch_bounds__(256) void k_bake_shadow(int64_t nbuckets, int n,
+                                                     const float* __restrict__ origins,
+                                                     const float* __restrict__ frames,
+                                                     Occluders occ, uint32_t* __restrict__ words) {
+    __shared__ float It[3 * 32 * 32];
+    __shared__ float4 ball[MAX_OCCLUDERS];
+    const int nn = n * n;
+    if (threadIdx.x < occ.count)
+        ball[threadIdx.x] = make_float4(occ.ball[threadIdx.x][0], occ.ball[threadIdx.x][1],
+                                        occ.ball[threadIdx.x][2], occ.ball[threadIdx.x][3]);
+    for (int q = threadIdx.x; q < nn; q += 256) {
+        const int y = q / n, x = q - y * n;
+        float R[3], I[3];
+        sample_directions(x, y, n, R, I);
+        It[3 * q + 0] = I[0];
+        It[3 * q + 1] = I[1];
+        It[3 * q + 2] = I[2];
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const int wpb = bit_words(n);
+    const int chunks = (nn + 63) >> 6;
+    const int64_t waves = (int64_t)gridDim.x * 4;
+    const int64_t first = (int64_t)xcd_block_id(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
+    for (int64_t b = first; b < nbuckets; b += waves) {
+        float M[9] = {1.f, 0.f, 0.f, 0.f, 1.f, 0.f, 0.f, 0.f, 1.f};
+        if (frames) {
+#pragma unroll
+            for (int k = 0; k < 9; k++) M[k] = frames[b * 9 + k];
+        }
+        const float ox = origins[b * 3 + 0], oy = origins[b * 3 + 1], oz = origins[b * 3 + 2];
+        for (int c = 0; c < chunks; c++) {
+            const int k = c * 64 + lane;
+            bool lit = false;
+            if (k < nn) {
+                const float i0 = It[3 * k + 0], i1 = It[3 * k + 1], i2 = It[3 * k + 2];
+                float dx = M[0] * i0 + M[3] * i1 + M[6] * i2;
+                float dy = M[1] * i0 + M[4] * i1 + M[7] * i2;
+                float dz = M[2] * i0 + M[5] * i1 + M[8] * i2;
+                const float inv = 1.0f / sqrtf(dx * dx + dy * dy + dz * dz);
+                dx *= inv;
+                dy *= inv;
+                dz *= inv;
+                bool hit = false;
+                for (int q = 0; q < occ.count; q++) {
+                    const float4 bl = ball[q];
+                    const float ex = bl.x - ox, ey = bl.y - oy, ez = bl.z - oz;
+                    const float r2 = bl.w * bl.w;
+                    const float ts = dx * ex + dy * ey + dz * ez;
+                    const float hx = ex - ts * dx, hy = ey - ts * dy, hz = ez - ts * dz;
+                    const bool inside = ex * ex + ey * ey + ez * ez <= r2;
+                    hit |= inside || (ts > 0.f && hx * hx + hy * hy + hz * hz <= r2);
+                }
+                lit = !hit;
+            }
+            const uint64_t bits = __ballot(lit);
+            const int w = 2 * c + lane;
+            if (lane < 2 && w < wpb)
+                words[b * wpb + w] = lane == 0 ? (uint32_t)bits : (uint32_t)(bits >> 32);
+        }
+    }
+}
+
+hipError_t launch_bake_shadow(int W, int H, int n, const float* origins, const float* frames,
+                              const Occluders& occ, uint32_t* words, hipStream_t s) {
+    const int64_t nb = (int64_t)W * H;
+    if (nb == 0) return hipSuccess;
+    const uint32_t blocks = (uint32_t)std::min<int64_t>((nb + 3) / 4, 256 * 16);
+    prof_begin(K_BAKE_SHADOW, s);
+    hipLaunchKernelGGL(k_bake_shadow, dim3(blocks), dim3(256), 0, s, nb, n, origins, frames, occ,
+                       words);
+    prof_end(K_BAKE_SHADOW, s);
+    return hipGetLastError();
 }
 
 hipError_t launch_bake_directions(int n, float* inc, float* refl, hipStream_t s) {

@@ -1,6 +1,7 @@
 // rt_device.hpp -- device-side building blocks shared by the gfx950 kernels of
 // the radiance-bucket lookup: the incidence -> bucket mapping in binary32,
-// texel loads and decodes for the three storage formats, and launch helpers.
+// texel loads and decodes for the storage formats, the sample directions of
+// the bake, and launch helpers.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -11,6 +12,11 @@ namespace rt {
 constexpr int FMT_F32 = 0;
 constexpr int FMT_BF16 = 1;
 constexpr int FMT_FP8 = 2;
+constexpr int FMT_BIT1 = 3;  // one bit per sample, one channel
+
+// 32-bit words per bucket of the 1-bit storage: sample k = y n + x is bit
+// k % 32 of word k / 32 of its bucket; the bits past n n are zero.
+__host__ __device__ __forceinline__ int bit_words(int n) { return (n * n + 31) >> 5; }
 
 constexpr int MODE_NEAREST = 0;
 constexpr int MODE_BILINEAR = 1;
@@ -21,7 +27,7 @@ typedef uint32_t u2v __attribute__((ext_vector_type(2)));
 
 // Texture as seen by a kernel: bucket-major [H][W][n][n][C].
 struct TexView {
-    const void* data;
+    const void* data;     // FMT_BIT1: uint32 words, bit_words(n) per bucket
     const float* scales;  // [H][W], FP8 only
     int W, H, n, C;
 };
@@ -276,22 +282,62 @@ __device__ __forceinline__ int bucket_of(float u, int W) {
 }
 
 // Bilinear-bucket footprint in UV: p = frac(u) W - 1/2, columns floor(p) and
-// floor(p)+1 (wrapping), weight a = p - floor(p).  Evaluated from
-// q = u W - 1/2 (one rounding, exact for a power-of-two W) for the reason
-// given above; non-finite and huge coordinates behave as u = 0.
+// floor(p)+1 (wrapping), weight a = p - floor(p).  Evaluated from t = u W
+// (exact for a power-of-two W) split into floor(t) and r = t - floor(t)
+// (exact, except for -1/2 < t < 0 where it rounds by at most 2^-25); then
+// a = r - 1/2 (exact) or r + 1/2 (rounded by at most 2^-25).  The weight is
+// thus within 2^-24 however large u W is, whereas forming u W - 1/2 first
+// would round it to the ulp of u W.  Non-finite and huge coordinates behave
+// as u = 0.
 __device__ __forceinline__ void bucket_pair(float u, int W, int& i0, int& i1, float& a) {
-    const float q = fmaf(u, (float)W, -0.5f);
-    const float fq = floorf(q);
-    if (!(fabsf(fq) < 1073741824.0f)) {
+    const float t = u * (float)W;
+    const float ft = floorf(t);
+    if (!(fabsf(ft) < 1073741824.0f)) {
         i0 = W - 1;
         i1 = 0;
         a = 0.5f;
         return;
     }
-    a = q - fq;
-    int k = (int)fq % W;
+    const float r = t - ft;
+    int k = (int)ft;
+    if (r >= 0.5f) {
+        a = r - 0.5f;
+    } else {
+        a = r + 0.5f;
+        k -= 1;
+    }
+    k %= W;
     i0 = k < 0 ? k + W : k;
     i1 = i0 + 1 == W ? 0 : i0 + 1;
+}
+
+// ---------------------------------------------------------------------------
+// Sample centres of a bucket as directions (the write side: Eqs. 4a, 4b, 2c).
+// At sample (x, y) of an n x n bucket: B = ((2x+1)/n - 1, (2y+1)/n - 1);
+// A = max(|B_x|, |B_y|) / |B| B (A = 0 at B = 0); the reflection vector
+// R = (-A_x w, -A_y w, 1 - |A|^2), w = sqrt(2 - |A|^2), and the incidence
+// I = (A_x w, A_y w, 1 - |A|^2) that the lookup maps onto the sample (R
+// mirrored about the normal).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void sample_directions(int x, int y, int n, float R[3], float I[3]) {
+    const float bx = (float)(2 * x + 1) / (float)n - 1.f;
+    const float by = (float)(2 * y + 1) / (float)n - 1.f;
+    const float rho = sqrtf(bx * bx + by * by);
+    const float m = fmaxf(fabsf(bx), fabsf(by));
+    float ax = 0.f, ay = 0.f;
+    if (rho > 0.f) {
+        const float f = m / rho;
+        ax = f * bx;
+        ay = f * by;
+    }
+    const float r2 = ax * ax + ay * ay;
+    const float w = sqrtf(fmaxf(0.f, 2.f - r2));
+    R[0] = -ax * w;
+    R[1] = -ay * w;
+    R[2] = 1.f - r2;
+    I[0] = ax * w;
+    I[1] = ay * w;
+    I[2] = 1.f - r2;
 }
 
 }  // namespace rt

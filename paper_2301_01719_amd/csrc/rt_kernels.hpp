@@ -33,6 +33,9 @@ enum KernelId {
     K_BAKE_ENV,
     K_BUILD_MIP,
     K_LOOKUP_LOD,
+    K_PACK_BITS,
+    K_LOOKUP_LIGHT,
+    K_BAKE_SHADOW,
     K_COUNT
 };
 const char* kernel_name(int id);
@@ -51,6 +54,20 @@ hipError_t launch_build_mip(const TexView& src, float* dst, hipStream_t s);
 hipError_t launch_lookup_lod(const LevelSet& ls, int fmt, int mode, const float* uv,
                              const float* tbn, const float* view, const float* duv, float* out,
                              const FragMap& m, hipStream_t s);
+// Light lookup (shadowing with a 1-bit texture, or any radiance texture
+// indexed by the light direction): per fragment the mean over the light's
+// samples of the lookup taken with the direction toward the light.
+constexpr int MAX_LIGHT_SAMPLES = 64;
+constexpr int LIGHT_DIRECTIONAL = 0, LIGHT_POINT = 1;
+struct LightParams {
+    int kind;           // LIGHT_DIRECTIONAL: vec = directions; LIGHT_POINT: sample points
+    int samples;        // 1..MAX_LIGHT_SAMPLES
+    float inv_samples;  // 1 / samples
+    float vec[MAX_LIGHT_SAMPLES][3];
+};
+hipError_t launch_lookup_light(const TexView& t, int fmt, int mode, const float* uv,
+                               const float* tbn, const float* pos, const LightParams& lp,
+                               float* out, const FragMap& m, hipStream_t s);
 hipError_t launch_atlas_to_buckets(const void* atlas, void* dst, int W, int H, int n, int C,
                                    int elem_bytes, hipStream_t s);
 
@@ -64,6 +81,15 @@ struct EnvParams {
     float lobe[MAX_LOBES][8];
 };
 hipError_t launch_bake_directions(int n, float* inc, float* refl, hipStream_t s);
+
+// Shadow bake: balls (centre x, y, z, radius) as the occluders.
+constexpr int MAX_OCCLUDERS = 64;
+struct Occluders {
+    int count;
+    float ball[MAX_OCCLUDERS][4];
+};
+hipError_t launch_bake_shadow(int W, int H, int n, const float* origins, const float* frames,
+                              const Occluders& occ, uint32_t* words, hipStream_t s);
 hipError_t launch_bake_env(int W, int H, int n, int C, const float* frames, const EnvParams& env,
                            float* texels, hipStream_t s);
 

@@ -7,6 +7,10 @@
 // (Sec. 2) and four taps of C channels are read from the bucket-major
 // texture and blended bilinearly.  The path is a gather: no contraction, so
 // no MFMA; the bound is HBM bandwidth (the G-buffer stream dominates).
+//
+// The light lookup (shadowing) takes the direction toward the light in place
+// of the view vector and averages the lookups over an area light's samples;
+// on a 1-bit texture each tap is one bit of the bucket's words.
 #include "rt_device.hpp"
 #include "rt_kernels.hpp"
 
@@ -16,6 +20,19 @@ template <int FMT, int C>
 __device__ __forceinline__ void bucket_bilerp(const TexView& t, int64_t b, const Foot& p,
                                               float wgt, float acc[4]) {
     const int n = t.n;
+    if constexpr (FMT == FMT_BIT1) {
+        const uint32_t* w = (const uint32_t*)t.data + b * bit_words(n);
+        const int k00 = p.y0 * n + p.x0, k01 = p.y0 * n + p.x1;
+        const int k10 = p.y1 * n + p.x0, k11 = p.y1 * n + p.x1;
+        const float t00 = (float)((w[k00 >> 5] >> (k00 & 31)) & 1u);
+        const float t01 = (float)((w[k01 >> 5] >> (k01 & 31)) & 1u);
+        const float t10 = (float)((w[k10 >> 5] >> (k10 & 31)) & 1u);
+        const float t11 = (float)((w[k11 >> 5] >> (k11 & 31)) & 1u);
+        const float v = (1.f - p.fx) * (1.f - p.fy) * t00 + p.fx * (1.f - p.fy) * t01 +
+                        (1.f - p.fx) * p.fy * t10 + p.fx * p.fy * t11;
+        acc[0] += wgt * v;
+        return;
+    }
     const int64_t base = b * (int64_t)(n * n);
     F4 t00 = load_texel<FMT, C>(t.data, base + p.y0 * n + p.x0);
     F4 t01 = load_texel<FMT, C>(t.data, base + p.y0 * n + p.x1);
@@ -182,7 +199,14 @@ hipError_t launch_lookup_fwd(const TexView& t, int fmt, int mode, const float* u
     if (m.N <= 0) return hipSuccess;
     hipError_t e;
     prof_begin(K_LOOKUP_FWD, s);
-    if (mode == MODE_NEAREST) {
+    const uint32_t blocks = fragmap_blocks(m);
+    if (fmt == FMT_BIT1) {
+        if (mode == MODE_NEAREST)
+            hipLaunchKernelGGL((k_lookup_fwd<FMT_BIT1, 1, MODE_NEAREST>), dim3(blocks), dim3(256), 0, s, t, uv, tbn, view, out, m);
+        else
+            hipLaunchKernelGGL((k_lookup_fwd<FMT_BIT1, 1, MODE_BILINEAR>), dim3(blocks), dim3(256), 0, s, t, uv, tbn, view, out, m);
+        e = hipGetLastError();
+    } else if (mode == MODE_NEAREST) {
         if (fmt == FMT_F32) e = launch_fwd_c<FMT_F32, MODE_NEAREST>(t, uv, tbn, view, out, m, s);
         else if (fmt == FMT_BF16) e = launch_fwd_c<FMT_BF16, MODE_NEAREST>(t, uv, tbn, view, out, m, s);
         else e = launch_fwd_c<FMT_FP8, MODE_NEAREST>(t, uv, tbn, view, out, m, s);
@@ -231,6 +255,101 @@ hipError_t launch_debug_indices(const TexView& t, const float* uv, const float* 
     if (m.N <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_debug_indices, dim3(fragmap_blocks(m)), dim3(256), 0, s, t, uv, tbn,
                        view, idx, frac, m);
+    return hipGetLastError();
+}
+
+// Light lookup: the bucket footprint depends on (u, v) only, so it is formed
+// once per fragment; each light sample then maps its own direction (Eq. 1b,
+// Eq. 3, the clamp) and adds its bilinear taps.  The direction toward the
+// light is the sample's vector (directional light) or the sample point minus
+// the fragment's position (point light).  The samples live in the kernel's
+// argument block and are read with scalar loads (every lane of a wave reads
+// the same sample).
+template <int FMT, int C, int MODE>
+__global__ __launch_bounds__(256) void k_lookup_light(TexView t, const float* __restrict__ uv,
+                                                      const float* __restrict__ tbn,
+                                                      const float* __restrict__ pos,
+                                                      LightParams lp, float* __restrict__ out,
+                                                      FragMap m) {
+    const int64_t f = frag_of(m, blockIdx.x, gridDim.x, threadIdx.x);
+    if (f < 0) return;
+    const float2 q = ((const float2*)uv)[f];
+    float M[9];
+#pragma unroll
+    for (int k = 0; k < 9; k++) M[k] = tbn[f * 9 + k];
+    float P[3] = {0.f, 0.f, 0.f};
+    if (lp.kind == LIGHT_POINT) {
+#pragma unroll
+        for (int k = 0; k < 3; k++) P[k] = pos[f * 3 + k];
+    }
+    constexpr int NB = MODE == MODE_NEAREST ? 1 : 4;
+    int64_t bk[NB];
+    float bw[NB];
+    if constexpr (MODE == MODE_NEAREST) {
+        bk[0] = (int64_t)bucket_of(q.y, t.H) * t.W + bucket_of(q.x, t.W);
+        bw[0] = 1.f;
+    } else {
+        int i0, i1, j0, j1;
+        float a, bb;
+        bucket_pair(q.x, t.W, i0, i1, a);
+        bucket_pair(q.y, t.H, j0, j1, bb);
+        bk[0] = (int64_t)j0 * t.W + i0;
+        bk[1] = (int64_t)j0 * t.W + i1;
+        bk[2] = (int64_t)j1 * t.W + i0;
+        bk[3] = (int64_t)j1 * t.W + i1;
+        bw[0] = (1.f - a) * (1.f - bb);
+        bw[1] = a * (1.f - bb);
+        bw[2] = (1.f - a) * bb;
+        bw[3] = a * bb;
+    }
+    float acc[4] = {0.f, 0.f, 0.f, 0.f};
+    for (int s = 0; s < lp.samples; s++) {
+        float L[3];
+#pragma unroll
+        for (int k = 0; k < 3; k++) L[k] = lp.vec[s][k] - P[k];
+        const Dir d = map_direction(M, L, t.n);
+        const Foot p = footprint(d.sx, d.sy, t.n);
+#pragma unroll
+        for (int r = 0; r < NB; r++) bucket_bilerp<FMT, C>(t, bk[r], p, bw[r], acc);
+    }
+#pragma unroll
+    for (int c = 0; c < C; c++) acc[c] *= lp.inv_samples;
+    store_out<C>(out, f, acc);
+}
+
+template <int FMT, int MODE>
+static void launch_light_c(const TexView& t, const float* uv, const float* tbn, const float* pos,
+                           const LightParams& lp, float* out, const FragMap& m, hipStream_t s) {
+    const uint32_t blocks = fragmap_blocks(m);
+    switch (t.C) {
+    case 1: hipLaunchKernelGGL((k_lookup_light<FMT, 1, MODE>), dim3(blocks), dim3(256), 0, s, t, uv, tbn, pos, lp, out, m); break;
+    case 2: hipLaunchKernelGGL((k_lookup_light<FMT, 2, MODE>), dim3(blocks), dim3(256), 0, s, t, uv, tbn, pos, lp, out, m); break;
+    case 3: hipLaunchKernelGGL((k_lookup_light<FMT, 3, MODE>), dim3(blocks), dim3(256), 0, s, t, uv, tbn, pos, lp, out, m); break;
+    default: hipLaunchKernelGGL((k_lookup_light<FMT, 4, MODE>), dim3(blocks), dim3(256), 0, s, t, uv, tbn, pos, lp, out, m); break;
+    }
+}
+
+hipError_t launch_lookup_light(const TexView& t, int fmt, int mode, const float* uv,
+                               const float* tbn, const float* pos, const LightParams& lp,
+                               float* out, const FragMap& m, hipStream_t s) {
+    if (m.N <= 0) return hipSuccess;
+    prof_begin(K_LOOKUP_LIGHT, s);
+    const uint32_t blocks = fragmap_blocks(m);
+    if (fmt == FMT_BIT1) {
+        if (mode == MODE_NEAREST)
+            hipLaunchKernelGGL((k_lookup_light<FMT_BIT1, 1, MODE_NEAREST>), dim3(blocks), dim3(256), 0, s, t, uv, tbn, pos, lp, out, m);
+        else
+            hipLaunchKernelGGL((k_lookup_light<FMT_BIT1, 1, MODE_BILINEAR>), dim3(blocks), dim3(256), 0, s, t, uv, tbn, pos, lp, out, m);
+    } else if (mode == MODE_NEAREST) {
+        if (fmt == FMT_F32) launch_light_c<FMT_F32, MODE_NEAREST>(t, uv, tbn, pos, lp, out, m, s);
+        else if (fmt == FMT_BF16) launch_light_c<FMT_BF16, MODE_NEAREST>(t, uv, tbn, pos, lp, out, m, s);
+        else launch_light_c<FMT_FP8, MODE_NEAREST>(t, uv, tbn, pos, lp, out, m, s);
+    } else {
+        if (fmt == FMT_F32) launch_light_c<FMT_F32, MODE_BILINEAR>(t, uv, tbn, pos, lp, out, m, s);
+        else if (fmt == FMT_BF16) launch_light_c<FMT_BF16, MODE_BILINEAR>(t, uv, tbn, pos, lp, out, m, s);
+        else launch_light_c<FMT_FP8, MODE_BILINEAR>(t, uv, tbn, pos, lp, out, m, s);
+    }
+    prof_end(K_LOOKUP_LIGHT, s);
     return hipGetLastError();
 }
 

@@ -1,7 +1,7 @@
-// rt_quantize.hip -- per-bucket BF16 / FP8-E4M3 quantiser and the atlas ->
-// bucket-major re-layout, for gfx950.
+// rt_quantize.hip -- per-bucket BF16 / FP8-E4M3 quantiser, the 1-bit packer
+// of shadow textures, and the atlas -> bucket-major re-layout, for gfx950.
 //
-// Both are HBM streams.  BF16 is elementwise (float4 in, 4 x bf16 out).  FP8
+// All are HBM streams.  BF16 is elementwise (float4 in, 4 x bf16 out).  FP8
 // runs one wavefront per bucket: the bucket's amax is reduced across the wave
 // with cross-lane max, then every lane encodes its values with the bucket's
 // inverse scale.  Encodes are written from the formats' definitions with
@@ -140,10 +140,74 @@ __global__ __launch_bounds__(256) void k_quant_fp8(const float* __restrict__ src
     }
 }
 
+// 1-bit packer (Sec. 5, Shadowing: a 1-bit texture holds occlusion): each
+// sample becomes the bit (x >= 1/2).  When n is a multiple of 8 a bucket is
+// a whole number of words and the bits of the texture are one flat array:
+// each lane reads a float4 (four consecutive samples) and eight neighbouring
+// lanes OR their nibbles into one word.
+template <int U>
+__global__ __launch_bounds__(256) void k_pack_bits_flat(const float* __restrict__ src,
+                                                        uint32_t* __restrict__ words,
+                                                        int64_t quads) {
+    const int64_t base = (int64_t)xcd_block_id(blockIdx.x, gridDim.x) * (256 * U) + threadIdx.x;
+    f4v v[U];
+#pragma unroll
+    for (int k = 0; k < U; k++) {
+        const int64_t q = base + k * 256;
+        if (q < quads) v[k] = __builtin_nontemporal_load((const f4v*)src + q);
+    }
+#pragma unroll
+    for (int k = 0; k < U; k++) {
+        const int64_t q = base + k * 256;
+        uint32_t nib = 0;
+        if (q < quads)
+            nib = (v[k].x >= 0.5f ? 1u : 0u) | (v[k].y >= 0.5f ? 2u : 0u) |
+                  (v[k].z >= 0.5f ? 4u : 0u) | (v[k].w >= 0.5f ? 8u : 0u);
+        uint32_t w = nib << (4 * (threadIdx.x & 7));
+        w |= __shfl_xor(w, 1, 64);
+        w |= __shfl_xor(w, 2, 64);
+        w |= __shfl_xor(w, 4, 64);
+        if (q < quads && (threadIdx.x & 7) == 0) words[q >> 3] = w;
+    }
+}
+
+// Any n: one lane per word, reading the (up to) 32 samples it holds.
+__global__ __launch_bounds__(256) void k_pack_bits_words(const float* __restrict__ src,
+                                                         uint32_t* __restrict__ words,
+                                                         int64_t total_words, int nn, int wpb) {
+    const int64_t g = (int64_t)xcd_block_id(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
+    if (g >= total_words) return;
+    const int64_t b = g / wpb;
+    const int k0 = (int)(g - b * wpb) * 32;
+    const int k1 = min(k0 + 32, nn);
+    const float* p = src + b * nn;
+    uint32_t w = 0;
+    for (int k = k0; k < k1; k++) w |= (p[k] >= 0.5f ? 1u : 0u) << (k - k0);
+    words[g] = w;
+}
+
 hipError_t launch_quantize(const TexView& t, int dst_fmt, void* codes, float* scales,
                            hipStream_t s) {
     const int64_t nb = (int64_t)t.W * t.H;
     const int elems = t.n * t.n * t.C;
+    if (dst_fmt == FMT_BIT1) {
+        prof_begin(K_PACK_BITS, s);
+        if (t.n % 8 == 0) {
+            constexpr int U = 2;
+            const int64_t quads = nb * elems / 4;
+            const uint32_t blocks = (uint32_t)((quads + 256 * U - 1) / (256 * U));
+            hipLaunchKernelGGL(k_pack_bits_flat<U>, dim3(blocks), dim3(256), 0, s,
+                               (const float*)t.data, (uint32_t*)codes, quads);
+        } else {
+            const int wpb = bit_words(t.n);
+            const int64_t total = nb * wpb;
+            const uint32_t blocks = (uint32_t)((total + 255) / 256);
+            hipLaunchKernelGGL(k_pack_bits_words, dim3(blocks), dim3(256), 0, s,
+                               (const float*)t.data, (uint32_t*)codes, total, elems, wpb);
+        }
+        prof_end(K_PACK_BITS, s);
+        return hipGetLastError();
+    }
     if (dst_fmt == FMT_BF16) {
         const int64_t total = nb * elems;
         const int64_t quads = total / 4;

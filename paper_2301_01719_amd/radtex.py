@@ -19,19 +19,29 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("RADTEX_LIBRARY", os.path.join(HERE, "libradtex.so"))
 
 RT_OK = 0
-RT_FMT_F32, RT_FMT_BF16, RT_FMT_FP8_E4M3 = 0, 1, 2
+RT_FMT_F32, RT_FMT_BF16, RT_FMT_FP8_E4M3, RT_FMT_BIT1 = 0, 1, 2, 3
 RT_LAYOUT_BUCKET_MAJOR, RT_LAYOUT_ATLAS = 0, 1
 RT_BUCKET_NEAREST, RT_BUCKET_BILINEAR = 0, 1
+RT_LIGHT_DIRECTIONAL, RT_LIGHT_POINT = 0, 1
+RT_MAX_LIGHT_SAMPLES = 64
 
-FORMATS = {"f32": RT_FMT_F32, "bf16": RT_FMT_BF16, "fp8": RT_FMT_FP8_E4M3}
+FORMATS = {"f32": RT_FMT_F32, "bf16": RT_FMT_BF16, "fp8": RT_FMT_FP8_E4M3, "bit1": RT_FMT_BIT1}
 MODES = {"nearest": RT_BUCKET_NEAREST, "bilinear": RT_BUCKET_BILINEAR}
-_CODE_DTYPE = {RT_FMT_F32: torch.float32, RT_FMT_BF16: torch.int16, RT_FMT_FP8_E4M3: torch.uint8}
+LIGHTS = {"directional": RT_LIGHT_DIRECTIONAL, "point": RT_LIGHT_POINT}
+_CODE_DTYPE = {RT_FMT_F32: torch.float32, RT_FMT_BF16: torch.int16, RT_FMT_FP8_E4M3: torch.uint8,
+               RT_FMT_BIT1: torch.int32}
+
+
+def bit_words(n: int) -> int:
+    """32-bit words per bucket of a 1-bit texture: ceil(n n / 32)."""
+    return (int(n) * int(n) + 31) // 32
 
 EXPORTS = ("rt_create_texture", "rt_destroy_texture", "rt_quantize", "rt_lookup_fwd",
            "rt_lookup_bwd_workspace", "rt_lookup_bwd", "rt_debug_indices", "rt_last_error",
            "rt_status_string", "rt_version", "rt_profile_enable", "rt_profile_reset",
            "rt_profile_kernel_count", "rt_profile_kernel_name", "rt_profile_read",
-           "rt_bake_directions", "rt_bake_environment", "rt_build_mip", "rt_lookup_fwd_lod")
+           "rt_bake_directions", "rt_bake_environment", "rt_build_mip", "rt_lookup_fwd_lod",
+           "rt_lookup_light", "rt_bake_shadow")
 
 
 class RadtexError(RuntimeError):
@@ -50,6 +60,11 @@ class TextureDesc(ctypes.Structure):
 class EnvLobe(ctypes.Structure):
     _fields_ = [("axis", ctypes.c_float * 3), ("sharpness", ctypes.c_float),
                 ("amplitude", ctypes.c_float * 4)]
+
+
+class Light(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("samples", ctypes.c_int32),
+                ("vec", (ctypes.c_float * 3) * RT_MAX_LIGHT_SAMPLES)]
 
 
 class Fragments(ctypes.Structure):
@@ -87,6 +102,9 @@ def _load() -> ctypes.CDLL:
                               i32),
         "rt_bake_environment": ([i32, i32, i32, i32, P, ctypes.POINTER(EnvLobe), i32,
                                  ctypes.POINTER(ctypes.c_float), P, P], i32),
+        "rt_lookup_light": ([P, ctypes.POINTER(Fragments), P, ctypes.POINTER(Light), P, u32, P],
+                            i32),
+        "rt_bake_shadow": ([i32, i32, i32, P, P, ctypes.POINTER(ctypes.c_float), i32, P, P], i32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -138,8 +156,12 @@ class Texture:
             _need_gpu(scales, "scales", torch.float32)
         self.data, self.scales = data, scales
         self.W, self.H, self.n, self.C = int(W), int(H), int(n), int(C)
-        if data.numel() * data.element_size() != W * H * n * n * C * [4, 2, 1][self.fmt]:
-            raise ValueError("texture data size does not match W*H*n*n*C in this format")
+        if self.fmt == RT_FMT_BIT1:
+            want = W * H * bit_words(n) * 4
+        else:
+            want = W * H * n * n * C * [4, 2, 1][self.fmt]
+        if data.numel() * data.element_size() != want:
+            raise ValueError("texture data size does not match the matrix in this format")
         desc = TextureDesc(self.W, self.H, self.n, self.C, self.fmt,
                            RT_LAYOUT_ATLAS if layout == "atlas" else RT_LAYOUT_BUCKET_MAJOR,
                            data.data_ptr(), None if scales is None else scales.data_ptr())
@@ -166,20 +188,28 @@ class Texture:
 
 def _frags(uv, tbn, view, image=None) -> Fragments:
     """image = (views, height, width): the fragments are that many row-major
-    images (a tiling hint, checked by the library); None: a flat list."""
+    images (a tiling hint, checked by the library); None: a flat list.  view
+    may be None where the entry point does not read it."""
     N = uv.shape[0]
     for t, name, shape in ((uv, "uv", (N, 2)), (tbn, "tbn", (N, 3, 3)), (view, "view", (N, 3))):
+        if t is None and name == "view":
+            continue
         _need_gpu(t, name, torch.float32)
         if tuple(t.shape) != shape and not (name == "tbn" and tuple(t.shape) == (N, 9)):
             raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {shape}")
     v, h, w = image if image is not None else (0, 0, 0)
-    return Fragments(N, v, h, w, uv.data_ptr(), tbn.data_ptr(), view.data_ptr())
+    return Fragments(N, v, h, w, uv.data_ptr(), tbn.data_ptr(),
+                     None if view is None else view.data_ptr())
 
 
 def quantize(tex: Texture, fmt: str):
-    """Per-bucket quantiser: returns (codes, scales); scales is None for BF16."""
+    """Per-bucket quantiser: returns (codes, scales); scales is None for BF16
+    and 1-bit ("bit1": int32 words [H, W, ceil(n n/32)] of a one-channel
+    texture)."""
     f = FORMATS[fmt]
     shape = (tex.H, tex.W, tex.n, tex.n, tex.C)
+    if f == RT_FMT_BIT1:
+        shape = (tex.H, tex.W, bit_words(tex.n))
     codes = torch.empty(shape, dtype=_CODE_DTYPE[f], device=tex.device)
     scales = (torch.empty((tex.H, tex.W), dtype=torch.float32, device=tex.device)
               if f == RT_FMT_FP8_E4M3 else None)
@@ -325,6 +355,63 @@ def bake_environment(W: int, H: int, n: int, C: int, lobes, ambient, frames=None
     amb = (ctypes.c_float * 4)(*[float(a) for a in ambient])
     _check(LIB.rt_bake_environment(int(W), int(H), int(n), int(C), _ptr(frames), arr, K, amb,
                                    _ptr(out), _stream(out.device)))
+    return out
+
+
+# --- shadowing: 1-bit textures read with the light direction -------------------
+
+def make_light(vecs, kind: str = "directional") -> Light:
+    """A light of S = len(vecs) samples (S <= 64): directions toward the light
+    ("directional") or points of the light ("point"), scene space."""
+    import numpy as np
+    v = np.asarray(vecs, dtype=np.float32).reshape(-1, 3)
+    if not 1 <= v.shape[0] <= RT_MAX_LIGHT_SAMPLES:
+        raise ValueError(f"a light has 1..{RT_MAX_LIGHT_SAMPLES} samples, got {v.shape[0]}")
+    L = Light()
+    L.kind = LIGHTS[kind]
+    L.samples = v.shape[0]
+    for s in range(v.shape[0]):
+        for k in range(3):
+            L.vec[s][k] = float(v[s, k])
+    return L
+
+
+def lookup_light(tex: Texture, uv, tbn, light: Light, pos=None, mode: str = "nearest",
+                 out=None, image=None):
+    """Mean over the light's samples of the lookup with the direction toward
+    the light in place of the view vector (rt_lookup_light); pos [N, 3] is the
+    fragments' scene positions, read for point lights."""
+    fr = _frags(uv, tbn, None, image)
+    if pos is not None:
+        _need_gpu(pos, "pos", torch.float32)
+        if tuple(pos.shape) != (fr.count, 3):
+            raise ValueError(f"pos has shape {tuple(pos.shape)}, expected {(fr.count, 3)}")
+    if out is None:
+        out = torch.empty((fr.count, tex.C), dtype=torch.float32, device=tex.device)
+    else:
+        _need_gpu(out, "out", torch.float32)
+    _check(LIB.rt_lookup_light(tex.handle, ctypes.byref(fr), _ptr(pos), ctypes.byref(light),
+                               _ptr(out), MODES[mode], _stream(tex.device)))
+    return out
+
+
+def bake_shadow(W: int, H: int, n: int, origins, balls, frames=None, out=None):
+    """1-bit shadow texture (int32 words [H, W, ceil(n n/32)]) of the balls
+    [K, 4] (centre, radius; host values) seen from the buckets' scene points
+    origins [H, W, 3] with frames [H, W, 3, 3] (None: identity)."""
+    import numpy as np
+    _need_gpu(origins, "origins", torch.float32)
+    dev = origins.device
+    b = np.ascontiguousarray(np.asarray(balls, dtype=np.float32).reshape(-1, 4))
+    if frames is not None:
+        _need_gpu(frames, "frames", torch.float32)
+    if out is None:
+        out = torch.empty((H, W, bit_words(n)), dtype=torch.int32, device=dev)
+    else:
+        _need_gpu(out, "out", torch.int32)
+    _check(LIB.rt_bake_shadow(int(W), int(H), int(n), _ptr(origins), _ptr(frames),
+                              b.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), b.shape[0],
+                              _ptr(out), _stream(dev)))
     return out
 
 

@@ -19,6 +19,10 @@ Workloads (bucket matrix W x H of n x n samples with C channels):
   C4  256x256 buckets, n=8, RGB, smooth radiance; 16 views of 512x512.
   C5  2048x2048 buckets, n=16, RGBA, smooth radiance; 8 views of 3840x2160
       over a bumpy height field (gradient noise, amplitude 0.1).
+
+Shadow scenes (Sec. 5, Shadowing): balls hovering over the UV-tiled plane
+z = 0 stand in for static occluders; lights are sets of directions (a sun
+disc) or points (a spherical lamp), sampled on golden-angle spirals.
 """
 from __future__ import annotations
 
@@ -41,7 +45,7 @@ _K1 = _s64(0xBF58476D1CE4E5B9)
 _K2 = _s64(0x94D049BB133111EB)
 
 # stream ids
-S_TEXTURE, S_CAMERA, S_UV, S_VIEW, S_NORMAL, S_GRAD, S_NOISE = 0, 1, 2, 3, 4, 5, 6
+S_TEXTURE, S_CAMERA, S_UV, S_VIEW, S_NORMAL, S_GRAD, S_NOISE, S_BALLS = 0, 1, 2, 3, 4, 5, 6, 7
 
 
 def _mix_py(z: int) -> int:
@@ -161,6 +165,7 @@ class GBuffer:
     view: torch.Tensor  # [N, 3] float32, surface -> eye
     image: Optional[Tuple[int, int, int]] = None  # (views, height, width), row-major
     duv: Optional[torch.Tensor] = None  # [N, 4] float32 du/dx, dv/dx, du/dy, dv/dy per pixel
+    pos: Optional[torch.Tensor] = None  # [N, 3] float32 scene position of the surface point
 
     @property
     def count(self) -> int:
@@ -168,11 +173,13 @@ class GBuffer:
 
     def slice(self, a: int, b: int) -> "GBuffer":
         return GBuffer(self.uv[a:b], self.tbn[a:b], self.view[a:b], None,
-                       None if self.duv is None else self.duv[a:b])
+                       None if self.duv is None else self.duv[a:b],
+                       None if self.pos is None else self.pos[a:b])
 
     def to(self, device) -> "GBuffer":
         return GBuffer(self.uv.to(device), self.tbn.to(device), self.view.to(device), self.image,
-                       None if self.duv is None else self.duv.to(device))
+                       None if self.duv is None else self.duv.to(device),
+                       None if self.pos is None else self.pos.to(device))
 
 
 def screen_derivatives(uv: torch.Tensor, views: int, height: int, width: int) -> torch.Tensor:
@@ -243,7 +250,7 @@ def plane_gbuffer(views: int, width: int, height: int, seed: int, device="cpu",
     U[0,8)^2, yaw U[0, 2 pi), pitch U[-90, -40] degrees, so every pixel hits
     the plane.  Per-pixel normals are tilted by two N(0, sigma) angles."""
     npx = width * height
-    uvs, tbns, viewsl = [], [], []
+    uvs, tbns, viewsl, poss = [], [], [], []
     sig = math.radians(normal_sigma_deg)
     for v in range(views):
         h, x, y, yaw, pitch = _camera(seed, v)
@@ -259,10 +266,12 @@ def plane_gbuffer(views: int, width: int, height: int, seed: int, device="cpu",
         uvs.append(uv)
         tbns.append(tbn)
         viewsl.append(vw.to(torch.float32))
+        poss.append(P.to(torch.float32))
         del eye, d, lam, P, Nv
     uv_all = torch.cat(uvs).contiguous()
     return GBuffer(uv_all, torch.cat(tbns).contiguous(), torch.cat(viewsl).contiguous(),
-                   (views, height, width), screen_derivatives(uv_all, views, height, width))
+                   (views, height, width), screen_derivatives(uv_all, views, height, width),
+                   torch.cat(poss).contiguous())
 
 
 # --- gradient noise height field (C5) -----------------------------------------
@@ -323,6 +332,7 @@ def heightfield_gbuffer(views: int, width: int, height: int, seed: int, device="
     uv = torch.empty((N_all, 2), dtype=torch.float32, device=device)
     tbn = torch.empty((N_all, 3, 3), dtype=torch.float32, device=device)
     vw = torch.empty((N_all, 3), dtype=torch.float32, device=device)
+    pos = torch.empty((N_all, 3), dtype=torch.float32, device=device)
     for v in range(views):
         h, x, y, yaw, pitch = _camera(seed, v)
         eye, d_all = _rays(h, x, y, yaw, pitch, width, height, device)
@@ -348,9 +358,72 @@ def heightfield_gbuffer(views: int, width: int, height: int, seed: int, device="
             uv[a:b] = (P[:, :2] * uv_scale).to(torch.float32)
             tbn[a:b] = _frame_from_normal(Nv).to(torch.float32)
             vw[a:b] = (-d / torch.linalg.vector_norm(d, dim=1, keepdim=True)).to(torch.float32)
+            pos[a:b] = P.to(torch.float32)
         del d_all
     return GBuffer(uv, tbn, vw, (views, height, width),
-                   screen_derivatives(uv, views, height, width))
+                   screen_derivatives(uv, views, height, width), pos)
+
+
+# --- shadow scenes ----------------------------------------------------------------
+
+PLANE_EXTENT = 8.0  # the plane generators map scene (x, y) to UV = (x, y) / 8
+
+
+def shadow_balls(K: int, seed: int, extent: float = PLANE_EXTENT, zlim=(0.6, 2.0),
+                 rlim=(0.15, 0.5)) -> torch.Tensor:
+    """K balls [K, 4] float32 (centre x, y, z, radius) over the plane tile
+    [0, extent)^2: centres uniform in the tile at heights U[zlim], radii
+    U[rlim] (each ball clears the plane)."""
+    idx = torch.arange(4 * K, dtype=torch.int64).reshape(K, 4)
+    u = uniform64(seed, S_BALLS, idx)
+    z = zlim[0] + (zlim[1] - zlim[0]) * u[:, 2]
+    r = rlim[0] + (rlim[1] - rlim[0]) * u[:, 3]
+    r = torch.minimum(r, 0.9 * z)
+    return torch.stack([extent * u[:, 0], extent * u[:, 1], z, r], 1).to(torch.float32)
+
+
+def bucket_origins(W: int, H: int, extent: float = PLANE_EXTENT, device="cpu") -> torch.Tensor:
+    """Scene points of the buckets of a W x H matrix laid over the plane tile
+    [0, extent)^2 (UV = (x, y) / extent): the bucket centres, [H, W, 3]."""
+    x = (torch.arange(W, dtype=torch.float64, device=device) + 0.5) * (extent / W)
+    y = (torch.arange(H, dtype=torch.float64, device=device) + 0.5) * (extent / H)
+    o = torch.zeros((H, W, 3), dtype=torch.float64, device=device)
+    o[..., 0] = x[None, :]
+    o[..., 1] = y[:, None]
+    return o.to(torch.float32)
+
+
+def spiral_cap(axis, half_angle: float, k: int) -> torch.Tensor:
+    """k unit directions [k, 3] float64 uniform in solid angle over the cap of
+    the given half-angle (radians) around axis, on a golden-angle spiral."""
+    i = torch.arange(k, dtype=torch.float64) + 0.5
+    cz = 1.0 - i / k * (1.0 - math.cos(half_angle))
+    phi = i * math.pi * (3.0 - math.sqrt(5.0))
+    sz = torch.sqrt(torch.clamp(1.0 - cz * cz, min=0.0))
+    loc = torch.stack([sz * torch.cos(phi), sz * torch.sin(phi), cz], 1)
+    a = torch.tensor(axis, dtype=torch.float64)
+    a = a / torch.linalg.vector_norm(a)
+    ref = torch.tensor([1.0, 0.0, 0.0] if abs(float(a[0])) < 0.9 else [0.0, 1.0, 0.0],
+                       dtype=torch.float64)
+    t = torch.linalg.cross(a, ref, dim=0)
+    t = t / torch.linalg.vector_norm(t)
+    b = torch.linalg.cross(a, t, dim=0)
+    return loc @ torch.stack([t, b, a])
+
+
+def sun_light(k: int, elevation_deg: float = 55.0, azimuth_deg: float = 30.0,
+              radius_deg: float = 2.0) -> torch.Tensor:
+    """Directions [k, 3] float32 toward a sun disc of the given angular radius."""
+    el, az = math.radians(elevation_deg), math.radians(azimuth_deg)
+    axis = [math.cos(el) * math.cos(az), math.cos(el) * math.sin(az), math.sin(el)]
+    return spiral_cap(axis, math.radians(radius_deg), k).to(torch.float32)
+
+
+def lamp_light(k: int, centre=(4.0, 4.0, 3.0), radius: float = 0.25) -> torch.Tensor:
+    """Points [k, 3] float32 on a spherical lamp (the full sphere, uniform by
+    area), centre and radius in scene units."""
+    d = spiral_cap([0.0, 0.0, 1.0], math.pi, k)
+    return (torch.tensor(centre, dtype=torch.float64) + radius * d).to(torch.float32)
 
 
 def grad_out(N: int, C: int, seed: int, device="cpu") -> torch.Tensor:

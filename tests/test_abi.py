@@ -231,3 +231,108 @@ def test_mip_entries_reject_bad_arguments(rt):
     assert L.rt_lookup_fwd_lod(lv, 18, ctypes.byref(fr), 0x4000, 0x5000, 0, None) == 2
     assert L.rt_lookup_fwd_lod(lv, 2, ctypes.byref(fr), 0x4000, 0x5000, 0, None) == 1
     assert "level 0 is NULL" in L.rt_last_error().decode()
+
+
+def test_one_bit_texture_descriptors(rt):
+    """1-bit textures: one channel, bucket-major, no scales (host checks made
+    before the device is looked for)."""
+    L = rt.LIB
+    h = ctypes.c_void_p()
+    for kw, status, text in ((dict(format=3, channels=4), 1, "one channel"),
+                             (dict(format=3, channels=1, layout=1), 2, "bucket-major"),
+                             (dict(format=3, channels=1, scales=0x2000), 1, "scales"),
+                             (dict(format=4, channels=1), 1, "unknown format")):
+        d = _desc(rt, **kw)
+        assert L.rt_create_texture(ctypes.byref(d), None, ctypes.byref(h)) == status, kw
+        assert text in L.rt_last_error().decode(), (kw, L.rt_last_error())
+
+
+def test_shadow_bake_validation(rt):
+    import math
+    import torch
+    L = rt.LIB
+
+    def call(W=4, H=3, n=8, origins=0x1000, frames=None, balls=((0, 0, 2, 1),), nballs=None,
+             words=0x3000):
+        import numpy as np
+        b = np.ascontiguousarray(np.asarray(balls, np.float32).reshape(-1, 4))
+        ptr = b.ctypes.data_as(ctypes.POINTER(ctypes.c_float)) if b.size else None
+        return L.rt_bake_shadow(W, H, n, origins, frames, ptr,
+                                b.shape[0] if nballs is None else nballs, words, None)
+
+    for kw, status, text in (
+            (dict(W=0), 1, "bucket matrix"), (dict(H=70000), 2, "exceeds"),
+            (dict(n=0), 1, "angular resolution"), (dict(n=33), 2, "exceeds 32"),
+            (dict(nballs=65), 2, "exceeds 64"), (dict(nballs=-1), 1, "< 0"),
+            (dict(balls=(), nballs=2), 1, "balls is NULL"),
+            (dict(origins=None), 1, "origins"), (dict(words=None), 1, "words"),
+            (dict(origins=0x1002), 1, "aligned"), (dict(frames=0x2001), 1, "aligned"),
+            (dict(words=0x3002), 1, "aligned"),
+            (dict(balls=((0, 0, 2, 0),)), 1, "radius"), (dict(balls=((0, 0, 2, -1),)), 1, "radius"),
+            (dict(balls=((0, math.nan, 2, 1),)), 1, "finite"),
+            (dict(balls=((0, 0, math.inf, 1),)), 1, "finite")):
+        assert call(**kw) == status, kw
+        assert text in L.rt_last_error().decode(), (kw, L.rt_last_error())
+    if not torch.cuda.is_available():
+        assert call() == 5 and "no HIP device" in L.rt_last_error().decode()
+        assert call(balls=(), nballs=0) == 5
+
+
+def test_light_lookup_needs_a_texture_and_a_light(rt):
+    L = rt.LIB
+    fr = _fr(rt, 10, 0x1000, 0x2000, None)
+    light = rt.make_light([(0, 0, 1)])
+    assert L.rt_lookup_light(None, ctypes.byref(fr), None, ctypes.byref(light), 0x4000, 0,
+                             None) == 1
+    assert "texture handle" in L.rt_last_error().decode()
+    with pytest.raises(ValueError, match="1..64"):
+        rt.make_light([(0, 0, 1)] * 65)
+    with pytest.raises(KeyError):
+        rt.make_light([(0, 0, 1)], kind="spot")
+
+
+def test_light_lookup_validation_with_a_handle(rt):
+    """Checks that need a texture handle (skipped where no device is visible)."""
+    import math
+    L = rt.LIB
+    h = ctypes.c_void_p()
+    d = _desc(rt, format=3, channels=1)
+    st = L.rt_create_texture(ctypes.byref(d), None, ctypes.byref(h))
+    if st == 5:
+        pytest.skip("no device: handle creation refused before the light checks")
+    assert st == 0
+    try:
+        good = _fr(rt, 10, 0x1000, 0x2000, None)
+        lt = rt.make_light([(0, 0, 1), (0.1, 0, 1)])
+
+        def call(fr=good, pos=None, light=lt, out=0x4000, flags=0):
+            return L.rt_lookup_light(h, ctypes.byref(fr), pos,
+                                     None if light is None else ctypes.byref(light), out, flags,
+                                     None)
+        assert call(light=None) == 1 and "light is NULL" in L.rt_last_error().decode()
+        bad = rt.make_light([(0, 0, 1)])
+        bad.kind = 7
+        assert call(light=bad) == 1 and "kind" in L.rt_last_error().decode()
+        bad = rt.make_light([(0, 0, 1)])
+        bad.samples = 0
+        assert call(light=bad) == 1 and "samples" in L.rt_last_error().decode()
+        bad.samples = 65
+        assert call(light=bad) == 1 and "samples" in L.rt_last_error().decode()
+        bad = rt.make_light([(0, 0, math.nan)])
+        assert call(light=bad) == 1 and "finite" in L.rt_last_error().decode()
+        pl = rt.make_light([(0, 0, 3)], kind="point")
+        assert call(light=pl) == 1 and "positions" in L.rt_last_error().decode()
+        assert call(light=pl, pos=0x5002) == 1 and "pos" in L.rt_last_error().decode()
+        assert call(out=None) == 1 and "out is NULL" in L.rt_last_error().decode()
+        assert call(flags=2) == 1 and "flags" in L.rt_last_error().decode()
+        nouv = _fr(rt, 10, None, 0x2000, None)
+        assert call(fr=nouv) == 1 and "uv and tbn" in L.rt_last_error().decode()
+        # the backward and the level-of-detail lookup refuse 1-bit textures
+        fr3 = _fr(rt, 10, 0x1000, 0x2000, 0x3000)
+        assert L.rt_lookup_bwd(h, ctypes.byref(fr3), 0x6000, 0x7000, None, None, 0x8000,
+                               1 << 30, 0, None) == 2
+        lv = (ctypes.c_void_p * 1)(h)
+        assert L.rt_lookup_fwd_lod(lv, 1, ctypes.byref(fr3), 0x4000, 0x5000, 0, None) == 2
+        assert L.rt_build_mip(h, 0x1000, None) == 2
+    finally:
+        L.rt_destroy_texture(h)

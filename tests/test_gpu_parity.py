@@ -470,3 +470,25 @@ def test_graph_replay(rt):
         _sync()
         for a, b in zip(ref, (codes, out, gt, gv_g, gu_g)):
             assert torch.equal(a, b), r
+
+
+@pytest.mark.parametrize("W,H", [(4096, 2), (1, 2048), (1024, 1024)])
+def test_bilinear_bucket_weights_keep_their_precision_on_wide_matrices(rt, W, H):
+    # the bucket weight a = frac(u) W - 1/2 - floor(...) must not be rounded
+    # to the ulp of u W (3e-5 at u W ~ 512): coordinates spread over
+    # [-3, 3] against a matrix of up to 4096 buckets per side, with a texture
+    # of full contrast between neighbouring buckets
+    n, C, N = 2, 1, 20000
+    g = torch.Generator().manual_seed(W + H)
+    tex_c = (torch.rand((H, W, n, n, C), generator=g) < 0.5).to(torch.float32)
+    uv = (torch.rand((N, 2), generator=g, dtype=torch.float64) * 6 - 3).to(torch.float32)
+    tbn = torch.eye(3).expand(N, 3, 3).contiguous()
+    view = torch.tensor([[0.1, 0.2, 1.0]]).expand(N, 3).contiguous()
+    tex_d = tex_c.to(DEV)
+    tex = rt.Texture(tex_d, W, H, n, C)
+    out = rt.lookup_fwd(tex, uv.to(DEV), tbn.to(DEV), view.to(DEV), mode="bilinear")
+    _sync()
+    ref = oracle.lookup_fwd(oracle.Tex(tex_c.numpy(), W, H, n, C), uv.numpy(), tbn.numpy(),
+                            view.numpy(), mode=oracle.MODE_BILINEAR)
+    err = check_fwd(host(out), ref)
+    print(f"W={W} H={H}: max |err| {err:.3g}")

@@ -1,0 +1,373 @@
+"""Shadowing (Sec. 5, Shadowing) on the GPU against the FP64 oracle: the 1-bit
+packer (bit-exact), the lookup of 1-bit textures, the light lookup (the
+lookup with the direction toward the light, averaged over an area light's
+samples) for every storage format, and the shadow bake of analytic
+occluders; end to end, a baked shadow texture read with a sun's samples
+approaches the exact penumbra as the resolution grows.
+
+Tolerances.  Packed words and baked bits are compared bit for bit (the bake
+away from rays that graze a ball within 1e-4: the GPU forms each direction
+and the ray-ball distance in binary32, a few ulp of scene-sized values).
+Light lookups are compared to 1e-5 absolute, the forward's bound: each light
+sample is one forward lookup (binary32 weights within a few ulp of n) and the
+mean over samples does not add to that error.  As in the forward's tests the
+directions stay out of the neighbourhood of -N, where Eq. (1b) is singular
+and its binary32 evaluation ill-conditioned (1 + I_z cancels): surfaces face
+up within 45 degrees and lights shine from above, so that in texture space
+every direction has I_z >= -0.3.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from helpers import FWD_TOL, bucket_edge_mask, check_fwd, host
+from paper_2301_01719_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+BAKE_MARGIN = 1e-4
+
+
+@pytest.fixture(scope="module")
+def rt():
+    from paper_2301_01719_amd import radtex
+    return radtex
+
+
+def _rand_rot(g, N):
+    q, r = torch.linalg.qr(torch.randn((N, 3, 3), generator=g, dtype=torch.float64))
+    q = q * torch.sign(torch.diagonal(r, dim1=1, dim2=2))[:, None, :]
+    return q.transpose(1, 2).contiguous()
+
+
+def _frames_up(g, N, max_deg=45.0):
+    """Frames (rows T, B, N) whose normal lies within max_deg of +z, with a
+    random twist about it."""
+    zmin = math.cos(math.radians(max_deg))
+    z = torch.rand(N, generator=g, dtype=torch.float64) * (1 - zmin) + zmin
+    phi = torch.rand(N, generator=g, dtype=torch.float64) * 2 * math.pi
+    r = torch.sqrt(1 - z * z)
+    Nv = torch.stack([r * torch.cos(phi), r * torch.sin(phi), z], 1)
+    a = torch.randn((N, 3), generator=g, dtype=torch.float64)
+    T = a - (a * Nv).sum(1, keepdim=True) * Nv
+    T = T / torch.linalg.vector_norm(T, dim=1, keepdim=True)
+    B = torch.linalg.cross(Nv, T, dim=1)
+    return torch.stack([T, B, Nv], 1)
+
+
+def _frags(seed, N):
+    g = torch.Generator().manual_seed(seed)
+    uv = (torch.rand((N, 2), generator=g, dtype=torch.float64) * 5 - 2).to(torch.float32)
+    tbn = _frames_up(g, N).to(torch.float32)
+    pos = (torch.rand((N, 3), generator=g, dtype=torch.float64) * 4 - 2).to(torch.float32)
+    return uv.contiguous(), tbn.contiguous(), pos.contiguous()
+
+
+def _views(seed, tbn, zmin=-0.3):
+    """View vectors whose texture-space direction is uniform on the cap
+    z >= zmin, with lengths in [0.25, 2.25]."""
+    N = tbn.shape[0]
+    g = torch.Generator().manual_seed(seed)
+    z = torch.rand(N, generator=g, dtype=torch.float64) * (1 - zmin) + zmin
+    phi = torch.rand(N, generator=g, dtype=torch.float64) * 2 * math.pi
+    r = torch.sqrt(torch.clamp(1 - z * z, min=0))
+    vt = torch.stack([r * torch.cos(phi), r * torch.sin(phi), z], 1)
+    v = torch.einsum("nkm,nk->nm", tbn.to(torch.float64), vt)
+    v = v * (torch.rand((N, 1), generator=g, dtype=torch.float64) * 2 + 0.25)
+    return v.to(torch.float32).contiguous()
+
+
+def _bits_of(words, n):
+    """[buckets, n n] flags from uint32 words [buckets * ceil(n n/32)]."""
+    w = np.asarray(words).view(np.uint32).reshape(-1, (n * n + 31) // 32)
+    k = np.arange(n * n)
+    return (w[:, k // 32] >> (k % 32)) & 1
+
+
+# ---------------------------------------------------------------------------
+# the 1-bit packer
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("W,H,n", [(1, 1, 1), (3, 2, 3), (5, 3, 5), (7, 4, 7), (9, 5, 8),
+                                   (33, 17, 16), (3, 3, 24), (2, 5, 31), (4, 3, 32),
+                                   (129, 65, 16), (1, 1, 8)])
+def test_pack_bits_bit_exact(rt, W, H, n):
+    g = torch.Generator().manual_seed(W * 100 + n)
+    x = torch.rand((H, W, n, n), generator=g, dtype=torch.float64).mul(2).sub(0.5)
+    x = x.to(torch.float32)
+    flat = x.reshape(-1)
+    special = torch.tensor([0.5, float(np.nextafter(np.float32(0.5), np.float32(0))),
+                            float("nan"), float("inf"), -float("inf"), -0.0, 1.0, 0.0])
+    k = min(flat.numel(), special.numel())
+    flat[:k] = special[:k]
+    tex = rt.Texture(x.reshape(H, W, n, n, 1).to(DEV), W, H, n, 1)
+    words, scales = rt.quantize(tex, "bit1")
+    torch.cuda.synchronize()
+    assert scales is None and tuple(words.shape) == (H, W, rt.bit_words(n))
+    want = oracle.pack_bits(x.numpy(), n)
+    np.testing.assert_array_equal(host(words).view(np.uint32).reshape(-1), want)
+
+
+# ---------------------------------------------------------------------------
+# lookups of 1-bit textures
+# ---------------------------------------------------------------------------
+
+def _bit_texture(rt, W, H, n, seed, p=0.5):
+    """The same seeded flags packed by the GPU packer and by the oracle's
+    (each side packs its own; the words agree bit for bit)."""
+    g = torch.Generator().manual_seed(seed)
+    x = (torch.rand((H, W, n, n), generator=g) < p).to(torch.float32)
+    master = rt.Texture(x.reshape(H, W, n, n, 1).to(DEV), W, H, n, 1)
+    words, _ = rt.quantize(master, "bit1")
+    ow = oracle.pack_bits(x.numpy(), n)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(host(words).view(np.uint32).reshape(-1), ow)
+    return rt.Texture(words, W, H, n, 1, "bit1"), oracle.Tex(ow, W, H, n, 1, oracle.FMT_BIT1)
+
+
+@pytest.mark.parametrize("W,H,n,N", [(5, 3, 3, 257), (7, 2, 8, 1000), (4, 4, 16, 3000),
+                                     (3, 5, 31, 777), (2, 2, 32, 513), (1, 1, 1, 100)])
+@pytest.mark.parametrize("mode", ["nearest", "bilinear"])
+def test_view_lookup_of_a_bit_texture(rt, W, H, n, N, mode):
+    tex, otex = _bit_texture(rt, W, H, n, seed=W * 7 + n)
+    uv, tbn, _ = _frags(N + n, N)
+    view = _views(N, tbn)
+    out = rt.lookup_fwd(tex, uv.to(DEV), tbn.to(DEV), view.to(DEV), mode=mode)
+    torch.cuda.synchronize()
+    m = oracle.MODE_NEAREST if mode == "nearest" else oracle.MODE_BILINEAR
+    ref = oracle.lookup_fwd(otex, uv.numpy(), tbn.numpy(), view.numpy(), m)
+    keep = (bucket_edge_mask(uv.numpy(), tbn.numpy(), view.numpy(), W, H, n)
+            if mode == "nearest" else np.ones(N, bool))
+    check_fwd(host(out), ref, keep)
+    assert host(out).min() >= 0 and host(out).max() <= 1 + 1e-6
+
+
+# ---------------------------------------------------------------------------
+# the light lookup
+# ---------------------------------------------------------------------------
+
+def _light_vecs(kind, S, seed):
+    """Directional: directions within 45 degrees of +z, lengths in [0.1, 3.1].
+    Point: points over the fragments' box [-2, 2]^3, at x, y in [-2, 2] and
+    z in [6, 8] (so every direction toward them is within 55 degrees of +z)."""
+    g = torch.Generator().manual_seed(seed)
+    if kind == "directional":
+        zmin = math.cos(math.radians(45))
+        z = torch.rand(S, generator=g, dtype=torch.float64) * (1 - zmin) + zmin
+        phi = torch.rand(S, generator=g, dtype=torch.float64) * 2 * math.pi
+        r = torch.sqrt(1 - z * z)
+        v = torch.stack([r * torch.cos(phi), r * torch.sin(phi), z], 1)
+        v = v * (torch.rand((S, 1), generator=g, dtype=torch.float64) * 3 + 0.1)
+    else:
+        v = torch.rand((S, 3), generator=g, dtype=torch.float64)
+        v = v * torch.tensor([4.0, 4.0, 2.0], dtype=torch.float64) - torch.tensor(
+            [2.0, 2.0, -6.0], dtype=torch.float64)
+    return v.to(torch.float32)
+
+
+@pytest.mark.parametrize("kind", ["directional", "point"])
+@pytest.mark.parametrize("S", [1, 5, 64])
+@pytest.mark.parametrize("mode", ["nearest", "bilinear"])
+def test_light_lookup_of_a_bit_texture(rt, kind, S, mode):
+    W, H, n, N = 6, 5, 16, 2053
+    tex, otex = _bit_texture(rt, W, H, n, seed=S)
+    uv, tbn, pos = _frags(S * 3 + len(kind), N)
+    vec = _light_vecs(kind, S, seed=S + 1)
+    light = rt.make_light(vec.numpy(), kind)
+    out = rt.lookup_light(tex, uv.to(DEV), tbn.to(DEV), light,
+                          pos=pos.to(DEV) if kind == "point" else None, mode=mode)
+    torch.cuda.synchronize()
+    ref = oracle.lookup_light(otex, uv.numpy(), tbn.numpy(), vec.numpy(),
+                              oracle.LIGHT_POINT if kind == "point" else oracle.LIGHT_DIRECTIONAL,
+                              pos=pos.numpy(),
+                              mode=oracle.MODE_NEAREST if mode == "nearest" else oracle.MODE_BILINEAR)
+    keep = (bucket_edge_mask(uv.numpy(), tbn.numpy(), np.ones((N, 3), np.float32), W, H, n)
+            if mode == "nearest" else np.ones(N, bool))
+    err = check_fwd(host(out), ref, keep)
+    print(f"{kind} S={S} {mode}: max |err| {err:.3g}")
+
+
+@pytest.mark.parametrize("fmt,C", [("f32", 1), ("f32", 2), ("f32", 3), ("f32", 4), ("bf16", 4),
+                                   ("fp8", 4), ("fp8", 3), ("bf16", 1)])
+@pytest.mark.parametrize("kind", ["directional", "point"])
+def test_light_lookup_of_radiance_textures(rt, fmt, C, kind):
+    """Any storage format read with light directions (light-indexed radiance);
+    BF16/FP8 against the oracle on its own quantised texture, whose codes match
+    the GPU quantiser's bit for bit."""
+    W, H, n, N, S = 5, 4, 8, 1500, 7
+    g = torch.Generator().manual_seed(C * 10 + len(fmt))
+    x = torch.rand((H, W, n, n, C), generator=g)
+    master = rt.Texture(x.to(DEV), W, H, n, C)
+    if fmt == "f32":
+        tex, otex = master, oracle.Tex(x.numpy(), W, H, n, C)
+    else:
+        codes, scales = rt.quantize(master, fmt)
+        of = oracle.FMT_BF16 if fmt == "bf16" else oracle.FMT_FP8_E4M3
+        oc, osc = oracle.quantize(x.numpy(), W * H, n * n * C, of)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(host(codes).reshape(-1).view(oc.dtype), oc.reshape(-1))
+        tex = rt.Texture(codes, W, H, n, C, fmt, scales)
+        otex = oracle.Tex(oc, W, H, n, C, of, osc)
+    uv, tbn, pos = _frags(C + 100 * len(kind), N)
+    vec = _light_vecs(kind, S, seed=C)
+    light = rt.make_light(vec.numpy(), kind)
+    for mode, om in (("nearest", oracle.MODE_NEAREST), ("bilinear", oracle.MODE_BILINEAR)):
+        out = rt.lookup_light(tex, uv.to(DEV), tbn.to(DEV), light,
+                              pos=pos.to(DEV) if kind == "point" else None, mode=mode)
+        torch.cuda.synchronize()
+        ref = oracle.lookup_light(otex, uv.numpy(), tbn.numpy(), vec.numpy(),
+                                  oracle.LIGHT_POINT if kind == "point" else oracle.LIGHT_DIRECTIONAL,
+                                  pos=pos.numpy(), mode=om)
+        keep = (bucket_edge_mask(uv.numpy(), tbn.numpy(), np.ones((N, 3), np.float32), W, H, n)
+                if mode == "nearest" else np.ones(N, bool))
+        check_fwd(host(out), ref, keep)
+
+
+def test_one_light_sample_is_the_view_lookup_on_gpu(rt):
+    # a directional light of one sample reads exactly what rt_lookup_fwd reads
+    # with that vector as every fragment's view (same kernels' arithmetic)
+    W, H, n, N = 4, 4, 16, 4096
+    tex, _ = _bit_texture(rt, W, H, n, seed=3)
+    uv, tbn, _ = _frags(5, N)
+    L = torch.tensor([[0.2, -0.4, 0.8]])
+    for mode in ("nearest", "bilinear"):
+        a = rt.lookup_light(tex, uv.to(DEV), tbn.to(DEV), rt.make_light(L.numpy()), mode=mode)
+        b = rt.lookup_fwd(tex, uv.to(DEV), tbn.to(DEV), L.expand(N, 3).contiguous().to(DEV),
+                          mode=mode)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(host(a), host(b))
+
+
+def test_light_lookup_empty_and_tiled(rt):
+    tex, otex = _bit_texture(rt, 3, 3, 8, seed=1)
+    light = rt.make_light(wl.sun_light(16).numpy())
+    z2 = torch.empty((0, 2), device=DEV)
+    out = rt.lookup_light(tex, z2, torch.empty((0, 3, 3), device=DEV), light)
+    torch.cuda.synchronize()
+    assert out.shape == (0, 1)
+    # the tiling hint changes the visiting order only
+    gb = wl.plane_gbuffer(2, 37, 11, seed=4, device=DEV)
+    flat = rt.lookup_light(tex, gb.uv, gb.tbn, light)
+    tiled = rt.lookup_light(tex, gb.uv, gb.tbn, light, image=gb.image)
+    lamp = rt.make_light(wl.lamp_light(9).numpy(), "point")
+    pf = rt.lookup_light(tex, gb.uv, gb.tbn, lamp, pos=gb.pos, mode="bilinear")
+    pt = rt.lookup_light(tex, gb.uv, gb.tbn, lamp, pos=gb.pos, mode="bilinear", image=gb.image)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(host(flat), host(tiled))
+    np.testing.assert_array_equal(host(pf), host(pt))
+    ref = oracle.lookup_light(otex, host(gb.uv), host(gb.tbn), wl.lamp_light(9).numpy(),
+                              oracle.LIGHT_POINT, pos=host(gb.pos), mode=oracle.MODE_BILINEAR)
+    check_fwd(host(pt), ref)
+
+
+# ---------------------------------------------------------------------------
+# the shadow bake
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("W,H,n,K,with_frames", [(5, 3, 8, 3, False), (7, 2, 5, 16, True),
+                                                 (3, 4, 1, 1, True), (2, 2, 32, 0, False),
+                                                 (33, 17, 16, 8, True), (1, 1, 31, 5, True),
+                                                 (9, 9, 12, 64, False)])
+def test_shadow_bake_vs_oracle(rt, W, H, n, K, with_frames):
+    g = torch.Generator().manual_seed(W * 31 + n)
+    origins = (torch.rand((H, W, 3), generator=g) * 4 - 2).contiguous()
+    balls = torch.cat([torch.rand((K, 3), generator=g) * 6 - 3,
+                       torch.rand((K, 1), generator=g) * 0.8 + 0.2], 1)
+    frames = (_rand_rot(g, W * H).reshape(H, W, 3, 3).to(torch.float32)
+              if with_frames else None)
+    words = rt.bake_shadow(W, H, n, origins.to(DEV), balls.numpy(),
+                           frames=None if frames is None else frames.to(DEV))
+    torch.cuda.synchronize()
+    ow, margin = oracle.bake_shadow(W, H, n, origins.numpy(), balls.numpy(),
+                                    frames=None if frames is None else frames.numpy())
+    gw = host(words).view(np.uint32).reshape(-1)
+    gb, ob = _bits_of(gw, n), _bits_of(ow, n)
+    keep = margin.reshape(W * H, n * n) > BAKE_MARGIN
+    assert keep.mean() > 0.95
+    np.testing.assert_array_equal(gb[keep], ob[keep])
+    if (n * n) % 32:  # padding bits past n n are clear
+        assert np.all(gw.reshape(W * H, -1)[:, -1] >> ((n * n) % 32) == 0)
+    if K == 0:
+        assert np.all(gb == 1)
+
+
+def _exact_visibility(P, sun, balls):
+    """Per fragment the fraction of the sun's directions whose ray from P
+    escapes every ball (the cone each ball subtends at P)."""
+    P = P.astype(np.float64)
+    vis = np.ones((P.shape[0], sun.shape[0]), bool)
+    for c in balls.astype(np.float64):
+        e = c[None, :3] - P                                   # [N, 3]
+        l = np.linalg.norm(e, axis=1)
+        cosang = (e @ sun.T) / l[:, None]                     # [N, S]
+        half = np.arcsin(np.clip(c[3] / l, -1, 1))
+        hit = cosang >= np.cos(half)[:, None]
+        vis &= ~hit
+    return vis.mean(axis=1)
+
+
+def test_baked_shadow_converges_to_the_exact_penumbra(rt):
+    """A W x W shadow texture of n x n samples baked over the plane tile and
+    read with a 64-sample sun disc of 4 degrees at fragments spread over the
+    tile: the mean error against the exact area visibility falls as the
+    matrix and the angular resolution grow together."""
+    balls = wl.shadow_balls(12, seed=21)
+    sun = wl.sun_light(64, elevation_deg=50.0, azimuth_deg=20.0, radius_deg=4.0)
+    rng = np.random.default_rng(22)
+    N = 20000
+    P = np.zeros((N, 3), np.float32)
+    P[:, :2] = rng.uniform(0.05, 7.95, (N, 2))
+    exact = _exact_visibility(P, sun.numpy().astype(np.float64), balls.numpy())
+    uv = torch.from_numpy(P[:, :2] / wl.PLANE_EXTENT).to(DEV)
+    tbn = torch.eye(3).expand(N, 3, 3).contiguous().to(DEV)
+    light = rt.make_light(sun.numpy())
+    errs = []
+    for W, n in ((64, 8), (128, 16), (256, 32)):
+        words = rt.bake_shadow(W, W, n, wl.bucket_origins(W, W).to(DEV), balls.numpy())
+        tex = rt.Texture(words, W, W, n, 1, "bit1")
+        out = rt.lookup_light(tex, uv, tbn, light, mode="bilinear")
+        torch.cuda.synchronize()
+        errs.append(np.abs(host(out)[:, 0] - exact).mean())
+    print("mean |error| by resolution:", errs)
+    assert 0.05 < exact.mean() < 0.95
+    for a, b in zip(errs, errs[1:]):
+        assert b < 0.7 * a, errs
+
+
+def test_full_size_light_lookup_sampled(rt):
+    """The single-view workload's geometry: a 1024 x 1024 matrix of 16 x 16
+    one-bit buckets (32 MiB, packed by the GPU packer from seeded values and
+    checked against the oracle's packing) read by 1920 x 1080 fragments with
+    a 64-sample sun and a 16-sample lamp, in one launch each; checked on a
+    sample of fragments."""
+    w = wl.WORKLOADS["c2"]
+    W, H, n = w.W, w.H, 16
+    gb = w.make_gbuffer(DEV)
+    N = gb.count
+    x = wl.uniform(7, wl.S_TEXTURE, torch.arange(W * H * n * n, device=DEV))
+    x = (x < 0.4).to(torch.float32).reshape(H, W, n, n, 1)
+    master = rt.Texture(x, W, H, n, 1)
+    words, _ = rt.quantize(master, "bit1")
+    tex = rt.Texture(words, W, H, n, 1, "bit1")
+    sun = wl.sun_light(64)
+    lamp = wl.lamp_light(16)
+    o_sun = rt.lookup_light(tex, gb.uv, gb.tbn, rt.make_light(sun.numpy()), image=gb.image)
+    o_lamp = rt.lookup_light(tex, gb.uv, gb.tbn, rt.make_light(lamp.numpy(), "point"),
+                             pos=gb.pos, mode="bilinear", image=gb.image)
+    torch.cuda.synchronize()
+    ow = oracle.pack_bits(host(x), n)
+    np.testing.assert_array_equal(host(words).view(np.uint32).reshape(-1), ow)
+    otex = oracle.Tex(ow, W, H, n, 1, oracle.FMT_BIT1)
+    sel = np.unique(np.concatenate([np.linspace(0, N - 1, 3000).astype(np.int64),
+                                    np.arange(N - 64, N)]))
+    uv, tbn, pos = host(gb.uv)[sel], host(gb.tbn)[sel], host(gb.pos)[sel]
+    ref = oracle.lookup_light(otex, uv, tbn, sun.numpy())
+    keep = bucket_edge_mask(uv, tbn, np.ones((len(sel), 3), np.float32), W, H, n)
+    check_fwd(host(o_sun)[sel], ref, keep)
+    ref = oracle.lookup_light(otex, uv, tbn, lamp.numpy(), oracle.LIGHT_POINT, pos=pos,
+                              mode=oracle.MODE_BILINEAR)
+    check_fwd(host(o_lamp)[sel], ref)
