@@ -46,6 +46,12 @@ HBM_PEAK_GBS = 8000.0
 KERNEL_SOURCES = ["rt_device.hpp", "rt_lookup.hip", "rt_quantize.hip", "rt_backward.hip",
                   "rt_bake.hip", "rt_mip.hip"]
 
+# the shadow measurement (Sec. 5, Shadowing): balls over the plane tile, a sun
+# disc and a spherical lamp
+SHADOW_BALLS = 16
+SHADOW_CASES = (("sun", 1, "nearest"), ("sun", 16, "nearest"), ("sun", 64, "nearest"),
+                ("lamp", 16, "bilinear"))
+
 
 def source_hash() -> str:
     h = hashlib.sha256()
@@ -84,6 +90,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-bake", action="store_true", help="skip the bake measurement")
     ap.add_argument("--no-mip", action="store_true", help="skip the mip-chain measurement")
+    ap.add_argument("--no-shadow", action="store_true", help="skip the shadow measurement")
     ap.add_argument("--graph", action="store_true",
                     help="time replays of the step captured in a HIP graph (same kernels, no "
                          "host launch gaps; measured equal to eager launches on this workload)")
@@ -95,7 +102,108 @@ def parse():
     ap.add_argument("--profile-mip", type=int, default=0,
                     help="with --profile-steps: also build the mip chain and run the "
                          "level-of-detail lookup this many times")
+    ap.add_argument("--profile-shadow", type=int, default=0,
+                    help="with --profile-steps: also run the shadow bake, the 1-bit packer "
+                         "and the light lookups this many times")
     return ap.parse_args()
+
+
+def run_shadow(rt, w, gb, reps, timed):
+    """Shadowing on the workload's matrix and G-buffer: the bake of a 1-bit
+    shadow texture from SHADOW_BALLS balls, the 1-bit packer on a one-channel
+    FP32 matrix, and the light lookups of SHADOW_CASES.  With timed=False the
+    kernels only run (for a profiler) and nothing is returned."""
+    import numpy as np
+    import torch
+    from paper_2301_01719_amd import workloads as wl
+    dev = gb.uv.device
+    W, H, n = w.W, w.H, w.n
+    N = gb.count
+    nb = W * H
+    wpb = rt.bit_words(n)
+    balls = wl.shadow_balls(SHADOW_BALLS, seed=w.seed).numpy()
+    origins = wl.bucket_origins(W, H, device=dev)
+    words = torch.empty((H, W, wpb), dtype=torch.int32, device=dev)
+    flags = (wl.uniform(w.seed, wl.S_TEXTURE, torch.arange(nb * n * n, device=dev)) < 0.5)
+    x1 = flags.to(torch.float32).reshape(H, W, n, n, 1)
+    del flags
+    src = rt.Texture(x1, W, H, n, 1)
+    packed = torch.empty_like(words)
+
+    def light_of(kind, S):
+        vec = (wl.sun_light(S) if kind == "sun" else wl.lamp_light(S)).numpy()
+        return rt.make_light(vec, "directional" if kind == "sun" else "point")
+
+    out = torch.empty((N, 1), dtype=torch.float32, device=dev)
+
+    def everything():
+        rt.bake_shadow(W, H, n, origins, balls, out=words)
+        rt._check(rt.LIB.rt_quantize(src.handle, rt.RT_FMT_BIT1, rt._ptr(packed), None,
+                                     rt._stream(dev)))
+    stex = rt.Texture(words, W, H, n, 1, "bit1")
+    if not timed:
+        for _ in range(reps):
+            everything()
+            for kind, S, mode in SHADOW_CASES:
+                rt.lookup_light(stex, gb.uv, gb.tbn, light_of(kind, S),
+                                pos=gb.pos if kind == "lamp" else None, mode=mode, out=out,
+                                image=gb.image)
+        torch.cuda.synchronize()
+        return None
+    for _ in range(2):
+        everything()
+    torch.cuda.synchronize()
+    rt.profile_reset()
+    rt.profile_enable(True)
+    for _ in range(reps):
+        everything()
+    torch.cuda.synchronize()
+    rt.profile_enable(False)
+    prof = rt.profile_read()
+    bake_ms = prof["k_bake_shadow"][1] / prof["k_bake_shadow"][0]
+    pack_ms = prof["k_pack_bits"][1] / prof["k_pack_bits"][0]
+    pack_bytes = nb * n * n * 4 + nb * wpb * 4
+    lit = float((torch.bitwise_and(
+        words.reshape(-1, 1) >> torch.arange(32, device=dev, dtype=torch.int32)[None], 1)
+        .sum()) / (nb * n * n))
+    cases = {}
+    for kind, S, mode in SHADOW_CASES:
+        L = light_of(kind, S)
+        pos = gb.pos if kind == "lamp" else None
+        for _ in range(3):
+            rt.lookup_light(stex, gb.uv, gb.tbn, L, pos=pos, mode=mode, out=out, image=gb.image)
+        torch.cuda.synchronize()
+        ms = []
+        for _ in range(20):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            rt.lookup_light(stex, gb.uv, gb.tbn, L, pos=pos, mode=mode, out=out, image=gb.image)
+            b.record()
+            b.synchronize()
+            ms.append(a.elapsed_time(b))
+        q = [round(float(v), 5) for v in np.percentile(np.array(ms), [10, 50, 90])]
+        gbytes = N * (8 + 36 + 4 + (12 if pos is not None else 0))  # uv, frame, (pos), out
+        cases[f"{kind}{S}_{mode}"] = {
+            "light": kind, "samples": S, "mode": mode, "ms_p10_p50_p90": q,
+            "fragments_per_s": round(N / (q[1] * 1e-3), 1),
+            "fragment_samples_per_s": round(N * S / (q[1] * 1e-3), 1),
+            "gbuffer_GBps": round(gbytes / (q[1] * 1e-3) / 1e9, 1),
+            "gbuffer_hbm_frac": round(gbytes / (q[1] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "mean_visibility": round(float(out.mean()), 4)}
+    del x1, src, packed
+    return {"texture": f"{W}x{H} buckets of {n}x{n} bits ({nb * wpb * 4} bytes)",
+            "bake_ms": round(bake_ms, 5), "bake_balls": SHADOW_BALLS,
+            "bake_ray_ball_tests_per_s": round(nb * n * n * SHADOW_BALLS / (bake_ms * 1e-3), 1),
+            "bake_lit_fraction": round(lit, 4),
+            "pack_ms": round(pack_ms, 5), "pack_alg_bytes": pack_bytes,
+            "pack_GBps": round(pack_bytes / (pack_ms * 1e-3) / 1e9, 1),
+            "pack_hbm_frac": round(pack_bytes / (pack_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "light_lookups": cases,
+            "note": "1-bit shadow texture baked from balls over the plane tile, read by the "
+                    "G-buffer with a sun disc (directional samples, nearest bucket) and a "
+                    "spherical lamp (point samples from each fragment's position, "
+                    "bilinear-bucket); G-buffer bytes per fragment: uv 8, frame 36, "
+                    "position 12 (lamp), out 4"}
 
 
 def calibrate_copy():
@@ -176,6 +284,9 @@ def main():
                 for l in range(1, len(chain)):
                     rt.build_mip(chain[l - 1], out=chain[l].data)
                 rt.lookup_fwd_lod(chain, gb.uv, gb.tbn, gb.view, gb.duv, out=out, image=gb.image)
+            del chain
+        if args.profile_shadow and gb.pos is not None:
+            run_shadow(rt, w, gb, args.profile_shadow, timed=False)
         torch.cuda.synchronize()
         print(json.dumps({"profile_steps": args.profile_steps, "workload": w.name}), flush=True)
         return
@@ -394,6 +505,11 @@ def main():
                        "derivatives from the G-buffer (central differences)"}
         del chain, o
 
+    # ---- shadowing: 1-bit bake, packer and light lookups ----------------------
+    shadow = None
+    if not args.no_shadow and gb.pos is not None:
+        shadow = run_shadow(rt, w, gb, 5, timed=True)
+
     # ---- the FP64 oracle on a bounded sample (CPU baseline and error) -------
     cpu = None
     errors = None
@@ -460,6 +576,7 @@ def main():
         "formats": formats,
         "bake": bake,
         "mip": mip,
+        "shadow": shadow,
         "errors": errors,
         "unique_texels_touched": uniq_texels,
         "source_hash": source_hash(),

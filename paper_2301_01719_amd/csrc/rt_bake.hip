@@ -132,20 +132,29 @@ __global__ __launch_bounds__(256) void k_bake_env(int64_t nbuckets, int n,
 }
 
 // Shadow bake: one wavefront per bucket at a time, one lane per sample.  The
-// incidence directions of the n x n samples and the balls sit in LDS; each
-// lane turns its direction into the scene frame (M^T I, normalised), tests
-// the balls, and a wave ballot packs 64 samples into two words.  Samples
-// past n n give 0, which clears the padding bits of the last word.
-//
-// Ray o + t d (t > 0, |d| = 1) against ball (c, r): with e = c - o, the ray
-// meets the ball iff |e| <= r (o inside) or t* = d . e > 0 and the distance
-// |e - t* d| of the line from c is at most r.
+// incidence directions of the n x n samples sit in LDS.  Per bucket, lane q
+// first forms ball q's offset from the bucket's origin o, e = c - o (into the
+// wave's LDS slots), and whether o lies inside it (then every sample of the
+// bucket is shaded).  Each lane then turns its direction into the scene
+// frame (d = M^T I, normalised) and tests every ball: the ray o + t d
+// (t > 0) meets ball (c, r) iff t* = d . e > 0 and |e - t* d| <= r.  The
+// distance is formed from the vector e - t* d rather than as |e|^2 - t*^2,
+// which cancels when the ray points at the centre.  A wave ballot packs 64
+// samples into two words; samples past n n give 0, which clears the padding
+// bits of the last word.
+__device__ __forceinline__ void wave_sync_lds() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 __global__ __launch_bounds__(256) void k_bake_shadow(int64_t nbuckets, int n,
                                                      const float* __restrict__ origins,
                                                      const float* __restrict__ frames,
                                                      Occluders occ, uint32_t* __restrict__ words) {
     __shared__ float It[3 * 32 * 32];
     __shared__ float4 ball[MAX_OCCLUDERS];
+    __shared__ float4 rel[4][MAX_OCCLUDERS];  // per wave: (e, r^2) of each ball
     const int nn = n * n;
     if (threadIdx.x < occ.count)
         ball[threadIdx.x] = make_float4(occ.ball[threadIdx.x][0], occ.ball[threadIdx.x][1],
@@ -160,10 +169,12 @@ __global__ __launch_bounds__(256) void k_bake_shadow(int64_t nbuckets, int n,
     }
     __syncthreads();
     const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    const int nballs = occ.count;
     const int wpb = bit_words(n);
     const int chunks = (nn + 63) >> 6;
     const int64_t waves = (int64_t)gridDim.x * 4;
-    const int64_t first = (int64_t)xcd_block_id(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
+    const int64_t first = (int64_t)xcd_block_id(blockIdx.x, gridDim.x) * 4 + wv;
     for (int64_t b = first; b < nbuckets; b += waves) {
         float M[9] = {1.f, 0.f, 0.f, 0.f, 1.f, 0.f, 0.f, 0.f, 1.f};
         if (frames) {
@@ -171,10 +182,20 @@ __global__ __launch_bounds__(256) void k_bake_shadow(int64_t nbuckets, int n,
             for (int k = 0; k < 9; k++) M[k] = frames[b * 9 + k];
         }
         const float ox = origins[b * 3 + 0], oy = origins[b * 3 + 1], oz = origins[b * 3 + 2];
+        bool inside = false;
+        if (lane < nballs) {
+            const float4 bl = ball[lane];
+            const float ex = bl.x - ox, ey = bl.y - oy, ez = bl.z - oz;
+            const float r2 = bl.w * bl.w;
+            rel[wv][lane] = make_float4(ex, ey, ez, r2);
+            inside = ex * ex + ey * ey + ez * ez <= r2;
+        }
+        const bool blocked = __ballot(inside) != 0;
+        wave_sync_lds();
         for (int c = 0; c < chunks; c++) {
             const int k = c * 64 + lane;
             bool lit = false;
-            if (k < nn) {
+            if (k < nn && !blocked) {
                 const float i0 = It[3 * k + 0], i1 = It[3 * k + 1], i2 = It[3 * k + 2];
                 float dx = M[0] * i0 + M[3] * i1 + M[6] * i2;
                 float dy = M[1] * i0 + M[4] * i1 + M[7] * i2;
@@ -184,14 +205,11 @@ __global__ __launch_bounds__(256) void k_bake_shadow(int64_t nbuckets, int n,
                 dy *= inv;
                 dz *= inv;
                 bool hit = false;
-                for (int q = 0; q < occ.count; q++) {
-                    const float4 bl = ball[q];
-                    const float ex = bl.x - ox, ey = bl.y - oy, ez = bl.z - oz;
-                    const float r2 = bl.w * bl.w;
-                    const float ts = dx * ex + dy * ey + dz * ez;
-                    const float hx = ex - ts * dx, hy = ey - ts * dy, hz = ez - ts * dz;
-                    const bool inside = ex * ex + ey * ey + ez * ez <= r2;
-                    hit |= inside || (ts > 0.f && hx * hx + hy * hy + hz * hz <= r2);
+                for (int q = 0; q < nballs; q++) {
+                    const float4 e = rel[wv][q];
+                    const float ts = dx * e.x + dy * e.y + dz * e.z;
+                    const float hx = e.x - ts * dx, hy = e.y - ts * dy, hz = e.z - ts * dz;
+                    hit |= ts > 0.f && hx * hx + hy * hy + hz * hz <= e.w;
                 }
                 lit = !hit;
             }
@@ -200,6 +218,7 @@ __global__ __launch_bounds__(256) void k_bake_shadow(int64_t nbuckets, int n,
             if (lane < 2 && w < wpb)
                 words[b * wpb + w] = lane == 0 ? (uint32_t)bits : (uint32_t)(bits >> 32);
         }
+        wave_sync_lds();  // the next bucket rewrites this wave's ball terms
     }
 }
 

@@ -258,19 +258,52 @@ hipError_t launch_debug_indices(const TexView& t, const float* uv, const float* 
     return hipGetLastError();
 }
 
+// In-bucket sample coordinate of a light direction for the light lookup:
+// the steps of map_direction (u = M L, Eq. 1b in the k = 1/sqrt(|u| (|u| +
+// u_z)) form, Eq. 3, the clamp) with the hardware square root, reciprocal
+// square root and reciprocal (about 1 ulp each) in place of the correctly
+// rounded ones.  Eq. 3's factor |A|_2 / |A|_inf is taken from u directly (k
+// cancels).  The coordinate moves by a few ulp of n, far below the bilinear
+// weights' tolerance, and an area light evaluates this once per sample, so
+// the light lookup is bound by this arithmetic rather than by memory.
+__device__ __forceinline__ void light_coord(const float M[9], const float L[3], int n, float& sx,
+                                            float& sy) {
+    const float ux = M[0] * L[0] + M[1] * L[1] + M[2] * L[2];
+    const float uy = M[3] * L[0] + M[4] * L[1] + M[5] * L[2];
+    const float uz = M[6] * L[0] + M[7] * L[1] + M[8] * L[2];
+    const float rho2 = ux * ux + uy * uy;
+    const float len = __builtin_amdgcn_sqrtf(rho2 + uz * uz);
+    const float q = len * (len + uz);
+    const float k = q > 0.f ? __builtin_amdgcn_rsqf(q) : 0.f;  // q = 0: u = -|u| N or 0
+    const float mx = fmaxf(fabsf(ux), fabsf(uy));
+    const float r = mx > 0.f ? __builtin_amdgcn_sqrtf(rho2) * __builtin_amdgcn_rcpf(mx) : 0.f;
+    const float kr = k * r;
+    const float half_n = 0.5f * (float)n;
+    const float top = (float)(n - 1);
+    sx = fminf(fmaxf((ux * kr + 1.0f) * half_n - 0.5f, 0.f), top);  // NaN -> 0
+    sy = fminf(fmaxf((uy * kr + 1.0f) * half_n - 0.5f, 0.f), top);
+}
+
 // Light lookup: the bucket footprint depends on (u, v) only, so it is formed
-// once per fragment; each light sample then maps its own direction (Eq. 1b,
-// Eq. 3, the clamp) and adds its bilinear taps.  The direction toward the
-// light is the sample's vector (directional light) or the sample point minus
-// the fragment's position (point light).  The samples live in the kernel's
-// argument block and are read with scalar loads (every lane of a wave reads
-// the same sample).
-template <int FMT, int C, int MODE>
+// once per fragment; each light sample then maps its own direction and adds
+// its bilinear taps.  The direction toward the light is the sample's vector
+// (directional light) or the sample point minus the fragment's position
+// (point light).  The samples live in the kernel's argument block and are
+// read with scalar loads (every lane of a wave reads the same sample).
+//
+// CACHE (1-bit textures of n <= 16, several samples): the words of the
+// fragment's buckets (at most 8 each) are copied once into LDS, word-major
+// ([word][lane], so that lanes reading different words still hit distinct
+// banks), and every tap of every sample is one LDS read instead of a global
+// gather.  Each lane reads only its own column: no barrier is needed.
+template <int FMT, int C, int MODE, bool CACHE>
 __global__ __launch_bounds__(256) void k_lookup_light(TexView t, const float* __restrict__ uv,
                                                       const float* __restrict__ tbn,
                                                       const float* __restrict__ pos,
                                                       LightParams lp, float* __restrict__ out,
                                                       FragMap m) {
+    constexpr int NB = MODE == MODE_NEAREST ? 1 : 4;
+    __shared__ uint32_t cache[CACHE ? 8 * NB : 1][256];
     const int64_t f = frag_of(m, blockIdx.x, gridDim.x, threadIdx.x);
     if (f < 0) return;
     const float2 q = ((const float2*)uv)[f];
@@ -282,7 +315,6 @@ __global__ __launch_bounds__(256) void k_lookup_light(TexView t, const float* __
 #pragma unroll
         for (int k = 0; k < 3; k++) P[k] = pos[f * 3 + k];
     }
-    constexpr int NB = MODE == MODE_NEAREST ? 1 : 4;
     int64_t bk[NB];
     float bw[NB];
     if constexpr (MODE == MODE_NEAREST) {
@@ -302,15 +334,42 @@ __global__ __launch_bounds__(256) void k_lookup_light(TexView t, const float* __
         bw[2] = (1.f - a) * bb;
         bw[3] = a * bb;
     }
+    const int n = t.n;
+    if constexpr (CACHE) {
+        const int wpb = bit_words(n);
+#pragma unroll
+        for (int r = 0; r < NB; r++) {
+            const uint32_t* src = (const uint32_t*)t.data + bk[r] * wpb;
+#pragma unroll
+            for (int w = 0; w < 8; w++) cache[r * 8 + w][threadIdx.x] = w < wpb ? src[w] : 0u;
+        }
+    }
     float acc[4] = {0.f, 0.f, 0.f, 0.f};
     for (int s = 0; s < lp.samples; s++) {
         float L[3];
 #pragma unroll
         for (int k = 0; k < 3; k++) L[k] = lp.vec[s][k] - P[k];
-        const Dir d = map_direction(M, L, t.n);
-        const Foot p = footprint(d.sx, d.sy, t.n);
+        float sx, sy;
+        light_coord(M, L, n, sx, sy);
+        const Foot p = footprint(sx, sy, n);
+        if constexpr (CACHE) {
+            const int k00 = p.y0 * n + p.x0, k01 = p.y0 * n + p.x1;
+            const int k10 = p.y1 * n + p.x0, k11 = p.y1 * n + p.x1;
+            const float w00 = (1.f - p.fx) * (1.f - p.fy), w01 = p.fx * (1.f - p.fy);
+            const float w10 = (1.f - p.fx) * p.fy, w11 = p.fx * p.fy;
 #pragma unroll
-        for (int r = 0; r < NB; r++) bucket_bilerp<FMT, C>(t, bk[r], p, bw[r], acc);
+            for (int r = 0; r < NB; r++) {
+                const uint32_t* col = &cache[r * 8][threadIdx.x];
+                const float t00 = (float)((col[(k00 >> 5) * 256] >> (k00 & 31)) & 1u);
+                const float t01 = (float)((col[(k01 >> 5) * 256] >> (k01 & 31)) & 1u);
+                const float t10 = (float)((col[(k10 >> 5) * 256] >> (k10 & 31)) & 1u);
+                const float t11 = (float)((col[(k11 >> 5) * 256] >> (k11 & 31)) & 1u);
+                acc[0] += bw[r] * (w00 * t00 + w01 * t01 + w10 * t10 + w11 * t11);
+            }
+        } else {
+#pragma unroll
+            for (int r = 0; r < NB; r++) bucket_bilerp<FMT, C>(t, bk[r], p, bw[r], acc);
+        }
     }
 #pragma unroll
     for (int c = 0; c < C; c++) acc[c] *= lp.inv_samples;
@@ -322,10 +381,10 @@ static void launch_light_c(const TexView& t, const float* uv, const float* tbn, 
                            const LightParams& lp, float* out, const FragMap& m, hipStream_t s) {
     const uint32_t blocks = fragmap_blocks(m);
     switch (t.C) {
-    case 1: hipLaunchKernelGGL((k_lookup_light<FMT, 1, MODE>), dim3(blocks), dim3(256), 0, s, t, uv, tbn, pos, lp, out, m); break;
-    case 2: hipLaunchKernelGGL((k_lookup_light<FMT, 2, MODE>), dim3(blocks), dim3(256), 0, s, t, uv, tbn, pos, lp, out, m); break;
-    case 3: hipLaunchKernelGGL((k_lookup_light<FMT, 3, MODE>), dim3(blocks), dim3(256), 0, s, t, uv, tbn, pos, lp, out, m); break;
-    default: hipLaunchKernelGGL((k_lookup_light<FMT, 4, MODE>), dim3(blocks), dim3(256), 0, s, t, uv, tbn, pos, lp, out, m); break;
+    case 1: hipLaunchKernelGGL((k_lookup_light<FMT, 1, MODE, false>), dim3(blocks), dim3(256), 0, s, t, uv, tbn, pos, lp, out, m); break;
+    case 2: hipLaunchKernelGGL((k_lookup_light<FMT, 2, MODE, false>), dim3(blocks), dim3(256), 0, s, t, uv, tbn, pos, lp, out, m); break;
+    case 3: hipLaunchKernelGGL((k_lookup_light<FMT, 3, MODE, false>), dim3(blocks), dim3(256), 0, s, t, uv, tbn, pos, lp, out, m); break;
+    default: hipLaunchKernelGGL((k_lookup_light<FMT, 4, MODE, false>), dim3(blocks), dim3(256), 0, s, t, uv, tbn, pos, lp, out, m); break;
     }
 }
 
@@ -336,10 +395,15 @@ hipError_t launch_lookup_light(const TexView& t, int fmt, int mode, const float*
     prof_begin(K_LOOKUP_LIGHT, s);
     const uint32_t blocks = fragmap_blocks(m);
     if (fmt == FMT_BIT1) {
-        if (mode == MODE_NEAREST)
-            hipLaunchKernelGGL((k_lookup_light<FMT_BIT1, 1, MODE_NEAREST>), dim3(blocks), dim3(256), 0, s, t, uv, tbn, pos, lp, out, m);
-        else
-            hipLaunchKernelGGL((k_lookup_light<FMT_BIT1, 1, MODE_BILINEAR>), dim3(blocks), dim3(256), 0, s, t, uv, tbn, pos, lp, out, m);
+        // the LDS copy of the buckets pays off once several samples read them
+        const bool cache = t.n <= 16 && lp.samples >= 4;
+        if (mode == MODE_NEAREST) {
+            if (cache) hipLaunchKernelGGL((k_lookup_light<FMT_BIT1, 1, MODE_NEAREST, true>), dim3(blocks), dim3(256), 0, s, t, uv, tbn, pos, lp, out, m);
+            else hipLaunchKernelGGL((k_lookup_light<FMT_BIT1, 1, MODE_NEAREST, false>), dim3(blocks), dim3(256), 0, s, t, uv, tbn, pos, lp, out, m);
+        } else {
+            if (cache) hipLaunchKernelGGL((k_lookup_light<FMT_BIT1, 1, MODE_BILINEAR, true>), dim3(blocks), dim3(256), 0, s, t, uv, tbn, pos, lp, out, m);
+            else hipLaunchKernelGGL((k_lookup_light<FMT_BIT1, 1, MODE_BILINEAR, false>), dim3(blocks), dim3(256), 0, s, t, uv, tbn, pos, lp, out, m);
+        }
     } else if (mode == MODE_NEAREST) {
         if (fmt == FMT_F32) launch_light_c<FMT_F32, MODE_NEAREST>(t, uv, tbn, pos, lp, out, m, s);
         else if (fmt == FMT_BF16) launch_light_c<FMT_BF16, MODE_NEAREST>(t, uv, tbn, pos, lp, out, m, s);

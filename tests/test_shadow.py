@@ -228,8 +228,9 @@ def test_light_lookup_of_radiance_textures(rt, fmt, C, kind):
 
 
 def test_one_light_sample_is_the_view_lookup_on_gpu(rt):
-    # a directional light of one sample reads exactly what rt_lookup_fwd reads
-    # with that vector as every fragment's view (same kernels' arithmetic)
+    # a directional light of one sample reads what rt_lookup_fwd reads with
+    # that vector as every fragment's view, up to the light path's hardware
+    # square roots and reciprocals (a few ulp of the sample coordinate)
     W, H, n, N = 4, 4, 16, 4096
     tex, _ = _bit_texture(rt, W, H, n, seed=3)
     uv, tbn, _ = _frags(5, N)
@@ -239,7 +240,7 @@ def test_one_light_sample_is_the_view_lookup_on_gpu(rt):
         b = rt.lookup_fwd(tex, uv.to(DEV), tbn.to(DEV), L.expand(N, 3).contiguous().to(DEV),
                           mode=mode)
         torch.cuda.synchronize()
-        np.testing.assert_array_equal(host(a), host(b))
+        assert np.max(np.abs(host(a) - host(b))) <= FWD_TOL
 
 
 def test_light_lookup_empty_and_tiled(rt):
