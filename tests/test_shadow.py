@@ -372,3 +372,28 @@ def test_full_size_light_lookup_sampled(rt):
     ref = oracle.lookup_light(otex, uv, tbn, lamp.numpy(), oracle.LIGHT_POINT, pos=pos,
                               mode=oracle.MODE_BILINEAR)
     check_fwd(host(o_lamp)[sel], ref)
+
+
+def test_subsurface_reading_light_relative_to_the_eye(rt):
+    """Sec. 5 (Subsurface scattering): the texture is sampled with the light's
+    direction relative to the view position.  With the eye position passed as
+    every fragment's `pos`, a point light's samples give L = Q - E, so the
+    light lookup of an RGB radiance texture equals the view lookup with
+    view = Q - E (to the light path's few ulp)."""
+    W, H, n, C, N = 6, 4, 16, 3, 3000
+    g = torch.Generator().manual_seed(41)
+    x = torch.rand((H, W, n, n, C), generator=g)
+    tex = rt.Texture(x.to(DEV), W, H, n, C)
+    uv, tbn, _ = _frags(42, N)
+    eye = torch.tensor([[0.3, -0.2, 0.5]]).expand(N, 3).contiguous()
+    Q = torch.tensor([[1.0, 2.0, 7.0]])
+    a = rt.lookup_light(tex, uv.to(DEV), tbn.to(DEV), rt.make_light(Q.numpy(), "point"),
+                        pos=eye.to(DEV), mode="bilinear")
+    b = rt.lookup_fwd(tex, uv.to(DEV), tbn.to(DEV), (Q - eye).contiguous().to(DEV),
+                      mode="bilinear")
+    torch.cuda.synchronize()
+    assert np.max(np.abs(host(a) - host(b))) <= FWD_TOL
+    ref = oracle.lookup_light(oracle.Tex(x.numpy(), W, H, n, C), uv.numpy(), tbn.numpy(),
+                              Q.numpy(), oracle.LIGHT_POINT, pos=eye.numpy(),
+                              mode=oracle.MODE_BILINEAR)
+    check_fwd(host(a), ref)
