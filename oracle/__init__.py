@@ -63,6 +63,10 @@ def _load():
     lib.orc_lookup_light.argtypes = [i64, P, P, P, i32, i32, P, i32, i32, i32, i32, i32, P, P,
                                      i32, P]
     lib.orc_bake_shadow.argtypes = [i32, i32, i32, P, P, P, i32, P, P]
+    lib.orc_lookup_fwd_dict.argtypes = [i64, P, P, P, i32, i32, i32, i32, i32, P, i32, P, P, i32,
+                                        P]
+    lib.orc_vq_assign.argtypes = [i64, i32, P, i32, P, P, P]
+    lib.orc_vq_update.argtypes = [i64, i32, P, P, i32, P, P, P]
     _lib = lib
     return lib
 
@@ -413,3 +417,53 @@ def bake_shadow(W, H, n, origins, spheres, frames=None):
     _load().orc_bake_shadow(int(W), int(H), int(n), _p(origins), _p(frames), _p(spheres),
                             spheres.shape[0], _p(words), _p(margin))
     return words, margin
+
+
+# --- bucket dictionary: codebook + index map (+ gains), and Lloyd's steps ---------
+
+def lookup_fwd_dict(codebook, K, index, gains, W, H, n, C, uv, tbn, view, fmt=FMT_F32,
+                    mode=MODE_NEAREST):
+    """Lookup on a dictionary texture: bucket b decodes to gains[b] (1 if
+    gains is None) times codebook entry index[b]; codebook [K, n, n, C] in
+    FMT_F32 (float32) or FMT_BF16 (uint16 codes)."""
+    dt = {FMT_F32: np.float32, FMT_BF16: np.uint16}[fmt]
+    cb = _c(codebook, dt).reshape(-1)
+    assert cb.size == K * n * n * C
+    idx = _c(index, np.int32).reshape(-1)
+    assert idx.size == W * H and idx.min() >= 0 and idx.max() < K
+    g = None if gains is None else _c(gains, np.float32).reshape(-1)
+    uv, tbn, view = _frags(uv, tbn, view)
+    N = uv.shape[0]
+    out = np.empty((N, C), np.float64)
+    _load().orc_lookup_fwd_dict(N, _p(uv), _p(tbn), _p(view), int(W), int(H), int(n), int(C),
+                                int(fmt), _p(cb), int(K), _p(idx), _p(g), int(mode), _p(out))
+    return out
+
+
+def vq_assign(X, codebook):
+    """Nearest entry of every row of X [M, D] float32 among codebook [K, D]
+    float32 (squared distance in binary64, ties to the smallest index):
+    (assign [M] int32, dist [M] float64)."""
+    X = _c(X, np.float32)
+    cb = _c(codebook, np.float32)
+    M, D = X.shape
+    K = cb.shape[0]
+    assert cb.shape[1] == D
+    a = np.empty(M, np.int32)
+    d = np.empty(M, np.float64)
+    _load().orc_vq_assign(M, D, _p(X), K, _p(cb), _p(a), _p(d))
+    return a, d
+
+
+def vq_update(X, assign, codebook):
+    """Lloyd update: (entries [K, D] float64 = mean of the assigned rows, or
+    the previous entry when none is assigned; counts [K] int64)."""
+    X = _c(X, np.float32)
+    cb = _c(codebook, np.float32)
+    a = _c(assign, np.int32)
+    M, D = X.shape
+    K = cb.shape[0]
+    out = np.empty((K, D), np.float64)
+    cnt = np.empty(K, np.int64)
+    _load().orc_vq_update(M, D, _p(X), _p(a), K, _p(cb), _p(out), _p(cnt))
+    return out, cnt

@@ -35,6 +35,9 @@
  *                             incidence, averaged over an area light's
  *                             samples; analytic occluders stand in for the
  *                             ray-traced visibility of the bake
+ *   bucket dictionary         the compression of repetitive buckets (Sec. 1,
+ *                             Sec. 2) as a codebook, an index map and gains;
+ *                             Lloyd's assignment and update steps build it
  *
  * Readings of points the paper leaves open (texel-centre convention, UV wrap,
  * axis orientation, the A = 0 case of Eq. (3), the storage formats) are listed
@@ -413,6 +416,10 @@ typedef struct {
     int W, H, n, C, fmt;
     const void *data;
     const float *scales;
+    /* bucket dictionary (NULL: none): bucket b reads entry index[b] of data,
+     * times gains[b] (NULL: 1) */
+    const int32_t *index;
+    const float *gains;
 } tex_t;
 
 /* Texel (row y, column x, channel c) of bucket (column i, row j).  Storage is
@@ -420,6 +427,13 @@ typedef struct {
 static double texel(const tex_t *t, int i, int j, int y, int x, int c)
 {
     int64_t b = (int64_t)j * t->W + i;
+    if (t->index) {
+        /* the dictionary form: the decoded bucket is gain(b) times its entry */
+        double g = t->gains ? (double)t->gains[b] : 1.0;
+        tex_t plain = {t->W, t->H, t->n, t->C, t->fmt, t->data, t->scales, NULL, NULL};
+        int64_t k = t->index[b];
+        return g * texel(&plain, (int)(k % t->W), (int)(k / t->W), y, x, c);
+    }
     int64_t e = ((b * t->n + y) * t->n + x) * t->C + c;
     switch (t->fmt) {
     case ORC_FMT_F32:
@@ -1165,4 +1179,83 @@ void orc_bake_shadow(int W, int H, int n, const float *origins, const float *fra
         }
     }
     free(I);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Bucket dictionary (the "simple compression" of repetitive buckets, Sec. 1 */
+/* and Sec. 2): a codebook of K bucket entries, an index map giving each     */
+/* bucket its entry, and optionally a gain per bucket.  Decoded bucket b is  */
+/* gain(b) * entry(index(b)); the lookup is the lookup of the decoded matrix. */
+/* The codebook is built by Lloyd's k-means iteration on the buckets as      */
+/* vectors of D = n n C values.                                              */
+/* ------------------------------------------------------------------------- */
+
+/* Lookup of N fragments on a dictionary texture: the codebook (K entries of
+ * n n C values, format fmt: F32 or BF16 codes) seen as a K x 1 matrix of
+ * buckets, index [H W] int32 in [0, K), gains [H W] or NULL. */
+void orc_lookup_fwd_dict(int64_t N, const float *uv, const float *tbn, const float *view, int W,
+                         int H, int n, int C, int fmt, const void *codebook, int K,
+                         const int32_t *index, const float *gains, int mode, double *out)
+{
+    /* W_entries = K so that entry k is "bucket" (k, 0) of the codebook */
+    tex_t t = {W, H, n, C, fmt, codebook, NULL, index, gains};
+    (void)K;
+#pragma omp parallel for schedule(static)
+    for (int64_t f = 0; f < N; f++) {
+        double U[2], M[9], V[3];
+        widen_fragment(uv, tbn, view, f, U, M, V);
+        lookup_one(&t, U, M, V, mode, out + f * C);
+    }
+}
+
+/* Assignment step: e(b) = argmin_k |x_b - c_k|^2 over the K entries, the
+ * squared distance summed in binary64 from the binary32 values; ties go to
+ * the smallest k.  dist[b] receives the minimum. */
+void orc_vq_assign(int64_t M, int D, const float *X, int K, const float *Cb, int32_t *assign,
+                   double *dist)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t b = 0; b < M; b++) {
+        const float *x = X + b * D;
+        double best = INFINITY;
+        int bk = 0;
+        for (int k = 0; k < K; k++) {
+            const float *c = Cb + (int64_t)k * D;
+            double d = 0.0;
+            for (int i = 0; i < D; i++) {
+                double e = (double)x[i] - (double)c[i];
+                d += e * e;
+            }
+            if (d < best) {
+                best = d;
+                bk = k;
+            }
+        }
+        assign[b] = bk;
+        if (dist)
+            dist[b] = best;
+    }
+}
+
+/* Update step: each entry becomes the mean of the vectors assigned to it
+ * (summed in binary64 in increasing b); an entry with no vector keeps its
+ * previous value.  out [K][D] binary64, counts [K]. */
+void orc_vq_update(int64_t M, int D, const float *X, const int32_t *assign, int K,
+                   const float *Cb, double *out, int64_t *counts)
+{
+    for (int64_t q = 0; q < (int64_t)K * D; q++)
+        out[q] = 0.0;
+    for (int k = 0; k < K; k++)
+        counts[k] = 0;
+    for (int64_t b = 0; b < M; b++) {
+        int k = assign[b];
+        counts[k]++;
+        for (int i = 0; i < D; i++)
+            out[(int64_t)k * D + i] += (double)X[b * D + i];
+    }
+    for (int k = 0; k < K; k++)
+        for (int i = 0; i < D; i++) {
+            int64_t q = (int64_t)k * D + i;
+            out[q] = counts[k] ? out[q] / (double)counts[k] : (double)Cb[q];
+        }
 }

@@ -1144,3 +1144,116 @@ def test_area_shadow_converges_to_the_exact_penumbra():
     cap = ((math.cos(math.radians(30)) - math.cos(math.radians(40)))
            / (1 - math.cos(math.radians(40))))
     assert abs(got[0, 0] - cap) < 0.03, (got[0, 0], cap)
+
+
+# --------------------------------------------------------------------------
+# Bucket dictionary: "simple compression" of repetitive buckets (Sec. 1,
+# Sec. 2) as a codebook of bucket entries, an index map and per-bucket gains;
+# the codebook built by Lloyd's k-means steps
+# --------------------------------------------------------------------------
+
+def _dict_case(seed, W=5, H=4, n=6, C=3, K=7, N=500):
+    rng = np.random.default_rng(seed)
+    cb = rng.uniform(0, 1, (K, n, n, C)).astype(np.float32)
+    index = rng.integers(0, K, (H, W)).astype(np.int32)
+    gains = rng.uniform(0.5, 2.0, (H, W)).astype(np.float32)
+    uv = rng.uniform(-1, 2, (N, 2)).astype(np.float32)
+    tbn = np.stack([_rand_rot(rng) for _ in range(N)]).astype(np.float32)
+    view = rng.normal(size=(N, 3)).astype(np.float32)
+    return cb, index, gains, uv, tbn, view
+
+
+@pytest.mark.parametrize("mode", [oracle.MODE_NEAREST, oracle.MODE_BILINEAR])
+@pytest.mark.parametrize("with_gains", [False, True])
+def test_dictionary_lookup_is_the_lookup_of_the_decoded_matrix(mode, with_gains):
+    # decoded bucket b = gain(b) * codebook[index(b)], formed here by numpy's
+    # fancy indexing; the dictionary lookup reads exactly that matrix
+    W, H, n, C, K = 5, 4, 6, 3, 7
+    cb, index, gains, uv, tbn, view = _dict_case(31)
+    g = gains if with_gains else None
+    dec = cb.astype(np.float64)[index]
+    if with_gains:
+        dec = dec * gains.astype(np.float64)[:, :, None, None, None]
+    want = oracle.lookup_fwd(oracle.Tex(dec, W, H, n, C, oracle.FMT_F64), uv, tbn, view, mode)
+    got = oracle.lookup_fwd_dict(cb, K, index, g, W, H, n, C, uv, tbn, view, mode=mode)
+    np.testing.assert_allclose(got, want, rtol=0, atol=1e-14)
+
+
+def test_dictionary_with_bf16_entries_and_the_identity_map():
+    # an identity index map without gains is the plain texture; BF16 entries
+    # decode exactly (the bits of the upper half of a binary32)
+    W, H, n, C = 4, 3, 5, 2
+    rng = np.random.default_rng(32)
+    tex = rng.uniform(0, 1, (H, W, n, n, C)).astype(np.float32)
+    uv = rng.uniform(0, 1, (300, 2)).astype(np.float32)
+    tbn = np.stack([_rand_rot(rng) for _ in range(300)]).astype(np.float32)
+    view = rng.normal(size=(300, 3)).astype(np.float32)
+    ident = np.arange(W * H, dtype=np.int32).reshape(H, W)
+    for mode in (oracle.MODE_NEAREST, oracle.MODE_BILINEAR):
+        np.testing.assert_array_equal(
+            oracle.lookup_fwd_dict(tex.reshape(W * H, n, n, C), W * H, ident, None, W, H, n, C,
+                                   uv, tbn, view, mode=mode),
+            oracle.lookup_fwd(oracle.Tex(tex, W, H, n, C), uv, tbn, view, mode))
+    codes = (tex.view(np.uint32) >> 16).astype(np.uint16)
+    trunc = (codes.astype(np.uint32) << 16).view(np.float32)
+    np.testing.assert_array_equal(
+        oracle.lookup_fwd_dict(codes.reshape(W * H, n, n, C), W * H, ident, None, W, H, n, C, uv,
+                               tbn, view, fmt=oracle.FMT_BF16),
+        oracle.lookup_fwd(oracle.Tex(trunc, W, H, n, C), uv, tbn, view))
+
+
+def test_vq_assignment_is_scipys_nearest_neighbour():
+    from scipy.spatial.distance import cdist
+    rng = np.random.default_rng(33)
+    X = rng.normal(size=(400, 48)).astype(np.float32)
+    cb = rng.normal(size=(37, 48)).astype(np.float32)
+    cb[5] = cb[20]  # an exact duplicate entry: ties go to the smaller index
+    a, d = oracle.vq_assign(X, cb)
+    full = cdist(X.astype(np.float64), cb.astype(np.float64), "sqeuclidean")
+    np.testing.assert_array_equal(a, np.argmin(full, axis=1))
+    np.testing.assert_allclose(d, full.min(axis=1), rtol=1e-12)
+    assert not np.any(a == 20)
+    # a row equal to an entry is assigned to it at distance 0
+    a2, d2 = oracle.vq_assign(cb[[3, 9]], cb)
+    np.testing.assert_array_equal(a2, [3, 9])
+    assert np.all(d2 == 0)
+
+
+def test_vq_update_is_the_mean_of_each_cluster():
+    rng = np.random.default_rng(34)
+    X = rng.normal(size=(300, 20)).astype(np.float32)
+    K = 9
+    a = rng.integers(0, K - 2, 300).astype(np.int32)  # entries 7 and 8 stay empty
+    prev = rng.normal(size=(K, 20)).astype(np.float32)
+    out, cnt = oracle.vq_update(X, a, prev)
+    np.testing.assert_array_equal(cnt, np.bincount(a, minlength=K))
+    for k in range(K):
+        if cnt[k]:
+            np.testing.assert_allclose(out[k], X[a == k].astype(np.float64).mean(0), rtol=1e-13,
+                                       atol=1e-15)
+        else:
+            np.testing.assert_array_equal(out[k], prev[k].astype(np.float64))
+
+
+def test_lloyd_never_increases_the_distortion_and_recovers_separated_clusters():
+    # the k-means invariant: an assignment step then an update step cannot
+    # raise the sum of squared distances; on repetitive buckets (noisy copies
+    # of a few prototypes) one step from one member of each group finds them
+    rng = np.random.default_rng(35)
+    X = rng.normal(size=(600, 16)).astype(np.float32)
+    cb = X[rng.choice(600, 12, replace=False)].copy()
+    prev = np.inf
+    for _ in range(6):
+        a, d = oracle.vq_assign(X, cb)
+        assert d.sum() <= prev * (1 + 1e-12)
+        prev = d.sum()
+        cb = oracle.vq_update(X, a, cb)[0].astype(np.float32)
+    protos = rng.uniform(0, 1, (8, 32)).astype(np.float32)
+    labels = rng.integers(0, 8, 2000)
+    Y = (protos[labels] + rng.normal(0, 0.01, (2000, 32))).astype(np.float32)
+    init = np.stack([Y[np.nonzero(labels == k)[0][0]] for k in range(8)])
+    a, _ = oracle.vq_assign(Y, init)
+    np.testing.assert_array_equal(a, labels)
+    new, cnt = oracle.vq_update(Y, a, init)
+    np.testing.assert_array_equal(cnt, np.bincount(labels, minlength=8))
+    assert np.abs(new - protos).max() < 0.003
