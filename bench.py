@@ -44,7 +44,7 @@ BAKE_AMBIENT = (0.05, 0.05, 0.05, 0.0)
 METRIC = "lookups/s + % HBM peak, fwd & bwd; FP32 vs BF16/FP8 texture at stated error"
 HBM_PEAK_GBS = 8000.0
 KERNEL_SOURCES = ["rt_device.hpp", "rt_lookup.hip", "rt_quantize.hip", "rt_backward.hip",
-                  "rt_bake.hip", "rt_mip.hip"]
+                  "rt_bake.hip", "rt_mip.hip", "rt_dictionary.hip"]
 
 # the shadow measurement (Sec. 5, Shadowing): balls over the plane tile, a sun
 # disc and a spherical lamp

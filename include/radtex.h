@@ -140,6 +140,36 @@ typedef struct rt_texture rt_texture;   /* opaque handle (host metadata)        
  * RT_ERR_NO_DEVICE, RT_ERR_HIP. */
 rt_status rt_create_texture(const rt_texture_desc* desc, void* stream, rt_texture** out);
 
+/* A bucket dictionary: the compression of repetitive buckets ("highly
+ * repetitive ... simple compression", Sec. 1 and Sec. 2) as a codebook of K
+ * bucket entries, an index map naming each bucket's entry, and optionally a
+ * gain per bucket.  Decoded bucket b = gains[b] * codebook[index[b]]; every
+ * lookup reads that decoded matrix (a two-level gather). */
+typedef struct {
+    int32_t buckets_w;      /* W                                                  */
+    int32_t buckets_h;      /* H                                                  */
+    int32_t n;              /* angular resolution                                 */
+    int32_t channels;       /* C, 1..4                                            */
+    int32_t entries;        /* K >= 1 (<= 256 for 1-byte, <= 65536 for 2-byte   */
+                            /* entry numbers)                                     */
+    int32_t format;         /* codebook storage: RT_FMT_F32 or RT_FMT_BF16        */
+    int32_t index_bytes;    /* 1, 2 or 4: unsigned entry numbers                  */
+    int32_t reserved;       /* 0                                                  */
+    const void* codebook;   /* [K][n][n][C] in `format`, 16-byte aligned          */
+    const void* index;      /* [H][W] entry numbers; a number >= K reads entry    */
+                            /* K-1 (device data is not checked on the host)       */
+    const float* gains;     /* [H][W] per-bucket factor, or NULL (1)              */
+} rt_dictionary_desc;
+
+/* Wrap a bucket dictionary.  The handle BORROWS codebook, index and gains
+ * (device memory the caller keeps alive).  It is accepted by rt_lookup_fwd,
+ * rt_lookup_light and rt_debug_indices; rt_lookup_bwd, rt_quantize,
+ * rt_build_mip and rt_lookup_fwd_lod refuse it.
+ * Errors: RT_ERR_INVALID_ARG (NULL pointers, sizes, index_bytes, entries that
+ * do not fit the entry numbers, alignment), RT_ERR_UNSUPPORTED (limits, a
+ * format other than F32 or BF16), RT_ERR_NO_DEVICE. */
+rt_status rt_create_dictionary_texture(const rt_dictionary_desc* desc, rt_texture** out);
+
 /* Release a handle (and its owned copy, after a device synchronisation when
  * it owns one).  NULL is accepted. */
 rt_status rt_destroy_texture(rt_texture* tex);
@@ -350,6 +380,41 @@ rt_status rt_lookup_light(const rt_texture* tex, const rt_fragments* frags, cons
 rt_status rt_bake_shadow(int32_t W, int32_t H, int32_t n, const float* origins,
                          const float* frames, const float* balls, int32_t nballs,
                          uint32_t* words, void* stream);
+
+/* --- Building a bucket dictionary: Lloyd's k-means steps --------------------
+ * The rows are buckets as vectors of D = n*n*C values (a bucket-major FP32
+ * texture is such a [W*H][D] matrix as it stands). */
+
+/* Assignment: assign[b] = argmin_k |x_b - c_k|^2 over the K codebook rows,
+ * evaluated as |c_k|^2 - 2 x_b . c_k with the products on the matrix cores in
+ * binary32 (ties to the smaller k; near-ties within binary32 rounding may go
+ * either way); dist[b] (if not NULL) = |x_b - c_assign|^2 >= 0.
+ * x: DEVICE float [M][D], codebook: DEVICE float [K][D], both 16-byte
+ * aligned; assign: DEVICE int32 [M]; dist: DEVICE float [M] or NULL.
+ * Errors: RT_ERR_INVALID_ARG (NULL, alignment, M < 0, D < 1, K < 1),
+ * RT_ERR_UNSUPPORTED (M >= 2^31, K > 65536). */
+rt_status rt_vq_assign(const float* x, int64_t M, int32_t D, const float* codebook, int32_t K,
+                       int32_t* assign, float* dist, void* stream);
+
+/* Bytes of device workspace rt_vq_update needs (0 when the sizes are
+ * outside its limits). */
+size_t rt_vq_update_workspace(int64_t M, int32_t D, int32_t K);
+
+/* Update: every codebook row k with at least one assigned row becomes the
+ * mean of its rows (binary32 sums in a fixed order: the rows of an entry in
+ * increasing b, in pieces of 64 whose sums are added in order), so the result
+ * is bitwise reproducible; rows with no assigned row are left unchanged.
+ * counts[k] (if not NULL) = rows assigned to k.  An entry number outside
+ * [0, K) counts as the nearest valid one.
+ * x: DEVICE float [M][D]; assign: DEVICE int32 [M]; codebook: DEVICE float
+ * [K][D], updated in place; counts: DEVICE int32 [K] or NULL; all 4-byte
+ * aligned.  workspace: DEVICE, rt_vq_update_workspace bytes, 256-byte
+ * aligned, caller-owned, not shared by concurrent calls.
+ * Errors: RT_ERR_INVALID_ARG (NULL, alignment, M < 1, D < 1, K < 1),
+ * RT_ERR_WORKSPACE_TOO_SMALL, RT_ERR_UNSUPPORTED (K > 4096, M >= 2^31). */
+rt_status rt_vq_update(const float* x, int64_t M, int32_t D, const int32_t* assign, int32_t K,
+                       float* codebook, int32_t* counts, void* workspace,
+                       size_t workspace_bytes, void* stream);
 
 /* Thread-local description of the last non-OK status ("" if none). */
 const char* rt_last_error(void);

@@ -143,7 +143,8 @@ const char* kernel_name(int id) {
         "k_scan",         "k_radix_scatter", "k_bucket_ranges", "k_segacc",
         "k_segacc_hot",   "k_combine_hot",   "k_segacc_big",    "k_bake_directions",
         "k_bake_env",     "k_build_mip",     "k_lookup_lod",    "k_pack_bits",
-        "k_lookup_light", "k_bake_shadow"};
+        "k_lookup_light", "k_bake_shadow",   "k_vq_assign",     "k_vq_hist",
+        "k_vq_scatter",   "k_vq_pieces",     "k_vq_combine"};
     return (id >= 0 && id < K_COUNT) ? names[id] : "";
 }
 
@@ -264,6 +265,50 @@ rt_status rt_create_texture(const rt_texture_desc* d, void* stream, rt_texture**
     RT_GUARD_END
 }
 
+rt_status rt_create_dictionary_texture(const rt_dictionary_desc* d, rt_texture** out) {
+    RT_GUARD_BEGIN
+    if (!out) return fail(RT_ERR_INVALID_ARG, "out is NULL");
+    if (!d) return fail(RT_ERR_INVALID_ARG, "desc is NULL");
+    if (d->buckets_w < 1 || d->buckets_h < 1)
+        return fail(RT_ERR_INVALID_ARG, "bucket matrix %d x %d must be at least 1 x 1", d->buckets_w, d->buckets_h);
+    if (d->buckets_w > 65536 || d->buckets_h > 65536)
+        return fail(RT_ERR_UNSUPPORTED, "bucket matrix %d x %d exceeds 65536 per side", d->buckets_w, d->buckets_h);
+    if (d->n < 1) return fail(RT_ERR_INVALID_ARG, "angular resolution n = %d must be >= 1", d->n);
+    if (d->n > 32) return fail(RT_ERR_UNSUPPORTED, "angular resolution n = %d exceeds 32", d->n);
+    if (d->channels < 1 || d->channels > 4)
+        return fail(RT_ERR_INVALID_ARG, "channels = %d must be in 1..4", d->channels);
+    if (d->format != RT_FMT_F32 && d->format != RT_FMT_BF16)
+        return fail(RT_ERR_UNSUPPORTED, "dictionary entries are stored as F32 or BF16, not format %d", d->format);
+    if (d->index_bytes != 1 && d->index_bytes != 2 && d->index_bytes != 4)
+        return fail(RT_ERR_INVALID_ARG, "index_bytes = %d must be 1, 2 or 4", d->index_bytes);
+    if (d->entries < 1) return fail(RT_ERR_INVALID_ARG, "entries = %d must be >= 1", d->entries);
+    if ((d->index_bytes == 1 && d->entries > 256) || (d->index_bytes == 2 && d->entries > 65536))
+        return fail(RT_ERR_INVALID_ARG, "%d entries do not fit %d-byte entry numbers", d->entries, d->index_bytes);
+    if (!d->codebook || !d->index) return fail(RT_ERR_INVALID_ARG, "codebook and index must be non-NULL");
+    if (!aligned(d->codebook, 16)) return fail(RT_ERR_INVALID_ARG, "codebook must be 16-byte aligned");
+    if (!aligned(d->index, (size_t)d->index_bytes))
+        return fail(RT_ERR_INVALID_ARG, "index must be %d-byte aligned", d->index_bytes);
+    if (d->gains && !aligned(d->gains, 4)) return fail(RT_ERR_INVALID_ARG, "gains must be 4-byte aligned");
+    rt_status st = check_device();
+    if (st != RT_OK) return st;
+    rt_texture* t = new rt_texture();
+    t->view.data = d->codebook;
+    t->view.scales = nullptr;
+    t->view.W = d->buckets_w;
+    t->view.H = d->buckets_h;
+    t->view.n = d->n;
+    t->view.C = d->channels;
+    t->view.index = d->index;
+    t->view.gains = d->gains;
+    t->view.index_bytes = d->index_bytes;
+    t->view.entries = d->entries;
+    t->fmt = d->format;
+    t->owned = nullptr;
+    *out = t;
+    return ok();
+    RT_GUARD_END
+}
+
 rt_status rt_destroy_texture(rt_texture* t) {
     RT_GUARD_BEGIN
     if (!t) return RT_OK;
@@ -281,7 +326,8 @@ rt_status rt_quantize(const rt_texture* src, int32_t dst_format, void* codes, fl
     RT_GUARD_BEGIN
     rt_status st = check_tex(src);
     if (st != RT_OK) return st;
-    if (src->fmt != RT_FMT_F32) return fail(RT_ERR_INVALID_ARG, "quantiser source must be an F32 texture");
+    if (src->fmt != RT_FMT_F32 || src->view.index)
+        return fail(RT_ERR_INVALID_ARG, "quantiser source must be an F32 texture (not a dictionary)");
     if (!codes) return fail(RT_ERR_INVALID_ARG, "dst_codes is NULL");
     if (dst_format == RT_FMT_BF16) {
         if (scales) return fail(RT_ERR_INVALID_ARG, "BF16 has no scales: dst_scales must be NULL");
@@ -347,6 +393,8 @@ rt_status rt_lookup_bwd(const rt_texture* t, const rt_fragments* f, const float*
     if (flags > RT_BUCKET_BILINEAR) return fail(RT_ERR_INVALID_ARG, "unknown flags 0x%x", flags);
     if (t->fmt == RT_FMT_BIT1)
         return fail(RT_ERR_UNSUPPORTED, "1-bit textures have no backward (their values are flags)");
+    if (t->view.index)
+        return fail(RT_ERR_UNSUPPORTED, "the backward of a bucket dictionary is not supported");
     const int C = t->view.C;
     if (f->count > 0) {
         if (!grad_out) return fail(RT_ERR_INVALID_ARG, "grad_out is NULL");
@@ -478,8 +526,8 @@ rt_status rt_build_mip(const rt_texture* src, float* dst, void* stream) {
     rt_status st = check_tex(src);
     if (st != RT_OK) return st;
     const rt::TexView& v = src->view;
-    if (src->fmt != RT_FMT_F32)
-        return fail(RT_ERR_UNSUPPORTED, "mip levels are built from FP32 textures");
+    if (src->fmt != RT_FMT_F32 || src->view.index)
+        return fail(RT_ERR_UNSUPPORTED, "mip levels are built from FP32 textures (not dictionaries)");
     if (!pow2(v.W) || !pow2(v.H))
         return fail(RT_ERR_INVALID_ARG, "bucket matrix %d x %d: a mip chain needs powers of two", v.W, v.H);
     if (v.W == 1 && v.H == 1) return fail(RT_ERR_INVALID_ARG, "a 1 x 1 matrix has no next level");
@@ -502,8 +550,9 @@ rt_status rt_lookup_fwd_lod(const rt_texture* const* levels, int32_t nlevels,
     for (int l = 0; l < nlevels; l++)
         if (!levels[l]) return fail(RT_ERR_INVALID_ARG, "level %d is NULL", l);
     const rt::TexView& v0 = levels[0]->view;
-    if (levels[0]->fmt == RT_FMT_BIT1)
-        return fail(RT_ERR_UNSUPPORTED, "mip chains of 1-bit textures are not supported");
+    for (int l = 0; l < nlevels; l++)
+        if (levels[l]->fmt == RT_FMT_BIT1 || levels[l]->view.index)
+            return fail(RT_ERR_UNSUPPORTED, "mip chains of 1-bit or dictionary textures are not supported");
     if (nlevels > 1) {
         if (!pow2(v0.W) || !pow2(v0.H))
             return fail(RT_ERR_INVALID_ARG, "bucket matrix %d x %d: a mip chain needs powers of two", v0.W, v0.H);
@@ -619,6 +668,63 @@ rt_status rt_bake_shadow(int32_t W, int32_t H, int32_t n, const float* origins,
     if (st != RT_OK) return st;
     hipError_t e = rt::launch_bake_shadow(W, H, n, origins, frames, occ, words, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "shadow bake launch");
+    return ok();
+    RT_GUARD_END
+}
+
+rt_status rt_vq_assign(const float* x, int64_t M, int32_t D, const float* codebook, int32_t K,
+                       int32_t* assign, float* dist, void* stream) {
+    RT_GUARD_BEGIN
+    if (M < 0) return fail(RT_ERR_INVALID_ARG, "M = %lld < 0", (long long)M);
+    if (M >= (1ll << 31)) return fail(RT_ERR_UNSUPPORTED, "M = %lld >= 2^31", (long long)M);
+    if (D < 1) return fail(RT_ERR_INVALID_ARG, "D = %d must be >= 1", D);
+    if (K < 1) return fail(RT_ERR_INVALID_ARG, "K = %d must be >= 1", K);
+    if (K > 65536) return fail(RT_ERR_UNSUPPORTED, "K = %d exceeds 65536", K);
+    if (M == 0) return ok();
+    if (!x || !codebook || !assign)
+        return fail(RT_ERR_INVALID_ARG, "x, codebook and assign must be non-NULL");
+    if (!aligned(x, 16) || !aligned(codebook, 16))
+        return fail(RT_ERR_INVALID_ARG, "x and codebook must be 16-byte aligned");
+    if (!aligned(assign, 4) || (dist && !aligned(dist, 4)))
+        return fail(RT_ERR_INVALID_ARG, "assign and dist must be 4-byte aligned");
+    hipError_t e = rt::launch_vq_assign(x, M, D, codebook, K, assign, dist, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "assignment launch");
+    return ok();
+    RT_GUARD_END
+}
+
+size_t rt_vq_update_workspace(int64_t M, int32_t D, int32_t K) {
+    try {
+        rt::VqPlan p;
+        if (!rt::plan_vq_update(M, D, K, &p)) return 0;
+        return p.total;
+    } catch (...) {
+        return 0;
+    }
+}
+
+rt_status rt_vq_update(const float* x, int64_t M, int32_t D, const int32_t* assign, int32_t K,
+                       float* codebook, int32_t* counts, void* ws, size_t ws_bytes,
+                       void* stream) {
+    RT_GUARD_BEGIN
+    if (M < 1) return fail(RT_ERR_INVALID_ARG, "M = %lld must be >= 1", (long long)M);
+    if (D < 1) return fail(RT_ERR_INVALID_ARG, "D = %d must be >= 1", D);
+    if (K < 1) return fail(RT_ERR_INVALID_ARG, "K = %d must be >= 1", K);
+    rt::VqPlan plan;
+    if (!rt::plan_vq_update(M, D, K, &plan))
+        return fail(RT_ERR_UNSUPPORTED, "the update takes K <= %d entries and M < 2^31 rows",
+                    rt::VQ_MAX_UPDATE_ENTRIES);
+    if (!x || !assign || !codebook)
+        return fail(RT_ERR_INVALID_ARG, "x, assign and codebook must be non-NULL");
+    if (!aligned(x, 4) || !aligned(assign, 4) || !aligned(codebook, 4) ||
+        (counts && !aligned(counts, 4)))
+        return fail(RT_ERR_INVALID_ARG, "x, assign, codebook and counts must be 4-byte aligned");
+    if (!ws) return fail(RT_ERR_INVALID_ARG, "workspace is NULL");
+    if (!aligned(ws, 256)) return fail(RT_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+    if (ws_bytes < plan.total)
+        return fail(RT_ERR_WORKSPACE_TOO_SMALL, "workspace has %zu bytes, %zu needed", ws_bytes, plan.total);
+    hipError_t e = rt::launch_vq_update(x, assign, codebook, counts, plan, ws, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "update launch");
     return ok();
     RT_GUARD_END
 }

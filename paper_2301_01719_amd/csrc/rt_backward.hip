@@ -1020,6 +1020,13 @@ static void launch_scan(const uint32_t* in, uint32_t* out, uint32_t* part, int64
     prof_end(K_SCAN, s);
 }
 
+hipError_t launch_exclusive_scan(const uint32_t* in, uint32_t* out, uint32_t* part, int64_t L,
+                                 hipStream_t s) {
+    if (L <= 0) return hipSuccess;
+    launch_scan(in, out, part, L, (L + SCAN_TILE - 1) / SCAN_TILE, s);
+    return hipGetLastError();
+}
+
 hipError_t launch_backward(const TexView& t, int fmt, int mode, const float* uv,
                            const float* tbn, const float* view, const float* grad_out,
                            float* grad_tex, float* grad_view, float* grad_uv, const FragMap& m,

@@ -25,12 +25,29 @@ constexpr int MODE_BILINEAR = 1;
 typedef float f4v __attribute__((ext_vector_type(4)));
 typedef uint32_t u2v __attribute__((ext_vector_type(2)));
 
-// Texture as seen by a kernel: bucket-major [H][W][n][n][C].
+// Texture as seen by a kernel: bucket-major [H][W][n][n][C].  A bucket
+// dictionary keeps `entries` buckets in data (its codebook) and an index map
+// [H][W] (1, 2 or 4 bytes per bucket) naming each bucket's entry, with an
+// optional gain per bucket.
 struct TexView {
     const void* data;     // FMT_BIT1: uint32 words, bit_words(n) per bucket
     const float* scales;  // [H][W], FP8 only
     int W, H, n, C;
+    const void* index;    // dictionary: entry of each bucket, or nullptr
+    const float* gains;   // dictionary: gain of each bucket, or nullptr (1)
+    int index_bytes;      // 1, 2 or 4
+    int entries;          // dictionary: codebook entries K
 };
+
+// Entry of bucket b of a dictionary; numbers past the codebook read its last
+// entry (the index map is caller data that the host cannot check).
+__device__ __forceinline__ int64_t dict_entry(const TexView& t, int64_t b) {
+    uint32_t e;
+    if (t.index_bytes == 1) e = ((const uint8_t*)t.index)[b];
+    else if (t.index_bytes == 2) e = ((const uint16_t*)t.index)[b];
+    else e = ((const uint32_t*)t.index)[b];
+    return (int64_t)min(e, (uint32_t)(t.entries - 1));
+}
 
 // A mip chain: level l has max(1, W >> l) x max(1, H >> l) buckets of the
 // same n, C and format; only the storage pointers differ per level.

@@ -36,6 +36,11 @@ enum KernelId {
     K_PACK_BITS,
     K_LOOKUP_LIGHT,
     K_BAKE_SHADOW,
+    K_VQ_ASSIGN,
+    K_VQ_HIST,
+    K_VQ_SCATTER,
+    K_VQ_PIECES,
+    K_VQ_COMBINE,
     K_COUNT
 };
 const char* kernel_name(int id);
@@ -118,6 +123,28 @@ constexpr int BIG_LISTS = 64; // big-bucket lists, each with its own counter
 constexpr int BIG_STRIDE = 64;  // u32 between two counters (256 bytes)
 constexpr int BIG_RUN = 64;     // consecutive groups that append to one list
 bool plan_backward(int W, int H, int n, int C, int64_t N, int mode, BwdPlan* p);
+
+// Device-wide exclusive scan of L uint32 values (the backward's three-kernel
+// scan); part holds ceil(L / 4096) + 1 words.
+hipError_t launch_exclusive_scan(const uint32_t* in, uint32_t* out, uint32_t* part, int64_t L,
+                                 hipStream_t s);
+
+// Bucket dictionary: Lloyd's assignment (MFMA) and update steps.
+constexpr int VQ_MAX_UPDATE_ENTRIES = 4096;  // entries the update's LDS counters hold
+constexpr int VQ_CHUNK = 4096;               // rows per chunk of the update's counting sort
+constexpr int VQ_PIECE = 64;                 // rows summed by one workgroup of the update
+struct VqPlan {
+    int64_t M;
+    int D, K;
+    int64_t chunks, hist_len, pieces_max;
+    size_t off_hist, off_offs, off_part, off_sorted, off_ptab, off_pstart, off_ppart, off_sums,
+        total;
+};
+bool plan_vq_update(int64_t M, int D, int K, VqPlan* p);
+hipError_t launch_vq_assign(const float* x, int64_t M, int D, const float* codebook, int K,
+                            int32_t* assign, float* dist, hipStream_t s);
+hipError_t launch_vq_update(const float* x, const int32_t* assign, float* codebook,
+                            int32_t* counts, const VqPlan& plan, void* ws, hipStream_t s);
 
 hipError_t launch_backward(const TexView& t, int fmt, int mode, const float* uv,
                            const float* tbn, const float* view, const float* grad_out,

@@ -16,10 +16,17 @@
 
 namespace rt {
 
-template <int FMT, int C>
+// The four taps of bucket b around footprint p, blended and added to acc
+// with weight wgt.  DICT: b is read through the dictionary (its entry in the
+// codebook, times its gain).
+template <int FMT, int C, bool DICT = false>
 __device__ __forceinline__ void bucket_bilerp(const TexView& t, int64_t b, const Foot& p,
                                               float wgt, float acc[4]) {
     const int n = t.n;
+    if constexpr (DICT) {
+        if (t.gains) wgt *= t.gains[b];
+        b = dict_entry(t, b);
+    }
     if constexpr (FMT == FMT_BIT1) {
         const uint32_t* w = (const uint32_t*)t.data + b * bit_words(n);
         const int k00 = p.y0 * n + p.x0, k01 = p.y0 * n + p.x1;
@@ -60,7 +67,7 @@ __device__ __forceinline__ void store_out(float* __restrict__ out, int64_t f, co
     }
 }
 
-template <int FMT, int C, int MODE>
+template <int FMT, int C, int MODE, bool DICT>
 __global__ __launch_bounds__(256) void k_lookup_fwd(TexView t, const float* __restrict__ uv,
                                                     const float* __restrict__ tbn,
                                                     const float* __restrict__ view,
@@ -73,16 +80,16 @@ __global__ __launch_bounds__(256) void k_lookup_fwd(TexView t, const float* __re
     float acc[4] = {0.f, 0.f, 0.f, 0.f};
     if constexpr (MODE == MODE_NEAREST) {
         int i = bucket_of(g.u, t.W), j = bucket_of(g.v, t.H);
-        bucket_bilerp<FMT, C>(t, (int64_t)j * t.W + i, p, 1.0f, acc);
+        bucket_bilerp<FMT, C, DICT>(t, (int64_t)j * t.W + i, p, 1.0f, acc);
     } else {
         int i0, i1, j0, j1;
         float a, bb;
         bucket_pair(g.u, t.W, i0, i1, a);
         bucket_pair(g.v, t.H, j0, j1, bb);
-        bucket_bilerp<FMT, C>(t, (int64_t)j0 * t.W + i0, p, (1.f - a) * (1.f - bb), acc);
-        bucket_bilerp<FMT, C>(t, (int64_t)j0 * t.W + i1, p, a * (1.f - bb), acc);
-        bucket_bilerp<FMT, C>(t, (int64_t)j1 * t.W + i0, p, (1.f - a) * bb, acc);
-        bucket_bilerp<FMT, C>(t, (int64_t)j1 * t.W + i1, p, a * bb, acc);
+        bucket_bilerp<FMT, C, DICT>(t, (int64_t)j0 * t.W + i0, p, (1.f - a) * (1.f - bb), acc);
+        bucket_bilerp<FMT, C, DICT>(t, (int64_t)j0 * t.W + i1, p, a * (1.f - bb), acc);
+        bucket_bilerp<FMT, C, DICT>(t, (int64_t)j1 * t.W + i0, p, (1.f - a) * bb, acc);
+        bucket_bilerp<FMT, C, DICT>(t, (int64_t)j1 * t.W + i1, p, a * bb, acc);
     }
     store_out<C>(out, f, acc);
 }
@@ -120,7 +127,7 @@ __device__ __forceinline__ void level_storage(const LevelSet& ls, int l, const v
 template <int FMT, int C, int MODE>
 __device__ __forceinline__ void level_lookup(const LevelSet& ls, int l, const Frag& g,
                                              const Foot& p, float acc[4]) {
-    TexView t;
+    TexView t{};
     level_storage(ls, l, t.data, t.scales);
     t.W = max(ls.W >> l, 1);
     t.H = max(ls.H >> l, 1);
@@ -180,15 +187,15 @@ __global__ __launch_bounds__(256) void k_lookup_lod(LevelSet ls, const float* __
     store_out<C>(out, f, a);
 }
 
-template <int FMT, int MODE>
+template <int FMT, int MODE, bool DICT = false>
 static hipError_t launch_fwd_c(const TexView& t, const float* uv, const float* tbn,
                                const float* view, float* out, const FragMap& m, hipStream_t s) {
     const uint32_t blocks = fragmap_blocks(m);
     switch (t.C) {
-    case 1: hipLaunchKernelGGL((k_lookup_fwd<FMT, 1, MODE>), dim3(blocks), dim3(256), 0, s, t, uv, tbn, view, out, m); break;
-    case 2: hipLaunchKernelGGL((k_lookup_fwd<FMT, 2, MODE>), dim3(blocks), dim3(256), 0, s, t, uv, tbn, view, out, m); break;
-    case 3: hipLaunchKernelGGL((k_lookup_fwd<FMT, 3, MODE>), dim3(blocks), dim3(256), 0, s, t, uv, tbn, view, out, m); break;
-    default: hipLaunchKernelGGL((k_lookup_fwd<FMT, 4, MODE>), dim3(blocks), dim3(256), 0, s, t, uv, tbn, view, out, m); break;
+    case 1: hipLaunchKernelGGL((k_lookup_fwd<FMT, 1, MODE, DICT>), dim3(blocks), dim3(256), 0, s, t, uv, tbn, view, out, m); break;
+    case 2: hipLaunchKernelGGL((k_lookup_fwd<FMT, 2, MODE, DICT>), dim3(blocks), dim3(256), 0, s, t, uv, tbn, view, out, m); break;
+    case 3: hipLaunchKernelGGL((k_lookup_fwd<FMT, 3, MODE, DICT>), dim3(blocks), dim3(256), 0, s, t, uv, tbn, view, out, m); break;
+    default: hipLaunchKernelGGL((k_lookup_fwd<FMT, 4, MODE, DICT>), dim3(blocks), dim3(256), 0, s, t, uv, tbn, view, out, m); break;
     }
     return hipGetLastError();
 }
@@ -200,11 +207,19 @@ hipError_t launch_lookup_fwd(const TexView& t, int fmt, int mode, const float* u
     hipError_t e;
     prof_begin(K_LOOKUP_FWD, s);
     const uint32_t blocks = fragmap_blocks(m);
-    if (fmt == FMT_BIT1) {
+    if (t.index) {  // a bucket dictionary (F32 or BF16 codebook)
+        if (mode == MODE_NEAREST) {
+            if (fmt == FMT_F32) e = launch_fwd_c<FMT_F32, MODE_NEAREST, true>(t, uv, tbn, view, out, m, s);
+            else e = launch_fwd_c<FMT_BF16, MODE_NEAREST, true>(t, uv, tbn, view, out, m, s);
+        } else {
+            if (fmt == FMT_F32) e = launch_fwd_c<FMT_F32, MODE_BILINEAR, true>(t, uv, tbn, view, out, m, s);
+            else e = launch_fwd_c<FMT_BF16, MODE_BILINEAR, true>(t, uv, tbn, view, out, m, s);
+        }
+    } else if (fmt == FMT_BIT1) {
         if (mode == MODE_NEAREST)
-            hipLaunchKernelGGL((k_lookup_fwd<FMT_BIT1, 1, MODE_NEAREST>), dim3(blocks), dim3(256), 0, s, t, uv, tbn, view, out, m);
+            hipLaunchKernelGGL((k_lookup_fwd<FMT_BIT1, 1, MODE_NEAREST, false>), dim3(blocks), dim3(256), 0, s, t, uv, tbn, view, out, m);
         else
-            hipLaunchKernelGGL((k_lookup_fwd<FMT_BIT1, 1, MODE_BILINEAR>), dim3(blocks), dim3(256), 0, s, t, uv, tbn, view, out, m);
+            hipLaunchKernelGGL((k_lookup_fwd<FMT_BIT1, 1, MODE_BILINEAR, false>), dim3(blocks), dim3(256), 0, s, t, uv, tbn, view, out, m);
         e = hipGetLastError();
     } else if (mode == MODE_NEAREST) {
         if (fmt == FMT_F32) e = launch_fwd_c<FMT_F32, MODE_NEAREST>(t, uv, tbn, view, out, m, s);
@@ -296,7 +311,7 @@ __device__ __forceinline__ void light_coord(const float M[9], const float L[3], 
 // ([word][lane], so that lanes reading different words still hit distinct
 // banks), and every tap of every sample is one LDS read instead of a global
 // gather.  Each lane reads only its own column: no barrier is needed.
-template <int FMT, int C, int MODE, bool CACHE>
+template <int FMT, int C, int MODE, bool CACHE, bool DICT>
 __global__ __launch_bounds__(256) void k_lookup_light(TexView t, const float* __restrict__ uv,
                                                       const float* __restrict__ tbn,
                                                       const float* __restrict__ pos,
@@ -368,7 +383,7 @@ __global__ __launch_bounds__(256) void k_lookup_light(TexView t, const float* __
             }
         } else {
 #pragma unroll
-            for (int r = 0; r < NB; r++) bucket_bilerp<FMT, C>(t, bk[r], p, bw[r], acc);
+            for (int r = 0; r < NB; r++) bucket_bilerp<FMT, C, DICT>(t, bk[r], p, bw[r], acc);
         }
     }
 #pragma unroll
@@ -376,15 +391,15 @@ __global__ __launch_bounds__(256) void k_lookup_light(TexView t, const float* __
     store_out<C>(out, f, acc);
 }
 
-template <int FMT, int MODE>
+template <int FMT, int MODE, bool DICT = false>
 static void launch_light_c(const TexView& t, const float* uv, const float* tbn, const float* pos,
                            const LightParams& lp, float* out, const FragMap& m, hipStream_t s) {
     const uint32_t blocks = fragmap_blocks(m);
     switch (t.C) {
-    case 1: hipLaunchKernelGGL((k_lookup_light<FMT, 1, MODE, false>), dim3(blocks), dim3(256), 0, s, t, uv, tbn, pos, lp, out, m); break;
-    case 2: hipLaunchKernelGGL((k_lookup_light<FMT, 2, MODE, false>), dim3(blocks), dim3(256), 0, s, t, uv, tbn, pos, lp, out, m); break;
-    case 3: hipLaunchKernelGGL((k_lookup_light<FMT, 3, MODE, false>), dim3(blocks), dim3(256), 0, s, t, uv, tbn, pos, lp, out, m); break;
-    default: hipLaunchKernelGGL((k_lookup_light<FMT, 4, MODE, false>), dim3(blocks), dim3(256), 0, s, t, uv, tbn, pos, lp, out, m); break;
+    case 1: hipLaunchKernelGGL((k_lookup_light<FMT, 1, MODE, false, DICT>), dim3(blocks), dim3(256), 0, s, t, uv, tbn, pos, lp, out, m); break;
+    case 2: hipLaunchKernelGGL((k_lookup_light<FMT, 2, MODE, false, DICT>), dim3(blocks), dim3(256), 0, s, t, uv, tbn, pos, lp, out, m); break;
+    case 3: hipLaunchKernelGGL((k_lookup_light<FMT, 3, MODE, false, DICT>), dim3(blocks), dim3(256), 0, s, t, uv, tbn, pos, lp, out, m); break;
+    default: hipLaunchKernelGGL((k_lookup_light<FMT, 4, MODE, false, DICT>), dim3(blocks), dim3(256), 0, s, t, uv, tbn, pos, lp, out, m); break;
     }
 }
 
@@ -398,11 +413,19 @@ hipError_t launch_lookup_light(const TexView& t, int fmt, int mode, const float*
         // the LDS copy of the buckets pays off once several samples read them
         const bool cache = t.n <= 16 && lp.samples >= 4;
         if (mode == MODE_NEAREST) {
-            if (cache) hipLaunchKernelGGL((k_lookup_light<FMT_BIT1, 1, MODE_NEAREST, true>), dim3(blocks), dim3(256), 0, s, t, uv, tbn, pos, lp, out, m);
-            else hipLaunchKernelGGL((k_lookup_light<FMT_BIT1, 1, MODE_NEAREST, false>), dim3(blocks), dim3(256), 0, s, t, uv, tbn, pos, lp, out, m);
+            if (cache) hipLaunchKernelGGL((k_lookup_light<FMT_BIT1, 1, MODE_NEAREST, true, false>), dim3(blocks), dim3(256), 0, s, t, uv, tbn, pos, lp, out, m);
+            else hipLaunchKernelGGL((k_lookup_light<FMT_BIT1, 1, MODE_NEAREST, false, false>), dim3(blocks), dim3(256), 0, s, t, uv, tbn, pos, lp, out, m);
         } else {
-            if (cache) hipLaunchKernelGGL((k_lookup_light<FMT_BIT1, 1, MODE_BILINEAR, true>), dim3(blocks), dim3(256), 0, s, t, uv, tbn, pos, lp, out, m);
-            else hipLaunchKernelGGL((k_lookup_light<FMT_BIT1, 1, MODE_BILINEAR, false>), dim3(blocks), dim3(256), 0, s, t, uv, tbn, pos, lp, out, m);
+            if (cache) hipLaunchKernelGGL((k_lookup_light<FMT_BIT1, 1, MODE_BILINEAR, true, false>), dim3(blocks), dim3(256), 0, s, t, uv, tbn, pos, lp, out, m);
+            else hipLaunchKernelGGL((k_lookup_light<FMT_BIT1, 1, MODE_BILINEAR, false, false>), dim3(blocks), dim3(256), 0, s, t, uv, tbn, pos, lp, out, m);
+        }
+    } else if (t.index) {  // a bucket dictionary (F32 or BF16 codebook)
+        if (mode == MODE_NEAREST) {
+            if (fmt == FMT_F32) launch_light_c<FMT_F32, MODE_NEAREST, true>(t, uv, tbn, pos, lp, out, m, s);
+            else launch_light_c<FMT_BF16, MODE_NEAREST, true>(t, uv, tbn, pos, lp, out, m, s);
+        } else {
+            if (fmt == FMT_F32) launch_light_c<FMT_F32, MODE_BILINEAR, true>(t, uv, tbn, pos, lp, out, m, s);
+            else launch_light_c<FMT_BF16, MODE_BILINEAR, true>(t, uv, tbn, pos, lp, out, m, s);
         }
     } else if (mode == MODE_NEAREST) {
         if (fmt == FMT_F32) launch_light_c<FMT_F32, MODE_NEAREST>(t, uv, tbn, pos, lp, out, m, s);

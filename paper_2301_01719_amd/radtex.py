@@ -41,7 +41,8 @@ EXPORTS = ("rt_create_texture", "rt_destroy_texture", "rt_quantize", "rt_lookup_
            "rt_status_string", "rt_version", "rt_profile_enable", "rt_profile_reset",
            "rt_profile_kernel_count", "rt_profile_kernel_name", "rt_profile_read",
            "rt_bake_directions", "rt_bake_environment", "rt_build_mip", "rt_lookup_fwd_lod",
-           "rt_lookup_light", "rt_bake_shadow")
+           "rt_lookup_light", "rt_bake_shadow", "rt_create_dictionary_texture",
+           "rt_vq_assign", "rt_vq_update_workspace", "rt_vq_update")
 
 
 class RadtexError(RuntimeError):
@@ -55,6 +56,15 @@ class TextureDesc(ctypes.Structure):
                 ("n", ctypes.c_int32), ("channels", ctypes.c_int32),
                 ("format", ctypes.c_int32), ("layout", ctypes.c_int32),
                 ("data", ctypes.c_void_p), ("scales", ctypes.c_void_p)]
+
+
+class DictionaryDesc(ctypes.Structure):
+    _fields_ = [("buckets_w", ctypes.c_int32), ("buckets_h", ctypes.c_int32),
+                ("n", ctypes.c_int32), ("channels", ctypes.c_int32),
+                ("entries", ctypes.c_int32), ("format", ctypes.c_int32),
+                ("index_bytes", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("codebook", ctypes.c_void_p), ("index", ctypes.c_void_p),
+                ("gains", ctypes.c_void_p)]
 
 
 class EnvLobe(ctypes.Structure):
@@ -105,6 +115,10 @@ def _load() -> ctypes.CDLL:
         "rt_lookup_light": ([P, ctypes.POINTER(Fragments), P, ctypes.POINTER(Light), P, u32, P],
                             i32),
         "rt_bake_shadow": ([i32, i32, i32, P, P, ctypes.POINTER(ctypes.c_float), i32, P, P], i32),
+        "rt_create_dictionary_texture": ([ctypes.POINTER(DictionaryDesc), ctypes.POINTER(P)], i32),
+        "rt_vq_assign": ([P, i64, i32, P, i32, P, P, P], i32),
+        "rt_vq_update_workspace": ([i64, i32, i32], sz),
+        "rt_vq_update": ([P, i64, i32, P, i32, P, P, P, sz, P], i32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -184,6 +198,64 @@ class Texture:
     @property
     def bucket_elems(self) -> int:
         return self.n * self.n * self.C
+
+
+class DictionaryTexture(Texture):
+    """A bucket dictionary (rt_create_dictionary_texture): bucket (i, j)
+    decodes to gains[j, i] (1 without gains) times codebook[index[j, i]].
+    codebook [K, n, n, C] float32 or bf16 codes (int16), index [H, W] uint8,
+    int16 (read as unsigned 16-bit) or int32, gains [H, W] float32 or None.
+    All tensors stay referenced by this object."""
+
+    def __init__(self, codebook: torch.Tensor, index: torch.Tensor, W: int, H: int, n: int,
+                 C: int, fmt="f32", gains: Optional[torch.Tensor] = None):
+        self.fmt = FORMATS[fmt] if isinstance(fmt, str) else int(fmt)
+        _need_gpu(codebook, "codebook")
+        _need_gpu(index, "index")
+        if gains is not None:
+            _need_gpu(gains, "gains", torch.float32)
+        K = codebook.shape[0]
+        self.data, self.scales, self.index, self.gains = codebook, None, index, gains
+        self.W, self.H, self.n, self.C, self.K = int(W), int(H), int(n), int(C), int(K)
+        ib = index.element_size()
+        desc = DictionaryDesc(self.W, self.H, self.n, self.C, self.K, self.fmt, ib, 0,
+                              codebook.data_ptr(), index.data_ptr(),
+                              None if gains is None else gains.data_ptr())
+        h = ctypes.c_void_p()
+        _check(LIB.rt_create_dictionary_texture(ctypes.byref(desc), ctypes.byref(h)))
+        self.handle = h
+        self.device = codebook.device
+
+
+def vq_assign(x: torch.Tensor, codebook: torch.Tensor, want_dist: bool = False):
+    """Nearest codebook row of every row of x [M, D] (rt_vq_assign): returns
+    assign [M] int32 and, if asked, the squared distances [M] float32."""
+    _need_gpu(x, "x", torch.float32)
+    _need_gpu(codebook, "codebook", torch.float32)
+    M, D = x.shape
+    K = codebook.shape[0]
+    assign = torch.empty(M, dtype=torch.int32, device=x.device)
+    dist = torch.empty(M, dtype=torch.float32, device=x.device) if want_dist else None
+    _check(LIB.rt_vq_assign(_ptr(x), M, D, _ptr(codebook), K, _ptr(assign), _ptr(dist),
+                            _stream(x.device)))
+    return (assign, dist) if want_dist else assign
+
+
+def vq_update(x: torch.Tensor, assign: torch.Tensor, codebook: torch.Tensor, workspace=None):
+    """Lloyd update of codebook [K, D] in place (rt_vq_update); returns the
+    counts [K] int32."""
+    _need_gpu(x, "x", torch.float32)
+    _need_gpu(assign, "assign", torch.int32)
+    _need_gpu(codebook, "codebook", torch.float32)
+    M, D = x.shape
+    K = codebook.shape[0]
+    need = LIB.rt_vq_update_workspace(M, D, K)
+    if workspace is None:
+        workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=x.device)
+    counts = torch.empty(K, dtype=torch.int32, device=x.device)
+    _check(LIB.rt_vq_update(_ptr(x), M, D, _ptr(assign), K, _ptr(codebook), _ptr(counts),
+                            _ptr(workspace), workspace.numel(), _stream(x.device)))
+    return counts
 
 
 def _frags(uv, tbn, view, image=None) -> Fragments:

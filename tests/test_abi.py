@@ -336,3 +336,55 @@ def test_light_lookup_validation_with_a_handle(rt):
         assert L.rt_build_mip(h, 0x1000, None) == 2
     finally:
         L.rt_destroy_texture(h)
+
+
+def test_dictionary_and_encoder_validation(rt):
+    """Host checks of the dictionary texture and of Lloyd's steps."""
+    L = rt.LIB
+    h = ctypes.c_void_p()
+
+    def desc(**kw):
+        d = dict(buckets_w=4, buckets_h=4, n=8, channels=4, entries=16, format=0, index_bytes=1,
+                 reserved=0, codebook=0x10000, index=0x20000, gains=None)
+        d.update(kw)
+        return rt.DictionaryDesc(**d)
+    for kw, status, text in ((dict(buckets_w=0), 1, "bucket matrix"),
+                             (dict(n=33), 2, "exceeds 32"), (dict(channels=5), 1, "channels"),
+                             (dict(format=2), 2, "F32 or BF16"), (dict(format=3), 2, "F32 or BF16"),
+                             (dict(index_bytes=3), 1, "index_bytes"), (dict(entries=0), 1, "entries"),
+                             (dict(entries=257), 1, "do not fit"),
+                             (dict(index_bytes=2, entries=65537), 1, "do not fit"),
+                             (dict(codebook=None), 1, "non-NULL"), (dict(index=None), 1, "non-NULL"),
+                             (dict(codebook=0x10008), 1, "16-byte"),
+                             (dict(index_bytes=4, index=0x20002), 1, "4-byte"),
+                             (dict(gains=0x30002), 1, "gains")):
+        d = desc(**kw)
+        assert L.rt_create_dictionary_texture(ctypes.byref(d), ctypes.byref(h)) == status, kw
+        assert text in L.rt_last_error().decode(), (kw, L.rt_last_error())
+    assert L.rt_create_dictionary_texture(None, ctypes.byref(h)) == 1
+    # assignment
+    A = L.rt_vq_assign
+    assert A(0x1000, -1, 8, 0x2000, 4, 0x3000, None, None) == 1
+    assert A(0x1000, 1 << 31, 8, 0x2000, 4, 0x3000, None, None) == 2
+    assert A(0x1000, 10, 0, 0x2000, 4, 0x3000, None, None) == 1
+    assert A(0x1000, 10, 8, 0x2000, 0, 0x3000, None, None) == 1
+    assert A(0x1000, 10, 8, 0x2000, 65537, 0x3000, None, None) == 2
+    assert A(None, 0, 8, None, 4, None, None, None) == 0  # nothing to assign
+    assert A(None, 10, 8, 0x2000, 4, 0x3000, None, None) == 1
+    assert A(0x1008, 10, 8, 0x2000, 4, 0x3000, None, None) == 1
+    assert "16-byte" in L.rt_last_error().decode()
+    assert A(0x1000, 10, 8, 0x2000, 4, 0x3002, None, None) == 1
+    assert A(0x1000, 10, 8, 0x2000, 4, 0x3000, 0x4001, None) == 1
+    # update
+    assert L.rt_vq_update_workspace(1000, 16, 4096) > 0
+    assert L.rt_vq_update_workspace(1000, 16, 4097) == 0
+    assert L.rt_vq_update_workspace(0, 16, 4) == 0
+    Up = L.rt_vq_update
+    need = L.rt_vq_update_workspace(1000, 16, 8)
+    assert Up(0x1000, 0, 16, 0x2000, 8, 0x3000, None, 0x10000, need, None) == 1
+    assert Up(0x1000, 1000, 16, 0x2000, 5000, 0x3000, None, 0x10000, need, None) == 2
+    assert Up(None, 1000, 16, 0x2000, 8, 0x3000, None, 0x10000, need, None) == 1
+    assert Up(0x1000, 1000, 16, 0x2000, 8, 0x3000, None, None, need, None) == 1
+    assert Up(0x1000, 1000, 16, 0x2000, 8, 0x3000, None, 0x10080, need, None) == 1
+    assert Up(0x1000, 1000, 16, 0x2000, 8, 0x3000, None, 0x10000, need - 1, None) == 4
+    assert Up(0x1000, 1000, 16, 0x2000, 8, 0x3000, 0x5002, 0x10000, need, None) == 1
