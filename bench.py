@@ -43,12 +43,21 @@ BAKE_AMBIENT = (0.05, 0.05, 0.05, 0.0)
 
 METRIC = "lookups/s + % HBM peak, fwd & bwd; FP32 vs BF16/FP8 texture at stated error"
 HBM_PEAK_GBS = 8000.0
+FP32_MFMA_PEAK_TFLOPS = 157.3
 KERNEL_SOURCES = ["rt_device.hpp", "rt_lookup.hip", "rt_quantize.hip", "rt_backward.hip",
                   "rt_bake.hip", "rt_mip.hip", "rt_dictionary.hip"]
 
 # the shadow measurement (Sec. 5, Shadowing): balls over the plane tile, a sun
 # disc and a spherical lamp
 SHADOW_BALLS = 16
+
+# the bucket-dictionary measurement: the matrix as repetitive buckets (each a
+# noisy copy of one of DICT_PROTOTYPES buckets of the smooth texture), encoded
+# into DICT_ENTRIES entries by DICT_ITERATIONS Lloyd steps
+DICT_PROTOTYPES = 64
+DICT_ENTRIES = 256
+DICT_NOISE = 0.01
+DICT_ITERATIONS = 3
 SHADOW_CASES = (("sun", 1, "nearest"), ("sun", 16, "nearest"), ("sun", 64, "nearest"),
                 ("lamp", 16, "bilinear"))
 
@@ -91,6 +100,8 @@ def parse():
     ap.add_argument("--no-bake", action="store_true", help="skip the bake measurement")
     ap.add_argument("--no-mip", action="store_true", help="skip the mip-chain measurement")
     ap.add_argument("--no-shadow", action="store_true", help="skip the shadow measurement")
+    ap.add_argument("--no-dictionary", action="store_true",
+                    help="skip the bucket-dictionary measurement")
     ap.add_argument("--graph", action="store_true",
                     help="time replays of the step captured in a HIP graph (same kernels, no "
                          "host launch gaps; measured equal to eager launches on this workload)")
@@ -102,6 +113,9 @@ def parse():
     ap.add_argument("--profile-mip", type=int, default=0,
                     help="with --profile-steps: also build the mip chain and run the "
                          "level-of-detail lookup this many times")
+    ap.add_argument("--profile-dictionary", type=int, default=0,
+                    help="with --profile-steps: also run this many Lloyd steps and dictionary "
+                         "lookups")
     ap.add_argument("--profile-shadow", type=int, default=0,
                     help="with --profile-steps: also run the shadow bake, the 1-bit packer "
                          "and the light lookups this many times")
@@ -206,6 +220,100 @@ def run_shadow(rt, w, gb, reps, timed):
                     "position 12 (lamp), out 4"}
 
 
+def run_dictionary(rt, w, gb, tex32, reps, timed):
+    """The bucket dictionary on the workload's matrix: a repetitive texture
+    (every bucket a noisy copy of one of DICT_PROTOTYPES buckets of the smooth
+    texture), DICT_ITERATIONS Lloyd steps into DICT_ENTRIES entries from
+    seeded initial rows, then the lookup through the dictionary against the
+    plain lookup of the repetitive texture.  timed=False only runs the
+    kernels (for a profiler)."""
+    import numpy as np
+    import torch
+    from paper_2301_01719_amd import workloads as wl
+    dev = gb.uv.device
+    W, H, n, C = w.W, w.H, w.n, w.C
+    M, D, K = W * H, n * n * C, DICT_ENTRIES
+    src = tex32.reshape(M, D)
+    pick = (wl.uniform64(w.seed, wl.S_TEXTURE, torch.arange(DICT_PROTOTYPES, device=dev))
+            * M).to(torch.int64)
+    lab = (wl.uniform64(w.seed + 1, wl.S_TEXTURE, torch.arange(M, device=dev))
+           * DICT_PROTOTYPES).to(torch.int64)
+    X = src[pick][lab]
+    a, b = wl.normal_pair(w.seed, wl.S_NOISE, M * D // 2, dev)
+    X += DICT_NOISE * torch.cat([a, b]).reshape(M, D)
+    del a, b, lab
+    X = X.contiguous()
+    init = (wl.uniform64(w.seed + 2, wl.S_TEXTURE, torch.arange(K, device=dev)) * M).to(torch.int64)
+    cb = X[init].contiguous()
+    ws = torch.empty(rt.LIB.rt_vq_update_workspace(M, D, K), dtype=torch.uint8, device=dev)
+    out = torch.empty((gb.count, C), dtype=torch.float32, device=dev)
+
+    def step():
+        asg = rt.vq_assign(X, cb)
+        rt.vq_update(X, asg, cb, workspace=ws)
+        return asg
+    if not timed:
+        for _ in range(reps):
+            asg = step()
+        dtex = rt.DictionaryTexture(cb.reshape(K, n, n, C), asg.reshape(H, W), W, H, n, C)
+        for _ in range(reps):
+            rt.lookup_fwd(dtex, gb.uv, gb.tbn, gb.view, out=out, image=gb.image)
+        torch.cuda.synchronize()
+        return None
+    rt.profile_reset()
+    rt.profile_enable(True)
+    for _ in range(DICT_ITERATIONS):
+        asg = step()
+    torch.cuda.synchronize()
+    rt.profile_enable(False)
+    prof = rt.profile_read()
+    assign_ms = prof["k_vq_assign"][1] / prof["k_vq_assign"][0]
+    upd = [k for k in ("k_vq_hist", "k_scan", "k_vq_scatter", "k_vq_pieces", "k_vq_combine")]
+    update_ms = sum(prof[k][1] for k in upd) / DICT_ITERATIONS
+    asg, dist = rt.vq_assign(X, cb, want_dist=True)
+    torch.cuda.synchronize()
+    flops = 2.0 * M * K * D
+    idx8 = asg.to(torch.uint8).reshape(H, W)
+    dtex = rt.DictionaryTexture(cb.reshape(K, n, n, C), idx8, W, H, n, C)
+    ptex = rt.Texture(X.reshape(H, W, n, n, C), W, H, n, C)
+
+    def timed_lookup(tex):
+        for _ in range(3):
+            rt.lookup_fwd(tex, gb.uv, gb.tbn, gb.view, out=out, image=gb.image)
+        torch.cuda.synchronize()
+        ms = []
+        for _ in range(30):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            rt.lookup_fwd(tex, gb.uv, gb.tbn, gb.view, out=out, image=gb.image)
+            e1.record()
+            e1.synchronize()
+            ms.append(e0.elapsed_time(e1))
+        return [round(float(v), 5) for v in np.percentile(np.array(ms), [10, 50, 90])]
+    q_dict = timed_lookup(dtex)
+    o_dict = out.clone()
+    q_plain = timed_lookup(ptex)
+    diff = (o_dict - out).abs()
+    mse = float((diff.double() ** 2).mean())
+    res = {"rows": M, "dim": D, "entries": K, "prototypes": DICT_PROTOTYPES, "noise": DICT_NOISE,
+           "iterations": DICT_ITERATIONS,
+           "assign_ms": round(assign_ms, 5),
+           "assign_TFLOPs": round(flops / (assign_ms * 1e-3) / 1e12, 2),
+           "assign_mfma_frac": round(flops / (assign_ms * 1e-3) / 1e12 / FP32_MFMA_PEAK_TFLOPS, 4),
+           "update_ms": round(update_ms, 5),
+           "lloyd_step_ms": round(assign_ms + update_ms, 5),
+           "mean_sq_distance": round(float(dist.double().mean()), 6),
+           "dictionary_bytes": K * D * 4 + M, "texture_bytes": M * D * 4,
+           "lookup_ms_p10_p50_p90": q_dict, "plain_lookup_ms_p10_p50_p90": q_plain,
+           "lookup_lookups_per_s": round(gb.count / (q_dict[1] * 1e-3), 1),
+           "lookup_max_abs_diff_vs_plain": float(diff.max()),
+           "lookup_psnr_db_vs_plain": round(10 * np.log10(1.0 / max(mse, 1e-30)), 2),
+           "note": "FP32 entries, 1-byte entry numbers; the assignment is an M x K x D contraction "
+                   "on v_mfma_f32_16x16x4_f32 (peak %.1f TFLOP/s)" % FP32_MFMA_PEAK_TFLOPS}
+    del X, cb, ws, dtex, ptex
+    return res
+
+
 def calibrate_copy():
     import torch
     n = 1 << 28  # 1 GiB of float32
@@ -287,6 +395,8 @@ def main():
             del chain
         if args.profile_shadow and gb.pos is not None:
             run_shadow(rt, w, gb, args.profile_shadow, timed=False)
+        if args.profile_dictionary:
+            run_dictionary(rt, w, gb, tex32, args.profile_dictionary, timed=False)
         torch.cuda.synchronize()
         print(json.dumps({"profile_steps": args.profile_steps, "workload": w.name}), flush=True)
         return
@@ -510,6 +620,11 @@ def main():
     if not args.no_shadow and gb.pos is not None:
         shadow = run_shadow(rt, w, gb, 5, timed=True)
 
+    # ---- bucket dictionary: Lloyd steps and the two-level lookup ------------
+    dictionary = None
+    if not args.no_dictionary:
+        dictionary = run_dictionary(rt, w, gb, tex32, 3, timed=True)
+
     # ---- the FP64 oracle on a bounded sample (CPU baseline and error) -------
     cpu = None
     errors = None
@@ -577,6 +692,7 @@ def main():
         "bake": bake,
         "mip": mip,
         "shadow": shadow,
+        "dictionary": dictionary,
         "errors": errors,
         "unique_texels_touched": uniq_texels,
         "source_hash": source_hash(),
