@@ -287,8 +287,17 @@ __global__ __launch_bounds__(256) void k_vq_piece_sum(const float* __restrict__ 
     const uint32_t m0 = start + (q - pstart[k]) * VQ_PIECE;
     const uint32_t m1 = std::min<uint32_t>(m0 + VQ_PIECE, end);
     for (int d = threadIdx.x; d < D; d += 256) {
+        // eight rows' loads in flight at a time; the sum still runs in order
         float acc = 0.f;
-        for (uint32_t m = m0; m < m1; m++) acc += X[(int64_t)sorted[m] * D + d];
+        uint32_t m = m0;
+        for (; m + 8 <= m1; m += 8) {
+            float v[8];
+#pragma unroll
+            for (int j = 0; j < 8; j++) v[j] = X[(int64_t)sorted[m + j] * D + d];
+#pragma unroll
+            for (int j = 0; j < 8; j++) acc += v[j];
+        }
+        for (; m < m1; m++) acc += X[(int64_t)sorted[m] * D + d];
         psum[(int64_t)q * D + d] = acc;
     }
 }
