@@ -302,7 +302,8 @@ __global__ __launch_bounds__(256) void k_vq_piece_sum(const float* __restrict__ 
     }
 }
 
-// one workgroup per entry: its pieces in order, then the mean
+// one workgroup per (entry, 256 columns): the entry's pieces in order, then
+// the mean; eight pieces' loads in flight at a time
 __global__ __launch_bounds__(256) void k_vq_combine(int64_t M, int D, int K, int64_t chunks,
                                                     const uint32_t* __restrict__ offs,
                                                     const uint32_t* __restrict__ pstart,
@@ -311,17 +312,25 @@ __global__ __launch_bounds__(256) void k_vq_combine(int64_t M, int D, int K, int
                                                     float* __restrict__ Cb,
                                                     int32_t* __restrict__ counts) {
     const int k = blockIdx.x;
+    const int d = blockIdx.y * 256 + threadIdx.x;
     const uint32_t start = offs[(int64_t)k * chunks];
     const uint32_t end = k + 1 < K ? offs[(int64_t)(k + 1) * chunks] : (uint32_t)M;
     const uint32_t cnt = end - start;
-    if (threadIdx.x == 0 && counts) counts[k] = (int32_t)cnt;
-    if (cnt == 0) return;
-    const float inv = 1.0f / (float)cnt;
-    for (int d = threadIdx.x; d < D; d += 256) {
-        float acc = 0.f;
-        for (uint32_t p = 0; p < ptab[k]; p++) acc += psum[(int64_t)(pstart[k] + p) * D + d];
-        Cb[(int64_t)k * D + d] = acc * inv;
+    if (blockIdx.y == 0 && threadIdx.x == 0 && counts) counts[k] = (int32_t)cnt;
+    if (cnt == 0 || d >= D) return;
+    const float* src = psum + (int64_t)pstart[k] * D + d;
+    const uint32_t np = ptab[k];
+    float acc = 0.f;
+    uint32_t p = 0;
+    for (; p + 8 <= np; p += 8) {
+        float v[8];
+#pragma unroll
+        for (int j = 0; j < 8; j++) v[j] = src[(int64_t)(p + j) * D];
+#pragma unroll
+        for (int j = 0; j < 8; j++) acc += v[j];
     }
+    for (; p < np; p++) acc += src[(int64_t)p * D];
+    Cb[(int64_t)k * D + d] = acc * (1.0f / (float)cnt);
 }
 
 static size_t a256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -383,7 +392,7 @@ hipError_t launch_vq_update(const float* x, const int32_t* assign, float* codebo
                        (const uint32_t*)ptab, (const uint32_t*)sorted, psum);
     prof_end(K_VQ_PIECES, s);
     prof_begin(K_VQ_COMBINE, s);
-    hipLaunchKernelGGL(k_vq_combine, dim3((uint32_t)p.K), dim3(256), 0, s, p.M, p.D, p.K,
+    hipLaunchKernelGGL(k_vq_combine, dim3((uint32_t)p.K, (uint32_t)((p.D + 255) / 256)), dim3(256), 0, s, p.M, p.D, p.K,
                        p.chunks, (const uint32_t*)offs, (const uint32_t*)pstart,
                        (const uint32_t*)ptab, (const float*)psum, codebook, counts);
     prof_end(K_VQ_COMBINE, s);
