@@ -90,9 +90,10 @@ enum {
                                 UV: four buckets around frac(u)W - 1/2, wrapping   */
 };
 
-/* Limits: 1 <= W, H <= 65536; 1 <= n <= 32; 1 <= C <= 4.  The backward
- * additionally needs W*H*n*n <= 2^32 (its sort key), and the number of
- * records (N, or 4N in the bilinear-bucket mode) below 2^31. */
+/* Limits: 1 <= W, H <= 65536; 1 <= n <= 64; 1 <= C <= 4.  The backward
+ * additionally needs W*H*n*n <= 2^32 (its sort key), n*n*C <= 4096 (its
+ * bucket tiles in LDS: n = 64 with one channel, n = 32 with four), and the
+ * number of records (N, or 4N in the bilinear-bucket mode) below 2^31. */
 
 typedef struct {
     int32_t buckets_w;      /* W: bucket-matrix width  (paper's w, Sec. 2)        */
@@ -231,7 +232,8 @@ size_t rt_lookup_bwd_workspace(const rt_texture* tex, int64_t count, uint32_t fl
  * workspace: device memory of at least rt_lookup_bwd_workspace() bytes,
  * 256-byte aligned, owned by the caller, not used by concurrent calls.
  * Errors: RT_ERR_INVALID_ARG, RT_ERR_WORKSPACE_TOO_SMALL, RT_ERR_UNSUPPORTED
- * (sort key or record count beyond the limits above, an RT_FMT_BIT1 texture). */
+ * (sort key, bucket size or record count beyond the limits above, an
+ * RT_FMT_BIT1 texture, a dictionary). */
 rt_status rt_lookup_bwd(const rt_texture* tex, const rt_fragments* frags,
                         const float* grad_out, float* grad_tex, float* grad_view,
                         float* grad_uv, void* workspace, size_t workspace_bytes,
@@ -291,7 +293,7 @@ rt_status rt_lookup_fwd_lod(const rt_texture* const* levels, int32_t nlevels,
  * the reflection vector of Eq. (4b) and inc[y][x] the incidence of Eq. (2c)
  * (its mirror image about N, the view direction the lookup maps onto that
  * sample).  inc, refl: DEVICE float [n][n][3], 4-byte aligned, either NULL.
- * Errors: RT_ERR_INVALID_ARG (n < 1, alignment), RT_ERR_UNSUPPORTED (n > 32),
+ * Errors: RT_ERR_INVALID_ARG (n < 1, alignment), RT_ERR_UNSUPPORTED (n > 64),
  * RT_ERR_NO_DEVICE. */
 rt_status rt_bake_directions(int32_t n, float* inc, float* refl, void* stream);
 
@@ -316,7 +318,7 @@ typedef struct {
  * every element OVERWRITTEN.
  * Errors: RT_ERR_INVALID_ARG (sizes, NULL pointers, alignment, a zero or
  * non-finite axis, negative or non-finite sharpness, non-finite amplitude or
- * ambient), RT_ERR_UNSUPPORTED (W or H > 65536, n > 32, nlobes > 16),
+ * ambient), RT_ERR_UNSUPPORTED (W or H > 65536, n > 64, nlobes > 16),
  * RT_ERR_NO_DEVICE, RT_ERR_HIP (launch). */
 rt_status rt_bake_environment(int32_t W, int32_t H, int32_t n, int32_t C, const float* frames,
                               const rt_env_lobe* lobes, int32_t nlobes, const float* ambient,
@@ -375,7 +377,7 @@ rt_status rt_lookup_light(const rt_texture* tex, const rt_fragments* frags, cons
  * [H][W][ceil(n*n/32)] in the layout of RT_FMT_BIT1, 4-byte aligned, every
  * word OVERWRITTEN.
  * Errors: RT_ERR_INVALID_ARG (sizes, NULL pointers, alignment, non-finite
- * balls, radius <= 0), RT_ERR_UNSUPPORTED (W or H > 65536, n > 32,
+ * balls, radius <= 0), RT_ERR_UNSUPPORTED (W or H > 65536, n > 64,
  * nballs > 64), RT_ERR_NO_DEVICE, RT_ERR_HIP (launch). */
 rt_status rt_bake_shadow(int32_t W, int32_t H, int32_t n, const float* origins,
                          const float* frames, const float* balls, int32_t nballs,

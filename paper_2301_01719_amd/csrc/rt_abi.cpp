@@ -208,7 +208,7 @@ rt_status rt_create_texture(const rt_texture_desc* d, void* stream, rt_texture**
     if (d->buckets_w > 65536 || d->buckets_h > 65536)
         return fail(RT_ERR_UNSUPPORTED, "bucket matrix %d x %d exceeds 65536 per side", d->buckets_w, d->buckets_h);
     if (d->n < 1) return fail(RT_ERR_INVALID_ARG, "angular resolution n = %d must be >= 1", d->n);
-    if (d->n > 32) return fail(RT_ERR_UNSUPPORTED, "angular resolution n = %d exceeds 32", d->n);
+    if (d->n > 64) return fail(RT_ERR_UNSUPPORTED, "angular resolution n = %d exceeds 64", d->n);
     if (d->channels < 1 || d->channels > 4)
         return fail(RT_ERR_INVALID_ARG, "channels = %d must be in 1..4", d->channels);
     if (d->format < RT_FMT_F32 || d->format > RT_FMT_BIT1)
@@ -274,7 +274,7 @@ rt_status rt_create_dictionary_texture(const rt_dictionary_desc* d, rt_texture**
     if (d->buckets_w > 65536 || d->buckets_h > 65536)
         return fail(RT_ERR_UNSUPPORTED, "bucket matrix %d x %d exceeds 65536 per side", d->buckets_w, d->buckets_h);
     if (d->n < 1) return fail(RT_ERR_INVALID_ARG, "angular resolution n = %d must be >= 1", d->n);
-    if (d->n > 32) return fail(RT_ERR_UNSUPPORTED, "angular resolution n = %d exceeds 32", d->n);
+    if (d->n > 64) return fail(RT_ERR_UNSUPPORTED, "angular resolution n = %d exceeds 64", d->n);
     if (d->channels < 1 || d->channels > 4)
         return fail(RT_ERR_INVALID_ARG, "channels = %d must be in 1..4", d->channels);
     if (d->format != RT_FMT_F32 && d->format != RT_FMT_BF16)
@@ -406,7 +406,7 @@ rt_status rt_lookup_bwd(const rt_texture* t, const rt_fragments* f, const float*
     if (grad_uv && !aligned(grad_uv, 8)) return fail(RT_ERR_INVALID_ARG, "grad_uv must be 8-byte aligned");
     rt::BwdPlan plan;
     if (!rt::plan_backward(t->view.W, t->view.H, t->view.n, C, f->count, (int)flags, &plan))
-        return fail(RT_ERR_UNSUPPORTED, "sort key (W*H*n*n) or record count beyond the backward's limits");
+        return fail(RT_ERR_UNSUPPORTED, "sort key (W*H*n*n), bucket size (n*n*C <= 4096) or record count beyond the backward's limits");
     if (!grad_tex && !grad_view && !grad_uv) return ok();  // nothing requested
     if (grad_tex) {
         if (!ws) return fail(RT_ERR_INVALID_ARG, "workspace is NULL");
@@ -446,7 +446,7 @@ rt_status rt_debug_indices(const rt_texture* t, const rt_fragments* f, int32_t* 
 rt_status rt_bake_directions(int32_t n, float* inc, float* refl, void* stream) {
     RT_GUARD_BEGIN
     if (n < 1) return fail(RT_ERR_INVALID_ARG, "angular resolution n = %d must be >= 1", n);
-    if (n > 32) return fail(RT_ERR_UNSUPPORTED, "angular resolution n = %d exceeds 32", n);
+    if (n > 64) return fail(RT_ERR_UNSUPPORTED, "angular resolution n = %d exceeds 64", n);
     if ((inc && !aligned(inc, 4)) || (refl && !aligned(refl, 4)))
         return fail(RT_ERR_INVALID_ARG, "inc and refl must be 4-byte aligned");
     if (!inc && !refl) return ok();
@@ -467,7 +467,7 @@ rt_status rt_bake_environment(int32_t W, int32_t H, int32_t n, int32_t C, const 
     if (W > 65536 || H > 65536)
         return fail(RT_ERR_UNSUPPORTED, "bucket matrix %d x %d exceeds 65536 per side", W, H);
     if (n < 1) return fail(RT_ERR_INVALID_ARG, "angular resolution n = %d must be >= 1", n);
-    if (n > 32) return fail(RT_ERR_UNSUPPORTED, "angular resolution n = %d exceeds 32", n);
+    if (n > 64) return fail(RT_ERR_UNSUPPORTED, "angular resolution n = %d exceeds 64", n);
     if (C < 1 || C > 4) return fail(RT_ERR_INVALID_ARG, "channels = %d must be in 1..4", C);
     if (nlobes < 0) return fail(RT_ERR_INVALID_ARG, "nlobes = %d < 0", nlobes);
     if (nlobes > rt::MAX_LOBES)
@@ -644,7 +644,7 @@ rt_status rt_bake_shadow(int32_t W, int32_t H, int32_t n, const float* origins,
     if (W > 65536 || H > 65536)
         return fail(RT_ERR_UNSUPPORTED, "bucket matrix %d x %d exceeds 65536 per side", W, H);
     if (n < 1) return fail(RT_ERR_INVALID_ARG, "angular resolution n = %d must be >= 1", n);
-    if (n > 32) return fail(RT_ERR_UNSUPPORTED, "angular resolution n = %d exceeds 32", n);
+    if (n > 64) return fail(RT_ERR_UNSUPPORTED, "angular resolution n = %d exceeds 64", n);
     if (nballs < 0) return fail(RT_ERR_INVALID_ARG, "nballs = %d < 0", nballs);
     if (nballs > rt::MAX_OCCLUDERS)
         return fail(RT_ERR_UNSUPPORTED, "nballs = %d exceeds %d", nballs, rt::MAX_OCCLUDERS);

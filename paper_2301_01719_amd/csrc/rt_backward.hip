@@ -894,6 +894,8 @@ static int ceil_log2(uint64_t x) {
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 bool plan_backward(int W, int H, int n, int C, int64_t N, int mode, BwdPlan* p) {
+    // the accumulation holds four bucket tiles per workgroup in LDS (64 KiB)
+    if ((int64_t)n * n * C > 4096) return false;
     const int64_t nb = (int64_t)W * H;
     const int bucket_bits = ceil_log2((uint64_t)nb);
     const int cell_bits = ceil_log2((uint64_t)n * n);

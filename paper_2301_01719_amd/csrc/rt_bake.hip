@@ -40,12 +40,17 @@ __global__ __launch_bounds__(256) void k_bake_directions(int n, float* __restric
 // (bucket, sample) pair of its texel incrementally, with no division per
 // texel.  Each lobe arrives as (lambda log2e mu, -lambda log2e), so its value
 // is the hardware exp2 of one fused dot product.
+// LDS of the bake kernels: 3 n n floats of sample directions, then (16-byte
+// aligned) the kernel's float4 tables.
+__host__ __device__ __forceinline__ int bake_dir_floats(int n) { return (3 * n * n + 3) & ~3; }
+
 template <int C>
 __global__ __launch_bounds__(256) void k_bake_env(int64_t nbuckets, int n,
                                                   const float* __restrict__ frames, EnvParams env,
                                                   float* __restrict__ texels) {
-    __shared__ float Rt[3 * 32 * 32];
-    __shared__ float4 lob[2 * MAX_LOBES];
+    extern __shared__ float smem[];
+    float* Rt = smem;
+    float4* lob = (float4*)(smem + bake_dir_floats(n));  // 2 MAX_LOBES entries
     const int nn = n * n;
     const int nl = env.lobes;
     if (threadIdx.x < 2 * nl) {
@@ -152,9 +157,10 @@ __global__ __launch_bounds__(256) void k_bake_shadow(int64_t nbuckets, int n,
                                                      const float* __restrict__ origins,
                                                      const float* __restrict__ frames,
                                                      Occluders occ, uint32_t* __restrict__ words) {
-    __shared__ float It[3 * 32 * 32];
-    __shared__ float4 ball[MAX_OCCLUDERS];
-    __shared__ float4 rel[4][MAX_OCCLUDERS];  // per wave: (e, r^2) of each ball
+    extern __shared__ float smem[];
+    float* It = smem;
+    float4* ball = (float4*)(smem + bake_dir_floats(n));  // MAX_OCCLUDERS entries
+    float4* relw = ball + MAX_OCCLUDERS;                   // per wave: (e, r^2) of each ball
     const int nn = n * n;
     if (threadIdx.x < occ.count)
         ball[threadIdx.x] = make_float4(occ.ball[threadIdx.x][0], occ.ball[threadIdx.x][1],
@@ -187,7 +193,7 @@ __global__ __launch_bounds__(256) void k_bake_shadow(int64_t nbuckets, int n,
             const float4 bl = ball[lane];
             const float ex = bl.x - ox, ey = bl.y - oy, ez = bl.z - oz;
             const float r2 = bl.w * bl.w;
-            rel[wv][lane] = make_float4(ex, ey, ez, r2);
+            relw[wv * MAX_OCCLUDERS + lane] = make_float4(ex, ey, ez, r2);
             inside = ex * ex + ey * ey + ez * ez <= r2;
         }
         const bool blocked = __ballot(inside) != 0;
@@ -206,7 +212,7 @@ __global__ __launch_bounds__(256) void k_bake_shadow(int64_t nbuckets, int n,
                 dz *= inv;
                 bool hit = false;
                 for (int q = 0; q < nballs; q++) {
-                    const float4 e = rel[wv][q];
+                    const float4 e = relw[wv * MAX_OCCLUDERS + q];
                     const float ts = dx * e.x + dy * e.y + dz * e.z;
                     const float hx = e.x - ts * dx, hy = e.y - ts * dy, hz = e.z - ts * dz;
                     hit |= ts > 0.f && hx * hx + hy * hy + hz * hz <= e.w;
@@ -228,7 +234,8 @@ hipError_t launch_bake_shadow(int W, int H, int n, const float* origins, const f
     if (nb == 0) return hipSuccess;
     const uint32_t blocks = (uint32_t)std::min<int64_t>((nb + 3) / 4, 256 * 16);
     prof_begin(K_BAKE_SHADOW, s);
-    hipLaunchKernelGGL(k_bake_shadow, dim3(blocks), dim3(256), 0, s, nb, n, origins, frames, occ,
+    const size_t shm = (size_t)(bake_dir_floats(n) + 4 * MAX_OCCLUDERS * 5) * 4;
+    hipLaunchKernelGGL(k_bake_shadow, dim3(blocks), dim3(256), shm, s, nb, n, origins, frames, occ,
                        words);
     prof_end(K_BAKE_SHADOW, s);
     return hipGetLastError();
@@ -249,12 +256,13 @@ hipError_t launch_bake_env(int W, int H, int n, int C, const float* frames, cons
     // 16 workgroups per CU: each lane then covers many texels, so the per-
     // workgroup table of sample directions is formed once for all of them
     const uint32_t blocks = (uint32_t)std::min<int64_t>((total + 255) / 256, 256 * 16);
+    const size_t shm = (size_t)(bake_dir_floats(n) + 4 * 2 * MAX_LOBES) * 4;
     prof_begin(K_BAKE_ENV, s);
     switch (C) {
-    case 1: hipLaunchKernelGGL((k_bake_env<1>), dim3(blocks), dim3(256), 0, s, (int64_t)W * H, n, frames, env, texels); break;
-    case 2: hipLaunchKernelGGL((k_bake_env<2>), dim3(blocks), dim3(256), 0, s, (int64_t)W * H, n, frames, env, texels); break;
-    case 3: hipLaunchKernelGGL((k_bake_env<3>), dim3(blocks), dim3(256), 0, s, (int64_t)W * H, n, frames, env, texels); break;
-    default: hipLaunchKernelGGL((k_bake_env<4>), dim3(blocks), dim3(256), 0, s, (int64_t)W * H, n, frames, env, texels); break;
+    case 1: hipLaunchKernelGGL((k_bake_env<1>), dim3(blocks), dim3(256), shm, s, (int64_t)W * H, n, frames, env, texels); break;
+    case 2: hipLaunchKernelGGL((k_bake_env<2>), dim3(blocks), dim3(256), shm, s, (int64_t)W * H, n, frames, env, texels); break;
+    case 3: hipLaunchKernelGGL((k_bake_env<3>), dim3(blocks), dim3(256), shm, s, (int64_t)W * H, n, frames, env, texels); break;
+    default: hipLaunchKernelGGL((k_bake_env<4>), dim3(blocks), dim3(256), shm, s, (int64_t)W * H, n, frames, env, texels); break;
     }
     prof_end(K_BAKE_ENV, s);
     return hipGetLastError();

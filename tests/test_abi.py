@@ -66,7 +66,7 @@ def _desc(rt, **kw):
     (dict(buckets_h=-3), 1, "bucket matrix"),
     (dict(buckets_w=70000), 2, "exceeds"),
     (dict(n=0), 1, "angular resolution"),
-    (dict(n=33), 2, "exceeds 32"),
+    (dict(n=65), 2, "exceeds 64"),
     (dict(channels=5), 1, "channels"),
     (dict(channels=0), 1, "channels"),
     (dict(format=7), 1, "format"),
@@ -200,7 +200,7 @@ def test_bake_validation(rt):
 
     for kw, status, text in (
             (dict(W=0), 1, "bucket matrix"), (dict(H=70000), 2, "exceeds"),
-            (dict(n=0), 1, "angular resolution"), (dict(n=33), 2, "exceeds 32"),
+            (dict(n=0), 1, "angular resolution"), (dict(n=65), 2, "exceeds 64"),
             (dict(C=0), 1, "channels"), (dict(C=5), 1, "channels"),
             (dict(nlobes=17), 2, "exceeds 16"), (dict(nlobes=-1), 1, "< 0"),
             (dict(ambient=None), 1, "ambient"), (dict(texels=None), 1, "texels is NULL"),
@@ -213,7 +213,7 @@ def test_bake_validation(rt):
         assert call(**kw) == status, kw
         assert text in L.rt_last_error().decode(), (kw, L.rt_last_error())
     assert L.rt_bake_directions(0, 0x1000, 0x2000, None) == 1
-    assert L.rt_bake_directions(33, 0x1000, 0x2000, None) == 2
+    assert L.rt_bake_directions(65, 0x1000, 0x2000, None) == 2
     assert L.rt_bake_directions(8, 0x1002, None, None) == 1
     assert L.rt_bake_directions(8, None, None, None) == 0  # nothing asked, nothing launched
     if not torch.cuda.is_available():
@@ -262,7 +262,7 @@ def test_shadow_bake_validation(rt):
 
     for kw, status, text in (
             (dict(W=0), 1, "bucket matrix"), (dict(H=70000), 2, "exceeds"),
-            (dict(n=0), 1, "angular resolution"), (dict(n=33), 2, "exceeds 32"),
+            (dict(n=0), 1, "angular resolution"), (dict(n=65), 2, "exceeds 64"),
             (dict(nballs=65), 2, "exceeds 64"), (dict(nballs=-1), 1, "< 0"),
             (dict(balls=(), nballs=2), 1, "balls is NULL"),
             (dict(origins=None), 1, "origins"), (dict(words=None), 1, "words"),
@@ -349,7 +349,7 @@ def test_dictionary_and_encoder_validation(rt):
         d.update(kw)
         return rt.DictionaryDesc(**d)
     for kw, status, text in ((dict(buckets_w=0), 1, "bucket matrix"),
-                             (dict(n=33), 2, "exceeds 32"), (dict(channels=5), 1, "channels"),
+                             (dict(n=65), 2, "exceeds 64"), (dict(channels=5), 1, "channels"),
                              (dict(format=2), 2, "F32 or BF16"), (dict(format=3), 2, "F32 or BF16"),
                              (dict(index_bytes=3), 1, "index_bytes"), (dict(entries=0), 1, "entries"),
                              (dict(entries=257), 1, "do not fit"),

@@ -57,7 +57,7 @@ def _frames(W, H, seed):
 AMB = np.array([0.05, -0.1, 0.2, 0.3], np.float32)
 
 
-@pytest.mark.parametrize("n", [1, 2, 5, 8, 16, 31, 32])
+@pytest.mark.parametrize("n", [1, 2, 5, 8, 16, 31, 32, 47, 64])
 def test_bake_directions(rt, n):
     inc, refl = rt.bake_directions(n)
     torch.cuda.synchronize()
@@ -73,6 +73,8 @@ def test_bake_directions(rt, n):
     (2, 2, 32, 2, 0, False),
     (33, 17, 16, 4, 8, True),
     (1, 1, 31, 4, 5, True),
+    (2, 3, 64, 4, 6, True),
+    (3, 1, 45, 2, 3, False),
 ])
 def test_bake_environment_vs_oracle(rt, W, H, n, C, K, with_frames):
     lobes = _lobes(K, seed=W * 100 + n)

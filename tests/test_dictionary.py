@@ -69,7 +69,8 @@ def _index(g, H, W, K, dtype):
 
 @pytest.mark.parametrize("W,H,n,C,K,idx_t", [(5, 3, 4, 3, 7, "u8"), (16, 9, 8, 4, 200, "u8"),
                                              (7, 6, 16, 4, 1000, "u16"), (3, 2, 5, 1, 6, "i32"),
-                                             (33, 17, 16, 2, 256, "u8"), (1, 1, 32, 4, 3, "u16")])
+                                             (33, 17, 16, 2, 256, "u8"), (1, 1, 32, 4, 3, "u16"),
+                                             (3, 2, 64, 4, 5, "u8")])
 @pytest.mark.parametrize("fmt", ["f32", "bf16"])
 @pytest.mark.parametrize("with_gains", [False, True])
 def test_dictionary_lookup_vs_oracle(rt, W, H, n, C, K, idx_t, fmt, with_gains):

@@ -82,7 +82,8 @@ def test_c1_full_forward_and_indices(rt):
 
 @pytest.mark.parametrize("W,H,n,C,N", [
     (5, 3, 3, 3, 1), (5, 3, 3, 3, 255), (7, 2, 8, 1, 257), (3, 9, 16, 2, 1000),
-    (1, 1, 2, 4, 513), (64, 32, 8, 4, 4097), (2, 2, 1, 4, 300), (4, 4, 32, 3, 777)])
+    (1, 1, 2, 4, 513), (64, 32, 8, 4, 4097), (2, 2, 1, 4, 300), (4, 4, 32, 3, 777),
+    (3, 2, 64, 4, 1500), (2, 3, 48, 3, 999)])
 @pytest.mark.parametrize("mode", ["nearest", "bilinear"])
 def test_forward_ragged_shapes(rt, W, H, n, C, N, mode):
     tex_c, gb_c = _rand_case(W * 1000 + n * 10 + C + N, W, H, n, C, N)
@@ -193,7 +194,8 @@ def test_bounds_fuzz(rt):
 # quantiser and the BF16 / FP8 forwards
 # ---------------------------------------------------------------------------
 
-@pytest.mark.parametrize("W,H,n,C", [(64, 64, 8, 4), (16, 8, 16, 4), (7, 5, 8, 3), (5, 3, 3, 1)])
+@pytest.mark.parametrize("W,H,n,C", [(64, 64, 8, 4), (16, 8, 16, 4), (7, 5, 8, 3), (5, 3, 3, 1),
+                                     (3, 2, 64, 4), (2, 2, 40, 3)])
 def test_quantizer_bit_exact(rt, W, H, n, C):
     g = torch.Generator().manual_seed(W * H + n + C)
     t = torch.randn((H, W, n, n, C), generator=g) * torch.exp2(
@@ -307,7 +309,8 @@ def _smooth_mask(uv, tbn, view, W, H, n, mode):
 
 
 @pytest.mark.parametrize("W,H,n,C,N", [(16, 16, 8, 3, 30000), (5, 3, 3, 1, 777),
-                                       (64, 64, 16, 4, 50000), (2, 2, 2, 2, 4097)])
+                                       (64, 64, 16, 4, 50000), (2, 2, 2, 2, 4097),
+                                       (6, 5, 64, 1, 20000), (3, 3, 48, 1, 5000)])
 @pytest.mark.parametrize("mode", ["nearest", "bilinear"])
 def test_backward_vs_oracle(rt, W, H, n, C, N, mode):
     (gt, gv, gu), ref, (uv, tbn, view), go = _bwd_case(rt, W + N + n, W, H, n, C, N, mode)
@@ -492,3 +495,16 @@ def test_bilinear_bucket_weights_keep_their_precision_on_wide_matrices(rt, W, H)
                             view.numpy(), mode=oracle.MODE_BILINEAR)
     err = check_fwd(host(out), ref)
     print(f"W={W} H={H}: max |err| {err:.3g}")
+
+
+def test_backward_refuses_buckets_beyond_its_tiles(rt):
+    # n n C above 4096 (n = 64 with two channels) is refused on the host: the
+    # accumulation keeps four bucket tiles per workgroup in LDS
+    W, H, n, C, N = 2, 2, 64, 2, 100
+    tex_c, gb_c = _rand_case(5, W, H, n, C, N)
+    tex_d, gb_d = _to_dev(tex_c, gb_c)
+    tex = rt.Texture(tex_d, W, H, n, C)
+    assert rt.LIB.rt_lookup_bwd_workspace(tex.handle, N, 0) == 0
+    with pytest.raises(rt.RadtexError) as e:
+        rt.lookup_bwd(tex, gb_d.uv, gb_d.tbn, gb_d.view, torch.ones((N, C), device=DEV))
+    assert e.value.status == 2

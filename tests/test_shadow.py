@@ -92,7 +92,8 @@ def _bits_of(words, n):
 # the 1-bit packer
 # ---------------------------------------------------------------------------
 
-@pytest.mark.parametrize("W,H,n", [(1, 1, 1), (3, 2, 3), (5, 3, 5), (7, 4, 7), (9, 5, 8),
+@pytest.mark.parametrize("W,H,n", [(1, 1, 1), (3, 2, 3), (5, 3, 5), (7, 4, 7), (9, 5, 8), (3, 2, 64),
+                                   (2, 3, 45),
                                    (33, 17, 16), (3, 3, 24), (2, 5, 31), (4, 3, 32),
                                    (129, 65, 16), (1, 1, 8)])
 def test_pack_bits_bit_exact(rt, W, H, n):
@@ -129,7 +130,7 @@ def _bit_texture(rt, W, H, n, seed, p=0.5):
     return rt.Texture(words, W, H, n, 1, "bit1"), oracle.Tex(ow, W, H, n, 1, oracle.FMT_BIT1)
 
 
-@pytest.mark.parametrize("W,H,n,N", [(5, 3, 3, 257), (7, 2, 8, 1000), (4, 4, 16, 3000),
+@pytest.mark.parametrize("W,H,n,N", [(5, 3, 3, 257), (7, 2, 8, 1000), (4, 4, 16, 3000), (2, 2, 64, 900),
                                      (3, 5, 31, 777), (2, 2, 32, 513), (1, 1, 1, 100)])
 @pytest.mark.parametrize("mode", ["nearest", "bilinear"])
 def test_view_lookup_of_a_bit_texture(rt, W, H, n, N, mode):
@@ -270,6 +271,7 @@ def test_light_lookup_empty_and_tiled(rt):
 # ---------------------------------------------------------------------------
 
 @pytest.mark.parametrize("W,H,n,K,with_frames", [(5, 3, 8, 3, False), (7, 2, 5, 16, True),
+                                                 (2, 2, 64, 6, True), (3, 2, 50, 4, False),
                                                  (3, 4, 1, 1, True), (2, 2, 32, 0, False),
                                                  (33, 17, 16, 8, True), (1, 1, 31, 5, True),
                                                  (9, 9, 12, 64, False)])
