@@ -44,27 +44,26 @@ BAKE_AMBIENT = (0.05, 0.05, 0.05, 0.0)
 METRIC = "lookups/s + % HBM peak, fwd & bwd; FP32 vs BF16/FP8 texture at stated error"
 HBM_PEAK_GBS = 8000.0
 FP32_MFMA_PEAK_TFLOPS = 157.3
-KERNEL_SOURCES = ["rt_device.hpp", "rt_lookup.hip", "rt_quantize.hip", "rt_backward.hip",
-                  "rt_bake.hip", "rt_mip.hip", "rt_dictionary.hip"]
-
-# the shadow measurement (Sec. 5, Shadowing): balls over the plane tile, a sun
-# disc and a spherical lamp
-SHADOW_BALLS = 16
-
-# the bucket-dictionary measurement: the matrix as repetitive buckets (each a
-# noisy copy of one of DICT_PROTOTYPES buckets of the smooth texture), encoded
-# into DICT_ENTRIES entries by DICT_ITERATIONS Lloyd steps
-DICT_PROTOTYPES = 64
-DICT_ENTRIES = 256
-DICT_NOISE = 0.01
-DICT_ITERATIONS = 3
-SHADOW_CASES = (("sun", 1, "nearest"), ("sun", 16, "nearest"), ("sun", 64, "nearest"),
-                ("lamp", 16, "bilinear"))
+# Source file of each kernel whose counters are committed under profiles/: a
+# summary counts as current while its kernel's file and the shared headers
+# (device helpers, launch constants) are unchanged.
+KERNEL_SOURCES = {
+    "k_lookup_fwd": "rt_lookup.hip", "k_lookup_lod": "rt_lookup.hip",
+    "k_lookup_light": "rt_lookup.hip", "k_quant_bf16": "rt_quantize.hip",
+    "k_quant_fp8": "rt_quantize.hip", "k_pack_bits_flat": "rt_quantize.hip",
+    "k_bwd_fragment": "rt_backward.hip", "k_segacc": "rt_backward.hip",
+    "k_segacc_big": "rt_backward.hip", "k_bake_env": "rt_bake.hip",
+    "k_bake_shadow": "rt_bake.hip", "k_build_mip": "rt_mip.hip",
+    "k_vq_assign": "rt_dictionary.hip",
+}
+SHARED_SOURCES = ["rt_device.hpp", "rt_kernels.hpp"]
 
 
-def source_hash() -> str:
+def source_hash(kernel: str) -> str:
+    """Hash of the sources that make up `kernel` (its file and the shared
+    headers)."""
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in SHARED_SOURCES + [KERNEL_SOURCES[kernel]]:
         with open(os.path.join(ROOT, "paper_2301_01719_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -81,7 +80,7 @@ def pmc_traffic(kernel: str, workload: str):
         if ":" in line and not line.startswith("#"):
             k, v = line.split(":", 1)
             vals[k.strip()] = v.strip()
-    if vals.get("source_hash") != source_hash():
+    if kernel not in KERNEL_SOURCES or vals.get("source_hash") != source_hash(kernel):
         return None
     try:
         return float(vals["traffic_bytes_per_launch"])
@@ -706,7 +705,7 @@ def main():
         "dictionary": dictionary,
         "errors": errors,
         "unique_texels_touched": uniq_texels,
-        "source_hash": source_hash(),
+        "source_hash": {k: source_hash(k) for k in sorted(KERNEL_SOURCES)},
     }
     print(json.dumps(line), flush=True)
 
