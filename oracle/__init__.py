@@ -59,6 +59,9 @@ def _load():
     lib.orc_lod.argtypes = [P, i32, i32, i32]
     lib.orc_lod.restype = d
     lib.orc_lookup_lod.argtypes = [i64, P, P, P, P, i32, i32, i32, i32, i32, P, i32, P, P]
+    lib.orc_lookup_lod_bwd.argtypes = [i64, P, P, P, P, P, i32, i32, i32, i32, i32, P, i32, P,
+                                       P, P]
+    lib.orc_build_mip_adjoint.argtypes = [i32, i32, i32, i32, P, P]
     lib.orc_pack_bits.argtypes = [P, i64, i32, P]
     lib.orc_lookup_light.argtypes = [i64, P, P, P, i32, i32, P, i32, i32, i32, i32, i32, P, P,
                                      i32, P]
@@ -361,6 +364,40 @@ def lookup_lod(chain, uv, tbn, view, duv, W, H, n, C, mode=MODE_NEAREST):
     _load().orc_lookup_lod(N, _p(uv), _p(tbn), _p(view), _p(duv), int(W), int(H), int(n),
                            int(C), len(chain), _p(flat), int(mode), _p(out), _p(lam))
     return out, lam
+
+
+def lookup_lod_bwd(chain, uv, tbn, view, duv, g, W, H, n, C, mode=MODE_NEAREST):
+    """Backward of the trilinear lookup over the mip chain (list of float64
+    levels) for upstream g [N, C] float32: (list of per-level gradients,
+    grad_view [N, 3], grad_uv [N, 2]), all float64."""
+    uv, tbn, view = _frags(uv, tbn, view)
+    duv = _c(duv, np.float32).reshape(-1, 4)
+    g = _c(g, np.float32).reshape(-1, C)
+    N = uv.shape[0]
+    flat = np.ascontiguousarray(np.concatenate([np.asarray(c, np.float64).reshape(-1)
+                                                for c in chain]))
+    gchain = np.empty_like(flat)
+    gv = np.empty((N, 3), np.float64)
+    gu = np.empty((N, 2), np.float64)
+    _load().orc_lookup_lod_bwd(N, _p(uv), _p(tbn), _p(view), _p(duv), _p(g), int(W), int(H),
+                               int(n), int(C), len(chain), _p(flat), int(mode), _p(gchain), _p(gv),
+                               _p(gu))
+    out, off = [], 0
+    for c in chain:
+        k = np.asarray(c).size
+        out.append(gchain[off:off + k].reshape(np.asarray(c).shape))
+        off += k
+    return out, gv, gu
+
+
+def build_mip_adjoint(grad_dst, W, H, n, C, grad_src=None):
+    """Adds the adjoint of one chain level (level W x H -> the next) applied to
+    grad_dst into grad_src (zeros if None); returns grad_src (float64)."""
+    gd = _c(grad_dst, np.float64)
+    gs = np.zeros((H, W, n, n, C), np.float64) if grad_src is None else grad_src
+    assert gs.dtype == np.float64 and gs.flags.c_contiguous
+    _load().orc_build_mip_adjoint(int(W), int(H), int(n), int(C), _p(gd), _p(gs))
+    return gs
 
 
 # --- shadowing: 1-bit textures and the light-direction lookup -------------------

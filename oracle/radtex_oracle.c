@@ -740,14 +740,17 @@ static void view_gradient(const double M[9], const dirmap_t *d, int n, const dou
  *              evaluation's rounding error is measured); either may be NULL.
  * Taps that coincide (x1 = x0 at the clamp bound) each receive their own
  * weight, so the texel gets the sum. */
-void orc_lookup_bwd(int64_t N, const float *uv, const float *tbn, const float *view,
-                    const float *g, int W, int H, int n, int C, int fmt, const void *data,
-                    const float *scales, int mode, double *grad_tex, double *abs_tex,
-                    double *absg_tex, int bi0,
-                    int bj0, int bw, int bh, double *grad_view, double *grad_uv,
-                    double *scale_view, double *scale_uv)
+/* The body of the backward for one texture; wf (may be NULL: all 1) scales
+ * fragment f's upstream gradient by wf[f] (the level weight of a trilinear
+ * lookup). */
+static void lookup_bwd_core(int64_t N, const float *uv, const float *tbn, const float *view,
+                            const float *g, const double *wf, const tex_t *tp, int mode,
+                            double *grad_tex, double *abs_tex, double *absg_tex, int bi0,
+                            int bj0, int bw, int bh, double *grad_view, double *grad_uv,
+                            double *scale_view, double *scale_uv)
 {
-    tex_t t = {W, H, n, C, fmt, data, scales};
+    const tex_t t = *tp;
+    const int W = t.W, H = t.H, n = t.n, C = t.C;
     if (grad_view || grad_uv || scale_view || scale_uv) {
 #pragma omp parallel for schedule(static)
         for (int64_t f = 0; f < N; f++) {
@@ -757,7 +760,9 @@ void orc_lookup_bwd(int64_t N, const float *uv, const float *tbn, const float *v
             bucketfp_t bf;
             map_direction(M, V, n, &d);
             bucket_footprint(U[0], U[1], W, H, mode, &bf);
-            const float *gf = g + f * C;
+            double gf[4];
+            for (int c = 0; c < C; c++)
+                gf[c] = (wf ? wf[f] : 1.0) * (double)g[f * C + c];
             double gs[2] = {0.0, 0.0}, gsa[2] = {0.0, 0.0};
             double Lb[4] = {0, 0, 0, 0}; /* sum_c g_c * bilerp per footprint bucket */
             double La[4] = {0, 0, 0, 0}; /* the same with magnitudes */
@@ -823,7 +828,9 @@ void orc_lookup_bwd(int64_t N, const float *uv, const float *tbn, const float *v
             bucketfp_t bf;
             map_direction(M, V, n, &d);
             bucket_footprint(U[0], U[1], W, H, mode, &bf);
-            const float *gf = g + f * C;
+            double gf[4];
+            for (int c = 0; c < C; c++)
+                gf[c] = (wf ? wf[f] : 1.0) * (double)g[f * C + c];
             double wt[4] = {(1.0 - d.fx) * (1.0 - d.fy), d.fx * (1.0 - d.fy),
                             (1.0 - d.fx) * d.fy, d.fx * d.fy};
             int ty[4] = {d.y0, d.y0, d.y1, d.y1};
@@ -840,12 +847,24 @@ void orc_lookup_bwd(int64_t N, const float *uv, const float *tbn, const float *v
                         if (abs_tex)
                             abs_tex[base + c] += fabs(contrib);
                         if (absg_tex)
-                            absg_tex[base + c] += fabs((double)gf[c]);
+                            absg_tex[base + c] += fabs(gf[c]);
                     }
                 }
             }
         }
     }
+}
+
+void orc_lookup_bwd(int64_t N, const float *uv, const float *tbn, const float *view,
+                    const float *g, int W, int H, int n, int C, int fmt, const void *data,
+                    const float *scales, int mode, double *grad_tex, double *abs_tex,
+                    double *absg_tex, int bi0,
+                    int bj0, int bw, int bh, double *grad_view, double *grad_uv,
+                    double *scale_view, double *scale_uv)
+{
+    tex_t t = {W, H, n, C, fmt, data, scales};
+    lookup_bwd_core(N, uv, tbn, view, g, NULL, &t, mode, grad_tex, abs_tex, absg_tex, bi0, bj0,
+                    bw, bh, grad_view, grad_uv, scale_view, scale_uv);
 }
 
 /* ------------------------------------------------------------------------- */
@@ -1048,6 +1067,86 @@ void orc_lookup_lod(int64_t N, const float *uv, const float *tbn, const float *v
             out[f * C + c] = t > 0.0 ? (1.0 - t) * a[c] + t * b[c] : a[c];
     }
     free(lv);
+}
+
+/* Backward of the trilinear lookup: with the level weights w_l(f) = 1 - t on
+ * l0, t on l0 + 1 and 0 elsewhere (lambda, l0 and t as in orc_lookup_lod;
+ * the level of detail is taken as given, not differentiated), the gradient
+ * of level l's texels is the plain backward on level l with upstream
+ * w_l(f) g(f), and dL/dview, dL/duv are the sums over the levels of theirs.
+ * grad_chain (may be NULL) receives every level's dense gradient back to
+ * back in the layout of chain; grad_view [N][3], grad_uv [N][2] may be NULL. */
+void orc_lookup_lod_bwd(int64_t N, const float *uv, const float *tbn, const float *view,
+                        const float *duv, const float *g, int W, int H, int n, int C, int levels,
+                        const double *chain, int mode, double *grad_chain, double *grad_view,
+                        double *grad_uv)
+{
+    double *wf = (double *)malloc(sizeof(double) * (N > 0 ? N : 1));
+    double *tv = (double *)malloc(sizeof(double) * 3 * (N > 0 ? N : 1));
+    double *tu = (double *)malloc(sizeof(double) * 2 * (N > 0 ? N : 1));
+    if (!wf || !tv || !tu) {
+        free(wf);
+        free(tv);
+        free(tu);
+        return;
+    }
+    if (grad_view)
+        for (int64_t q = 0; q < 3 * N; q++)
+            grad_view[q] = 0.0;
+    if (grad_uv)
+        for (int64_t q = 0; q < 2 * N; q++)
+            grad_uv[q] = 0.0;
+    int64_t off = 0;
+    for (int l = 0; l < levels; l++) {
+        const int Wl = level_dim(W, l), Hl = level_dim(H, l);
+        for (int64_t f = 0; f < N; f++) {
+            double D[4];
+            for (int k = 0; k < 4; k++)
+                D[k] = duv[4 * f + k];
+            double lambda = orc_lod(D, W, H, levels);
+            int l0 = (int)floor(lambda);
+            double t = lambda - l0;
+            if (l0 >= levels - 1) {
+                l0 = levels - 1;
+                t = 0.0;
+            }
+            wf[f] = l == l0 ? 1.0 - t : (l == l0 + 1 ? t : 0.0);
+        }
+        tex_t tl = {Wl, Hl, n, C, ORC_FMT_F64, chain + off, NULL, NULL, NULL};
+        lookup_bwd_core(N, uv, tbn, view, g, wf, &tl, mode, grad_chain ? grad_chain + off : NULL,
+                        NULL, NULL, 0, 0, Wl, Hl, grad_view ? tv : NULL, grad_uv ? tu : NULL,
+                        NULL, NULL);
+        if (grad_view)
+            for (int64_t q = 0; q < 3 * N; q++)
+                grad_view[q] += tv[q];
+        if (grad_uv)
+            for (int64_t q = 0; q < 2 * N; q++)
+                grad_uv[q] += tu[q];
+        off += (int64_t)Wl * Hl * n * n * C;
+    }
+    free(wf);
+    free(tv);
+    free(tu);
+}
+
+/* Adjoint of one level of the chain (orc_build_mip): level l+1's bucket
+ * (i, j) is the mean of the buckets of level l it covers, so each of those
+ * buckets receives the parent's gradient divided by their number.
+ * grad_src [H][W][n][n][C] (level l, W and H as in orc_build_mip) is added
+ * to; grad_dst is level l+1's gradient. */
+void orc_build_mip_adjoint(int W, int H, int n, int C, const double *grad_dst, double *grad_src)
+{
+    int W2 = W > 1 ? W / 2 : 1, H2 = H > 1 ? H / 2 : 1;
+    int fx = W > 1 ? 2 : 1, fy = H > 1 ? 2 : 1;
+    int64_t E = (int64_t)n * n * C;
+    for (int j = 0; j < H; j++)
+        for (int i = 0; i < W; i++) {
+            int64_t parent = (int64_t)(j / fy) * W2 + i / fx;
+            int64_t child = (int64_t)j * W + i;
+            for (int64_t e = 0; e < E; e++)
+                grad_src[child * E + e] += grad_dst[parent * E + e] / (fx * fy);
+        }
+    (void)H2;
 }
 
 /* ------------------------------------------------------------------------- */

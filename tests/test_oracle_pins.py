@@ -1257,3 +1257,110 @@ def test_lloyd_never_increases_the_distortion_and_recovers_separated_clusters():
     new, cnt = oracle.vq_update(Y, a, init)
     np.testing.assert_array_equal(cnt, np.bincount(labels, minlength=8))
     assert np.abs(new - protos).max() < 0.003
+
+
+# --------------------------------------------------------------------------
+# Backward of the level-of-detail lookup and the adjoint of the mip chain
+# --------------------------------------------------------------------------
+
+def _lod_bwd_case(seed, mode, W=8, H=4, n=5, C=3, N=200):
+    tex, uv, tbn, view = _mip_case(seed, W, H, n, C, N)
+    rng = np.random.default_rng(seed + 1)
+    L = _levels(W, H)
+    chain = oracle.build_mips(tex, W, H, n, C, L)
+    # footprints from 0.3 to 12 buckets: every level and the clamp are used
+    s = np.exp(rng.uniform(np.log(0.3), np.log(12.0), N))
+    duv = np.stack([s / W, s * rng.uniform(-0.3, 0.3, N) / H, s * rng.uniform(-0.3, 0.3, N) / W,
+                    s / H], 1).astype(np.float32)
+    g = rng.normal(size=(N, C)).astype(np.float32)
+    return chain, uv, tbn, view, duv, g
+
+
+@pytest.mark.parametrize("mode", [oracle.MODE_NEAREST, oracle.MODE_BILINEAR])
+def test_lod_backward_is_the_adjoint_of_the_lod_lookup(mode):
+    # the trilinear lookup is linear in the chain's texels, so for any
+    # perturbation of every level sum_f g_f . out_f(delta) = <grad_chain, delta>
+    W, H, n, C = 8, 4, 5, 3
+    chain, uv, tbn, view, duv, g = _lod_bwd_case(40 + mode, mode)
+    grads, _, _ = oracle.lookup_lod_bwd(chain, uv, tbn, view, duv, g, W, H, n, C, mode=mode)
+    rng = np.random.default_rng(41)
+    delta = [rng.normal(size=np.asarray(c).shape) for c in chain]
+    out, _ = oracle.lookup_lod(delta, uv, tbn, view, duv, W, H, n, C, mode=mode)
+    lhs = float(np.sum(g.astype(np.float64) * out))
+    rhs = float(sum(np.sum(a * b) for a, b in zip(grads, delta)))
+    assert abs(lhs - rhs) <= 1e-10 * max(1.0, abs(lhs))
+    assert all(np.any(gr != 0) for gr in grads[:3])  # several levels are reached
+
+
+def test_lod_backward_of_one_level_is_the_plain_backward():
+    W, H, n, C = 8, 4, 5, 3
+    chain, uv, tbn, view, duv, g = _lod_bwd_case(42, oracle.MODE_BILINEAR)
+    grads, gv, gu = oracle.lookup_lod_bwd(chain[:1], uv, tbn, view, duv, g, W, H, n, C,
+                                          mode=oracle.MODE_BILINEAR)
+    ref = oracle.lookup_bwd(oracle.Tex(chain[0], W, H, n, C, oracle.FMT_F64), uv, tbn, view, g,
+                            mode=oracle.MODE_BILINEAR)
+    np.testing.assert_allclose(grads[0], ref["grad_tex"], rtol=0, atol=1e-13)
+    np.testing.assert_allclose(gv, ref["grad_view"], rtol=0, atol=1e-13)
+    np.testing.assert_allclose(gu, ref["grad_uv"], rtol=0, atol=1e-13)
+
+
+@pytest.mark.parametrize("mode", [oracle.MODE_NEAREST, oracle.MODE_BILINEAR])
+def test_lod_backward_view_and_uv_finite_differences(mode):
+    W, H, n, C = 8, 4, 5, 3
+    chain, uv, tbn, view, duv, g = _lod_bwd_case(44 + mode, mode, N=80)
+    _, gv, gu = oracle.lookup_lod_bwd(chain, uv, tbn, view, duv, g, W, H, n, C, mode=mode)
+    checked = 0
+    for f in range(len(uv)):
+        if not _away_from_kinks(tbn[f].astype(np.float64).reshape(9), view[f].astype(np.float64), n):
+            continue
+        U = uv[f].astype(np.float64)
+        p = (U - np.floor(U)) * [W, H] - 0.5
+        fd_v, fd_u = np.zeros(3), np.zeros(2)
+        for k in range(3):
+            # central differences with a step the float32 inputs represent
+            # exactly in size (the actual step is taken from the rounded values)
+            h = 2e-4
+            Vp, Vm = view[f].astype(np.float64).copy(), view[f].astype(np.float64).copy()
+            Vp[k] += h
+            Vm[k] -= h
+            Vp32, Vm32 = Vp.astype(np.float32), Vm.astype(np.float32)
+            op, _ = oracle.lookup_lod(chain, uv[f:f + 1], tbn[f:f + 1], Vp32[None],
+                                      duv[f:f + 1], W, H, n, C, mode=mode)
+            om, _ = oracle.lookup_lod(chain, uv[f:f + 1], tbn[f:f + 1], Vm32[None],
+                                      duv[f:f + 1], W, H, n, C, mode=mode)
+            step = float(Vp32[k]) - float(Vm32[k])
+            fd_v[k] = np.dot(g[f].astype(np.float64), (op[0] - om[0]) / step)
+        assert np.linalg.norm(gv[f] - fd_v) <= 2e-4 * max(1.0, np.linalg.norm(fd_v)), (f, gv[f], fd_v)
+        if mode == oracle.MODE_BILINEAR and np.all(np.abs(p - np.round(p)) > 2e-2):
+            for k in range(2):
+                h = 2e-3 / max(W, H)
+                Up, Um = U.copy(), U.copy()
+                Up[k] += h
+                Um[k] -= h
+                op, _ = oracle.lookup_lod(chain, Up.astype(np.float32)[None], tbn[f:f + 1],
+                                          view[f:f + 1], duv[f:f + 1], W, H, n, C, mode=mode)
+                om, _ = oracle.lookup_lod(chain, Um.astype(np.float32)[None], tbn[f:f + 1],
+                                          view[f:f + 1], duv[f:f + 1], W, H, n, C, mode=mode)
+                step = float(np.float32(Up[k])) - float(np.float32(Um[k]))
+                fd_u[k] = np.dot(g[f].astype(np.float64), (op[0] - om[0]) / step)
+            assert np.linalg.norm(gu[f] - fd_u) <= 1e-3 * max(1.0, np.linalg.norm(fd_u)), (f, gu[f], fd_u)
+        if mode == oracle.MODE_NEAREST:
+            assert np.all(gu[f] == 0)
+        checked += 1
+    assert checked > 20
+
+
+@pytest.mark.parametrize("W,H", [(8, 4), (1, 8), (4, 1), (2, 2)])
+def test_mip_adjoint_identity(W, H):
+    # the adjoint of the 2 x 2 (or 2) block mean: <A^T G, X> = <G, A X>
+    n, C = 3, 2
+    rng = np.random.default_rng(W * 10 + H)
+    X = rng.normal(size=(H, W, n, n, C))
+    nxt = oracle.build_mips(X, W, H, n, C, 2)[1]
+    G = rng.normal(size=nxt.shape)
+    AtG = oracle.build_mip_adjoint(G, W, H, n, C)
+    assert abs(np.sum(AtG * X) - np.sum(G * nxt)) <= 1e-12 * np.sum(np.abs(G * nxt))
+    # adding into an existing gradient
+    base = rng.normal(size=X.shape)
+    acc = oracle.build_mip_adjoint(G, W, H, n, C, grad_src=base.copy())
+    np.testing.assert_allclose(acc - base, AtG, atol=1e-14)
