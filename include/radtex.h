@@ -282,6 +282,45 @@ rt_status rt_lookup_fwd_lod(const rt_texture* const* levels, int32_t nlevels,
                             const rt_fragments* frags, const float* duv, float* out,
                             uint32_t flags, void* stream);
 
+/* Bytes of device workspace rt_lookup_lod_bwd needs for `count` fragments
+ * (0 when the arguments are invalid). */
+size_t rt_lookup_lod_bwd_workspace(const rt_texture* const* levels, int32_t nlevels,
+                                   int64_t count, uint32_t flags);
+
+/* Backward of rt_lookup_fwd_lod for upstream gradients grad_out [N][C] (an
+ * addition to the paper, like rt_lookup_bwd).  The level of detail is taken
+ * as given (not differentiated): with each fragment's weights 1 - t on level
+ * l0 and t on l0 + 1,
+ *   grad_levels[l]  float [H_l][W_l][n][n][C], dL/d(level l's decoded texels):
+ *                   rt_lookup_bwd's gradient on level l with every fragment's
+ *                   upstream gradient times its weight on l; every element
+ *                   OVERWRITTEN; a NULL entry skips that level;
+ *   grad_view       float [N][3], the sum over the levels of rt_lookup_bwd's
+ *                   view gradients (NULL skips it);
+ *   grad_uv         float [N][2], likewise (0 in nearest mode).
+ * Bitwise reproducible (per-level sums in level order).  To reach level 0 of
+ * a chain built by rt_build_mip, fold each level's gradient down with
+ * rt_build_mip_adjoint.  grad_levels: HOST array of nlevels DEVICE pointers
+ * (16-byte aligned); duv as for rt_lookup_fwd_lod; workspace: DEVICE, at
+ * least rt_lookup_lod_bwd_workspace() bytes, 256-byte aligned.
+ * Errors: as rt_lookup_fwd_lod and rt_lookup_bwd (RT_ERR_UNSUPPORTED for a
+ * level beyond the backward's limits). */
+rt_status rt_lookup_lod_bwd(const rt_texture* const* levels, int32_t nlevels,
+                            const rt_fragments* frags, const float* duv, const float* grad_out,
+                            float* const* grad_levels, float* grad_view, float* grad_uv,
+                            void* workspace, size_t workspace_bytes, uint32_t flags,
+                            void* stream);
+
+/* Adjoint of rt_build_mip: src is the source level (its W x H, n, C; W and H
+ * powers of two, not both 1); every bucket (i, j) of it receives
+ * grad_dst[j / 2][i / 2] (for a side of 1: that coordinate itself) divided by
+ * the number of buckets its parent averages (4, or 2 once a side is 1),
+ * ADDED to grad_src.  grad_dst: DEVICE float [max(1,H/2)][max(1,W/2)][n][n][C];
+ * grad_src: DEVICE float [H][W][n][n][C]; both 4-byte aligned.
+ * Errors: RT_ERR_INVALID_ARG (NULL, alignment, sizes). */
+rt_status rt_build_mip_adjoint(const rt_texture* src, const float* grad_dst, float* grad_src,
+                               void* stream);
+
 /* --- The bake: the write side of the method --------------------------------
  * Sec. 2.1 (after Eq. (4b)): ray-traced data is sampled onto the radiance
  * texture along the equisolid reflection vector R of every sample.  Here an

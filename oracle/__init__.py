@@ -60,7 +60,7 @@ def _load():
     lib.orc_lod.restype = d
     lib.orc_lookup_lod.argtypes = [i64, P, P, P, P, i32, i32, i32, i32, i32, P, i32, P, P]
     lib.orc_lookup_lod_bwd.argtypes = [i64, P, P, P, P, P, i32, i32, i32, i32, i32, P, i32, P,
-                                       P, P]
+                                       P, P, P, P, P, P]
     lib.orc_build_mip_adjoint.argtypes = [i32, i32, i32, i32, P, P]
     lib.orc_pack_bits.argtypes = [P, i64, i32, P]
     lib.orc_lookup_light.argtypes = [i64, P, P, P, i32, i32, P, i32, i32, i32, i32, i32, P, P,
@@ -366,28 +366,36 @@ def lookup_lod(chain, uv, tbn, view, duv, W, H, n, C, mode=MODE_NEAREST):
     return out, lam
 
 
-def lookup_lod_bwd(chain, uv, tbn, view, duv, g, W, H, n, C, mode=MODE_NEAREST):
+def lookup_lod_bwd(chain, uv, tbn, view, duv, g, W, H, n, C, mode=MODE_NEAREST, full=False):
     """Backward of the trilinear lookup over the mip chain (list of float64
     levels) for upstream g [N, C] float32: (list of per-level gradients,
-    grad_view [N, 3], grad_uv [N, 2]), all float64."""
+    grad_view [N, 3], grad_uv [N, 2]), all float64.  With full=True a dict
+    that also holds the per-level magnitude sums abs / absg (as in
+    lookup_bwd) and scale_view / scale_uv."""
     uv, tbn, view = _frags(uv, tbn, view)
     duv = _c(duv, np.float32).reshape(-1, 4)
     g = _c(g, np.float32).reshape(-1, C)
     N = uv.shape[0]
     flat = np.ascontiguousarray(np.concatenate([np.asarray(c, np.float64).reshape(-1)
                                                 for c in chain]))
-    gchain = np.empty_like(flat)
-    gv = np.empty((N, 3), np.float64)
-    gu = np.empty((N, 2), np.float64)
+    gchain, achain, bchain = (np.empty_like(flat) for _ in range(3))
+    gv, sv = np.empty((N, 3), np.float64), np.empty((N, 3), np.float64)
+    gu, su = np.empty((N, 2), np.float64), np.empty((N, 2), np.float64)
     _load().orc_lookup_lod_bwd(N, _p(uv), _p(tbn), _p(view), _p(duv), _p(g), int(W), int(H),
-                               int(n), int(C), len(chain), _p(flat), int(mode), _p(gchain), _p(gv),
-                               _p(gu))
-    out, off = [], 0
-    for c in chain:
-        k = np.asarray(c).size
-        out.append(gchain[off:off + k].reshape(np.asarray(c).shape))
-        off += k
-    return out, gv, gu
+                               int(n), int(C), len(chain), _p(flat), int(mode), _p(gchain),
+                               _p(achain), _p(bchain), _p(gv), _p(gu), _p(sv), _p(su))
+
+    def split(a):
+        out, off = [], 0
+        for c in chain:
+            k = np.asarray(c).size
+            out.append(a[off:off + k].reshape(np.asarray(c).shape))
+            off += k
+        return out
+    if full:
+        return {"grad": split(gchain), "abs": split(achain), "absg": split(bchain),
+                "grad_view": gv, "grad_uv": gu, "scale_view": sv, "scale_uv": su}
+    return split(gchain), gv, gu
 
 
 def build_mip_adjoint(grad_dst, W, H, n, C, grad_src=None):

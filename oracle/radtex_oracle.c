@@ -1075,27 +1075,36 @@ void orc_lookup_lod(int64_t N, const float *uv, const float *tbn, const float *v
  * of level l's texels is the plain backward on level l with upstream
  * w_l(f) g(f), and dL/dview, dL/duv are the sums over the levels of theirs.
  * grad_chain (may be NULL) receives every level's dense gradient back to
- * back in the layout of chain; grad_view [N][3], grad_uv [N][2] may be NULL. */
+ * back in the layout of chain, abs_chain / absg_chain (may be NULL) the
+ * magnitude sums of orc_lookup_bwd per level; grad_view [N][3], grad_uv
+ * [N][2] and their magnitude scales scale_view, scale_uv (summed over the
+ * levels) may be NULL. */
 void orc_lookup_lod_bwd(int64_t N, const float *uv, const float *tbn, const float *view,
                         const float *duv, const float *g, int W, int H, int n, int C, int levels,
-                        const double *chain, int mode, double *grad_chain, double *grad_view,
-                        double *grad_uv)
+                        const double *chain, int mode, double *grad_chain, double *abs_chain,
+                        double *absg_chain, double *grad_view, double *grad_uv,
+                        double *scale_view, double *scale_uv)
 {
-    double *wf = (double *)malloc(sizeof(double) * (N > 0 ? N : 1));
-    double *tv = (double *)malloc(sizeof(double) * 3 * (N > 0 ? N : 1));
-    double *tu = (double *)malloc(sizeof(double) * 2 * (N > 0 ? N : 1));
-    if (!wf || !tv || !tu) {
+    int64_t M = N > 0 ? N : 1;
+    double *wf = (double *)malloc(sizeof(double) * M);
+    double *tv = (double *)malloc(sizeof(double) * 3 * M);
+    double *tu = (double *)malloc(sizeof(double) * 2 * M);
+    double *sv = (double *)malloc(sizeof(double) * 3 * M);
+    double *su = (double *)malloc(sizeof(double) * 2 * M);
+    if (!wf || !tv || !tu || !sv || !su) {
         free(wf);
         free(tv);
         free(tu);
+        free(sv);
+        free(su);
         return;
     }
-    if (grad_view)
-        for (int64_t q = 0; q < 3 * N; q++)
-            grad_view[q] = 0.0;
-    if (grad_uv)
-        for (int64_t q = 0; q < 2 * N; q++)
-            grad_uv[q] = 0.0;
+    double *acc[4] = {grad_view, grad_uv, scale_view, scale_uv};
+    int64_t len[4] = {3 * N, 2 * N, 3 * N, 2 * N};
+    for (int a = 0; a < 4; a++)
+        if (acc[a])
+            for (int64_t q = 0; q < len[a]; q++)
+                acc[a][q] = 0.0;
     int64_t off = 0;
     for (int l = 0; l < levels; l++) {
         const int Wl = level_dim(W, l), Hl = level_dim(H, l);
@@ -1114,19 +1123,21 @@ void orc_lookup_lod_bwd(int64_t N, const float *uv, const float *tbn, const floa
         }
         tex_t tl = {Wl, Hl, n, C, ORC_FMT_F64, chain + off, NULL, NULL, NULL};
         lookup_bwd_core(N, uv, tbn, view, g, wf, &tl, mode, grad_chain ? grad_chain + off : NULL,
-                        NULL, NULL, 0, 0, Wl, Hl, grad_view ? tv : NULL, grad_uv ? tu : NULL,
-                        NULL, NULL);
-        if (grad_view)
-            for (int64_t q = 0; q < 3 * N; q++)
-                grad_view[q] += tv[q];
-        if (grad_uv)
-            for (int64_t q = 0; q < 2 * N; q++)
-                grad_uv[q] += tu[q];
+                        abs_chain ? abs_chain + off : NULL, absg_chain ? absg_chain + off : NULL,
+                        0, 0, Wl, Hl, grad_view ? tv : NULL, grad_uv ? tu : NULL,
+                        scale_view ? sv : NULL, scale_uv ? su : NULL);
+        double *part[4] = {tv, tu, sv, su};
+        for (int a = 0; a < 4; a++)
+            if (acc[a])
+                for (int64_t q = 0; q < len[a]; q++)
+                    acc[a][q] += part[a][q];
         off += (int64_t)Wl * Hl * n * n * C;
     }
     free(wf);
     free(tv);
     free(tu);
+    free(sv);
+    free(su);
 }
 
 /* Adjoint of one level of the chain (orc_build_mip): level l+1's bucket

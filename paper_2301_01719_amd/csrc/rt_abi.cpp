@@ -144,7 +144,8 @@ const char* kernel_name(int id) {
         "k_segacc_hot",   "k_combine_hot",   "k_segacc_big",    "k_bake_directions",
         "k_bake_env",     "k_build_mip",     "k_lookup_lod",    "k_pack_bits",
         "k_lookup_light", "k_bake_shadow",   "k_vq_assign",     "k_vq_hist",
-        "k_vq_scatter",   "k_vq_pieces",     "k_vq_combine"};
+        "k_vq_scatter",   "k_vq_pieces",     "k_vq_combine",    "k_lod_bwd_scale",
+        "k_mip_adjoint"};
     return (id >= 0 && id < K_COUNT) ? names[id] : "";
 }
 
@@ -539,10 +540,10 @@ rt_status rt_build_mip(const rt_texture* src, float* dst, void* stream) {
     RT_GUARD_END
 }
 
-rt_status rt_lookup_fwd_lod(const rt_texture* const* levels, int32_t nlevels,
-                            const rt_fragments* f, const float* duv, float* out, uint32_t flags,
-                            void* stream) {
-    RT_GUARD_BEGIN
+namespace {
+// Shared checks of a mip chain: sizes halve from level 0, one n, C and format,
+// no 1-bit or dictionary level.
+rt_status check_chain(const rt_texture* const* levels, int32_t nlevels, rt::LevelSet* ls) {
     if (!levels) return fail(RT_ERR_INVALID_ARG, "levels is NULL");
     if (nlevels < 1) return fail(RT_ERR_INVALID_ARG, "nlevels = %d < 1", nlevels);
     if (nlevels > rt::MAX_LEVELS)
@@ -559,13 +560,12 @@ rt_status rt_lookup_fwd_lod(const rt_texture* const* levels, int32_t nlevels,
         if (nlevels > 1 + log2i(std::max(v0.W, v0.H)))
             return fail(RT_ERR_INVALID_ARG, "%d levels exceed the chain of a %d x %d matrix", nlevels, v0.W, v0.H);
     }
-    rt::LevelSet ls;
-    memset(&ls, 0, sizeof(ls));
-    ls.levels = nlevels;
-    ls.W = v0.W;
-    ls.H = v0.H;
-    ls.n = v0.n;
-    ls.C = v0.C;
+    memset(ls, 0, sizeof(*ls));
+    ls->levels = nlevels;
+    ls->W = v0.W;
+    ls->H = v0.H;
+    ls->n = v0.n;
+    ls->C = v0.C;
     for (int l = 0; l < nlevels; l++) {
         const rt::TexView& v = levels[l]->view;
         const int w = std::max(v0.W >> l, 1), h = std::max(v0.H >> l, 1);
@@ -573,22 +573,134 @@ rt_status rt_lookup_fwd_lod(const rt_texture* const* levels, int32_t nlevels,
             return fail(RT_ERR_INVALID_ARG, "level %d is %d x %d, the chain needs %d x %d", l, v.W, v.H, w, h);
         if (v.n != v0.n || v.C != v0.C || levels[l]->fmt != levels[0]->fmt)
             return fail(RT_ERR_INVALID_ARG, "level %d differs from level 0 in n, channels or format", l);
-        ls.data[l] = v.data;
-        ls.scales[l] = v.scales;
+        ls->data[l] = v.data;
+        ls->scales[l] = v.scales;
     }
-    rt_status st = check_frags(f);
+    return RT_OK;
+}
+
+// Backward plans of every level and the workspace layout of the LOD backward.
+bool plan_lod_backward(const rt_texture* const* levels, int nlevels, int64_t N, int mode,
+                       rt::BwdPlan* plans, rt::LodBwdLayout* lay) {
+    size_t bwd = 0;
+    for (int l = 0; l < nlevels; l++) {
+        const rt::TexView& v = levels[l]->view;
+        if (!rt::plan_backward(v.W, v.H, v.n, v.C, N, mode, &plans[l])) return false;
+        bwd = std::max(bwd, plans[l].total);
+    }
+    auto a256 = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    const size_t n1 = (size_t)std::max<int64_t>(N, 1);
+    lay->off_bwd = 0;
+    lay->off_gl = a256(bwd);
+    lay->off_view = lay->off_gl + a256(n1 * levels[0]->view.C * 4);
+    lay->off_uv = lay->off_view + a256(n1 * 12);
+    lay->total = lay->off_uv + a256(n1 * 8);
+    return true;
+}
+}  // namespace
+
+rt_status rt_lookup_fwd_lod(const rt_texture* const* levels, int32_t nlevels,
+                            const rt_fragments* f, const float* duv, float* out, uint32_t flags,
+                            void* stream) {
+    RT_GUARD_BEGIN
+    rt::LevelSet ls;
+    rt_status st = check_chain(levels, nlevels, &ls);
+    if (st != RT_OK) return st;
+    st = check_frags(f);
     if (st != RT_OK) return st;
     if (flags > RT_BUCKET_BILINEAR) return fail(RT_ERR_INVALID_ARG, "unknown flags 0x%x", flags);
     if (f->count > 0) {
         if (!duv) return fail(RT_ERR_INVALID_ARG, "duv is NULL");
         if (!aligned(duv, 16)) return fail(RT_ERR_INVALID_ARG, "duv must be 16-byte aligned");
         if (!out) return fail(RT_ERR_INVALID_ARG, "out is NULL");
-        if (!aligned(out, out_align(v0.C)))
-            return fail(RT_ERR_INVALID_ARG, "out must be %zu-byte aligned", out_align(v0.C));
+        if (!aligned(out, out_align(ls.C)))
+            return fail(RT_ERR_INVALID_ARG, "out must be %zu-byte aligned", out_align(ls.C));
     }
     hipError_t e = rt::launch_lookup_lod(ls, levels[0]->fmt, (int)flags, f->uv, f->tbn, f->view,
                                          duv, out, fragmap(f), (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "lod lookup launch");
+    return ok();
+    RT_GUARD_END
+}
+
+size_t rt_lookup_lod_bwd_workspace(const rt_texture* const* levels, int32_t nlevels, int64_t count,
+                                   uint32_t flags) {
+    try {
+        if (!levels || nlevels < 1 || nlevels > rt::MAX_LEVELS || count < 0 ||
+            flags > RT_BUCKET_BILINEAR)
+            return 0;
+        for (int l = 0; l < nlevels; l++)
+            if (!levels[l]) return 0;
+        rt::BwdPlan plans[rt::MAX_LEVELS];
+        rt::LodBwdLayout lay;
+        if (!plan_lod_backward(levels, nlevels, count, (int)flags, plans, &lay)) return 0;
+        return lay.total;
+    } catch (...) {
+        return 0;
+    }
+}
+
+rt_status rt_lookup_lod_bwd(const rt_texture* const* levels, int32_t nlevels,
+                            const rt_fragments* f, const float* duv, const float* grad_out,
+                            float* const* grad_levels, float* grad_view, float* grad_uv, void* ws,
+                            size_t ws_bytes, uint32_t flags, void* stream) {
+    RT_GUARD_BEGIN
+    rt::LevelSet ls;
+    rt_status st = check_chain(levels, nlevels, &ls);
+    if (st != RT_OK) return st;
+    st = check_frags(f);
+    if (st != RT_OK) return st;
+    if (flags > RT_BUCKET_BILINEAR) return fail(RT_ERR_INVALID_ARG, "unknown flags 0x%x", flags);
+    if (!grad_levels) return fail(RT_ERR_INVALID_ARG, "grad_levels is NULL");
+    for (int l = 0; l < nlevels; l++)
+        if (grad_levels[l] && !aligned(grad_levels[l], 16))
+            return fail(RT_ERR_INVALID_ARG, "grad_levels[%d] must be 16-byte aligned", l);
+    if (grad_view && !aligned(grad_view, 4)) return fail(RT_ERR_INVALID_ARG, "grad_view must be 4-byte aligned");
+    if (grad_uv && !aligned(grad_uv, 8)) return fail(RT_ERR_INVALID_ARG, "grad_uv must be 8-byte aligned");
+    if (f->count > 0) {
+        if (!duv || !grad_out) return fail(RT_ERR_INVALID_ARG, "duv and grad_out must be non-NULL");
+        if (!aligned(duv, 16)) return fail(RT_ERR_INVALID_ARG, "duv must be 16-byte aligned");
+        if (!aligned(grad_out, out_align(ls.C)))
+            return fail(RT_ERR_INVALID_ARG, "grad_out must be %zu-byte aligned", out_align(ls.C));
+    }
+    rt::BwdPlan plans[rt::MAX_LEVELS];
+    rt::LodBwdLayout lay;
+    if (!plan_lod_backward(levels, nlevels, f->count, (int)flags, plans, &lay))
+        return fail(RT_ERR_UNSUPPORTED, "sort key (W*H*n*n), bucket size (n*n*C <= 4096) or record count beyond the backward's limits");
+    bool any = grad_view || grad_uv;
+    for (int l = 0; l < nlevels; l++) any = any || grad_levels[l];
+    if (!any) return ok();  // nothing requested
+    if (f->count > 0) {
+        if (!ws) return fail(RT_ERR_INVALID_ARG, "workspace is NULL");
+        if (!aligned(ws, 256)) return fail(RT_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+        if (ws_bytes < lay.total)
+            return fail(RT_ERR_WORKSPACE_TOO_SMALL, "workspace has %zu bytes, %zu needed", ws_bytes, lay.total);
+    }
+    rt::TexView views[rt::MAX_LEVELS];
+    for (int l = 0; l < nlevels; l++) views[l] = levels[l]->view;
+    hipError_t e = rt::launch_lookup_lod_bwd(views, nlevels, levels[0]->fmt, (int)flags, f->uv,
+                                             f->tbn, f->view, duv, grad_out, grad_levels,
+                                             grad_view, grad_uv, fragmap(f), plans, lay, ws,
+                                             (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "lod backward launch");
+    return ok();
+    RT_GUARD_END
+}
+
+rt_status rt_build_mip_adjoint(const rt_texture* src, const float* grad_dst, float* grad_src,
+                               void* stream) {
+    RT_GUARD_BEGIN
+    rt_status st = check_tex(src);
+    if (st != RT_OK) return st;
+    const rt::TexView& v = src->view;
+    if (!pow2(v.W) || !pow2(v.H))
+        return fail(RT_ERR_INVALID_ARG, "bucket matrix %d x %d: a mip chain needs powers of two", v.W, v.H);
+    if (v.W == 1 && v.H == 1) return fail(RT_ERR_INVALID_ARG, "a 1 x 1 matrix has no next level");
+    if (!grad_dst || !grad_src) return fail(RT_ERR_INVALID_ARG, "grad_dst and grad_src must be non-NULL");
+    if (!aligned(grad_dst, 4) || !aligned(grad_src, 4))
+        return fail(RT_ERR_INVALID_ARG, "grad_dst and grad_src must be 4-byte aligned");
+    hipError_t e = rt::launch_mip_adjoint(v, grad_dst, grad_src, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "mip adjoint launch");
     return ok();
     RT_GUARD_END
 }

@@ -328,6 +328,26 @@ __device__ __forceinline__ void bucket_pair(float u, int W, int& i0, int& i1, fl
     i1 = i0 + 1 == W ? 0 : i0 + 1;
 }
 
+// Level of detail of a fragment from its UV screen derivatives d = (du/dx,
+// dv/dx, du/dy, dv/dy): rho = the larger pixel footprint in buckets of level 0
+// (W x H), lambda = log2 rho clamped to [0, levels - 1] (0 when rho is 0 or
+// not finite); the lookup blends levels l0 = floor(lambda) and l0 + 1 with
+// weights 1 - t and t (t = 0 on the last level).
+__device__ __forceinline__ void lod_split(const float4 d, int W, int H, int levels, int& l0,
+                                          float& t) {
+    const float ax = d.x * (float)W, ay = d.y * (float)H;
+    const float bx = d.z * (float)W, by = d.w * (float)H;
+    const float rho = fmaxf(sqrtf(ax * ax + ay * ay), sqrtf(bx * bx + by * by));
+    float lambda = 0.f;
+    if (rho > 0.f && rho <= 3.0e38f) lambda = fminf(fmaxf(log2f(rho), 0.f), (float)(levels - 1));
+    l0 = (int)floorf(lambda);
+    t = lambda - (float)l0;
+    if (l0 >= levels - 1) {
+        l0 = levels - 1;
+        t = 0.f;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Sample centres of a bucket as directions (the write side: Eqs. 4a, 4b, 2c).
 // At sample (x, y) of an n x n bucket: B = ((2x+1)/n - 1, (2y+1)/n - 1);

@@ -41,6 +41,8 @@ enum KernelId {
     K_VQ_SCATTER,
     K_VQ_PIECES,
     K_VQ_COMBINE,
+    K_LOD_BWD_SCALE,
+    K_MIP_ADJOINT,
     K_COUNT
 };
 const char* kernel_name(int id);
@@ -123,6 +125,22 @@ constexpr int BIG_LISTS = 64; // big-bucket lists, each with its own counter
 constexpr int BIG_STRIDE = 64;  // u32 between two counters (256 bytes)
 constexpr int BIG_RUN = 64;     // consecutive groups that append to one list
 bool plan_backward(int W, int H, int n, int C, int64_t N, int mode, BwdPlan* p);
+
+// Backward of the level-of-detail lookup: one plain backward per level, on
+// the upstream gradient scaled by the level's weight.  Workspace: the largest
+// level's backward workspace, then the scaled gradient [N][C] and the
+// per-level view [N][3] and uv [N][2] gradients.
+struct LodBwdLayout {
+    size_t off_bwd, off_gl, off_view, off_uv, total;
+};
+hipError_t launch_lookup_lod_bwd(const TexView* levels, int nlevels, int fmt, int mode,
+                                 const float* uv, const float* tbn, const float* view,
+                                 const float* duv, const float* grad_out, float* const* grad_levels,
+                                 float* grad_view, float* grad_uv, const FragMap& m,
+                                 const BwdPlan* plans, const LodBwdLayout& lay, void* ws,
+                                 hipStream_t s);
+hipError_t launch_mip_adjoint(const TexView& src, const float* grad_dst, float* grad_src,
+                              hipStream_t s);
 
 // Device-wide exclusive scan of L uint32 values (the backward's three-kernel
 // scan); part holds ceil(L / 4096) + 1 words.

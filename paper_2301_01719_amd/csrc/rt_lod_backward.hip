@@ -1,0 +1,121 @@
+// rt_lod_backward.hip -- backward of the level-of-detail lookup over a mip
+// chain, and the adjoint of one chain step, for gfx950.
+//
+// The trilinear lookup blends the lookups on levels l0 and l0 + 1 with
+// weights 1 - t and t (the level of detail comes from the UV screen
+// derivatives and is not differentiated).  So the gradient of level l's
+// texels is the plain backward on level l with each fragment's upstream
+// gradient scaled by its weight on that level, and the view and uv gradients
+// are the sums over the levels of the plain backward's.  Each level reuses
+// the deterministic sort-and-accumulate backward; the per-level view and uv
+// gradients are added in level order, so the result is bitwise reproducible.
+//
+// Chain adjoint: level l+1's bucket is the mean of the 2 x 2 (or 2) buckets of
+// level l it covers, so each of those receives the parent's gradient divided
+// by their number (one thread per element of level l: no two threads write
+// one element).
+#include "rt_device.hpp"
+#include "rt_kernels.hpp"
+
+namespace rt {
+
+// g_l[f][c] = w_l(f) g[f][c], w_l = 1 - t on l0, t on l0 + 1, 0 elsewhere
+__global__ __launch_bounds__(256) void k_lod_scale(const float* __restrict__ grad_out,
+                                                   const float* __restrict__ duv, int64_t N,
+                                                   int C, int W, int H, int levels, int l,
+                                                   float* __restrict__ gl) {
+    const int64_t f = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (f >= N) return;
+    int l0;
+    float t;
+    lod_split(((const float4*)duv)[f], W, H, levels, l0, t);
+    const float w = l == l0 ? 1.f - t : (l == l0 + 1 ? t : 0.f);
+    for (int c = 0; c < C; c++) gl[f * C + c] = w * grad_out[f * C + c];
+}
+
+__global__ __launch_bounds__(256) void k_fill_f32(float* __restrict__ p, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) p[i] = 0.f;
+}
+
+__global__ __launch_bounds__(256) void k_add_f32(float* __restrict__ dst,
+                                                 const float* __restrict__ src, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) dst[i] += src[i];
+}
+
+static uint32_t blocks_of(int64_t n) { return (uint32_t)((n + 255) / 256); }
+
+hipError_t launch_lookup_lod_bwd(const TexView* levels, int nlevels, int fmt, int mode,
+                                 const float* uv, const float* tbn, const float* view,
+                                 const float* duv, const float* grad_out, float* const* grad_levels,
+                                 float* grad_view, float* grad_uv, const FragMap& m,
+                                 const BwdPlan* plans, const LodBwdLayout& lay, void* ws,
+                                 hipStream_t s) {
+    const int64_t N = m.N;
+    if (N <= 0) {
+        // no fragment: every level's gradient is zero
+        for (int l = 0; l < nlevels; l++) {
+            if (!grad_levels[l]) continue;
+            const int64_t e = (int64_t)levels[l].W * levels[l].H * levels[l].n * levels[l].n *
+                              levels[l].C;
+            hipLaunchKernelGGL(k_fill_f32, dim3(blocks_of(e)), dim3(256), 0, s, grad_levels[l], e);
+        }
+        return hipGetLastError();
+    }
+    const int C = levels[0].C;
+    char* base = (char*)ws;
+    float* gl = (float*)(base + lay.off_gl);
+    float* tv = (float*)(base + lay.off_view);
+    float* tu = (float*)(base + lay.off_uv);
+    void* bws = base + lay.off_bwd;
+    prof_begin(K_LOD_BWD_SCALE, s);
+    if (grad_view) hipLaunchKernelGGL(k_fill_f32, dim3(blocks_of(3 * N)), dim3(256), 0, s, grad_view, 3 * N);
+    if (grad_uv) hipLaunchKernelGGL(k_fill_f32, dim3(blocks_of(2 * N)), dim3(256), 0, s, grad_uv, 2 * N);
+    prof_end(K_LOD_BWD_SCALE, s);
+    for (int l = 0; l < nlevels; l++) {
+        if (!grad_levels[l] && !grad_view && !grad_uv) continue;
+        prof_begin(K_LOD_BWD_SCALE, s);
+        hipLaunchKernelGGL(k_lod_scale, dim3(blocks_of(N)), dim3(256), 0, s, grad_out, duv, N, C,
+                           levels[0].W, levels[0].H, nlevels, l, gl);
+        prof_end(K_LOD_BWD_SCALE, s);
+        hipError_t e = launch_backward(levels[l], fmt, mode, uv, tbn, view, gl, grad_levels[l],
+                                       grad_view ? tv : nullptr, grad_uv ? tu : nullptr, m,
+                                       plans[l], bws, s);
+        if (e != hipSuccess) return e;
+        prof_begin(K_LOD_BWD_SCALE, s);
+        if (grad_view) hipLaunchKernelGGL(k_add_f32, dim3(blocks_of(3 * N)), dim3(256), 0, s, grad_view, (const float*)tv, 3 * N);
+        if (grad_uv) hipLaunchKernelGGL(k_add_f32, dim3(blocks_of(2 * N)), dim3(256), 0, s, grad_uv, (const float*)tu, 2 * N);
+        prof_end(K_LOD_BWD_SCALE, s);
+    }
+    return hipGetLastError();
+}
+
+// grad_src (level l, W x H buckets of E values) += adjoint of the chain step
+// applied to grad_dst (level l+1)
+__global__ __launch_bounds__(256) void k_mip_adjoint(const float* __restrict__ grad_dst,
+                                                     float* __restrict__ grad_src, int W, int H,
+                                                     int64_t E) {
+    const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t total = (int64_t)W * H * E;
+    if (q >= total) return;
+    const int64_t b = q / E, e = q - b * E;
+    const int j = (int)(b / W), i = (int)(b - (int64_t)j * W);
+    const int fx = W > 1 ? 2 : 1, fy = H > 1 ? 2 : 1;
+    const int W2 = W > 1 ? W / 2 : 1;
+    const int64_t parent = (int64_t)(j / fy) * W2 + i / fx;
+    grad_src[q] += grad_dst[parent * E + e] * (1.0f / (float)(fx * fy));
+}
+
+hipError_t launch_mip_adjoint(const TexView& src, const float* grad_dst, float* grad_src,
+                              hipStream_t s) {
+    const int64_t E = (int64_t)src.n * src.n * src.C;
+    const int64_t total = (int64_t)src.W * src.H * E;
+    prof_begin(K_MIP_ADJOINT, s);
+    hipLaunchKernelGGL(k_mip_adjoint, dim3(blocks_of(total)), dim3(256), 0, s, grad_dst, grad_src,
+                       src.W, src.H, E);
+    prof_end(K_MIP_ADJOINT, s);
+    return hipGetLastError();
+}
+
+}  // namespace rt

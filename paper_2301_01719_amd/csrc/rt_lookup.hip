@@ -162,19 +162,9 @@ __global__ __launch_bounds__(256) void k_lookup_lod(LevelSet ls, const float* __
     const int64_t f = frag_of(m, blockIdx.x, gridDim.x, threadIdx.x);
     if (f < 0) return;
     const Frag g = load_frag(uv, tbn, view, f);
-    const float4 d = ((const float4*)duv)[f];
-    const float ax = d.x * (float)ls.W, ay = d.y * (float)ls.H;
-    const float bx = d.z * (float)ls.W, by = d.w * (float)ls.H;
-    const float rho = fmaxf(sqrtf(ax * ax + ay * ay), sqrtf(bx * bx + by * by));
-    float lambda = 0.f;
-    if (rho > 0.f && rho <= 3.0e38f)
-        lambda = fminf(fmaxf(log2f(rho), 0.f), (float)(ls.levels - 1));
-    int l0 = (int)floorf(lambda);
-    float t = lambda - (float)l0;
-    if (l0 >= ls.levels - 1) {
-        l0 = ls.levels - 1;
-        t = 0.f;
-    }
+    int l0;
+    float t;
+    lod_split(((const float4*)duv)[f], ls.W, ls.H, ls.levels, l0, t);
     const Dir dd = map_direction(g.m, g.w, ls.n);
     const Foot p = footprint(dd.sx, dd.sy, ls.n);
     float a[4] = {0.f, 0.f, 0.f, 0.f}, b[4] = {0.f, 0.f, 0.f, 0.f};

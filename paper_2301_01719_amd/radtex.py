@@ -42,7 +42,8 @@ EXPORTS = ("rt_create_texture", "rt_destroy_texture", "rt_quantize", "rt_lookup_
            "rt_profile_kernel_count", "rt_profile_kernel_name", "rt_profile_read",
            "rt_bake_directions", "rt_bake_environment", "rt_build_mip", "rt_lookup_fwd_lod",
            "rt_lookup_light", "rt_bake_shadow", "rt_create_dictionary_texture",
-           "rt_vq_assign", "rt_vq_update_workspace", "rt_vq_update")
+           "rt_vq_assign", "rt_vq_update_workspace", "rt_vq_update",
+           "rt_lookup_lod_bwd_workspace", "rt_lookup_lod_bwd", "rt_build_mip_adjoint")
 
 
 class RadtexError(RuntimeError):
@@ -119,6 +120,10 @@ def _load() -> ctypes.CDLL:
         "rt_vq_assign": ([P, i64, i32, P, i32, P, P, P], i32),
         "rt_vq_update_workspace": ([i64, i32, i32], sz),
         "rt_vq_update": ([P, i64, i32, P, i32, P, P, P, sz, P], i32),
+        "rt_lookup_lod_bwd_workspace": ([ctypes.POINTER(P), i32, i64, u32], sz),
+        "rt_lookup_lod_bwd": ([ctypes.POINTER(P), i32, ctypes.POINTER(Fragments), P, P,
+                               ctypes.POINTER(P), P, P, P, sz, u32, P], i32),
+        "rt_build_mip_adjoint": ([P, P, P, P], i32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -365,6 +370,43 @@ def build_mips(tex: Texture, levels: Optional[int] = None):
         data = build_mip(prev)
         chain.append(Texture(data, max(1, prev.W // 2), max(1, prev.H // 2), prev.n, prev.C))
     return chain
+
+
+def lookup_lod_bwd(levels, uv, tbn, view, duv, grad_out, mode: str = "nearest",
+                   want_levels=True, want_view=True, want_uv=True, workspace=None, image=None):
+    """Backward of lookup_fwd_lod (rt_lookup_lod_bwd): returns (per-level
+    texel gradients (None where not wanted), grad_view, grad_uv)."""
+    fr = _frags(uv, tbn, view, image)
+    _need_gpu(duv, "duv", torch.float32)
+    _need_gpu(grad_out, "grad_out", torch.float32)
+    t0 = levels[0]
+    dev = t0.device
+    L = len(levels)
+    handles = (ctypes.c_void_p * L)(*[t.handle for t in levels])
+    if isinstance(want_levels, bool):
+        want_levels = [want_levels] * L
+    grads = [torch.empty((t.H, t.W, t.n, t.n, t.C), dtype=torch.float32, device=dev)
+             if want_levels[l] else None for l, t in enumerate(levels)]
+    gptr = (ctypes.c_void_p * L)(*[None if g is None else g.data_ptr() for g in grads])
+    gv = torch.empty((fr.count, 3), dtype=torch.float32, device=dev) if want_view else None
+    gu = torch.empty((fr.count, 2), dtype=torch.float32, device=dev) if want_uv else None
+    need = LIB.rt_lookup_lod_bwd_workspace(handles, L, fr.count, MODES[mode])
+    if workspace is None:
+        workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
+    _check(LIB.rt_lookup_lod_bwd(handles, L, ctypes.byref(fr), _ptr(duv), _ptr(grad_out), gptr,
+                                 _ptr(gv), _ptr(gu), _ptr(workspace), workspace.numel(),
+                                 MODES[mode], _stream(dev)))
+    return grads, gv, gu
+
+
+def build_mip_adjoint(src: Texture, grad_dst: torch.Tensor, grad_src: torch.Tensor):
+    """grad_src (level of src's shape) += the adjoint of build_mip applied to
+    grad_dst (the next level's gradient); returns grad_src."""
+    _need_gpu(grad_dst, "grad_dst", torch.float32)
+    _need_gpu(grad_src, "grad_src", torch.float32)
+    _check(LIB.rt_build_mip_adjoint(src.handle, _ptr(grad_dst), _ptr(grad_src),
+                                    _stream(src.device)))
+    return grad_src
 
 
 def lookup_fwd_lod(levels, uv, tbn, view, duv, mode: str = "nearest", out=None, image=None):

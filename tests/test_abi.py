@@ -233,6 +233,31 @@ def test_mip_entries_reject_bad_arguments(rt):
     assert "level 0 is NULL" in L.rt_last_error().decode()
 
 
+def test_lod_backward_entries_reject_bad_arguments(rt):
+    """Host checks of the level-of-detail backward and the chain adjoint, made
+    before any device work."""
+    L = rt.LIB
+    fr = _fr(rt, 10, 0x1000, 0x2000, 0x3000)
+    gl = (ctypes.c_void_p * 2)(None, None)
+
+    def bwd(levels, nlevels, duv=0x4000, grad_out=0x5000, grads=gl):
+        return L.rt_lookup_lod_bwd(levels, nlevels, ctypes.byref(fr), duv, grad_out, grads,
+                                   None, None, None, 0, 0, None)
+
+    assert bwd(None, 1) == 1 and "levels is NULL" in L.rt_last_error().decode()
+    lv = (ctypes.c_void_p * 2)(None, None)
+    assert bwd(lv, 0) == 1 and "< 1" in L.rt_last_error().decode()
+    assert bwd(lv, 18) == 2 and "exceeds" in L.rt_last_error().decode()
+    assert bwd(lv, 2) == 1 and "level 0 is NULL" in L.rt_last_error().decode()
+    # the workspace query answers 0 for arguments it cannot plan
+    assert L.rt_lookup_lod_bwd_workspace(None, 1, 10, 0) == 0
+    assert L.rt_lookup_lod_bwd_workspace(lv, 0, 10, 0) == 0
+    assert L.rt_lookup_lod_bwd_workspace(lv, 2, 10, 0) == 0
+    assert L.rt_lookup_lod_bwd_workspace(lv, 1, -1, 0) == 0
+    assert L.rt_build_mip_adjoint(None, 0x1000, 0x2000, None) == 1
+    assert "texture handle" in L.rt_last_error().decode()
+
+
 def test_one_bit_texture_descriptors(rt):
     """1-bit textures: one channel, bucket-major, no scales (host checks made
     before the device is looked for)."""

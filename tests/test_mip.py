@@ -151,3 +151,110 @@ def test_lod_validation(rt):
     with pytest.raises(rt.RadtexError, match="FP32"):
         c, _ = rt.quantize(chain[0], "bf16")
         rt.build_mip(rt.Texture(c, W, H, n, C, "bf16"))
+
+
+# ---------------------------------------------------------------------------
+# Backward of the level-of-detail lookup and the chain's adjoint.  Each level's
+# texel gradient is the plain backward with the weighted upstream gradient,
+# so the plain backward's criteria apply per level (1e-4 of the sum of
+# |w g| plus the weights' rounding); view and uv gradients against the sum
+# of the levels' magnitude scales (the GPU chain's binary32 means differ from
+# the oracle's exact chain by l 2e-7 relative, far inside that); fragments
+# near a cell edge or an integer level of detail are left out, as for the
+# forward.
+# ---------------------------------------------------------------------------
+
+def _lod_bwd_setup(rt, seed, W, H, n, C, mode):
+    """The camera views of _views_case over an i.i.d. texture: neighbouring
+    texels differ by O(1), so the binary32 rounding of the GPU chain's means
+    (about 1e-7 of the texel values) stays negligible against the texel
+    differences the view and uv gradients are made of (a smooth texture's
+    differences can be 1e-3 of its values)."""
+    gb, _, duv = _views_case(seed, W, H, n, C)
+    tex = torch.rand((H, W, n, n, C), generator=torch.Generator().manual_seed(seed + 9)).to(DEV)
+    uv, tbn, view = gb_host(gb)
+    keep = away_from_edges(uv, tbn, view, W, H, n, mode) & _lod_keep(host(duv), W, H)
+    k = torch.from_numpy(np.nonzero(keep)[0]).to(DEV)
+    gb = wl.GBuffer(gb.uv[k].contiguous(), gb.tbn[k].contiguous(), gb.view[k].contiguous())
+    duv = duv[k].contiguous()
+    go = torch.randn((gb.count, C), generator=torch.Generator().manual_seed(seed + 5)).to(DEV)
+    chain = rt.build_mips(rt.Texture(tex, W, H, n, C))
+    return gb, tex, duv, go, chain
+
+
+@pytest.mark.parametrize("mode", ["nearest", "bilinear"])
+def test_lod_backward_vs_oracle(rt, mode):
+    from helpers import check_grad_tex, check_grad_vec
+    W, H, n, C = 32, 16, 8, 4
+    gb, tex, duv, go, chain = _lod_bwd_setup(rt, 51, W, H, n, C, mode)
+    grads, gv, gu = rt.lookup_lod_bwd(chain, gb.uv, gb.tbn, gb.view, duv, go, mode)
+    g2, gv2, gu2 = rt.lookup_lod_bwd(chain, gb.uv, gb.tbn, gb.view, duv, go, mode)
+    torch.cuda.synchronize()
+    assert all(torch.equal(a, b) for a, b in zip(grads, g2))  # bitwise reproducible
+    assert torch.equal(gv, gv2) and torch.equal(gu, gu2)
+    uv, tbn, view = gb_host(gb)
+    och = oracle.build_mips(host(tex), W, H, n, C, len(chain))  # the oracle's own chain
+    omode = oracle.MODE_NEAREST if mode == "nearest" else oracle.MODE_BILINEAR
+    ref = oracle.lookup_lod_bwd(och, uv, tbn, view, host(duv), host(go), W, H, n, C, mode=omode,
+                                full=True)
+    reached = 0
+    for l in range(len(chain)):
+        r = {"grad_tex": ref["grad"][l], "abs_tex": ref["abs"][l], "absg_tex": ref["absg"][l]}
+        check_grad_tex(host(grads[l]), r, n)
+        reached += int(np.any(ref["grad"][l] != 0))
+    assert reached >= 4
+    # as for the plain backward: away from the kinks of the mapping (texel
+    # lines, clamp bounds, the diagonal of Eq. (3)), the same in every level
+    _, _, edge = oracle.indices(uv, tbn, view, W, H, n)
+    keep = (edge[:, 1] >= 1e-5) & (edge[:, 2] >= 1e-5)
+    assert keep.mean() > 0.9
+    check_grad_vec(host(gv)[keep], ref["grad_view"][keep], ref["scale_view"][keep])
+    check_grad_vec(host(gu)[keep], ref["grad_uv"][keep], ref["scale_uv"][keep])
+
+
+def test_lod_backward_of_one_level_is_the_plain_backward(rt):
+    W, H, n, C = 16, 8, 4, 3
+    gb, tex, duv, go, chain = _lod_bwd_setup(rt, 53, W, H, n, C, "bilinear")
+    grads, gv, gu = rt.lookup_lod_bwd(chain[:1], gb.uv, gb.tbn, gb.view, duv, go, "bilinear")
+    gt, gv1, gu1 = rt.lookup_bwd(chain[0], gb.uv, gb.tbn, gb.view, go, mode="bilinear")
+    torch.cuda.synchronize()
+    assert torch.equal(grads[0], gt) and torch.equal(gv, gv1) and torch.equal(gu, gu1)
+
+
+@pytest.mark.parametrize("W,H", [(16, 8), (1, 16), (8, 1), (2, 2)])
+def test_mip_adjoint_vs_oracle(rt, W, H):
+    n, C = 3, 2
+    g = torch.Generator().manual_seed(W + 7 * H)
+    src = rt.Texture(torch.zeros((H, W, n, n, C), device=DEV), W, H, n, C)
+    W2, H2 = max(1, W // 2), max(1, H // 2)
+    gd = torch.randn((H2, W2, n, n, C), generator=g)
+    gs0 = torch.randn((H, W, n, n, C), generator=g)
+    gs = gs0.clone().to(DEV)
+    rt.build_mip_adjoint(src, gd.to(DEV), gs)
+    torch.cuda.synchronize()
+    ref = oracle.build_mip_adjoint(gd.numpy(), W, H, n, C,
+                                   grad_src=gs0.numpy().astype(np.float64).copy())
+    np.testing.assert_allclose(host(gs), ref, rtol=0, atol=1e-6)
+
+
+def test_chain_gradient_reaches_level_zero(rt):
+    """The loss through the chain built from level 0: folding every level's
+    gradient down with the adjoint gives dL/d(level 0), checked against the
+    linearity of the whole map (build the chain of a random perturbation of
+    level 0, look it up, and compare sum g . out with the folded gradient)."""
+    W, H, n, C = 16, 16, 4, 2
+    gb, tex, duv, go, chain = _lod_bwd_setup(rt, 55, W, H, n, C, "nearest")
+    grads, _, _ = rt.lookup_lod_bwd(chain, gb.uv, gb.tbn, gb.view, duv, go, want_view=False,
+                                    want_uv=False)
+    for l in range(len(chain) - 1, 0, -1):
+        rt.build_mip_adjoint(chain[l - 1], grads[l], grads[l - 1])
+    torch.cuda.synchronize()
+    g0 = host(grads[0]).astype(np.float64)
+    rng = np.random.default_rng(56)
+    delta = rng.normal(size=(H, W, n, n, C))
+    och = oracle.build_mips(delta, W, H, n, C, len(chain))
+    uv, tbn, view = gb_host(gb)
+    out, _ = oracle.lookup_lod(och, uv, tbn, view, host(duv), W, H, n, C)
+    lhs = float(np.sum(host(go).astype(np.float64) * out))
+    rhs = float(np.sum(g0 * delta))
+    assert abs(lhs - rhs) <= 1e-4 * np.sum(np.abs(host(go))) * np.abs(delta).max(), (lhs, rhs)
