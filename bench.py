@@ -610,6 +610,31 @@ def main():
             b.synchronize()
             ms.append(a.elapsed_time(b))
         q = [round(float(x), 5) for x in np.percentile(np.array(ms), [10, 50, 90])]
+        # backward of the level-of-detail lookup (every level's texel gradient,
+        # view and uv gradients), upstream gradient of unit normal entries
+        go = torch.randn(out.shape, generator=torch.Generator(device=dev).manual_seed(17),
+                         device=dev)
+        ws = torch.empty(max(rt.lookup_lod_bwd_workspace(chain, N), 1), dtype=torch.uint8,
+                         device=dev)
+        for _ in range(2):
+            rt.lookup_lod_bwd(chain, gb.uv, gb.tbn, gb.view, gb.duv, go, workspace=ws,
+                              image=gb.image)
+        torch.cuda.synchronize()
+        bms = []
+        rt.profile_reset()
+        rt.profile_enable(True)
+        for _ in range(10):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            rt.lookup_lod_bwd(chain, gb.uv, gb.tbn, gb.view, gb.duv, go, workspace=ws,
+                              image=gb.image)
+            b.record()
+            b.synchronize()
+            bms.append(a.elapsed_time(b))
+        rt.profile_enable(False)
+        bprof = {k: round(v[1] / 10, 5) for k, v in rt.profile_read().items() if v[0] > 0}
+        bq = [round(float(x), 5) for x in np.percentile(np.array(bms), [10, 50, 90])]
+        del ws, go
         d = gb.duv.to(torch.float64)
         rho = torch.maximum(torch.hypot(d[:, 0] * W, d[:, 1] * H), torch.hypot(d[:, 2] * W, d[:, 3] * H))
         lam = torch.clamp(torch.log2(rho), 0, L - 1)
@@ -619,6 +644,7 @@ def main():
                "lod_fwd_ms_p10_p50_p90": q,
                "lod_fwd_lookups_per_s": round(N / (q[1] * 1e-3), 1),
                "plain_fwd_f32_ms": formats["f32"]["fwd_ms"],
+               "lod_bwd_ms_p10_p50_p90": bq, "lod_bwd_kernel_ms": bprof,
                "lambda_min_mean_max": [round(float(lam.min()), 3), round(float(lam.mean()), 3),
                                        round(float(lam.max()), 3)],
                "note": "FP32 chain of the whole matrix; the lookup takes each pixel's UV "

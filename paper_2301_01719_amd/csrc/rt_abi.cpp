@@ -585,7 +585,9 @@ bool plan_lod_backward(const rt_texture* const* levels, int nlevels, int64_t N, 
     size_t bwd = 0;
     for (int l = 0; l < nlevels; l++) {
         const rt::TexView& v = levels[l]->view;
-        if (!rt::plan_backward(v.W, v.H, v.n, v.C, N, mode, &plans[l])) return false;
+        // sparse: a fragment makes records only on the (one or two) levels it
+        // blends; on the others its scaled upstream gradient is zero
+        if (!rt::plan_backward(v.W, v.H, v.n, v.C, N, mode, &plans[l], true)) return false;
         bwd = std::max(bwd, plans[l].total);
     }
     auto a256 = [](size_t x) { return (x + 255) & ~(size_t)255; };

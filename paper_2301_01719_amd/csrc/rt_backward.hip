@@ -109,16 +109,34 @@ __global__ __launch_bounds__(256) void k_bwd_fragment(
     TexView t, const float* __restrict__ uv, const float* __restrict__ tbn,
     const float* __restrict__ view, const float* __restrict__ grad_out,
     float* __restrict__ grad_view, float* __restrict__ grad_uv, uint32_t* __restrict__ keys,
-    float* __restrict__ wrec, FragMap m, int cell_bits) {
+    float* __restrict__ wrec, FragMap m, int cell_bits, uint32_t sentinel) {
     const int64_t f = frag_of(m, blockIdx.x, gridDim.x, threadIdx.x);
     if (f < 0) return;
     const int n = t.n;
+    float go[4] = {0.f, 0.f, 0.f, 0.f};
+    bool zero = true;
+#pragma unroll
+    for (int c = 0; c < C; c++) {
+        go[c] = grad_out[f * C + c];
+        zero = zero && go[c] == 0.f;
+    }
+    if (sentinel != 0u && zero) {
+        // sparse plan: no contribution, no records; its gradients are 0
+        if (grad_view) {
+            grad_view[f * 3 + 0] = 0.f;
+            grad_view[f * 3 + 1] = 0.f;
+            grad_view[f * 3 + 2] = 0.f;
+        }
+        if (grad_uv) ((float2*)grad_uv)[f] = make_float2(0.f, 0.f);
+        if (keys) {
+            if constexpr (MODE == MODE_NEAREST) keys[f] = sentinel;
+            else ((uint4*)keys)[f] = make_uint4(sentinel, sentinel, sentinel, sentinel);
+        }
+        return;
+    }
     Frag g = load_frag(uv, tbn, view, f);
     Dir d = map_direction(g.m, g.w, n);
     Foot p = footprint(d.sx, d.sy, n);
-    float go[4] = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int c = 0; c < C; c++) go[c] = grad_out[f * C + c];
     const uint32_t cell = (uint32_t)(p.y0 * n + p.x0);
 
     float gsx = 0.f, gsy = 0.f;
@@ -413,11 +431,12 @@ __global__ __launch_bounds__(256) void k_fill_u32(uint32_t* __restrict__ p, int6
 }
 
 __global__ __launch_bounds__(256) void k_bucket_ranges(const uint32_t* __restrict__ skeys,
-                                                       int64_t R, int cell_bits,
+                                                       int64_t R, int cell_bits, int64_t nb,
                                                        int2* __restrict__ range) {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (i >= R) return;
     const uint32_t b = skeys[i] >> cell_bits;
+    if (b >= nb) return;  // records of a sparse plan without a bucket (sorted last)
     if (i == 0 || (skeys[i - 1] >> cell_bits) != b) range[b].x = (int)i;
     if (i == R - 1 || (skeys[i + 1] >> cell_bits) != b) range[b].y = (int)(i + 1);
 }
@@ -815,7 +834,7 @@ __global__ __launch_bounds__(64) void k_segacc_hot(const uint32_t* __restrict__ 
                                                    const float* __restrict__ grad_out,
                                                    const int2* __restrict__ range,
                                                    float* __restrict__ part, int64_t R, int n,
-                                                   int cell_bits) {
+                                                   int cell_bits, int64_t nb) {
     extern __shared__ float lds[];
     const int te = n * n * C;
     const uint32_t cell_mask = (cell_bits >= 32) ? 0xFFFFFFFFu : ((1u << cell_bits) - 1u);
@@ -827,6 +846,7 @@ __global__ __launch_bounds__(64) void k_segacc_hot(const uint32_t* __restrict__ 
     for (int slot = 0; slot < 2; slot++) {
         const uint32_t b = slot == 0 ? bf : bl;
         if (slot == 1 && bl == bf) break;
+        if (b >= nb) break;  // the records past the last bucket (sparse plans)
         const int2 r = range[b];
         if ((int64_t)r.y - r.x <= PIECE) continue;
         const int64_t a = r.x > c0 ? r.x : c0;
@@ -844,7 +864,7 @@ __global__ __launch_bounds__(64) void k_combine_hot(const uint32_t* __restrict__
                                                     const int2* __restrict__ range,
                                                     const float* __restrict__ part,
                                                     float* __restrict__ grad_tex, int64_t R,
-                                                    int te, int cell_bits) {
+                                                    int te, int cell_bits, int64_t nb) {
     const int lane = threadIdx.x;
     const int64_t k = blockIdx.x;
     const int64_t c0 = k * PIECE;
@@ -854,6 +874,7 @@ __global__ __launch_bounds__(64) void k_combine_hot(const uint32_t* __restrict__
     for (int slot = 0; slot < 2; slot++) {
         const uint32_t b = slot == 0 ? bf : bl;
         if (slot == 1 && bl == bf) break;
+        if (b >= nb) break;  // the records past the last bucket (sparse plans)
         const int2 r = range[b];
         if ((int64_t)r.y - r.x <= PIECE) continue;
         if ((int64_t)r.x / PIECE != k) continue;  // combined by the chunk it starts in
@@ -893,11 +914,12 @@ static int ceil_log2(uint64_t x) {
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-bool plan_backward(int W, int H, int n, int C, int64_t N, int mode, BwdPlan* p) {
+bool plan_backward(int W, int H, int n, int C, int64_t N, int mode, BwdPlan* p, bool sparse) {
     // the accumulation holds four bucket tiles per workgroup in LDS (64 KiB)
     if ((int64_t)n * n * C > 4096) return false;
     const int64_t nb = (int64_t)W * H;
-    const int bucket_bits = ceil_log2((uint64_t)nb);
+    // a sparse plan keeps the all-ones key free for records without a bucket
+    const int bucket_bits = ceil_log2((uint64_t)nb + (sparse ? 1 : 0));
     const int cell_bits = ceil_log2((uint64_t)n * n);
     if (bucket_bits + cell_bits > 32) return false;
     const int64_t R = mode == MODE_NEAREST ? N : 4 * N;
@@ -905,6 +927,9 @@ bool plan_backward(int W, int H, int n, int C, int64_t N, int mode, BwdPlan* p) 
     p->records = R;
     p->key_bits = bucket_bits + cell_bits;
     p->cell_bits = cell_bits;
+    p->buckets = nb;
+    p->sentinel = !sparse ? 0u
+                  : (p->key_bits >= 32 ? 0xFFFFFFFFu : (uint32_t)((1ull << p->key_bits) - 1));
     // as few passes as digits of at most 10 bits allow (9 bits beyond 4M
     // records, where the histograms, their scan and the scatter's LDS, which
     // grow as 2^D, cost more than a pass saves), the bits spread evenly
@@ -958,13 +983,13 @@ template <int FMT, int MODE>
 static void launch_bwd_fragment_c(const TexView& t, const float* uv, const float* tbn,
                                   const float* view, const float* go, float* gview, float* guv,
                                   uint32_t* keys, float* wrec, const FragMap& m, int cell_bits,
-                                  hipStream_t s) {
+                                  uint32_t sentinel, hipStream_t s) {
     const uint32_t blocks = fragmap_blocks(m);
     switch (t.C) {
-    case 1: hipLaunchKernelGGL((k_bwd_fragment<FMT, 1, MODE>), dim3(blocks), dim3(256), 0, s, t, uv, tbn, view, go, gview, guv, keys, wrec, m, cell_bits); break;
-    case 2: hipLaunchKernelGGL((k_bwd_fragment<FMT, 2, MODE>), dim3(blocks), dim3(256), 0, s, t, uv, tbn, view, go, gview, guv, keys, wrec, m, cell_bits); break;
-    case 3: hipLaunchKernelGGL((k_bwd_fragment<FMT, 3, MODE>), dim3(blocks), dim3(256), 0, s, t, uv, tbn, view, go, gview, guv, keys, wrec, m, cell_bits); break;
-    default: hipLaunchKernelGGL((k_bwd_fragment<FMT, 4, MODE>), dim3(blocks), dim3(256), 0, s, t, uv, tbn, view, go, gview, guv, keys, wrec, m, cell_bits); break;
+    case 1: hipLaunchKernelGGL((k_bwd_fragment<FMT, 1, MODE>), dim3(blocks), dim3(256), 0, s, t, uv, tbn, view, go, gview, guv, keys, wrec, m, cell_bits, sentinel); break;
+    case 2: hipLaunchKernelGGL((k_bwd_fragment<FMT, 2, MODE>), dim3(blocks), dim3(256), 0, s, t, uv, tbn, view, go, gview, guv, keys, wrec, m, cell_bits, sentinel); break;
+    case 3: hipLaunchKernelGGL((k_bwd_fragment<FMT, 3, MODE>), dim3(blocks), dim3(256), 0, s, t, uv, tbn, view, go, gview, guv, keys, wrec, m, cell_bits, sentinel); break;
+    default: hipLaunchKernelGGL((k_bwd_fragment<FMT, 4, MODE>), dim3(blocks), dim3(256), 0, s, t, uv, tbn, view, go, gview, guv, keys, wrec, m, cell_bits, sentinel); break;
     }
 }
 
@@ -997,12 +1022,13 @@ static void launch_segacc_big_c(int C, dim3 grid, size_t shm, hipStream_t s, con
 template <int MODE>
 static void launch_segacc_hot_c(int C, dim3 grid, size_t shm, hipStream_t s, const uint32_t* sk,
                                 const uint32_t* sv, const float* wrec, const float* go,
-                                const int2* range, float* part, int64_t R, int n, int cb) {
+                                const int2* range, float* part, int64_t R, int n, int cb,
+                                int64_t nb) {
     switch (C) {
-    case 1: hipLaunchKernelGGL((k_segacc_hot<1, MODE>), grid, dim3(64), shm, s, sk, sv, wrec, go, range, part, R, n, cb); break;
-    case 2: hipLaunchKernelGGL((k_segacc_hot<2, MODE>), grid, dim3(64), shm, s, sk, sv, wrec, go, range, part, R, n, cb); break;
-    case 3: hipLaunchKernelGGL((k_segacc_hot<3, MODE>), grid, dim3(64), shm, s, sk, sv, wrec, go, range, part, R, n, cb); break;
-    default: hipLaunchKernelGGL((k_segacc_hot<4, MODE>), grid, dim3(64), shm, s, sk, sv, wrec, go, range, part, R, n, cb); break;
+    case 1: hipLaunchKernelGGL((k_segacc_hot<1, MODE>), grid, dim3(64), shm, s, sk, sv, wrec, go, range, part, R, n, cb, nb); break;
+    case 2: hipLaunchKernelGGL((k_segacc_hot<2, MODE>), grid, dim3(64), shm, s, sk, sv, wrec, go, range, part, R, n, cb, nb); break;
+    case 3: hipLaunchKernelGGL((k_segacc_hot<3, MODE>), grid, dim3(64), shm, s, sk, sv, wrec, go, range, part, R, n, cb, nb); break;
+    default: hipLaunchKernelGGL((k_segacc_hot<4, MODE>), grid, dim3(64), shm, s, sk, sv, wrec, go, range, part, R, n, cb, nb); break;
     }
 }
 
@@ -1055,13 +1081,13 @@ hipError_t launch_backward(const TexView& t, int fmt, int mode, const float* uv,
         prof_begin(K_BWD_FRAGMENT, s);
         uint32_t* kp = want_tex ? keys0 : nullptr;
         if (mode == MODE_NEAREST) {
-            if (fmt == FMT_F32) launch_bwd_fragment_c<FMT_F32, MODE_NEAREST>(t, uv, tbn, view, grad_out, grad_view, grad_uv, kp, wrec, m, plan.cell_bits, s);
-            else if (fmt == FMT_BF16) launch_bwd_fragment_c<FMT_BF16, MODE_NEAREST>(t, uv, tbn, view, grad_out, grad_view, grad_uv, kp, wrec, m, plan.cell_bits, s);
-            else launch_bwd_fragment_c<FMT_FP8, MODE_NEAREST>(t, uv, tbn, view, grad_out, grad_view, grad_uv, kp, wrec, m, plan.cell_bits, s);
+            if (fmt == FMT_F32) launch_bwd_fragment_c<FMT_F32, MODE_NEAREST>(t, uv, tbn, view, grad_out, grad_view, grad_uv, kp, wrec, m, plan.cell_bits, plan.sentinel, s);
+            else if (fmt == FMT_BF16) launch_bwd_fragment_c<FMT_BF16, MODE_NEAREST>(t, uv, tbn, view, grad_out, grad_view, grad_uv, kp, wrec, m, plan.cell_bits, plan.sentinel, s);
+            else launch_bwd_fragment_c<FMT_FP8, MODE_NEAREST>(t, uv, tbn, view, grad_out, grad_view, grad_uv, kp, wrec, m, plan.cell_bits, plan.sentinel, s);
         } else {
-            if (fmt == FMT_F32) launch_bwd_fragment_c<FMT_F32, MODE_BILINEAR>(t, uv, tbn, view, grad_out, grad_view, grad_uv, kp, wrec, m, plan.cell_bits, s);
-            else if (fmt == FMT_BF16) launch_bwd_fragment_c<FMT_BF16, MODE_BILINEAR>(t, uv, tbn, view, grad_out, grad_view, grad_uv, kp, wrec, m, plan.cell_bits, s);
-            else launch_bwd_fragment_c<FMT_FP8, MODE_BILINEAR>(t, uv, tbn, view, grad_out, grad_view, grad_uv, kp, wrec, m, plan.cell_bits, s);
+            if (fmt == FMT_F32) launch_bwd_fragment_c<FMT_F32, MODE_BILINEAR>(t, uv, tbn, view, grad_out, grad_view, grad_uv, kp, wrec, m, plan.cell_bits, plan.sentinel, s);
+            else if (fmt == FMT_BF16) launch_bwd_fragment_c<FMT_BF16, MODE_BILINEAR>(t, uv, tbn, view, grad_out, grad_view, grad_uv, kp, wrec, m, plan.cell_bits, plan.sentinel, s);
+            else launch_bwd_fragment_c<FMT_FP8, MODE_BILINEAR>(t, uv, tbn, view, grad_out, grad_view, grad_uv, kp, wrec, m, plan.cell_bits, plan.sentinel, s);
         }
         prof_end(K_BWD_FRAGMENT, s);
         hipError_t e = hipGetLastError();
@@ -1106,7 +1132,7 @@ hipError_t launch_backward(const TexView& t, int fmt, int mode, const float* uv,
     if (R > 0) {
         prof_begin(K_BUCKET_RANGES, s);
         hipLaunchKernelGGL(k_bucket_ranges, dim3((uint32_t)((R + 255) / 256)), dim3(256), 0, s,
-                           skeys, R, plan.cell_bits, range);
+                           skeys, R, plan.cell_bits, nb, range);
         prof_end(K_BUCKET_RANGES, s);
     }
 
@@ -1140,13 +1166,13 @@ hipError_t launch_backward(const TexView& t, int fmt, int mode, const float* uv,
         const dim3 g2((uint32_t)plan.chunks);
         prof_begin(K_SEGACC_HOT, s);
         if (mode == MODE_NEAREST)
-            launch_segacc_hot_c<MODE_NEAREST>(t.C, g2, (size_t)te * 4, s, skeys, svals, wrec, grad_out, range, part, R, t.n, plan.cell_bits);
+            launch_segacc_hot_c<MODE_NEAREST>(t.C, g2, (size_t)te * 4, s, skeys, svals, wrec, grad_out, range, part, R, t.n, plan.cell_bits, nb);
         else
-            launch_segacc_hot_c<MODE_BILINEAR>(t.C, g2, (size_t)te * 4, s, skeys, svals, wrec, grad_out, range, part, R, t.n, plan.cell_bits);
+            launch_segacc_hot_c<MODE_BILINEAR>(t.C, g2, (size_t)te * 4, s, skeys, svals, wrec, grad_out, range, part, R, t.n, plan.cell_bits, nb);
         prof_end(K_SEGACC_HOT, s);
         prof_begin(K_COMBINE_HOT, s);
         hipLaunchKernelGGL(k_combine_hot, g2, dim3(64), 0, s, skeys, range, part, grad_tex, R, te,
-                           plan.cell_bits);
+                           plan.cell_bits, nb);
         prof_end(K_COMBINE_HOT, s);
     }
     return hipGetLastError();

@@ -115,6 +115,9 @@ struct BwdPlan {
     int64_t chunks;       // fixed chunks of the sorted records (hot buckets)
     int64_t tile_elems;   // n*n*C
     int64_t big_cap;      // entries per big-bucket list (one list per counter)
+    int64_t buckets;      // W * H
+    uint32_t sentinel;    // sparse plans: the key of a fragment whose upstream
+                          // gradient is zero (past every bucket); 0 otherwise
     // workspace offsets (bytes)
     size_t off_keys0, off_keys1, off_vals0, off_vals1, off_wrec, off_hist, off_hoff, off_scanp,
         off_range, off_biglist, off_part, total;
@@ -124,7 +127,10 @@ constexpr int SEG_GROUP = 8;  // buckets per wavefront in the first accumulation
 constexpr int BIG_LISTS = 64; // big-bucket lists, each with its own counter
 constexpr int BIG_STRIDE = 64;  // u32 between two counters (256 bytes)
 constexpr int BIG_RUN = 64;     // consecutive groups that append to one list
-bool plan_backward(int W, int H, int n, int C, int64_t N, int mode, BwdPlan* p);
+// sparse: fragments whose upstream gradient is all zero make no records (their
+// keys sort past every bucket and are skipped), at the price of one key bit.
+bool plan_backward(int W, int H, int n, int C, int64_t N, int mode, BwdPlan* p,
+                   bool sparse = false);
 
 // Backward of the level-of-detail lookup: one plain backward per level, on
 // the upstream gradient scaled by the level's weight.  Workspace: the largest

@@ -7,8 +7,11 @@
 // texels is the plain backward on level l with each fragment's upstream
 // gradient scaled by its weight on that level, and the view and uv gradients
 // are the sums over the levels of the plain backward's.  Each level reuses
-// the deterministic sort-and-accumulate backward; the per-level view and uv
-// gradients are added in level order, so the result is bitwise reproducible.
+// the deterministic sort-and-accumulate backward with a sparse plan: a
+// fragment whose weight on the level is 0 makes no records there (otherwise
+// the coarse levels' few buckets would each collect every fragment of the
+// view).  The per-level view and uv gradients are added in level order, so
+// the result is bitwise reproducible.
 //
 // Chain adjoint: level l+1's bucket is the mean of the 2 x 2 (or 2) buckets of
 // level l it covers, so each of those receives the parent's gradient divided

@@ -372,6 +372,12 @@ def build_mips(tex: Texture, levels: Optional[int] = None):
     return chain
 
 
+def lookup_lod_bwd_workspace(levels, count: int, mode: str = "nearest") -> int:
+    """Bytes of workspace rt_lookup_lod_bwd needs for `count` fragments."""
+    handles = (ctypes.c_void_p * len(levels))(*[t.handle for t in levels])
+    return int(LIB.rt_lookup_lod_bwd_workspace(handles, len(levels), count, MODES[mode]))
+
+
 def lookup_lod_bwd(levels, uv, tbn, view, duv, grad_out, mode: str = "nearest",
                    want_levels=True, want_view=True, want_uv=True, workspace=None, image=None):
     """Backward of lookup_fwd_lod (rt_lookup_lod_bwd): returns (per-level
@@ -390,7 +396,7 @@ def lookup_lod_bwd(levels, uv, tbn, view, duv, grad_out, mode: str = "nearest",
     gptr = (ctypes.c_void_p * L)(*[None if g is None else g.data_ptr() for g in grads])
     gv = torch.empty((fr.count, 3), dtype=torch.float32, device=dev) if want_view else None
     gu = torch.empty((fr.count, 2), dtype=torch.float32, device=dev) if want_uv else None
-    need = LIB.rt_lookup_lod_bwd_workspace(handles, L, fr.count, MODES[mode])
+    need = lookup_lod_bwd_workspace(levels, fr.count, mode)
     if workspace is None:
         workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
     _check(LIB.rt_lookup_lod_bwd(handles, L, ctypes.byref(fr), _ptr(duv), _ptr(grad_out), gptr,

@@ -212,6 +212,47 @@ def test_lod_backward_vs_oracle(rt, mode):
     check_grad_vec(host(gu)[keep], ref["grad_uv"][keep], ref["scale_uv"][keep])
 
 
+@pytest.mark.parametrize("mode", ["nearest", "bilinear"])
+def test_lod_backward_hot_coarse_level(rt, mode):
+    """A 2 x 2 matrix and its 1 x 1 level under 12000 fragments with lambda
+    uniform in [-1, 1]: every bucket of both levels holds more than a chunk of
+    records (the pieces-and-combine path), and about half the fragments have
+    weight 0 on level 1 (their records are left out there)."""
+    from helpers import check_grad_tex, check_grad_vec
+    W, H, n, C, N = 2, 2, 4, 2, 12000
+    gb = wl.flat_gbuffer(N, seed=71, device=DEV)
+    g = torch.Generator().manual_seed(72)
+    rho = torch.exp2(torch.rand(N, generator=g, dtype=torch.float64) * 2 - 1)
+    duv = torch.zeros((N, 4), dtype=torch.float64)
+    duv[:, 0] = rho / W
+    duv = duv.float()
+    uv, tbn, view = gb_host(gb)
+    keep = away_from_edges(uv, tbn, view, W, H, n, mode) & _lod_keep(duv.numpy(), W, H)
+    k = torch.from_numpy(np.nonzero(keep)[0]).to(DEV)
+    gb = wl.GBuffer(gb.uv[k].contiguous(), gb.tbn[k].contiguous(), gb.view[k].contiguous())
+    duv = duv.to(DEV)[k].contiguous()
+    tex = torch.rand((H, W, n, n, C), generator=g).to(DEV)
+    go = torch.randn((gb.count, C), generator=g).to(DEV)
+    chain = rt.build_mips(rt.Texture(tex, W, H, n, C))
+    assert len(chain) == 2
+    grads, gv, gu = rt.lookup_lod_bwd(chain, gb.uv, gb.tbn, gb.view, duv, go, mode)
+    torch.cuda.synchronize()
+    uv, tbn, view = gb_host(gb)
+    och = oracle.build_mips(host(tex), W, H, n, C, 2)
+    omode = oracle.MODE_NEAREST if mode == "nearest" else oracle.MODE_BILINEAR
+    ref = oracle.lookup_lod_bwd(och, uv, tbn, view, host(duv), host(go), W, H, n, C, mode=omode,
+                                full=True)
+    lam = np.log2(np.hypot(host(duv)[:, 0].astype(np.float64) * W, 0.0))
+    assert 0.4 < np.mean(lam <= 0) < 0.6  # weight 0 on level 1
+    for l in range(2):
+        r = {"grad_tex": ref["grad"][l], "abs_tex": ref["abs"][l], "absg_tex": ref["absg"][l]}
+        check_grad_tex(host(grads[l]), r, n)
+    _, _, edge = oracle.indices(uv, tbn, view, W, H, n)
+    keep = (edge[:, 1] >= 1e-5) & (edge[:, 2] >= 1e-5)
+    check_grad_vec(host(gv)[keep], ref["grad_view"][keep], ref["scale_view"][keep])
+    check_grad_vec(host(gu)[keep], ref["grad_uv"][keep], ref["scale_uv"][keep])
+
+
 def test_lod_backward_of_one_level_is_the_plain_backward(rt):
     W, H, n, C = 16, 8, 4, 3
     gb, tex, duv, go, chain = _lod_bwd_setup(rt, 53, W, H, n, C, "bilinear")
