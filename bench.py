@@ -54,9 +54,23 @@ KERNEL_SOURCES = {
     "k_bwd_fragment": "rt_backward.hip", "k_segacc": "rt_backward.hip",
     "k_segacc_big": "rt_backward.hip", "k_bake_env": "rt_bake.hip",
     "k_bake_shadow": "rt_bake.hip", "k_build_mip": "rt_mip.hip",
-    "k_vq_assign": "rt_dictionary.hip",
+    "k_vq_assign": "rt_dictionary.hip", "k_mip_adjoint": "rt_lod_backward.hip",
 }
 SHARED_SOURCES = ["rt_device.hpp", "rt_kernels.hpp"]
+
+# the shadow measurement (Sec. 5, Shadowing): balls over the plane tile, a sun
+# disc and a spherical lamp
+SHADOW_BALLS = 16
+SHADOW_CASES = (("sun", 1, "nearest"), ("sun", 16, "nearest"), ("sun", 64, "nearest"),
+                ("lamp", 16, "bilinear"))
+
+# the bucket-dictionary measurement: the matrix as repetitive buckets (each a
+# noisy copy of one of DICT_PROTOTYPES buckets of the smooth texture), encoded
+# into DICT_ENTRIES entries by DICT_ITERATIONS Lloyd steps
+DICT_PROTOTYPES = 64
+DICT_ENTRIES = 256
+DICT_NOISE = 0.01
+DICT_ITERATIONS = 3
 
 
 def source_hash(kernel: str) -> str:
@@ -328,9 +342,9 @@ def calibrate_copy():
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU: the lookup needs no communication and this build "
-              "runs on a single MI355X (see the sharding notes in DESIGN.md); use --gpus 1",
-              file=sys.stderr)
+        print("bench.py measures one GPU: the lookup needs no communication between GPUs "
+              "and the library runs on a single MI355X; sharding over several GPUs is not "
+              "built. Use --gpus 1", file=sys.stderr)
         sys.exit(2)
     if args.calibrate_copy:
         calibrate_copy()
@@ -391,7 +405,11 @@ def main():
                 for l in range(1, len(chain)):
                     rt.build_mip(chain[l - 1], out=chain[l].data)
                 rt.lookup_fwd_lod(chain, gb.uv, gb.tbn, gb.view, gb.duv, out=out, image=gb.image)
-            del chain
+            gls = [torch.zeros_like(t.data) for t in chain]
+            for _ in range(args.profile_mip):
+                for l in range(len(chain) - 1, 0, -1):
+                    rt.build_mip_adjoint(chain[l - 1], gls[l], gls[l - 1])
+            del chain, gls
         if args.profile_shadow and gb.pos is not None:
             run_shadow(rt, w, gb, args.profile_shadow, timed=False)
         if args.profile_dictionary:
@@ -635,6 +653,20 @@ def main():
         bprof = {k: round(v[1] / 10, 5) for k, v in rt.profile_read().items() if v[0] > 0}
         bq = [round(float(x), 5) for x in np.percentile(np.array(bms), [10, 50, 90])]
         del ws, go
+        # the chain's adjoint: every level's gradient folded down to level 0
+        # (each step reads the parent's and the child's gradient, writes the child's)
+        gls = [torch.zeros_like(t.data) for t in chain]
+        torch.cuda.synchronize()
+        rt.profile_reset()
+        rt.profile_enable(True)
+        for _ in range(3):
+            for l in range(L - 1, 0, -1):
+                rt.build_mip_adjoint(chain[l - 1], gls[l], gls[l - 1])
+        torch.cuda.synchronize()
+        rt.profile_enable(False)
+        adj_ms = rt.profile_read()["k_mip_adjoint"][1] / 3
+        adj_bytes = sum(lvl_bytes[1:]) + 2 * sum(lvl_bytes[:-1])
+        del gls
         d = gb.duv.to(torch.float64)
         rho = torch.maximum(torch.hypot(d[:, 0] * W, d[:, 1] * H), torch.hypot(d[:, 2] * W, d[:, 3] * H))
         lam = torch.clamp(torch.log2(rho), 0, L - 1)
@@ -645,6 +677,8 @@ def main():
                "lod_fwd_lookups_per_s": round(N / (q[1] * 1e-3), 1),
                "plain_fwd_f32_ms": formats["f32"]["fwd_ms"],
                "lod_bwd_ms_p10_p50_p90": bq, "lod_bwd_kernel_ms": bprof,
+               "adjoint_chain_ms": round(adj_ms, 5), "adjoint_alg_bytes": adj_bytes,
+               "adjoint_hbm_frac": round(adj_bytes / (adj_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                "lambda_min_mean_max": [round(float(lam.min()), 3), round(float(lam.mean()), 3),
                                        round(float(lam.max()), 3)],
                "note": "FP32 chain of the whole matrix; the lookup takes each pixel's UV "
