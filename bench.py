@@ -630,12 +630,12 @@ def main():
         q = [round(float(x), 5) for x in np.percentile(np.array(ms), [10, 50, 90])]
         # backward of the level-of-detail lookup (every level's texel gradient,
         # view and uv gradients), upstream gradient of unit normal entries
-        go = torch.randn(out.shape, generator=torch.Generator(device=dev).manual_seed(17),
+        go_lod = torch.randn(out.shape, generator=torch.Generator(device=dev).manual_seed(17),
                          device=dev)
-        ws = torch.empty(max(rt.lookup_lod_bwd_workspace(chain, N), 1), dtype=torch.uint8,
+        ws_lod = torch.empty(max(rt.lookup_lod_bwd_workspace(chain, N), 1), dtype=torch.uint8,
                          device=dev)
         for _ in range(2):
-            rt.lookup_lod_bwd(chain, gb.uv, gb.tbn, gb.view, gb.duv, go, workspace=ws,
+            rt.lookup_lod_bwd(chain, gb.uv, gb.tbn, gb.view, gb.duv, go_lod, workspace=ws_lod,
                               image=gb.image)
         torch.cuda.synchronize()
         bms = []
@@ -644,7 +644,7 @@ def main():
         for _ in range(10):
             a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             a.record()
-            rt.lookup_lod_bwd(chain, gb.uv, gb.tbn, gb.view, gb.duv, go, workspace=ws,
+            rt.lookup_lod_bwd(chain, gb.uv, gb.tbn, gb.view, gb.duv, go_lod, workspace=ws_lod,
                               image=gb.image)
             b.record()
             b.synchronize()
@@ -652,7 +652,7 @@ def main():
         rt.profile_enable(False)
         bprof = {k: round(v[1] / 10, 5) for k, v in rt.profile_read().items() if v[0] > 0}
         bq = [round(float(x), 5) for x in np.percentile(np.array(bms), [10, 50, 90])]
-        del ws, go
+        del ws_lod, go_lod
         # the chain's adjoint: every level's gradient folded down to level 0
         # (each step reads the parent's and the child's gradient, writes the child's)
         gls = [torch.zeros_like(t.data) for t in chain]
