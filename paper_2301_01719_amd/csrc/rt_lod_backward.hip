@@ -17,6 +17,8 @@
 // level l it covers, so each of those receives the parent's gradient divided
 // by their number (one thread per element of level l: no two threads write
 // one element).
+#include <algorithm>
+
 #include "rt_device.hpp"
 #include "rt_kernels.hpp"
 
@@ -95,28 +97,56 @@ hipError_t launch_lookup_lod_bwd(const TexView* levels, int nlevels, int fmt, in
 }
 
 // grad_src (level l, W x H buckets of E values) += adjoint of the chain step
-// applied to grad_dst (level l+1)
+// applied to grad_dst (level l+1).  One workgroup per bucket of level l, so
+// the parent's position is worked out once per bucket; the bucket's E values
+// and its parent's are streamed with 16-byte accesses when both buffers allow.
+// Each element adds its parent's value times 1/2 or 1/4 (an exact product).
+template <bool VEC>
 __global__ __launch_bounds__(256) void k_mip_adjoint(const float* __restrict__ grad_dst,
                                                      float* __restrict__ grad_src, int W, int H,
-                                                     int64_t E) {
-    const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    const int64_t total = (int64_t)W * H * E;
-    if (q >= total) return;
-    const int64_t b = q / E, e = q - b * E;
+                                                     int E) {
+    const int64_t b = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
+    if (b >= (int64_t)W * H) return;
     const int j = (int)(b / W), i = (int)(b - (int64_t)j * W);
     const int fx = W > 1 ? 2 : 1, fy = H > 1 ? 2 : 1;
     const int W2 = W > 1 ? W / 2 : 1;
     const int64_t parent = (int64_t)(j / fy) * W2 + i / fx;
-    grad_src[q] += grad_dst[parent * E + e] * (1.0f / (float)(fx * fy));
+    const float s = 1.0f / (float)(fx * fy);
+    const float* __restrict__ src = grad_dst + parent * E;
+    float* __restrict__ dst = grad_src + b * E;
+    if constexpr (VEC) {
+        const float4* s4 = (const float4*)src;
+        float4* d4 = (float4*)dst;
+        for (int q = threadIdx.x; q < E / 4; q += 256) {
+            const float4 p = s4[q];
+            float4 d = d4[q];
+            d.x += p.x * s;
+            d.y += p.y * s;
+            d.z += p.z * s;
+            d.w += p.w * s;
+            d4[q] = d;
+        }
+    } else {
+        for (int q = threadIdx.x; q < E; q += 256) dst[q] += src[q] * s;
+    }
 }
 
 hipError_t launch_mip_adjoint(const TexView& src, const float* grad_dst, float* grad_src,
                               hipStream_t s) {
-    const int64_t E = (int64_t)src.n * src.n * src.C;
-    const int64_t total = (int64_t)src.W * src.H * E;
+    const int E = src.n * src.n * src.C;
+    const int64_t nb = (int64_t)src.W * src.H;
+    // buckets as a 2-D grid of at most 65535 rows of 65536 workgroups
+    const uint32_t gx = (uint32_t)std::min<int64_t>(nb, 65536);
+    const uint32_t gy = (uint32_t)((nb + gx - 1) / gx);
+    const bool vec = (E % 4) == 0 && ((uintptr_t)grad_dst % 16) == 0 &&
+                     ((uintptr_t)grad_src % 16) == 0;
     prof_begin(K_MIP_ADJOINT, s);
-    hipLaunchKernelGGL(k_mip_adjoint, dim3(blocks_of(total)), dim3(256), 0, s, grad_dst, grad_src,
-                       src.W, src.H, E);
+    if (vec)
+        hipLaunchKernelGGL(k_mip_adjoint<true>, dim3(gx, gy), dim3(256), 0, s, grad_dst, grad_src,
+                           src.W, src.H, E);
+    else
+        hipLaunchKernelGGL(k_mip_adjoint<false>, dim3(gx, gy), dim3(256), 0, s, grad_dst,
+                           grad_src, src.W, src.H, E);
     prof_end(K_MIP_ADJOINT, s);
     return hipGetLastError();
 }

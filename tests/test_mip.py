@@ -262,9 +262,10 @@ def test_lod_backward_of_one_level_is_the_plain_backward(rt):
     assert torch.equal(grads[0], gt) and torch.equal(gv, gv1) and torch.equal(gu, gu1)
 
 
-@pytest.mark.parametrize("W,H", [(16, 8), (1, 16), (8, 1), (2, 2)])
-def test_mip_adjoint_vs_oracle(rt, W, H):
-    n, C = 3, 2
+@pytest.mark.parametrize("W,H,n,C", [(16, 8, 3, 2), (1, 16, 3, 2), (8, 1, 3, 2), (2, 2, 3, 2),
+                                     (16, 8, 4, 4), (4, 1, 2, 2), (1, 2, 5, 4)])
+def test_mip_adjoint_vs_oracle(rt, W, H, n, C):
+    """Buckets of n*n*C values: a multiple of 4 takes the 16-byte path."""
     g = torch.Generator().manual_seed(W + 7 * H)
     src = rt.Texture(torch.zeros((H, W, n, n, C), device=DEV), W, H, n, C)
     W2, H2 = max(1, W // 2), max(1, H // 2)
