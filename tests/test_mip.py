@@ -262,6 +262,52 @@ def test_lod_backward_of_one_level_is_the_plain_backward(rt):
     assert torch.equal(grads[0], gt) and torch.equal(gv, gv1) and torch.equal(gu, gu1)
 
 
+
+def test_lod_backward_subsets_are_bitwise_the_full_results(rt):
+    """A 64 x 4 matrix (a chain of 7 levels, the last ones 1 bucket high):
+    leaving out some levels' gradients, or the view and uv gradients, changes
+    none of the bits of what is still computed."""
+    W, H, n, C = 64, 4, 4, 3
+    gb, tex, duv, go, chain = _lod_bwd_setup(rt, 57, W, H, n, C, "bilinear")
+    assert len(chain) == 7
+    args = (chain, gb.uv, gb.tbn, gb.view, duv, go, "bilinear")
+    full, gv, gu = rt.lookup_lod_bwd(*args)
+    want = [l % 2 == 0 for l in range(len(chain))]
+    part, gv2, gu2 = rt.lookup_lod_bwd(*args, want_levels=want)
+    tex_only, gv3, gu3 = rt.lookup_lod_bwd(*args, want_view=False, want_uv=False)
+    view_only, gv4, gu4 = rt.lookup_lod_bwd(*args, want_levels=False, want_uv=False)
+    torch.cuda.synchronize()
+    for l in range(len(chain)):
+        assert (part[l] is None) != want[l]
+        if want[l]:
+            assert torch.equal(part[l], full[l]), l
+        assert torch.equal(tex_only[l], full[l]), l
+        assert view_only[l] is None
+    assert torch.equal(gv2, gv) and torch.equal(gu2, gu)
+    assert gv3 is None and gu3 is None and gu4 is None
+    assert torch.equal(gv4, gv)
+    assert sum(int(torch.count_nonzero(g)) > 0 for g in full) >= 4
+
+
+def test_lod_backward_without_contributions_writes_zeros(rt):
+    """No fragment, or an upstream gradient of zeros (every record of every
+    level is then left out): every level's gradient is overwritten with zeros,
+    and so are the view and uv gradients."""
+    W, H, n, C = 16, 8, 4, 4
+    gb, tex, duv, go, chain = _lod_bwd_setup(rt, 59, W, H, n, C, "nearest")
+    for mode in ("nearest", "bilinear"):
+        grads, gv, gu = rt.lookup_lod_bwd(chain, gb.uv, gb.tbn, gb.view, duv,
+                                          torch.zeros_like(go), mode)
+        torch.cuda.synchronize()
+        assert all(int(torch.count_nonzero(g)) == 0 for g in grads)
+        assert int(torch.count_nonzero(gv)) == 0 and int(torch.count_nonzero(gu)) == 0
+        e = gb.uv[:0]
+        grads, gv, gu = rt.lookup_lod_bwd(chain, e, gb.tbn[:0], gb.view[:0], duv[:0], go[:0],
+                                          mode)
+        torch.cuda.synchronize()
+        assert all(int(torch.count_nonzero(g)) == 0 for g in grads)
+        assert gv.shape == (0, 3) and gu.shape == (0, 2)
+
 @pytest.mark.parametrize("W,H,n,C", [(16, 8, 3, 2), (1, 16, 3, 2), (8, 1, 3, 2), (2, 2, 3, 2),
                                      (16, 8, 4, 4), (4, 1, 2, 2), (1, 2, 5, 4)])
 def test_mip_adjoint_vs_oracle(rt, W, H, n, C):
