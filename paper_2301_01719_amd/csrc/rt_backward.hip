@@ -208,7 +208,10 @@ __global__ __launch_bounds__(256) void k_bwd_fragment(
 // 2. stable LSD radix sort of (key, record index), 8-bit digits
 // ---------------------------------------------------------------------------
 
-// Digit counts of one tile of SORT_TILE keys: hist[d * tiles + tile].
+// Digit counts of one tile of SORT_TILE keys: hist[d * tiles + tile].  Tiles
+// are renumbered so that each XCD takes a contiguous range: the counts of
+// neighbouring tiles share cache lines of the digit-major table, and so the
+// strided 4-byte stores of one XCD's tiles combine in its L2.
 template <int D>
 __global__ __launch_bounds__(SORT_THREADS) void k_radix_hist(const uint32_t* __restrict__ keys,
                                                              int64_t R, int shift,
@@ -219,7 +222,8 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_hist(const uint32_t* __r
     const int t = threadIdx.x;
     for (int d = t; d < B; d += SORT_THREADS) cnt[d] = 0;
     __syncthreads();
-    const int64_t base = (int64_t)blockIdx.x * SORT_TILE;
+    const int64_t tile = xcd_block_id(blockIdx.x, gridDim.x);
+    const int64_t base = tile * SORT_TILE;
     uint32_t k[SORT_IPT];
 #pragma unroll
     for (int r = 0; r < SORT_IPT; r++) {
@@ -232,7 +236,7 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_hist(const uint32_t* __r
         if (i < R) atomicAdd(&cnt[(k[r] >> shift) & (B - 1)], 1u);
     }
     __syncthreads();
-    for (int d = t; d < B; d += SORT_THREADS) hist[(int64_t)d * tiles + blockIdx.x] = cnt[d];
+    for (int d = t; d < B; d += SORT_THREADS) hist[(int64_t)d * tiles + tile] = cnt[d];
 }
 
 // exclusive prefix of v over the 256 threads of the block; *total receives the sum
@@ -321,7 +325,9 @@ __global__ __launch_bounds__(256) void k_scan_down(const uint32_t* __restrict__ 
 // count of that digit (kept in LDS by the digit's lowest lane).  The tile's
 // order within a digit is therefore wave, round, lane: index order.  The tile
 // is ordered in LDS, then written so that each digit's run is contiguous in
-// memory.
+// memory.  Tiles are renumbered per XCD as in the histogram: a digit's runs
+// from neighbouring tiles are adjacent in the output, so their partial-line
+// stores meet in one L2.
 template <int D>
 __global__ __launch_bounds__(SORT_THREADS) void k_radix_scatter(
     const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in,
@@ -336,7 +342,7 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_scatter(
     __shared__ uint32_t dstart[B], goff[B];
     __shared__ uint32_t wsum[4];
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-    const int64_t tile = blockIdx.x;
+    const int64_t tile = xcd_block_id(blockIdx.x, gridDim.x);
     const int64_t base = tile * SORT_TILE;
     for (int d = t; d < B; d += SORT_THREADS) {
         wcnt[0][d] = wcnt[1][d] = wcnt[2][d] = wcnt[3][d] = 0;
