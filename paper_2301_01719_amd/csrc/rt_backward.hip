@@ -263,15 +263,35 @@ __device__ __forceinline__ uint32_t block_exclusive(uint32_t v, uint32_t* wsum, 
 }
 
 // device-wide exclusive scan: per-block sums, a one-block scan of the sums,
-// then per-block scans offset by the scanned sums
+// then per-block scans offset by the scanned sums.  Each thread owns 16
+// consecutive counts, read (and written) as four 16-byte vectors when all 16
+// lie inside the array and the pointers are 16-byte aligned.
+__device__ __forceinline__ void load16(const uint32_t* __restrict__ in, int64_t base, int64_t L,
+                                       bool vec, uint32_t v[16]) {
+    if (vec && base + 16 <= L) {
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            const uint4 q = ((const uint4*)(in + base))[k];
+            v[4 * k] = q.x;
+            v[4 * k + 1] = q.y;
+            v[4 * k + 2] = q.z;
+            v[4 * k + 3] = q.w;
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < 16; k++) v[k] = (base + k < L) ? in[base + k] : 0u;
+    }
+}
+
 __global__ __launch_bounds__(256) void k_scan_reduce(const uint32_t* __restrict__ in, int64_t L,
                                                      uint32_t* __restrict__ part) {
     __shared__ uint32_t wsum[4];
     const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + threadIdx.x * 16;
-    uint32_t s = 0;
+    const bool vec = ((uintptr_t)in & 15) == 0;
+    uint32_t v[16], s = 0;
+    load16(in, base, L, vec, v);
 #pragma unroll
-    for (int k = 0; k < 16; k++)
-        if (base + k < L) s += in[base + k];
+    for (int k = 0; k < 16; k++) s += v[k];
     uint32_t total;
     block_exclusive(s, wsum, &total);
     if (threadIdx.x == 0) part[blockIdx.x] = total;
@@ -304,17 +324,26 @@ __global__ __launch_bounds__(256) void k_scan_down(const uint32_t* __restrict__ 
                                                    uint32_t* __restrict__ out) {
     __shared__ uint32_t wsum[4];
     const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + threadIdx.x * 16;
+    const bool vec = (((uintptr_t)in | (uintptr_t)out) & 15) == 0;
     uint32_t v[16], s = 0;
+    load16(in, base, L, vec, v);
 #pragma unroll
-    for (int k = 0; k < 16; k++) {
-        v[k] = (base + k < L) ? in[base + k] : 0u;
-        s += v[k];
-    }
+    for (int k = 0; k < 16; k++) s += v[k];
     uint32_t run = part[blockIdx.x] + block_exclusive(s, wsum, nullptr);
+    uint32_t o[16];
 #pragma unroll
     for (int k = 0; k < 16; k++) {
-        if (base + k < L) out[base + k] = run;
+        o[k] = run;
         run += v[k];
+    }
+    if (vec && base + 16 <= L) {
+#pragma unroll
+        for (int k = 0; k < 4; k++)
+            ((uint4*)(out + base))[k] = make_uint4(o[4 * k], o[4 * k + 1], o[4 * k + 2], o[4 * k + 3]);
+    } else {
+#pragma unroll
+        for (int k = 0; k < 16; k++)
+            if (base + k < L) out[base + k] = o[k];
     }
 }
 
@@ -436,15 +465,28 @@ __global__ __launch_bounds__(256) void k_fill_u32(uint32_t* __restrict__ p, int6
     if (i < n) p[i] = v;
 }
 
+// Four sorted keys per thread (one 16-byte load; the key buffer is padded to
+// 256 bytes, so the load of a partial last group stays inside it) and the
+// two neighbours, loaded unconditionally from clamped positions.
 __global__ __launch_bounds__(256) void k_bucket_ranges(const uint32_t* __restrict__ skeys,
                                                        int64_t R, int cell_bits, int64_t nb,
                                                        int2* __restrict__ range) {
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i >= R) return;
-    const uint32_t b = skeys[i] >> cell_bits;
-    if (b >= nb) return;  // records of a sparse plan without a bucket (sorted last)
-    if (i == 0 || (skeys[i - 1] >> cell_bits) != b) range[b].x = (int)i;
-    if (i == R - 1 || (skeys[i + 1] >> cell_bits) != b) range[b].y = (int)(i + 1);
+    const int64_t i0 = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 4;
+    if (i0 >= R) return;
+    const uint4 q = *(const uint4*)(skeys + i0);
+    const uint32_t prev = skeys[i0 > 0 ? i0 - 1 : 0];
+    const uint32_t next = skeys[i0 + 4 < R ? i0 + 4 : R - 1];
+    const uint32_t b[6] = {prev >> cell_bits, q.x >> cell_bits, q.y >> cell_bits,
+                           q.z >> cell_bits, q.w >> cell_bits, next >> cell_bits};
+#pragma unroll
+    for (int u = 0; u < 4; u++) {
+        const int64_t i = i0 + u;
+        if (i >= R) break;
+        const uint32_t bu = b[u + 1];
+        if (bu >= nb) continue;  // records of a sparse plan without a bucket (sorted last)
+        if (i == 0 || b[u] != bu) range[bu].x = (int)i;
+        if (i == R - 1 || b[u + 2] != bu) range[bu].y = (int)(i + 1);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1137,7 +1179,7 @@ hipError_t launch_backward(const TexView& t, int fmt, int mode, const float* uv,
     launch_fill(big_count, BIG_LISTS * BIG_STRIDE + nb * 2, 0u, s);  // counters and ranges
     if (R > 0) {
         prof_begin(K_BUCKET_RANGES, s);
-        hipLaunchKernelGGL(k_bucket_ranges, dim3((uint32_t)((R + 255) / 256)), dim3(256), 0, s,
+        hipLaunchKernelGGL(k_bucket_ranges, dim3((uint32_t)((R + 1023) / 1024)), dim3(256), 0, s,
                            skeys, R, plan.cell_bits, nb, range);
         prof_end(K_BUCKET_RANGES, s);
     }
