@@ -52,7 +52,8 @@ KERNEL_SOURCES = {
     "k_lookup_light": "rt_lookup.hip", "k_quant_bf16": "rt_quantize.hip",
     "k_quant_fp8": "rt_quantize.hip", "k_pack_bits_flat": "rt_quantize.hip",
     "k_bwd_fragment": "rt_backward.hip", "k_segacc": "rt_backward.hip",
-    "k_segacc_big": "rt_backward.hip", "k_bake_env": "rt_bake.hip",
+    "k_segacc_big": "rt_backward.hip", "k_payload": "rt_backward.hip",
+    "k_bake_env": "rt_bake.hip",
     "k_bake_shadow": "rt_bake.hip", "k_build_mip": "rt_mip.hip",
     "k_vq_assign": "rt_dictionary.hip", "k_mip_adjoint": "rt_lod_backward.hip",
 }
@@ -468,16 +469,25 @@ def main():
     del taps, idx, cnt, small, big
     texel_bytes = uniq_texels * C * eb + (uniq_buckets * 4 if args.storage == "fp8" else 0)
     gbuf = N * 56
+    # the backward writes the records' payload in sorted order when buckets
+    # hold at most 64 records on average (one record per fragment here)
+    pay = N <= 64 * W * H
     alg = {
         "k_quant_bf16": E * 4 + E * 2,
         "k_quant_fp8": E * 4 + E + W * H * 4,
         "k_lookup_fwd": gbuf + N * C * 4 + texel_bytes,
         "k_bwd_fragment": gbuf + N * C * 4 + texel_bytes + N * (12 + 8) + N * (4 + 8),
         # tiles written + records read (key, index, fractions, upstream
+        # gradient; with the sorted payload: key, fractions, weighted
         # gradient) + bucket ranges read (+ the list entries for the big pass)
-        "k_segacc": n_small * n * n * C * 4 + r_small * (4 + 4 + 8 + C * 4) + W * H * 8,
+        "k_segacc": n_small * n * n * C * 4 + r_small * ((4 + 8 + C * 4) if pay else
+                                                         (4 + 4 + 8 + C * 4)) + W * H * 8,
         "k_segacc_big": n_big * n * n * C * 4 + r_big * (4 + 4 + 8 + C * 4) + n_big * (8 + 4),
     }
+    if pay:
+        # every key and the ranges read; for the records of buckets with at
+        # most 64: index, fractions and upstream gradient read, payload written
+        alg["k_payload"] = N * 4 + W * H * 8 + r_small * (4 + 8 + C * 4 + 8 + C * 4)
     if n_big == 0:
         del alg["k_segacc_big"]
     per_kernel = {}

@@ -145,7 +145,7 @@ const char* kernel_name(int id) {
         "k_bake_env",     "k_build_mip",     "k_lookup_lod",    "k_pack_bits",
         "k_lookup_light", "k_bake_shadow",   "k_vq_assign",     "k_vq_hist",
         "k_vq_scatter",   "k_vq_pieces",     "k_vq_combine",    "k_lod_bwd_scale",
-        "k_mip_adjoint"};
+        "k_mip_adjoint",  "k_payload"};
     return (id >= 0 && id < K_COUNT) ? names[id] : "";
 }
 

@@ -489,9 +489,83 @@ __global__ __launch_bounds__(256) void k_bucket_ranges(const uint32_t* __restric
     }
 }
 
+// The payload of the sorted records of buckets with at most 64 records (the
+// ones the first accumulation pass serves from its register window), in
+// sorted order: the fractions (fx, fy) and the upstream gradient times the
+// bucket weight (1 in nearest mode).  That pass then reads its records
+// contiguously instead of gathering them from the fragments; the passes for
+// bigger buckets, whose records share cache lines, keep gathering.  Records
+// past the last bucket (sparse plans) are skipped.  Workgroups are renumbered
+// per XCD: neighbouring records gather from neighbouring fragments.
+template <int C, int MODE>
+__global__ __launch_bounds__(256) void k_payload(const uint32_t* __restrict__ skeys,
+                                                 const uint32_t* __restrict__ svals,
+                                                 const float* __restrict__ wrec,
+                                                 const float* __restrict__ grad_out,
+                                                 const int2* __restrict__ range, int64_t R,
+                                                 int cell_bits, int64_t nb,
+                                                 float* __restrict__ payf,
+                                                 float* __restrict__ payg) {
+    const int64_t i = (int64_t)xcd_block_id(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
+    if (i >= R) return;
+    const uint32_t b = skeys[i] >> cell_bits;
+    if (b >= nb) return;
+    const int2 r = range[b];
+    if (r.y - r.x > 64) return;
+    const uint32_t rec = svals[i];
+    float fx, fy, wb = 1.f;
+    int64_t frag;
+    if constexpr (MODE == MODE_NEAREST) {
+        frag = rec;
+        const float2 w2 = ((const float2*)wrec)[frag];
+        fx = w2.x;
+        fy = w2.y;
+    } else {
+        frag = rec >> 2;
+        const int k = rec & 3;
+        const float4 w4 = ((const float4*)wrec)[frag];
+        fx = w4.x;
+        fy = w4.y;
+        const float aa = w4.z, bb = w4.w;
+        wb = (k == 0) ? (1.f - aa) * (1.f - bb)
+                      : (k == 1) ? aa * (1.f - bb) : (k == 2) ? (1.f - aa) * bb : aa * bb;
+    }
+    ((float2*)payf)[i] = make_float2(fx, fy);
+    if constexpr (C == 4) {
+        const float4 g = ((const float4*)grad_out)[frag];
+        ((float4*)payg)[i] = make_float4(g.x * wb, g.y * wb, g.z * wb, g.w * wb);
+    } else if constexpr (C == 2) {
+        const float2 g = ((const float2*)grad_out)[frag];
+        ((float2*)payg)[i] = make_float2(g.x * wb, g.y * wb);
+    } else {
+#pragma unroll
+        for (int c = 0; c < C; c++) payg[i * C + c] = grad_out[frag * C + c] * wb;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // 4./5. segmented reduction of a bucket's records into its gradient tile
 // ---------------------------------------------------------------------------
+
+// Upstream gradient of sorted record i from the payload (bucket weight
+// already applied).
+template <int C>
+__device__ __forceinline__ void load_payg(const float* __restrict__ payg, int64_t i, float g[C]) {
+    if constexpr (C == 4) {
+        const float4 q = ((const float4*)payg)[i];
+        g[0] = q.x;
+        g[1] = q.y;
+        g[2] = q.z;
+        g[3] = q.w;
+    } else if constexpr (C == 2) {
+        const float2 q = ((const float2*)payg)[i];
+        g[0] = q.x;
+        g[1] = q.y;
+    } else {
+#pragma unroll
+        for (int c = 0; c < C; c++) g[c] = payg[i * C + c];
+    }
+}
 
 // The four tap contributions of sorted record i: v = (w00, w01, w10, w11) x g
 // times the bucket weight (1 in nearest mode); returns the record's cell.
@@ -644,22 +718,26 @@ __device__ __forceinline__ void reduce_records(const uint32_t* __restrict__ skey
 }
 
 // A window of up to 64 consecutive sorted records held in registers, one per
-// lane (cell, bilinear fractions, bucket weight and upstream gradient), so that
-// the small buckets of a group are served without further global loads.
+// lane (cell, bilinear fractions and weighted upstream gradient), so that the
+// small buckets of a group are served without further global loads.
 template <int C>
 struct RecWindow {
     int64_t start, end;  // records [start, end) are held; lane l holds start + l
     int cell;
     uint32_t key;
-    float fx, fy, wb;
+    float fx, fy;
     float g[C];
 };
 
+// payf == nullptr: the records are gathered from the fragments (svals, wrec,
+// grad_out); otherwise they are read from the sorted payload (payf, payg).
 template <int C, int MODE>
 __device__ __forceinline__ void load_window(const uint32_t* __restrict__ skeys,
                                             const uint32_t* __restrict__ svals,
                                             const float* __restrict__ wrec,
-                                            const float* __restrict__ grad_out, int64_t start,
+                                            const float* __restrict__ grad_out,
+                                            const float* __restrict__ payf,
+                                            const float* __restrict__ payg, int64_t start,
                                             int64_t R, uint32_t cell_mask, RecWindow<C>& w) {
     const int lane = threadIdx.x & 63;
     w.start = start;
@@ -667,32 +745,39 @@ __device__ __forceinline__ void load_window(const uint32_t* __restrict__ skeys,
     w.cell = -2 - lane;
     w.key = 0u;
     w.fx = w.fy = 0.f;
-    w.wb = 1.f;
 #pragma unroll
     for (int c = 0; c < C; c++) w.g[c] = 0.f;
     const int64_t i = start + lane;
     if (i < w.end) {
-        const uint32_t rec = svals[i];
         w.key = skeys[i];
         w.cell = (int)(w.key & cell_mask);
-        int64_t frag;
-        if constexpr (MODE == MODE_NEAREST) {
-            frag = rec;
-            const float2 w2 = ((const float2*)wrec)[frag];
-            w.fx = w2.x;
-            w.fy = w2.y;
+        if (payf) {
+            const float2 f2 = ((const float2*)payf)[i];
+            w.fx = f2.x;
+            w.fy = f2.y;
+            load_payg<C>(payg, i, w.g);
         } else {
-            frag = rec >> 2;
-            const int k = rec & 3;
-            const float4 w4 = ((const float4*)wrec)[frag];
-            w.fx = w4.x;
-            w.fy = w4.y;
-            const float aa = w4.z, bb = w4.w;
-            w.wb = (k == 0) ? (1.f - aa) * (1.f - bb)
-                            : (k == 1) ? aa * (1.f - bb) : (k == 2) ? (1.f - aa) * bb : aa * bb;
-        }
+            const uint32_t rec = svals[i];
+            float wb = 1.f;
+            int64_t frag;
+            if constexpr (MODE == MODE_NEAREST) {
+                frag = rec;
+                const float2 w2 = ((const float2*)wrec)[frag];
+                w.fx = w2.x;
+                w.fy = w2.y;
+            } else {
+                frag = rec >> 2;
+                const int k = rec & 3;
+                const float4 w4 = ((const float4*)wrec)[frag];
+                w.fx = w4.x;
+                w.fy = w4.y;
+                const float aa = w4.z, bb = w4.w;
+                wb = (k == 0) ? (1.f - aa) * (1.f - bb)
+                              : (k == 1) ? aa * (1.f - bb) : (k == 2) ? (1.f - aa) * bb : aa * bb;
+            }
 #pragma unroll
-        for (int c = 0; c < C; c++) w.g[c] = grad_out[frag * C + c];
+            for (int c = 0; c < C; c++) w.g[c] = grad_out[frag * C + c] * wb;
+        }
     }
 }
 
@@ -708,7 +793,7 @@ __device__ __forceinline__ void scan_window(const RecWindow<C>& w, float v[4 * C
     const float w10 = (1.f - w.fx) * w.fy, w11 = w.fx * w.fy;
 #pragma unroll
     for (int c = 0; c < C; c++) {
-        const float gc = valid ? w.g[c] * w.wb : 0.f;
+        const float gc = valid ? w.g[c] : 0.f;
         v[0 * C + c] = w00 * gc;
         v[1 * C + c] = w01 * gc;
         v[2 * C + c] = w10 * gc;
@@ -781,6 +866,8 @@ __global__ __launch_bounds__(256) void k_segacc(const uint32_t* __restrict__ ske
                                                 const uint32_t* __restrict__ svals,
                                                 const float* __restrict__ wrec,
                                                 const float* __restrict__ grad_out,
+                                                const float* __restrict__ payf,
+                                                const float* __restrict__ payg,
                                                 const int2* __restrict__ range,
                                                 float* __restrict__ grad_tex, int64_t nbuckets,
                                                 int64_t R, int n, uint32_t cell_mask,
@@ -828,7 +915,8 @@ __global__ __launch_bounds__(256) void k_segacc(const uint32_t* __restrict__ ske
             }
             if (cnt > 64) continue;  // listed above, or hot
             if (!(rx >= win.start && ry <= win.end)) {
-                load_window<C, MODE>(skeys, svals, wrec, grad_out, rx, R, cell_mask, win);
+                load_window<C, MODE>(skeys, svals, wrec, grad_out, payf, payg, rx, R, cell_mask,
+                                     win);
                 scan_window<C>(win, v, tail);
             }
             tile_zero(tile, te);
@@ -1009,6 +1097,8 @@ bool plan_backward(int W, int H, int n, int C, int64_t N, int mode, BwdPlan* p, 
     p->off_vals0 = take((size_t)R * 4);
     p->off_vals1 = take((size_t)R * 4);
     p->off_wrec = take((size_t)N * (mode == MODE_NEAREST ? 8 : 16));
+    p->off_payf = take((size_t)R * 8);
+    p->off_payg = take((size_t)R * 4 * C);
     p->off_hist = take((size_t)p->scan_len * 4);
     p->off_hoff = take((size_t)p->scan_len * 4);
     p->off_scanp = take((size_t)(p->scan_blocks + 1) * 4);
@@ -1044,13 +1134,14 @@ static void launch_bwd_fragment_c(const TexView& t, const float* uv, const float
 template <int MODE>
 static void launch_segacc_c(int C, dim3 grid, size_t shm, hipStream_t s, const uint32_t* sk,
                             const uint32_t* sv, const float* wrec, const float* go,
+                            const float* pf, const float* pg,
                             const int2* range, float* gt, int64_t nb, int64_t R, int n,
                             uint32_t mask, uint32_t* bc, uint32_t* bl, int64_t cap) {
     switch (C) {
-    case 1: hipLaunchKernelGGL((k_segacc<1, MODE>), grid, dim3(256), shm, s, sk, sv, wrec, go, range, gt, nb, R, n, mask, bc, bl, cap); break;
-    case 2: hipLaunchKernelGGL((k_segacc<2, MODE>), grid, dim3(256), shm, s, sk, sv, wrec, go, range, gt, nb, R, n, mask, bc, bl, cap); break;
-    case 3: hipLaunchKernelGGL((k_segacc<3, MODE>), grid, dim3(256), shm, s, sk, sv, wrec, go, range, gt, nb, R, n, mask, bc, bl, cap); break;
-    default: hipLaunchKernelGGL((k_segacc<4, MODE>), grid, dim3(256), shm, s, sk, sv, wrec, go, range, gt, nb, R, n, mask, bc, bl, cap); break;
+    case 1: hipLaunchKernelGGL((k_segacc<1, MODE>), grid, dim3(256), shm, s, sk, sv, wrec, go, pf, pg, range, gt, nb, R, n, mask, bc, bl, cap); break;
+    case 2: hipLaunchKernelGGL((k_segacc<2, MODE>), grid, dim3(256), shm, s, sk, sv, wrec, go, pf, pg, range, gt, nb, R, n, mask, bc, bl, cap); break;
+    case 3: hipLaunchKernelGGL((k_segacc<3, MODE>), grid, dim3(256), shm, s, sk, sv, wrec, go, pf, pg, range, gt, nb, R, n, mask, bc, bl, cap); break;
+    default: hipLaunchKernelGGL((k_segacc<4, MODE>), grid, dim3(256), shm, s, sk, sv, wrec, go, pf, pg, range, gt, nb, R, n, mask, bc, bl, cap); break;
     }
 }
 
@@ -1077,6 +1168,19 @@ static void launch_segacc_hot_c(int C, dim3 grid, size_t shm, hipStream_t s, con
     case 2: hipLaunchKernelGGL((k_segacc_hot<2, MODE>), grid, dim3(64), shm, s, sk, sv, wrec, go, range, part, R, n, cb, nb); break;
     case 3: hipLaunchKernelGGL((k_segacc_hot<3, MODE>), grid, dim3(64), shm, s, sk, sv, wrec, go, range, part, R, n, cb, nb); break;
     default: hipLaunchKernelGGL((k_segacc_hot<4, MODE>), grid, dim3(64), shm, s, sk, sv, wrec, go, range, part, R, n, cb, nb); break;
+    }
+}
+
+template <int MODE>
+static void launch_payload_c(int C, dim3 grid, hipStream_t s, const uint32_t* sk,
+                             const uint32_t* sv, const float* wrec, const float* go,
+                             const int2* range, int64_t R, int cb, int64_t nb, float* pf,
+                             float* pg) {
+    switch (C) {
+    case 1: hipLaunchKernelGGL((k_payload<1, MODE>), grid, dim3(256), 0, s, sk, sv, wrec, go, range, R, cb, nb, pf, pg); break;
+    case 2: hipLaunchKernelGGL((k_payload<2, MODE>), grid, dim3(256), 0, s, sk, sv, wrec, go, range, R, cb, nb, pf, pg); break;
+    case 3: hipLaunchKernelGGL((k_payload<3, MODE>), grid, dim3(256), 0, s, sk, sv, wrec, go, range, R, cb, nb, pf, pg); break;
+    default: hipLaunchKernelGGL((k_payload<4, MODE>), grid, dim3(256), 0, s, sk, sv, wrec, go, range, R, cb, nb, pf, pg); break;
     }
 }
 
@@ -1114,6 +1218,8 @@ hipError_t launch_backward(const TexView& t, int fmt, int mode, const float* uv,
     uint32_t* vals0 = (uint32_t*)(wsb + plan.off_vals0);
     uint32_t* vals1 = (uint32_t*)(wsb + plan.off_vals1);
     float* wrec = (float*)(wsb + plan.off_wrec);
+    float* payf = (float*)(wsb + plan.off_payf);
+    float* payg = (float*)(wsb + plan.off_payg);
     uint32_t* hist = (uint32_t*)(wsb + plan.off_hist);
     uint32_t* hoff = (uint32_t*)(wsb + plan.off_hoff);
     uint32_t* scanp = (uint32_t*)(wsb + plan.off_scanp);
@@ -1184,16 +1290,26 @@ hipError_t launch_backward(const TexView& t, int fmt, int mode, const float* uv,
         prof_end(K_BUCKET_RANGES, s);
     }
 
-    // 4. pass 1 over buckets
+    // 4. the records' payload in sorted order (when buckets hold 64 records or
+    // fewer on average: most records then go through the register window),
+    // then pass 1 over buckets
+    const bool pay = R > 0 && R <= 64 * nb;
+    if (pay) {
+        const dim3 gp((uint32_t)((R + 255) / 256));
+        prof_begin(K_PAYLOAD, s);
+        if (mode == MODE_NEAREST) launch_payload_c<MODE_NEAREST>(t.C, gp, s, skeys, svals, wrec, grad_out, range, R, plan.cell_bits, nb, payf, payg);
+        else launch_payload_c<MODE_BILINEAR>(t.C, gp, s, skeys, svals, wrec, grad_out, range, R, plan.cell_bits, nb, payf, payg);
+        prof_end(K_PAYLOAD, s);
+    }
     const int te = (int)plan.tile_elems;
     const uint32_t cell_mask = plan.cell_bits >= 32 ? 0xFFFFFFFFu : ((1u << plan.cell_bits) - 1u);
     const int64_t groups = (nb + SEG_GROUP - 1) / SEG_GROUP;
     const dim3 g1((uint32_t)((groups + 3) / 4));
     prof_begin(K_SEGACC, s);
     if (mode == MODE_NEAREST)
-        launch_segacc_c<MODE_NEAREST>(t.C, g1, (size_t)4 * te * 4, s, skeys, svals, wrec, grad_out, range, grad_tex, nb, R, t.n, cell_mask, big_count, big_list, plan.big_cap);
+        launch_segacc_c<MODE_NEAREST>(t.C, g1, (size_t)4 * te * 4, s, skeys, svals, wrec, grad_out, pay ? payf : nullptr, payg, range, grad_tex, nb, R, t.n, cell_mask, big_count, big_list, plan.big_cap);
     else
-        launch_segacc_c<MODE_BILINEAR>(t.C, g1, (size_t)4 * te * 4, s, skeys, svals, wrec, grad_out, range, grad_tex, nb, R, t.n, cell_mask, big_count, big_list, plan.big_cap);
+        launch_segacc_c<MODE_BILINEAR>(t.C, g1, (size_t)4 * te * 4, s, skeys, svals, wrec, grad_out, pay ? payf : nullptr, payg, range, grad_tex, nb, R, t.n, cell_mask, big_count, big_list, plan.big_cap);
     prof_end(K_SEGACC, s);
     if (R > 64) {
         // BIG_LISTS x parts workgroups, four wavefronts each; parts grows with

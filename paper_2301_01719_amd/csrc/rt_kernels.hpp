@@ -43,6 +43,7 @@ enum KernelId {
     K_VQ_COMBINE,
     K_LOD_BWD_SCALE,
     K_MIP_ADJOINT,
+    K_PAYLOAD,
     K_COUNT
 };
 const char* kernel_name(int id);
@@ -119,8 +120,8 @@ struct BwdPlan {
     uint32_t sentinel;    // sparse plans: the key of a fragment whose upstream
                           // gradient is zero (past every bucket); 0 otherwise
     // workspace offsets (bytes)
-    size_t off_keys0, off_keys1, off_vals0, off_vals1, off_wrec, off_hist, off_hoff, off_scanp,
-        off_range, off_biglist, off_part, total;
+    size_t off_keys0, off_keys1, off_vals0, off_vals1, off_wrec, off_payf, off_payg, off_hist,
+        off_hoff, off_scanp, off_range, off_biglist, off_part, total;
 };
 constexpr int PIECE = 2048;  // records per chunk; buckets with more are "hot"
 constexpr int SEG_GROUP = 8;  // buckets per wavefront in the first accumulation pass

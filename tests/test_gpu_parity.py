@@ -360,6 +360,59 @@ def test_backward_hot_buckets(rt, mode):
     check_grad_tex(host(gt2), r2, n)
 
 
+
+def _records_per_bucket(uv, W, H, mode):
+    """Records per bucket of the accumulation: one per fragment (nearest) or
+    one per fragment and bucket of its bilinear footprint."""
+    f = uv.astype(np.float64) - np.floor(uv.astype(np.float64))
+    if mode == "nearest":
+        i = np.minimum((f[:, 0] * W).astype(np.int64), W - 1)
+        j = np.minimum((f[:, 1] * H).astype(np.int64), H - 1)
+        return np.bincount(j * W + i, minlength=W * H)
+    p = f * [W, H] - 0.5
+    i0 = np.floor(p[:, 0]).astype(np.int64)
+    j0 = np.floor(p[:, 1]).astype(np.int64)
+    b = [((j0 + dj) % H) * W + (i0 + di) % W for dj in (0, 1) for di in (0, 1)]
+    return np.bincount(np.concatenate(b), minlength=W * H)
+
+
+@pytest.mark.parametrize("W,N_uni,clusters", [(16, 2000, ((3, 4, 20000), (10, 11, 600))),
+                                              (64, 40000, ((10, 20, 5000), (40, 7, 300)))])
+@pytest.mark.parametrize("mode", ["nearest", "bilinear"])
+def test_backward_mixed_bucket_sizes(rt, W, N_uni, clusters, mode):
+    """Small, big (65..2048 records) and hot buckets in one launch, with more
+    and with fewer than 64 records per bucket on average: the accumulation's
+    register window then gathers its records from the fragments, or reads
+    them from the payload written in sorted order."""
+    H, n, C = W, 8, 4
+    N = N_uni + sum(c[2] for c in clusters)
+    tex_c, gb = _rand_case(81 + W, W, H, n, C, N, uv_range=(0.0, 1.0))
+    g = torch.Generator().manual_seed(82 + W)
+    uv = gb.uv.clone()
+    at = N_uni
+    for i, j, cnt in clusters:
+        jit = (torch.rand((cnt, 2), generator=g, dtype=torch.float64) - 0.5) * 0.6
+        uv[at:at + cnt, 0] = ((i + 0.5 + jit[:, 0]) / W).float()
+        uv[at:at + cnt, 1] = ((j + 0.5 + jit[:, 1]) / H).float()
+        at += cnt
+    gb = wl.GBuffer(uv.contiguous(), gb.tbn, gb.view)
+    gb = _select(gb, away_from_edges(*gb_host(gb), W, H, n, mode))
+    cnt = _records_per_bucket(host(gb.uv), W, H, mode)
+    assert cnt.min() <= 64 and np.any((cnt > 64) & (cnt <= 2048)) and cnt.max() > 2048
+    window_path = "payload" if cnt.sum() <= 64 * W * H else "gather"
+    assert window_path == ("gather" if W == 16 else "payload")
+    go = torch.randn((gb.count, C), generator=torch.Generator().manual_seed(83 + W))
+    tex = rt.Texture(tex_c.to(DEV), W, H, n, C)
+    gt, gv, gu = rt.lookup_bwd(tex, gb.uv.to(DEV), gb.tbn.to(DEV), gb.view.to(DEV), go.to(DEV),
+                               mode=mode)
+    _sync()
+    u, t, v = gb_host(gb)
+    m = oracle.MODE_NEAREST if mode == "nearest" else oracle.MODE_BILINEAR
+    ref = oracle.lookup_bwd(oracle.Tex(tex_c.numpy(), W, H, n, C), u, t, v, go.numpy(), mode=m)
+    check_grad_tex(host(gt), ref, n)
+    keep = _smooth_mask(u, t, v, W, H, n, mode)
+    check_grad_vec(host(gv)[keep], ref["grad_view"][keep], ref["scale_view"][keep])
+
 def test_backward_deterministic(rt):
     W, H, n, C, N = 32, 32, 8, 4, 200000
     tex_c, gb_c = _rand_case(11, W, H, n, C, N, uv_range=(0.0, 0.3))
