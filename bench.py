@@ -74,13 +74,38 @@ DICT_NOISE = 0.01
 DICT_ITERATIONS = 3
 
 
+def source_code(text: str) -> str:
+    """C++ source without its comments and with whitespace collapsed: what a
+    profile depends on (an edited comment leaves the kernels as they were)."""
+    out, i, n = [], 0, len(text)
+    while i < n:
+        c = text[i]
+        if c == '"' or c == "'":
+            j = i + 1
+            while j < n and text[j] != c:
+                j += 2 if text[j] == "\\" else 1
+            out.append(text[i:j + 1])
+            i = j + 1
+        elif text.startswith("//", i):
+            j = text.find("\n", i)
+            i = n if j < 0 else j
+        elif text.startswith("/*", i):
+            j = text.find("*/", i + 2)
+            i = n if j < 0 else j + 2
+            out.append(" ")
+        else:
+            out.append(c)
+            i += 1
+    return " ".join("".join(out).split())
+
+
 def source_hash(kernel: str) -> str:
-    """Hash of the sources that make up `kernel` (its file and the shared
-    headers)."""
+    """Hash of the code (comments left out) of the sources that make up
+    `kernel`: its file and the shared headers."""
     h = hashlib.sha256()
     for f in SHARED_SOURCES + [KERNEL_SOURCES[kernel]]:
-        with open(os.path.join(ROOT, "paper_2301_01719_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_2301_01719_amd", "csrc", f)) as fh:
+            h.update(source_code(fh.read()).encode())
     return h.hexdigest()[:16]
 
 

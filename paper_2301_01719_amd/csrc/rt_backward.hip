@@ -13,13 +13,20 @@
 //                       keep record order, so the sorted sequence depends only
 //                       on the inputs.
 //   3. k_bucket_ranges  [start, end) of every bucket in the sorted records.
-//   4. k_segacc         one wavefront per bucket (pass 1): the bucket's records
-//                       are reduced per cell by a segmented scan across lanes
-//                       with a fixed shape, the four cell sums are added to the
-//                       texels of the cell in four ordered phases in LDS, and
-//                       the n x n x C tile is written once.  Untouched buckets
-//                       get zeros.  Buckets with more than PIECE records are
-//                       left to pass 2.
+//      k_payload        (buckets of at most 64 records on average) the
+//                       fractions and weighted upstream gradient of the
+//                       records of buckets with at most 64 records, written in
+//                       sorted order.
+//   4. k_segacc         eight buckets per wavefront (pass 1): the records of a
+//                       bucket with at most 64 are held in a register window
+//                       (read from the payload, or gathered from the
+//                       fragments) and reduced per cell by a segmented scan
+//                       across lanes with a fixed shape; the four cell sums are
+//                       added to the texels of the cell in four ordered phases
+//                       in LDS, and the n x n x C tile is written once.
+//                       Untouched buckets get zeros.  Buckets with 65..PIECE
+//                       records go to k_segacc_big (rounds of 64 with a
+//                       carry), more to pass 2.
 //   5. k_segacc_hot /   pass 2: hot buckets are cut at fixed chunk boundaries of
 //      k_combine_hot    the sorted records; each chunk's part is reduced as in
 //                       pass 1 into a partial tile, and the partials are summed

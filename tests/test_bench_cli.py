@@ -44,3 +44,17 @@ def test_bench_refuses_more_than_one_gpu():
                        text=True, timeout=300)
     assert r.returncode == 2
     assert "one GPU" in r.stderr and r.stdout == ""
+
+
+def test_profile_hash_ignores_comments_only():
+    """A profile stays current when a comment of its sources changes, not when
+    their code does (strings keep their slashes)."""
+    sys.path.insert(0, ROOT)
+    import bench
+    a = 'int f(int x) { return x + 1; } // one\n/* two */ const char* s = "a//b";\n'
+    b = 'int f(int x)  {\n  return x + 1;  // another comment\n}\nconst char* s = "a//b";'
+    c = 'int f(int x) { return x + 2; } // one\n/* two */ const char* s = "a//b";\n'
+    d = 'int f(int x) { return x + 1; } // one\n/* two */ const char* s = "a/b";\n'
+    assert bench.source_code(a) == bench.source_code(b)
+    assert bench.source_code(a) != bench.source_code(c)
+    assert bench.source_code(a) != bench.source_code(d)
