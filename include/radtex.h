@@ -303,8 +303,9 @@ size_t rt_lookup_lod_bwd_workspace(const rt_texture* const* levels, int32_t nlev
  * rt_build_mip_adjoint.  grad_levels: HOST array of nlevels DEVICE pointers
  * (16-byte aligned); duv as for rt_lookup_fwd_lod; workspace: DEVICE, at
  * least rt_lookup_lod_bwd_workspace() bytes, 256-byte aligned.
- * A fragment makes records only on the levels it blends (its sort key takes
- * one bit more than rt_lookup_bwd's: levels up to 2^23 buckets at n = 16).
+ * All levels are done in one pass: one sort key numbers the buckets of every
+ * level, so the chain's buckets plus one must fit in 32 - ceil(log2(n*n))
+ * bits (a level 0 of up to 4096 x 2048 buckets at n = 16).
  * Errors: as rt_lookup_fwd_lod and rt_lookup_bwd (RT_ERR_UNSUPPORTED for a
  * level beyond the backward's limits). */
 rt_status rt_lookup_lod_bwd(const rt_texture* const* levels, int32_t nlevels,

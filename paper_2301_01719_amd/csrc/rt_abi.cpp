@@ -144,7 +144,7 @@ const char* kernel_name(int id) {
         "k_segacc_hot",   "k_combine_hot",   "k_segacc_big",    "k_bake_directions",
         "k_bake_env",     "k_build_mip",     "k_lookup_lod",    "k_pack_bits",
         "k_lookup_light", "k_bake_shadow",   "k_vq_assign",     "k_vq_hist",
-        "k_vq_scatter",   "k_vq_pieces",     "k_vq_combine",    "k_lod_bwd_scale",
+        "k_vq_scatter",   "k_vq_pieces",     "k_vq_combine",    "k_lod_bwd_fragment",
         "k_mip_adjoint",  "k_payload"};
     return (id >= 0 && id < K_COUNT) ? names[id] : "";
 }
@@ -579,24 +579,23 @@ rt_status check_chain(const rt_texture* const* levels, int32_t nlevels, rt::Leve
     return RT_OK;
 }
 
-// Backward plans of every level and the workspace layout of the LOD backward.
+// The LOD backward's plan: the chain's buckets numbered one level after the
+// other, two units per fragment (its levels l0 and l0 + 1), sparse keys; then
+// the workspace layout (the backward's workspace, the units' weighted
+// upstream gradient).
 bool plan_lod_backward(const rt_texture* const* levels, int nlevels, int64_t N, int mode,
-                       rt::BwdPlan* plans, rt::LodBwdLayout* lay) {
-    size_t bwd = 0;
-    for (int l = 0; l < nlevels; l++) {
-        const rt::TexView& v = levels[l]->view;
-        // sparse: a fragment makes records only on the (one or two) levels it
-        // blends; on the others its scaled upstream gradient is zero
-        if (!rt::plan_backward(v.W, v.H, v.n, v.C, N, mode, &plans[l], true)) return false;
-        bwd = std::max(bwd, plans[l].total);
-    }
+                       rt::BwdPlan* plan, rt::LodBwdLayout* lay) {
+    const rt::TexView& v0 = levels[0]->view;
+    int64_t nb = 0;
+    for (int l = 0; l < nlevels; l++) nb += (int64_t)levels[l]->view.W * levels[l]->view.H;
+    if (nb > INT32_MAX || N > INT64_MAX / 2) return false;
+    const int64_t units = 2 * N;
+    if (!rt::plan_backward((int)nb, 1, v0.n, v0.C, units, mode, plan, true)) return false;
     auto a256 = [](size_t x) { return (x + 255) & ~(size_t)255; };
-    const size_t n1 = (size_t)std::max<int64_t>(N, 1);
+    const size_t u1 = (size_t)std::max<int64_t>(units, 1);
     lay->off_bwd = 0;
-    lay->off_gl = a256(bwd);
-    lay->off_view = lay->off_gl + a256(n1 * levels[0]->view.C * 4);
-    lay->off_uv = lay->off_view + a256(n1 * 12);
-    lay->total = lay->off_uv + a256(n1 * 8);
+    lay->off_gl = a256(plan->total);
+    lay->total = lay->off_gl + a256(u1 * v0.C * 4);
     return true;
 }
 }  // namespace
@@ -633,9 +632,9 @@ size_t rt_lookup_lod_bwd_workspace(const rt_texture* const* levels, int32_t nlev
             return 0;
         for (int l = 0; l < nlevels; l++)
             if (!levels[l]) return 0;
-        rt::BwdPlan plans[rt::MAX_LEVELS];
+        rt::BwdPlan plan;
         rt::LodBwdLayout lay;
-        if (!plan_lod_backward(levels, nlevels, count, (int)flags, plans, &lay)) return 0;
+        if (!plan_lod_backward(levels, nlevels, count, (int)flags, &plan, &lay)) return 0;
         return lay.total;
     } catch (...) {
         return 0;
@@ -665,9 +664,9 @@ rt_status rt_lookup_lod_bwd(const rt_texture* const* levels, int32_t nlevels,
         if (!aligned(grad_out, out_align(ls.C)))
             return fail(RT_ERR_INVALID_ARG, "grad_out must be %zu-byte aligned", out_align(ls.C));
     }
-    rt::BwdPlan plans[rt::MAX_LEVELS];
+    rt::BwdPlan plan;
     rt::LodBwdLayout lay;
-    if (!plan_lod_backward(levels, nlevels, f->count, (int)flags, plans, &lay))
+    if (!plan_lod_backward(levels, nlevels, f->count, (int)flags, &plan, &lay))
         return fail(RT_ERR_UNSUPPORTED, "sort key (W*H*n*n), bucket size (n*n*C <= 4096) or record count beyond the backward's limits");
     bool any = grad_view || grad_uv;
     for (int l = 0; l < nlevels; l++) any = any || grad_levels[l];
@@ -678,11 +677,9 @@ rt_status rt_lookup_lod_bwd(const rt_texture* const* levels, int32_t nlevels,
         if (ws_bytes < lay.total)
             return fail(RT_ERR_WORKSPACE_TOO_SMALL, "workspace has %zu bytes, %zu needed", ws_bytes, lay.total);
     }
-    rt::TexView views[rt::MAX_LEVELS];
-    for (int l = 0; l < nlevels; l++) views[l] = levels[l]->view;
-    hipError_t e = rt::launch_lookup_lod_bwd(views, nlevels, levels[0]->fmt, (int)flags, f->uv,
-                                             f->tbn, f->view, duv, grad_out, grad_levels,
-                                             grad_view, grad_uv, fragmap(f), plans, lay, ws,
+    hipError_t e = rt::launch_lookup_lod_bwd(ls, levels[0]->fmt, (int)flags, f->uv, f->tbn,
+                                             f->view, duv, grad_out, grad_levels, grad_view,
+                                             grad_uv, fragmap(f), plan, lay, ws,
                                              (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "lod backward launch");
     return ok();

@@ -211,6 +211,153 @@ __global__ __launch_bounds__(256) void k_bwd_fragment(
     }
 }
 
+// Level-of-detail backward, per fragment (the lookup blends levels l0 and
+// l0 + 1 with weights 1 - t and t; the level of detail is not
+// differentiated).  The mapping is formed once; each of the fragment's two
+// units u = 2f + s (level l0 + s) gets the upstream gradient times its weight,
+// its records in the chain's bucket numbering (start[l] + the level's bucket)
+// and the level's view and uv gradients, computed as in k_bwd_fragment and
+// summed over the units in level order.  A unit without weight or past the
+// last level makes no records (sentinel keys).  Units on a level whose
+// gradient is not wanted still make theirs (only the stores are skipped), so
+// the sorted positions, and with them the summation order of every written
+// level, do not depend on which levels are asked for.
+struct LevelStarts {
+    int64_t v[MAX_LEVELS + 1];
+};
+
+template <int FMT, int C, int MODE>
+__global__ __launch_bounds__(256) void k_lod_bwd_fragment(
+    LevelSet ls, const float* __restrict__ uv, const float* __restrict__ tbn,
+    const float* __restrict__ view, const float* __restrict__ duv,
+    const float* __restrict__ grad_out, LevelStarts start,
+    float* __restrict__ grad_view, float* __restrict__ grad_uv, uint32_t* __restrict__ keys,
+    float* __restrict__ wrec, float* __restrict__ gl, FragMap m, int cell_bits,
+    uint32_t sentinel) {
+    const int64_t f = frag_of(m, blockIdx.x, gridDim.x, threadIdx.x);
+    if (f < 0) return;
+    const int n = ls.n;
+    float g[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int c = 0; c < C; c++) g[c] = grad_out[f * C + c];
+    int l0;
+    float tt;
+    lod_split(((const float4*)duv)[f], ls.W, ls.H, ls.levels, l0, tt);
+    const Frag fr = load_frag(uv, tbn, view, f);
+    const Dir d = map_direction(fr.m, fr.w, n);
+    const Foot p = footprint(d.sx, d.sy, n);
+    const uint32_t cell = (uint32_t)(p.y0 * n + p.x0);
+    float vx = 0.f, vy = 0.f, vz = 0.f, su = 0.f, sv = 0.f;
+    for (int sl = 0; sl < 2; sl++) {
+        const int l = l0 + sl;
+        const int64_t u = 2 * f + sl;
+        const float w = sl == 0 ? 1.f - tt : tt;
+        float go[4] = {0.f, 0.f, 0.f, 0.f};
+        bool zero = true;
+#pragma unroll
+        for (int c = 0; c < C; c++) {
+            go[c] = w * g[c];
+            zero = zero && go[c] == 0.f;
+        }
+        const bool live = l < ls.levels && !zero;
+        const bool rec = live && keys != nullptr;
+        if (!rec && keys) {
+            if constexpr (MODE == MODE_NEAREST) keys[u] = sentinel;
+            else ((uint4*)keys)[u] = make_uint4(sentinel, sentinel, sentinel, sentinel);
+        }
+        if (!live) continue;
+        TexView t{};
+        t.data = ls.data[0];
+        t.scales = ls.scales[0];
+#pragma unroll
+        for (int k = 1; k < MAX_LEVELS; k++) {
+            if (l == k) {
+                t.data = ls.data[k];
+                t.scales = ls.scales[k];
+            }
+        }
+        t.W = max(ls.W >> l, 1);
+        t.H = max(ls.H >> l, 1);
+        t.n = n;
+        t.C = C;
+        if (rec) {
+#pragma unroll
+            for (int c = 0; c < C; c++) gl[u * C + c] = go[c];
+        }
+        const int64_t b0 = start.v[0];
+        int64_t off = b0;
+#pragma unroll
+        for (int k = 1; k < MAX_LEVELS; k++)
+            if (l == k) off = start.v[k];
+        float gsx = 0.f, gsy = 0.f;
+        if constexpr (MODE == MODE_NEAREST) {
+            const int i = bucket_of(fr.u, t.W), j = bucket_of(fr.v, t.H);
+            const int64_t b = (int64_t)j * t.W + i;
+            float lv;
+            if (grad_view) bucket_grads<FMT, C>(t, b, p, go, gsx, gsy, lv);
+            if (rec) {
+                keys[u] = ((uint32_t)(off + b) << cell_bits) | cell;
+                ((float2*)wrec)[u] = make_float2(p.fx, p.fy);
+            }
+        } else {
+            int i0, i1, j0, j1;
+            float a, bb;
+            bucket_pair(fr.u, t.W, i0, i1, a);
+            bucket_pair(fr.v, t.H, j0, j1, bb);
+            const int64_t bk[4] = {(int64_t)j0 * t.W + i0, (int64_t)j0 * t.W + i1,
+                                   (int64_t)j1 * t.W + i0, (int64_t)j1 * t.W + i1};
+            const float wb[4] = {(1.f - a) * (1.f - bb), a * (1.f - bb), (1.f - a) * bb, a * bb};
+            if (grad_view || grad_uv) {
+                float lv[4];
+#pragma unroll
+                for (int k = 0; k < 4; k++) {
+                    float dx, dy;
+                    bucket_grads<FMT, C>(t, bk[k], p, go, dx, dy, lv[k]);
+                    gsx += wb[k] * dx;
+                    gsy += wb[k] * dy;
+                }
+                if (grad_uv) {
+                    const float gu = (float)t.W * ((1.f - bb) * (lv[1] - lv[0]) + bb * (lv[3] - lv[2]));
+                    const float gv = (float)t.H * ((1.f - a) * (lv[2] - lv[0]) + a * (lv[3] - lv[1]));
+                    su += gu;
+                    sv += gv;
+                }
+            }
+            if (rec) {
+#pragma unroll
+                for (int k = 0; k < 4; k++)
+                    keys[4 * u + k] = ((uint32_t)(off + bk[k]) << cell_bits) | cell;
+                ((float4*)wrec)[u] = make_float4(p.fx, p.fy, a, bb);
+            }
+        }
+        if (grad_view) {
+            // as in k_bwd_fragment: dL/dB = (n/2) dL/ds on unclamped axes
+            float gbx = d.clx ? 0.f : gsx * (0.5f * (float)n);
+            float gby = d.cly ? 0.f : gsy * (0.5f * (float)n);
+            float gax, gay;
+            square_vjp(d.ax, d.ay, gbx, gby, gax, gay);
+            float gux = 0.f, guy = 0.f, guz = 0.f;
+            if (d.k > 0.f && d.L > 0.f) {
+                float sdot = d.ux * gax + d.uy * gay;
+                float coef = -0.5f * d.k * d.k * d.k * sdot;
+                float t2 = (2.f * d.L + d.uz) / d.L;
+                gux = d.k * gax + coef * d.ux * t2;
+                guy = d.k * gay + coef * d.uy * t2;
+                guz = coef * (d.uz * t2 + d.L);
+            }
+            vx += fr.m[0] * gux + fr.m[3] * guy + fr.m[6] * guz;
+            vy += fr.m[1] * gux + fr.m[4] * guy + fr.m[7] * guz;
+            vz += fr.m[2] * gux + fr.m[5] * guy + fr.m[8] * guz;
+        }
+    }
+    if (grad_view) {
+        grad_view[f * 3 + 0] = vx;
+        grad_view[f * 3 + 1] = vy;
+        grad_view[f * 3 + 2] = vz;
+    }
+    if (grad_uv) ((float2*)grad_uv)[f] = make_float2(su, sv);
+}
+
 // ---------------------------------------------------------------------------
 // 2. stable LSD radix sort of (key, record index), 8-bit digits
 // ---------------------------------------------------------------------------
@@ -846,6 +993,21 @@ __device__ __forceinline__ void tile_store(const float* tile, float* __restrict_
     wave_sync_lds();
 }
 
+// Destination of the tile of bucket b (wave-uniform), or nullptr when the
+// bucket's level is not written.  The level index is wave-uniform, so the
+// table is read from the kernel arguments with scalar loads, one level at a
+// time (a single level for the plain backward: no loop at all).
+__device__ __forceinline__ float* tile_dst(const TileOut& o, int64_t b, int te) {
+    const int64_t bu = (int64_t)__builtin_amdgcn_readfirstlane((uint32_t)b);
+    int l = 0;
+#pragma unroll 1
+    for (int k = 1; k < o.levels; k++)
+        if (bu >= o.start[k]) l = k;
+    l = __builtin_amdgcn_readfirstlane(l);
+    float* g = o.grad[l];
+    return g ? g + (bu - o.start[l]) * (int64_t)te : nullptr;
+}
+
 __device__ __forceinline__ void zero_store(float* __restrict__ dst, int te) {
     const int lane = threadIdx.x & 63;
     if ((te & 255) == 0) {
@@ -876,7 +1038,7 @@ __global__ __launch_bounds__(256) void k_segacc(const uint32_t* __restrict__ ske
                                                 const float* __restrict__ payf,
                                                 const float* __restrict__ payg,
                                                 const int2* __restrict__ range,
-                                                float* __restrict__ grad_tex, int64_t nbuckets,
+                                                const TileOut out, int64_t nbuckets,
                                                 int64_t R, int n, uint32_t cell_mask,
                                                 uint32_t* __restrict__ big_count,
                                                 uint32_t* __restrict__ big_list,
@@ -914,13 +1076,13 @@ __global__ __launch_bounds__(256) void k_segacc(const uint32_t* __restrict__ ske
             // wave-uniform bucket range (scalar registers, scalar loop control)
             const int rx = __builtin_amdgcn_readfirstlane(__shfl(rl.x, k, 64));
             const int ry = __builtin_amdgcn_readfirstlane(__shfl(rl.y, k, 64));
-            float* dst = grad_tex + (b0 + k) * te;
+            float* dst = tile_dst(out, b0 + k, te);
             const int cnt = ry - rx;
             if (cnt <= 0) {
-                zero_store(dst, te);
+                if (dst) zero_store(dst, te);
                 continue;
             }
-            if (cnt > 64) continue;  // listed above, or hot
+            if (cnt > 64 || !dst) continue;  // listed above, or hot; or not written
             if (!(rx >= win.start && ry <= win.end)) {
                 load_window<C, MODE>(skeys, svals, wrec, grad_out, payf, payg, rx, R, cell_mask,
                                      win);
@@ -943,7 +1105,7 @@ __global__ __launch_bounds__(256) void k_segacc_big(const uint32_t* __restrict__
                                                     const float* __restrict__ wrec,
                                                     const float* __restrict__ grad_out,
                                                     const int2* __restrict__ range,
-                                                    float* __restrict__ grad_tex, int n,
+                                                    const TileOut out, int n,
                                                     uint32_t cell_mask,
                                                     const uint32_t* __restrict__ big_count,
                                                     const uint32_t* __restrict__ big_list,
@@ -961,9 +1123,11 @@ __global__ __launch_bounds__(256) void k_segacc_big(const uint32_t* __restrict__
         const int2 r = range[b];
         const int rx = __builtin_amdgcn_readfirstlane(r.x);
         const int ry = __builtin_amdgcn_readfirstlane(r.y);
+        float* dst = tile_dst(out, b, te);
+        if (!dst) continue;
         tile_zero(tile, te);
         reduce_records<C, MODE>(skeys, svals, wrec, grad_out, rx, ry, n, cell_mask, tile);
-        tile_store(tile, grad_tex + (int64_t)b * te, te);
+        tile_store(tile, dst, te);
     }
 }
 
@@ -1006,7 +1170,7 @@ __global__ __launch_bounds__(64) void k_segacc_hot(const uint32_t* __restrict__ 
 __global__ __launch_bounds__(64) void k_combine_hot(const uint32_t* __restrict__ skeys,
                                                     const int2* __restrict__ range,
                                                     const float* __restrict__ part,
-                                                    float* __restrict__ grad_tex, int64_t R,
+                                                    const TileOut out, int64_t R,
                                                     int te, int cell_bits, int64_t nb) {
     const int lane = threadIdx.x;
     const int64_t k = blockIdx.x;
@@ -1022,7 +1186,8 @@ __global__ __launch_bounds__(64) void k_combine_hot(const uint32_t* __restrict__
         if ((int64_t)r.y - r.x <= PIECE) continue;
         if ((int64_t)r.x / PIECE != k) continue;  // combined by the chunk it starts in
         const int64_t k0 = (int64_t)r.x / PIECE, k1 = ((int64_t)r.y - 1) / PIECE;
-        float* dst = grad_tex + (int64_t)b * te;
+        float* dst = tile_dst(out, b, te);
+        if (!dst) continue;
         for (int q0 = 0; q0 < te; q0 += 64 * 8) {
             float acc[8];
 #pragma unroll
@@ -1142,7 +1307,7 @@ template <int MODE>
 static void launch_segacc_c(int C, dim3 grid, size_t shm, hipStream_t s, const uint32_t* sk,
                             const uint32_t* sv, const float* wrec, const float* go,
                             const float* pf, const float* pg,
-                            const int2* range, float* gt, int64_t nb, int64_t R, int n,
+                            const int2* range, const TileOut& gt, int64_t nb, int64_t R, int n,
                             uint32_t mask, uint32_t* bc, uint32_t* bl, int64_t cap) {
     switch (C) {
     case 1: hipLaunchKernelGGL((k_segacc<1, MODE>), grid, dim3(256), shm, s, sk, sv, wrec, go, pf, pg, range, gt, nb, R, n, mask, bc, bl, cap); break;
@@ -1155,7 +1320,7 @@ static void launch_segacc_c(int C, dim3 grid, size_t shm, hipStream_t s, const u
 template <int MODE>
 static void launch_segacc_big_c(int C, dim3 grid, size_t shm, hipStream_t s, const uint32_t* sk,
                                 const uint32_t* sv, const float* wrec, const float* go,
-                                const int2* range, float* gt, int n, uint32_t mask,
+                                const int2* range, const TileOut& gt, int n, uint32_t mask,
                                 const uint32_t* bc, const uint32_t* bl, int64_t cap) {
     switch (C) {
     case 1: hipLaunchKernelGGL((k_segacc_big<1, MODE>), grid, dim3(256), shm, s, sk, sv, wrec, go, range, gt, n, mask, bc, bl, cap); break;
@@ -1221,20 +1386,7 @@ hipError_t launch_backward(const TexView& t, int fmt, int mode, const float* uv,
     const int64_t N = m.N;
     char* wsb = (char*)ws;
     uint32_t* keys0 = (uint32_t*)(wsb + plan.off_keys0);
-    uint32_t* keys1 = (uint32_t*)(wsb + plan.off_keys1);
-    uint32_t* vals0 = (uint32_t*)(wsb + plan.off_vals0);
-    uint32_t* vals1 = (uint32_t*)(wsb + plan.off_vals1);
     float* wrec = (float*)(wsb + plan.off_wrec);
-    float* payf = (float*)(wsb + plan.off_payf);
-    float* payg = (float*)(wsb + plan.off_payg);
-    uint32_t* hist = (uint32_t*)(wsb + plan.off_hist);
-    uint32_t* hoff = (uint32_t*)(wsb + plan.off_hoff);
-    uint32_t* scanp = (uint32_t*)(wsb + plan.off_scanp);
-    uint32_t* big_count = (uint32_t*)(wsb + plan.off_range);  // BIG_LISTS counters
-    int2* range = (int2*)(big_count + BIG_LISTS * BIG_STRIDE);
-    uint32_t* big_list = (uint32_t*)(wsb + plan.off_biglist);
-    float* part = (float*)(wsb + plan.off_part);
-    const int64_t R = plan.records;
     const bool want_tex = grad_tex != nullptr;
 
     // 1. per fragment
@@ -1255,6 +1407,33 @@ hipError_t launch_backward(const TexView& t, int fmt, int mode, const float* uv,
         if (e != hipSuccess) return e;
     }
     if (!want_tex) return hipSuccess;
+
+    TileOut out{};
+    out.levels = 1;
+    out.start[0] = 0;
+    out.start[1] = (int64_t)t.W * t.H;
+    out.grad[0] = grad_tex;
+    return launch_accumulate(t.n, t.C, mode, grad_out, out, plan, ws, s);
+}
+
+hipError_t launch_accumulate(int n, int C, int mode, const float* grad_out, const TileOut& out,
+                             const BwdPlan& plan, void* ws, hipStream_t s) {
+    char* wsb = (char*)ws;
+    uint32_t* keys0 = (uint32_t*)(wsb + plan.off_keys0);
+    uint32_t* keys1 = (uint32_t*)(wsb + plan.off_keys1);
+    uint32_t* vals0 = (uint32_t*)(wsb + plan.off_vals0);
+    uint32_t* vals1 = (uint32_t*)(wsb + plan.off_vals1);
+    float* wrec = (float*)(wsb + plan.off_wrec);
+    float* payf = (float*)(wsb + plan.off_payf);
+    float* payg = (float*)(wsb + plan.off_payg);
+    uint32_t* hist = (uint32_t*)(wsb + plan.off_hist);
+    uint32_t* hoff = (uint32_t*)(wsb + plan.off_hoff);
+    uint32_t* scanp = (uint32_t*)(wsb + plan.off_scanp);
+    uint32_t* big_count = (uint32_t*)(wsb + plan.off_range);  // BIG_LISTS counters
+    int2* range = (int2*)(big_count + BIG_LISTS * BIG_STRIDE);
+    uint32_t* big_list = (uint32_t*)(wsb + plan.off_biglist);
+    float* part = (float*)(wsb + plan.off_part);
+    const int64_t R = plan.records;
 
     // 2. sort
     const uint32_t* skeys = keys0;
@@ -1288,7 +1467,7 @@ hipError_t launch_backward(const TexView& t, int fmt, int mode, const float* uv,
     }
 
     // 3. ranges
-    const int64_t nb = (int64_t)t.W * t.H;
+    const int64_t nb = plan.buckets;
     launch_fill(big_count, BIG_LISTS * BIG_STRIDE + nb * 2, 0u, s);  // counters and ranges
     if (R > 0) {
         prof_begin(K_BUCKET_RANGES, s);
@@ -1304,8 +1483,8 @@ hipError_t launch_backward(const TexView& t, int fmt, int mode, const float* uv,
     if (pay) {
         const dim3 gp((uint32_t)((R + 255) / 256));
         prof_begin(K_PAYLOAD, s);
-        if (mode == MODE_NEAREST) launch_payload_c<MODE_NEAREST>(t.C, gp, s, skeys, svals, wrec, grad_out, range, R, plan.cell_bits, nb, payf, payg);
-        else launch_payload_c<MODE_BILINEAR>(t.C, gp, s, skeys, svals, wrec, grad_out, range, R, plan.cell_bits, nb, payf, payg);
+        if (mode == MODE_NEAREST) launch_payload_c<MODE_NEAREST>(C, gp, s, skeys, svals, wrec, grad_out, range, R, plan.cell_bits, nb, payf, payg);
+        else launch_payload_c<MODE_BILINEAR>(C, gp, s, skeys, svals, wrec, grad_out, range, R, plan.cell_bits, nb, payf, payg);
         prof_end(K_PAYLOAD, s);
     }
     const int te = (int)plan.tile_elems;
@@ -1314,9 +1493,9 @@ hipError_t launch_backward(const TexView& t, int fmt, int mode, const float* uv,
     const dim3 g1((uint32_t)((groups + 3) / 4));
     prof_begin(K_SEGACC, s);
     if (mode == MODE_NEAREST)
-        launch_segacc_c<MODE_NEAREST>(t.C, g1, (size_t)4 * te * 4, s, skeys, svals, wrec, grad_out, pay ? payf : nullptr, payg, range, grad_tex, nb, R, t.n, cell_mask, big_count, big_list, plan.big_cap);
+        launch_segacc_c<MODE_NEAREST>(C, g1, (size_t)4 * te * 4, s, skeys, svals, wrec, grad_out, pay ? payf : nullptr, payg, range, out, nb, R, n, cell_mask, big_count, big_list, plan.big_cap);
     else
-        launch_segacc_c<MODE_BILINEAR>(t.C, g1, (size_t)4 * te * 4, s, skeys, svals, wrec, grad_out, pay ? payf : nullptr, payg, range, grad_tex, nb, R, t.n, cell_mask, big_count, big_list, plan.big_cap);
+        launch_segacc_c<MODE_BILINEAR>(C, g1, (size_t)4 * te * 4, s, skeys, svals, wrec, grad_out, pay ? payf : nullptr, payg, range, out, nb, R, n, cell_mask, big_count, big_list, plan.big_cap);
     prof_end(K_SEGACC, s);
     if (R > 64) {
         // BIG_LISTS x parts workgroups, four wavefronts each; parts grows with
@@ -1326,9 +1505,9 @@ hipError_t launch_backward(const TexView& t, int fmt, int mode, const float* uv,
         const dim3 g2((uint32_t)(BIG_LISTS * parts));
         prof_begin(K_SEGACC_BIG, s);
         if (mode == MODE_NEAREST)
-            launch_segacc_big_c<MODE_NEAREST>(t.C, g2, (size_t)4 * te * 4, s, skeys, svals, wrec, grad_out, range, grad_tex, t.n, cell_mask, big_count, big_list, plan.big_cap);
+            launch_segacc_big_c<MODE_NEAREST>(C, g2, (size_t)4 * te * 4, s, skeys, svals, wrec, grad_out, range, out, n, cell_mask, big_count, big_list, plan.big_cap);
         else
-            launch_segacc_big_c<MODE_BILINEAR>(t.C, g2, (size_t)4 * te * 4, s, skeys, svals, wrec, grad_out, range, grad_tex, t.n, cell_mask, big_count, big_list, plan.big_cap);
+            launch_segacc_big_c<MODE_BILINEAR>(C, g2, (size_t)4 * te * 4, s, skeys, svals, wrec, grad_out, range, out, n, cell_mask, big_count, big_list, plan.big_cap);
         prof_end(K_SEGACC_BIG, s);
     }
 
@@ -1337,15 +1516,52 @@ hipError_t launch_backward(const TexView& t, int fmt, int mode, const float* uv,
         const dim3 g2((uint32_t)plan.chunks);
         prof_begin(K_SEGACC_HOT, s);
         if (mode == MODE_NEAREST)
-            launch_segacc_hot_c<MODE_NEAREST>(t.C, g2, (size_t)te * 4, s, skeys, svals, wrec, grad_out, range, part, R, t.n, plan.cell_bits, nb);
+            launch_segacc_hot_c<MODE_NEAREST>(C, g2, (size_t)te * 4, s, skeys, svals, wrec, grad_out, range, part, R, n, plan.cell_bits, nb);
         else
-            launch_segacc_hot_c<MODE_BILINEAR>(t.C, g2, (size_t)te * 4, s, skeys, svals, wrec, grad_out, range, part, R, t.n, plan.cell_bits, nb);
+            launch_segacc_hot_c<MODE_BILINEAR>(C, g2, (size_t)te * 4, s, skeys, svals, wrec, grad_out, range, part, R, n, plan.cell_bits, nb);
         prof_end(K_SEGACC_HOT, s);
         prof_begin(K_COMBINE_HOT, s);
-        hipLaunchKernelGGL(k_combine_hot, g2, dim3(64), 0, s, skeys, range, part, grad_tex, R, te,
+        hipLaunchKernelGGL(k_combine_hot, g2, dim3(64), 0, s, skeys, range, part, out, R, te,
                            plan.cell_bits, nb);
         prof_end(K_COMBINE_HOT, s);
     }
+    return hipGetLastError();
+}
+
+
+template <int FMT, int MODE>
+static void launch_lod_frag_c(int C, dim3 grid, hipStream_t s, const LevelSet& ls,
+                              const float* uv, const float* tbn, const float* view,
+                              const float* duv, const float* go, const LevelStarts& st, float* gview, float* guv, uint32_t* keys,
+                              float* wrec, float* gl, const FragMap& m, int cb, uint32_t sent) {
+    switch (C) {
+    case 1: hipLaunchKernelGGL((k_lod_bwd_fragment<FMT, 1, MODE>), grid, dim3(256), 0, s, ls, uv, tbn, view, duv, go, st, gview, guv, keys, wrec, gl, m, cb, sent); break;
+    case 2: hipLaunchKernelGGL((k_lod_bwd_fragment<FMT, 2, MODE>), grid, dim3(256), 0, s, ls, uv, tbn, view, duv, go, st, gview, guv, keys, wrec, gl, m, cb, sent); break;
+    case 3: hipLaunchKernelGGL((k_lod_bwd_fragment<FMT, 3, MODE>), grid, dim3(256), 0, s, ls, uv, tbn, view, duv, go, st, gview, guv, keys, wrec, gl, m, cb, sent); break;
+    default: hipLaunchKernelGGL((k_lod_bwd_fragment<FMT, 4, MODE>), grid, dim3(256), 0, s, ls, uv, tbn, view, duv, go, st, gview, guv, keys, wrec, gl, m, cb, sent); break;
+    }
+}
+
+hipError_t launch_lod_bwd_fragment(const LevelSet& ls, int fmt, int mode, const float* uv,
+                                   const float* tbn, const float* view, const float* duv,
+                                   const float* grad_out, const int64_t* start, float* grad_view, float* grad_uv,
+                                   uint32_t* keys, float* wrec, float* gl, const FragMap& m,
+                                   int cell_bits, uint32_t sentinel, hipStream_t s) {
+    LevelStarts st{};
+    for (int l = 0; l <= ls.levels && l <= MAX_LEVELS; l++) st.v[l] = start[l];
+    const dim3 grid(fragmap_blocks(m));
+    const int C = ls.C;
+    prof_begin(K_LOD_BWD_FRAGMENT, s);
+    if (mode == MODE_NEAREST) {
+        if (fmt == FMT_F32) launch_lod_frag_c<FMT_F32, MODE_NEAREST>(C, grid, s, ls, uv, tbn, view, duv, grad_out, st, grad_view, grad_uv, keys, wrec, gl, m, cell_bits, sentinel);
+        else if (fmt == FMT_BF16) launch_lod_frag_c<FMT_BF16, MODE_NEAREST>(C, grid, s, ls, uv, tbn, view, duv, grad_out, st, grad_view, grad_uv, keys, wrec, gl, m, cell_bits, sentinel);
+        else launch_lod_frag_c<FMT_FP8, MODE_NEAREST>(C, grid, s, ls, uv, tbn, view, duv, grad_out, st, grad_view, grad_uv, keys, wrec, gl, m, cell_bits, sentinel);
+    } else {
+        if (fmt == FMT_F32) launch_lod_frag_c<FMT_F32, MODE_BILINEAR>(C, grid, s, ls, uv, tbn, view, duv, grad_out, st, grad_view, grad_uv, keys, wrec, gl, m, cell_bits, sentinel);
+        else if (fmt == FMT_BF16) launch_lod_frag_c<FMT_BF16, MODE_BILINEAR>(C, grid, s, ls, uv, tbn, view, duv, grad_out, st, grad_view, grad_uv, keys, wrec, gl, m, cell_bits, sentinel);
+        else launch_lod_frag_c<FMT_FP8, MODE_BILINEAR>(C, grid, s, ls, uv, tbn, view, duv, grad_out, st, grad_view, grad_uv, keys, wrec, gl, m, cell_bits, sentinel);
+    }
+    prof_end(K_LOD_BWD_FRAGMENT, s);
     return hipGetLastError();
 }
 

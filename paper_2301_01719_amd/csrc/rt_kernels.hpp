@@ -41,7 +41,7 @@ enum KernelId {
     K_VQ_SCATTER,
     K_VQ_PIECES,
     K_VQ_COMBINE,
-    K_LOD_BWD_SCALE,
+    K_LOD_BWD_FRAGMENT,
     K_MIP_ADJOINT,
     K_PAYLOAD,
     K_COUNT
@@ -133,19 +133,43 @@ constexpr int BIG_RUN = 64;     // consecutive groups that append to one list
 bool plan_backward(int W, int H, int n, int C, int64_t N, int mode, BwdPlan* p,
                    bool sparse = false);
 
-// Backward of the level-of-detail lookup: one plain backward per level, on
-// the upstream gradient scaled by the level's weight.  Workspace: the largest
-// level's backward workspace, then the scaled gradient [N][C] and the
-// per-level view [N][3] and uv [N][2] gradients.
-struct LodBwdLayout {
-    size_t off_bwd, off_gl, off_view, off_uv, total;
+// Where the accumulation writes the tile of bucket b: the buckets of one
+// gradient, or those of the levels of a chain numbered one level after the
+// other (level l holds buckets [start[l], start[l + 1]) and writes them to
+// grad[l]; a NULL level is not written).
+struct TileOut {
+    int levels;
+    int64_t start[MAX_LEVELS + 1];
+    float* grad[MAX_LEVELS];
 };
-hipError_t launch_lookup_lod_bwd(const TexView* levels, int nlevels, int fmt, int mode,
-                                 const float* uv, const float* tbn, const float* view,
-                                 const float* duv, const float* grad_out, float* const* grad_levels,
+
+// Steps after the per-fragment kernel: sort the records, find the bucket
+// ranges, write the sorted payload, accumulate the tiles into `out`.
+// grad_out: the upstream gradient of the records' fragments (units).
+hipError_t launch_accumulate(int n, int C, int mode, const float* grad_out, const TileOut& out,
+                             const BwdPlan& plan, void* ws, hipStream_t s);
+
+// Backward of the level-of-detail lookup in one pass: every fragment makes
+// records on the (one or two) levels it blends, in the chain's bucket
+// numbering, as two units 2f and 2f + 1 (levels l0 and l0 + 1) whose upstream
+// gradient is the fragment's times the level's weight; one sort and one
+// accumulation serve all levels.  Workspace: the backward's for 2N units, then
+// the units' weighted gradient [2N][C].
+struct LodBwdLayout {
+    size_t off_bwd, off_gl, total;
+};
+hipError_t launch_lookup_lod_bwd(const LevelSet& ls, int fmt, int mode, const float* uv,
+                                 const float* tbn, const float* view, const float* duv,
+                                 const float* grad_out, float* const* grad_levels,
                                  float* grad_view, float* grad_uv, const FragMap& m,
-                                 const BwdPlan* plans, const LodBwdLayout& lay, void* ws,
+                                 const BwdPlan& plan, const LodBwdLayout& lay, void* ws,
                                  hipStream_t s);
+hipError_t launch_lod_bwd_fragment(const LevelSet& ls, int fmt, int mode, const float* uv,
+                                   const float* tbn, const float* view, const float* duv,
+                                   const float* grad_out, const int64_t* start,
+                                   float* grad_view, float* grad_uv,
+                                   uint32_t* keys, float* wrec, float* gl, const FragMap& m,
+                                   int cell_bits, uint32_t sentinel, hipStream_t s);
 hipError_t launch_mip_adjoint(const TexView& src, const float* grad_dst, float* grad_src,
                               hipStream_t s);
 

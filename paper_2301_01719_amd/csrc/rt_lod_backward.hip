@@ -6,12 +6,12 @@
 // derivatives and is not differentiated).  So the gradient of level l's
 // texels is the plain backward on level l with each fragment's upstream
 // gradient scaled by its weight on that level, and the view and uv gradients
-// are the sums over the levels of the plain backward's.  Each level reuses
-// the deterministic sort-and-accumulate backward with a sparse plan: a
-// fragment whose weight on the level is 0 makes no records there (otherwise
-// the coarse levels' few buckets would each collect every fragment of the
-// view).  The per-level view and uv gradients are added in level order, so
-// the result is bitwise reproducible.
+// are the sums over the levels of the plain backward's.  All levels are done
+// in one pass: the chain's buckets are numbered one level after the other,
+// every fragment makes records on the (at most two) levels it blends, and one
+// sort and one accumulation (the plain backward's) write every level's tiles.
+// The view and uv gradients are summed over the fragment's levels in level
+// order in registers, so the result is bitwise reproducible.
 //
 // Chain adjoint: level l+1's bucket is the mean of the 2 x 2 (or 2) buckets of
 // level l it covers, so each of those receives the parent's gradient divided
@@ -24,76 +24,51 @@
 
 namespace rt {
 
-// g_l[f][c] = w_l(f) g[f][c], w_l = 1 - t on l0, t on l0 + 1, 0 elsewhere
-__global__ __launch_bounds__(256) void k_lod_scale(const float* __restrict__ grad_out,
-                                                   const float* __restrict__ duv, int64_t N,
-                                                   int C, int W, int H, int levels, int l,
-                                                   float* __restrict__ gl) {
-    const int64_t f = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (f >= N) return;
-    int l0;
-    float t;
-    lod_split(((const float4*)duv)[f], W, H, levels, l0, t);
-    const float w = l == l0 ? 1.f - t : (l == l0 + 1 ? t : 0.f);
-    for (int c = 0; c < C; c++) gl[f * C + c] = w * grad_out[f * C + c];
-}
-
 __global__ __launch_bounds__(256) void k_fill_f32(float* __restrict__ p, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (i < n) p[i] = 0.f;
 }
 
-__global__ __launch_bounds__(256) void k_add_f32(float* __restrict__ dst,
-                                                 const float* __restrict__ src, int64_t n) {
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i < n) dst[i] += src[i];
-}
-
 static uint32_t blocks_of(int64_t n) { return (uint32_t)((n + 255) / 256); }
 
-hipError_t launch_lookup_lod_bwd(const TexView* levels, int nlevels, int fmt, int mode,
-                                 const float* uv, const float* tbn, const float* view,
-                                 const float* duv, const float* grad_out, float* const* grad_levels,
+hipError_t launch_lookup_lod_bwd(const LevelSet& ls, int fmt, int mode, const float* uv,
+                                 const float* tbn, const float* view, const float* duv,
+                                 const float* grad_out, float* const* grad_levels,
                                  float* grad_view, float* grad_uv, const FragMap& m,
-                                 const BwdPlan* plans, const LodBwdLayout& lay, void* ws,
+                                 const BwdPlan& plan, const LodBwdLayout& lay, void* ws,
                                  hipStream_t s) {
     const int64_t N = m.N;
+    const int64_t te = (int64_t)ls.n * ls.n * ls.C;
+    TileOut out{};
+    out.levels = ls.levels;
+    uint32_t want = 0;
+    int64_t at = 0;
+    for (int l = 0; l < ls.levels; l++) {
+        out.start[l] = at;
+        out.grad[l] = grad_levels[l];
+        if (grad_levels[l]) want |= 1u << l;
+        at += (int64_t)std::max(ls.W >> l, 1) * std::max(ls.H >> l, 1);
+    }
+    out.start[ls.levels] = at;
     if (N <= 0) {
         // no fragment: every level's gradient is zero
-        for (int l = 0; l < nlevels; l++) {
+        for (int l = 0; l < ls.levels; l++) {
             if (!grad_levels[l]) continue;
-            const int64_t e = (int64_t)levels[l].W * levels[l].H * levels[l].n * levels[l].n *
-                              levels[l].C;
+            const int64_t e = (out.start[l + 1] - out.start[l]) * te;
             hipLaunchKernelGGL(k_fill_f32, dim3(blocks_of(e)), dim3(256), 0, s, grad_levels[l], e);
         }
         return hipGetLastError();
     }
-    const int C = levels[0].C;
     char* base = (char*)ws;
+    char* bws = base + lay.off_bwd;
     float* gl = (float*)(base + lay.off_gl);
-    float* tv = (float*)(base + lay.off_view);
-    float* tu = (float*)(base + lay.off_uv);
-    void* bws = base + lay.off_bwd;
-    prof_begin(K_LOD_BWD_SCALE, s);
-    if (grad_view) hipLaunchKernelGGL(k_fill_f32, dim3(blocks_of(3 * N)), dim3(256), 0, s, grad_view, 3 * N);
-    if (grad_uv) hipLaunchKernelGGL(k_fill_f32, dim3(blocks_of(2 * N)), dim3(256), 0, s, grad_uv, 2 * N);
-    prof_end(K_LOD_BWD_SCALE, s);
-    for (int l = 0; l < nlevels; l++) {
-        if (!grad_levels[l] && !grad_view && !grad_uv) continue;
-        prof_begin(K_LOD_BWD_SCALE, s);
-        hipLaunchKernelGGL(k_lod_scale, dim3(blocks_of(N)), dim3(256), 0, s, grad_out, duv, N, C,
-                           levels[0].W, levels[0].H, nlevels, l, gl);
-        prof_end(K_LOD_BWD_SCALE, s);
-        hipError_t e = launch_backward(levels[l], fmt, mode, uv, tbn, view, gl, grad_levels[l],
-                                       grad_view ? tv : nullptr, grad_uv ? tu : nullptr, m,
-                                       plans[l], bws, s);
-        if (e != hipSuccess) return e;
-        prof_begin(K_LOD_BWD_SCALE, s);
-        if (grad_view) hipLaunchKernelGGL(k_add_f32, dim3(blocks_of(3 * N)), dim3(256), 0, s, grad_view, (const float*)tv, 3 * N);
-        if (grad_uv) hipLaunchKernelGGL(k_add_f32, dim3(blocks_of(2 * N)), dim3(256), 0, s, grad_uv, (const float*)tu, 2 * N);
-        prof_end(K_LOD_BWD_SCALE, s);
-    }
-    return hipGetLastError();
+    uint32_t* keys = want ? (uint32_t*)(bws + plan.off_keys0) : nullptr;
+    float* wrec = (float*)(bws + plan.off_wrec);
+    hipError_t e = launch_lod_bwd_fragment(ls, fmt, mode, uv, tbn, view, duv, grad_out,
+                                           out.start, grad_view, grad_uv, keys, wrec, gl, m,
+                                           plan.cell_bits, plan.sentinel, s);
+    if (e != hipSuccess || !want) return e;
+    return launch_accumulate(ls.n, ls.C, mode, gl, out, plan, bws, s);
 }
 
 // grad_src (level l, W x H buckets of E values) += adjoint of the chain step
