@@ -212,6 +212,58 @@ def test_lod_backward_vs_oracle(rt, mode):
     check_grad_vec(host(gu)[keep], ref["grad_uv"][keep], ref["scale_uv"][keep])
 
 
+
+@pytest.mark.parametrize("fmt", ["bf16", "fp8"])
+@pytest.mark.parametrize("mode", ["nearest", "bilinear"])
+def test_lod_backward_quantized_levels(rt, fmt, mode):
+    """Levels stored in BF16 or FP8 (each level of the chain quantised on its
+    own): the gradients are the oracle's on the decoded chain.  Level 0 holds
+    multiples of 1/256 below 1, so every mean of the chain is exact in binary32
+    and binary64 alike and both sides quantise the same values, each with its
+    own quantiser (the codes are compared bit for bit)."""
+    from helpers import check_grad_tex, check_grad_vec
+    W, H, n, C = 16, 8, 4, 4
+    gb, _, duv = _views_case(61, W, H, n, C)
+    g = torch.Generator().manual_seed(62)
+    tex = (torch.randint(0, 256, (H, W, n, n, C), generator=g).float() / 256).to(DEV)
+    uv, tbn, view = gb_host(gb)
+    keep = away_from_edges(uv, tbn, view, W, H, n, mode) & _lod_keep(host(duv), W, H)
+    k = torch.from_numpy(np.nonzero(keep)[0]).to(DEV)
+    gb = wl.GBuffer(gb.uv[k].contiguous(), gb.tbn[k].contiguous(), gb.view[k].contiguous())
+    duv = duv[k].contiguous()
+    go = torch.randn((gb.count, C), generator=torch.Generator().manual_seed(63)).to(DEV)
+    chain = rt.build_mips(rt.Texture(tex, W, H, n, C))
+    och = oracle.build_mips(host(tex), W, H, n, C, len(chain))
+    ofmt = oracle.FMT_BF16 if fmt == "bf16" else oracle.FMT_FP8_E4M3
+    qchain, dec = [], []
+    for lvl, t in zip(och, chain):
+        nb = t.W * t.H
+        codes, scales = rt.quantize(t, fmt)
+        qchain.append(rt.Texture(codes, t.W, t.H, n, C, fmt, scales))
+        oc, osc = oracle.quantize(lvl.astype(np.float32), nb, n * n * C, ofmt)
+        gpu_codes = host(codes).reshape(-1).view(oc.dtype)
+        assert np.array_equal(gpu_codes, oc)
+        if fmt == "bf16":
+            vals = np.vectorize(oracle.bf16_to_f64)(oc)
+        else:
+            assert np.array_equal(host(scales).reshape(-1), osc)
+            vals = (np.vectorize(oracle.e4m3_to_f64)(oc).reshape(nb, -1)
+                    * osc.astype(np.float64)[:, None])
+        dec.append(vals.reshape(lvl.shape))
+    grads, gv, gu = rt.lookup_lod_bwd(qchain, gb.uv, gb.tbn, gb.view, duv, go, mode)
+    torch.cuda.synchronize()
+    uv, tbn, view = gb_host(gb)
+    omode = oracle.MODE_NEAREST if mode == "nearest" else oracle.MODE_BILINEAR
+    ref = oracle.lookup_lod_bwd(dec, uv, tbn, view, host(duv), host(go), W, H, n, C, mode=omode,
+                                full=True)
+    for l in range(len(chain)):
+        r = {"grad_tex": ref["grad"][l], "abs_tex": ref["abs"][l], "absg_tex": ref["absg"][l]}
+        check_grad_tex(host(grads[l]), r, n)
+    _, _, edge = oracle.indices(uv, tbn, view, W, H, n)
+    keep = (edge[:, 1] >= 1e-5) & (edge[:, 2] >= 1e-5)
+    check_grad_vec(host(gv)[keep], ref["grad_view"][keep], ref["scale_view"][keep])
+    check_grad_vec(host(gu)[keep], ref["grad_uv"][keep], ref["scale_uv"][keep])
+
 @pytest.mark.parametrize("mode", ["nearest", "bilinear"])
 def test_lod_backward_hot_coarse_level(rt, mode):
     """A 2 x 2 matrix and its 1 x 1 level under 12000 fragments with lambda
