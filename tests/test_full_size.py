@@ -9,7 +9,10 @@ checked on sampled outputs the oracle computes one by one.
 * 64 views of 1024x1024 over 512x512 buckets: indices and forwards on a sample;
 * 8 views of 3840x2160 over 2048x2048 buckets stored as FP8 with per-bucket
   scales: forward and backward on samples, and the end-to-end error against
-  FP32 storage.
+  FP32 storage;
+* 16 views of 512x512 over 256x256 buckets of 8x8 RGB (FP32, three channels):
+  indices and forward on a sample, view gradients on sampled fragments and
+  the dense gradient on a bucket window.
 
 Indices are compared only for fragments at least 1e-6 (normalised) from every
 cell edge that decides them.  For the dense gradient the upstream gradient of
@@ -246,5 +249,45 @@ def test_large_fp8_forward_backward(rt):
     rt_tex = check_grad_tex(G, r3, n)
     print(f"large fp8: {N} fragments; fwd err vs oracle {err8:.2e} on {int(fsel.sum())}; "
           f"end-to-end vs FP32 storage max {e2e_max:.3e} mean {e2e_mean:.3e}; "
+          f"grad_view err/tol {rv[0]:.2e}; grad_tex err/tol {rt_tex:.2e} "
+          f"({len(near_ids)} fragments near the window, {n_near} masked)")
+
+
+def test_rgb_multi_view_full_size(rt):
+    w = wl.WORKLOADS["c4"]
+    W, H, n, C = w.W, w.H, w.n, w.C
+    assert C == 3 and n == 8
+    tex = w.make_texture(DEV)
+    gb = w.make_gbuffer(DEV)
+    N = gb.count
+    t = rt.Texture(tex, W, H, n, C)
+    out = rt.lookup_fwd(t, gb.uv, gb.tbn, gb.view, image=gb.image)
+    idx_g, _ = rt.debug_indices(t, gb.uv, gb.tbn, gb.view)
+    go = wl.grad_out(N, C, seed=w.seed, device=DEV)
+    win = (100, 60, 24, 24)
+    near_ids = _window_fragments(rt, t, gb, win)
+    gm, n_near = _mask_near_edges(gb, go, near_ids, W, H, n)
+    gt, gv, _ = rt.lookup_bwd(t, gb.uv, gb.tbn, gb.view, gm, want_uv=False, image=gb.image)
+    torch.cuda.synchronize()
+    otex = oracle.Tex(host(tex), W, H, n, C)
+    sel = _sample(N, 300000, 4)
+    uv, tbn, view, o, gi, g_s, gv_s = _take((gb.uv, gb.tbn, gb.view, out, idx_g, gm, gv), sel)
+    idx, _, edge = oracle.indices(uv, tbn, view, W, H, n)
+    keep = _keep(edge)
+    assert np.array_equal(gi[keep], idx[keep])
+    err = check_fwd(o, oracle.lookup_fwd(otex, uv, tbn, view), keep)
+    # view gradients on sampled fragments away from the kinks
+    part = np.nonzero(keep)[0][:50000]
+    r = oracle.lookup_bwd(otex, uv[part], tbn[part], view[part], g_s[part], want_tex=False,
+                          want_uv=False)
+    smooth = (edge[part, 1] >= 1e-5) & (edge[part, 2] >= 1e-5)
+    rv = check_grad_vec(gv_s[part][smooth], r["grad_view"][smooth], r["scale_view"][smooth])
+    # the dense gradient on the window
+    uvw, tbnw, vw, gw = _take((gb.uv, gb.tbn, gb.view, gm), near_ids)
+    r3 = oracle.lookup_bwd(otex, uvw, tbnw, vw, gw, window=win, want_view=False, want_uv=False)
+    assert np.count_nonzero(r3["absg_tex"]) > 100
+    G = host(gt[win[1]:win[1] + win[3], win[0]:win[0] + win[2]])
+    rt_tex = check_grad_tex(G, r3, n)
+    print(f"16 views RGB: {N} fragments; fwd max err {err:.2e} on {int(keep.sum())}; "
           f"grad_view err/tol {rv[0]:.2e}; grad_tex err/tol {rt_tex:.2e} "
           f"({len(near_ids)} fragments near the window, {n_near} masked)")
