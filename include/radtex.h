@@ -298,7 +298,9 @@ size_t rt_lookup_lod_bwd_workspace(const rt_texture* const* levels, int32_t nlev
  *   grad_view       float [N][3], the sum over the levels of rt_lookup_bwd's
  *                   view gradients (NULL skips it);
  *   grad_uv         float [N][2], likewise (0 in nearest mode).
- * Bitwise reproducible (per-level sums in level order).  To reach level 0 of
+ * Bitwise reproducible (a fixed summation order per bucket; the view and uv
+ * gradients summed over the levels in level order), and a level's bits do
+ * not depend on which other levels are requested.  To reach level 0 of
  * a chain built by rt_build_mip, fold each level's gradient down with
  * rt_build_mip_adjoint.  grad_levels: HOST array of nlevels DEVICE pointers
  * (16-byte aligned); duv as for rt_lookup_fwd_lod; workspace: DEVICE, at
