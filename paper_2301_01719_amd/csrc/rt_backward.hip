@@ -1018,10 +1018,12 @@ __device__ __forceinline__ void zero_store(float* __restrict__ dst, int te) {
     }
 }
 
-// pass 1: each wavefront owns SEG_GROUP consecutive buckets (their ranges come
-// in one coalesced load) and writes their tiles one after the other, so the
-// stores of untouched buckets are issued back to back; four wavefronts per
-// workgroup.  k_segacc writes the untouched buckets and those with at most 64
+// pass 1: each wavefront owns G consecutive buckets (their ranges come in one
+// coalesced load) and writes their tiles one after the other, so the stores
+// of untouched buckets are issued back to back; four wavefronts per
+// workgroup.  G = SEG_GROUP (8), or 4 when the records are read from the
+// sorted payload (shorter groups spread the buckets over more wavefronts once
+// the window loads are cheap).  k_segacc writes the untouched buckets and those with at most 64
 // records (served from one register window) and lists those with 65..PIECE
 // records for k_segacc_big (rounds of 64 with a carry).  Splitting keeps the
 // register footprint of the common case small.  The list is split over
@@ -1030,7 +1032,7 @@ __device__ __forceinline__ void zero_store(float* __restrict__ dst, int te) {
 // take the lists in turn (group g appends to list (g / BIG_RUN) mod
 // BIG_LISTS), which keeps neighbouring buckets on one XCD in k_segacc_big.
 // The order inside a list does not matter, each bucket is reduced alone.
-template <int C, int MODE>
+template <int C, int MODE, int G>
 __global__ __launch_bounds__(256) void k_segacc(const uint32_t* __restrict__ skeys,
                                                 const uint32_t* __restrict__ svals,
                                                 const float* __restrict__ wrec,
@@ -1047,13 +1049,13 @@ __global__ __launch_bounds__(256) void k_segacc(const uint32_t* __restrict__ ske
     const int te = n * n * C;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     float* tile = lds + w * te;
-    const int64_t ngroups = (nbuckets + SEG_GROUP - 1) / SEG_GROUP;
+    const int64_t ngroups = (nbuckets + G - 1) / G;
     for (int64_t grp = (int64_t)xcd_block_id(blockIdx.x, gridDim.x) * 4 + w; grp < ngroups;
          grp += (int64_t)gridDim.x * 4) {
-        const int64_t b0 = grp * SEG_GROUP;
+        const int64_t b0 = grp * G;
         int2 rl = make_int2(0, 0);
-        if (lane < SEG_GROUP && b0 + lane < nbuckets) rl = range[b0 + lane];
-        const int nb = (int)((nbuckets - b0) < SEG_GROUP ? (nbuckets - b0) : SEG_GROUP);
+        if (lane < G && b0 + lane < nbuckets) rl = range[b0 + lane];
+        const int nb = (int)((nbuckets - b0) < G ? (nbuckets - b0) : G);
         // list the group's buckets with 65..PIECE records (more go to pass 2)
         const int cl = rl.y - rl.x;
         const bool big = cl > 64 && cl <= PIECE;
@@ -1303,17 +1305,17 @@ static void launch_bwd_fragment_c(const TexView& t, const float* uv, const float
     }
 }
 
-template <int MODE>
+template <int MODE, int G>
 static void launch_segacc_c(int C, dim3 grid, size_t shm, hipStream_t s, const uint32_t* sk,
                             const uint32_t* sv, const float* wrec, const float* go,
                             const float* pf, const float* pg,
                             const int2* range, const TileOut& gt, int64_t nb, int64_t R, int n,
                             uint32_t mask, uint32_t* bc, uint32_t* bl, int64_t cap) {
     switch (C) {
-    case 1: hipLaunchKernelGGL((k_segacc<1, MODE>), grid, dim3(256), shm, s, sk, sv, wrec, go, pf, pg, range, gt, nb, R, n, mask, bc, bl, cap); break;
-    case 2: hipLaunchKernelGGL((k_segacc<2, MODE>), grid, dim3(256), shm, s, sk, sv, wrec, go, pf, pg, range, gt, nb, R, n, mask, bc, bl, cap); break;
-    case 3: hipLaunchKernelGGL((k_segacc<3, MODE>), grid, dim3(256), shm, s, sk, sv, wrec, go, pf, pg, range, gt, nb, R, n, mask, bc, bl, cap); break;
-    default: hipLaunchKernelGGL((k_segacc<4, MODE>), grid, dim3(256), shm, s, sk, sv, wrec, go, pf, pg, range, gt, nb, R, n, mask, bc, bl, cap); break;
+    case 1: hipLaunchKernelGGL((k_segacc<1, MODE, G>), grid, dim3(256), shm, s, sk, sv, wrec, go, pf, pg, range, gt, nb, R, n, mask, bc, bl, cap); break;
+    case 2: hipLaunchKernelGGL((k_segacc<2, MODE, G>), grid, dim3(256), shm, s, sk, sv, wrec, go, pf, pg, range, gt, nb, R, n, mask, bc, bl, cap); break;
+    case 3: hipLaunchKernelGGL((k_segacc<3, MODE, G>), grid, dim3(256), shm, s, sk, sv, wrec, go, pf, pg, range, gt, nb, R, n, mask, bc, bl, cap); break;
+    default: hipLaunchKernelGGL((k_segacc<4, MODE, G>), grid, dim3(256), shm, s, sk, sv, wrec, go, pf, pg, range, gt, nb, R, n, mask, bc, bl, cap); break;
     }
 }
 
@@ -1489,13 +1491,20 @@ hipError_t launch_accumulate(int n, int C, int mode, const float* grad_out, cons
     }
     const int te = (int)plan.tile_elems;
     const uint32_t cell_mask = plan.cell_bits >= 32 ? 0xFFFFFFFFu : ((1u << plan.cell_bits) - 1u);
-    const int64_t groups = (nb + SEG_GROUP - 1) / SEG_GROUP;
+    // the big-bucket lists' capacity (planned for SEG_GROUP) also holds the
+    // lists of groups of 4: ceil(2x) <= 2 ceil(x) runs of half the buckets
+    const int G = pay ? 4 : SEG_GROUP;
+    const int64_t groups = (nb + G - 1) / G;
     const dim3 g1((uint32_t)((groups + 3) / 4));
+    const float* pf = pay ? payf : nullptr;
     prof_begin(K_SEGACC, s);
-    if (mode == MODE_NEAREST)
-        launch_segacc_c<MODE_NEAREST>(C, g1, (size_t)4 * te * 4, s, skeys, svals, wrec, grad_out, pay ? payf : nullptr, payg, range, out, nb, R, n, cell_mask, big_count, big_list, plan.big_cap);
-    else
-        launch_segacc_c<MODE_BILINEAR>(C, g1, (size_t)4 * te * 4, s, skeys, svals, wrec, grad_out, pay ? payf : nullptr, payg, range, out, nb, R, n, cell_mask, big_count, big_list, plan.big_cap);
+    if (mode == MODE_NEAREST) {
+        if (pay) launch_segacc_c<MODE_NEAREST, 4>(C, g1, (size_t)4 * te * 4, s, skeys, svals, wrec, grad_out, pf, payg, range, out, nb, R, n, cell_mask, big_count, big_list, plan.big_cap);
+        else launch_segacc_c<MODE_NEAREST, SEG_GROUP>(C, g1, (size_t)4 * te * 4, s, skeys, svals, wrec, grad_out, pf, payg, range, out, nb, R, n, cell_mask, big_count, big_list, plan.big_cap);
+    } else {
+        if (pay) launch_segacc_c<MODE_BILINEAR, 4>(C, g1, (size_t)4 * te * 4, s, skeys, svals, wrec, grad_out, pf, payg, range, out, nb, R, n, cell_mask, big_count, big_list, plan.big_cap);
+        else launch_segacc_c<MODE_BILINEAR, SEG_GROUP>(C, g1, (size_t)4 * te * 4, s, skeys, svals, wrec, grad_out, pf, payg, range, out, nb, R, n, cell_mask, big_count, big_list, plan.big_cap);
+    }
     prof_end(K_SEGACC, s);
     if (R > 64) {
         // BIG_LISTS x parts workgroups, four wavefronts each; parts grows with
