@@ -15,7 +15,7 @@
 //
 // Chain adjoint: level l+1's bucket is the mean of the 2 x 2 (or 2) buckets of
 // level l it covers, so each of those receives the parent's gradient divided
-// by their number (one thread per element of level l: no two threads write
+// by their number (one workgroup per bucket of level l: no two threads write
 // one element).
 #include <algorithm>
 
