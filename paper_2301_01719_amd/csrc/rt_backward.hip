@@ -111,6 +111,14 @@ __device__ __forceinline__ void bucket_grads(const TexView& t, int64_t b, const 
     lval = f * lv;
 }
 
+// The per-fragment outputs (view and uv gradients, and in nearest mode the
+// sort keys and fractions) are stored non-temporally: they are written once
+// and read back, if at all, by later passes over millions of records.
+__device__ __forceinline__ void nt_store2(float* p, float a, float b) {
+    __builtin_nontemporal_store(a, p);
+    __builtin_nontemporal_store(b, p + 1);
+}
+
 template <int FMT, int C, int MODE>
 __global__ __launch_bounds__(256) void k_bwd_fragment(
     TexView t, const float* __restrict__ uv, const float* __restrict__ tbn,
@@ -134,7 +142,7 @@ __global__ __launch_bounds__(256) void k_bwd_fragment(
             grad_view[f * 3 + 1] = 0.f;
             grad_view[f * 3 + 2] = 0.f;
         }
-        if (grad_uv) ((float2*)grad_uv)[f] = make_float2(0.f, 0.f);
+        if (grad_uv) nt_store2(grad_uv + 2 * f, 0.f, 0.f);
         if (keys) {
             if constexpr (MODE == MODE_NEAREST) keys[f] = sentinel;
             else ((uint4*)keys)[f] = make_uint4(sentinel, sentinel, sentinel, sentinel);
@@ -152,10 +160,10 @@ __global__ __launch_bounds__(256) void k_bwd_fragment(
         int64_t b = (int64_t)j * t.W + i;
         float lv;
         if (grad_view) bucket_grads<FMT, C>(t, b, p, go, gsx, gsy, lv);
-        if (grad_uv) ((float2*)grad_uv)[f] = make_float2(0.f, 0.f);
+        if (grad_uv) nt_store2(grad_uv + 2 * f, 0.f, 0.f);
         if (keys) {
-            keys[f] = ((uint32_t)b << cell_bits) | cell;
-            ((float2*)wrec)[f] = make_float2(p.fx, p.fy);
+            __builtin_nontemporal_store(((uint32_t)b << cell_bits) | cell, keys + f);
+            nt_store2(wrec + 2 * f, p.fx, p.fy);
         }
     } else {
         int i0, i1, j0, j1;
@@ -177,7 +185,7 @@ __global__ __launch_bounds__(256) void k_bwd_fragment(
             if (grad_uv) {
                 float gu = (float)t.W * ((1.f - bb) * (lv[1] - lv[0]) + bb * (lv[3] - lv[2]));
                 float gv = (float)t.H * ((1.f - a) * (lv[2] - lv[0]) + a * (lv[3] - lv[1]));
-                ((float2*)grad_uv)[f] = make_float2(gu, gv);
+                nt_store2(grad_uv + 2 * f, gu, gv);
             }
         }
         if (keys) {
@@ -205,9 +213,9 @@ __global__ __launch_bounds__(256) void k_bwd_fragment(
             guz = coef * (d.uz * t2 + d.L);
         }
         // dL/dV = M^T dL/du
-        grad_view[f * 3 + 0] = g.m[0] * gux + g.m[3] * guy + g.m[6] * guz;
-        grad_view[f * 3 + 1] = g.m[1] * gux + g.m[4] * guy + g.m[7] * guz;
-        grad_view[f * 3 + 2] = g.m[2] * gux + g.m[5] * guy + g.m[8] * guz;
+        __builtin_nontemporal_store(g.m[0] * gux + g.m[3] * guy + g.m[6] * guz, grad_view + f * 3 + 0);
+        __builtin_nontemporal_store(g.m[1] * gux + g.m[4] * guy + g.m[7] * guz, grad_view + f * 3 + 1);
+        __builtin_nontemporal_store(g.m[2] * gux + g.m[5] * guy + g.m[8] * guz, grad_view + f * 3 + 2);
     }
 }
 
