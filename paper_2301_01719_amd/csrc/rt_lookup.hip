@@ -55,15 +55,16 @@ __device__ __forceinline__ void bucket_bilerp(const TexView& t, int64_t b, const
     }
 }
 
+// The lookup's output is written once and not read back by the library: it
+// is stored non-temporally (past the caches the G-buffer and the taps use).
 template <int C>
 __device__ __forceinline__ void store_out(float* __restrict__ out, int64_t f, const float acc[4]) {
     if constexpr (C == 4) {
-        ((float4*)out)[f] = make_float4(acc[0], acc[1], acc[2], acc[3]);
-    } else if constexpr (C == 2) {
-        ((float2*)out)[f] = make_float2(acc[0], acc[1]);
+        const f4v v = {acc[0], acc[1], acc[2], acc[3]};
+        __builtin_nontemporal_store(v, (f4v*)out + f);
     } else {
 #pragma unroll
-        for (int c = 0; c < C; c++) out[f * C + c] = acc[c];
+        for (int c = 0; c < C; c++) __builtin_nontemporal_store(acc[c], out + f * C + c);
     }
 }
 
