@@ -24,12 +24,14 @@
 
 namespace rt {
 
+// Grid-stride zero fill: a level can hold 2^32 elements or more, more than one
+// dispatch may have work-items.
 __global__ __launch_bounds__(256) void k_fill_f32(float* __restrict__ p, int64_t n) {
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i < n) p[i] = 0.f;
+    const int64_t stride = (int64_t)gridDim.x * 256;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) p[i] = 0.f;
 }
 
-static uint32_t blocks_of(int64_t n) { return (uint32_t)((n + 255) / 256); }
+static uint32_t blocks_of(int64_t n) { return (uint32_t)std::min<int64_t>((n + 255) / 256, 65536); }
 
 hipError_t launch_lookup_lod_bwd(const LevelSet& ls, int fmt, int mode, const float* uv,
                                  const float* tbn, const float* view, const float* duv,

@@ -6,6 +6,8 @@
 // with cross-lane max, then every lane encodes its values with the bucket's
 // inverse scale.  Encodes are written from the formats' definitions with
 // integer arithmetic (round to nearest even, E4M3 saturating to +-448).
+#include <algorithm>
+
 #include "rt_device.hpp"
 #include "rt_kernels.hpp"
 
@@ -186,73 +188,104 @@ __global__ __launch_bounds__(256) void k_pack_bits_words(const float* __restrict
     words[g] = w;
 }
 
+// A dispatch holds fewer than 2^32 work-items, so a texture that would need
+// more is quantised in chunks of at most MAX_LAUNCH_BLOCKS workgroups, each a
+// launch over its own slice (cut at a bucket, or for the elementwise kernels at
+// a whole group of float4).  Every workload up to 2^31 FP32 values (BF16) or
+// 2^22 buckets (FP8) is one launch.
+constexpr int64_t MAX_LAUNCH_BLOCKS = int64_t(1) << 20;
+
 hipError_t launch_quantize(const TexView& t, int dst_fmt, void* codes, float* scales,
                            hipStream_t s) {
     const int64_t nb = (int64_t)t.W * t.H;
     const int elems = t.n * t.n * t.C;
+    const float* src = (const float*)t.data;
     if (dst_fmt == FMT_BIT1) {
         prof_begin(K_PACK_BITS, s);
         if (t.n % 8 == 0) {
+            // a chunk is a whole number of words: 8 float4 per word
             constexpr int U = 2;
             const int64_t quads = nb * elems / 4;
-            const uint32_t blocks = (uint32_t)((quads + 256 * U - 1) / (256 * U));
-            hipLaunchKernelGGL(k_pack_bits_flat<U>, dim3(blocks), dim3(256), 0, s,
-                               (const float*)t.data, (uint32_t*)codes, quads);
+            const int64_t chunk = MAX_LAUNCH_BLOCKS * 256 * U;
+            for (int64_t q0 = 0; q0 < quads; q0 += chunk) {
+                const int64_t q = std::min(chunk, quads - q0);
+                hipLaunchKernelGGL(k_pack_bits_flat<U>, dim3((uint32_t)((q + 256 * U - 1) / (256 * U))),
+                                   dim3(256), 0, s, src + q0 * 4, (uint32_t*)codes + q0 / 8, q);
+            }
         } else {
             const int wpb = bit_words(t.n);
-            const int64_t total = nb * wpb;
-            const uint32_t blocks = (uint32_t)((total + 255) / 256);
-            hipLaunchKernelGGL(k_pack_bits_words, dim3(blocks), dim3(256), 0, s,
-                               (const float*)t.data, (uint32_t*)codes, total, elems, wpb);
+            const int64_t chunk_b = MAX_LAUNCH_BLOCKS * 256 / wpb;
+            for (int64_t b0 = 0; b0 < nb; b0 += chunk_b) {
+                const int64_t words = std::min(chunk_b, nb - b0) * wpb;
+                hipLaunchKernelGGL(k_pack_bits_words, dim3((uint32_t)((words + 255) / 256)),
+                                   dim3(256), 0, s, src + b0 * elems,
+                                   (uint32_t*)codes + b0 * wpb, words, elems, wpb);
+            }
         }
         prof_end(K_PACK_BITS, s);
         return hipGetLastError();
     }
     if (dst_fmt == FMT_BF16) {
+        // only the last chunk holds the (total mod 4) tail elements
         const int64_t total = nb * elems;
         const int64_t quads = total / 4;
-        const uint32_t blocks =
-            (uint32_t)((quads + 256 * QB_UNROLL - 1) / (256 * QB_UNROLL)) + (quads == 0 ? 1 : 0);
+        const int64_t chunk = MAX_LAUNCH_BLOCKS * 256 * QB_UNROLL;
         prof_begin(K_QUANT_BF16, s);
-        hipLaunchKernelGGL(k_quant_bf16<QB_UNROLL>, dim3(blocks), dim3(256), 0, s,
-                           (const float*)t.data, (uint16_t*)codes, total);
+        int64_t q0 = 0;
+        do {
+            const int64_t q = std::min(chunk, quads - q0);
+            const bool last = q0 + q == quads;
+            const int64_t count = last ? total - q0 * 4 : q * 4;
+            const uint32_t blocks =
+                (uint32_t)((q + 256 * QB_UNROLL - 1) / (256 * QB_UNROLL)) + (q == 0 ? 1 : 0);
+            hipLaunchKernelGGL(k_quant_bf16<QB_UNROLL>, dim3(blocks), dim3(256), 0, s,
+                               src + q0 * 4, (uint16_t*)codes + q0 * 4, count);
+            q0 += q;
+        } while (q0 < quads);
         prof_end(K_QUANT_BF16, s);
         return hipGetLastError();
     }
-    const uint32_t blocks = (uint32_t)((nb + 3) / 4);
+    const int64_t chunk_b = MAX_LAUNCH_BLOCKS * 4;
     prof_begin(K_QUANT_FP8, s);
-    if (elems % 256 == 0)
-        hipLaunchKernelGGL(k_quant_fp8<true>, dim3(blocks), dim3(256), 0, s,
-                           (const float*)t.data, (uint8_t*)codes, scales, nb, elems);
-    else
-        hipLaunchKernelGGL(k_quant_fp8<false>, dim3(blocks), dim3(256), 0, s,
-                           (const float*)t.data, (uint8_t*)codes, scales, nb, elems);
+    for (int64_t b0 = 0; b0 < nb; b0 += chunk_b) {
+        const int64_t b = std::min(chunk_b, nb - b0);
+        const uint32_t blocks = (uint32_t)((b + 3) / 4);
+        if (elems % 256 == 0)
+            hipLaunchKernelGGL(k_quant_fp8<true>, dim3(blocks), dim3(256), 0, s, src + b0 * elems,
+                               (uint8_t*)codes + b0 * elems, scales + b0, b, elems);
+        else
+            hipLaunchKernelGGL(k_quant_fp8<false>, dim3(blocks), dim3(256), 0, s, src + b0 * elems,
+                               (uint8_t*)codes + b0 * elems, scales + b0, b, elems);
+    }
     prof_end(K_QUANT_FP8, s);
     return hipGetLastError();
 }
 
-// Atlas [H*n][W*n][C] -> bucket-major [H][W][n][n][C]; one lane per texel,
-// elements of `eb` bytes (4, 2 or 1).
+// Atlas [H*n][W*n][C] -> bucket-major [H][W][n][n][C]; a lane per texel
+// (grid-stride), elements of `eb` bytes (4, 2 or 1).
 template <typename E>
 __global__ __launch_bounds__(256) void k_atlas_to_buckets(const E* __restrict__ src,
                                                           E* __restrict__ dst, int W, int H,
                                                           int n, int C) {
-    const int64_t texel = (int64_t)blockIdx.x * 256 + threadIdx.x;
     const int64_t total = (int64_t)W * H * n * n;
-    if (texel >= total) return;
-    const int x = (int)(texel % n);
-    const int y = (int)((texel / n) % n);
-    const int64_t b = texel / ((int64_t)n * n);
-    const int i = (int)(b % W), j = (int)(b / W);
-    const int64_t row = (int64_t)j * n + y, col = (int64_t)i * n + x;
-    const int64_t s = (row * ((int64_t)W * n) + col) * C;
-    for (int c = 0; c < C; c++) dst[texel * C + c] = src[s + c];
+    const int64_t stride = (int64_t)gridDim.x * 256;
+    for (int64_t texel = (int64_t)blockIdx.x * 256 + threadIdx.x; texel < total; texel += stride) {
+        const int x = (int)(texel % n);
+        const int y = (int)((texel / n) % n);
+        const int64_t b = texel / ((int64_t)n * n);
+        const int i = (int)(b % W), j = (int)(b / W);
+        const int64_t row = (int64_t)j * n + y, col = (int64_t)i * n + x;
+        const int64_t s = (row * ((int64_t)W * n) + col) * C;
+        for (int c = 0; c < C; c++) dst[texel * C + c] = src[s + c];
+    }
 }
 
 hipError_t launch_atlas_to_buckets(const void* atlas, void* dst, int W, int H, int n, int C,
                                    int elem_bytes, hipStream_t s) {
+    // grid-stride: a texture can hold 2^32 texels or more, more than one
+    // dispatch may have work-items
     const int64_t total = (int64_t)W * H * n * n;
-    const uint32_t blocks = (uint32_t)((total + 255) / 256);
+    const uint32_t blocks = (uint32_t)std::min<int64_t>((total + 255) / 256, 1 << 20);
     prof_begin(K_ATLAS_RELAYOUT, s);
     if (elem_bytes == 4)
         hipLaunchKernelGGL(k_atlas_to_buckets<uint32_t>, dim3(blocks), dim3(256), 0, s,

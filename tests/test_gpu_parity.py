@@ -238,6 +238,35 @@ def test_e4m3_encode_exhaustive_grid(rt):
     np.testing.assert_array_equal(host(c8).reshape(-1), o8)
 
 
+@pytest.mark.parametrize("fmt", ["f32", "bf16", "fp8"])
+@pytest.mark.parametrize("W,H,n,C", [(16, 8, 8, 4), (7, 5, 3, 3), (5, 9, 16, 1), (1, 1, 1, 2)])
+def test_atlas_layout_looks_up_as_bucket_major(rt, W, H, n, C, fmt):
+    """A texture handed over as an atlas [H n, W n, C] (sample (x, y) of
+    bucket (i, j) at row j n + y, column i n + x) looks up exactly as the
+    bucket-major matrix torch makes from it by a permutation, in both modes."""
+    g = torch.Generator().manual_seed(W * 1000 + H * 100 + n * 10 + C)
+    scales = None
+    if fmt == "fp8":
+        # finite codes only (E4M3 NaN is S.1111.111), random signs
+        atlas = (torch.randint(0, 0x7F, (H * n, W * n, C), generator=g)
+                 | (torch.randint(0, 2, (H * n, W * n, C), generator=g) << 7)).to(torch.uint8)
+        scales = torch.rand((H, W), generator=g).to(DEV)
+    else:
+        atlas = torch.randn((H * n, W * n, C), generator=g)
+        if fmt == "bf16":
+            atlas = atlas.to(torch.bfloat16)
+    bucket = atlas.reshape(H, n, W, n, C).permute(0, 2, 1, 3, 4).contiguous()
+    tex_a = rt.Texture(atlas.to(DEV), W, H, n, C, fmt, scales, layout="atlas")
+    tex_b = rt.Texture(bucket.to(DEV), W, H, n, C, fmt, scales)
+    gb = wl.flat_gbuffer(4096, W + H + n + C, DEV)
+    for mode in ("nearest", "bilinear"):
+        out_a = rt.lookup_fwd(tex_a, gb.uv, gb.tbn, gb.view, mode)
+        out_b = rt.lookup_fwd(tex_b, gb.uv, gb.tbn, gb.view, mode)
+        _sync()
+        assert torch.isfinite(out_b).all()
+        assert torch.equal(out_a, out_b), mode
+
+
 @pytest.mark.parametrize("fmt", ["bf16", "fp8"])
 @pytest.mark.parametrize("mode", ["nearest", "bilinear"])
 def test_quantized_forward(rt, fmt, mode):
