@@ -622,9 +622,10 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_scatter(
 // 3. bucket ranges in the sorted records
 // ---------------------------------------------------------------------------
 
+// Grid-stride fill (the bucket ranges of 2^31 buckets are 2^32 words).
 __global__ __launch_bounds__(256) void k_fill_u32(uint32_t* __restrict__ p, int64_t n, uint32_t v) {
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i < n) p[i] = v;
+    const int64_t stride = (int64_t)gridDim.x * 256;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) p[i] = v;
 }
 
 // Four sorted keys per thread (one 16-byte load; the key buffer is padded to
@@ -1369,7 +1370,8 @@ static void launch_payload_c(int C, dim3 grid, hipStream_t s, const uint32_t* sk
 static void launch_fill(uint32_t* p, int64_t n, uint32_t v, hipStream_t s) {
     if (n <= 0) return;
     prof_begin(K_FILL, s);
-    hipLaunchKernelGGL(k_fill_u32, dim3((uint32_t)((n + 255) / 256)), dim3(256), 0, s, p, n, v);
+    const uint32_t blocks = (uint32_t)std::min<int64_t>((n + 255) / 256, int64_t(1) << 20);
+    hipLaunchKernelGGL(k_fill_u32, dim3(blocks), dim3(256), 0, s, p, n, v);
     prof_end(K_FILL, s);
 }
 
@@ -1503,7 +1505,9 @@ hipError_t launch_accumulate(int n, int C, int mode, const float* grad_out, cons
     // lists of groups of 4: ceil(2x) <= 2 ceil(x) runs of half the buckets
     const int G = pay ? 4 : SEG_GROUP;
     const int64_t groups = (nb + G - 1) / G;
-    const dim3 g1((uint32_t)((groups + 3) / 4));
+    // the workgroups stride over the groups, so at most 2^20 of them keep the
+    // launch within one dispatch (2^28 buckets and more at small n)
+    const dim3 g1((uint32_t)std::min<int64_t>((groups + 3) / 4, int64_t(1) << 20));
     const float* pf = pay ? payf : nullptr;
     prof_begin(K_SEGACC, s);
     if (mode == MODE_NEAREST) {

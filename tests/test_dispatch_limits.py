@@ -4,19 +4,21 @@ A dispatch holds fewer than 2^32 work-items, so the library splits or strides
 the elementwise launches that would need more: the quantisers (BF16 and the
 1-bit packer past 2^31 values, FP8 past 2^22 buckets, the 1-bit packer of
 other n past 2^28 words), the atlas re-layout (2^32 texels and more) and the
-zero fill of the level-of-detail backward (a level of 2^32 values).  Each test
+zero fill of the level-of-detail backward (a level of 2^32 values), and the
+backward's accumulation over groups of buckets (2^28 buckets).  Each test
 takes a texture just past the limit, with a ragged end where the format
 allows one, and checks the outputs at every cut, at both ends and on a random
 sample: the quantisers against the oracle's quantiser on the sampled buckets
 (a bucket's codes depend on that bucket's values alone), the re-layout
-through lookups against torch's own permutation of the atlas.
+through lookups against torch's own permutation of the atlas, the backward
+against the oracle's on the bucket window its fragments reach.
 """
 import numpy as np
 import pytest
 import torch
 
 import oracle
-from helpers import host
+from helpers import EDGE, check_grad_tex, host
 from paper_2301_01719_amd import workloads as wl
 
 pytestmark = [pytest.mark.gpu, pytest.mark.slow]
@@ -176,3 +178,36 @@ def test_lod_backward_without_fragments_fills_a_level_of_2_32_values(rt):
     assert all(g is None for g in grads[1:-1])
     for t in chain:
         t.close()
+
+
+def test_backward_over_2_28_buckets(rt):
+    """16384 x 16384 buckets of 2 x 2 one-channel samples: the accumulation's
+    groups of 4 buckets would need 2^32 work-items in one dispatch.  The
+    fragments fall in the last 64 x 64 buckets (the last groups); the dense
+    gradient there matches the oracle's, and every other element of a
+    gradient buffer filled with ones beforehand is overwritten with zero."""
+    W = H = 16384
+    n, C = 2, 1
+    N = 1 << 16
+    b0 = W - 64
+    gb = wl.flat_gbuffer(N, 12, DEV)
+    uv = ((b0 + 0.5 + 63 * gb.uv) / W).contiguous()
+    g = torch.Generator(device=DEV).manual_seed(13)
+    texels = torch.rand((H, W, n, n, C), generator=g, device=DEV)
+    tex = rt.Texture(texels, W, H, n, C)
+    go = torch.randn((N, C), generator=g, device=DEV)
+    uvh, tbnh, viewh = host(uv), host(gb.tbn), host(gb.view)
+    _, _, edge = oracle.indices(uvh, tbnh, viewh, W, H, n)
+    near = ~((edge[:, 0] >= EDGE) & (edge[:, 1] >= EDGE))
+    go[torch.from_numpy(np.nonzero(near)[0]).to(DEV)] = 0.0
+    gt = torch.ones((H, W, n, n, C), device=DEV)
+    gt, _, _ = rt.lookup_bwd(tex, uv, gb.tbn, gb.view, go, "nearest", want_view=False,
+                             want_uv=False, grad_tex=gt)
+    torch.cuda.synchronize()
+    win = host(gt[b0:, b0:])
+    ref = oracle.lookup_bwd(oracle.Tex(np.zeros(W * H * n * n * C, np.float32), W, H, n, C),
+                            uvh, tbnh, viewh, host(go), oracle.MODE_NEAREST,
+                            window=(b0, b0, 64, 64), want_view=False, want_uv=False)
+    check_grad_tex(win, ref, n)
+    assert int(torch.count_nonzero(gt)) == int(np.count_nonzero(win))
+    tex.close()
