@@ -44,6 +44,7 @@ constexpr int SORT_THREADS = 256;
 constexpr int SORT_IPT = 16;
 constexpr int SORT_TILE = SORT_THREADS * SORT_IPT;  // 4096
 constexpr int SCAN_TILE = 4096;
+constexpr int64_t SCAN_FUSED_BLOCKS = 4096;
 
 // orders one wavefront's LDS accesses before and after it
 __device__ __forceinline__ void wave_sync_lds() {
@@ -425,7 +426,9 @@ __device__ __forceinline__ uint32_t block_exclusive(uint32_t v, uint32_t* wsum, 
 }
 
 // device-wide exclusive scan: per-block sums, a one-block scan of the sums,
-// then per-block scans offset by the scanned sums.  Each thread owns 16
+// then per-block scans offset by the scanned sums; up to SCAN_FUSED_BLOCKS
+// blocks (every sort of up to 2^27 records) the per-block scans add up the sums
+// before them themselves, one launch fewer.  Each thread owns 16
 // consecutive counts, read (and written) as four 16-byte vectors when all 16
 // lie inside the array and the pointers are 16-byte aligned.
 __device__ __forceinline__ void load16(const uint32_t* __restrict__ in, int64_t base, int64_t L,
@@ -481,17 +484,29 @@ __global__ __launch_bounds__(256) void k_scan_top(uint32_t* __restrict__ part, i
     }
 }
 
+// SCANNED: part holds the scanned block sums (k_scan_top ran); otherwise it
+// holds the plain sums and the block adds up those of the blocks before it
+// (at most SCAN_FUSED_BLOCKS of them, so at most 16 loads per thread).
+template <bool SCANNED>
 __global__ __launch_bounds__(256) void k_scan_down(const uint32_t* __restrict__ in, int64_t L,
                                                    const uint32_t* __restrict__ part,
                                                    uint32_t* __restrict__ out) {
     __shared__ uint32_t wsum[4];
+    uint32_t offset;
+    if constexpr (SCANNED) {
+        offset = part[blockIdx.x];
+    } else {
+        uint32_t ps = 0;
+        for (uint32_t j = threadIdx.x; j < blockIdx.x; j += 256) ps += part[j];
+        block_exclusive(ps, wsum, &offset);
+    }
     const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + threadIdx.x * 16;
     const bool vec = (((uintptr_t)in | (uintptr_t)out) & 15) == 0;
     uint32_t v[16], s = 0;
     load16(in, base, L, vec, v);
 #pragma unroll
     for (int k = 0; k < 16; k++) s += v[k];
-    uint32_t run = part[blockIdx.x] + block_exclusive(s, wsum, nullptr);
+    uint32_t run = offset + block_exclusive(s, wsum, nullptr);
     uint32_t o[16];
 #pragma unroll
     for (int k = 0; k < 16; k++) {
@@ -1379,8 +1394,14 @@ static void launch_scan(const uint32_t* in, uint32_t* out, uint32_t* part, int64
                         int64_t blocks, hipStream_t s) {
     prof_begin(K_SCAN, s);
     hipLaunchKernelGGL(k_scan_reduce, dim3((uint32_t)blocks), dim3(256), 0, s, in, L, part);
-    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(256), 0, s, part, blocks);
-    hipLaunchKernelGGL(k_scan_down, dim3((uint32_t)blocks), dim3(256), 0, s, in, L, part, out);
+    if (blocks <= SCAN_FUSED_BLOCKS) {
+        hipLaunchKernelGGL(k_scan_down<false>, dim3((uint32_t)blocks), dim3(256), 0, s, in, L,
+                           part, out);
+    } else {
+        hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(256), 0, s, part, blocks);
+        hipLaunchKernelGGL(k_scan_down<true>, dim3((uint32_t)blocks), dim3(256), 0, s, in, L,
+                           part, out);
+    }
     prof_end(K_SCAN, s);
 }
 

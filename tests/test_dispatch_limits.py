@@ -211,3 +211,46 @@ def test_backward_over_2_28_buckets(rt):
     check_grad_tex(win, ref, n)
     assert int(torch.count_nonzero(gt)) == int(np.count_nonzero(win))
     tex.close()
+
+
+def test_backward_sort_past_2_27_records(rt):
+    """A bilinear backward of 35.65M fragments (142.6M records) over 1024 x
+    1024 buckets of 8 x 8 RGB.  Its 26-bit keys sort in passes of 9, 9 and 8
+    bits; the 9-bit passes' histograms hold 512 x 34.8k counts, more block sums
+    (4352) than a down-sweep workgroup adds up itself, so their scan takes the
+    one-block pass over the sums, and the 8-bit pass (2176 sums) does not.  The
+    dense gradient on a 32 x 32 bucket window matches the oracle's (from the
+    fragments within one bucket of the window), and the whole gradient sums to
+    the upstream gradient's sum (a fragment's bilinear weights sum to 1)."""
+    from helpers import away_from_edges
+    W = H = 1024
+    n, C = 8, 3
+    N = 34 * 1024 * 1024
+    assert 4 * N > 2**27
+    gb = wl.flat_gbuffer(N, 21, DEV)
+    g = torch.Generator(device=DEV).manual_seed(22)
+    texels = torch.rand((H, W, n, n, C), generator=g, device=DEV)
+    tex = rt.Texture(texels, W, H, n, C)
+    go = torch.randn((N, C), generator=g, device=DEV)
+    bi0, bj0, bw, bh = win = (500, 700, 32, 32)
+    idx, _ = rt.debug_indices(tex, gb.uv, gb.tbn, gb.view)
+    m = ((idx[:, 0] >= bi0 - 1) & (idx[:, 0] <= bi0 + bw) & (idx[:, 1] >= bj0 - 1)
+         & (idx[:, 1] <= bj0 + bh))
+    near = torch.nonzero(m).flatten()
+    del idx, m
+    uvw, tbnw, vw = host(gb.uv[near]), host(gb.tbn[near]), host(gb.view[near])
+    keep = away_from_edges(uvw, tbnw, vw, W, H, n, "bilinear")
+    go[near[torch.from_numpy(~keep).to(DEV)]] = 0.0
+    gt, _, _ = rt.lookup_bwd(tex, gb.uv, gb.tbn, gb.view, go, "bilinear", want_view=False,
+                             want_uv=False)
+    torch.cuda.synchronize()
+    ref = oracle.lookup_bwd(oracle.Tex(host(texels), W, H, n, C), uvw, tbnw, vw,
+                            host(go[near]), oracle.MODE_BILINEAR, window=win,
+                            want_view=False, want_uv=False)
+    assert np.count_nonzero(ref["absg_tex"]) > 1000
+    check_grad_tex(host(gt[bj0:bj0 + bh, bi0:bi0 + bw]), ref, n)
+    mass = float(torch.sum(gt, dtype=torch.float64))
+    want = float(torch.sum(go, dim=0, dtype=torch.float64).sum())
+    scale = float(torch.sum(go.abs(), dtype=torch.float64))
+    assert abs(mass - want) <= 1e-5 * scale, (mass, want, scale)
+    tex.close()
