@@ -48,6 +48,9 @@ def _load():
     lib.orc_texel_coord.argtypes = [P, i32, P]
     lib.orc_lookup_fwd.argtypes = [i64, P, P, P, i32, i32, i32, i32, i32, P, P, i32, P]
     lib.orc_lookup_one_f64.argtypes = [P, P, P, i32, i32, i32, i32, i32, P, P, i32, P]
+    lib.orc_lookup_fwd_f64.argtypes = [i64, P, P, P, i32, i32, i32, i32, i32, P, P, i32, P]
+    lib.orc_lookup_bwd_round.argtypes = [i64, P, P, P, P, i32, i32, i32, i32, i32, P, P, i32, d,
+                                         d, P, P]
     lib.orc_indices.argtypes = [i64, P, P, P, i32, i32, i32, P, P, P]
     lib.orc_map_one.argtypes = [P, P, i32, P]
     lib.orc_lookup_bwd.argtypes = [i64, P, P, P, P, i32, i32, i32, i32, i32, P, P, i32,
@@ -230,6 +233,19 @@ def lookup_one_f64(tex: Tex, U, M, V, mode=MODE_NEAREST):
     return out
 
 
+def lookup_fwd_f64(tex: Tex, U, M, V, mode=MODE_NEAREST):
+    """Forward lookup of N fragments whose u,v [N,2], frames [N,3,3] and view
+    vectors [N,3] are binary64 (finite differences); out [N,C] float64."""
+    U = _c(U, np.float64).reshape(-1, 2)
+    M = _c(M, np.float64).reshape(-1, 9)
+    V = _c(V, np.float64).reshape(-1, 3)
+    N = U.shape[0]
+    assert M.shape[0] == N and V.shape[0] == N
+    out = np.empty((N, tex.C), np.float64)
+    _load().orc_lookup_fwd_f64(N, _p(U), _p(M), _p(V), *tex.args(), int(mode), _p(out))
+    return out
+
+
 def indices(uv, tbn, view, W, H, n):
     """Returns idx [N,4] int32 (i, j, x0, y0), frac [N,2] and edge [N,3]:
     distances to the nearest bucket edge, sample edge (clamp bounds included)
@@ -277,6 +293,24 @@ def lookup_bwd(tex: Tex, uv, tbn, view, g, mode=MODE_NEAREST, want_tex=True, win
                            _p(su))
     return {"grad_tex": gt, "abs_tex": at, "absg_tex": ag, "grad_view": gv, "grad_uv": gu,
             "scale_view": sv, "scale_uv": su}
+
+
+def lookup_bwd_round(tex: Tex, uv, tbn, view, g, delta_s, delta_w=0.0, mode=MODE_NEAREST):
+    """Per fragment, how far the exact view and uv gradients move when the
+    sample coordinate s moves by +-delta_s along each axis and (bilinear-bucket
+    mode) the bucket fractions a, b by +-delta_w, everything else held: the
+    largest 2-norm change over the sign patterns.  This is the part of a
+    binary32 gradient's error that the rounding of those quantities alone
+    causes.  Returns (round_view [N], round_uv [N]) float64."""
+    uv, tbn, view = _frags(uv, tbn, view)
+    g = _c(g, np.float32).reshape(-1, tex.C)
+    N = uv.shape[0]
+    assert g.shape[0] == N
+    rv = np.empty(N, np.float64)
+    ru = np.empty(N, np.float64)
+    _load().orc_lookup_bwd_round(N, _p(uv), _p(tbn), _p(view), _p(g), *tex.args(), int(mode),
+                                 float(delta_s), float(delta_w), _p(rv), _p(ru))
+    return rv, ru
 
 
 # --- the bake ----------------------------------------------------------------

@@ -143,8 +143,10 @@ uint16_t orc_f32_to_bf16_rne(float x)
 /* Round-to-nearest-even to E4M3 with saturation to +-448 ("satfinite"),
  * written from the definition: the non-negative finite codes 0x00..0x7E are
  * in increasing order of value, the nearest one to |y| is chosen, ties go to
- * the even code, values above 448 (and infinities) become 448, NaN stays NaN. */
-uint8_t orc_f32_to_e4m3_sat(float y)
+ * the even code, values above 448 (and infinities) become 448, NaN stays NaN.
+ * tab[k] holds the value of code k (0 <= k <= 0x7E); the code just below |y|
+ * is found by bisection over that ordered list. */
+static uint8_t e4m3_encode_sat(float y, const double *tab)
 {
     if (isnan(y))
         return (uint8_t)(signbit(y) ? 0xFF : 0x7F);
@@ -154,15 +156,20 @@ uint8_t orc_f32_to_e4m3_sat(float y)
     if (a >= 448.0) {
         best = 0x7E;
     } else {
-        /* find k with v(k) <= a < v(k+1) by scanning the ordered code list */
-        int k = 0;
-        while (k < 0x7E && orc_e4m3_to_f64((uint8_t)(k + 1)) <= a)
-            k++;
+        /* the largest k with v(k) <= a (v(0) = 0 <= a) */
+        int lo = 0, hi = 0x7E;
+        while (lo < hi) {
+            int mid = (lo + hi + 1) / 2;
+            if (tab[mid] <= a)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+        int k = lo;
         if (k == 0x7E) {
             best = 0x7E;
         } else {
-            double vl = orc_e4m3_to_f64((uint8_t)k);
-            double vh = orc_e4m3_to_f64((uint8_t)(k + 1));
+            double vl = tab[k], vh = tab[k + 1];
             double dl = a - vl, dh = vh - a;
             if (dl < dh)
                 best = k;
@@ -173,6 +180,19 @@ uint8_t orc_f32_to_e4m3_sat(float y)
         }
     }
     return (uint8_t)((neg << 7) | best);
+}
+
+static void e4m3_table(double tab[0x7F])
+{
+    for (int k = 0; k <= 0x7E; k++)
+        tab[k] = orc_e4m3_to_f64((uint8_t)k);
+}
+
+uint8_t orc_f32_to_e4m3_sat(float y)
+{
+    double tab[0x7F];
+    e4m3_table(tab);
+    return e4m3_encode_sat(y, tab);
 }
 
 /* Per-bucket quantiser.  Texture is bucket-major [H][W][n][n][C] float32.
@@ -195,6 +215,8 @@ void orc_quantize(const float *tex, int64_t n_buckets, int64_t bucket_elems, int
         return;
     }
     uint8_t *out = (uint8_t *)codes;
+    double tab[0x7F];
+    e4m3_table(tab);
 #pragma omp parallel for schedule(static)
     for (int64_t b = 0; b < n_buckets; b++) {
         const float *src = tex + b * bucket_elems;
@@ -214,7 +236,7 @@ void orc_quantize(const float *tex, int64_t n_buckets, int64_t bucket_elems, int
         }
         for (int64_t e = 0; e < bucket_elems; e++) {
             volatile float y = src[e] * inv;
-            out[b * bucket_elems + e] = orc_f32_to_e4m3_sat(y);
+            out[b * bucket_elems + e] = e4m3_encode_sat(y, tab);
         }
         scales[b] = scale;
     }
@@ -588,6 +610,19 @@ void orc_lookup_one_f64(const double U[2], const double M[9], const double V[3],
     lookup_one(&t, U, M, V, mode, out);
 }
 
+/* Forward lookup of N fragments given in binary64 (finite differences over
+ * many fragments at once): the same lookup as orc_lookup_one_f64 per
+ * fragment, U [N][2], M [N][9], V [N][3], out [N][C]. */
+void orc_lookup_fwd_f64(int64_t N, const double *U, const double *M, const double *V, int W,
+                        int H, int n, int C, int fmt, const void *data, const float *scales,
+                        int mode, double *out)
+{
+    tex_t t = {W, H, n, C, fmt, data, scales};
+#pragma omp parallel for schedule(static)
+    for (int64_t f = 0; f < N; f++)
+        lookup_one(&t, U + 2 * f, M + 9 * f, V + 3 * f, mode, out + f * C);
+}
+
 /* Per-fragment indices of the nearest-bucket lookup, for bit-exact checks:
  * idx[f] = (i, j, x0, y0), frac[f] = (fx, fy), and the distances of the
  * unrounded quantities to the points where a result changes discontinuously
@@ -724,6 +759,48 @@ static void view_gradient(const double M[9], const dirmap_t *d, int n, const dou
         gV[m] = Mx[0 * 3 + m] * gu[0] + Mx[1 * 3 + m] * gu[1] + Mx[2 * 3 + m] * gu[2];
 }
 
+/* dL/ds of one fragment (per axis, summed over the buckets of its footprint
+ * with their weights) and, per footprint bucket, sum_c g_c times the bucket's
+ * bilinear value, at the in-bucket fractions of d (gf: the upstream gradient
+ * in binary64). */
+static void footprint_slopes(const tex_t *t, const bucketfp_t *bf, const dirmap_t *d,
+                             const double gf[4], double gs[2], double Lb[4])
+{
+    gs[0] = gs[1] = 0.0;
+    Lb[0] = Lb[1] = Lb[2] = Lb[3] = 0.0;
+    for (int k = 0; k < bf->count; k++) {
+        int i = bf->i[k], j = bf->j[k];
+        for (int c = 0; c < t->C; c++) {
+            double T00 = texel(t, i, j, d->y0, d->x0, c);
+            double T01 = texel(t, i, j, d->y0, d->x1, c);
+            double T10 = texel(t, i, j, d->y1, d->x0, c);
+            double T11 = texel(t, i, j, d->y1, d->x1, c);
+            double dsx = (1.0 - d->fy) * (T01 - T00) + d->fy * (T11 - T10);
+            double dsy = (1.0 - d->fx) * (T10 - T00) + d->fx * (T11 - T01);
+            gs[0] += bf->w[k] * gf[c] * dsx;
+            gs[1] += bf->w[k] * gf[c] * dsy;
+            Lb[k] += gf[c] * bilerp(t, i, j, d, c);
+        }
+    }
+}
+
+/* dL/d(u, v) of one fragment from its buckets' values Lb: zero in nearest
+ * mode (piecewise constant in u, v) and for non-finite coordinates; in the
+ * bilinear-bucket mode the derivative of sum_k w_k(a, b) L_k with
+ * a = frac(u) W - 1/2, b = frac(v) H - 1/2. */
+static void uv_gradient(const bucketfp_t *bf, const double Lb[4], const double U[2], int W,
+                        int H, int mode, double guv[2])
+{
+    if (mode == ORC_MODE_NEAREST || !isfinite(U[0] - floor(U[0])) ||
+        !isfinite(U[1] - floor(U[1]))) {
+        guv[0] = guv[1] = 0.0;
+        return;
+    }
+    double a = bf->a, b = bf->b;
+    guv[0] = W * ((1.0 - b) * (Lb[1] - Lb[0]) + b * (Lb[3] - Lb[2]));
+    guv[1] = H * ((1.0 - a) * (Lb[2] - Lb[0]) + a * (Lb[3] - Lb[1]));
+}
+
 /* Backward of N fragments with upstream gradient g[N][C] (binary32).
  *   grad_tex   dL/d(texel) accumulated in fragment order, binary64, over the
  *              bucket window [bi0, bi0+bw) x [bj0, bj0+bh) only (laid out
@@ -763,9 +840,10 @@ static void lookup_bwd_core(int64_t N, const float *uv, const float *tbn, const 
             double gf[4];
             for (int c = 0; c < C; c++)
                 gf[c] = (wf ? wf[f] : 1.0) * (double)g[f * C + c];
-            double gs[2] = {0.0, 0.0}, gsa[2] = {0.0, 0.0};
-            double Lb[4] = {0, 0, 0, 0}; /* sum_c g_c * bilerp per footprint bucket */
+            double gs[2], gsa[2] = {0.0, 0.0};
+            double Lb[4]; /* sum_c g_c * bilerp per footprint bucket */
             double La[4] = {0, 0, 0, 0}; /* the same with magnitudes */
+            footprint_slopes(&t, &bf, &d, gf, gs, Lb);
             for (int k = 0; k < bf.count; k++) {
                 int i = bf.i[k], j = bf.j[k];
                 for (int c = 0; c < C; c++) {
@@ -773,11 +851,6 @@ static void lookup_bwd_core(int64_t N, const float *uv, const float *tbn, const 
                     double T01 = texel(&t, i, j, d.y0, d.x1, c);
                     double T10 = texel(&t, i, j, d.y1, d.x0, c);
                     double T11 = texel(&t, i, j, d.y1, d.x1, c);
-                    double dsx = (1.0 - d.fy) * (T01 - T00) + d.fy * (T11 - T10);
-                    double dsy = (1.0 - d.fx) * (T10 - T00) + d.fx * (T11 - T01);
-                    gs[0] += bf.w[k] * gf[c] * dsx;
-                    gs[1] += bf.w[k] * gf[c] * dsy;
-                    Lb[k] += gf[c] * bilerp(&t, i, j, &d, c);
                     double ag = fabs(bf.w[k] * gf[c]);
                     gsa[0] += ag * ((1.0 - d.fy) * fabs(T01 - T00) + d.fy * fabs(T11 - T10));
                     gsa[1] += ag * ((1.0 - d.fx) * fabs(T10 - T00) + d.fx * fabs(T11 - T01));
@@ -799,19 +872,8 @@ static void lookup_bwd_core(int64_t N, const float *uv, const float *tbn, const 
                     scale_uv[2 * f + 1] = H * ((1.0 - a) * (La[2] + La[0]) + a * (La[3] + La[1]));
                 }
             }
-            if (grad_uv) {
-                if (mode == ORC_MODE_NEAREST || !isfinite(U[0] - floor(U[0])) ||
-                    !isfinite(U[1] - floor(U[1]))) {
-                    grad_uv[2 * f] = grad_uv[2 * f + 1] = 0.0;
-                } else {
-                    /* d/du of sum_k w_k(a,b) L_k with a = frac(u) W - 1/2 */
-                    double a = bf.a, b = bf.b;
-                    grad_uv[2 * f + 0] =
-                        W * ((1.0 - b) * (Lb[1] - Lb[0]) + b * (Lb[3] - Lb[2]));
-                    grad_uv[2 * f + 1] =
-                        H * ((1.0 - a) * (Lb[2] - Lb[0]) + a * (Lb[3] - Lb[1]));
-                }
-            }
+            if (grad_uv)
+                uv_gradient(&bf, Lb, U, W, H, mode, grad_uv + 2 * f);
         }
     }
     if (grad_tex) {
@@ -865,6 +927,76 @@ void orc_lookup_bwd(int64_t N, const float *uv, const float *tbn, const float *v
     tex_t t = {W, H, n, C, fmt, data, scales};
     lookup_bwd_core(N, uv, tbn, view, g, NULL, &t, mode, grad_tex, abs_tex, absg_tex, bi0, bj0,
                     bw, bh, grad_view, grad_uv, scale_view, scale_uv);
+}
+
+/* How far the view and uv gradients of each fragment move under the rounding
+ * that a binary32 evaluation cannot avoid in the quantities its taps are
+ * weighted with: the sample coordinate s (the texel coordinate of the clamp
+ * Note after Eq. (3)), held to within delta_s, and, in the bilinear-bucket
+ * mode, the bucket fractions a, b, held to within delta_w.  The result is the
+ * largest |grad(moved) - grad|_2 over the sign patterns of the moves (fx +-
+ * delta_s, fy +- delta_s, and a +- delta_w, b +- delta_w), every other factor
+ * of the chain held at the fragment's own values.  The moved in-bucket
+ * fractions stay on the same taps (the cell's bilinear patch extended past
+ * it) and the clamp decisions are those of s.  round_view [N], round_uv [N]
+ * (either may be NULL; round_uv is 0 in nearest mode). */
+void orc_lookup_bwd_round(int64_t N, const float *uv, const float *tbn, const float *view,
+                          const float *g, int W, int H, int n, int C, int fmt, const void *data,
+                          const float *scales, int mode, double delta_s, double delta_w,
+                          double *round_view, double *round_uv)
+{
+    tex_t t = {W, H, n, C, fmt, data, scales};
+    const int nw = mode == ORC_MODE_NEAREST ? 1 : 4; /* sign patterns of (a, b) */
+#pragma omp parallel for schedule(static)
+    for (int64_t f = 0; f < N; f++) {
+        double U[2], M[9], V[3];
+        widen_fragment(uv, tbn, view, f, U, M, V);
+        dirmap_t d;
+        bucketfp_t bf;
+        map_direction(M, V, n, &d);
+        bucket_footprint(U[0], U[1], W, H, mode, &bf);
+        double gf[4];
+        for (int c = 0; c < C; c++)
+            gf[c] = (double)g[f * C + c];
+        double gs[2], Lb[4], gV[3], guv[2];
+        footprint_slopes(&t, &bf, &d, gf, gs, Lb);
+        view_gradient(M, &d, n, gs, 0, gV);
+        uv_gradient(&bf, Lb, U, W, H, mode, guv);
+        double rv = 0.0, ru = 0.0;
+        for (int q = 0; q < 4 * nw; q++) {
+            const int sx = (q & 1) ? 1 : -1, sy = (q & 2) ? 1 : -1;
+            const int sa = (q & 4) ? 1 : -1, sb = (q & 8) ? 1 : -1;
+            dirmap_t e = d;
+            e.fx = d.fx + sx * delta_s;
+            e.fy = d.fy + sy * delta_s;
+            bucketfp_t bm = bf;
+            if (mode != ORC_MODE_NEAREST) {
+                bm.a = bf.a + sa * delta_w;
+                bm.b = bf.b + sb * delta_w;
+                bm.w[0] = (1.0 - bm.a) * (1.0 - bm.b);
+                bm.w[1] = bm.a * (1.0 - bm.b);
+                bm.w[2] = (1.0 - bm.a) * bm.b;
+                bm.w[3] = bm.a * bm.b;
+            }
+            double gs2[2], Lb2[4], gV2[3], guv2[2];
+            footprint_slopes(&t, &bm, &e, gf, gs2, Lb2);
+            view_gradient(M, &e, n, gs2, 0, gV2);
+            uv_gradient(&bm, Lb2, U, W, H, mode, guv2);
+            double dv = sqrt((gV2[0] - gV[0]) * (gV2[0] - gV[0]) +
+                             (gV2[1] - gV[1]) * (gV2[1] - gV[1]) +
+                             (gV2[2] - gV[2]) * (gV2[2] - gV[2]));
+            double du = sqrt((guv2[0] - guv[0]) * (guv2[0] - guv[0]) +
+                             (guv2[1] - guv[1]) * (guv2[1] - guv[1]));
+            if (dv > rv)
+                rv = dv;
+            if (du > ru)
+                ru = du;
+        }
+        if (round_view)
+            round_view[f] = rv;
+        if (round_uv)
+            round_uv[f] = ru;
+    }
 }
 
 /* ------------------------------------------------------------------------- */

@@ -93,13 +93,46 @@ def check_grad_tex(G_gpu, ref, n, rel=BWD_REL):
     return float(ratio.max()) if ratio.size else 0.0
 
 
-def check_grad_vec(g_gpu, g_o, scale, rel=BWD_REL):
-    """Per fragment |dg|_2 <= rel * |scale|_2, where scale is the oracle's chain
-    rule evaluated with the magnitude of every factor (the quantity a binary32
-    evaluation's rounding error is proportional to); where the scale is 0 the
-    gradient must be exactly 0.  Returns (max error / bound, max plain relative
-    error over fragments whose gradient is not tiny)."""
-    d = np.linalg.norm(g_gpu.astype(np.float64) - g_o, axis=1)
+# The binary32 sample coordinate s lies in [0, n-1] and is formed by a few
+# roundings of relative size 2^-24 of quantities up to n; ROUND_S(n) bounds
+# how far it can sit from the exact one (checked against the oracle's
+# fractions by the GPU tests), and the oracle's lookup_bwd_round gives how far
+# the exact gradient moves when s moves that much.
+def round_s(n: int) -> float:
+    return 2.0 ** -21 * max(n, 1)
+
+
+def round_w(W: int, H: int, uv) -> float:
+    """Bound on the rounding of the bilinear-bucket fractions a = frac(u) W -
+    1/2 in binary32: t = u W is exact for a power-of-two W and the split into
+    floor and fraction is exact, leaving one rounding of r + 1/2 (2^-25);
+    otherwise u W itself rounds, by up to 2^-24 |u W|."""
+    pow2 = lambda x: x > 0 and (x & (x - 1)) == 0
+    if pow2(W) and pow2(H):
+        return 2.0 ** -24
+    u = np.abs(np.asarray(uv, np.float64))
+    m = max(1.0, W * float(u[:, 0].max()) if u.size else 0.0,
+            H * float(u[:, 1].max()) if u.size else 0.0)
+    return 2.0 ** -23 * m
+
+
+def check_grad_vec(g_gpu, g_o, scale, go=None, rnd=None, rel=BWD_REL, absolute=1e-6):
+    """Two bounds per fragment, both enforced:
+
+    * |dg|_2 <= rel * |S|_2, S the oracle's chain rule evaluated with the
+      magnitude of every factor (the scale of a binary32 evaluation's
+      rounding); where S is 0 the gradient must be exactly 0;
+    * with the upstream gradient go given: |dg|_2 <= rel * |g*|_2 +
+      absolute * sum_c |go_c| + rnd, where rnd (default 0) is the oracle's
+      change of the gradient under the rounding of the sample coordinate
+      (lookup_bwd_round with round_s(n)).
+
+    Returns a dict: the worst error / bound of each, the number of fragments
+    that exceed rel |g*| + absolute sum |go| alone (those the rounding term
+    admits), and the largest plain relative error over fragments whose
+    gradient is not tiny."""
+    g_gpu = g_gpu.astype(np.float64)
+    d = np.linalg.norm(g_gpu - g_o, axis=1)
     sc = np.linalg.norm(scale, axis=1)
     zero = sc == 0
     assert np.all(d[zero] == 0.0), "non-zero gradient where the oracle's scale is 0"
@@ -108,6 +141,14 @@ def check_grad_vec(g_gpu, g_o, scale, rel=BWD_REL):
     assert bad.size == 0, (bad[:5], d[bad[:5]], bound[bad[:5]], g_gpu[bad[:5]], g_o[bad[:5]])
     gn = np.linalg.norm(g_o, axis=1)
     big = gn > 1e-3 * (gn.max() if gn.size else 0)
-    plain = float(np.max(d[big] / gn[big])) if np.any(big) else 0.0
-    worst = float(np.max(d[~zero] / bound[~zero])) if np.any(~zero) else 0.0
-    return worst, plain
+    res = {"magnitude": float(np.max(d[~zero] / bound[~zero])) if np.any(~zero) else 0.0,
+           "plain_rel": float(np.max(d[big] / gn[big])) if np.any(big) else 0.0,
+           "survey": None, "needs_rounding_term": 0}
+    if go is not None:
+        base = rel * gn + absolute * np.abs(go.astype(np.float64)).sum(1)
+        res["needs_rounding_term"] = int(np.sum(d > base))
+        b2 = base + (0.0 if rnd is None else rnd)
+        bad = np.nonzero(d > b2)[0]
+        assert bad.size == 0, ("survey bound", bad[:5], d[bad[:5]], b2[bad[:5]], gn[bad[:5]])
+        res["survey"] = float(np.max(d / np.maximum(b2, 1e-300))) if d.size else 0.0
+    return res

@@ -15,7 +15,7 @@ import torch
 
 import oracle
 from helpers import (EDGE, away_from_edges, bucket_edge_mask, check_fwd, check_grad_tex,
-                     check_grad_vec, check_indices, gb_host, host)
+                     check_grad_vec, check_indices, gb_host, host, round_s, round_w)
 from paper_2301_01719_amd import workloads as wl
 
 pytestmark = pytest.mark.gpu
@@ -318,11 +318,34 @@ def _bwd_case(rt, seed, W, H, n, C, N, mode, fmt="f32", uv_range=(-1.0, 2.0), fr
         oc, osc = oracle.quantize(tex_c.numpy(), W * H, n * n * C, f)
         otex = oracle.Tex(oc, W, H, n, C, f, osc)
     gt, gv, gu = rt.lookup_bwd(tex, gb_d.uv, gb_d.tbn, gb_d.view, go.to(DEV), mode=mode)
+    _, frac = rt.debug_indices(tex, gb_d.uv, gb_d.tbn, gb_d.view)
     _sync()
     uv, tbn, view = gb_host(gb_c)
     m = oracle.MODE_NEAREST if mode == "nearest" else oracle.MODE_BILINEAR
     ref = oracle.lookup_bwd(otex, uv, tbn, view, go.numpy(), mode=m)
+    ref["round_view"], ref["round_uv"] = oracle.lookup_bwd_round(
+        otex, uv, tbn, view, go.numpy(), round_s(n), round_w(W, H, uv), mode=m)
+    ref["frac_gpu"] = host(frac)
     return (gt, gv, gu), ref, (uv, tbn, view), go.numpy()
+
+
+def _check_fracs(ref, uv, tbn, view, W, H, n, keep):
+    """The GPU's in-bucket fractions within round_s(n) of the oracle's: the
+    rounding that the gradients' rounding term assumes."""
+    _, fo, _ = oracle.indices(uv, tbn, view, W, H, n)
+    d = np.abs(ref["frac_gpu"].astype(np.float64) - fo)[keep]
+    assert d.size == 0 or d.max() <= round_s(n), (d.max(), round_s(n))
+    return float(d.max()) if d.size else 0.0
+
+
+def _check_view_uv(ref, gv, gu, go, uv, tbn, view, W, H, n, mode):
+    keep = _smooth_mask(uv, tbn, view, W, H, n, mode)
+    _check_fracs(ref, uv, tbn, view, W, H, n, keep)
+    rv = check_grad_vec(host(gv)[keep], ref["grad_view"][keep], ref["scale_view"][keep],
+                        go[keep], ref["round_view"][keep])
+    ru = check_grad_vec(host(gu)[keep], ref["grad_uv"][keep], ref["scale_uv"][keep],
+                        go[keep], ref["round_uv"][keep])
+    return keep, rv, ru
 
 
 def _smooth_mask(uv, tbn, view, W, H, n, mode):
@@ -344,12 +367,9 @@ def _smooth_mask(uv, tbn, view, W, H, n, mode):
 def test_backward_vs_oracle(rt, W, H, n, C, N, mode):
     (gt, gv, gu), ref, (uv, tbn, view), go = _bwd_case(rt, W + N + n, W, H, n, C, N, mode)
     rt_tex = check_grad_tex(host(gt), ref, n)
-    keep = _smooth_mask(uv, tbn, view, W, H, n, mode)
-    rv = check_grad_vec(host(gv)[keep], ref["grad_view"][keep], ref["scale_view"][keep])
-    ru = check_grad_vec(host(gu)[keep], ref["grad_uv"][keep], ref["scale_uv"][keep])
-    print(f"{mode} {W}x{H}x{n}x{C} N={N}: grad_tex err/tol {rt_tex:.2e}; grad_view err/tol "
-          f"{rv[0]:.2e} (plain rel {rv[1]:.2e}); grad_uv err/tol {ru[0]:.2e} (plain rel "
-          f"{ru[1]:.2e}); {int((~keep).sum())} fragments near kinks")
+    keep, rv, ru = _check_view_uv(ref, gv, gu, go, uv, tbn, view, W, H, n, mode)
+    print(f"{mode} {W}x{H}x{n}x{C} N={N}: grad_tex err/tol {rt_tex:.2e}; grad_view {rv}; "
+          f"grad_uv {ru}; {int((~keep).sum())} fragments near kinks")
 
 
 @pytest.mark.parametrize("fmt", ["bf16", "fp8"])
@@ -357,8 +377,7 @@ def test_backward_quantized_storage(rt, fmt):
     (gt, gv, gu), ref, (uv, tbn, view), go = _bwd_case(rt, 9, 12, 10, 8, 4, 20000, "nearest",
                                                        fmt=fmt)
     check_grad_tex(host(gt), ref, 8)
-    keep = _smooth_mask(uv, tbn, view, 12, 10, 8, "nearest")
-    check_grad_vec(host(gv)[keep], ref["grad_view"][keep], ref["scale_view"][keep])
+    _check_view_uv(ref, gv, gu, go, uv, tbn, view, 12, 10, 8, "nearest")
 
 
 @pytest.mark.parametrize("mode", ["nearest", "bilinear"])
@@ -437,10 +456,16 @@ def test_backward_mixed_bucket_sizes(rt, W, N_uni, clusters, mode):
     _sync()
     u, t, v = gb_host(gb)
     m = oracle.MODE_NEAREST if mode == "nearest" else oracle.MODE_BILINEAR
-    ref = oracle.lookup_bwd(oracle.Tex(tex_c.numpy(), W, H, n, C), u, t, v, go.numpy(), mode=m)
+    otex = oracle.Tex(tex_c.numpy(), W, H, n, C)
+    ref = oracle.lookup_bwd(otex, u, t, v, go.numpy(), mode=m)
     check_grad_tex(host(gt), ref, n)
     keep = _smooth_mask(u, t, v, W, H, n, mode)
-    check_grad_vec(host(gv)[keep], ref["grad_view"][keep], ref["scale_view"][keep])
+    rv, ru = oracle.lookup_bwd_round(otex, u, t, v, go.numpy(), round_s(n), round_w(W, H, u),
+                                     mode=m)
+    check_grad_vec(host(gv)[keep], ref["grad_view"][keep], ref["scale_view"][keep],
+                   go.numpy()[keep], rv[keep])
+    check_grad_vec(host(gu)[keep], ref["grad_uv"][keep], ref["scale_uv"][keep],
+                   go.numpy()[keep], ru[keep])
 
 def test_backward_deterministic(rt):
     W, H, n, C, N = 32, 32, 8, 4, 200000

@@ -1364,3 +1364,221 @@ def test_mip_adjoint_identity(W, H):
     base = rng.normal(size=X.shape)
     acc = oracle.build_mip_adjoint(G, W, H, n, C, grad_src=base.copy())
     np.testing.assert_allclose(acc - base, AtG, atol=1e-14)
+
+
+# --------------------------------------------------------------------------
+# the error scales of the backward's criterion: the magnitude chain S
+# (scale_view, scale_uv) and the rounding term (lookup_bwd_round)
+# --------------------------------------------------------------------------
+
+def _scale_case(seed, W, H, n, C, N, frames=True):
+    rng = np.random.default_rng(seed)
+    T = _tex(rng, W, H, n, C)
+    uv = rng.uniform(-1, 2, (N, 2)).astype(np.float32)
+    d = _rand_dirs(rng, N, zmin=0.05) * rng.uniform(0.5, 2.0, (N, 1))
+    if frames:
+        R = np.array([_rand_rot(rng) for _ in range(N)])
+        tbn = R.astype(np.float32)
+        view = np.einsum("nkm,nk->nm", R, d).astype(np.float32)  # M view = d
+    else:
+        tbn = np.tile(np.eye(3, dtype=np.float32), (N, 1, 1))
+        view = d.astype(np.float32)
+    g = rng.normal(size=(N, C)).astype(np.float32)
+    return T, uv, tbn, view, g
+
+
+def _smooth(uv, tbn, view, W, H, n, mode, margin=1e-5):
+    _, _, edge = oracle.indices(uv, tbn, view, W, H, n)
+    keep = (edge[:, 0] >= margin) & (edge[:, 1] >= margin) & (edge[:, 2] >= margin)
+    if mode == oracle.MODE_BILINEAR:
+        f = uv.astype(np.float64) - np.floor(uv.astype(np.float64))
+        p = f * [W, H] - 0.5
+        keep &= np.all(np.abs(p - np.round(p)) >= margin * np.array([W, H]), axis=1)
+    return keep
+
+
+@pytest.mark.parametrize("mode", [oracle.MODE_NEAREST, oracle.MODE_BILINEAR])
+def test_magnitude_scale_bounds_the_gradient(mode):
+    # S takes every factor and term of the chain by its magnitude, so by the
+    # triangle inequality it bounds each component of the gradient
+    W, H, n, C = 6, 5, 8, 3
+    T, uv, tbn, view, g = _scale_case(60 + mode, W, H, n, C, 3000)
+    r = oracle.lookup_bwd(oracle.Tex(T, W, H, n, C), uv, tbn, view, g, mode=mode,
+                          want_tex=False)
+    assert np.all(np.abs(r["grad_view"]) <= r["scale_view"] * (1 + 1e-12))
+    assert np.all(np.abs(r["grad_uv"]) <= r["scale_uv"] * (1 + 1e-12))
+    assert np.all(r["scale_view"] >= 0) and np.any(r["scale_view"] > 0)
+    if mode == oracle.MODE_BILINEAR:
+        assert np.any(r["scale_uv"] > 0)
+    else:
+        assert np.all(r["scale_uv"] == 0)
+
+
+def test_magnitude_scale_equals_the_gradient_without_cancellation():
+    # normal incidence in the identity frame: A = 0, Eq. (3)'s Jacobian is the
+    # identity, Eq. (1b)'s is sqrt(2)/2 on the tangent axes, and no term of the
+    # chain has a sign of its own; with each channel's texel slope and upstream
+    # gradient of one sign along an axis, nothing cancels and S = |g*|
+    n, C = 8, 3
+    bx = np.array([0.1, -0.2, 0.05])
+    by = np.array([-0.05, 0.1, -0.02])
+    y, x = np.mgrid[0:n, 0:n]
+    T = (0.5 + bx * x[..., None] + by * y[..., None]).astype(np.float32)[None, None]
+    tex = oracle.Tex(T, 1, 1, n, C)
+    uv = np.array([[0.3, 0.6]], np.float32)
+    tbn = np.eye(3, dtype=np.float32)[None]
+    view = np.array([[0, 0, 1.0]], np.float32)
+    for g in ([1.0, -2.0, 0.5], [-1.0, 2.0, -0.5]):
+        g = np.array([g], np.float32)
+        r = oracle.lookup_bwd(tex, uv, tbn, view, g, want_tex=False)
+        np.testing.assert_allclose(r["scale_view"], np.abs(r["grad_view"]), rtol=1e-14,
+                                   atol=1e-16)
+        # and the closed form: (sqrt2/2)(n/2) sum_c g_c (slope_x, slope_y), 0
+        want = np.sqrt(2) / 2 * n / 2 * np.array([np.dot(g[0], bx), np.dot(g[0], by), 0.0])
+        np.testing.assert_allclose(r["grad_view"][0], want, rtol=1e-6, atol=1e-12)
+    # the uv scale: bucket column i0 = 0 holds zeros and column 1 holds positive
+    # texels, so dL/du = W ((1 - b) L1 + b L3) with nothing subtracted
+    W, H = 2, 2
+    rng = np.random.default_rng(61)
+    T = rng.uniform(0.1, 1.0, (H, W, n, n, C)).astype(np.float32)
+    T[:, 0] = 0.0
+    tex = oracle.Tex(T, W, H, n, C)
+    N = 200
+    uv = np.stack([rng.uniform(0.26, 0.74, N), rng.uniform(0, 1, N)], 1).astype(np.float32)
+    view = _rand_dirs(rng, N, zmin=0.2).astype(np.float32)
+    tbn = np.tile(np.eye(3, dtype=np.float32), (N, 1, 1))
+    g = rng.uniform(0.1, 1.0, (N, C)).astype(np.float32)
+    r = oracle.lookup_bwd(tex, uv, tbn, view, g, mode=oracle.MODE_BILINEAR, want_tex=False)
+    assert np.all(r["grad_uv"][:, 0] > 0)
+    np.testing.assert_allclose(r["scale_uv"][:, 0], r["grad_uv"][:, 0], rtol=1e-13)
+
+
+@pytest.mark.parametrize("W,H,n,C,mode,frames", [
+    (6, 5, 8, 3, oracle.MODE_NEAREST, True), (6, 5, 8, 3, oracle.MODE_BILINEAR, True),
+    (8, 8, 16, 4, oracle.MODE_NEAREST, True), (8, 8, 16, 4, oracle.MODE_BILINEAR, False),
+    (4, 4, 64, 1, oracle.MODE_BILINEAR, True)])
+def test_error_scales_bound_a_binary32_evaluation(W, H, n, C, mode, frames):
+    # an independent binary32 evaluation of the lookup and its chain (numpy
+    # float32, one rounding per operation) differs from the oracle's gradient
+    # by at most 2^-20 S plus the rounding term: S covers the rounding of the
+    # chain's own arithmetic and the rounding term that of the quantities the
+    # taps are weighted with.  A scale missing a factor or a term would let
+    # some fragment exceed it.
+    from binary32_model import model
+    from helpers import round_s, round_w
+    T, uv, tbn, view, g = _scale_case(70 + n + mode, W, H, n, C, 20000, frames)
+    tex = oracle.Tex(T, W, H, n, C)
+    r = oracle.lookup_bwd(tex, uv, tbn, view, g, mode=mode, want_tex=False)
+    rv, ru = oracle.lookup_bwd_round(tex, uv, tbn, view, g, round_s(n), round_w(W, H, uv),
+                                     mode=mode)
+    keep = _smooth(uv, tbn, view, W, H, n, mode)
+    gv, gu = model(T, W, H, n, C, uv, tbn, view, g, mode)
+    for mine, ref, S, rnd in ((gv, r["grad_view"], r["scale_view"], rv),
+                              (gu, r["grad_uv"], r["scale_uv"], ru)):
+        err = np.linalg.norm(mine - ref, axis=1)[keep]
+        bound = 2.0 ** -20 * np.linalg.norm(S, axis=1)[keep] + rnd[keep]
+        assert np.all(err <= bound), (np.max(err / np.maximum(bound, 1e-300)))
+        # and the survey's reading of "1e-4 relative" with the rounding term
+        gn = np.linalg.norm(ref, axis=1)[keep]
+        assert np.all(err <= 1e-4 * gn + 1e-6 * np.abs(g[keep]).sum(1) + rnd[keep])
+    if n == 64:
+        # at n = 64 the rounding of s (up to 2^-24 n) outweighs the chain's
+        # own: without the rounding term some fragments exceed 2^-20 S, so
+        # the term is needed, not decoration
+        err = np.linalg.norm(gv - r["grad_view"], axis=1)[keep]
+        assert np.any(err > 2.0 ** -20 * np.linalg.norm(r["scale_view"], axis=1)[keep])
+
+
+@pytest.mark.parametrize("mode", [oracle.MODE_NEAREST, oracle.MODE_BILINEAR])
+def test_rounding_term_vanishes_on_untwisted_buckets(mode):
+    # buckets whose texels are affine in (x, y) with one slope for all buckets:
+    # dL/ds is then the same wherever s sits in its cell, and the buckets'
+    # differences do not depend on s either, so moving s (or a, b: the
+    # gradient is linear in them, with the same slopes) changes nothing that
+    # the rounding term measures -- except a, b for dL/dview, which weigh
+    # equal slopes and so also change nothing
+    W, H, n, C = 4, 4, 8, 2
+    rng = np.random.default_rng(80)
+    y, x = np.mgrid[0:n, 0:n]
+    sl = np.array([[0.03, -0.02], [0.01, 0.04]])  # [axis][channel]
+    off = rng.uniform(0, 0.5, (H, W, 1, 1, C))
+    T = off + sl[0] * x[..., None] + sl[1] * y[..., None]  # binary64: exactly affine
+    tex = oracle.Tex(T, W, H, n, C, oracle.FMT_F64)
+    T2, uv, tbn, view, g = _scale_case(81, W, H, n, C, 500)
+    keep = _smooth(uv, tbn, view, W, H, n, mode)
+    rv, ru = oracle.lookup_bwd_round(tex, uv, tbn, view, g, 1e-3, 1e-3, mode=mode)
+    r = oracle.lookup_bwd(tex, uv, tbn, view, g, mode=mode, want_tex=False)
+    gscale = np.linalg.norm(r["scale_view"], axis=1)[keep]
+    assert np.all(rv[keep] <= 1e-12 * gscale + 1e-15)
+    if mode == oracle.MODE_NEAREST:
+        assert np.all(ru == 0)
+    # a random (twisted) texture moves the gradient by an amount linear in the move
+    tex2 = oracle.Tex(T2, W, H, n, C)
+    a1, b1 = oracle.lookup_bwd_round(tex2, uv, tbn, view, g, 1e-4, 0.0, mode=mode)
+    a2, b2 = oracle.lookup_bwd_round(tex2, uv, tbn, view, g, 2e-4, 0.0, mode=mode)
+    live = keep & (a1 > 1e-9)  # both axes clamped: no view gradient to move
+    assert live.sum() > 0.5 * keep.sum()
+    np.testing.assert_allclose(a2[live], 2 * a1[live], rtol=1e-3)
+
+
+def test_rounding_term_is_the_gradient_at_the_moved_coordinate():
+    # brute force through the ordinary backward: replacing a fragment's four
+    # taps by its cell's bilinear patch shifted by (sx, sy) delta (corner values
+    # of the extended patch, binary64 texture) makes the plain backward return
+    # the gradient at s + (sx, sy) delta with every other factor unchanged; the
+    # largest change over the four shifts is the rounding term
+    n, C = 8, 3
+    rng = np.random.default_rng(82)
+    T = rng.uniform(0, 1, (1, 1, n, n, C))
+    delta = 1e-3
+    _, uv, tbn, view, g = _scale_case(83, 1, 1, n, C, 40)
+    idx, frac, edge = oracle.indices(uv, tbn, view, 1, 1, n)
+    checked = 0
+    for f in range(len(uv)):
+        x0, y0 = idx[f, 2], idx[f, 3]
+        if edge[f, 1] < 1e-3 or edge[f, 2] < 1e-3 or x0 >= n - 1 or y0 >= n - 1:
+            continue
+        one = (uv[f:f + 1], tbn[f:f + 1], view[f:f + 1], g[f:f + 1])
+        base = oracle.lookup_bwd(oracle.Tex(T, 1, 1, n, C, oracle.FMT_F64), *one,
+                                 want_tex=False)["grad_view"][0]
+        c = T[0, 0, y0:y0 + 2, x0:x0 + 2]  # [dy, dx, C]
+
+        def patch(u, v):
+            return (1 - v) * ((1 - u) * c[0, 0] + u * c[0, 1]) + v * ((1 - u) * c[1, 0] + u * c[1, 1])
+        worst = 0.0
+        for sy in (-1, 1):
+            for sx in (-1, 1):
+                Tm = T.copy()
+                du, dv = sx * delta, sy * delta
+                Tm[0, 0, y0, x0] = patch(du, dv)
+                Tm[0, 0, y0, x0 + 1] = patch(1 + du, dv)
+                Tm[0, 0, y0 + 1, x0] = patch(du, 1 + dv)
+                Tm[0, 0, y0 + 1, x0 + 1] = patch(1 + du, 1 + dv)
+                moved = oracle.lookup_bwd(oracle.Tex(Tm, 1, 1, n, C, oracle.FMT_F64), *one,
+                                          want_tex=False)["grad_view"][0]
+                worst = max(worst, np.linalg.norm(moved - base))
+        rv, _ = oracle.lookup_bwd_round(oracle.Tex(T, 1, 1, n, C, oracle.FMT_F64), *one, delta)
+        assert abs(rv[0] - worst) <= 1e-9 * max(worst, 1e-12), (f, rv[0], worst)
+        checked += 1
+    assert checked >= 20
+    # the bucket fractions: moving u, v by delta_w / W, delta_w / H moves a, b
+    # by delta_w and nothing else (dyadic coordinates keep the moves exact)
+    W, H = 4, 4
+    T = rng.uniform(0, 1, (H, W, n, n, C)).astype(np.float32)
+    tex = oracle.Tex(T, W, H, n, C)
+    dw = 2.0 ** -10
+    _, _, tbn, view, g = _scale_case(84, W, H, n, C, 30)
+    uv = (np.round(rng.uniform(0.1, 0.9, (30, 2)) * 2 ** 16) / 2 ** 16).astype(np.float32)
+    for f in range(len(uv)):
+        one = lambda u: (u[None].astype(np.float32), tbn[f:f + 1], view[f:f + 1], g[f:f + 1])
+        base = oracle.lookup_bwd(tex, *one(uv[f]), mode=oracle.MODE_BILINEAR, want_tex=False)
+        worst_v = worst_u = 0.0
+        for sb in (-1, 1):
+            for sa in (-1, 1):
+                u2 = uv[f].astype(np.float64) + [sa * dw / W, sb * dw / H]
+                m = oracle.lookup_bwd(tex, *one(u2), mode=oracle.MODE_BILINEAR, want_tex=False)
+                worst_v = max(worst_v, np.linalg.norm(m["grad_view"][0] - base["grad_view"][0]))
+                worst_u = max(worst_u, np.linalg.norm(m["grad_uv"][0] - base["grad_uv"][0]))
+        rv, ru = oracle.lookup_bwd_round(tex, *one(uv[f]), 0.0, dw, mode=oracle.MODE_BILINEAR)
+        assert abs(rv[0] - worst_v) <= 1e-9 * max(worst_v, 1e-12)
+        assert abs(ru[0] - worst_u) <= 1e-9 * max(worst_u, 1e-12)
