@@ -112,6 +112,65 @@ __device__ __forceinline__ void bucket_grads(const TexView& t, int64_t b, const 
     lval = f * lv;
 }
 
+// Bilinear-bucket mode: the slopes dL/ds of the four buckets (weighted by
+// their bucket weights wb, as bucket_grads forms them) and dL/du, dL/dv.  The
+// uv derivatives are formed from the differences of corresponding taps of
+// neighbouring buckets, each tap times its bucket's factor, so their rounding
+// follows the size of those differences rather than of the texel values:
+//   dL/du = W sum_c g_c sum_taps w_tap [(1 - b)(T(i1,j0) - T(i0,j0)) + b (T(i1,j1) - T(i0,j1))]
+//   dL/dv = H sum_c g_c sum_taps w_tap [(1 - a)(T(i0,j1) - T(i0,j0)) + a (T(i1,j1) - T(i1,j0))]
+// with the buckets ordered (i0,j0), (i1,j0), (i0,j1), (i1,j1).
+template <int FMT, int C>
+__device__ __forceinline__ void pair_grads(const TexView& t, const int64_t bk[4], const float wb[4],
+                                           float a, float bb, const Foot& p, const float go[4],
+                                           bool want_uv, float& gsx, float& gsy, float& gu,
+                                           float& gv) {
+    const int n = t.n;
+    float T[4][4][4];  // [bucket][tap 00, 01, 10, 11][channel], times the bucket factor
+    gsx = 0.f;
+    gsy = 0.f;
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+        const int64_t base = bk[k] * (int64_t)(n * n);
+        const F4 t00 = load_texel<FMT, C>(t.data, base + p.y0 * n + p.x0);
+        const F4 t01 = load_texel<FMT, C>(t.data, base + p.y0 * n + p.x1);
+        const F4 t10 = load_texel<FMT, C>(t.data, base + p.y1 * n + p.x0);
+        const F4 t11 = load_texel<FMT, C>(t.data, base + p.y1 * n + p.x1);
+        const float f = bucket_factor<FMT>(t.scales, bk[k]);
+        float gx = 0.f, gy = 0.f;
+#pragma unroll
+        for (int c = 0; c < C; c++) {
+            gx += go[c] * ((1.f - p.fy) * (t01.v[c] - t00.v[c]) + p.fy * (t11.v[c] - t10.v[c]));
+            gy += go[c] * ((1.f - p.fx) * (t10.v[c] - t00.v[c]) + p.fx * (t11.v[c] - t01.v[c]));
+            T[k][0][c] = f * t00.v[c];
+            T[k][1][c] = f * t01.v[c];
+            T[k][2][c] = f * t10.v[c];
+            T[k][3][c] = f * t11.v[c];
+        }
+        gsx += wb[k] * (f * gx);
+        gsy += wb[k] * (f * gy);
+    }
+    gu = 0.f;
+    gv = 0.f;
+    if (!want_uv) return;
+    const float w[4] = {(1.f - p.fx) * (1.f - p.fy), p.fx * (1.f - p.fy), (1.f - p.fx) * p.fy,
+                        p.fx * p.fy};
+    float su = 0.f, sv = 0.f;
+#pragma unroll
+    for (int c = 0; c < C; c++) {
+        float du = 0.f, dv = 0.f;
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            du += w[q] * ((1.f - bb) * (T[1][q][c] - T[0][q][c]) + bb * (T[3][q][c] - T[2][q][c]));
+            dv += w[q] * ((1.f - a) * (T[2][q][c] - T[0][q][c]) + a * (T[3][q][c] - T[1][q][c]));
+        }
+        su += go[c] * du;
+        sv += go[c] * dv;
+    }
+    gu = (float)t.W * su;
+    gv = (float)t.H * sv;
+}
+
 // The per-fragment outputs (view and uv gradients, and in nearest mode the
 // sort keys and fractions) are stored non-temporally: they are written once
 // and read back, if at all, by later passes over millions of records.
@@ -175,19 +234,9 @@ __global__ __launch_bounds__(256) void k_bwd_fragment(
                                (int64_t)j1 * t.W + i0, (int64_t)j1 * t.W + i1};
         const float wb[4] = {(1.f - a) * (1.f - bb), a * (1.f - bb), (1.f - a) * bb, a * bb};
         if (grad_view || grad_uv) {
-            float lv[4];
-#pragma unroll
-            for (int k = 0; k < 4; k++) {
-                float dx, dy;
-                bucket_grads<FMT, C>(t, bk[k], p, go, dx, dy, lv[k]);
-                gsx += wb[k] * dx;
-                gsy += wb[k] * dy;
-            }
-            if (grad_uv) {
-                float gu = (float)t.W * ((1.f - bb) * (lv[1] - lv[0]) + bb * (lv[3] - lv[2]));
-                float gv = (float)t.H * ((1.f - a) * (lv[2] - lv[0]) + a * (lv[3] - lv[1]));
-                nt_store2(grad_uv + 2 * f, gu, gv);
-            }
+            float gu, gv;
+            pair_grads<FMT, C>(t, bk, wb, a, bb, p, go, grad_uv != nullptr, gsx, gsy, gu, gv);
+            if (grad_uv) nt_store2(grad_uv + 2 * f, gu, gv);
         }
         if (keys) {
 #pragma unroll
@@ -317,20 +366,10 @@ __global__ __launch_bounds__(256) void k_lod_bwd_fragment(
                                    (int64_t)j1 * t.W + i0, (int64_t)j1 * t.W + i1};
             const float wb[4] = {(1.f - a) * (1.f - bb), a * (1.f - bb), (1.f - a) * bb, a * bb};
             if (grad_view || grad_uv) {
-                float lv[4];
-#pragma unroll
-                for (int k = 0; k < 4; k++) {
-                    float dx, dy;
-                    bucket_grads<FMT, C>(t, bk[k], p, go, dx, dy, lv[k]);
-                    gsx += wb[k] * dx;
-                    gsy += wb[k] * dy;
-                }
-                if (grad_uv) {
-                    const float gu = (float)t.W * ((1.f - bb) * (lv[1] - lv[0]) + bb * (lv[3] - lv[2]));
-                    const float gv = (float)t.H * ((1.f - a) * (lv[2] - lv[0]) + a * (lv[3] - lv[1]));
-                    su += gu;
-                    sv += gv;
-                }
+                float gu, gv;
+                pair_grads<FMT, C>(t, bk, wb, a, bb, p, go, grad_uv != nullptr, gsx, gsy, gu, gv);
+                su += gu;
+                sv += gv;
             }
             if (rec) {
 #pragma unroll
