@@ -53,7 +53,7 @@
 extern "C" {
 #endif
 
-#define RT_VERSION 100
+#define RT_VERSION 200
 
 typedef enum {
     RT_OK = 0,
@@ -238,6 +238,47 @@ rt_status rt_lookup_bwd(const rt_texture* tex, const rt_fragments* frags,
                         const float* grad_out, float* grad_tex, float* grad_view,
                         float* grad_uv, void* workspace, size_t workspace_bytes,
                         uint32_t flags, void* stream);
+
+/* --- Visit plan ------------------------------------------------------------
+ * The lookup is a gather (Sec. 2: the bucket is chosen by u, v and the sample
+ * inside it by the view direction), so the order in which fragments are
+ * visited decides how often a bucket's lines are fetched.  A visit plan
+ * reorders a G-buffer by the backward's record key -- bucket (j W + i), then
+ * cell (y0 n + x0) of the bilinear footprint, ties in the caller's fragment
+ * order -- so that fragments reading the same bucket are visited together
+ * (and, in nearest mode, the backward finds its records already sorted and
+ * skips its sort; the results are the same bits either way).  It depends on
+ * u, v, the frame and the view vector only, not on the texels: one plan
+ * serves every step of a fit whose G-buffer stays fixed.
+ *
+ * Every per-fragment array of a planned lookup is in plan order: out and
+ * grad_out of planned fragment k belong to the caller's fragment order[k].
+ * A caller that keeps its own per-fragment data (targets, weights) permutes
+ * it once with order. */
+
+/* Bytes of device workspace rt_plan_fragments needs (0 when the arguments are
+ * invalid). */
+size_t rt_plan_workspace(const rt_texture* tex, int64_t count, uint32_t flags);
+
+/* Plan the fragments of `frags` against the geometry (W, H, n) of `tex`
+ * (its texels are not read).  flags: RT_BUCKET_NEAREST keys by the nearest
+ * bucket; RT_BUCKET_BILINEAR by the first bucket (i0, j0) of the bilinear
+ * footprint.
+ *   order     DEVICE int32 [N], written: order[k] is the caller's index of
+ *             planned fragment k (a permutation of 0..N-1).
+ *   uv_out    DEVICE float [N][2], tbn_out [N][3][3], view_out [N][3],
+ *             written: the planned G-buffer (fragment order[k] of the input at
+ *             position k), for rt_lookup_fwd / rt_lookup_bwd without a tiling
+ *             hint.  None of the four may overlap the input or each other.
+ * The tiling hint of `frags` only decides which thread reads which fragment.
+ * workspace: at least rt_plan_workspace() bytes, 256-byte aligned, owned by
+ * the caller, not used by concurrent calls.  Asynchronous on `stream`.
+ * Errors: RT_ERR_INVALID_ARG (NULL, alignment: order, tbn_out, view_out 4 B,
+ * uv_out 8 B; overlapping arrays), RT_ERR_WORKSPACE_TOO_SMALL,
+ * RT_ERR_UNSUPPORTED (W H n n beyond 2^32, count >= 2^31). */
+rt_status rt_plan_fragments(const rt_texture* tex, const rt_fragments* frags, uint32_t flags,
+                            int32_t* order, float* uv_out, float* tbn_out, float* view_out,
+                            void* workspace, size_t workspace_bytes, void* stream);
 
 /* Per-fragment indices of the nearest-bucket lookup, for exact checks:
  * idx int32 [N][4] = (i, j, x0, y0) with x0 = floor(s_x) in [0, n-1], and

@@ -145,7 +145,8 @@ const char* kernel_name(int id) {
         "k_bake_env",     "k_build_mip",     "k_lookup_lod",    "k_pack_bits",
         "k_lookup_light", "k_bake_shadow",   "k_vq_assign",     "k_vq_hist",
         "k_vq_scatter",   "k_vq_pieces",     "k_vq_combine",    "k_lod_bwd_fragment",
-        "k_mip_adjoint",  "k_payload"};
+        "k_mip_adjoint",  "k_payload",       "k_keys_in_order", "k_plan_keys",
+        "k_plan_gather"};
     return (id >= 0 && id < K_COUNT) ? names[id] : "";
 }
 
@@ -419,6 +420,68 @@ rt_status rt_lookup_bwd(const rt_texture* t, const rt_fragments* f, const float*
                                        grad_out, grad_tex, grad_view, grad_uv, fragmap(f), plan,
                                        ws, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "backward launch");
+    return ok();
+    RT_GUARD_END
+}
+
+size_t rt_plan_workspace(const rt_texture* t, int64_t count, uint32_t flags) {
+    try {
+        if (!t || count < 0 || flags > RT_BUCKET_BILINEAR) return 0;
+        rt::BwdPlan p;
+        if (!rt::plan_backward(t->view.W, t->view.H, t->view.n, 1, count, rt::MODE_NEAREST, &p))
+            return 0;
+        return p.sort_total;
+    } catch (...) {
+        return 0;
+    }
+}
+
+namespace {
+bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
+    const uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
+    return x < y + nb && y < x + na;
+}
+}  // namespace
+
+rt_status rt_plan_fragments(const rt_texture* t, const rt_fragments* f, uint32_t flags,
+                            int32_t* order, float* uv_out, float* tbn_out, float* view_out,
+                            void* ws, size_t ws_bytes, void* stream) {
+    RT_GUARD_BEGIN
+    rt_status st = check_tex(t);
+    if (st != RT_OK) return st;
+    st = check_frags(f);
+    if (st != RT_OK) return st;
+    if (flags > RT_BUCKET_BILINEAR) return fail(RT_ERR_INVALID_ARG, "unknown flags 0x%x", flags);
+    rt::BwdPlan plan;
+    if (!rt::plan_backward(t->view.W, t->view.H, t->view.n, 1, f->count, rt::MODE_NEAREST, &plan))
+        return fail(RT_ERR_UNSUPPORTED, "sort key (W*H*n*n) beyond 32 bits");
+    const int64_t N = f->count;
+    if (N == 0) return ok();
+    if (!order || !uv_out || !tbn_out || !view_out)
+        return fail(RT_ERR_INVALID_ARG, "order, uv_out, tbn_out and view_out must be non-NULL");
+    if (!aligned(order, 4) || !aligned(uv_out, 8) || !aligned(tbn_out, 4) || !aligned(view_out, 4))
+        return fail(RT_ERR_INVALID_ARG, "order, tbn_out and view_out must be 4-byte and uv_out "
+                    "8-byte aligned");
+    const void* ins[3] = {f->uv, f->tbn, f->view};
+    const size_t insz[3] = {(size_t)N * 8, (size_t)N * 36, (size_t)N * 12};
+    const void* outs[4] = {order, uv_out, tbn_out, view_out};
+    const size_t outsz[4] = {(size_t)N * 4, (size_t)N * 8, (size_t)N * 36, (size_t)N * 12};
+    for (int a = 0; a < 4; a++) {
+        for (int b = 0; b < 3; b++)
+            if (overlaps(outs[a], outsz[a], ins[b], insz[b]))
+                return fail(RT_ERR_INVALID_ARG, "the planned arrays must not overlap the input");
+        for (int b = a + 1; b < 4; b++)
+            if (overlaps(outs[a], outsz[a], outs[b], outsz[b]))
+                return fail(RT_ERR_INVALID_ARG, "the planned arrays must not overlap each other");
+    }
+    if (!ws) return fail(RT_ERR_INVALID_ARG, "workspace is NULL");
+    if (!aligned(ws, 256)) return fail(RT_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+    if (ws_bytes < plan.sort_total)
+        return fail(RT_ERR_WORKSPACE_TOO_SMALL, "workspace has %zu bytes, %zu needed", ws_bytes,
+                    plan.sort_total);
+    hipError_t e = rt::launch_plan(t->view, (int)flags, f->uv, f->tbn, f->view, fragmap(f), plan,
+                                   ws, order, uv_out, tbn_out, view_out, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "plan launch");
     return ok();
     RT_GUARD_END
 }

@@ -410,6 +410,41 @@ __global__ __launch_bounds__(256) void k_lod_bwd_fragment(
 // 2. stable LSD radix sort of (key, record index), 8-bit digits
 // ---------------------------------------------------------------------------
 
+// Records made in key order already (fragments visited in the order of a
+// visit plan): k_keys_in_order leaves 0 in the disorder word, every launch of
+// the sort then returns at once, and the later passes read the keys where the
+// per-fragment pass wrote them, each record's position being its number.  A
+// stable sort of keys in order is the identity, so the results are the same
+// bits either way.
+__device__ __forceinline__ bool sort_skipped(const uint32_t* __restrict__ disorder) {
+    return disorder != nullptr && __builtin_amdgcn_readfirstlane(*disorder) == 0u;
+}
+
+// Any key smaller than the one before it sets *disorder (cleared before the
+// launch).  Four keys per thread with one 16-byte load (the key buffer is
+// padded to 256 bytes) and the key before them.  A wave that finds a descent
+// reads the word first (past its L1) and sets it only while it is still
+// clear: on unsorted keys nearly every wave finds one, and a million atomics
+// on one address would serialise.
+__global__ __launch_bounds__(256) void k_keys_in_order(const uint32_t* __restrict__ keys, int64_t R,
+                                                       uint32_t* __restrict__ disorder) {
+    const int64_t i0 = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 4;
+    bool down = false;
+    if (i0 < R) {
+        const uint4 q = *(const uint4*)(keys + i0);
+        const uint32_t k[5] = {keys[i0 > 0 ? i0 - 1 : 0], q.x, q.y, q.z, q.w};
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            const int64_t i = i0 + u;
+            if (i > 0 && i < R && k[u + 1] < k[u]) down = true;
+        }
+    }
+    const uint64_t m = __ballot(down);
+    if (m != 0ull && (threadIdx.x & 63) == (unsigned)__builtin_ctzll(m) &&
+        __hip_atomic_load(disorder, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u)
+        atomicOr(disorder, 1u);
+}
+
 // Digit counts of one tile of SORT_TILE keys: hist[d * tiles + tile].  Tiles
 // are renumbered so that each XCD takes a contiguous range: the counts of
 // neighbouring tiles share cache lines of the digit-major table, and so the
@@ -418,9 +453,11 @@ template <int D>
 __global__ __launch_bounds__(SORT_THREADS) void k_radix_hist(const uint32_t* __restrict__ keys,
                                                              int64_t R, int shift,
                                                              uint32_t* __restrict__ hist,
-                                                             int64_t tiles) {
+                                                             int64_t tiles,
+                                                             const uint32_t* __restrict__ skip) {
     constexpr int B = 1 << D;
     __shared__ uint32_t cnt[B];
+    if (sort_skipped(skip)) return;
     const int t = threadIdx.x;
     for (int d = t; d < B; d += SORT_THREADS) cnt[d] = 0;
     __syncthreads();
@@ -488,8 +525,10 @@ __device__ __forceinline__ void load16(const uint32_t* __restrict__ in, int64_t 
 }
 
 __global__ __launch_bounds__(256) void k_scan_reduce(const uint32_t* __restrict__ in, int64_t L,
-                                                     uint32_t* __restrict__ part) {
+                                                     uint32_t* __restrict__ part,
+                                                     const uint32_t* __restrict__ skip) {
     __shared__ uint32_t wsum[4];
+    if (sort_skipped(skip)) return;
     const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + threadIdx.x * 16;
     const bool vec = ((uintptr_t)in & 15) == 0;
     uint32_t v[16], s = 0;
@@ -501,8 +540,10 @@ __global__ __launch_bounds__(256) void k_scan_reduce(const uint32_t* __restrict_
     if (threadIdx.x == 0) part[blockIdx.x] = total;
 }
 
-__global__ __launch_bounds__(256) void k_scan_top(uint32_t* __restrict__ part, int64_t P) {
+__global__ __launch_bounds__(256) void k_scan_top(uint32_t* __restrict__ part, int64_t P,
+                                                  const uint32_t* __restrict__ skip) {
     __shared__ uint32_t wsum[4];
+    if (sort_skipped(skip)) return;
     uint32_t carry = 0;
     for (int64_t base = 0; base < P; base += 256 * 16) {
         const int64_t b = base + threadIdx.x * 16;
@@ -529,8 +570,10 @@ __global__ __launch_bounds__(256) void k_scan_top(uint32_t* __restrict__ part, i
 template <bool SCANNED>
 __global__ __launch_bounds__(256) void k_scan_down(const uint32_t* __restrict__ in, int64_t L,
                                                    const uint32_t* __restrict__ part,
-                                                   uint32_t* __restrict__ out) {
+                                                   uint32_t* __restrict__ out,
+                                                   const uint32_t* __restrict__ skip) {
     __shared__ uint32_t wsum[4];
+    if (sort_skipped(skip)) return;
     uint32_t offset;
     if constexpr (SCANNED) {
         offset = part[blockIdx.x];
@@ -577,7 +620,7 @@ template <int D>
 __global__ __launch_bounds__(SORT_THREADS) void k_radix_scatter(
     const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in,
     uint32_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out, int64_t R, int shift,
-    const uint32_t* __restrict__ hoff, int64_t tiles) {
+    const uint32_t* __restrict__ hoff, int64_t tiles, const uint32_t* __restrict__ skip) {
     constexpr int B = 1 << D;
     constexpr int DPT = B / SORT_THREADS;  // digits per thread in the digit phase
     constexpr int QUARTER = SORT_TILE / 4;
@@ -586,6 +629,7 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_scatter(
     __shared__ uint32_t wcnt[4][B];  // running counts, then exclusive prefixes over waves
     __shared__ uint32_t dstart[B], goff[B];
     __shared__ uint32_t wsum[4];
+    if (sort_skipped(skip)) return;
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     const int64_t tile = xcd_block_id(blockIdx.x, gridDim.x);
     const int64_t base = tile * SORT_TILE;
@@ -687,7 +731,10 @@ __global__ __launch_bounds__(256) void k_fill_u32(uint32_t* __restrict__ p, int6
 // two neighbours, loaded unconditionally from clamped positions.
 __global__ __launch_bounds__(256) void k_bucket_ranges(const uint32_t* __restrict__ skeys,
                                                        int64_t R, int cell_bits, int64_t nb,
-                                                       int2* __restrict__ range) {
+                                                       int2* __restrict__ range,
+                                                       const uint32_t* __restrict__ keys_made,
+                                                       const uint32_t* __restrict__ disorder) {
+    if (sort_skipped(disorder)) skeys = keys_made;
     const int64_t i0 = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 4;
     if (i0 >= R) return;
     const uint4 q = *(const uint4*)(skeys + i0);
@@ -722,7 +769,10 @@ __global__ __launch_bounds__(256) void k_payload(const uint32_t* __restrict__ sk
                                                  const int2* __restrict__ range, int64_t R,
                                                  int cell_bits, int64_t nb,
                                                  float* __restrict__ payf,
-                                                 float* __restrict__ payg) {
+                                                 float* __restrict__ payg,
+                                                 const uint32_t* __restrict__ disorder) {
+    // records in key order are read where they were made: no payload
+    if (sort_skipped(disorder)) return;
     const int64_t i = (int64_t)xcd_block_id(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
     if (i >= R) return;
     const uint32_t b = skeys[i] >> cell_bits;
@@ -793,7 +843,7 @@ __device__ __forceinline__ int load_record(const uint32_t* __restrict__ skeys,
                                            const float* __restrict__ grad_out, int64_t i,
                                            uint32_t cell_mask, float v[4 * C]) {
     const uint32_t key = skeys[i];
-    const uint32_t rec = svals[i];
+    const uint32_t rec = svals ? svals[i] : (uint32_t)i;
     float fx, fy, wb = 1.f;
     int64_t frag;
     if constexpr (MODE == MODE_NEAREST) {
@@ -974,7 +1024,7 @@ __device__ __forceinline__ void load_window(const uint32_t* __restrict__ skeys,
             w.fy = f2.y;
             load_payg<C>(payg, i, w.g);
         } else {
-            const uint32_t rec = svals[i];
+            const uint32_t rec = svals ? svals[i] : (uint32_t)i;
             float wb = 1.f;
             int64_t frag;
             if constexpr (MODE == MODE_NEAREST) {
@@ -1107,7 +1157,14 @@ __global__ __launch_bounds__(256) void k_segacc(const uint32_t* __restrict__ ske
                                                 int64_t R, int n, uint32_t cell_mask,
                                                 uint32_t* __restrict__ big_count,
                                                 uint32_t* __restrict__ big_list,
-                                                int64_t big_cap) {
+                                                int64_t big_cap,
+                                                const uint32_t* __restrict__ keys_made,
+                                                const uint32_t* __restrict__ disorder) {
+    if (sort_skipped(disorder)) {
+        skeys = keys_made;
+        svals = nullptr;
+        payf = nullptr;
+    }
     extern __shared__ float lds[];
     const int te = n * n * C;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -1174,7 +1231,13 @@ __global__ __launch_bounds__(256) void k_segacc_big(const uint32_t* __restrict__
                                                     uint32_t cell_mask,
                                                     const uint32_t* __restrict__ big_count,
                                                     const uint32_t* __restrict__ big_list,
-                                                    int64_t big_cap) {
+                                                    int64_t big_cap,
+                                                    const uint32_t* __restrict__ keys_made,
+                                                    const uint32_t* __restrict__ disorder) {
+    if (sort_skipped(disorder)) {
+        skeys = keys_made;
+        svals = nullptr;
+    }
     extern __shared__ float lds[];
     const int te = n * n * C;
     const int w = threadIdx.x >> 6;
@@ -1206,7 +1269,13 @@ __global__ __launch_bounds__(64) void k_segacc_hot(const uint32_t* __restrict__ 
                                                    const float* __restrict__ grad_out,
                                                    const int2* __restrict__ range,
                                                    float* __restrict__ part, int64_t R, int n,
-                                                   int cell_bits, int64_t nb) {
+                                                   int cell_bits, int64_t nb,
+                                                   const uint32_t* __restrict__ keys_made,
+                                                   const uint32_t* __restrict__ disorder) {
+    if (sort_skipped(disorder)) {
+        skeys = keys_made;
+        svals = nullptr;
+    }
     extern __shared__ float lds[];
     const int te = n * n * C;
     const uint32_t cell_mask = (cell_bits >= 32) ? 0xFFFFFFFFu : ((1u << cell_bits) - 1u);
@@ -1236,7 +1305,10 @@ __global__ __launch_bounds__(64) void k_combine_hot(const uint32_t* __restrict__
                                                     const int2* __restrict__ range,
                                                     const float* __restrict__ part,
                                                     const TileOut out, int64_t R,
-                                                    int te, int cell_bits, int64_t nb) {
+                                                    int te, int cell_bits, int64_t nb,
+                                                    const uint32_t* __restrict__ keys_made,
+                                                    const uint32_t* __restrict__ disorder) {
+    if (sort_skipped(disorder)) skeys = keys_made;
     const int lane = threadIdx.x;
     const int64_t k = blockIdx.x;
     const int64_t c0 = k * PIECE;
@@ -1329,16 +1401,20 @@ bool plan_backward(int W, int H, int n, int C, int64_t N, int mode, BwdPlan* p, 
         o += align256(bytes);
         return at;
     };
+    // the sort's buffers and the disorder word first: a visit plan's
+    // workspace is this prefix
     p->off_keys0 = take((size_t)R * 4);
     p->off_keys1 = take((size_t)R * 4);
     p->off_vals0 = take((size_t)R * 4);
     p->off_vals1 = take((size_t)R * 4);
-    p->off_wrec = take((size_t)N * (mode == MODE_NEAREST ? 8 : 16));
-    p->off_payf = take((size_t)R * 8);
-    p->off_payg = take((size_t)R * 4 * C);
     p->off_hist = take((size_t)p->scan_len * 4);
     p->off_hoff = take((size_t)p->scan_len * 4);
     p->off_scanp = take((size_t)(p->scan_blocks + 1) * 4);
+    p->off_disorder = take(4);
+    p->sort_total = o;
+    p->off_wrec = take((size_t)N * (mode == MODE_NEAREST ? 8 : 16));
+    p->off_payf = take((size_t)R * 8);
+    p->off_payg = take((size_t)R * 4 * C);
     // big-bucket lists: list l receives the runs r of BIG_RUN groups with
     // r mod BIG_LISTS = l, at most ceil(ngroups / (BIG_RUN BIG_LISTS)) runs of
     // BIG_RUN * SEG_GROUP buckets, and no list exceeds the R/65 buckets that
@@ -1373,12 +1449,13 @@ static void launch_segacc_c(int C, dim3 grid, size_t shm, hipStream_t s, const u
                             const uint32_t* sv, const float* wrec, const float* go,
                             const float* pf, const float* pg,
                             const int2* range, const TileOut& gt, int64_t nb, int64_t R, int n,
-                            uint32_t mask, uint32_t* bc, uint32_t* bl, int64_t cap) {
+                            uint32_t mask, uint32_t* bc, uint32_t* bl, int64_t cap,
+                            const uint32_t* km, const uint32_t* dis) {
     switch (C) {
-    case 1: hipLaunchKernelGGL((k_segacc<1, MODE, G>), grid, dim3(256), shm, s, sk, sv, wrec, go, pf, pg, range, gt, nb, R, n, mask, bc, bl, cap); break;
-    case 2: hipLaunchKernelGGL((k_segacc<2, MODE, G>), grid, dim3(256), shm, s, sk, sv, wrec, go, pf, pg, range, gt, nb, R, n, mask, bc, bl, cap); break;
-    case 3: hipLaunchKernelGGL((k_segacc<3, MODE, G>), grid, dim3(256), shm, s, sk, sv, wrec, go, pf, pg, range, gt, nb, R, n, mask, bc, bl, cap); break;
-    default: hipLaunchKernelGGL((k_segacc<4, MODE, G>), grid, dim3(256), shm, s, sk, sv, wrec, go, pf, pg, range, gt, nb, R, n, mask, bc, bl, cap); break;
+    case 1: hipLaunchKernelGGL((k_segacc<1, MODE, G>), grid, dim3(256), shm, s, sk, sv, wrec, go, pf, pg, range, gt, nb, R, n, mask, bc, bl, cap, km, dis); break;
+    case 2: hipLaunchKernelGGL((k_segacc<2, MODE, G>), grid, dim3(256), shm, s, sk, sv, wrec, go, pf, pg, range, gt, nb, R, n, mask, bc, bl, cap, km, dis); break;
+    case 3: hipLaunchKernelGGL((k_segacc<3, MODE, G>), grid, dim3(256), shm, s, sk, sv, wrec, go, pf, pg, range, gt, nb, R, n, mask, bc, bl, cap, km, dis); break;
+    default: hipLaunchKernelGGL((k_segacc<4, MODE, G>), grid, dim3(256), shm, s, sk, sv, wrec, go, pf, pg, range, gt, nb, R, n, mask, bc, bl, cap, km, dis); break;
     }
 }
 
@@ -1386,12 +1463,13 @@ template <int MODE>
 static void launch_segacc_big_c(int C, dim3 grid, size_t shm, hipStream_t s, const uint32_t* sk,
                                 const uint32_t* sv, const float* wrec, const float* go,
                                 const int2* range, const TileOut& gt, int n, uint32_t mask,
-                                const uint32_t* bc, const uint32_t* bl, int64_t cap) {
+                                const uint32_t* bc, const uint32_t* bl, int64_t cap,
+                                const uint32_t* km, const uint32_t* dis) {
     switch (C) {
-    case 1: hipLaunchKernelGGL((k_segacc_big<1, MODE>), grid, dim3(256), shm, s, sk, sv, wrec, go, range, gt, n, mask, bc, bl, cap); break;
-    case 2: hipLaunchKernelGGL((k_segacc_big<2, MODE>), grid, dim3(256), shm, s, sk, sv, wrec, go, range, gt, n, mask, bc, bl, cap); break;
-    case 3: hipLaunchKernelGGL((k_segacc_big<3, MODE>), grid, dim3(256), shm, s, sk, sv, wrec, go, range, gt, n, mask, bc, bl, cap); break;
-    default: hipLaunchKernelGGL((k_segacc_big<4, MODE>), grid, dim3(256), shm, s, sk, sv, wrec, go, range, gt, n, mask, bc, bl, cap); break;
+    case 1: hipLaunchKernelGGL((k_segacc_big<1, MODE>), grid, dim3(256), shm, s, sk, sv, wrec, go, range, gt, n, mask, bc, bl, cap, km, dis); break;
+    case 2: hipLaunchKernelGGL((k_segacc_big<2, MODE>), grid, dim3(256), shm, s, sk, sv, wrec, go, range, gt, n, mask, bc, bl, cap, km, dis); break;
+    case 3: hipLaunchKernelGGL((k_segacc_big<3, MODE>), grid, dim3(256), shm, s, sk, sv, wrec, go, range, gt, n, mask, bc, bl, cap, km, dis); break;
+    default: hipLaunchKernelGGL((k_segacc_big<4, MODE>), grid, dim3(256), shm, s, sk, sv, wrec, go, range, gt, n, mask, bc, bl, cap, km, dis); break;
     }
 }
 
@@ -1399,12 +1477,12 @@ template <int MODE>
 static void launch_segacc_hot_c(int C, dim3 grid, size_t shm, hipStream_t s, const uint32_t* sk,
                                 const uint32_t* sv, const float* wrec, const float* go,
                                 const int2* range, float* part, int64_t R, int n, int cb,
-                                int64_t nb) {
+                                int64_t nb, const uint32_t* km, const uint32_t* dis) {
     switch (C) {
-    case 1: hipLaunchKernelGGL((k_segacc_hot<1, MODE>), grid, dim3(64), shm, s, sk, sv, wrec, go, range, part, R, n, cb, nb); break;
-    case 2: hipLaunchKernelGGL((k_segacc_hot<2, MODE>), grid, dim3(64), shm, s, sk, sv, wrec, go, range, part, R, n, cb, nb); break;
-    case 3: hipLaunchKernelGGL((k_segacc_hot<3, MODE>), grid, dim3(64), shm, s, sk, sv, wrec, go, range, part, R, n, cb, nb); break;
-    default: hipLaunchKernelGGL((k_segacc_hot<4, MODE>), grid, dim3(64), shm, s, sk, sv, wrec, go, range, part, R, n, cb, nb); break;
+    case 1: hipLaunchKernelGGL((k_segacc_hot<1, MODE>), grid, dim3(64), shm, s, sk, sv, wrec, go, range, part, R, n, cb, nb, km, dis); break;
+    case 2: hipLaunchKernelGGL((k_segacc_hot<2, MODE>), grid, dim3(64), shm, s, sk, sv, wrec, go, range, part, R, n, cb, nb, km, dis); break;
+    case 3: hipLaunchKernelGGL((k_segacc_hot<3, MODE>), grid, dim3(64), shm, s, sk, sv, wrec, go, range, part, R, n, cb, nb, km, dis); break;
+    default: hipLaunchKernelGGL((k_segacc_hot<4, MODE>), grid, dim3(64), shm, s, sk, sv, wrec, go, range, part, R, n, cb, nb, km, dis); break;
     }
 }
 
@@ -1412,12 +1490,12 @@ template <int MODE>
 static void launch_payload_c(int C, dim3 grid, hipStream_t s, const uint32_t* sk,
                              const uint32_t* sv, const float* wrec, const float* go,
                              const int2* range, int64_t R, int cb, int64_t nb, float* pf,
-                             float* pg) {
+                             float* pg, const uint32_t* dis) {
     switch (C) {
-    case 1: hipLaunchKernelGGL((k_payload<1, MODE>), grid, dim3(256), 0, s, sk, sv, wrec, go, range, R, cb, nb, pf, pg); break;
-    case 2: hipLaunchKernelGGL((k_payload<2, MODE>), grid, dim3(256), 0, s, sk, sv, wrec, go, range, R, cb, nb, pf, pg); break;
-    case 3: hipLaunchKernelGGL((k_payload<3, MODE>), grid, dim3(256), 0, s, sk, sv, wrec, go, range, R, cb, nb, pf, pg); break;
-    default: hipLaunchKernelGGL((k_payload<4, MODE>), grid, dim3(256), 0, s, sk, sv, wrec, go, range, R, cb, nb, pf, pg); break;
+    case 1: hipLaunchKernelGGL((k_payload<1, MODE>), grid, dim3(256), 0, s, sk, sv, wrec, go, range, R, cb, nb, pf, pg, dis); break;
+    case 2: hipLaunchKernelGGL((k_payload<2, MODE>), grid, dim3(256), 0, s, sk, sv, wrec, go, range, R, cb, nb, pf, pg, dis); break;
+    case 3: hipLaunchKernelGGL((k_payload<3, MODE>), grid, dim3(256), 0, s, sk, sv, wrec, go, range, R, cb, nb, pf, pg, dis); break;
+    default: hipLaunchKernelGGL((k_payload<4, MODE>), grid, dim3(256), 0, s, sk, sv, wrec, go, range, R, cb, nb, pf, pg, dis); break;
     }
 }
 
@@ -1430,16 +1508,16 @@ static void launch_fill(uint32_t* p, int64_t n, uint32_t v, hipStream_t s) {
 }
 
 static void launch_scan(const uint32_t* in, uint32_t* out, uint32_t* part, int64_t L,
-                        int64_t blocks, hipStream_t s) {
+                        int64_t blocks, hipStream_t s, const uint32_t* skip = nullptr) {
     prof_begin(K_SCAN, s);
-    hipLaunchKernelGGL(k_scan_reduce, dim3((uint32_t)blocks), dim3(256), 0, s, in, L, part);
+    hipLaunchKernelGGL(k_scan_reduce, dim3((uint32_t)blocks), dim3(256), 0, s, in, L, part, skip);
     if (blocks <= SCAN_FUSED_BLOCKS) {
         hipLaunchKernelGGL(k_scan_down<false>, dim3((uint32_t)blocks), dim3(256), 0, s, in, L,
-                           part, out);
+                           part, out, skip);
     } else {
-        hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(256), 0, s, part, blocks);
+        hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(256), 0, s, part, blocks, skip);
         hipLaunchKernelGGL(k_scan_down<true>, dim3((uint32_t)blocks), dim3(256), 0, s, in, L,
-                           part, out);
+                           part, out, skip);
     }
     prof_end(K_SCAN, s);
 }
@@ -1488,54 +1566,85 @@ hipError_t launch_backward(const TexView& t, int fmt, int mode, const float* uv,
     return launch_accumulate(t.n, t.C, mode, grad_out, out, plan, ws, s);
 }
 
-hipError_t launch_accumulate(int n, int C, int mode, const float* grad_out, const TileOut& out,
-                             const BwdPlan& plan, void* ws, hipStream_t s) {
+// The stable sort of the R records' keys in keys0 (record numbers implied by
+// position).  The sorted keys and their record numbers end in *skeys, *svals.
+// disorder: NULL, or the device word k_keys_in_order wrote: when it holds 0
+// every launch returns at once (the keys are already in order).
+void launch_sort_records(const BwdPlan& plan, void* ws, const uint32_t* disorder, hipStream_t s,
+                         const uint32_t** skeys_out, const uint32_t** svals_out) {
     char* wsb = (char*)ws;
     uint32_t* keys0 = (uint32_t*)(wsb + plan.off_keys0);
     uint32_t* keys1 = (uint32_t*)(wsb + plan.off_keys1);
     uint32_t* vals0 = (uint32_t*)(wsb + plan.off_vals0);
     uint32_t* vals1 = (uint32_t*)(wsb + plan.off_vals1);
-    float* wrec = (float*)(wsb + plan.off_wrec);
-    float* payf = (float*)(wsb + plan.off_payf);
-    float* payg = (float*)(wsb + plan.off_payg);
     uint32_t* hist = (uint32_t*)(wsb + plan.off_hist);
     uint32_t* hoff = (uint32_t*)(wsb + plan.off_hoff);
     uint32_t* scanp = (uint32_t*)(wsb + plan.off_scanp);
+    const int64_t R = plan.records;
+    const uint32_t* kin = keys0;
+    const uint32_t* vin = nullptr;
+    for (int pass = 0; pass < plan.passes; pass++) {
+        uint32_t* kout = (pass & 1) ? keys0 : keys1;
+        uint32_t* vout = (pass & 1) ? vals0 : vals1;
+        const int shift = plan.digit_shift[pass];
+        const int D = std::max(8, plan.digit_bits[pass]);
+        const int64_t len = ((int64_t)1 << D) * plan.tiles;
+        const dim3 grid((uint32_t)plan.tiles), block(SORT_THREADS);
+        prof_begin(K_RADIX_HIST, s);
+        if (D == 8) hipLaunchKernelGGL(k_radix_hist<8>, grid, block, 0, s, kin, R, shift, hist, plan.tiles, disorder);
+        else if (D == 9) hipLaunchKernelGGL(k_radix_hist<9>, grid, block, 0, s, kin, R, shift, hist, plan.tiles, disorder);
+        else hipLaunchKernelGGL(k_radix_hist<10>, grid, block, 0, s, kin, R, shift, hist, plan.tiles, disorder);
+        prof_end(K_RADIX_HIST, s);
+        launch_scan(hist, hoff, scanp, len, (len + SCAN_TILE - 1) / SCAN_TILE, s, disorder);
+        prof_begin(K_RADIX_SCATTER, s);
+        if (D == 8) hipLaunchKernelGGL(k_radix_scatter<8>, grid, block, 0, s, kin, vin, kout, vout, R, shift, hoff, plan.tiles, disorder);
+        else if (D == 9) hipLaunchKernelGGL(k_radix_scatter<9>, grid, block, 0, s, kin, vin, kout, vout, R, shift, hoff, plan.tiles, disorder);
+        else hipLaunchKernelGGL(k_radix_scatter<10>, grid, block, 0, s, kin, vin, kout, vout, R, shift, hoff, plan.tiles, disorder);
+        prof_end(K_RADIX_SCATTER, s);
+        kin = kout;
+        vin = vout;
+    }
+    *skeys_out = kin;
+    *svals_out = vin;
+}
+
+// Whether the R keys in keys0 are in order: the workspace's disorder word
+// is cleared, then set by any descent.
+static uint32_t* launch_order_check(const BwdPlan& plan, void* ws, hipStream_t s) {
+    char* wsb = (char*)ws;
+    const uint32_t* keys0 = (const uint32_t*)(wsb + plan.off_keys0);
+    uint32_t* disorder = (uint32_t*)(wsb + plan.off_disorder);
+    const int64_t R = plan.records;
+    launch_fill(disorder, 1, 0u, s);
+    if (R > 1) {
+        prof_begin(K_ORDER_CHECK, s);
+        hipLaunchKernelGGL(k_keys_in_order, dim3((uint32_t)((R + 1023) / 1024)), dim3(256), 0, s,
+                           keys0, R, disorder);
+        prof_end(K_ORDER_CHECK, s);
+    }
+    return disorder;
+}
+
+hipError_t launch_accumulate(int n, int C, int mode, const float* grad_out, const TileOut& out,
+                             const BwdPlan& plan, void* ws, hipStream_t s) {
+    char* wsb = (char*)ws;
+    uint32_t* keys0 = (uint32_t*)(wsb + plan.off_keys0);
+    float* wrec = (float*)(wsb + plan.off_wrec);
+    float* payf = (float*)(wsb + plan.off_payf);
+    float* payg = (float*)(wsb + plan.off_payg);
     uint32_t* big_count = (uint32_t*)(wsb + plan.off_range);  // BIG_LISTS counters
     int2* range = (int2*)(big_count + BIG_LISTS * BIG_STRIDE);
     uint32_t* big_list = (uint32_t*)(wsb + plan.off_biglist);
     float* part = (float*)(wsb + plan.off_part);
     const int64_t R = plan.records;
 
-    // 2. sort
+    // 2. sort, skipped on the device when the records were made in key order
     const uint32_t* skeys = keys0;
     const uint32_t* svals = nullptr;
+    const uint32_t* dis = nullptr;
     if (R > 0) {
-        const uint32_t* kin = keys0;
-        const uint32_t* vin = nullptr;
-        for (int pass = 0; pass < plan.passes; pass++) {
-            uint32_t* kout = (pass & 1) ? keys0 : keys1;
-            uint32_t* vout = (pass & 1) ? vals0 : vals1;
-            const int shift = plan.digit_shift[pass];
-            const int D = std::max(8, plan.digit_bits[pass]);
-            const int64_t len = ((int64_t)1 << D) * plan.tiles;
-            const dim3 grid((uint32_t)plan.tiles), block(SORT_THREADS);
-            prof_begin(K_RADIX_HIST, s);
-            if (D == 8) hipLaunchKernelGGL(k_radix_hist<8>, grid, block, 0, s, kin, R, shift, hist, plan.tiles);
-            else if (D == 9) hipLaunchKernelGGL(k_radix_hist<9>, grid, block, 0, s, kin, R, shift, hist, plan.tiles);
-            else hipLaunchKernelGGL(k_radix_hist<10>, grid, block, 0, s, kin, R, shift, hist, plan.tiles);
-            prof_end(K_RADIX_HIST, s);
-            launch_scan(hist, hoff, scanp, len, (len + SCAN_TILE - 1) / SCAN_TILE, s);
-            prof_begin(K_RADIX_SCATTER, s);
-            if (D == 8) hipLaunchKernelGGL(k_radix_scatter<8>, grid, block, 0, s, kin, vin, kout, vout, R, shift, hoff, plan.tiles);
-            else if (D == 9) hipLaunchKernelGGL(k_radix_scatter<9>, grid, block, 0, s, kin, vin, kout, vout, R, shift, hoff, plan.tiles);
-            else hipLaunchKernelGGL(k_radix_scatter<10>, grid, block, 0, s, kin, vin, kout, vout, R, shift, hoff, plan.tiles);
-            prof_end(K_RADIX_SCATTER, s);
-            kin = kout;
-            vin = vout;
-        }
-        skeys = kin;
-        svals = vin;
+        dis = launch_order_check(plan, ws, s);
+        launch_sort_records(plan, ws, dis, s, &skeys, &svals);
     }
 
     // 3. ranges
@@ -1544,19 +1653,19 @@ hipError_t launch_accumulate(int n, int C, int mode, const float* grad_out, cons
     if (R > 0) {
         prof_begin(K_BUCKET_RANGES, s);
         hipLaunchKernelGGL(k_bucket_ranges, dim3((uint32_t)((R + 1023) / 1024)), dim3(256), 0, s,
-                           skeys, R, plan.cell_bits, nb, range);
+                           skeys, R, plan.cell_bits, nb, range, keys0, dis);
         prof_end(K_BUCKET_RANGES, s);
     }
 
     // 4. the records' payload in sorted order (when buckets hold 64 records or
-    // fewer on average: most records then go through the register window),
-    // then pass 1 over buckets
+    // fewer on average: most records then go through the register window;
+    // not written when the records came in order), then pass 1 over buckets
     const bool pay = R > 0 && R <= 64 * nb;
     if (pay) {
         const dim3 gp((uint32_t)((R + 255) / 256));
         prof_begin(K_PAYLOAD, s);
-        if (mode == MODE_NEAREST) launch_payload_c<MODE_NEAREST>(C, gp, s, skeys, svals, wrec, grad_out, range, R, plan.cell_bits, nb, payf, payg);
-        else launch_payload_c<MODE_BILINEAR>(C, gp, s, skeys, svals, wrec, grad_out, range, R, plan.cell_bits, nb, payf, payg);
+        if (mode == MODE_NEAREST) launch_payload_c<MODE_NEAREST>(C, gp, s, skeys, svals, wrec, grad_out, range, R, plan.cell_bits, nb, payf, payg, dis);
+        else launch_payload_c<MODE_BILINEAR>(C, gp, s, skeys, svals, wrec, grad_out, range, R, plan.cell_bits, nb, payf, payg, dis);
         prof_end(K_PAYLOAD, s);
     }
     const int te = (int)plan.tile_elems;
@@ -1571,11 +1680,11 @@ hipError_t launch_accumulate(int n, int C, int mode, const float* grad_out, cons
     const float* pf = pay ? payf : nullptr;
     prof_begin(K_SEGACC, s);
     if (mode == MODE_NEAREST) {
-        if (pay) launch_segacc_c<MODE_NEAREST, 4>(C, g1, (size_t)4 * te * 4, s, skeys, svals, wrec, grad_out, pf, payg, range, out, nb, R, n, cell_mask, big_count, big_list, plan.big_cap);
-        else launch_segacc_c<MODE_NEAREST, SEG_GROUP>(C, g1, (size_t)4 * te * 4, s, skeys, svals, wrec, grad_out, pf, payg, range, out, nb, R, n, cell_mask, big_count, big_list, plan.big_cap);
+        if (pay) launch_segacc_c<MODE_NEAREST, 4>(C, g1, (size_t)4 * te * 4, s, skeys, svals, wrec, grad_out, pf, payg, range, out, nb, R, n, cell_mask, big_count, big_list, plan.big_cap, keys0, dis);
+        else launch_segacc_c<MODE_NEAREST, SEG_GROUP>(C, g1, (size_t)4 * te * 4, s, skeys, svals, wrec, grad_out, pf, payg, range, out, nb, R, n, cell_mask, big_count, big_list, plan.big_cap, keys0, dis);
     } else {
-        if (pay) launch_segacc_c<MODE_BILINEAR, 4>(C, g1, (size_t)4 * te * 4, s, skeys, svals, wrec, grad_out, pf, payg, range, out, nb, R, n, cell_mask, big_count, big_list, plan.big_cap);
-        else launch_segacc_c<MODE_BILINEAR, SEG_GROUP>(C, g1, (size_t)4 * te * 4, s, skeys, svals, wrec, grad_out, pf, payg, range, out, nb, R, n, cell_mask, big_count, big_list, plan.big_cap);
+        if (pay) launch_segacc_c<MODE_BILINEAR, 4>(C, g1, (size_t)4 * te * 4, s, skeys, svals, wrec, grad_out, pf, payg, range, out, nb, R, n, cell_mask, big_count, big_list, plan.big_cap, keys0, dis);
+        else launch_segacc_c<MODE_BILINEAR, SEG_GROUP>(C, g1, (size_t)4 * te * 4, s, skeys, svals, wrec, grad_out, pf, payg, range, out, nb, R, n, cell_mask, big_count, big_list, plan.big_cap, keys0, dis);
     }
     prof_end(K_SEGACC, s);
     if (R > 64) {
@@ -1586,9 +1695,9 @@ hipError_t launch_accumulate(int n, int C, int mode, const float* grad_out, cons
         const dim3 g2((uint32_t)(BIG_LISTS * parts));
         prof_begin(K_SEGACC_BIG, s);
         if (mode == MODE_NEAREST)
-            launch_segacc_big_c<MODE_NEAREST>(C, g2, (size_t)4 * te * 4, s, skeys, svals, wrec, grad_out, range, out, n, cell_mask, big_count, big_list, plan.big_cap);
+            launch_segacc_big_c<MODE_NEAREST>(C, g2, (size_t)4 * te * 4, s, skeys, svals, wrec, grad_out, range, out, n, cell_mask, big_count, big_list, plan.big_cap, keys0, dis);
         else
-            launch_segacc_big_c<MODE_BILINEAR>(C, g2, (size_t)4 * te * 4, s, skeys, svals, wrec, grad_out, range, out, n, cell_mask, big_count, big_list, plan.big_cap);
+            launch_segacc_big_c<MODE_BILINEAR>(C, g2, (size_t)4 * te * 4, s, skeys, svals, wrec, grad_out, range, out, n, cell_mask, big_count, big_list, plan.big_cap, keys0, dis);
         prof_end(K_SEGACC_BIG, s);
     }
 
@@ -1597,18 +1706,99 @@ hipError_t launch_accumulate(int n, int C, int mode, const float* grad_out, cons
         const dim3 g2((uint32_t)plan.chunks);
         prof_begin(K_SEGACC_HOT, s);
         if (mode == MODE_NEAREST)
-            launch_segacc_hot_c<MODE_NEAREST>(C, g2, (size_t)te * 4, s, skeys, svals, wrec, grad_out, range, part, R, n, plan.cell_bits, nb);
+            launch_segacc_hot_c<MODE_NEAREST>(C, g2, (size_t)te * 4, s, skeys, svals, wrec, grad_out, range, part, R, n, plan.cell_bits, nb, keys0, dis);
         else
-            launch_segacc_hot_c<MODE_BILINEAR>(C, g2, (size_t)te * 4, s, skeys, svals, wrec, grad_out, range, part, R, n, plan.cell_bits, nb);
+            launch_segacc_hot_c<MODE_BILINEAR>(C, g2, (size_t)te * 4, s, skeys, svals, wrec, grad_out, range, part, R, n, plan.cell_bits, nb, keys0, dis);
         prof_end(K_SEGACC_HOT, s);
         prof_begin(K_COMBINE_HOT, s);
         hipLaunchKernelGGL(k_combine_hot, g2, dim3(64), 0, s, skeys, range, part, out, R, te,
-                           plan.cell_bits, nb);
+                           plan.cell_bits, nb, keys0, dis);
         prof_end(K_COMBINE_HOT, s);
     }
     return hipGetLastError();
 }
 
+
+// ---------------------------------------------------------------------------
+// visit plan
+// ---------------------------------------------------------------------------
+
+// The record key of each fragment as k_bwd_fragment makes it in the nearest
+// mode (bucket << cell_bits | cell of its footprint); in the bilinear-bucket
+// mode the key of its first bucket (i0, j0) with its cell.
+template <int MODE>
+__global__ __launch_bounds__(256) void k_plan_keys(int W, int H, int n,
+                                                   const float* __restrict__ uv,
+                                                   const float* __restrict__ tbn,
+                                                   const float* __restrict__ view,
+                                                   uint32_t* __restrict__ keys, FragMap m,
+                                                   int cell_bits) {
+    const int64_t f = frag_of(m, blockIdx.x, gridDim.x, threadIdx.x);
+    if (f < 0) return;
+    const Frag g = load_frag(uv, tbn, view, f);
+    const Dir d = map_direction(g.m, g.w, n);
+    const Foot p = footprint(d.sx, d.sy, n);
+    int64_t b;
+    if constexpr (MODE == MODE_NEAREST) {
+        const int i = bucket_of(g.u, W), j = bucket_of(g.v, H);
+        b = (int64_t)j * W + i;
+    } else {
+        int i0, i1, j0, j1;
+        float a, bb;
+        bucket_pair(g.u, W, i0, i1, a);
+        bucket_pair(g.v, H, j0, j1, bb);
+        b = (int64_t)j0 * W + i0;
+    }
+    keys[f] = ((uint32_t)b << cell_bits) | (uint32_t)(p.y0 * n + p.x0);
+}
+
+// Planned fragment k is the caller's fragment svals[k] (k itself when the
+// keys came in order): its index and its 56-byte record are copied.
+__global__ __launch_bounds__(256) void k_plan_gather(const uint32_t* __restrict__ svals,
+                                                     int64_t N, const float* __restrict__ uv,
+                                                     const float* __restrict__ tbn,
+                                                     const float* __restrict__ view,
+                                                     int32_t* __restrict__ order,
+                                                     float* __restrict__ uv_out,
+                                                     float* __restrict__ tbn_out,
+                                                     float* __restrict__ view_out,
+                                                     const uint32_t* __restrict__ disorder) {
+    if (sort_skipped(disorder)) svals = nullptr;
+    const int64_t k = (int64_t)xcd_block_id(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
+    if (k >= N) return;
+    const int64_t f = svals ? (int64_t)svals[k] : k;
+    order[k] = (int32_t)f;
+    ((float2*)uv_out)[k] = ((const float2*)uv)[f];
+#pragma unroll
+    for (int q = 0; q < 9; q++) tbn_out[k * 9 + q] = tbn[f * 9 + q];
+#pragma unroll
+    for (int q = 0; q < 3; q++) view_out[k * 3 + q] = view[f * 3 + q];
+}
+
+hipError_t launch_plan(const TexView& t, int mode, const float* uv, const float* tbn,
+                       const float* view, const FragMap& m, const BwdPlan& plan, void* ws,
+                       int32_t* order, float* uv_out, float* tbn_out, float* view_out,
+                       hipStream_t s) {
+    const int64_t N = m.N;
+    if (N <= 0) return hipSuccess;
+    uint32_t* keys0 = (uint32_t*)((char*)ws + plan.off_keys0);
+    prof_begin(K_PLAN_KEYS, s);
+    if (mode == MODE_NEAREST)
+        hipLaunchKernelGGL(k_plan_keys<MODE_NEAREST>, dim3(fragmap_blocks(m)), dim3(256), 0, s,
+                           t.W, t.H, t.n, uv, tbn, view, keys0, m, plan.cell_bits);
+    else
+        hipLaunchKernelGGL(k_plan_keys<MODE_BILINEAR>, dim3(fragmap_blocks(m)), dim3(256), 0, s,
+                           t.W, t.H, t.n, uv, tbn, view, keys0, m, plan.cell_bits);
+    prof_end(K_PLAN_KEYS, s);
+    const uint32_t* dis = launch_order_check(plan, ws, s);
+    const uint32_t *skeys = nullptr, *svals = nullptr;
+    launch_sort_records(plan, ws, dis, s, &skeys, &svals);
+    prof_begin(K_PLAN_GATHER, s);
+    hipLaunchKernelGGL(k_plan_gather, dim3((uint32_t)((N + 255) / 256)), dim3(256), 0, s, svals,
+                       N, uv, tbn, view, order, uv_out, tbn_out, view_out, dis);
+    prof_end(K_PLAN_GATHER, s);
+    return hipGetLastError();
+}
 
 template <int FMT, int MODE>
 static void launch_lod_frag_c(int C, dim3 grid, hipStream_t s, const LevelSet& ls,

@@ -240,7 +240,12 @@ struct Dir {
     float k;             // 1 / sqrt(L (L + u_z))
 };
 
+// The mapping is evaluated with one rounding per operation (no fused
+// multiply-adds), so that every kernel that maps a fragment -- the lookups,
+// the backward, the visit plan -- computes the same sample coordinate and the
+// same footprint for it, whatever the surrounding code lets the compiler fuse.
 __device__ __forceinline__ Dir map_direction(const float m[9], const float w[3], int n) {
+#pragma clang fp contract(off)
     Dir d;
     d.ux = m[0] * w[0] + m[1] * w[1] + m[2] * w[2];
     d.uy = m[3] * w[0] + m[4] * w[1] + m[5] * w[2];
@@ -274,6 +279,7 @@ struct Foot {
 };
 
 __device__ __forceinline__ Foot footprint(float sx, float sy, int n) {
+#pragma clang fp contract(off)
     Foot p;
     int hi = n >= 2 ? n - 2 : 0;
     p.x0 = min((int)sx, hi);

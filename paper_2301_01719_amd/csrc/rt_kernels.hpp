@@ -44,6 +44,9 @@ enum KernelId {
     K_LOD_BWD_FRAGMENT,
     K_MIP_ADJOINT,
     K_PAYLOAD,
+    K_ORDER_CHECK,
+    K_PLAN_KEYS,
+    K_PLAN_GATHER,
     K_COUNT
 };
 const char* kernel_name(int id);
@@ -119,9 +122,11 @@ struct BwdPlan {
     int64_t buckets;      // W * H
     uint32_t sentinel;    // sparse plans: the key of a fragment whose upstream
                           // gradient is zero (past every bucket); 0 otherwise
-    // workspace offsets (bytes)
-    size_t off_keys0, off_keys1, off_vals0, off_vals1, off_wrec, off_payf, off_payg, off_hist,
-        off_hoff, off_scanp, off_range, off_biglist, off_part, total;
+    // workspace offsets (bytes); the sort's buffers and the disorder word
+    // come first and end at sort_total
+    size_t off_keys0, off_keys1, off_vals0, off_vals1, off_hist, off_hoff, off_scanp,
+        off_disorder, sort_total, off_wrec, off_payf, off_payg, off_range, off_biglist,
+        off_part, total;
 };
 constexpr int PIECE = 2048;  // records per chunk; buckets with more are "hot"
 constexpr int SEG_GROUP = 8;  // buckets per wavefront in the first accumulation pass
@@ -194,6 +199,21 @@ hipError_t launch_vq_assign(const float* x, int64_t M, int D, const float* codeb
                             int32_t* assign, float* dist, hipStream_t s);
 hipError_t launch_vq_update(const float* x, const int32_t* assign, float* codebook,
                             int32_t* counts, const VqPlan& plan, void* ws, hipStream_t s);
+
+// The stable sort of a plan's records (keys in the workspace's keys0); with
+// disorder non-NULL its launches return at once when that device word is 0.
+void launch_sort_records(const BwdPlan& plan, void* ws, const uint32_t* disorder, hipStream_t s,
+                         const uint32_t** skeys, const uint32_t** svals);
+
+// Visit plan: the fragments ordered by their nearest-mode record key (or the
+// key of their first bucket in the bilinear-bucket mode), stable in the
+// fragment index; writes order[k] (the caller's index of planned fragment k)
+// and the planned G-buffer.  plan: plan_backward(W, H, n, 1, N, MODE_NEAREST);
+// the workspace needs plan.sort_total bytes.
+hipError_t launch_plan(const TexView& t, int mode, const float* uv, const float* tbn,
+                       const float* view, const FragMap& m, const BwdPlan& plan, void* ws,
+                       int32_t* order, float* uv_out, float* tbn_out, float* view_out,
+                       hipStream_t s);
 
 hipError_t launch_backward(const TexView& t, int fmt, int mode, const float* uv,
                            const float* tbn, const float* view, const float* grad_out,

@@ -14,9 +14,7 @@ from typing import Optional
 import torch
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-# RADTEX_LIBRARY selects another build of the same library (for comparing
-# kernel variants); by default the in-tree build is loaded.
-LIB_PATH = os.environ.get("RADTEX_LIBRARY", os.path.join(HERE, "libradtex.so"))
+LIB_PATH = os.path.join(HERE, "libradtex.so")
 
 RT_OK = 0
 RT_FMT_F32, RT_FMT_BF16, RT_FMT_FP8_E4M3, RT_FMT_BIT1 = 0, 1, 2, 3
@@ -43,7 +41,8 @@ EXPORTS = ("rt_create_texture", "rt_destroy_texture", "rt_quantize", "rt_lookup_
            "rt_bake_directions", "rt_bake_environment", "rt_build_mip", "rt_lookup_fwd_lod",
            "rt_lookup_light", "rt_bake_shadow", "rt_create_dictionary_texture",
            "rt_vq_assign", "rt_vq_update_workspace", "rt_vq_update",
-           "rt_lookup_lod_bwd_workspace", "rt_lookup_lod_bwd", "rt_build_mip_adjoint")
+           "rt_lookup_lod_bwd_workspace", "rt_lookup_lod_bwd", "rt_build_mip_adjoint",
+           "rt_plan_workspace", "rt_plan_fragments")
 
 
 class RadtexError(RuntimeError):
@@ -99,6 +98,8 @@ def _load() -> ctypes.CDLL:
         "rt_lookup_bwd_workspace": ([P, i64, u32], sz),
         "rt_lookup_bwd": ([P, ctypes.POINTER(Fragments), P, P, P, P, P, sz, u32, P], i32),
         "rt_debug_indices": ([P, ctypes.POINTER(Fragments), P, P, P], i32),
+        "rt_plan_workspace": ([P, i64, u32], sz),
+        "rt_plan_fragments": ([P, ctypes.POINTER(Fragments), u32, P, P, P, P, P, sz, P], i32),
         "rt_last_error": ([], ctypes.c_char_p),
         "rt_status_string": ([i32], ctypes.c_char_p),
         "rt_version": ([], i32),
@@ -335,6 +336,33 @@ def lookup_bwd(tex: Texture, uv, tbn, view, grad_out, mode: str = "nearest", wan
                              _ptr(gu), _ptr(workspace) if want_tex else None,
                              ws_bytes if want_tex else 0, MODES[mode], _stream(dev)))
     return gt, gv, gu
+
+
+def plan_workspace_bytes(tex: Texture, count: int, mode: str = "nearest") -> int:
+    return int(LIB.rt_plan_workspace(tex.handle, int(count), MODES[mode]))
+
+
+def plan_fragments(tex: Texture, uv, tbn, view, mode: str = "nearest", image=None,
+                   workspace: Optional[torch.Tensor] = None, out=None):
+    """Visit plan (rt_plan_fragments): returns (order [N] int32, uv, tbn, view)
+    with the G-buffer in plan order; planned fragment k is the caller's
+    fragment order[k].  out = (order, uv, tbn, view) preallocated, or None."""
+    fr = _frags(uv, tbn, view, image)
+    dev = tex.device
+    N = fr.count
+    if out is None:
+        out = (torch.empty(N, dtype=torch.int32, device=dev),
+               torch.empty((N, 2), dtype=torch.float32, device=dev),
+               torch.empty((N, 3, 3), dtype=torch.float32, device=dev),
+               torch.empty((N, 3), dtype=torch.float32, device=dev))
+    order, puv, ptbn, pview = out
+    ws_bytes = plan_workspace_bytes(tex, N, mode)
+    if workspace is None or workspace.numel() < ws_bytes:
+        workspace = torch.empty(max(ws_bytes, 256), dtype=torch.uint8, device=dev)
+    _check(LIB.rt_plan_fragments(tex.handle, ctypes.byref(fr), MODES[mode], _ptr(order),
+                                 _ptr(puv), _ptr(ptbn), _ptr(pview), _ptr(workspace),
+                                 ws_bytes, _stream(dev)))
+    return order, puv, ptbn, pview
 
 
 def debug_indices(tex: Texture, uv, tbn, view, image=None):

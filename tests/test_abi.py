@@ -30,7 +30,7 @@ def test_header_declares_the_boundary():
     names = _declared()
     for required in ("rt_create_texture", "rt_destroy_texture", "rt_quantize", "rt_lookup_fwd",
                      "rt_lookup_bwd", "rt_lookup_bwd_workspace", "rt_debug_indices",
-                     "rt_last_error"):
+                     "rt_last_error", "rt_plan_workspace", "rt_plan_fragments"):
         assert required in names
 
 
@@ -42,7 +42,7 @@ def test_library_exports_every_declared_symbol(rt):
 
 
 def test_version_and_status_strings(rt):
-    assert rt.LIB.rt_version() == 100
+    assert rt.LIB.rt_version() == 200
     assert rt.LIB.rt_status_string(0) == b"RT_OK"
     assert rt.LIB.rt_status_string(4) == b"RT_ERR_WORKSPACE_TOO_SMALL"
     assert rt.LIB.rt_profile_kernel_count() >= 10
@@ -97,6 +97,10 @@ def test_null_arguments(rt):
     assert rt.LIB.rt_lookup_bwd(None, ctypes.byref(fr), 0x1000, 0x2000, None, None, 0x3000, 1 << 20,
                                 0, None) == 1
     assert rt.LIB.rt_lookup_bwd_workspace(None, 10, 0) == 0
+    assert rt.LIB.rt_plan_fragments(None, ctypes.byref(fr), 0, 0x1000, 0x2000, 0x3000, 0x4000,
+                                    0x5000, 1 << 20, None) == 1
+    assert "texture handle" in rt.LIB.rt_last_error().decode()
+    assert rt.LIB.rt_plan_workspace(None, 10, 0) == 0
     assert rt.LIB.rt_destroy_texture(None) == 0
 
 
