@@ -31,6 +31,7 @@ def _load():
     P = ctypes.c_void_p
     i64, i32, d = ctypes.c_int64, ctypes.c_int, ctypes.c_double
     lib.orc_num_threads.restype = i32
+    lib.orc_set_num_threads.argtypes = [i32]
     lib.orc_bf16_to_f64.argtypes = [ctypes.c_uint16]
     lib.orc_bf16_to_f64.restype = d
     lib.orc_e4m3_to_f64.argtypes = [ctypes.c_uint8]
@@ -87,6 +88,11 @@ def _c(a, dtype):
 
 def num_threads() -> int:
     return _load().orc_num_threads()
+
+
+def set_num_threads(k: int) -> None:
+    """Threads of the oracle's parallel loops from here on."""
+    _load().orc_set_num_threads(int(k))
 
 
 # --- scalar conversions ----------------------------------------------------
@@ -261,14 +267,15 @@ def indices(uv, tbn, view, W, H, n):
 
 
 def lookup_bwd(tex: Tex, uv, tbn, view, g, mode=MODE_NEAREST, want_tex=True, window=None,
-               want_view=True, want_uv=True):
+               want_view=True, want_uv=True, want_abs=True):
     """Analytic backward in binary64.
 
     window = (bi0, bj0, bw, bh) restricts grad_tex to that bucket rectangle
     (default: the whole matrix).  Returns dict with grad_tex [bh,bw,n,n,C],
     abs_tex (sum of |w g|), absg_tex (sum of |g| over the taps touching the
-    element), grad_view [N,3], grad_uv [N,2], and scale_view / scale_uv (the
-    chain rule evaluated with magnitudes); entries are None when not asked.
+    element; both left out with want_abs=False), grad_view [N,3], grad_uv
+    [N,2], and scale_view / scale_uv (the chain rule evaluated with
+    magnitudes); entries are None when not asked.
     """
     uv, tbn, view = _frags(uv, tbn, view)
     g = _c(g, np.float32).reshape(-1, tex.C)
@@ -280,8 +287,9 @@ def lookup_bwd(tex: Tex, uv, tbn, view, g, mode=MODE_NEAREST, want_tex=True, win
     gt = at = ag = gv = gu = sv = su = None
     if want_tex:
         gt = np.empty((bh, bw, tex.n, tex.n, tex.C), np.float64)
-        at = np.empty_like(gt)
-        ag = np.empty_like(gt)
+        if want_abs:
+            at = np.empty_like(gt)
+            ag = np.empty_like(gt)
     if want_view:
         gv = np.empty((N, 3), np.float64)
         sv = np.empty((N, 3), np.float64)

@@ -75,6 +75,16 @@ int orc_num_threads(void)
 #endif
 }
 
+/* Threads of the parallel loops from here on (at least 1). */
+void orc_set_num_threads(int k)
+{
+#ifdef _OPENMP
+    omp_set_num_threads(k > 0 ? k : 1);
+#else
+    (void)k;
+#endif
+}
+
 /* ------------------------------------------------------------------------ */
 /* Storage formats (the quantised storage is an addition to the paper, which  */
 /* only says buckets compress well; see the abstract and Sec. 2).             */
