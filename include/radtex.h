@@ -280,6 +280,20 @@ rt_status rt_plan_fragments(const rt_texture* tex, const rt_fragments* frags, ui
                             int32_t* order, float* uv_out, float* tbn_out, float* view_out,
                             void* workspace, size_t workspace_bytes, void* stream);
 
+/* Moves the rows of a per-fragment array by a plan's order: with
+ * RT_PLAN_GATHER dst[k] = src[order[k]] (the caller's data into plan order:
+ * targets, weights, an upstream gradient), with RT_PLAN_SCATTER
+ * dst[order[k]] = src[k] (plan-order results back to the caller's order).
+ * order: DEVICE int32 [count], a permutation of 0..count-1 (as written by
+ * rt_plan_fragments; other values give undefined results).  src, dst: DEVICE
+ * arrays of count rows of row_bytes bytes (a multiple of 4, at most 4096),
+ * 4-byte aligned (16-byte rows and alignment take 16-byte accesses), not
+ * overlapping.  Asynchronous on `stream`.
+ * Errors: RT_ERR_INVALID_ARG (NULL, alignment, sizes, overlap). */
+enum { RT_PLAN_GATHER = 0, RT_PLAN_SCATTER = 1 };
+rt_status rt_plan_permute(const int32_t* order, int64_t count, int32_t row_bytes,
+                          const void* src, void* dst, uint32_t direction, void* stream);
+
 /* Per-fragment indices of the nearest-bucket lookup, for exact checks:
  * idx int32 [N][4] = (i, j, x0, y0) with x0 = floor(s_x) in [0, n-1], and
  * frac float [N][2] = (s_x - x0, s_y - y0).  Same arithmetic as the lookup. */

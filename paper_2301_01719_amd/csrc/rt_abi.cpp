@@ -146,7 +146,7 @@ const char* kernel_name(int id) {
         "k_lookup_light", "k_bake_shadow",   "k_vq_assign",     "k_vq_hist",
         "k_vq_scatter",   "k_vq_pieces",     "k_vq_combine",    "k_lod_bwd_fragment",
         "k_mip_adjoint",  "k_payload",       "k_keys_in_order", "k_plan_keys",
-        "k_plan_gather"};
+        "k_plan_gather",  "k_permute_rows"};
     return (id >= 0 && id < K_COUNT) ? names[id] : "";
 }
 
@@ -384,10 +384,12 @@ size_t rt_lookup_bwd_workspace(const rt_texture* t, int64_t count, uint32_t flag
     }
 }
 
-rt_status rt_lookup_bwd(const rt_texture* t, const rt_fragments* f, const float* grad_out,
-                        float* grad_tex, float* grad_view, float* grad_uv, void* ws,
-                        size_t ws_bytes, uint32_t flags, void* stream) {
-    RT_GUARD_BEGIN
+namespace {
+// The arguments of the backward, checked before anything is enqueued; *plan
+// receives the backward's plan.
+rt_status check_bwd(const rt_texture* t, const rt_fragments* f, const float* grad_out,
+                    const float* grad_tex, const float* grad_view, const float* grad_uv,
+                    uint32_t flags, rt::BwdPlan* plan) {
     rt_status st = check_tex(t);
     if (st != RT_OK) return st;
     st = check_frags(f);
@@ -406,9 +408,19 @@ rt_status rt_lookup_bwd(const rt_texture* t, const rt_fragments* f, const float*
     if (grad_tex && !aligned(grad_tex, 16)) return fail(RT_ERR_INVALID_ARG, "grad_tex must be 16-byte aligned");
     if (grad_view && !aligned(grad_view, 4)) return fail(RT_ERR_INVALID_ARG, "grad_view must be 4-byte aligned");
     if (grad_uv && !aligned(grad_uv, 8)) return fail(RT_ERR_INVALID_ARG, "grad_uv must be 8-byte aligned");
-    rt::BwdPlan plan;
-    if (!rt::plan_backward(t->view.W, t->view.H, t->view.n, C, f->count, (int)flags, &plan))
+    if (!rt::plan_backward(t->view.W, t->view.H, t->view.n, C, f->count, (int)flags, plan))
         return fail(RT_ERR_UNSUPPORTED, "sort key (W*H*n*n), bucket size (n*n*C <= 4096) or record count beyond the backward's limits");
+    return RT_OK;
+}
+}  // namespace
+
+rt_status rt_lookup_bwd(const rt_texture* t, const rt_fragments* f, const float* grad_out,
+                        float* grad_tex, float* grad_view, float* grad_uv, void* ws,
+                        size_t ws_bytes, uint32_t flags, void* stream) {
+    RT_GUARD_BEGIN
+    rt::BwdPlan plan;
+    rt_status st = check_bwd(t, f, grad_out, grad_tex, grad_view, grad_uv, flags, &plan);
+    if (st != RT_OK) return st;
     if (!grad_tex && !grad_view && !grad_uv) return ok();  // nothing requested
     if (grad_tex) {
         if (!ws) return fail(RT_ERR_INVALID_ARG, "workspace is NULL");
@@ -482,6 +494,29 @@ rt_status rt_plan_fragments(const rt_texture* t, const rt_fragments* f, uint32_t
     hipError_t e = rt::launch_plan(t->view, (int)flags, f->uv, f->tbn, f->view, fragmap(f), plan,
                                    ws, order, uv_out, tbn_out, view_out, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "plan launch");
+    return ok();
+    RT_GUARD_END
+}
+
+rt_status rt_plan_permute(const int32_t* order, int64_t count, int32_t row_bytes,
+                          const void* src, void* dst, uint32_t direction, void* stream) {
+    RT_GUARD_BEGIN
+    if (count < 0 || count >= (1ll << 31))
+        return fail(RT_ERR_INVALID_ARG, "count %lld outside [0, 2^31)", (long long)count);
+    if (direction > RT_PLAN_SCATTER) return fail(RT_ERR_INVALID_ARG, "unknown direction %u", direction);
+    if (row_bytes <= 0 || row_bytes % 4 != 0 || row_bytes > 4096)
+        return fail(RT_ERR_INVALID_ARG, "row_bytes %d: a multiple of 4 in 4..4096", row_bytes);
+    if (count == 0) return ok();
+    if (!order || !src || !dst) return fail(RT_ERR_INVALID_ARG, "order, src and dst must be non-NULL");
+    if (!aligned(order, 4) || !aligned(src, 4) || !aligned(dst, 4))
+        return fail(RT_ERR_INVALID_ARG, "order, src and dst must be 4-byte aligned");
+    const size_t bytes = (size_t)count * (size_t)row_bytes;
+    const uintptr_t a = (uintptr_t)src, b = (uintptr_t)dst;
+    if (a < b + bytes && b < a + bytes)
+        return fail(RT_ERR_INVALID_ARG, "src and dst must not overlap");
+    hipError_t e = rt::launch_permute_rows(order, count, row_bytes / 4, src, dst,
+                                           direction == RT_PLAN_SCATTER, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "permute launch");
     return ok();
     RT_GUARD_END
 }

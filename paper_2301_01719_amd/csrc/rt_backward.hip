@@ -1775,6 +1775,45 @@ __global__ __launch_bounds__(256) void k_plan_gather(const uint32_t* __restrict_
     for (int q = 0; q < 3; q++) view_out[k * 3 + q] = view[f * 3 + q];
 }
 
+// Rows of a per-fragment array moved by a plan's order: gather (dst[k] =
+// src[order[k]], into plan order) or scatter (dst[order[k]] = src[k], back to
+// the caller's order).  Rows of `row` 4-byte words; 16-byte accesses when the
+// row is a whole number of them and both arrays are 16-byte aligned.
+template <bool VEC>
+__global__ __launch_bounds__(256) void k_permute_rows(const int32_t* __restrict__ order,
+                                                      int64_t N, int row,
+                                                      const uint32_t* __restrict__ src,
+                                                      uint32_t* __restrict__ dst, int scatter) {
+    const int64_t k = (int64_t)xcd_block_id(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
+    if (k >= N) return;
+    const int64_t o = order[k];
+    const int64_t from = scatter ? k : o, to = scatter ? o : k;
+    if constexpr (VEC) {
+        const int q = row / 4;
+        const uint4* s4 = (const uint4*)src + from * q;
+        uint4* d4 = (uint4*)dst + to * q;
+        for (int i = 0; i < q; i++) d4[i] = s4[i];
+    } else {
+        for (int i = 0; i < row; i++) dst[to * row + i] = src[from * row + i];
+    }
+}
+
+hipError_t launch_permute_rows(const int32_t* order, int64_t N, int row_words, const void* src,
+                               void* dst, bool scatter, hipStream_t s) {
+    if (N <= 0) return hipSuccess;
+    const bool vec = row_words % 4 == 0 && ((uintptr_t)src % 16) == 0 && ((uintptr_t)dst % 16) == 0;
+    const dim3 grid((uint32_t)((N + 255) / 256));
+    prof_begin(K_PERMUTE, s);
+    if (vec)
+        hipLaunchKernelGGL(k_permute_rows<true>, grid, dim3(256), 0, s, order, N, row_words,
+                           (const uint32_t*)src, (uint32_t*)dst, (int)scatter);
+    else
+        hipLaunchKernelGGL(k_permute_rows<false>, grid, dim3(256), 0, s, order, N, row_words,
+                           (const uint32_t*)src, (uint32_t*)dst, (int)scatter);
+    prof_end(K_PERMUTE, s);
+    return hipGetLastError();
+}
+
 hipError_t launch_plan(const TexView& t, int mode, const float* uv, const float* tbn,
                        const float* view, const FragMap& m, const BwdPlan& plan, void* ws,
                        int32_t* order, float* uv_out, float* tbn_out, float* view_out,

@@ -47,6 +47,7 @@ enum KernelId {
     K_ORDER_CHECK,
     K_PLAN_KEYS,
     K_PLAN_GATHER,
+    K_PERMUTE,
     K_COUNT
 };
 const char* kernel_name(int id);
@@ -214,6 +215,11 @@ hipError_t launch_plan(const TexView& t, int mode, const float* uv, const float*
                        const float* view, const FragMap& m, const BwdPlan& plan, void* ws,
                        int32_t* order, float* uv_out, float* tbn_out, float* view_out,
                        hipStream_t s);
+
+// Rows of row_words 4-byte words moved by a plan's order: dst[k] =
+// src[order[k]] (gather) or dst[order[k]] = src[k] (scatter).
+hipError_t launch_permute_rows(const int32_t* order, int64_t N, int row_words, const void* src,
+                               void* dst, bool scatter, hipStream_t s);
 
 hipError_t launch_backward(const TexView& t, int fmt, int mode, const float* uv,
                            const float* tbn, const float* view, const float* grad_out,

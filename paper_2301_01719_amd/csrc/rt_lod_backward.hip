@@ -82,29 +82,31 @@ template <bool VEC>
 __global__ __launch_bounds__(256) void k_mip_adjoint(const float* __restrict__ grad_dst,
                                                      float* __restrict__ grad_src, int W, int H,
                                                      int E) {
-    const int64_t b = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
-    if (b >= (int64_t)W * H) return;
-    const int j = (int)(b / W), i = (int)(b - (int64_t)j * W);
+    const int64_t nb = (int64_t)W * H;
     const int fx = W > 1 ? 2 : 1, fy = H > 1 ? 2 : 1;
     const int W2 = W > 1 ? W / 2 : 1;
-    const int64_t parent = (int64_t)(j / fy) * W2 + i / fx;
     const float s = 1.0f / (float)(fx * fy);
-    const float* __restrict__ src = grad_dst + parent * E;
-    float* __restrict__ dst = grad_src + b * E;
-    if constexpr (VEC) {
-        const float4* s4 = (const float4*)src;
-        float4* d4 = (float4*)dst;
-        for (int q = threadIdx.x; q < E / 4; q += 256) {
-            const float4 p = s4[q];
-            float4 d = d4[q];
-            d.x += p.x * s;
-            d.y += p.y * s;
-            d.z += p.z * s;
-            d.w += p.w * s;
-            d4[q] = d;
+    // at most ADJ_GRID workgroups stride over the buckets (one dispatch)
+    for (int64_t b = blockIdx.x; b < nb; b += gridDim.x) {
+        const int j = (int)(b / W), i = (int)(b - (int64_t)j * W);
+        const int64_t parent = (int64_t)(j / fy) * W2 + i / fx;
+        const float* __restrict__ src = grad_dst + parent * E;
+        float* __restrict__ dst = grad_src + b * E;
+        if constexpr (VEC) {
+            const float4* s4 = (const float4*)src;
+            float4* d4 = (float4*)dst;
+            for (int q = threadIdx.x; q < E / 4; q += 256) {
+                const float4 p = s4[q];
+                float4 d = d4[q];
+                d.x += p.x * s;
+                d.y += p.y * s;
+                d.z += p.z * s;
+                d.w += p.w * s;
+                d4[q] = d;
+            }
+        } else {
+            for (int q = threadIdx.x; q < E; q += 256) dst[q] += src[q] * s;
         }
-    } else {
-        for (int q = threadIdx.x; q < E; q += 256) dst[q] += src[q] * s;
     }
 }
 
@@ -112,17 +114,16 @@ hipError_t launch_mip_adjoint(const TexView& src, const float* grad_dst, float* 
                               hipStream_t s) {
     const int E = src.n * src.n * src.C;
     const int64_t nb = (int64_t)src.W * src.H;
-    // buckets as a 2-D grid of at most 65535 rows of 65536 workgroups
-    const uint32_t gx = (uint32_t)std::min<int64_t>(nb, 65536);
-    const uint32_t gy = (uint32_t)((nb + gx - 1) / gx);
+    // one workgroup per bucket, at most 2^20 of them striding over the rest
+    const uint32_t gx = (uint32_t)std::min<int64_t>(nb, int64_t(1) << 20);
     const bool vec = (E % 4) == 0 && ((uintptr_t)grad_dst % 16) == 0 &&
                      ((uintptr_t)grad_src % 16) == 0;
     prof_begin(K_MIP_ADJOINT, s);
     if (vec)
-        hipLaunchKernelGGL(k_mip_adjoint<true>, dim3(gx, gy), dim3(256), 0, s, grad_dst, grad_src,
+        hipLaunchKernelGGL(k_mip_adjoint<true>, dim3(gx), dim3(256), 0, s, grad_dst, grad_src,
                            src.W, src.H, E);
     else
-        hipLaunchKernelGGL(k_mip_adjoint<false>, dim3(gx, gy), dim3(256), 0, s, grad_dst,
+        hipLaunchKernelGGL(k_mip_adjoint<false>, dim3(gx), dim3(256), 0, s, grad_dst,
                            grad_src, src.W, src.H, E);
     prof_end(K_MIP_ADJOINT, s);
     return hipGetLastError();

@@ -17,28 +17,33 @@ namespace rt {
 // One workgroup per bucket of the next level (its position worked out once):
 // the threads stream the bucket's float4s, each the mean of the 2 x 2 (or 2)
 // source buckets' float4s at the same offset, summed as ((a + b) + (c + d)).
+// At most MIP_GRID workgroups stride over the buckets, so a launch stays
+// within one dispatch however many buckets the level has.
+constexpr int64_t MIP_GRID = int64_t(1) << 20;
+
 __global__ __launch_bounds__(256) void k_build_mip(const float* __restrict__ src,
                                                    float* __restrict__ dst, int W, int H,
                                                    int per) {
     const int W2 = W > 1 ? W / 2 : 1, H2 = H > 1 ? H / 2 : 1;
-    const int64_t b = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
-    if (b >= (int64_t)W2 * H2) return;
+    const int64_t nb2 = (int64_t)W2 * H2;
     const int sx = W > 1 ? 2 : 1, sy = H > 1 ? 2 : 1;
     const int q4 = per / 4;  // per (n n C) is a multiple of 4 on this path
     const float inv = 1.f / (float)(sx * sy);
-    const int j = (int)(b / W2), i = (int)(b - (int64_t)j * W2);
-    const f4v* s0 = (const f4v*)(src + ((int64_t)(j * sy) * W + i * sx) * per);
-    const f4v* s1 = (const f4v*)((const float*)s0 + (int64_t)W * per);
-    f4v* d = (f4v*)(dst + b * per);
-    for (int q = threadIdx.x; q < q4; q += blockDim.x) {
-        f4v acc = s0[q];
-        if (sx == 2) acc += s0[q4 + q];
-        if (sy == 2) {
-            f4v lo = s1[q];
-            if (sx == 2) lo += s1[q4 + q];
-            acc += lo;
+    for (int64_t b = blockIdx.x; b < nb2; b += gridDim.x) {
+        const int j = (int)(b / W2), i = (int)(b - (int64_t)j * W2);
+        const f4v* s0 = (const f4v*)(src + ((int64_t)(j * sy) * W + i * sx) * per);
+        const f4v* s1 = (const f4v*)((const float*)s0 + (int64_t)W * per);
+        f4v* d = (f4v*)(dst + b * per);
+        for (int q = threadIdx.x; q < q4; q += blockDim.x) {
+            f4v acc = s0[q];
+            if (sx == 2) acc += s0[q4 + q];
+            if (sy == 2) {
+                f4v lo = s1[q];
+                if (sx == 2) lo += s1[q4 + q];
+                acc += lo;
+            }
+            d[q] = acc * inv;
         }
-        d[q] = acc * inv;
     }
 }
 
@@ -75,14 +80,13 @@ hipError_t launch_build_mip(const TexView& src, float* dst, hipStream_t s) {
     const uint32_t blocks = (uint32_t)std::min<int64_t>((work + 255) / 256, 256 * 64);
     prof_begin(K_BUILD_MIP, s);
     if (per % 4 == 0) {
-        // one workgroup per bucket of the next level, in a 2-D grid of at most
-        // 65536 columns; as many threads as the bucket has float4s (rounded up
-        // to whole wavefronts, at most 256)
+        // one workgroup per bucket of the next level (at most MIP_GRID of them,
+        // striding); as many threads as the bucket has float4s (rounded up to
+        // whole wavefronts, at most 256)
         const int64_t nb2 = (int64_t)W2 * H2;
-        const uint32_t gx = (uint32_t)std::min<int64_t>(nb2, 65536);
-        const uint32_t gy = (uint32_t)((nb2 + gx - 1) / gx);
+        const uint32_t gx = (uint32_t)std::min<int64_t>(nb2, MIP_GRID);
         const int threads = std::min(256, ((per / 4 + 63) / 64) * 64);
-        hipLaunchKernelGGL(k_build_mip, dim3(gx, gy), dim3(threads), 0, s,
+        hipLaunchKernelGGL(k_build_mip, dim3(gx), dim3(threads), 0, s,
                            (const float*)src.data, dst, src.W, src.H, per);
     } else
         hipLaunchKernelGGL(k_build_mip_scalar, dim3(blocks), dim3(256), 0, s,

@@ -42,7 +42,7 @@ EXPORTS = ("rt_create_texture", "rt_destroy_texture", "rt_quantize", "rt_lookup_
            "rt_lookup_light", "rt_bake_shadow", "rt_create_dictionary_texture",
            "rt_vq_assign", "rt_vq_update_workspace", "rt_vq_update",
            "rt_lookup_lod_bwd_workspace", "rt_lookup_lod_bwd", "rt_build_mip_adjoint",
-           "rt_plan_workspace", "rt_plan_fragments")
+           "rt_plan_workspace", "rt_plan_fragments", "rt_plan_permute")
 
 
 class RadtexError(RuntimeError):
@@ -99,6 +99,7 @@ def _load() -> ctypes.CDLL:
         "rt_lookup_bwd": ([P, ctypes.POINTER(Fragments), P, P, P, P, P, sz, u32, P], i32),
         "rt_debug_indices": ([P, ctypes.POINTER(Fragments), P, P, P], i32),
         "rt_plan_workspace": ([P, i64, u32], sz),
+        "rt_plan_permute": ([P, i64, i32, P, P, u32, P], i32),
         "rt_plan_fragments": ([P, ctypes.POINTER(Fragments), u32, P, P, P, P, P, sz, P], i32),
         "rt_last_error": ([], ctypes.c_char_p),
         "rt_status_string": ([i32], ctypes.c_char_p),
@@ -363,6 +364,23 @@ def plan_fragments(tex: Texture, uv, tbn, view, mode: str = "nearest", image=Non
                                  _ptr(puv), _ptr(ptbn), _ptr(pview), _ptr(workspace),
                                  ws_bytes, _stream(dev)))
     return order, puv, ptbn, pview
+
+
+def plan_permute(order: torch.Tensor, src: torch.Tensor, out=None, scatter: bool = False):
+    """Rows of a per-fragment array moved by a plan's order (rt_plan_permute):
+    out[k] = src[order[k]] (into plan order), or with scatter=True
+    out[order[k]] = src[k] (back to the caller's order)."""
+    _need_gpu(order, "order", torch.int32)
+    _need_gpu(src, "src")
+    N = order.numel()
+    if src.shape[0] != N:
+        raise ValueError("src must have one row per fragment")
+    if out is None:
+        out = torch.empty_like(src)
+    row = src[0].numel() * src.element_size() if N else 4
+    _check(LIB.rt_plan_permute(_ptr(order), N, row, _ptr(src), _ptr(out), 1 if scatter else 0,
+                               _stream(src.device)))
+    return out
 
 
 def debug_indices(tex: Texture, uv, tbn, view, image=None):

@@ -254,3 +254,55 @@ def test_backward_sort_past_2_27_records(rt):
     scale = float(torch.sum(go.abs(), dtype=torch.float64))
     assert abs(mass - want) <= 1e-5 * scale, (mass, want, scale)
     tex.close()
+
+
+def _mip_windows(W2, H2, w=16):
+    """Aligned windows (j0, i0) of w x w buckets of the next level: both
+    corners, the middle, and the last buckets."""
+    return [(0, 0), (0, W2 - w), (H2 - w, 0), (H2 // 2, W2 // 2), (H2 - w, W2 - w)]
+
+
+def test_mip_level_past_one_dispatch(rt):
+    """16384 x 16384 buckets of one RGBA sample (4 GiB) to the 8192 x 8192
+    level: one workgroup of 64 threads per bucket of the next level would be
+    2^32 work-items; the capped grid strides.  Windows of the level against the
+    oracle's level of the same source window (the mean of a bucket's 2 x 2
+    sources depends on those alone)."""
+    W = H = 16384
+    n, C = 1, 4
+    g = torch.Generator(device=DEV).manual_seed(5)
+    src = torch.rand((H, W, n, n, C), generator=g, device=DEV)
+    tex = rt.Texture(src, W, H, n, C)
+    dst = rt.build_mip(tex)
+    torch.cuda.synchronize()
+    w = 16
+    for j0, i0 in _mip_windows(W // 2, H // 2, w):
+        s = host(src[2 * j0:2 * j0 + 2 * w, 2 * i0:2 * i0 + 2 * w]).copy()
+        want = oracle.build_mips(s, 2 * w, 2 * w, n, C, 2)[1]
+        got = host(dst[j0:j0 + w, i0:i0 + w]).astype(np.float64)
+        assert np.max(np.abs(got - want)) <= 2.0 ** -22, (j0, i0)
+    tex.close()
+
+
+def test_mip_adjoint_past_one_dispatch(rt):
+    """The adjoint of the 4096 x 4096 -> 2048 x 2048 step with one RGBA sample
+    per bucket: one 256-thread workgroup per source bucket would be 2^32
+    work-items; the capped grid strides.  Windows against the oracle's adjoint
+    of the same parent window (each bucket adds its own parent's share)."""
+    W = H = 4096
+    n, C = 1, 4
+    g = torch.Generator(device=DEV).manual_seed(6)
+    tex = rt.Texture(torch.zeros((H, W, n, n, C), device=DEV), W, H, n, C)
+    gd = torch.randn((H // 2, W // 2, n, n, C), generator=g, device=DEV)
+    gs0 = torch.randn((H, W, n, n, C), generator=g, device=DEV)
+    gs = rt.build_mip_adjoint(tex, gd, gs0.clone())
+    torch.cuda.synchronize()
+    w = 16
+    for j0, i0 in _mip_windows(W // 2, H // 2, w):
+        parent = host(gd[j0:j0 + w, i0:i0 + w]).astype(np.float64)
+        base = host(gs0[2 * j0:2 * j0 + 2 * w, 2 * i0:2 * i0 + 2 * w]).astype(np.float64).copy()
+        want = oracle.build_mip_adjoint(parent, 2 * w, 2 * w, n, C, grad_src=base)
+        got = host(gs[2 * j0:2 * j0 + 2 * w, 2 * i0:2 * i0 + 2 * w]).astype(np.float64)
+        # one product by 1/4 (exact) and one binary32 addition per element
+        assert np.all(np.abs(got - want) <= 2.0 ** -24 * np.abs(want) + 1e-30), (j0, i0)
+    tex.close()

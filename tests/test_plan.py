@@ -188,3 +188,33 @@ def test_plan_validation(rt):
     assert call(7, P(o), P(pu), P(pt), P(pv), P(ws), ws_bytes, None) == 1
     assert call(0, P(o), P(pu), P(pt), P(pv), P(ws), ws_bytes, None) == 0
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("cols,dtype", [(4, torch.float32), (3, torch.float32), (2, torch.float32),
+                                        (9, torch.float32), (1, torch.int32)])
+def test_plan_permute_gathers_and_scatters_rows(rt, cols, dtype):
+    N = 100003
+    g = torch.Generator(device=DEV).manual_seed(cols)
+    order = torch.randperm(N, generator=g, device=DEV).to(torch.int32)
+    src = torch.randn((N, cols), generator=g, device=DEV).to(dtype)
+    fwd = rt.plan_permute(order, src)
+    assert torch.equal(fwd, src[order.long()])
+    back = rt.plan_permute(order, fwd, scatter=True)
+    torch.cuda.synchronize()
+    assert torch.equal(back, src)
+    # an unaligned source takes the 4-byte path
+    if cols == 4:
+        big = torch.randn(N * 4 + 1, device=DEV)
+        s2 = big[1:].view(N, 4)
+        assert torch.equal(rt.plan_permute(order, s2), s2[order.long()])
+
+
+def test_plan_permute_validation(rt):
+    order = torch.arange(8, dtype=torch.int32, device=DEV)
+    x = torch.zeros((8, 4), device=DEV)
+    P = rt._ptr
+    assert rt.LIB.rt_plan_permute(P(order), 8, 16, P(x), P(x), 0, None) == 1  # overlap
+    assert rt.LIB.rt_plan_permute(P(order), 8, 6, P(x), P(order), 0, None) == 1  # row bytes
+    assert rt.LIB.rt_plan_permute(P(order), 8, 16, P(x), None, 0, None) == 1
+    assert rt.LIB.rt_plan_permute(P(order), 8, 16, P(x), P(x.clone()), 2, None) == 1
+    assert rt.LIB.rt_plan_permute(None, 0, 16, None, None, 0, None) == 0
