@@ -239,6 +239,25 @@ rt_status rt_lookup_bwd(const rt_texture* tex, const rt_fragments* frags,
                         float* grad_uv, void* workspace, size_t workspace_bytes,
                         uint32_t flags, void* stream);
 
+/* Allocation-free backward, for callers that cannot allocate device memory
+ * (code under HIP graph capture, serving loops that forbid allocation): the
+ * same computation, arguments and results as rt_lookup_bwd, with the
+ * workspace taken from a scratch array the library holds in device memory,
+ * RT_NOALLOC_SCRATCH_BYTES (256 MiB) per GPU, kept until the process ends.
+ * The call allocates nothing itself (with the kernel timer of rt_profile_*
+ * enabled it records no events for this call).  Every call on a GPU shares
+ * that GPU's scratch: calls that overlap in time on one GPU (other streams,
+ * other threads) race and give undefined results; calls ordered on one
+ * stream are safe (each clears what it needs).
+ * Errors: as rt_lookup_bwd, and RT_ERR_WORKSPACE_TOO_SMALL when
+ * rt_lookup_bwd_workspace() for these arguments exceeds
+ * RT_NOALLOC_SCRATCH_BYTES (about five million nearest-mode fragments of
+ * four channels), RT_ERR_HIP when the scratch's address cannot be found. */
+#define RT_NOALLOC_SCRATCH_BYTES ((size_t)256 << 20)
+rt_status rt_lookup_bwd_noalloc(const rt_texture* tex, const rt_fragments* frags,
+                                const float* grad_out, float* grad_tex, float* grad_view,
+                                float* grad_uv, uint32_t flags, void* stream);
+
 /* --- Visit plan ------------------------------------------------------------
  * The lookup is a gather (Sec. 2: the bucket is chosen by u, v and the sample
  * inside it by the view direction), so the order in which fragments are

@@ -13,7 +13,7 @@ CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libradtex.so")
 SOURCES = ["rt_abi.cpp", "rt_lookup.hip", "rt_quantize.hip", "rt_backward.hip", "rt_bake.hip",
-           "rt_mip.hip", "rt_dictionary.hip", "rt_lod_backward.hip"]
+           "rt_mip.hip", "rt_dictionary.hip", "rt_lod_backward.hip", "rt_noalloc.hip"]
 ARCH = os.environ.get("RADTEX_ARCH", "gfx950")
 
 

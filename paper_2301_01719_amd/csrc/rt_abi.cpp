@@ -150,15 +150,22 @@ const char* kernel_name(int id) {
     return (id >= 0 && id < K_COUNT) ? names[id] : "";
 }
 
+namespace {
+thread_local int t_prof_suspended = 0;
+}
+
+ProfileSuspend::ProfileSuspend() { t_prof_suspended++; }
+ProfileSuspend::~ProfileSuspend() { t_prof_suspended--; }
+
 void prof_begin(int, hipStream_t s) {
-    if (!g_prof_on) return;
+    if (!g_prof_on || t_prof_suspended) return;
     std::lock_guard<std::mutex> lk(g_prof_mu);
     t_open = pool_get();
     if (t_open) (void)hipEventRecord(t_open, s);
 }
 
 void prof_end(int id, hipStream_t s) {
-    if (!g_prof_on || !t_open) return;
+    if (!g_prof_on || !t_open || t_prof_suspended) return;
     std::lock_guard<std::mutex> lk(g_prof_mu);
     hipEvent_t b = pool_get();
     if (!b) return;
@@ -517,6 +524,32 @@ rt_status rt_plan_permute(const int32_t* order, int64_t count, int32_t row_bytes
     hipError_t e = rt::launch_permute_rows(order, count, row_bytes / 4, src, dst,
                                            direction == RT_PLAN_SCATTER, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "permute launch");
+    return ok();
+    RT_GUARD_END
+}
+
+rt_status rt_lookup_bwd_noalloc(const rt_texture* t, const rt_fragments* f,
+                                const float* grad_out, float* grad_tex, float* grad_view,
+                                float* grad_uv, uint32_t flags, void* stream) {
+    RT_GUARD_BEGIN
+    rt::BwdPlan plan;
+    rt_status st = check_bwd(t, f, grad_out, grad_tex, grad_view, grad_uv, flags, &plan);
+    if (st != RT_OK) return st;
+    if (!grad_tex && !grad_view && !grad_uv) return ok();  // nothing requested
+    void* ws = nullptr;
+    if (grad_tex) {
+        if (plan.total > rt::NOALLOC_SCRATCH_BYTES)
+            return fail(RT_ERR_WORKSPACE_TOO_SMALL, "this backward needs %zu bytes of workspace, "
+                        "more than the %zu bytes of the allocation-free entry's scratch: use "
+                        "rt_lookup_bwd with a workspace", plan.total, rt::NOALLOC_SCRATCH_BYTES);
+        hipError_t e = rt::noalloc_scratch(&ws);
+        if (e != hipSuccess) return hip_fail(e, "scratch address");
+    }
+    rt::ProfileSuspend quiet;  // the kernel timer would create events
+    hipError_t e = rt::launch_backward(t->view, t->fmt, (int)flags, f->uv, f->tbn, f->view,
+                                       grad_out, grad_tex, grad_view, grad_uv, fragmap(f), plan,
+                                       ws, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "backward launch");
     return ok();
     RT_GUARD_END
 }

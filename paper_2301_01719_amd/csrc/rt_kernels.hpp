@@ -216,6 +216,19 @@ hipError_t launch_plan(const TexView& t, int mode, const float* uv, const float*
                        int32_t* order, float* uv_out, float* tbn_out, float* view_out,
                        hipStream_t s);
 
+// The allocation-free backward's scratch: a file-scope device array of
+// NOALLOC_SCRATCH_BYTES per GPU; *out receives the current device's address
+// of it (looked up once per device).
+constexpr size_t NOALLOC_SCRATCH_BYTES = size_t(256) << 20;
+hipError_t noalloc_scratch(void** out);
+
+// While alive, the kernel timer records nothing on this thread (it would
+// create events).
+struct ProfileSuspend {
+    ProfileSuspend();
+    ~ProfileSuspend();
+};
+
 // Rows of row_words 4-byte words moved by a plan's order: dst[k] =
 // src[order[k]] (gather) or dst[order[k]] = src[k] (scatter).
 hipError_t launch_permute_rows(const int32_t* order, int64_t N, int row_words, const void* src,

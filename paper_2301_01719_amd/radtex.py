@@ -42,7 +42,8 @@ EXPORTS = ("rt_create_texture", "rt_destroy_texture", "rt_quantize", "rt_lookup_
            "rt_lookup_light", "rt_bake_shadow", "rt_create_dictionary_texture",
            "rt_vq_assign", "rt_vq_update_workspace", "rt_vq_update",
            "rt_lookup_lod_bwd_workspace", "rt_lookup_lod_bwd", "rt_build_mip_adjoint",
-           "rt_plan_workspace", "rt_plan_fragments", "rt_plan_permute")
+           "rt_plan_workspace", "rt_plan_fragments", "rt_plan_permute",
+           "rt_lookup_bwd_noalloc")
 
 
 class RadtexError(RuntimeError):
@@ -100,6 +101,7 @@ def _load() -> ctypes.CDLL:
         "rt_debug_indices": ([P, ctypes.POINTER(Fragments), P, P, P], i32),
         "rt_plan_workspace": ([P, i64, u32], sz),
         "rt_plan_permute": ([P, i64, i32, P, P, u32, P], i32),
+        "rt_lookup_bwd_noalloc": ([P, ctypes.POINTER(Fragments), P, P, P, P, u32, P], i32),
         "rt_plan_fragments": ([P, ctypes.POINTER(Fragments), u32, P, P, P, P, P, sz, P], i32),
         "rt_last_error": ([], ctypes.c_char_p),
         "rt_status_string": ([i32], ctypes.c_char_p),
@@ -381,6 +383,21 @@ def plan_permute(order: torch.Tensor, src: torch.Tensor, out=None, scatter: bool
     _check(LIB.rt_plan_permute(_ptr(order), N, row, _ptr(src), _ptr(out), 1 if scatter else 0,
                                _stream(src.device)))
     return out
+
+
+NOALLOC_SCRATCH_BYTES = 256 << 20
+
+
+def lookup_bwd_noalloc(tex: Texture, uv, tbn, view, grad_out, grad_tex, grad_view, grad_uv,
+                       mode: str = "nearest", image=None):
+    """rt_lookup_bwd_noalloc: the backward into caller-allocated outputs (any of
+    them None to skip it), with the library's scratch as the workspace; the
+    call allocates nothing."""
+    fr = _frags(uv, tbn, view, image)
+    _need_gpu(grad_out, "grad_out", torch.float32)
+    _check(LIB.rt_lookup_bwd_noalloc(tex.handle, ctypes.byref(fr), _ptr(grad_out),
+                                     _ptr(grad_tex), _ptr(grad_view), _ptr(grad_uv),
+                                     MODES[mode], _stream(tex.device)))
 
 
 def debug_indices(tex: Texture, uv, tbn, view, image=None):
