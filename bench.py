@@ -63,6 +63,7 @@ KERNEL_SOURCES = {
     "k_segacc_big": "rt_backward.hip", "k_payload": "rt_backward.hip",
     "k_bake_env": "rt_bake.hip", "k_keys_in_order": "rt_backward.hip",
     "k_plan_keys": "rt_backward.hip", "k_plan_gather": "rt_backward.hip",
+    "k_permute_rows": "rt_backward.hip",
     "k_bake_shadow": "rt_bake.hip", "k_build_mip": "rt_mip.hip",
     "k_vq_assign": "rt_dictionary.hip", "k_mip_adjoint": "rt_lod_backward.hip",
 }

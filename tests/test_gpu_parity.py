@@ -186,8 +186,22 @@ def test_bounds_fuzz(rt):
     fin = np.isfinite(uv).all(1) & np.isfinite(view).all(1) & (np.abs(view).sum(1) > 0)
     o = host(out)
     assert np.all(np.isfinite(o[fin]))
-    # the backward conserves the upstream gradient mass on finite inputs
-    assert np.isfinite(host(gt)).sum() > 0
+    # on the finite inputs the backward conserves the upstream gradient's mass:
+    # each fragment's tap weights sum to one (Eq. (5)), so the texture gradient
+    # summed over all texels equals the upstream gradient summed over fragments
+    nf = int(fin.sum())
+    g = torch.Generator().manual_seed(7)
+    g_up = torch.rand((nf, C), generator=g) + 0.5
+    sel = torch.from_numpy(np.nonzero(fin)[0]).to(DEV)
+    for mode in ("nearest", "bilinear"):
+        gt, gv, gu = rt.lookup_bwd(tex, uv_d[sel].contiguous(), tbn_d[sel].contiguous(),
+                                   v_d[sel].contiguous(), g_up.to(DEV), mode=mode)
+        _sync()
+        t = host(gt).astype(np.float64).reshape(-1, C)
+        assert np.all(np.isfinite(t)), mode
+        np.testing.assert_allclose(t.sum(0), g_up.double().sum(0).numpy(), rtol=1e-5,
+                                   err_msg=mode)
+        assert np.all(np.isfinite(host(gv))) and np.all(np.isfinite(host(gu))), mode
 
 
 # ---------------------------------------------------------------------------
