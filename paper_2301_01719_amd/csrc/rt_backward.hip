@@ -185,17 +185,27 @@ __global__ __launch_bounds__(256) void k_bwd_fragment(
     const float* __restrict__ view, const float* __restrict__ grad_out,
     float* __restrict__ grad_view, float* __restrict__ grad_uv, uint32_t* __restrict__ keys,
     float* __restrict__ wrec, FragMap m, int cell_bits, uint32_t sentinel) {
+    __shared__ FragStage stage;
     const int64_t f = frag_of(m, blockIdx.x, gridDim.x, threadIdx.x);
-    if (f < 0) return;
     const int n = t.n;
     float go[4] = {0.f, 0.f, 0.f, 0.f};
     bool zero = true;
+    if (f >= 0) {
 #pragma unroll
-    for (int c = 0; c < C; c++) {
-        go[c] = grad_out[f * C + c];
-        zero = zero && go[c] == 0.f;
+        for (int c = 0; c < C; c++) {
+            go[c] = grad_out[f * C + c];
+            zero = zero && go[c] == 0.f;
+        }
     }
-    if (sentinel != 0u && zero) {
+    Frag g;
+    if (sentinel == 0u) {
+        // every fragment contributes: its frame comes from the workgroup's
+        // staged block (all threads reach the staging barrier)
+        g = load_frag_block(uv, tbn, view, m, f, stage);
+        if (f < 0) return;
+    } else if (f < 0) {
+        return;
+    } else if (zero) {
         // sparse plan: no contribution, no records; its gradients are 0
         if (grad_view) {
             grad_view[f * 3 + 0] = 0.f;
@@ -208,8 +218,9 @@ __global__ __launch_bounds__(256) void k_bwd_fragment(
             else ((uint4*)keys)[f] = make_uint4(sentinel, sentinel, sentinel, sentinel);
         }
         return;
+    } else {
+        g = load_frag(uv, tbn, view, f);
     }
-    Frag g = load_frag(uv, tbn, view, f);
     Dir d = map_direction(g.m, g.w, n);
     Foot p = footprint(d.sx, d.sy, n);
     const uint32_t cell = (uint32_t)(p.y0 * n + p.x0);
@@ -753,28 +764,17 @@ __global__ __launch_bounds__(256) void k_bucket_ranges(const uint32_t* __restric
     }
 }
 
-// The payload of the sorted records of buckets with at most 64 records (the
-// ones the first accumulation pass serves from its register window), in
-// sorted order: the fractions (fx, fy) and the upstream gradient times the
-// bucket weight (1 in nearest mode).  That pass then reads its records
-// contiguously instead of gathering them from the fragments; the passes for
-// bigger buckets, whose records share cache lines, keep gathering.  Records
-// past the last bucket (sparse plans) are skipped.  Workgroups are renumbered
-// per XCD: neighbouring records gather from neighbouring fragments.
+// One sorted record's payload (records of buckets with more than 64 records
+// are skipped: their passes gather).
 template <int C, int MODE>
-__global__ __launch_bounds__(256) void k_payload(const uint32_t* __restrict__ skeys,
-                                                 const uint32_t* __restrict__ svals,
-                                                 const float* __restrict__ wrec,
-                                                 const float* __restrict__ grad_out,
-                                                 const int2* __restrict__ range, int64_t R,
-                                                 int cell_bits, int64_t nb,
-                                                 float* __restrict__ payf,
-                                                 float* __restrict__ payg,
-                                                 const uint32_t* __restrict__ disorder) {
-    // records in key order are read where they were made: no payload
-    if (sort_skipped(disorder)) return;
-    const int64_t i = (int64_t)xcd_block_id(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
-    if (i >= R) return;
+__device__ __forceinline__ void payload_record(const uint32_t* __restrict__ skeys,
+                                               const uint32_t* __restrict__ svals,
+                                               const float* __restrict__ wrec,
+                                               const float* __restrict__ grad_out,
+                                               const int2* __restrict__ range, int64_t i,
+                                               int cell_bits, int64_t nb,
+                                               float* __restrict__ payf,
+                                               float* __restrict__ payg) {
     const uint32_t b = skeys[i] >> cell_bits;
     if (b >= nb) return;
     const int2 r = range[b];
@@ -807,6 +807,36 @@ __global__ __launch_bounds__(256) void k_payload(const uint32_t* __restrict__ sk
     } else {
 #pragma unroll
         for (int c = 0; c < C; c++) payg[i * C + c] = grad_out[frag * C + c] * wb;
+    }
+}
+
+// The payload of the sorted records of buckets with at most 64 records (the
+// ones the first accumulation pass serves from its register window), in
+// sorted order: the fractions (fx, fy) and the upstream gradient times the
+// bucket weight (1 in nearest mode).  That pass then reads its records
+// contiguously instead of gathering them from the fragments; the passes for
+// bigger buckets, whose records share cache lines, keep gathering.  Records
+// past the last bucket (sparse plans) are skipped.  Workgroups are renumbered
+// per XCD (neighbouring records gather from neighbouring fragments) and stride
+// over the records, so that the launch stays small when the records came in
+// key order and there is nothing to do.
+template <int C, int MODE>
+__global__ __launch_bounds__(256) void k_payload(const uint32_t* __restrict__ skeys,
+                                                 const uint32_t* __restrict__ svals,
+                                                 const float* __restrict__ wrec,
+                                                 const float* __restrict__ grad_out,
+                                                 const int2* __restrict__ range, int64_t R,
+                                                 int cell_bits, int64_t nb,
+                                                 float* __restrict__ payf,
+                                                 float* __restrict__ payg,
+                                                 const uint32_t* __restrict__ disorder) {
+    // records in key order are read where they were made: no payload
+    if (sort_skipped(disorder)) return;
+    const int64_t stride = (int64_t)gridDim.x * 256;
+    for (int64_t i = (int64_t)xcd_block_id(blockIdx.x, gridDim.x) * 256 + threadIdx.x; i < R;
+         i += stride) {
+        payload_record<C, MODE>(skeys, svals, wrec, grad_out, range, i, cell_bits, nb, payf,
+                                payg);
     }
 }
 
@@ -1180,6 +1210,8 @@ __global__ __launch_bounds__(256) void k_segacc(const uint32_t* __restrict__ ske
         const int cl = rl.y - rl.x;
         const bool big = cl > 64 && cl <= PIECE;
         const uint64_t bm = __ballot(big);
+        // a bucket for pass 2: raise the flag that lets its kernels run
+        if (__ballot(cl > PIECE) != 0ull && lane == 0) atomicOr(big_count + HOT_FLAG, 1u);
         if (bm != 0ull) {
             const int64_t list = (grp / BIG_RUN) % BIG_LISTS;
             uint32_t base = 0;
@@ -1271,7 +1303,9 @@ __global__ __launch_bounds__(64) void k_segacc_hot(const uint32_t* __restrict__ 
                                                    float* __restrict__ part, int64_t R, int n,
                                                    int cell_bits, int64_t nb,
                                                    const uint32_t* __restrict__ keys_made,
-                                                   const uint32_t* __restrict__ disorder) {
+                                                   const uint32_t* __restrict__ disorder,
+                                                   const uint32_t* __restrict__ hot) {
+    if (__builtin_amdgcn_readfirstlane(hot[0]) == 0u) return;  // no bucket for pass 2
     if (sort_skipped(disorder)) {
         skeys = keys_made;
         svals = nullptr;
@@ -1307,7 +1341,9 @@ __global__ __launch_bounds__(64) void k_combine_hot(const uint32_t* __restrict__
                                                     const TileOut out, int64_t R,
                                                     int te, int cell_bits, int64_t nb,
                                                     const uint32_t* __restrict__ keys_made,
-                                                    const uint32_t* __restrict__ disorder) {
+                                                    const uint32_t* __restrict__ disorder,
+                                                    const uint32_t* __restrict__ hot) {
+    if (__builtin_amdgcn_readfirstlane(hot[0]) == 0u) return;  // no bucket for pass 2
     if (sort_skipped(disorder)) skeys = keys_made;
     const int lane = threadIdx.x;
     const int64_t k = blockIdx.x;
@@ -1477,12 +1513,13 @@ template <int MODE>
 static void launch_segacc_hot_c(int C, dim3 grid, size_t shm, hipStream_t s, const uint32_t* sk,
                                 const uint32_t* sv, const float* wrec, const float* go,
                                 const int2* range, float* part, int64_t R, int n, int cb,
-                                int64_t nb, const uint32_t* km, const uint32_t* dis) {
+                                int64_t nb, const uint32_t* km, const uint32_t* dis,
+                                const uint32_t* hot) {
     switch (C) {
-    case 1: hipLaunchKernelGGL((k_segacc_hot<1, MODE>), grid, dim3(64), shm, s, sk, sv, wrec, go, range, part, R, n, cb, nb, km, dis); break;
-    case 2: hipLaunchKernelGGL((k_segacc_hot<2, MODE>), grid, dim3(64), shm, s, sk, sv, wrec, go, range, part, R, n, cb, nb, km, dis); break;
-    case 3: hipLaunchKernelGGL((k_segacc_hot<3, MODE>), grid, dim3(64), shm, s, sk, sv, wrec, go, range, part, R, n, cb, nb, km, dis); break;
-    default: hipLaunchKernelGGL((k_segacc_hot<4, MODE>), grid, dim3(64), shm, s, sk, sv, wrec, go, range, part, R, n, cb, nb, km, dis); break;
+    case 1: hipLaunchKernelGGL((k_segacc_hot<1, MODE>), grid, dim3(64), shm, s, sk, sv, wrec, go, range, part, R, n, cb, nb, km, dis, hot); break;
+    case 2: hipLaunchKernelGGL((k_segacc_hot<2, MODE>), grid, dim3(64), shm, s, sk, sv, wrec, go, range, part, R, n, cb, nb, km, dis, hot); break;
+    case 3: hipLaunchKernelGGL((k_segacc_hot<3, MODE>), grid, dim3(64), shm, s, sk, sv, wrec, go, range, part, R, n, cb, nb, km, dis, hot); break;
+    default: hipLaunchKernelGGL((k_segacc_hot<4, MODE>), grid, dim3(64), shm, s, sk, sv, wrec, go, range, part, R, n, cb, nb, km, dis, hot); break;
     }
 }
 
@@ -1662,7 +1699,7 @@ hipError_t launch_accumulate(int n, int C, int mode, const float* grad_out, cons
     // not written when the records came in order), then pass 1 over buckets
     const bool pay = R > 0 && R <= 64 * nb;
     if (pay) {
-        const dim3 gp((uint32_t)((R + 255) / 256));
+        const dim3 gp((uint32_t)std::min<int64_t>((R + 255) / 256, PAYLOAD_BLOCKS));
         prof_begin(K_PAYLOAD, s);
         if (mode == MODE_NEAREST) launch_payload_c<MODE_NEAREST>(C, gp, s, skeys, svals, wrec, grad_out, range, R, plan.cell_bits, nb, payf, payg, dis);
         else launch_payload_c<MODE_BILINEAR>(C, gp, s, skeys, svals, wrec, grad_out, range, R, plan.cell_bits, nb, payf, payg, dis);
@@ -1706,13 +1743,13 @@ hipError_t launch_accumulate(int n, int C, int mode, const float* grad_out, cons
         const dim3 g2((uint32_t)plan.chunks);
         prof_begin(K_SEGACC_HOT, s);
         if (mode == MODE_NEAREST)
-            launch_segacc_hot_c<MODE_NEAREST>(C, g2, (size_t)te * 4, s, skeys, svals, wrec, grad_out, range, part, R, n, plan.cell_bits, nb, keys0, dis);
+            launch_segacc_hot_c<MODE_NEAREST>(C, g2, (size_t)te * 4, s, skeys, svals, wrec, grad_out, range, part, R, n, plan.cell_bits, nb, keys0, dis, big_count + HOT_FLAG);
         else
-            launch_segacc_hot_c<MODE_BILINEAR>(C, g2, (size_t)te * 4, s, skeys, svals, wrec, grad_out, range, part, R, n, plan.cell_bits, nb, keys0, dis);
+            launch_segacc_hot_c<MODE_BILINEAR>(C, g2, (size_t)te * 4, s, skeys, svals, wrec, grad_out, range, part, R, n, plan.cell_bits, nb, keys0, dis, big_count + HOT_FLAG);
         prof_end(K_SEGACC_HOT, s);
         prof_begin(K_COMBINE_HOT, s);
         hipLaunchKernelGGL(k_combine_hot, g2, dim3(64), 0, s, skeys, range, part, out, R, te,
-                           plan.cell_bits, nb, keys0, dis);
+                           plan.cell_bits, nb, keys0, dis, big_count + HOT_FLAG);
         prof_end(K_COMBINE_HOT, s);
     }
     return hipGetLastError();

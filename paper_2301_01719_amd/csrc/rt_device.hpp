@@ -222,6 +222,50 @@ __device__ __forceinline__ Frag load_frag(const float* __restrict__ uv, const fl
     return r;
 }
 
+// The frames and view vectors of a flat launch's workgroup (256 consecutive
+// fragments) staged in LDS.  A fragment's 36 + 12 bytes do not fall on a
+// lane's 16-byte vector, but the workgroup's 9216 + 3072 bytes do: the block
+// is read with 16-byte loads when both arrays are 16-byte aligned there, else
+// with 4-byte loads, and every lane then takes its own record from LDS (a
+// stride of 9 or 3 words: no bank conflicts).  Tiled launches read per lane.
+struct FragStage {
+    float tbn[256 * 9];
+    float view[256 * 3];
+};
+
+// Must be reached by every thread of the workgroup (it holds a barrier when
+// the launch is flat); returns the record of fragment f (f >= 0).
+__device__ __forceinline__ Frag load_frag_block(const float* __restrict__ uv,
+                                                const float* __restrict__ tbn,
+                                                const float* __restrict__ view, const FragMap& m,
+                                                int64_t f, FragStage& s) {
+    if (m.width != 0) return f >= 0 ? load_frag(uv, tbn, view, f) : Frag{};
+    const int tid = threadIdx.x;
+    const int64_t f0 = (int64_t)xcd_block_id(blockIdx.x, gridDim.x) * 256;
+    const int nf = (int)(m.N - f0 < 256 ? m.N - f0 : 256);
+    const float* bt = tbn + f0 * 9;
+    const float* bv = view + f0 * 3;
+    if (nf == 256 && ((((uintptr_t)bt) | ((uintptr_t)bv)) & 15) == 0) {
+        for (int q = tid; q < 576; q += 256) ((f4v*)s.tbn)[q] = ((const f4v*)bt)[q];
+        if (tid < 192) ((f4v*)s.view)[tid] = ((const f4v*)bv)[tid];
+    } else {
+        for (int q = tid; q < nf * 9; q += 256) s.tbn[q] = bt[q];
+        for (int q = tid; q < nf * 3; q += 256) s.view[q] = bv[q];
+    }
+    __syncthreads();
+    Frag r{};
+    if (f >= 0) {
+        const float2 t = ((const float2*)uv)[f];
+        r.u = t.x;
+        r.v = t.y;
+#pragma unroll
+        for (int k = 0; k < 9; k++) r.m[k] = s.tbn[tid * 9 + k];
+#pragma unroll
+        for (int k = 0; k < 3; k++) r.w[k] = s.view[tid * 3 + k];
+    }
+    return r;
+}
+
 // ---------------------------------------------------------------------------
 // Incidence -> in-bucket sample coordinate, binary32.
 //

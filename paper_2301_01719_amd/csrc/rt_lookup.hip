@@ -73,9 +73,10 @@ __global__ __launch_bounds__(256) void k_lookup_fwd(TexView t, const float* __re
                                                     const float* __restrict__ tbn,
                                                     const float* __restrict__ view,
                                                     float* __restrict__ out, FragMap m) {
+    __shared__ FragStage stage;
     const int64_t f = frag_of(m, blockIdx.x, gridDim.x, threadIdx.x);
+    Frag g = load_frag_block(uv, tbn, view, m, f, stage);
     if (f < 0) return;
-    Frag g = load_frag(uv, tbn, view, f);
     Dir d = map_direction(g.m, g.w, t.n);
     Foot p = footprint(d.sx, d.sy, t.n);
     float acc[4] = {0.f, 0.f, 0.f, 0.f};
