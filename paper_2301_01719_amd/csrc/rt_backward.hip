@@ -431,14 +431,15 @@ __device__ __forceinline__ bool sort_skipped(const uint32_t* __restrict__ disord
     return disorder != nullptr && __builtin_amdgcn_readfirstlane(*disorder) == 0u;
 }
 
-// Any key smaller than the one before it sets *disorder (cleared before the
-// launch).  Four keys per thread with one 16-byte load (the key buffer is
-// padded to 256 bytes) and the key before them.  A wave that finds a descent
-// reads the word first (past its L1) and sets it only while it is still
-// clear: on unsorted keys nearly every wave finds one, and a million atomics
-// on one address would serialise.
+// Whether any key is smaller than the one before it, in two launches.  The
+// first writes one flag per workgroup of 1024 keys (four per thread with one
+// 16-byte load -- the key buffer is padded to 256 bytes -- and the key before
+// them), the second ORs the flags into *disorder (cleared before) with one
+// atomic per 4096 flags.  On unsorted keys nearly every wave finds a descent,
+// and atomics of every wave on one address would serialise.
 __global__ __launch_bounds__(256) void k_keys_in_order(const uint32_t* __restrict__ keys, int64_t R,
-                                                       uint32_t* __restrict__ disorder) {
+                                                       uint32_t* __restrict__ flags) {
+    __shared__ uint32_t wave_down[4];
     const int64_t i0 = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 4;
     bool down = false;
     if (i0 < R) {
@@ -451,9 +452,23 @@ __global__ __launch_bounds__(256) void k_keys_in_order(const uint32_t* __restric
         }
     }
     const uint64_t m = __ballot(down);
-    if (m != 0ull && (threadIdx.x & 63) == (unsigned)__builtin_ctzll(m) &&
-        __hip_atomic_load(disorder, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u)
-        atomicOr(disorder, 1u);
+    if ((threadIdx.x & 63) == 0) wave_down[threadIdx.x >> 6] = m != 0ull ? 1u : 0u;
+    __syncthreads();
+    if (threadIdx.x == 0)
+        flags[blockIdx.x] = wave_down[0] | wave_down[1] | wave_down[2] | wave_down[3];
+}
+
+__global__ __launch_bounds__(256) void k_flags_any(const uint32_t* __restrict__ flags,
+                                                   int64_t nflags,
+                                                   uint32_t* __restrict__ disorder) {
+    const int64_t f0 = (int64_t)blockIdx.x * 4096 + threadIdx.x;
+    uint32_t any = 0u;
+#pragma unroll
+    for (int u = 0; u < 16; u++) {
+        const int64_t f = f0 + 256 * u;
+        if (f < nflags) any |= flags[f];
+    }
+    if (__syncthreads_or((int)any) && threadIdx.x == 0) atomicOr(disorder, 1u);
 }
 
 // Digit counts of one tile of SORT_TILE keys: hist[d * tiles + tile].  Tiles
@@ -817,9 +832,10 @@ __device__ __forceinline__ void payload_record(const uint32_t* __restrict__ skey
 // contiguously instead of gathering them from the fragments; the passes for
 // bigger buckets, whose records share cache lines, keep gathering.  Records
 // past the last bucket (sparse plans) are skipped.  Workgroups are renumbered
-// per XCD (neighbouring records gather from neighbouring fragments) and stride
-// over the records, so that the launch stays small when the records came in
-// key order and there is nothing to do.
+// per XCD (neighbouring records gather from neighbouring fragments); a
+// workgroup takes PAYLOAD_PER_THREAD x 256 consecutive records, a thread every
+// 256th of them with its loads issued together, which also keeps the launch
+// small when the records came in key order and there is nothing to do.
 template <int C, int MODE>
 __global__ __launch_bounds__(256) void k_payload(const uint32_t* __restrict__ skeys,
                                                  const uint32_t* __restrict__ svals,
@@ -832,11 +848,14 @@ __global__ __launch_bounds__(256) void k_payload(const uint32_t* __restrict__ sk
                                                  const uint32_t* __restrict__ disorder) {
     // records in key order are read where they were made: no payload
     if (sort_skipped(disorder)) return;
-    const int64_t stride = (int64_t)gridDim.x * 256;
-    for (int64_t i = (int64_t)xcd_block_id(blockIdx.x, gridDim.x) * 256 + threadIdx.x; i < R;
-         i += stride) {
-        payload_record<C, MODE>(skeys, svals, wrec, grad_out, range, i, cell_bits, nb, payf,
-                                payg);
+    const int64_t base =
+        (int64_t)xcd_block_id(blockIdx.x, gridDim.x) * (256 * PAYLOAD_PER_THREAD) + threadIdx.x;
+#pragma unroll
+    for (int k = 0; k < PAYLOAD_PER_THREAD; k++) {
+        const int64_t i = base + 256 * k;
+        if (i < R)
+            payload_record<C, MODE>(skeys, svals, wrec, grad_out, range, i, cell_bits, nb, payf,
+                                    payg);
     }
 }
 
@@ -1446,7 +1465,8 @@ bool plan_backward(int W, int H, int n, int C, int64_t N, int mode, BwdPlan* p, 
     p->off_hist = take((size_t)p->scan_len * 4);
     p->off_hoff = take((size_t)p->scan_len * 4);
     p->off_scanp = take((size_t)(p->scan_blocks + 1) * 4);
-    p->off_disorder = take(4);
+    // the disorder word, then one order flag per 1024 records
+    p->off_disorder = take((size_t)(ORDER_FLAGS_AT + (R + 1023) / 1024) * 4);
     p->sort_total = o;
     p->off_wrec = take((size_t)N * (mode == MODE_NEAREST ? 8 : 16));
     p->off_payf = take((size_t)R * 8);
@@ -1652,11 +1672,15 @@ static uint32_t* launch_order_check(const BwdPlan& plan, void* ws, hipStream_t s
     const uint32_t* keys0 = (const uint32_t*)(wsb + plan.off_keys0);
     uint32_t* disorder = (uint32_t*)(wsb + plan.off_disorder);
     const int64_t R = plan.records;
+    uint32_t* flags = disorder + ORDER_FLAGS_AT;
     launch_fill(disorder, 1, 0u, s);
     if (R > 1) {
+        const int64_t nflags = (R + 1023) / 1024;
         prof_begin(K_ORDER_CHECK, s);
-        hipLaunchKernelGGL(k_keys_in_order, dim3((uint32_t)((R + 1023) / 1024)), dim3(256), 0, s,
-                           keys0, R, disorder);
+        hipLaunchKernelGGL(k_keys_in_order, dim3((uint32_t)nflags), dim3(256), 0, s, keys0, R,
+                           flags);
+        hipLaunchKernelGGL(k_flags_any, dim3((uint32_t)((nflags + 4095) / 4096)), dim3(256), 0, s,
+                           flags, nflags, disorder);
         prof_end(K_ORDER_CHECK, s);
     }
     return disorder;
@@ -1699,7 +1723,8 @@ hipError_t launch_accumulate(int n, int C, int mode, const float* grad_out, cons
     // not written when the records came in order), then pass 1 over buckets
     const bool pay = R > 0 && R <= 64 * nb;
     if (pay) {
-        const dim3 gp((uint32_t)std::min<int64_t>((R + 255) / 256, PAYLOAD_BLOCKS));
+        const int64_t per_block = 256 * PAYLOAD_PER_THREAD;
+        const dim3 gp((uint32_t)((R + per_block - 1) / per_block));
         prof_begin(K_PAYLOAD, s);
         if (mode == MODE_NEAREST) launch_payload_c<MODE_NEAREST>(C, gp, s, skeys, svals, wrec, grad_out, range, R, plan.cell_bits, nb, payf, payg, dis);
         else launch_payload_c<MODE_BILINEAR>(C, gp, s, skeys, svals, wrec, grad_out, range, R, plan.cell_bits, nb, payf, payg, dis);

@@ -134,7 +134,8 @@ constexpr int SEG_GROUP = 8;  // buckets per wavefront in the first accumulation
 constexpr int BIG_LISTS = 64; // big-bucket lists, each with its own counter
 constexpr int BIG_STRIDE = 64;  // u32 between two counters (256 bytes)
 constexpr int HOT_FLAG = 1;     // u32 after counter 0: set when a bucket needs pass 2
-constexpr int PAYLOAD_BLOCKS = 8192;  // workgroups of the payload launch (they stride)
+constexpr int PAYLOAD_PER_THREAD = 4;  // sorted records per thread in the payload launch
+constexpr int ORDER_FLAGS_AT = 64;  // u32 after the disorder word where the order flags start
 constexpr int BIG_RUN = 64;     // consecutive groups that append to one list
 // sparse: fragments whose upstream gradient is all zero make no records (their
 // keys sort past every bucket and are skipped), at the price of one key bit.
