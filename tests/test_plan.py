@@ -166,6 +166,37 @@ def test_nearly_planned_fragments_are_still_sorted(rt, mode):
     assert torch.equal(sgv, gv[ot]) and torch.equal(sgu, gu[ot])
 
 
+@pytest.mark.parametrize("where", ["first", "last"])
+def test_a_descent_past_one_flag_block_is_found(rt, where):
+    """Over 4096 workgroups of 1024 keys the order check's flags are ORed by
+    more than one workgroup: one swapped pair in the first or in the last of
+    them still sends the backward through its sort (a missed descent would
+    split the runs of a key and change the texel gradient)."""
+    W, H, n, C, N = 64, 64, 8, 1, 4_400_000  # 4297 flags
+    g = torch.Generator().manual_seed(11)
+    tex = rt.Texture(torch.rand((H, W, n, n, C), generator=g).to(DEV), W, H, n, C)
+    uv = torch.rand((N, 2), generator=g).to(DEV)
+    vt = torch.rand((N, 3), generator=g) * 2 - 1
+    vt[:, 2] = vt[:, 2].abs() + 0.1
+    view = vt.to(DEV)
+    tbn = torch.eye(3, device=DEV).expand(N, 3, 3).contiguous()
+    order, puv, ptbn, pview = rt.plan_fragments(tex, uv, tbn, view)
+    go = torch.randn((N, C), generator=torch.Generator().manual_seed(12)).to(DEV)
+    gt, _, _ = rt.lookup_bwd(tex, uv, tbn, view, go, want_view=False, want_uv=False)
+    k = _keys(rt, tex, puv, ptbn, pview, W, n, "nearest")
+    steps = np.nonzero(np.diff(k) > 0)[0]
+    a = int(steps[0] if where == "first" else steps[-1])
+    assert (a // 1024 < 4096) == (where == "first")
+    perm = torch.arange(N, device=DEV)
+    perm[a], perm[a + 1] = a + 1, a
+    suv, stbn, sview = puv[perm].contiguous(), ptbn[perm].contiguous(), pview[perm].contiguous()
+    ot = order.long()[perm]
+    sgt, _, _ = rt.lookup_bwd(tex, suv, stbn, sview, go[ot].contiguous(), want_view=False,
+                              want_uv=False)
+    torch.cuda.synchronize()
+    assert torch.equal(sgt, gt)
+
+
 def test_plan_validation(rt):
     import ctypes
     tex = rt.Texture(torch.rand((4, 4, 8, 8, 4), device=DEV), 4, 4, 8, 4)
