@@ -531,8 +531,9 @@ def timed_launches(fn, reps, cold_scratch=None):
 
 def run_multi_view(rt, dev):
     """The 64-view workload's forward (512 x 512 buckets of 16 x 16 RGBA, 64
-    views of 1024 x 1024, one launch) per storage format, in plan order and
-    in image order (32 x 8 pixel tiles), with its algorithmic bytes."""
+    views of 1024 x 1024, one launch) per storage format, in plan order, in
+    image order (32 x 8 pixel tiles) and in plan order with bucket tiles
+    staged in LDS (RT_FWD_STAGE_BUCKETS), with its algorithmic bytes."""
     import torch
     from paper_2301_01719_amd import workloads as wl
     w = wl.WORKLOADS["c3"]
@@ -562,10 +563,11 @@ def run_multi_view(rt, dev):
         eb = {"f32": 4, "bf16": 2, "fp8": 1}[fmt]
         alg = N * 56 + N * C * 4 + uniq * C * eb + (ub * 4 if fmt == "fp8" else 0)
         r = {}
-        for tag, args_ in (("plan", (puv, ptbn, pview, None)),
-                           ("image", (gb.uv, gb.tbn, gb.view, gb.image))):
-            u, t, v, im = args_
-            fn = lambda: rt.lookup_fwd(tex, u, t, v, out=out, image=im)
+        for tag, args_ in (("plan", (puv, ptbn, pview, None, False)),
+                           ("image", (gb.uv, gb.tbn, gb.view, gb.image, False)),
+                           ("plan_staged_buckets", (puv, ptbn, pview, None, True))):
+            u, t, v, im, st = args_
+            fn = lambda: rt.lookup_fwd(tex, u, t, v, out=out, image=im, stage_buckets=st)
             for _ in range(3):
                 fn()
             torch.cuda.synchronize()
@@ -949,6 +951,18 @@ def main():
                             "max_abs_diff_vs_f32_storage": float(e2e.max()),
                             "mean_abs_diff_vs_f32_storage": float(e2e.mean())}
             del e2e
+            # the same launch with bucket tiles staged in LDS
+            # (RT_FWD_STAGE_BUCKETS), bits compared with the plain launch's
+            st_out = torch.empty_like(out)
+            sfn = lambda: rt.lookup_fwd(texs[fmt], fu, ft, fv, out=st_out, image=fimg,
+                                        stage_buckets=True)
+            for _ in range(3):
+                sfn()
+            torch.cuda.synchronize()
+            sq, _ = timed_launches(sfn, 20)
+            formats[fmt]["staged_buckets_fwd_ms_p10_p50_p90"] = sq
+            formats[fmt]["staged_buckets_bitwise_equal"] = bool(torch.equal(st_out, outs[fmt]))
+            del st_out
         from scipy.stats import mannwhitneyu
         for fmt in ("bf16", "fp8"):
             for cold, tag in ((False, ""), (True, "_cold")):

@@ -53,7 +53,7 @@
 extern "C" {
 #endif
 
-#define RT_VERSION 200
+#define RT_VERSION 201
 
 typedef enum {
     RT_OK = 0,
@@ -86,8 +86,15 @@ typedef enum {
 enum {
     RT_BUCKET_NEAREST = 0,   /* one bucket per fragment: the paper's "single sample
                                 per bucket" synthesis (Sec. 2)                    */
-    RT_BUCKET_BILINEAR = 1   /* the synthesised W x H output sampled bilinearly in
+    RT_BUCKET_BILINEAR = 1,  /* the synthesised W x H output sampled bilinearly in
                                 UV: four buckets around frac(u)W - 1/2, wrapping   */
+    RT_FWD_STAGE_BUCKETS = 2 /* rt_lookup_fwd only, with RT_BUCKET_NEAREST: each
+                                wavefront groups its fragments by bucket with
+                                ballots and copies each bucket whole into LDS,
+                                where the group reads its taps; the same results
+                                bit for bit.  Plain F32 / BF16 / FP8 textures
+                                whose bucket (n*n*C samples) is a multiple of 16
+                                bytes and at most 16 KiB.                         */
 };
 
 /* Limits: 1 <= W, H <= 65536; 1 <= n <= 64; 1 <= C <= 4.  The backward
@@ -202,10 +209,13 @@ rt_status rt_quantize(const rt_texture* src, int32_t dst_format, void* dst_codes
  *   s = (B + 1) n / 2 - 1/2 in [0, n-1]^2  (sample centres at integers)
  *   bucket i = floor(frac(u) W), j = floor(frac(v) H)       (Sec. 2; nearest)
  *   out[f][c] = bilinear fetch at s inside bucket (i, j), decoded to binary32.
- * flags: RT_BUCKET_NEAREST or RT_BUCKET_BILINEAR.  out: float [N][C].
+ * flags: RT_BUCKET_NEAREST or RT_BUCKET_BILINEAR, optionally with
+ * RT_FWD_STAGE_BUCKETS (see the flags).  out: float [N][C].
  * Any storage format, RT_FMT_BIT1 included (its taps read 0 or 1).
  * Non-finite inputs give unspecified values but never out-of-bounds reads.
- * Errors: RT_ERR_INVALID_ARG (NULL/misaligned pointers, N < 0, bad flags). */
+ * Errors: RT_ERR_INVALID_ARG (NULL/misaligned pointers, N < 0, bad flags),
+ * RT_ERR_UNSUPPORTED (RT_FWD_STAGE_BUCKETS with the bilinear-bucket mode, a
+ * dictionary or 1-bit texture, or a bucket it cannot stage). */
 rt_status rt_lookup_fwd(const rt_texture* tex, const rt_fragments* frags, float* out,
                         uint32_t flags, void* stream);
 

@@ -366,14 +366,24 @@ rt_status rt_lookup_fwd(const rt_texture* t, const rt_fragments* f, float* out, 
     if (st != RT_OK) return st;
     st = check_frags(f);
     if (st != RT_OK) return st;
-    if (flags > RT_BUCKET_BILINEAR) return fail(RT_ERR_INVALID_ARG, "unknown flags 0x%x", flags);
+    if (flags & ~(uint32_t)(RT_BUCKET_BILINEAR | RT_FWD_STAGE_BUCKETS))
+        return fail(RT_ERR_INVALID_ARG, "unknown flags 0x%x", flags);
+    const bool staged = (flags & RT_FWD_STAGE_BUCKETS) != 0;
+    const int mode = (int)(flags & RT_BUCKET_BILINEAR);
+    if (staged && (mode != RT_BUCKET_NEAREST || !rt::lookup_staged_supported(t->view, t->fmt)))
+        return fail(RT_ERR_UNSUPPORTED,
+                    "RT_FWD_STAGE_BUCKETS needs nearest buckets and a plain F32/BF16/FP8 texture "
+                    "whose bucket is a multiple of 16 bytes and at most %d bytes",
+                    rt::STAGED_BUCKET_BYTES);
     if (f->count > 0) {
         if (!out) return fail(RT_ERR_INVALID_ARG, "out is NULL");
         if (!aligned(out, out_align(t->view.C)))
             return fail(RT_ERR_INVALID_ARG, "out must be %zu-byte aligned", out_align(t->view.C));
     }
-    hipError_t e = rt::launch_lookup_fwd(t->view, t->fmt, (int)flags, f->uv, f->tbn, f->view, out,
-                                         fragmap(f), (hipStream_t)stream);
+    hipError_t e = staged ? rt::launch_lookup_fwd_staged(t->view, t->fmt, f->uv, f->tbn, f->view,
+                                                         out, fragmap(f), (hipStream_t)stream)
+                          : rt::launch_lookup_fwd(t->view, t->fmt, mode, f->uv, f->tbn, f->view,
+                                                  out, fragmap(f), (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "lookup launch");
     return ok();
     RT_GUARD_END

@@ -199,8 +199,8 @@ __global__ __launch_bounds__(256) void k_bwd_fragment(
     }
     Frag g;
     if (sentinel == 0u) {
-        // every fragment contributes: its frame comes from the workgroup's
-        // staged block (all threads reach the staging barrier)
+        // every fragment contributes: its frame comes from the wavefront's
+        // staged block (every lane takes part in staging it)
         g = load_frag_block(uv, tbn, view, m, f, stage);
         if (f < 0) return;
     } else if (f < 0) {
@@ -1588,8 +1588,9 @@ hipError_t launch_exclusive_scan(const uint32_t* in, uint32_t* out, uint32_t* pa
 
 hipError_t launch_backward(const TexView& t, int fmt, int mode, const float* uv,
                            const float* tbn, const float* view, const float* grad_out,
-                           float* grad_tex, float* grad_view, float* grad_uv, const FragMap& m,
-                           const BwdPlan& plan, void* ws, hipStream_t s) {
+                           float* grad_tex, float* grad_view, float* grad_uv,
+                           const FragMap& frags, const BwdPlan& plan, void* ws, hipStream_t s) {
+    const FragMap m = with_frame_staging(frags, t, fmt);
     const int64_t N = m.N;
     char* wsb = (char*)ws;
     uint32_t* keys0 = (uint32_t*)(wsb + plan.off_keys0);

@@ -142,6 +142,20 @@ __device__ __forceinline__ F4 load_texel(const void* __restrict__ data, int64_t 
     return r;
 }
 
+// Bytes of one stored sample value (channel) in format FMT (not RT_FMT_BIT1).
+template <int FMT>
+__host__ __device__ constexpr int storage_bytes() {
+    return FMT == FMT_F32 ? 4 : FMT == FMT_BF16 ? 2 : 1;
+}
+
+// Orders a wavefront's LDS accesses before and after it (the wavefront owns
+// the memory, so no workgroup barrier is needed).
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Factor applied to a bucket's decoded samples: 1, or 256 * scale for FP8.
 template <int FMT>
 __device__ __forceinline__ float bucket_factor(const float* __restrict__ scales, int64_t b) {
@@ -166,16 +180,36 @@ struct FragMap {
     int64_t N;
     int32_t width, height;     // 0: flat
     int32_t tiles_x, tiles_y;  // tiles per row and per column of an image
+    int32_t stage;             // flat launches: stage the frames in LDS
 };
 
 inline FragMap make_fragmap(int64_t N, int32_t views, int32_t height, int32_t width) {
-    FragMap m{N, 0, 0, 0, 0};
+    FragMap m{N, 0, 0, 0, 0, 0};
     if (views > 0 && height > 0 && width > 0) {
         m.width = width;
         m.height = height;
         m.tiles_x = (width + TILE_X - 1) / TILE_X;
         m.tiles_y = (height + TILE_Y - 1) / TILE_Y;
     }
+    return m;
+}
+
+// Flat launches of the lookup and of its per-fragment backward stage their
+// fragments' frames and view vectors through LDS (load_frag_block) when the
+// texture is larger than the caches.  Then the taps come from HBM and the
+// launch is bound by its memory instructions, which the 16-byte staging
+// loads reduce; on a texture the caches hold the launch is bound by issue,
+// and the staging's LDS traffic costs more than it saves.
+constexpr int64_t STAGE_FRAMES_MIN_TEXTURE_BYTES = int64_t(1) << 30;
+
+inline FragMap with_frame_staging(FragMap m, const TexView& t, int fmt) {
+    int64_t bytes = 0;
+    if (!t.index) {
+        const int64_t buckets = (int64_t)t.W * t.H;
+        if (fmt == FMT_BIT1) bytes = buckets * bit_words(t.n) * 4;
+        else bytes = buckets * t.n * t.n * t.C * (fmt == FMT_F32 ? 4 : fmt == FMT_BF16 ? 2 : 1);
+    }
+    m.stage = m.width == 0 && bytes >= STAGE_FRAMES_MIN_TEXTURE_BYTES ? 1 : 0;
     return m;
 }
 
@@ -222,46 +256,50 @@ __device__ __forceinline__ Frag load_frag(const float* __restrict__ uv, const fl
     return r;
 }
 
-// The frames and view vectors of a flat launch's workgroup (256 consecutive
+// The frames and view vectors of a flat launch's wavefront (64 consecutive
 // fragments) staged in LDS.  A fragment's 36 + 12 bytes do not fall on a
-// lane's 16-byte vector, but the workgroup's 9216 + 3072 bytes do: the block
-// is read with 16-byte loads when both arrays are 16-byte aligned there, else
+// lane's 16-byte vector, but the wavefront's 2304 + 768 bytes do: they are
+// read with 16-byte loads when both arrays are 16-byte aligned there, else
 // with 4-byte loads, and every lane then takes its own record from LDS (a
-// stride of 9 or 3 words: no bank conflicts).  Tiled launches read per lane.
+// stride of 9 or 3 words: no bank conflicts).  Each wavefront stages its own
+// records, so no workgroup barrier couples the wavefronts.  Tiled launches
+// read per lane.
 struct FragStage {
     float tbn[256 * 9];
     float view[256 * 3];
 };
 
-// Must be reached by every thread of the workgroup (it holds a barrier when
-// the launch is flat); returns the record of fragment f (f >= 0).
+// Returns the record of fragment f (f >= 0); every lane of a wavefront must
+// reach it together.
 __device__ __forceinline__ Frag load_frag_block(const float* __restrict__ uv,
                                                 const float* __restrict__ tbn,
                                                 const float* __restrict__ view, const FragMap& m,
                                                 int64_t f, FragStage& s) {
-    if (m.width != 0) return f >= 0 ? load_frag(uv, tbn, view, f) : Frag{};
-    const int tid = threadIdx.x;
-    const int64_t f0 = (int64_t)xcd_block_id(blockIdx.x, gridDim.x) * 256;
-    const int nf = (int)(m.N - f0 < 256 ? m.N - f0 : 256);
+    if (m.width != 0 || !m.stage) return f >= 0 ? load_frag(uv, tbn, view, f) : Frag{};
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t f0 = (int64_t)xcd_block_id(blockIdx.x, gridDim.x) * 256 + w * 64;
+    const int nf = (int)(m.N - f0 < 64 ? (m.N - f0 > 0 ? m.N - f0 : 0) : 64);
     const float* bt = tbn + f0 * 9;
     const float* bv = view + f0 * 3;
-    if (nf == 256 && ((((uintptr_t)bt) | ((uintptr_t)bv)) & 15) == 0) {
-        for (int q = tid; q < 576; q += 256) ((f4v*)s.tbn)[q] = ((const f4v*)bt)[q];
-        if (tid < 192) ((f4v*)s.view)[tid] = ((const f4v*)bv)[tid];
+    float* st = s.tbn + w * 64 * 9;
+    float* sv = s.view + w * 64 * 3;
+    if (nf == 64 && ((((uintptr_t)bt) | ((uintptr_t)bv)) & 15) == 0) {
+        for (int q = lane; q < 144; q += 64) ((f4v*)st)[q] = ((const f4v*)bt)[q];
+        if (lane < 48) ((f4v*)sv)[lane] = ((const f4v*)bv)[lane];
     } else {
-        for (int q = tid; q < nf * 9; q += 256) s.tbn[q] = bt[q];
-        for (int q = tid; q < nf * 3; q += 256) s.view[q] = bv[q];
+        for (int q = lane; q < nf * 9; q += 64) st[q] = bt[q];
+        for (int q = lane; q < nf * 3; q += 64) sv[q] = bv[q];
     }
-    __syncthreads();
+    wave_lds_sync();
     Frag r{};
     if (f >= 0) {
         const float2 t = ((const float2*)uv)[f];
         r.u = t.x;
         r.v = t.y;
 #pragma unroll
-        for (int k = 0; k < 9; k++) r.m[k] = s.tbn[tid * 9 + k];
+        for (int k = 0; k < 9; k++) r.m[k] = st[lane * 9 + k];
 #pragma unroll
-        for (int k = 0; k < 3; k++) r.w[k] = s.view[tid * 3 + k];
+        for (int k = 0; k < 3; k++) r.w[k] = sv[lane * 3 + k];
     }
     return r;
 }

@@ -57,6 +57,14 @@ void prof_end(int id, hipStream_t s);
 hipError_t launch_lookup_fwd(const TexView& t, int fmt, int mode, const float* uv,
                              const float* tbn, const float* view, float* out, const FragMap& m,
                              hipStream_t s);
+// The forward with bucket tiles staged in LDS (nearest buckets): supported
+// for plain F32 / BF16 / FP8 textures whose bucket is a multiple of 16 bytes
+// and at most STAGED_BUCKET_BYTES (four wavefronts' tiles per workgroup).
+constexpr int STAGED_BUCKET_BYTES = 16384;
+bool lookup_staged_supported(const TexView& t, int fmt);
+hipError_t launch_lookup_fwd_staged(const TexView& t, int fmt, const float* uv, const float* tbn,
+                                    const float* view, float* out, const FragMap& m,
+                                    hipStream_t s);
 hipError_t launch_debug_indices(const TexView& t, const float* uv, const float* tbn,
                                 const float* view, int32_t* idx, float* frac, const FragMap& m,
                                 hipStream_t s);

@@ -16,6 +16,25 @@
 
 namespace rt {
 
+// The four taps around footprint p of the bucket whose first texel is at
+// `bucket` (global memory or a copy in LDS), blended and added to acc with
+// factor f.
+template <int FMT, int C>
+__device__ __forceinline__ void blend_taps(const void* bucket, int n, const Foot& p, float f,
+                                           float acc[4]) {
+    F4 t00 = load_texel<FMT, C>(bucket, p.y0 * n + p.x0);
+    F4 t01 = load_texel<FMT, C>(bucket, p.y0 * n + p.x1);
+    F4 t10 = load_texel<FMT, C>(bucket, p.y1 * n + p.x0);
+    F4 t11 = load_texel<FMT, C>(bucket, p.y1 * n + p.x1);
+    float w00 = (1.f - p.fx) * (1.f - p.fy), w01 = p.fx * (1.f - p.fy);
+    float w10 = (1.f - p.fx) * p.fy, w11 = p.fx * p.fy;
+#pragma unroll
+    for (int c = 0; c < C; c++) {
+        float v = w00 * t00.v[c] + w01 * t01.v[c] + w10 * t10.v[c] + w11 * t11.v[c];
+        acc[c] += f * v;
+    }
+}
+
 // The four taps of bucket b around footprint p, blended and added to acc
 // with weight wgt.  DICT: b is read through the dictionary (its entry in the
 // codebook, times its gain).
@@ -40,19 +59,9 @@ __device__ __forceinline__ void bucket_bilerp(const TexView& t, int64_t b, const
         acc[0] += wgt * v;
         return;
     }
-    const int64_t base = b * (int64_t)(n * n);
-    F4 t00 = load_texel<FMT, C>(t.data, base + p.y0 * n + p.x0);
-    F4 t01 = load_texel<FMT, C>(t.data, base + p.y0 * n + p.x1);
-    F4 t10 = load_texel<FMT, C>(t.data, base + p.y1 * n + p.x0);
-    F4 t11 = load_texel<FMT, C>(t.data, base + p.y1 * n + p.x1);
-    float f = wgt * bucket_factor<FMT>(t.scales, b);
-    float w00 = (1.f - p.fx) * (1.f - p.fy), w01 = p.fx * (1.f - p.fy);
-    float w10 = (1.f - p.fx) * p.fy, w11 = p.fx * p.fy;
-#pragma unroll
-    for (int c = 0; c < C; c++) {
-        float v = w00 * t00.v[c] + w01 * t01.v[c] + w10 * t10.v[c] + w11 * t11.v[c];
-        acc[c] += f * v;
-    }
+    const unsigned char* bucket =
+        (const unsigned char*)t.data + b * (int64_t)(n * n) * C * storage_bytes<FMT>();
+    blend_taps<FMT, C>(bucket, n, p, wgt * bucket_factor<FMT>(t.scales, b), acc);
 }
 
 // The lookup's output is written once and not read back by the library: it
@@ -94,6 +103,53 @@ __global__ __launch_bounds__(256) void k_lookup_fwd(TexView t, const float* __re
         bucket_bilerp<FMT, C, DICT>(t, (int64_t)j1 * t.W + i1, p, a * bb, acc);
     }
     store_out<C>(out, f, acc);
+}
+
+// The forward with bucket tiles staged in LDS (nearest buckets, plain
+// textures): per wavefront, the bucket of the first fragment still to serve
+// is found with a ballot, every lane whose fragment lies in that bucket joins
+// the group, the wavefront copies the whole bucket into its LDS tile with
+// 16-byte loads, and the group blends its taps from LDS; repeated until every
+// fragment is served.  The blend is blend_taps on the copy, so the results
+// are those of k_lookup_fwd bit for bit.  It pays only where a wavefront's
+// fragments share few buckets and read much of each.
+template <int FMT, int C>
+__global__ __launch_bounds__(256) void k_lookup_fwd_staged(TexView t, const float* __restrict__ uv,
+                                                           const float* __restrict__ tbn,
+                                                           const float* __restrict__ view,
+                                                           float* __restrict__ out, FragMap m) {
+    extern __shared__ uint4 tiles[];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int bucket_bytes = t.n * t.n * C * storage_bytes<FMT>();  // a multiple of 16
+    uint4* mine = tiles + w * (bucket_bytes / 16);
+    const int64_t f = frag_of(m, blockIdx.x, gridDim.x, threadIdx.x);
+    const bool live = f >= 0;
+    Foot p{};
+    int64_t b = -1;
+    if (live) {
+        const Frag g = load_frag(uv, tbn, view, f);
+        const Dir d = map_direction(g.m, g.w, t.n);
+        p = footprint(d.sx, d.sy, t.n);
+        b = (int64_t)bucket_of(g.v, t.H) * t.W + bucket_of(g.u, t.W);
+    }
+    float acc[4] = {0.f, 0.f, 0.f, 0.f};
+    uint64_t todo = __ballot(live);
+    while (todo != 0ull) {
+        const int leader = __builtin_ctzll(todo);
+        const uint32_t lo = __builtin_amdgcn_readfirstlane(__shfl((uint32_t)b, leader, 64));
+        const uint32_t hi =
+            __builtin_amdgcn_readfirstlane(__shfl((uint32_t)((uint64_t)b >> 32), leader, 64));
+        const int64_t bk = (int64_t)(((uint64_t)hi << 32) | lo);
+        const uint64_t grp = __ballot(live && b == bk);
+        const uint4* src = (const uint4*)((const unsigned char*)t.data + bk * bucket_bytes);
+        for (int q = lane; q < bucket_bytes / 16; q += 64) mine[q] = src[q];
+        wave_lds_sync();
+        if ((grp >> lane) & 1ull)
+            blend_taps<FMT, C>(mine, t.n, p, 1.0f * bucket_factor<FMT>(t.scales, bk), acc);
+        wave_lds_sync();
+        todo &= ~grp;
+    }
+    if (live) store_out<C>(out, f, acc);
 }
 
 __global__ __launch_bounds__(256) void k_debug_indices(TexView t, const float* __restrict__ uv,
@@ -192,10 +248,45 @@ static hipError_t launch_fwd_c(const TexView& t, const float* uv, const float* t
     return hipGetLastError();
 }
 
-hipError_t launch_lookup_fwd(const TexView& t, int fmt, int mode, const float* uv,
-                             const float* tbn, const float* view, float* out, const FragMap& m,
-                             hipStream_t s) {
+template <int FMT>
+static hipError_t launch_fwd_staged_c(const TexView& t, const float* uv, const float* tbn,
+                                      const float* view, float* out, const FragMap& m,
+                                      hipStream_t s) {
+    const uint32_t blocks = fragmap_blocks(m);
+    const size_t shm = (size_t)4 * t.n * t.n * t.C * storage_bytes<FMT>();
+    switch (t.C) {
+    case 1: hipLaunchKernelGGL((k_lookup_fwd_staged<FMT, 1>), dim3(blocks), dim3(256), shm, s, t, uv, tbn, view, out, m); break;
+    case 2: hipLaunchKernelGGL((k_lookup_fwd_staged<FMT, 2>), dim3(blocks), dim3(256), shm, s, t, uv, tbn, view, out, m); break;
+    case 3: hipLaunchKernelGGL((k_lookup_fwd_staged<FMT, 3>), dim3(blocks), dim3(256), shm, s, t, uv, tbn, view, out, m); break;
+    default: hipLaunchKernelGGL((k_lookup_fwd_staged<FMT, 4>), dim3(blocks), dim3(256), shm, s, t, uv, tbn, view, out, m); break;
+    }
+    return hipGetLastError();
+}
+
+bool lookup_staged_supported(const TexView& t, int fmt) {
+    if (t.index || (fmt != FMT_F32 && fmt != FMT_BF16 && fmt != FMT_FP8)) return false;
+    const int64_t bytes = (int64_t)t.n * t.n * t.C * (fmt == FMT_F32 ? 4 : fmt == FMT_BF16 ? 2 : 1);
+    return bytes % 16 == 0 && bytes <= STAGED_BUCKET_BYTES;
+}
+
+hipError_t launch_lookup_fwd_staged(const TexView& t, int fmt, const float* uv, const float* tbn,
+                                    const float* view, float* out, const FragMap& m,
+                                    hipStream_t s) {
     if (m.N <= 0) return hipSuccess;
+    hipError_t e;
+    prof_begin(K_LOOKUP_FWD, s);
+    if (fmt == FMT_F32) e = launch_fwd_staged_c<FMT_F32>(t, uv, tbn, view, out, m, s);
+    else if (fmt == FMT_BF16) e = launch_fwd_staged_c<FMT_BF16>(t, uv, tbn, view, out, m, s);
+    else e = launch_fwd_staged_c<FMT_FP8>(t, uv, tbn, view, out, m, s);
+    prof_end(K_LOOKUP_FWD, s);
+    return e;
+}
+
+hipError_t launch_lookup_fwd(const TexView& t, int fmt, int mode, const float* uv,
+                             const float* tbn, const float* view, float* out, const FragMap& frags,
+                             hipStream_t s) {
+    if (frags.N <= 0) return hipSuccess;
+    const FragMap m = with_frame_staging(frags, t, fmt);
     hipError_t e;
     prof_begin(K_LOOKUP_FWD, s);
     const uint32_t blocks = fragmap_blocks(m);

@@ -20,6 +20,7 @@ RT_OK = 0
 RT_FMT_F32, RT_FMT_BF16, RT_FMT_FP8_E4M3, RT_FMT_BIT1 = 0, 1, 2, 3
 RT_LAYOUT_BUCKET_MAJOR, RT_LAYOUT_ATLAS = 0, 1
 RT_BUCKET_NEAREST, RT_BUCKET_BILINEAR = 0, 1
+RT_FWD_STAGE_BUCKETS = 2
 RT_LIGHT_DIRECTIONAL, RT_LIGHT_POINT = 0, 1
 RT_MAX_LIGHT_SAMPLES = 64
 
@@ -298,13 +299,16 @@ def quantize(tex: Texture, fmt: str):
     return codes, scales
 
 
-def lookup_fwd(tex: Texture, uv, tbn, view, mode: str = "nearest", out=None, image=None):
+def lookup_fwd(tex: Texture, uv, tbn, view, mode: str = "nearest", out=None, image=None,
+               stage_buckets: bool = False):
+    """rt_lookup_fwd; stage_buckets adds RT_FWD_STAGE_BUCKETS (nearest mode)."""
     fr = _frags(uv, tbn, view, image)
     if out is None:
         out = torch.empty((fr.count, tex.C), dtype=torch.float32, device=tex.device)
     else:
         _need_gpu(out, "out", torch.float32)
-    _check(LIB.rt_lookup_fwd(tex.handle, ctypes.byref(fr), _ptr(out), MODES[mode],
+    flags = MODES[mode] | (RT_FWD_STAGE_BUCKETS if stage_buckets else 0)
+    _check(LIB.rt_lookup_fwd(tex.handle, ctypes.byref(fr), _ptr(out), flags,
                              _stream(tex.device)))
     return out
 

@@ -42,7 +42,7 @@ def test_library_exports_every_declared_symbol(rt):
 
 
 def test_version_and_status_strings(rt):
-    assert rt.LIB.rt_version() == 200
+    assert rt.LIB.rt_version() == 201
     assert rt.LIB.rt_status_string(0) == b"RT_OK"
     assert rt.LIB.rt_status_string(4) == b"RT_ERR_WORKSPACE_TOO_SMALL"
     assert rt.LIB.rt_profile_kernel_count() >= 10
