@@ -989,9 +989,63 @@ __device__ __forceinline__ void accumulate_tails(int cell, const float v[4 * C],
     wave_sync_lds();
 }
 
+// A sorted record as loaded: its key, its bilinear fractions and its upstream
+// gradient times the bucket weight (1 in nearest mode).
+template <int C>
+struct RawRec {
+    uint32_t key;
+    float fx, fy;
+    float g[C];
+};
+
+template <int C, int MODE>
+__device__ __forceinline__ void load_raw(const uint32_t* __restrict__ skeys,
+                                         const uint32_t* __restrict__ svals,
+                                         const float* __restrict__ wrec,
+                                         const float* __restrict__ grad_out, int64_t i,
+                                         RawRec<C>& r) {
+    r.key = skeys[i];
+    const uint32_t rec = svals ? svals[i] : (uint32_t)i;
+    float wb = 1.f;
+    int64_t frag;
+    if constexpr (MODE == MODE_NEAREST) {
+        frag = rec;
+        const float2 w2 = ((const float2*)wrec)[frag];
+        r.fx = w2.x;
+        r.fy = w2.y;
+    } else {
+        frag = rec >> 2;
+        const int k = rec & 3;
+        const float4 w4 = ((const float4*)wrec)[frag];
+        r.fx = w4.x;
+        r.fy = w4.y;
+        const float aa = w4.z, bb = w4.w;
+        wb = (k == 0) ? (1.f - aa) * (1.f - bb)
+                      : (k == 1) ? aa * (1.f - bb) : (k == 2) ? (1.f - aa) * bb : aa * bb;
+    }
+#pragma unroll
+    for (int c = 0; c < C; c++) r.g[c] = grad_out[frag * C + c] * wb;
+}
+
+// The four tap contributions of a loaded record, as load_record forms them.
+template <int C>
+__device__ __forceinline__ void expand_raw(const RawRec<C>& r, float v[4 * C]) {
+    const float w00 = (1.f - r.fx) * (1.f - r.fy), w01 = r.fx * (1.f - r.fy);
+    const float w10 = (1.f - r.fx) * r.fy, w11 = r.fx * r.fy;
+#pragma unroll
+    for (int c = 0; c < C; c++) {
+        const float gc = r.g[c];
+        v[0 * C + c] = w00 * gc;
+        v[1 * C + c] = w01 * gc;
+        v[2 * C + c] = w10 * gc;
+        v[3 * C + c] = w11 * gc;
+    }
+}
+
 // Reduce sorted records [a, e) (all of one bucket) into the wave's LDS tile
 // (zeroed by the caller), in rounds of 64 records.  A cell that runs past a
-// round carries its partial sum into the next round's first lane.
+// round carries its partial sum into the next round's first lane.  Each
+// round's records are loaded while the round before is summed.
 template <int C, int MODE>
 __device__ __forceinline__ void reduce_records(const uint32_t* __restrict__ skeys,
                                                const uint32_t* __restrict__ svals,
@@ -1005,14 +1059,20 @@ __device__ __forceinline__ void reduce_records(const uint32_t* __restrict__ skey
 #pragma unroll
     for (int q = 0; q < F; q++) carry[q] = 0.f;
     int carry_cell = -1;
+    RawRec<C> cur{}, nxt{};
+    if (a + lane < e) load_raw<C, MODE>(skeys, svals, wrec, grad_out, a + lane, cur);
     for (int64_t base = a; base < e; base += 64) {
         const int64_t i = base + lane;
         const bool valid = i < e;
+        if (i + 64 < e) load_raw<C, MODE>(skeys, svals, wrec, grad_out, i + 64, nxt);
         int cell = -2 - lane;  // distinct from every real cell and from each other
         float v[F];
 #pragma unroll
         for (int q = 0; q < F; q++) v[q] = 0.f;
-        if (valid) cell = load_record<C, MODE>(skeys, svals, wrec, grad_out, i, cell_mask, v);
+        if (valid) {
+            cell = (int)(cur.key & cell_mask);
+            expand_raw<C>(cur, v);
+        }
         if (lane == 0 && cell == carry_cell) {
 #pragma unroll
             for (int q = 0; q < F; q++) v[q] = carry[q] + v[q];
@@ -1020,7 +1080,9 @@ __device__ __forceinline__ void reduce_records(const uint32_t* __restrict__ skey
         const int next_cell = __shfl_down(cell, 1, 64);
         bool next_same = valid && lane < 63 && i + 1 < e && next_cell == cell;
         bool spills = false;
-        if (valid && lane == 63 && i + 1 < e) spills = (int)(skeys[i + 1] & cell_mask) == cell;
+        // record i + 1 of lane 63 is the next round's first
+        const uint32_t key_after = __shfl(nxt.key, 0, 64);
+        if (valid && lane == 63 && i + 1 < e) spills = (int)(key_after & cell_mask) == cell;
         // the scan runs before the carry is taken from lane 63
         accumulate_round<C>(cell, v, valid, next_same || spills, n, tile);
         if (__ballot(spills) != 0ull) {
@@ -1030,6 +1092,7 @@ __device__ __forceinline__ void reduce_records(const uint32_t* __restrict__ skey
         } else {
             carry_cell = -1;
         }
+        cur = nxt;
     }
 }
 
@@ -1291,17 +1354,29 @@ __global__ __launch_bounds__(256) void k_segacc_big(const uint32_t* __restrict__
     }
     extern __shared__ float lds[];
     const int te = n * n * C;
-    const int w = threadIdx.x >> 6;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     float* tile = lds + w * te;
     const uint32_t list = blockIdx.x % BIG_LISTS;
     const uint32_t part = blockIdx.x / BIG_LISTS, parts = gridDim.x / BIG_LISTS;
     const uint32_t count = __builtin_amdgcn_readfirstlane(big_count[list * BIG_STRIDE]);
     const uint32_t* entries = big_list + list * big_cap;
-    for (uint32_t e = part * 4 + w; e < count; e += parts * 4) {
-        const uint32_t b = __builtin_amdgcn_readfirstlane(entries[e]);
-        const int2 r = range[b];
-        const int rx = __builtin_amdgcn_readfirstlane(r.x);
-        const int ry = __builtin_amdgcn_readfirstlane(r.y);
+    const uint32_t stride = parts * 4;
+    // the next listed bucket and its range are read while this one is summed
+    uint32_t e = part * 4 + w;
+    uint32_t b_next = 0;
+    int2 r_next = make_int2(0, 0);
+    if (e < count) {
+        b_next = __builtin_amdgcn_readfirstlane(entries[e]);
+        r_next = range[b_next];
+    }
+    for (; e < count; e += stride) {
+        const uint32_t b = b_next;
+        const int rx = __builtin_amdgcn_readfirstlane(r_next.x);
+        const int ry = __builtin_amdgcn_readfirstlane(r_next.y);
+        if (e + stride < count) {
+            b_next = __builtin_amdgcn_readfirstlane(entries[e + stride]);
+            r_next = range[b_next];
+        }
         float* dst = tile_dst(out, b, te);
         if (!dst) continue;
         tile_zero(tile, te);
