@@ -46,14 +46,6 @@ constexpr int SORT_TILE = SORT_THREADS * SORT_IPT;  // 4096
 constexpr int SCAN_TILE = 4096;
 constexpr int64_t SCAN_FUSED_BLOCKS = 4096;
 
-// orders one wavefront's LDS accesses before and after it
-__device__ __forceinline__ void wave_sync_lds() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-
 // ---------------------------------------------------------------------------
 // 1. per-fragment backward
 // ---------------------------------------------------------------------------
@@ -692,9 +684,9 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_scatter(
         const uint32_t rank = (uint32_t)__popcll(peers & lt_mask);
         const uint32_t before = valid ? wcnt[w][dg] : 0u;
         loc[r] = before + rank;
-        wave_sync_lds();
+        wave_lds_sync();
         if (valid && rank == 0) wcnt[w][dg] = before + (uint32_t)__popcll(peers);
-        wave_sync_lds();
+        wave_lds_sync();
     }
     __syncthreads();
     // digits: prefixes over the waves, and the tile's exclusive scan over digits
@@ -883,46 +875,6 @@ __device__ __forceinline__ void load_payg(const float* __restrict__ payg, int64_
     }
 }
 
-// The four tap contributions of sorted record i: v = (w00, w01, w10, w11) x g
-// times the bucket weight (1 in nearest mode); returns the record's cell.
-template <int C, int MODE>
-__device__ __forceinline__ int load_record(const uint32_t* __restrict__ skeys,
-                                           const uint32_t* __restrict__ svals,
-                                           const float* __restrict__ wrec,
-                                           const float* __restrict__ grad_out, int64_t i,
-                                           uint32_t cell_mask, float v[4 * C]) {
-    const uint32_t key = skeys[i];
-    const uint32_t rec = svals ? svals[i] : (uint32_t)i;
-    float fx, fy, wb = 1.f;
-    int64_t frag;
-    if constexpr (MODE == MODE_NEAREST) {
-        frag = rec;
-        float2 w2 = ((const float2*)wrec)[frag];
-        fx = w2.x;
-        fy = w2.y;
-    } else {
-        frag = rec >> 2;
-        const int k = rec & 3;
-        float4 w4 = ((const float4*)wrec)[frag];
-        fx = w4.x;
-        fy = w4.y;
-        const float aa = w4.z, bb = w4.w;
-        wb = (k == 0) ? (1.f - aa) * (1.f - bb)
-                      : (k == 1) ? aa * (1.f - bb) : (k == 2) ? (1.f - aa) * bb : aa * bb;
-    }
-    const float w00 = (1.f - fx) * (1.f - fy), w01 = fx * (1.f - fy);
-    const float w10 = (1.f - fx) * fy, w11 = fx * fy;
-#pragma unroll
-    for (int c = 0; c < C; c++) {
-        const float gc = grad_out[frag * C + c] * wb;
-        v[0 * C + c] = w00 * gc;
-        v[1 * C + c] = w01 * gc;
-        v[2 * C + c] = w10 * gc;
-        v[3 * C + c] = w11 * gc;
-    }
-    return (int)(key & cell_mask);
-}
-
 // One round of up to 64 sorted records of one bucket, one record per lane
 // (lanes without a record carry a cell no record has).  The four tap
 // contributions are summed per cell by an inclusive segmented scan across
@@ -966,27 +918,27 @@ __device__ __forceinline__ void accumulate_tails(int cell, const float v[4 * C],
         x1 = min(x0 + 1, n - 1);
         y1 = min(y0 + 1, n - 1);
     }
-    wave_sync_lds();
+    wave_lds_sync();
     if (tail) {
 #pragma unroll
         for (int c = 0; c < C; c++) tile[(y0 * n + x0) * C + c] += v[0 * C + c];
     }
-    wave_sync_lds();
+    wave_lds_sync();
     if (tail) {
 #pragma unroll
         for (int c = 0; c < C; c++) tile[(y0 * n + x1) * C + c] += v[1 * C + c];
     }
-    wave_sync_lds();
+    wave_lds_sync();
     if (tail) {
 #pragma unroll
         for (int c = 0; c < C; c++) tile[(y1 * n + x0) * C + c] += v[2 * C + c];
     }
-    wave_sync_lds();
+    wave_lds_sync();
     if (tail) {
 #pragma unroll
         for (int c = 0; c < C; c++) tile[(y1 * n + x1) * C + c] += v[3 * C + c];
     }
-    wave_sync_lds();
+    wave_lds_sync();
 }
 
 // A sorted record as loaded: its key, its bilinear fractions and its upstream
@@ -1027,7 +979,7 @@ __device__ __forceinline__ void load_raw(const uint32_t* __restrict__ skeys,
     for (int c = 0; c < C; c++) r.g[c] = grad_out[frag * C + c] * wb;
 }
 
-// The four tap contributions of a loaded record, as load_record forms them.
+// The four tap contributions of a loaded record: v = (w00, w01, w10, w11) x g.
 template <int C>
 __device__ __forceinline__ void expand_raw(const RawRec<C>& r, float v[4 * C]) {
     const float w00 = (1.f - r.fx) * (1.f - r.fy), w01 = r.fx * (1.f - r.fy);
@@ -1201,21 +1153,21 @@ __device__ __forceinline__ void tile_zero(float* tile, int te) {
     } else {
         for (int q = lane; q < te; q += 64) tile[q] = 0.f;
     }
-    wave_sync_lds();
+    wave_lds_sync();
 }
 
 // The dense gradient is written once and not read back by this library, so
 // its stores are non-temporal (streamed past the caches).
 __device__ __forceinline__ void tile_store(const float* tile, float* __restrict__ dst, int te) {
     const int lane = threadIdx.x & 63;
-    wave_sync_lds();
+    wave_lds_sync();
     if ((te & 255) == 0) {
         for (int q = lane; q < te / 4; q += 64)
             __builtin_nontemporal_store(((const f4v*)tile)[q], (f4v*)dst + q);
     } else {
         for (int q = lane; q < te; q += 64) __builtin_nontemporal_store(tile[q], dst + q);
     }
-    wave_sync_lds();
+    wave_lds_sync();
 }
 
 // Destination of the tile of bucket b (wave-uniform), or nullptr when the
@@ -1423,7 +1375,7 @@ __global__ __launch_bounds__(64) void k_segacc_hot(const uint32_t* __restrict__ 
         tile_zero(lds, te);
         reduce_records<C, MODE>(skeys, svals, wrec, grad_out, a, e, n, cell_mask, lds);
         tile_store(lds, part + (k * 2 + slot) * (int64_t)te, te);
-        wave_sync_lds();
+        wave_lds_sync();
     }
 }
 

@@ -147,12 +147,6 @@ __global__ __launch_bounds__(256) void k_bake_env(int64_t nbuckets, int n,
 // which cancels when the ray points at the centre.  A wave ballot packs 64
 // samples into two words; samples past n n give 0, which clears the padding
 // bits of the last word.
-__device__ __forceinline__ void wave_sync_lds() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 __global__ __launch_bounds__(256) void k_bake_shadow(int64_t nbuckets, int n,
                                                      const float* __restrict__ origins,
                                                      const float* __restrict__ frames,
@@ -197,7 +191,7 @@ __global__ __launch_bounds__(256) void k_bake_shadow(int64_t nbuckets, int n,
             inside = ex * ex + ey * ey + ez * ez <= r2;
         }
         const bool blocked = __ballot(inside) != 0;
-        wave_sync_lds();
+        wave_lds_sync();
         for (int c = 0; c < chunks; c++) {
             const int k = c * 64 + lane;
             bool lit = false;
@@ -224,7 +218,7 @@ __global__ __launch_bounds__(256) void k_bake_shadow(int64_t nbuckets, int n,
             if (lane < 2 && w < wpb)
                 words[b * wpb + w] = lane == 0 ? (uint32_t)bits : (uint32_t)(bits >> 32);
         }
-        wave_sync_lds();  // the next bucket rewrites this wave's ball terms
+        wave_lds_sync();  // the next bucket rewrites this wave's ball terms
     }
 }
 
