@@ -314,7 +314,9 @@ rt_status rt_plan_fragments(const rt_texture* tex, const rt_fragments* frags, ui
  * targets, weights, an upstream gradient), with RT_PLAN_SCATTER
  * dst[order[k]] = src[k] (plan-order results back to the caller's order).
  * order: DEVICE int32 [count], a permutation of 0..count-1 (as written by
- * rt_plan_fragments; other values give undefined results).  src, dst: DEVICE
+ * rt_plan_fragments); an entry outside 0..count-1 moves no row (its
+ * destination row keeps its contents), and a repeated entry leaves which of
+ * its rows a scatter keeps unspecified.  src, dst: DEVICE
  * arrays of count rows of row_bytes bytes (a multiple of 4, at most 4096),
  * 4-byte aligned (16-byte rows and alignment take 16-byte accesses), not
  * overlapping.  Asynchronous on `stream`.

@@ -1877,6 +1877,7 @@ __global__ __launch_bounds__(256) void k_permute_rows(const int32_t* __restrict_
     const int64_t k = (int64_t)xcd_block_id(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
     if (k >= N) return;
     const int64_t o = order[k];
+    if (o < 0 || o >= N) return;  // not an index of the array: no row moves
     const int64_t from = scatter ? k : o, to = scatter ? o : k;
     if constexpr (VEC) {
         const int q = row / 4;

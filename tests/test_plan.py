@@ -240,6 +240,27 @@ def test_plan_permute_gathers_and_scatters_rows(rt, cols, dtype):
         assert torch.equal(rt.plan_permute(order, s2), s2[order.long()])
 
 
+def test_plan_permute_skips_entries_that_are_not_indices(rt):
+    """Entries outside 0..count-1 move no row; the others move as usual."""
+    N = 5000
+    order = torch.arange(N, device=DEV, dtype=torch.int32).flip(0).contiguous()
+    bad = torch.tensor([0, 17, N - 1], device=DEV)
+    order[bad] = torch.tensor([-1, N, 2 ** 31 - 1], device=DEV, dtype=torch.int32)
+    src = torch.randn((N, 4), device=DEV)
+    dst = torch.full((N, 4), 7.0, device=DEV)
+    rt.plan_permute(order, src, out=dst)
+    back = torch.full((N, 4), 7.0, device=DEV)
+    rt.plan_permute(order, src, out=back, scatter=True)
+    torch.cuda.synchronize()
+    ok = torch.ones(N, dtype=torch.bool, device=DEV)
+    ok[bad] = False
+    o = order.long()
+    assert torch.equal(dst[ok], src[o[ok]])
+    assert torch.all(dst[~ok] == 7.0)
+    assert torch.equal(back[o[ok]], src[ok])
+    assert int((back == 7.0).all(1).sum()) == 3
+
+
 def test_plan_permute_validation(rt):
     order = torch.arange(8, dtype=torch.int32, device=DEV)
     x = torch.zeros((8, 4), device=DEV)
