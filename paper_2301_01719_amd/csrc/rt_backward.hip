@@ -496,6 +496,32 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_hist(const uint32_t* __r
     for (int d = t; d < B; d += SORT_THREADS) hist[(int64_t)d * tiles + tile] = cnt[d];
 }
 
+// x from the lane `o` below in the wavefront, for a power of two o < 64;
+// lanes under `o` receive some lane's x, which their callers mask.  Offsets
+// 1 and 2 take one or two DPP wavefront shifts (wave_shr:1) on the vector ALU
+// instead of a trip through the LDS crossbar (ds_bpermute); the value is the
+// same either way, so the segmented scans below add in the same order
+__device__ __forceinline__ int dpp_shr1(int x) {
+    return __builtin_amdgcn_update_dpp(x, x, 0x138, 0xF, 0xF, false);
+}
+__device__ __forceinline__ int lanes_up(int x, int o) {
+    if (o == 1) return dpp_shr1(x);
+    if (o == 2) return dpp_shr1(dpp_shr1(x));
+    return __shfl_up(x, o, 64);
+}
+__device__ __forceinline__ uint32_t lanes_up(uint32_t x, int o) {
+    return (uint32_t)lanes_up((int)x, o);
+}
+__device__ __forceinline__ float lanes_up(float x, int o) {
+    return __int_as_float(lanes_up(__float_as_int(x), o));
+}
+// x from the lane one above (lane 63 receives its own x): one DPP wavefront
+// shift (wave_shl:1)
+__device__ __forceinline__ int lane_above(int x) {
+    return __builtin_amdgcn_update_dpp(x, x, 0x130, 0xF, 0xF, false);
+}
+__device__ __forceinline__ uint32_t lane_above(uint32_t x) { return (uint32_t)lane_above((int)x); }
+
 // exclusive prefix of v over the 256 threads of the block; *total receives the sum
 __device__ __forceinline__ uint32_t block_exclusive(uint32_t v, uint32_t* wsum, uint32_t* total) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -894,12 +920,12 @@ __device__ __forceinline__ void accumulate_round(int cell, float v[4 * C], bool 
     // distance o every run is at most o long and the scan is complete
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
-        const int oc = __shfl_up(cell, o, 64);
+        const int oc = lanes_up(cell, o);
         const bool same = lane >= o && oc == cell;
         if (__ballot(same) == 0ull) break;
 #pragma unroll
         for (int q = 0; q < F; q++) {
-            const float ov = __shfl_up(v[q], o, 64);
+            const float ov = lanes_up(v[q], o);
             if (same) v[q] += ov;
         }
     }
@@ -1029,7 +1055,7 @@ __device__ __forceinline__ void reduce_records(const uint32_t* __restrict__ skey
 #pragma unroll
             for (int q = 0; q < F; q++) v[q] = carry[q] + v[q];
         }
-        const int next_cell = __shfl_down(cell, 1, 64);
+        const int next_cell = lane_above(cell);
         bool next_same = valid && lane < 63 && i + 1 < e && next_cell == cell;
         bool spills = false;
         // record i + 1 of lane 63 is the next round's first
@@ -1132,16 +1158,16 @@ __device__ __forceinline__ void scan_window(const RecWindow<C>& w, float v[4 * C
     }
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
-        const uint32_t ok = __shfl_up(w.key, o, 64);
+        const uint32_t ok = lanes_up(w.key, o);
         const bool same = valid && lane >= o && ok == w.key;
         if (__ballot(same) == 0ull) break;
 #pragma unroll
         for (int q = 0; q < 4 * C; q++) {
-            const float ov = __shfl_up(v[q], o, 64);
+            const float ov = lanes_up(v[q], o);
             if (same) v[q] += ov;
         }
     }
-    const uint32_t nk = __shfl_down(w.key, 1, 64);
+    const uint32_t nk = lane_above(w.key);
     tail = valid && (lane == 63 || i + 1 >= w.end || nk != w.key);
 }
 
