@@ -2,9 +2,9 @@
 // of shadow textures, and the atlas -> bucket-major re-layout, for gfx950.
 //
 // All are HBM streams.  BF16 is elementwise (float4 in, 4 x bf16 out).  FP8
-// runs one wavefront per bucket: the bucket's amax is reduced across the wave
-// with cross-lane max, then every lane encodes its values with the bucket's
-// inverse scale.  Encodes are written from the formats' definitions with
+// runs one or two wavefronts per bucket: the bucket's amax is reduced across
+// the wave with cross-lane max (and between the two waves through LDS), then
+// every lane encodes its values with the bucket's inverse scale.  Encodes are written from the formats' definitions with
 // integer arithmetic (round to nearest even, E4M3 saturating to +-448).
 #include <algorithm>
 
@@ -36,6 +36,24 @@ __device__ __forceinline__ uint32_t f32_to_e4m3_bits(float y) {
     // carry moves into the exponent field, which is the right result
     uint32_t r = a + 0x7FFFFu + ((a >> 20) & 1u);
     return sign | ((r >> 20) - (120u << 3));
+}
+
+// Codes of v * inv, byte k from component k, by the software encoder.
+__device__ __forceinline__ uint32_t e4m3_pack4(f4v v, float inv) {
+    return f32_to_e4m3_bits(v.x * inv) | (f32_to_e4m3_bits(v.y * inv) << 8) |
+           (f32_to_e4m3_bits(v.z * inv) << 16) | (f32_to_e4m3_bits(v.w * inv) << 24);
+}
+
+// The same by the hardware conversion (v_cvt_pk_fp8_f32, two values per
+// instruction).  It rounds to nearest even as the software encoder does but
+// does not saturate (magnitudes from 464 up and infinities become NaN) and
+// writes 0xFF for every NaN; on every other binary32 input its code is the
+// software encoder's.  So it serves buckets whose values and inverse scale
+// are finite, where every scaled value is at most 448 (1 + 2^-23) in
+// magnitude.
+__device__ __forceinline__ uint32_t e4m3_pack4_hw(f4v v, float inv) {
+    const int lo = __builtin_amdgcn_cvt_pk_fp8_f32(v.x * inv, v.y * inv, 0, false);
+    return (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(v.z * inv, v.w * inv, lo, true);
 }
 
 // Elementwise: each thread converts QB_UNROLL float4 (loads issued together),
@@ -76,22 +94,88 @@ __device__ __forceinline__ float wave_max(float v) {
     return v;
 }
 
-// One wavefront per bucket; VEC: the bucket's element count is a multiple of
-// 256 so each lane handles whole float4s (the common n = 8, 16 RGBA case),
-// and at most 4 float4 per lane stay in registers between the two passes.
-template <bool VEC>
-__global__ __launch_bounds__(256) void k_quant_fp8(const float* __restrict__ src,
-                                                   uint8_t* __restrict__ dst,
-                                                   float* __restrict__ scales,
-                                                   int64_t n_buckets, int elems) {
+// Shapes of the FP8 quantiser.  QF8_PAIR (buckets of 512, 1024 or 2048
+// values, HALF = values / 512): a 128-thread workgroup per bucket, each of its
+// two wavefronts streaming one contiguous half of the bucket's float4s (2 KiB
+// of a 16x16 RGBA bucket), the halves' maxima meeting in LDS; a bucket whose
+// values and inverse scale are finite is encoded by the hardware conversion,
+// any other by the software encoder.  With the encode that cheap, streaming 2 KiB per
+// wavefront moves this 4:1 read/write mix faster than 4 KiB.  QF8_WAVE: one
+// wavefront per bucket, whole float4s per lane.  QF8_SCALAR: one wavefront
+// per bucket, one element per lane and step (any element count).  The
+// bucket's largest magnitude is an exact maximum and both encoders give the
+// same codes where they are used, so the codes and scales do not depend on
+// the shape.
+constexpr int QF8_SCALAR = 0, QF8_WAVE = 1, QF8_PAIR = 2;
+
+template <int SHAPE, int HALF>
+__global__ __launch_bounds__(SHAPE == QF8_PAIR ? 128 : 256) void k_quant_fp8(
+    const float* __restrict__ src, uint8_t* __restrict__ dst, float* __restrict__ scales,
+    int64_t n_buckets, int elems) {
     const int lane = threadIdx.x & 63;
+    if constexpr (SHAPE == QF8_PAIR) {
+        // elems = 512 * HALF: HALF float4 per lane in each half; the
+        // workgroup's two wavefronts share its bucket
+        __shared__ float part[2];
+        __shared__ uint32_t odd[2];
+        const int w = threadIdx.x >> 6;
+        const int64_t b = (int64_t)xcd_block_id(blockIdx.x, gridDim.x);
+        const bool live = b < n_buckets;
+        const int64_t first = (int64_t)w * HALF * 64;  // float4 index of the half
+        const f4v* s = (const f4v*)(src + (live ? b : 0) * elems) + first;
+        f4v cache[HALF > 0 ? HALF : 1];
+        float amax = 0.f;
+        float nonfinite = 0.f;  // NaN once a NaN or an infinity is seen
+        if (live) {
+            // all loads issued before the first use
+#pragma unroll
+            for (int k = 0; k < HALF; k++) cache[k] = __builtin_nontemporal_load(s + k * 64 + lane);
+#pragma unroll
+            for (int k = 0; k < HALF; k++) {
+                amax = fmaxf(amax, fmaxf(fmaxf(fabsf(cache[k].x), fabsf(cache[k].y)),
+                                         fmaxf(fabsf(cache[k].z), fabsf(cache[k].w))));
+                nonfinite += (cache[k].x * 0.f + cache[k].y * 0.f) +
+                             (cache[k].z * 0.f + cache[k].w * 0.f);
+            }
+        }
+        amax = wave_max(amax);
+        const bool any_odd = __ballot(nonfinite != nonfinite) != 0ull;
+        if (lane == 0) {
+            part[w] = amax;
+            odd[w] = any_odd ? 1u : 0u;
+        }
+        __syncthreads();
+        if (!live) return;
+        amax = fmaxf(part[0], part[1]);
+        float inv = 1.f, scale = 1.f;
+        if (amax > 0.f && amax <= 3.402823466e38f) {
+            inv = 448.0f / amax;
+            scale = amax / 448.0f;
+        }
+        // finite values and a finite inverse scale (a largest magnitude below
+        // about 1.3e-36 overflows it): every scaled value is finite and at
+        // most 448 (1 + 2^-23) in magnitude
+        const bool finite = (odd[0] | odd[1]) == 0u && inv <= 3.402823466e38f;
+        uint32_t* d = (uint32_t*)(dst + b * elems) + first;
+        if (finite) {
+#pragma unroll
+            for (int k = 0; k < HALF; k++)
+                __builtin_nontemporal_store(e4m3_pack4_hw(cache[k], inv), d + k * 64 + lane);
+        } else {
+#pragma unroll
+            for (int k = 0; k < HALF; k++)
+                __builtin_nontemporal_store(e4m3_pack4(cache[k], inv), d + k * 64 + lane);
+        }
+        if (w == 0 && lane == 0) scales[b] = scale;
+        return;
+    }
     const int64_t b =
         (int64_t)xcd_block_id(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
     if (b >= n_buckets) return;
     const float* s = src + b * elems;
     uint8_t* d = dst + b * elems;
     float amax = 0.f;
-    if constexpr (VEC) {
+    if constexpr (SHAPE == QF8_WAVE) {
         const int per_lane = elems / 256;  // float4 per lane
         float4 cache[4];
 #pragma unroll
@@ -245,17 +329,30 @@ hipError_t launch_quantize(const TexView& t, int dst_fmt, void* codes, float* sc
         prof_end(K_QUANT_BF16, s);
         return hipGetLastError();
     }
+    // at most 2^22 buckets per launch: 2^22 workgroups of 128 work-items in
+    // the paired shape (2^29 work-items), 2^20 of 256 in the others
     const int64_t chunk_b = MAX_LAUNCH_BLOCKS * 4;
     prof_begin(K_QUANT_FP8, s);
     for (int64_t b0 = 0; b0 < nb; b0 += chunk_b) {
         const int64_t b = std::min(chunk_b, nb - b0);
-        const uint32_t blocks = (uint32_t)((b + 3) / 4);
-        if (elems % 256 == 0)
-            hipLaunchKernelGGL(k_quant_fp8<true>, dim3(blocks), dim3(256), 0, s, src + b0 * elems,
-                               (uint8_t*)codes + b0 * elems, scales + b0, b, elems);
+        const float* bs = src + b0 * elems;
+        uint8_t* bd = (uint8_t*)codes + b0 * elems;
+        const dim3 pairs((uint32_t)b), quads((uint32_t)((b + 3) / 4));
+        if (elems == 512)
+            hipLaunchKernelGGL((k_quant_fp8<QF8_PAIR, 1>), pairs, dim3(128), 0, s, bs, bd,
+                               scales + b0, b, elems);
+        else if (elems == 1024)
+            hipLaunchKernelGGL((k_quant_fp8<QF8_PAIR, 2>), pairs, dim3(128), 0, s, bs, bd,
+                               scales + b0, b, elems);
+        else if (elems == 2048)
+            hipLaunchKernelGGL((k_quant_fp8<QF8_PAIR, 4>), pairs, dim3(128), 0, s, bs, bd,
+                               scales + b0, b, elems);
+        else if (elems % 256 == 0)
+            hipLaunchKernelGGL((k_quant_fp8<QF8_WAVE, 0>), quads, dim3(256), 0, s, bs, bd,
+                               scales + b0, b, elems);
         else
-            hipLaunchKernelGGL(k_quant_fp8<false>, dim3(blocks), dim3(256), 0, s, src + b0 * elems,
-                               (uint8_t*)codes + b0 * elems, scales + b0, b, elems);
+            hipLaunchKernelGGL((k_quant_fp8<QF8_SCALAR, 0>), quads, dim3(256), 0, s, bs, bd,
+                               scales + b0, b, elems);
     }
     prof_end(K_QUANT_FP8, s);
     return hipGetLastError();

@@ -209,7 +209,8 @@ def test_bounds_fuzz(rt):
 # ---------------------------------------------------------------------------
 
 @pytest.mark.parametrize("W,H,n,C", [(64, 64, 8, 4), (16, 8, 16, 4), (7, 5, 8, 3), (5, 3, 3, 1),
-                                     (3, 2, 64, 4), (2, 2, 40, 3)])
+                                     (3, 2, 64, 4), (2, 2, 40, 3), (5, 3, 16, 4), (7, 3, 16, 2),
+                                     (3, 5, 32, 2)])
 def test_quantizer_bit_exact(rt, W, H, n, C):
     g = torch.Generator().manual_seed(W * H + n + C)
     t = torch.randn((H, W, n, n, C), generator=g) * torch.exp2(
@@ -227,6 +228,35 @@ def test_quantizer_bit_exact(rt, W, H, n, C):
     np.testing.assert_array_equal(host(c16).view(np.uint16).reshape(-1), o16)
     np.testing.assert_array_equal(host(c8).reshape(-1), o8)
     np.testing.assert_array_equal(host(s8).reshape(-1), os8)
+
+
+@pytest.mark.parametrize("n,C", [(16, 2), (16, 4), (32, 2)])
+def test_fp8_bucket_maximum_in_one_half(rt, n, C):
+    """Buckets of 512, 1024 and 2048 values are quantised by two wavefronts,
+    each over one contiguous half; the bucket's scale must come from the
+    larger half whichever half holds it, with NaN ignored and an infinity
+    giving scale 1 from either half.  An odd bucket count leaves the last
+    workgroup's second bucket empty."""
+    per = n * n * C
+    nb = 9
+    g = torch.Generator().manual_seed(per)
+    t = torch.randn((nb, per), generator=g)
+    t[0, : per // 2] *= 1000.0           # maximum in the first half
+    t[1, per // 2:] *= 1000.0            # maximum in the second half
+    t[2, per - 1] = -3.0e4               # a single largest value, last element
+    t[3, 0] = float("nan")               # NaN in the first half only
+    t[4, per // 2 + 5] = float("nan")    # NaN in the second half only
+    t[5, per // 2] = float("inf")        # infinity in the second half
+    t[6, 3] = float("-inf")              # infinity in the first half
+    t[7] = 0.0                           # all zero: scale 1
+    t[8, : per // 2] = 0.0               # first half zero
+    tex = rt.Texture(t.to(DEV).view(1, nb, n, n, C), nb, 1, n, C)
+    c8, s8 = rt.quantize(tex, "fp8")
+    _sync()
+    o8, os8 = oracle.quantize(t.numpy(), nb, per, oracle.FMT_FP8_E4M3)
+    np.testing.assert_array_equal(host(s8).reshape(-1), os8)
+    np.testing.assert_array_equal(host(c8).reshape(-1), o8)
+    assert os8[5] == 1.0 and os8[6] == 1.0 and os8[7] == 1.0
 
 
 def test_e4m3_encode_exhaustive_grid(rt):
