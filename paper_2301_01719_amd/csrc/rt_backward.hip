@@ -497,12 +497,15 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_hist(const uint32_t* __r
 }
 
 // x from the lane `o` below in the wavefront, for a power of two o < 64;
-// lanes under `o` receive some lane's x, which their callers mask.  Offsets
-// 1 and 2 take one or two DPP wavefront shifts (wave_shr:1) on the vector ALU
-// instead of a trip through the LDS crossbar (ds_bpermute); the value is the
-// same either way, so the segmented scans below add in the same order
+// lanes under `o` receive 0 or some lane's x, which their callers mask.
+// Offsets 1 and 2 take one or two DPP wavefront shifts (wave_shr:1) on the
+// vector ALU instead of a trip through the LDS crossbar (ds_bpermute); the
+// value is the same either way, so the segmented scans below add in the same
+// order.  A lane without a source lane reads 0 (bound_ctrl), which lets the
+// compiler fold the last shift into the addition that uses it
+// (v_add_f32_dpp).
 __device__ __forceinline__ int dpp_shr1(int x) {
-    return __builtin_amdgcn_update_dpp(x, x, 0x138, 0xF, 0xF, false);
+    return __builtin_amdgcn_mov_dpp(x, 0x138, 0xF, 0xF, true);
 }
 __device__ __forceinline__ int lanes_up(int x, int o) {
     if (o == 1) return dpp_shr1(x);
@@ -515,10 +518,10 @@ __device__ __forceinline__ uint32_t lanes_up(uint32_t x, int o) {
 __device__ __forceinline__ float lanes_up(float x, int o) {
     return __int_as_float(lanes_up(__float_as_int(x), o));
 }
-// x from the lane one above (lane 63 receives its own x): one DPP wavefront
-// shift (wave_shl:1)
+// x from the lane one above (lane 63 receives 0, which its callers mask): one
+// DPP wavefront shift (wave_shl:1)
 __device__ __forceinline__ int lane_above(int x) {
-    return __builtin_amdgcn_update_dpp(x, x, 0x130, 0xF, 0xF, false);
+    return __builtin_amdgcn_mov_dpp(x, 0x130, 0xF, 0xF, true);
 }
 __device__ __forceinline__ uint32_t lane_above(uint32_t x) { return (uint32_t)lane_above((int)x); }
 
