@@ -425,22 +425,42 @@ __device__ __forceinline__ bool sort_skipped(const uint32_t* __restrict__ disord
 
 // Whether any key is smaller than the one before it, in two launches.  The
 // first writes one flag per workgroup of 1024 keys (four per thread with one
-// 16-byte load -- the key buffer is padded to 256 bytes -- and the key before
-// them), the second ORs the flags into *disorder (cleared before) with one
-// atomic per 4096 flags.  On unsorted keys nearly every wave finds a descent,
-// and atomics of every wave on one address would serialise.
+// 16-byte load -- the key buffer is padded to 256 bytes -- and the keys
+// around them), the second ORs the flags into *disorder (cleared before) with
+// one atomic per 4096 flags.  On unsorted keys nearly every wave finds a
+// descent, and atomics of every wave on one address would serialise.
+//
+// With `range` the first launch also writes the [start, end) of every bucket
+// as k_bucket_ranges forms them, taking the keys to be in order: when they
+// are, the sort and k_bucket_ranges return at once and these are the ranges;
+// when they are not, k_bucket_ranges writes both ends of every bucket the
+// sorted keys hold (the same buckets these keys hold) after the sort, and
+// buckets without keys keep the zeros filled in before.
 __global__ __launch_bounds__(256) void k_keys_in_order(const uint32_t* __restrict__ keys, int64_t R,
-                                                       uint32_t* __restrict__ flags) {
+                                                       uint32_t* __restrict__ flags, int cell_bits,
+                                                       int64_t nb, int2* __restrict__ range) {
     __shared__ uint32_t wave_down[4];
     const int64_t i0 = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 4;
     bool down = false;
     if (i0 < R) {
         const uint4 q = *(const uint4*)(keys + i0);
-        const uint32_t k[5] = {keys[i0 > 0 ? i0 - 1 : 0], q.x, q.y, q.z, q.w};
+        const uint32_t k[6] = {keys[i0 > 0 ? i0 - 1 : 0], q.x, q.y, q.z, q.w,
+                               keys[i0 + 4 < R ? i0 + 4 : R - 1]};
 #pragma unroll
         for (int u = 0; u < 4; u++) {
             const int64_t i = i0 + u;
             if (i > 0 && i < R && k[u + 1] < k[u]) down = true;
+        }
+        if (range) {
+#pragma unroll
+            for (int u = 0; u < 4; u++) {
+                const int64_t i = i0 + u;
+                if (i >= R) break;
+                const uint32_t bu = k[u + 1] >> cell_bits;
+                if (bu >= nb) continue;  // records of a sparse plan without a bucket
+                if (i == 0 || (k[u] >> cell_bits) != bu) range[bu].x = (int)i;
+                if (i == R - 1 || (k[u + 2] >> cell_bits) != bu) range[bu].y = (int)(i + 1);
+            }
         }
     }
     const uint64_t m = __ballot(down);
@@ -779,9 +799,9 @@ __global__ __launch_bounds__(256) void k_fill_u32(uint32_t* __restrict__ p, int6
 __global__ __launch_bounds__(256) void k_bucket_ranges(const uint32_t* __restrict__ skeys,
                                                        int64_t R, int cell_bits, int64_t nb,
                                                        int2* __restrict__ range,
-                                                       const uint32_t* __restrict__ keys_made,
                                                        const uint32_t* __restrict__ disorder) {
-    if (sort_skipped(disorder)) skeys = keys_made;
+    // records made in key order: the order check wrote the ranges
+    if (sort_skipped(disorder)) return;
     const int64_t i0 = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 4;
     if (i0 >= R) return;
     const uint4 q = *(const uint4*)(skeys + i0);
@@ -1723,19 +1743,20 @@ void launch_sort_records(const BwdPlan& plan, void* ws, const uint32_t* disorder
 }
 
 // Whether the R keys in keys0 are in order: the workspace's disorder word
-// is cleared, then set by any descent.
-static uint32_t* launch_order_check(const BwdPlan& plan, void* ws, hipStream_t s) {
+// is cleared, then set by any descent.  With `range` (zero-filled before) the
+// check also writes the bucket ranges the keys give if they are in order.
+static uint32_t* launch_order_check(const BwdPlan& plan, void* ws, int2* range, hipStream_t s) {
     char* wsb = (char*)ws;
     const uint32_t* keys0 = (const uint32_t*)(wsb + plan.off_keys0);
     uint32_t* disorder = (uint32_t*)(wsb + plan.off_disorder);
     const int64_t R = plan.records;
     uint32_t* flags = disorder + ORDER_FLAGS_AT;
     launch_fill(disorder, 1, 0u, s);
-    if (R > 1) {
+    if (R > 0) {
         const int64_t nflags = (R + 1023) / 1024;
         prof_begin(K_ORDER_CHECK, s);
         hipLaunchKernelGGL(k_keys_in_order, dim3((uint32_t)nflags), dim3(256), 0, s, keys0, R,
-                           flags);
+                           flags, plan.cell_bits, plan.buckets, range);
         hipLaunchKernelGGL(k_flags_any, dim3((uint32_t)((nflags + 4095) / 4096)), dim3(256), 0, s,
                            flags, nflags, disorder);
         prof_end(K_ORDER_CHECK, s);
@@ -1757,21 +1778,22 @@ hipError_t launch_accumulate(int n, int C, int mode, const float* grad_out, cons
     const int64_t R = plan.records;
 
     // 2. sort, skipped on the device when the records were made in key order
+    // (the order check then also writes the bucket ranges)
+    const int64_t nb = plan.buckets;
+    launch_fill(big_count, BIG_LISTS * BIG_STRIDE + nb * 2, 0u, s);  // counters and ranges
     const uint32_t* skeys = keys0;
     const uint32_t* svals = nullptr;
     const uint32_t* dis = nullptr;
     if (R > 0) {
-        dis = launch_order_check(plan, ws, s);
+        dis = launch_order_check(plan, ws, range, s);
         launch_sort_records(plan, ws, dis, s, &skeys, &svals);
     }
 
-    // 3. ranges
-    const int64_t nb = plan.buckets;
-    launch_fill(big_count, BIG_LISTS * BIG_STRIDE + nb * 2, 0u, s);  // counters and ranges
+    // 3. ranges of sorted records (returns at once when the sort did)
     if (R > 0) {
         prof_begin(K_BUCKET_RANGES, s);
         hipLaunchKernelGGL(k_bucket_ranges, dim3((uint32_t)((R + 1023) / 1024)), dim3(256), 0, s,
-                           skeys, R, plan.cell_bits, nb, range, keys0, dis);
+                           skeys, R, plan.cell_bits, nb, range, dis);
         prof_end(K_BUCKET_RANGES, s);
     }
 
@@ -1949,7 +1971,7 @@ hipError_t launch_plan(const TexView& t, int mode, const float* uv, const float*
         hipLaunchKernelGGL(k_plan_keys<MODE_BILINEAR>, dim3(fragmap_blocks(m)), dim3(256), 0, s,
                            t.W, t.H, t.n, uv, tbn, view, keys0, m, plan.cell_bits);
     prof_end(K_PLAN_KEYS, s);
-    const uint32_t* dis = launch_order_check(plan, ws, s);
+    const uint32_t* dis = launch_order_check(plan, ws, nullptr, s);
     const uint32_t *skeys = nullptr, *svals = nullptr;
     launch_sort_records(plan, ws, dis, s, &skeys, &svals);
     prof_begin(K_PLAN_GATHER, s);
