@@ -143,6 +143,32 @@ def _same_texel_gradient(a, b, mode):
         assert torch.allclose(a, b, rtol=1e-5, atol=1e-6 * float(b.abs().max()))
 
 
+@pytest.mark.parametrize("N", [1, 2, 3, 5, 1023, 1025])
+@pytest.mark.parametrize("mode", ["nearest", "bilinear"])
+def test_backward_of_a_few_fragments_planned_and_not(rt, N, mode):
+    """A handful of records, in input order and in plan order: the order
+    check writes the bucket ranges when the records come in key order (one
+    record included), the sort and the range pass otherwise.  A range left
+    unwritten would drop records, so the texel gradient must carry the
+    upstream gradient's whole mass (each fragment's tap weights sum to one,
+    Eq. (5)) both ways, and the two ways agree."""
+    W, H, n, C = 6, 5, 8, 4
+    tex_d, uv, tbn, view = _case(100 + N, W, H, n, C, N)
+    tex = rt.Texture(tex_d, W, H, n, C)
+    go = (torch.rand((N, C), generator=torch.Generator().manual_seed(N)) + 0.5).to(DEV)
+    gt, gv, gu = rt.lookup_bwd(tex, uv, tbn, view, go, mode=mode)
+    order, puv, ptbn, pview = rt.plan_fragments(tex, uv, tbn, view, mode=mode)
+    ot = order.long()
+    pgt, pgv, pgu = rt.lookup_bwd(tex, puv, ptbn, pview, go[ot].contiguous(), mode=mode)
+    torch.cuda.synchronize()
+    want = go.double().sum(0).cpu().numpy()
+    for g in (gt, pgt):
+        t = g.double().reshape(-1, C).sum(0).cpu().numpy()
+        np.testing.assert_allclose(t, want, rtol=1e-5)
+    _same_texel_gradient(pgt, gt, mode)
+    assert torch.equal(pgv, gv[ot]) and torch.equal(pgu, gu[ot])
+
+
 @pytest.mark.parametrize("mode", ["nearest", "bilinear"])
 def test_nearly_planned_fragments_are_still_sorted(rt, mode):
     """One swapped pair breaks the key order: the backward's sort runs and
