@@ -431,43 +431,50 @@ __device__ __forceinline__ bool sort_skipped(const uint32_t* __restrict__ disord
 // descent, and atomics of every wave on one address would serialise.
 //
 // With `range` the first launch also writes the [start, end) of every bucket
-// as k_bucket_ranges forms them, taking the keys to be in order: when they
-// are, the sort and k_bucket_ranges return at once and these are the ranges;
-// when they are not, k_bucket_ranges writes both ends of every bucket the
-// sorted keys hold (the same buckets these keys hold) after the sort, and
-// buckets without keys keep the zeros filled in before.
+// as k_bucket_ranges forms them, from each workgroup whose 1024 keys (and
+// the key before them) are in order: when all are, the sort and
+// k_bucket_ranges return at once and these are the ranges; when some are not,
+// k_bucket_ranges writes both ends of every bucket the sorted keys hold (the
+// same buckets these keys hold) after the sort, and buckets without keys keep
+// the zeros filled in before.  Unsorted keys make nearly every record a
+// boundary, so workgroups with a descent write nothing.
 __global__ __launch_bounds__(256) void k_keys_in_order(const uint32_t* __restrict__ keys, int64_t R,
                                                        uint32_t* __restrict__ flags, int cell_bits,
                                                        int64_t nb, int2* __restrict__ range) {
     __shared__ uint32_t wave_down[4];
     const int64_t i0 = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 4;
     bool down = false;
+    uint32_t k[6] = {0u, 0u, 0u, 0u, 0u, 0u};
     if (i0 < R) {
         const uint4 q = *(const uint4*)(keys + i0);
-        const uint32_t k[6] = {keys[i0 > 0 ? i0 - 1 : 0], q.x, q.y, q.z, q.w,
-                               keys[i0 + 4 < R ? i0 + 4 : R - 1]};
+        k[0] = keys[i0 > 0 ? i0 - 1 : 0];
+        k[1] = q.x;
+        k[2] = q.y;
+        k[3] = q.z;
+        k[4] = q.w;
+        k[5] = keys[i0 + 4 < R ? i0 + 4 : R - 1];
 #pragma unroll
         for (int u = 0; u < 4; u++) {
             const int64_t i = i0 + u;
             if (i > 0 && i < R && k[u + 1] < k[u]) down = true;
         }
-        if (range) {
-#pragma unroll
-            for (int u = 0; u < 4; u++) {
-                const int64_t i = i0 + u;
-                if (i >= R) break;
-                const uint32_t bu = k[u + 1] >> cell_bits;
-                if (bu >= nb) continue;  // records of a sparse plan without a bucket
-                if (i == 0 || (k[u] >> cell_bits) != bu) range[bu].x = (int)i;
-                if (i == R - 1 || (k[u + 2] >> cell_bits) != bu) range[bu].y = (int)(i + 1);
-            }
-        }
     }
     const uint64_t m = __ballot(down);
     if ((threadIdx.x & 63) == 0) wave_down[threadIdx.x >> 6] = m != 0ull ? 1u : 0u;
     __syncthreads();
-    if (threadIdx.x == 0)
-        flags[blockIdx.x] = wave_down[0] | wave_down[1] | wave_down[2] | wave_down[3];
+    const uint32_t any = wave_down[0] | wave_down[1] | wave_down[2] | wave_down[3];
+    if (threadIdx.x == 0) flags[blockIdx.x] = any;
+    if (range && any == 0u && i0 < R) {
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            const int64_t i = i0 + u;
+            if (i >= R) break;
+            const uint32_t bu = k[u + 1] >> cell_bits;
+            if (bu >= nb) continue;  // records of a sparse plan without a bucket
+            if (i == 0 || (k[u] >> cell_bits) != bu) range[bu].x = (int)i;
+            if (i == R - 1 || (k[u + 2] >> cell_bits) != bu) range[bu].y = (int)(i + 1);
+        }
+    }
 }
 
 __global__ __launch_bounds__(256) void k_flags_any(const uint32_t* __restrict__ flags,
