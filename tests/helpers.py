@@ -143,12 +143,12 @@ def check_grad_vec(g_gpu, g_o, scale, go=None, rnd=None, rel=BWD_REL, absolute=1
     big = gn > 1e-3 * (gn.max() if gn.size else 0)
     res = {"magnitude": float(np.max(d[~zero] / bound[~zero])) if np.any(~zero) else 0.0,
            "plain_rel": float(np.max(d[big] / gn[big])) if np.any(big) else 0.0,
-           "survey": None, "needs_rounding_term": 0}
+           "relative": None, "needs_rounding_term": 0}
     if go is not None:
         base = rel * gn + absolute * np.abs(go.astype(np.float64)).sum(1)
         res["needs_rounding_term"] = int(np.sum(d > base))
         b2 = base + (0.0 if rnd is None else rnd)
         bad = np.nonzero(d > b2)[0]
-        assert bad.size == 0, ("survey bound", bad[:5], d[bad[:5]], b2[bad[:5]], gn[bad[:5]])
-        res["survey"] = float(np.max(d / np.maximum(b2, 1e-300))) if d.size else 0.0
+        assert bad.size == 0, ("relative bound", bad[:5], d[bad[:5]], b2[bad[:5]], gn[bad[:5]])
+        res["relative"] = float(np.max(d / np.maximum(b2, 1e-300))) if d.size else 0.0
     return res

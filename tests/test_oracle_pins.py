@@ -1478,7 +1478,7 @@ def test_error_scales_bound_a_binary32_evaluation(W, H, n, C, mode, frames):
         err = np.linalg.norm(mine - ref, axis=1)[keep]
         bound = 2.0 ** -20 * np.linalg.norm(S, axis=1)[keep] + rnd[keep]
         assert np.all(err <= bound), (np.max(err / np.maximum(bound, 1e-300)))
-        # and the survey's reading of "1e-4 relative" with the rounding term
+        # and the reading of "1e-4 relative": 1e-4 |g*| + 1e-6 sum |go| + the rounding term
         gn = np.linalg.norm(ref, axis=1)[keep]
         assert np.all(err <= 1e-4 * gn + 1e-6 * np.abs(g[keep]).sum(1) + rnd[keep])
     if n == 64:
